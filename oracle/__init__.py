@@ -1,0 +1,245 @@
+"""Python face of the CPU FP64 oracle (``gdg_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  The oracle is the plain, slow, literal CPU
+implementation of the graph-based DG scheme of arXiv 2402.04514 that the GPU
+library is checked against.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import it.  It shares no code with
+the GPU library.
+
+Conventions (the same interface conventions as the library, written
+independently): dofs are numbered cell-major, cells lexicographic with x
+fastest, local nodes lexicographic with x fastest; states are SoA arrays of
+shape ``(dim + 2, ndofs)`` holding ``rho, m_1..m_d, E``; box face ``f = 2*axis
++ side`` (side 0 = low); boundary kinds 0 periodic, 1 outflow, 2 slip.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gdg_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+BC_PERIODIC, BC_OUTFLOW, BC_SLIP = 0, 1, 2
+LOW_ORDER, HIGH_ORDER, LIMITED = 0, 1, 2
+KIND_CELL, KIND_FACE_COLLOC, KIND_FACE = 0, 1, 2
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc at -O2, no fast-math (OpenMP over rows)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-std=c11",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Params(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("cfl", C.c_double), ("c_ev", C.c_double),
+                ("c_k", C.c_double), ("c_r", C.c_double), ("p_r", C.c_double),
+                ("passes", C.c_int), ("scheme", C.c_int)]
+
+
+_DP = C.POINTER(C.c_double)
+
+
+class _Diag(C.Structure):
+    _fields_ = [("tau_max", C.c_double), ("N", _DP), ("rho_min", _DP), ("rho_max", _DP),
+                ("s_min", _DP), ("UL", _DP), ("dUH", _DP), ("U1", _DP), ("dij", _DP),
+                ("lij", _DP), ("lbd", _DP), ("Aij", _DP), ("Abd", _DP)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        L = _lib
+        L.or_create.restype = C.c_void_p
+        L.or_create.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_long), _DP, _DP, C.POINTER(C.c_int)]
+        L.or_destroy.argtypes = [C.c_void_p]
+        for fn in ("or_num_dofs", "or_nnz", "or_nbnd"):
+            getattr(L, fn).restype = C.c_long
+            getattr(L, fn).argtypes = [C.c_void_p]
+        L.or_volume.restype = C.c_double
+        L.or_volume.argtypes = [C.c_void_p]
+        L.or_csr.argtypes = [C.c_void_p, C.POINTER(C.c_long), C.POINTER(C.c_long), _DP, _DP,
+                             C.POINTER(C.c_int)]
+        L.or_lumped.argtypes = [C.c_void_p, _DP]
+        L.or_boundary.argtypes = [C.c_void_p, C.POINTER(C.c_long), C.POINTER(C.c_int), _DP]
+        L.or_node_coords.argtypes = [C.c_void_p, _DP]
+        L.or_literal_cij.argtypes = [C.c_void_p, C.c_long, C.c_long, _DP]
+        L.or_lambda_max.restype = C.c_double
+        L.or_lambda_max.argtypes = [C.c_double, C.c_int, _DP, _DP, _DP]
+        L.or_exact_riemann.restype = C.c_int
+        L.or_exact_riemann.argtypes = [C.c_double] * 7 + [_DP, _DP]
+        L.or_exact_lambda.restype = C.c_double
+        L.or_exact_lambda.argtypes = [C.c_double] * 7
+        L.or_riemann_sample.argtypes = [C.c_double] * 8 + [_DP]
+        L.or_stage.restype = C.c_int
+        L.or_stage.argtypes = [C.c_void_p, C.POINTER(_Params), _DP, C.c_double, _DP,
+                               C.POINTER(_Diag)]
+        L.or_tau_rows.argtypes = [C.c_void_p, C.POINTER(_Params), _DP, _DP]
+        L.or_step.restype = C.c_int
+        L.or_step.argtypes = [C.c_void_p, C.POINTER(_Params), _DP, C.c_double, C.c_double, _DP,
+                              C.POINTER(C.c_int)]
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_DP)
+
+
+def params(gamma=1.4, cfl=0.5, degree=1, c_ev=None, c_k=1.0, c_r=4.0, p_r=1.5, passes=2,
+           scheme=LIMITED) -> _Params:
+    """Scheme constants of Sec. 5 (c_ev = 1, 0.5, 0.25 for k = 1, 2, 3)."""
+    if c_ev is None:
+        c_ev = {1: 1.0, 2: 0.5, 3: 0.25}[degree]
+    return _Params(gamma, cfl, c_ev, c_k, c_r, p_r, passes, scheme)
+
+
+class Mesh:
+    """Uniform Cartesian DG Q_k mesh with the stencil of Sec. 2.3."""
+
+    def __init__(self, dim, degree, cells, lo, hi, bc):
+        self.dim, self.degree = dim, degree
+        self.cells = tuple(int(c) for c in cells)
+        self.lo = tuple(float(x) for x in lo)
+        self.hi = tuple(float(x) for x in hi)
+        self.bc = tuple(int(b) for b in bc)
+        L = lib()
+        c = (C.c_long * 3)(*(list(self.cells) + [1] * (3 - dim)))
+        lo_ = (C.c_double * 3)(*(list(self.lo) + [0.0] * (3 - dim)))
+        hi_ = (C.c_double * 3)(*(list(self.hi) + [1.0] * (3 - dim)))
+        b = (C.c_int * 6)(*(list(self.bc) + [1] * (6 - len(self.bc))))
+        self._h = L.or_create(dim, degree, c, lo_, hi_, b)
+        if not self._h:
+            raise ValueError("invalid mesh description")
+        self.ndofs = L.or_num_dofs(self._h)
+        self.m = dim + 2
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().or_destroy(h)
+            self._h = None
+
+    @property
+    def volume(self) -> float:
+        return lib().or_volume(self._h)
+
+    def coords(self) -> np.ndarray:
+        x = np.zeros((self.ndofs, self.dim))
+        lib().or_node_coords(self._h, _dp(x))
+        return x
+
+    def csr(self):
+        L = lib()
+        nnz = L.or_nnz(self._h)
+        rowptr = np.zeros(self.ndofs + 1, dtype=np.int64)
+        col = np.zeros(nnz, dtype=np.int64)
+        c = np.zeros((nnz, self.dim))
+        mij = np.zeros(nnz)
+        kind = np.zeros(nnz, dtype=np.int32)
+        L.or_csr(self._h, rowptr.ctypes.data_as(C.POINTER(C.c_long)),
+                 col.ctypes.data_as(C.POINTER(C.c_long)), _dp(c), _dp(mij),
+                 kind.ctypes.data_as(C.POINTER(C.c_int)))
+        return rowptr, col, c, mij, kind
+
+    def lumped(self) -> np.ndarray:
+        mi = np.zeros(self.ndofs)
+        lib().or_lumped(self._h, _dp(mi))
+        return mi
+
+    def boundary(self):
+        L = lib()
+        nb = L.or_nbnd(self._h)
+        bptr = np.zeros(self.ndofs + 1, dtype=np.int64)
+        bface = np.zeros(max(nb, 1), dtype=np.int32)
+        bc_c = np.zeros((max(nb, 1), self.dim))
+        L.or_boundary(self._h, bptr.ctypes.data_as(C.POINTER(C.c_long)),
+                      bface.ctypes.data_as(C.POINTER(C.c_int)), _dp(bc_c))
+        return bptr, bface[:nb], bc_c[:nb]
+
+    def literal_cij(self, i, j) -> np.ndarray:
+        out = np.zeros(self.dim)
+        lib().or_literal_cij(self._h, i, j, _dp(out))
+        return out
+
+    # -- scheme ------------------------------------------------------------
+    def stage(self, prm: _Params, U: np.ndarray, tau: float = 0.0, diag: bool = False):
+        """One forward-Euler stage Phi(U; tau); tau <= 0 picks Cr * tau_max."""
+        U = np.ascontiguousarray(U, dtype=np.float64).reshape(self.m, self.ndofs)
+        out = np.zeros_like(U)
+        d = _Diag()
+        arrs = {}
+        if diag:
+            N, nnz, m = self.ndofs, lib().or_nnz(self._h), self.m
+            shapes = {"N": (N,), "rho_min": (N,), "rho_max": (N,), "s_min": (N,),
+                      "UL": (m, N), "dUH": (m, N), "U1": (m, N), "dij": (nnz,),
+                      "lij": (nnz,), "lbd": (N,), "Aij": (nnz, m), "Abd": (N, m)}
+            for k, shp in shapes.items():
+                arrs[k] = np.zeros(shp)
+                setattr(d, k, _dp(arrs[k]))
+        st = lib().or_stage(self._h, C.byref(prm), _dp(U), float(tau), _dp(out), C.byref(d))
+        arrs["tau_max"] = d.tau_max
+        arrs["status"] = st
+        return (out, arrs) if diag else out
+
+    def tau_rows(self, prm: _Params, U: np.ndarray) -> np.ndarray:
+        U = np.ascontiguousarray(U, dtype=np.float64).reshape(self.m, self.ndofs)
+        out = np.zeros(self.ndofs)
+        lib().or_tau_rows(self._h, C.byref(prm), _dp(U), _dp(out))
+        return out
+
+    def step(self, prm: _Params, U: np.ndarray, dt_cap: float = 0.0, dt_fixed: float = 0.0):
+        """One SSP-RK3 step.  Returns (U_new, dt_taken, restarts, status)."""
+        U = np.array(U, dtype=np.float64).reshape(self.m, self.ndofs)
+        dt = C.c_double(0.0)
+        nres = C.c_int(0)
+        st = lib().or_step(self._h, C.byref(prm), _dp(U), float(dt_cap), float(dt_fixed),
+                           C.byref(dt), C.byref(nres))
+        return U, dt.value, nres.value, st
+
+    def run_to(self, prm: _Params, U: np.ndarray, t_final: float, max_steps: int = 10**9):
+        U = np.array(U, dtype=np.float64).reshape(self.m, self.ndofs)
+        t, n = 0.0, 0
+        while t < t_final and n < max_steps:
+            U, dt, _, st = self.step(prm, U, dt_cap=t_final - t)
+            if st:
+                raise RuntimeError("oracle step failed with status %d" % st)
+            t += dt
+            n += 1
+        return U, t, n
+
+
+# -- physics helpers -------------------------------------------------------
+def lambda_max(gamma, UL, UR, n) -> float:
+    UL = np.ascontiguousarray(UL, dtype=np.float64)
+    UR = np.ascontiguousarray(UR, dtype=np.float64)
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    return lib().or_lambda_max(gamma, len(n), _dp(UL), _dp(UR), _dp(n))
+
+
+def exact_riemann(gamma, rl, ul, pl, rr, ur, pr):
+    ps, us = C.c_double(), C.c_double()
+    vac = lib().or_exact_riemann(gamma, rl, ul, pl, rr, ur, pr, C.byref(ps), C.byref(us))
+    return ps.value, us.value, vac
+
+
+def exact_lambda(gamma, rl, ul, pl, rr, ur, pr) -> float:
+    return lib().or_exact_lambda(gamma, rl, ul, pl, rr, ur, pr)
+
+
+def riemann_sample(gamma, left, right, xi):
+    out = np.zeros(3)
+    lib().or_riemann_sample(gamma, *left, *right, float(xi), _dp(out))
+    return out

@@ -1,0 +1,1134 @@
+/*
+ * gdg_oracle.c -- plain CPU FP64 oracle for the graph-based DG scheme of
+ * Kronbichler, Maier & Tomas, "Graph-based methods for hyperbolic systems of
+ * conservation laws using discontinuous space discretizations" (arXiv 2402.04514).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, literal reference that the
+ * GPU library is checked against.  Only the tests, the smoke check and the
+ * bench's CPU-baseline leg may load it; the product path never does.  It
+ * shares no code, header, table or helper with the GPU library.
+ *
+ * Everything is double precision and written in the order the paper states
+ * the method: setup (Sec. 2.3), low-order update (Sec. 3, eq. cijdijscheme,
+ * dij_low_order), boundary data (Sec. 4), high-order update with entropy
+ * viscosity (Sec. 5.1-5.2), algebraic reformulation (Sec. 5.3) and convex
+ * limiting (Sec. 5.4), inside SSP-RK3 (Sec. 6.2).  Sums over a stencil run in
+ * stored CSR order.  Where the paper is silent or garbled the reading used is
+ * named in a comment ("reading R<n>"); the list of readings is kept with the
+ * design notes of the repository.
+ *
+ * Parity of the limited scheme's absolute values (N_i, d^H, l_ij, U^{n+1}) is
+ * unpinned by any printed example: the paper prints none.  Those values are
+ * pinned only through the invariants tested in tests/ (conservation, bounds,
+ * identities, limits l=0 / l=1, exact solutions).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_MAXD 3
+#define OR_MAXM 5
+
+enum { OR_BC_PERIODIC = 0, OR_BC_OUTFLOW = 1, OR_BC_SLIP = 2 };
+enum { OR_LOW_ORDER = 0, OR_HIGH_ORDER = 1, OR_LIMITED = 2 };
+enum { OR_KIND_CELL = 0, OR_KIND_FACE_COLLOC = 1, OR_KIND_FACE = 2 };
+
+typedef struct {
+  double gamma;   /* ratio of specific heats */
+  double cfl;     /* Cr of eq. MaxCFLdt */
+  double c_ev;    /* entropy-viscosity constant (Sec. 5.2) */
+  double c_k;     /* minimal-viscosity constant (eq. ViscMin) */
+  double c_r;     /* relaxation constant (eq. ViscMinConst2) */
+  double p_r;     /* relaxation power (eq. ViscMinConst2) */
+  int passes;     /* limiter passes (Sec. 6.1: two) */
+  int scheme;     /* OR_LOW_ORDER / OR_HIGH_ORDER / OR_LIMITED */
+} or_params;
+
+typedef struct {
+  int dim, deg, nb1, nloc, m;
+  long n[3];
+  double lo[3], hi[3], h[3];
+  int bc[6];
+  long ncells, ndofs;
+  double vol;
+  /* CSR of the stencil I(i), diagonal included (reading R4) */
+  long *rowptr;
+  long *col;
+  double *c;     /* nnz * dim */
+  double *mij;   /* nnz; zero outside the cell */
+  int *kind;     /* OR_KIND_* */
+  double *mi;    /* lumped mass, eq. mass_matrices */
+  /* boundary parts per row (Sec. 4.2): face id, c_i^{d,k}, boundary kind */
+  long *bptr;
+  int *bface;
+  double *bc_c;  /* nbnd * dim */
+  /* reference tables */
+  double xg[4];  /* Gauss-Lobatto nodes on [0,1] */
+  int nq;
+  double xq[4], wq[4]; /* Gauss-Legendre rule on [0,1] */
+} or_setup;
+
+/* ------------------------------------------------------------------------ */
+/* 1D reference element: Lagrange basis on Gauss-Lobatto nodes (Sec. 2.3).   */
+/* ------------------------------------------------------------------------ */
+
+static double lag(const or_setup *S, int a, double x) {
+  double v = 1.0;
+  for (int b = 0; b < S->nb1; ++b)
+    if (b != a) v *= (x - S->xg[b]) / (S->xg[a] - S->xg[b]);
+  return v;
+}
+
+static double dlag(const or_setup *S, int a, double x) {
+  double s = 0.0;
+  for (int c = 0; c < S->nb1; ++c) {
+    if (c == a) continue;
+    double t = 1.0 / (S->xg[a] - S->xg[c]);
+    for (int b = 0; b < S->nb1; ++b)
+      if (b != a && b != c) t *= (x - S->xg[b]) / (S->xg[a] - S->xg[b]);
+    s += t;
+  }
+  return s;
+}
+
+static void local_multi(const or_setup *S, int a, int *ai) {
+  for (int e = 0; e < 3; ++e) { ai[e] = a % S->nb1; a /= S->nb1; }
+}
+
+static void cell_multi(const or_setup *S, long K, long *ki) {
+  for (int e = 0; e < 3; ++e) {
+    long ne = e < S->dim ? S->n[e] : 1;
+    ki[e] = K % ne;
+    K /= ne;
+  }
+}
+
+static long cell_index(const or_setup *S, const long *ki) {
+  long K = 0, stride = 1;
+  for (int e = 0; e < S->dim; ++e) { K += ki[e] * stride; stride *= S->n[e]; }
+  return K;
+}
+
+/* Neighbour of cell K across face f = 2e+side; -1 on a non-periodic boundary. */
+static long neighbour(const or_setup *S, long K, int f) {
+  int e = f / 2, side = f % 2;
+  long ki[3];
+  cell_multi(S, K, ki);
+  ki[e] += side ? 1 : -1;
+  if (ki[e] < 0 || ki[e] >= S->n[e]) {
+    if (S->bc[f] != OR_BC_PERIODIC) return -1;
+    ki[e] = (ki[e] + S->n[e]) % S->n[e];
+  }
+  return cell_index(S, ki);
+}
+
+/* Tensor-product basis value / gradient at reference point xi of the cell. */
+static double phi(const or_setup *S, int a, const double *xi) {
+  int ai[3];
+  local_multi(S, a, ai);
+  double v = 1.0;
+  for (int e = 0; e < S->dim; ++e) v *= lag(S, ai[e], xi[e]);
+  return v;
+}
+
+static double dphi(const or_setup *S, int a, int dir, const double *xi) {
+  int ai[3];
+  local_multi(S, a, ai);
+  double v = 1.0;
+  for (int e = 0; e < S->dim; ++e)
+    v *= (e == dir) ? dlag(S, ai[e], xi[e]) / S->h[e] : lag(S, ai[e], xi[e]);
+  return v;
+}
+
+/* Cell quadrature: calls fn at every tensor Gauss point with weight w*|K|. */
+typedef struct { int a, b, dir; } pair_arg;
+
+static double cell_integral(const or_setup *S, int kind, pair_arg p) {
+  /* kind 0: m_ab = int phi_a phi_b ; kind 1: int d_dir phi_b phi_a ; kind 2: int phi_a */
+  double jac = 1.0;
+  for (int e = 0; e < S->dim; ++e) jac *= S->h[e];
+  int nq = S->nq, tot = 1;
+  for (int e = 0; e < S->dim; ++e) tot *= nq;
+  double sum = 0.0;
+  for (int q = 0; q < tot; ++q) {
+    double xi[3] = {0, 0, 0}, w = 1.0;
+    int r = q;
+    for (int e = 0; e < S->dim; ++e) { xi[e] = S->xq[r % nq]; w *= S->wq[r % nq]; r /= nq; }
+    double g;
+    if (kind == 0) g = phi(S, p.a, xi) * phi(S, p.b, xi);
+    else if (kind == 1) g = dphi(S, p.b, p.dir, xi) * phi(S, p.a, xi);
+    else g = phi(S, p.a, xi);
+    sum += w * g;
+  }
+  return sum * jac;
+}
+
+/* Face integral over face f of a cell: int_F phi_a^(A) phi_b^(B) ds where
+ * phi_b is either a basis function of the same cell (same_cell = 1) or of the
+ * neighbour across f (conforming uniform cells: the neighbour's reference
+ * coordinate normal to the face is 1 - side).  b < 0 means "phi_b = 1". */
+static double face_integral(const or_setup *S, int f, int a, int b, int same_cell) {
+  int e = f / 2, side = f % 2;
+  double area = 1.0;
+  for (int d = 0; d < S->dim; ++d) if (d != e) area *= S->h[d];
+  int nq = S->nq, tot = 1;
+  for (int d = 0; d < S->dim - 1; ++d) tot *= nq;
+  double sum = 0.0;
+  for (int q = 0; q < tot; ++q) {
+    double xi[3] = {0, 0, 0}, w = 1.0;
+    int r = q;
+    for (int d = 0; d < S->dim; ++d) {
+      if (d == e) { xi[d] = side ? 1.0 : 0.0; continue; }
+      xi[d] = S->xq[r % nq]; w *= S->wq[r % nq]; r /= nq;
+    }
+    double va = phi(S, a, xi), vb = 1.0;
+    if (b >= 0) {
+      double xb[3] = {xi[0], xi[1], xi[2]};
+      if (!same_cell) xb[e] = 1.0 - xi[e];
+      vb = phi(S, b, xb);
+    }
+    sum += w * va * vb;
+  }
+  return sum * area;
+}
+
+/* c_ij written out from eq. cij_def1 / cij_def2 for one ordered pair. */
+static void literal_cij(const or_setup *S, long i, long j, double *out) {
+  long Ki = i / S->nloc, Kj = j / S->nloc;
+  int a = (int)(i % S->nloc), b = (int)(j % S->nloc);
+  int ai[3], bi[3];
+  local_multi(S, a, ai);
+  local_multi(S, b, bi);
+  for (int e = 0; e < S->dim; ++e) out[e] = 0.0;
+  if (Ki == Kj) {
+    for (int e = 0; e < S->dim; ++e) {
+      pair_arg p = {a, b, e};
+      double cK = cell_integral(S, 1, p);
+      /* c^{dK}: half the boundary integral over all faces of K, outward n */
+      double cdK = 0.0;
+      for (int side = 0; side < 2; ++side) {
+        int f = 2 * e + side;
+        double n = side ? 1.0 : -1.0;
+        cdK += 0.5 * n * face_integral(S, f, a, b, 1);
+      }
+      out[e] = cK - cdK;
+    }
+    return;
+  }
+  /* different cells: the face of K_i shared with K_j that carries both nodes */
+  for (int f = 0; f < 2 * S->dim; ++f) {
+    int e = f / 2, side = f % 2;
+    if (ai[e] != side * S->deg) continue;
+    if (bi[e] != (1 - side) * S->deg) continue;
+    if (neighbour(S, Ki, f) != Kj) continue;
+    double n = side ? 1.0 : -1.0;
+    out[e] = 0.5 * n * face_integral(S, f, a, b, 0);
+    return;
+  }
+}
+
+/* Reading R3: c_ji is stored as exactly -c_ij, the pair evaluated from the
+ * lower index; c_ii = 0 (Lemma PropSkew). */
+static void canonical_cij(const or_setup *S, long i, long j, double *out) {
+  if (i == j) { for (int e = 0; e < S->dim; ++e) out[e] = 0.0; return; }
+  if (i < j) { literal_cij(S, i, j, out); return; }
+  literal_cij(S, j, i, out);
+  for (int e = 0; e < S->dim; ++e) out[e] = -out[e];
+}
+
+void or_destroy(or_setup *S) {
+  if (!S) return;
+  free(S->rowptr); free(S->col); free(S->c); free(S->mij); free(S->kind); free(S->mi);
+  free(S->bptr); free(S->bface); free(S->bc_c);
+  free(S);
+}
+
+/* Setup: GL nodes, cell-major numbering, m_ij, m_i, c_ij, c_i^{d,k} (Sec. 2.3,
+ * Sec. 4.2).  Exact Gauss-Legendre integration with k+1 points (reading R5). */
+or_setup *or_create(int dim, int deg, const long *cells, const double *lo, const double *hi,
+                    const int *bc) {
+  if (dim < 1 || dim > 3 || deg < 1 || deg > 2) return NULL;
+  or_setup *S = (or_setup *)calloc(1, sizeof(or_setup));
+  S->dim = dim; S->deg = deg; S->nb1 = deg + 1; S->m = dim + 2;
+  S->nloc = 1;
+  for (int e = 0; e < dim; ++e) S->nloc *= S->nb1;
+  S->ncells = 1; S->vol = 1.0;
+  for (int e = 0; e < 3; ++e) {
+    S->n[e] = e < dim ? cells[e] : 1;
+    S->lo[e] = e < dim ? lo[e] : 0.0;
+    S->hi[e] = e < dim ? hi[e] : 1.0;
+    S->h[e] = (S->hi[e] - S->lo[e]) / (double)S->n[e];
+    if (e < dim) { S->ncells *= S->n[e]; S->vol *= S->hi[e] - S->lo[e]; }
+  }
+  for (int f = 0; f < 6; ++f) S->bc[f] = f < 2 * dim ? bc[f] : OR_BC_OUTFLOW;
+  for (int e = 0; e < dim; ++e) {
+    int p0 = S->bc[2 * e] == OR_BC_PERIODIC, p1 = S->bc[2 * e + 1] == OR_BC_PERIODIC;
+    if (p0 != p1 || (p0 && S->n[e] < 2) || S->n[e] < 1) { free(S); return NULL; }
+  }
+  S->ndofs = S->ncells * S->nloc;
+  if (deg == 1) { S->xg[0] = 0.0; S->xg[1] = 1.0; }
+  else { S->xg[0] = 0.0; S->xg[1] = 0.5; S->xg[2] = 1.0; }
+  S->nq = deg + 1;
+  if (deg == 1) {
+    double r = 0.5 / sqrt(3.0);
+    S->xq[0] = 0.5 - r; S->xq[1] = 0.5 + r; S->wq[0] = S->wq[1] = 0.5;
+  } else {
+    double r = 0.5 * sqrt(0.6);
+    S->xq[0] = 0.5 - r; S->xq[1] = 0.5; S->xq[2] = 0.5 + r;
+    S->wq[0] = S->wq[2] = 5.0 / 18.0; S->wq[1] = 8.0 / 18.0;
+  }
+
+  long N = S->ndofs;
+  int nloc = S->nloc;
+  /* stencil rows: all in-cell dofs, then face neighbours on each face i lies on */
+  S->rowptr = (long *)calloc(N + 1, sizeof(long));
+  S->bptr = (long *)calloc(N + 1, sizeof(long));
+  long cap = N * (nloc + 2 * dim * nloc), bcap = N * dim + 1;
+  S->col = (long *)malloc(cap * sizeof(long));
+  S->c = (double *)malloc(cap * dim * sizeof(double));
+  S->mij = (double *)malloc(cap * sizeof(double));
+  S->kind = (int *)malloc(cap * sizeof(int));
+  S->mi = (double *)malloc(N * sizeof(double));
+  S->bface = (int *)malloc(bcap * sizeof(int));
+  S->bc_c = (double *)malloc(bcap * dim * sizeof(double));
+
+  /* reference cell quantities (identical for every uniform cell, but computed
+   * per row so the code reads as the definition) */
+  double *Mloc = (double *)malloc(nloc * nloc * sizeof(double));
+  double *mloc = (double *)malloc(nloc * sizeof(double));
+  for (int a = 0; a < nloc; ++a) {
+    pair_arg p = {a, 0, 0};
+    mloc[a] = cell_integral(S, 2, p);
+    for (int b = 0; b < nloc; ++b) {
+      pair_arg q = {a, b, 0};
+      Mloc[a * nloc + b] = cell_integral(S, 0, q);
+    }
+  }
+
+  long nnz = 0, nb = 0;
+  for (long i = 0; i < N; ++i) {
+    long K = i / nloc;
+    int a = (int)(i % nloc), ai[3];
+    local_multi(S, a, ai);
+    S->rowptr[i] = nnz;
+    S->bptr[i] = nb;
+    S->mi[i] = mloc[a];
+    for (int b = 0; b < nloc; ++b) {
+      long j = K * nloc + b;
+      S->col[nnz] = j;
+      canonical_cij(S, i, j, S->c + nnz * dim);
+      S->mij[nnz] = Mloc[a * nloc + b];
+      S->kind[nnz] = OR_KIND_CELL;
+      ++nnz;
+    }
+    for (int f = 0; f < 2 * dim; ++f) {
+      int e = f / 2, side = f % 2;
+      if (ai[e] != side * deg) continue;
+      long Kn = neighbour(S, K, f);
+      if (Kn >= 0) {
+        for (int b = 0; b < nloc; ++b) {
+          int bi[3];
+          local_multi(S, b, bi);
+          if (bi[e] != (1 - side) * deg) continue;
+          long j = Kn * nloc + b;
+          int colloc = 1;
+          for (int d = 0; d < dim; ++d) if (d != e && bi[d] != ai[d]) colloc = 0;
+          S->col[nnz] = j;
+          canonical_cij(S, i, j, S->c + nnz * dim);
+          S->mij[nnz] = 0.0;
+          S->kind[nnz] = colloc ? OR_KIND_FACE_COLLOC : OR_KIND_FACE;
+          ++nnz;
+        }
+      } else {
+        /* boundary part k = face f: c_i^{d,k} = 1/2 int_{dK cap dOmega_k} phi_i n */
+        double n = side ? 1.0 : -1.0;
+        for (int d = 0; d < dim; ++d) S->bc_c[nb * dim + d] = 0.0;
+        S->bc_c[nb * dim + e] = 0.5 * n * face_integral(S, f, a, -1, 1);
+        S->bface[nb] = f;
+        ++nb;
+      }
+    }
+  }
+  S->rowptr[N] = nnz;
+  S->bptr[N] = nb;
+  free(Mloc);
+  free(mloc);
+  return S;
+}
+
+long or_num_dofs(const or_setup *S) { return S->ndofs; }
+long or_nnz(const or_setup *S) { return S->rowptr[S->ndofs]; }
+long or_nbnd(const or_setup *S) { return S->bptr[S->ndofs]; }
+double or_volume(const or_setup *S) { return S->vol; }
+
+void or_csr(const or_setup *S, long *rowptr, long *col, double *c, double *mij, int *kind) {
+  long N = S->ndofs, nnz = S->rowptr[N];
+  memcpy(rowptr, S->rowptr, (N + 1) * sizeof(long));
+  memcpy(col, S->col, nnz * sizeof(long));
+  memcpy(c, S->c, nnz * S->dim * sizeof(double));
+  memcpy(mij, S->mij, nnz * sizeof(double));
+  memcpy(kind, S->kind, nnz * sizeof(int));
+}
+
+void or_lumped(const or_setup *S, double *mi) { memcpy(mi, S->mi, S->ndofs * sizeof(double)); }
+
+void or_boundary(const or_setup *S, long *bptr, int *bface, double *bc_c) {
+  long N = S->ndofs, nb = S->bptr[N];
+  memcpy(bptr, S->bptr, (N + 1) * sizeof(long));
+  memcpy(bface, S->bface, nb * sizeof(int));
+  memcpy(bc_c, S->bc_c, nb * S->dim * sizeof(double));
+}
+
+/* Collocation points x_i. */
+void or_node_coords(const or_setup *S, double *xyz) {
+  for (long i = 0; i < S->ndofs; ++i) {
+    long ki[3];
+    int ai[3];
+    cell_multi(S, i / S->nloc, ki);
+    local_multi(S, (int)(i % S->nloc), ai);
+    for (int e = 0; e < S->dim; ++e)
+      xyz[i * S->dim + e] = S->lo[e] + (ki[e] + S->xg[ai[e]]) * S->h[e];
+  }
+}
+
+/* literal c_ij for both orders (pins Lemma PropSkew without the R3 reading) */
+void or_literal_cij(const or_setup *S, long i, long j, double *out) { literal_cij(S, i, j, out); }
+
+/* ------------------------------------------------------------------------ */
+/* Euler physics (Sec. 2.2)                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* internal energy per volume eps = E - |m|^2/(2 rho), eq. PressurEuler */
+static double eps_of(int dim, const double *U) {
+  double m2 = 0.0;
+  for (int e = 0; e < dim; ++e) m2 += U[1 + e] * U[1 + e];
+  return U[dim + 1] - 0.5 * m2 / U[0];
+}
+
+static double pres_of(double g, int dim, const double *U) { return (g - 1.0) * eps_of(dim, U); }
+
+/* specific entropy s = log(rho^-gamma p), eq. EntropyEuler */
+static double spec_entropy(double g, int dim, const double *U) {
+  return log(pow(U[0], -g) * pres_of(g, dim, U));
+}
+
+/* rescaled entropy s~ = rho^-gamma eps (Sec. 5.4) */
+static double stilde(double g, int dim, const double *U) {
+  return pow(U[0], -g) * eps_of(dim, U);
+}
+
+/* f(U) c, the flux of eq. euler_flux applied to a vector c */
+static void flux_dot(double g, int dim, const double *U, const double *c, double *out) {
+  double rho = U[0], E = U[dim + 1], p = pres_of(g, dim, U);
+  double mc = 0.0;
+  for (int e = 0; e < dim; ++e) mc += U[1 + e] * c[e];
+  out[0] = mc;
+  for (int e = 0; e < dim; ++e) out[1 + e] = U[1 + e] * mc / rho + p * c[e];
+  out[dim + 1] = (E + p) * mc / rho;
+}
+
+/* Reading R1: lambda^+ is the two-rarefaction upper bound of Guermond & Popov
+ * (2016) for 1 < gamma <= 5/3, evaluated without Newton refinement; a
+ * non-positive numerator means vacuum, p* = 0. */
+double or_lambda_max(double g, int dim, const double *UL, const double *UR, const double *n) {
+  double rl = UL[0], rr = UR[0];
+  double ul = 0.0, ur = 0.0;
+  for (int e = 0; e < dim; ++e) { ul += UL[1 + e] * n[e]; ur += UR[1 + e] * n[e]; }
+  ul /= rl; ur /= rr;
+  double pl = pres_of(g, dim, UL), pr = pres_of(g, dim, UR);
+  double al = sqrt(g * pl / rl), ar = sqrt(g * pr / rr);
+  double alpha = (g - 1.0) / (2.0 * g);
+  double num = al + ar - 0.5 * (g - 1.0) * (ur - ul);
+  double den = al * pow(pl, -alpha) + ar * pow(pr, -alpha);
+  double pstar = num > 0.0 ? pow(num / den, 1.0 / alpha) : 0.0;
+  double kfac = (g + 1.0) / (2.0 * g);
+  double lam1 = ul - al * sqrt(1.0 + kfac * fmax(pstar - pl, 0.0) / pl);
+  double lam3 = ur + ar * sqrt(1.0 + kfac * fmax(pstar - pr, 0.0) / pr);
+  double lm = fmax(-lam1, lam3);
+  return fmax(lm, 0.0);
+}
+
+/* Exact 1D Riemann solver (textbook: Toro 2009, Ch. 4).  Test support only:
+ * the reference solution for the shock tube and the brute-force check of
+ * the wave-speed bound.  Returns 0, or 1 when a vacuum forms. */
+static double toro_f(double g, double p, double rk, double pk, double ak, double *df) {
+  if (p > pk) {
+    double A = 2.0 / ((g + 1.0) * rk), B = (g - 1.0) / (g + 1.0) * pk;
+    double q = sqrt(A / (p + B));
+    *df = q * (1.0 - 0.5 * (p - pk) / (p + B));
+    return (p - pk) * q;
+  }
+  double ex = (g - 1.0) / (2.0 * g);
+  *df = 1.0 / (rk * ak) * pow(p / pk, -(g + 1.0) / (2.0 * g));
+  return 2.0 * ak / (g - 1.0) * (pow(p / pk, ex) - 1.0);
+}
+
+int or_exact_riemann(double g, double rl, double ul, double pl, double rr, double ur, double pr,
+                     double *pstar, double *ustar) {
+  double al = sqrt(g * pl / rl), ar = sqrt(g * pr / rr);
+  double d0, d1;
+  double phi0 = toro_f(g, 0.0, rl, pl, al, &d0) + toro_f(g, 0.0, rr, pr, ar, &d1) + ur - ul;
+  if (phi0 >= 0.0) { *pstar = 0.0; *ustar = 0.5 * (ul + ur); return 1; }
+  /* bracket [0, hi] with phi(hi) > 0, then bisect to full precision */
+  double lo = 0.0, hi = fmax(pl, pr);
+  for (int it = 0; it < 200; ++it) {
+    double v = toro_f(g, hi, rl, pl, al, &d0) + toro_f(g, hi, rr, pr, ar, &d1) + ur - ul;
+    if (v > 0.0) break;
+    lo = hi;
+    hi *= 2.0;
+  }
+  for (int it = 0; it < 2000; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    double v = toro_f(g, mid, rl, pl, al, &d0) + toro_f(g, mid, rr, pr, ar, &d1) + ur - ul;
+    if (v > 0.0) hi = mid; else lo = mid;
+  }
+  double p = 0.5 * (lo + hi);
+  double fl = toro_f(g, p, rl, pl, al, &d0), fr = toro_f(g, p, rr, pr, ar, &d1);
+  *pstar = p;
+  *ustar = 0.5 * (ul + ur) + 0.5 * (fr - fl);
+  return 0;
+}
+
+/* Largest wave speed of the exact solution: the same wave-speed formulas as
+ * the bound, evaluated at the exact p*. */
+double or_exact_lambda(double g, double rl, double ul, double pl, double rr, double ur, double pr) {
+  double ps, us;
+  or_exact_riemann(g, rl, ul, pl, rr, ur, pr, &ps, &us);
+  double al = sqrt(g * pl / rl), ar = sqrt(g * pr / rr);
+  double kfac = (g + 1.0) / (2.0 * g);
+  double lam1 = ul - al * sqrt(1.0 + kfac * fmax(ps - pl, 0.0) / pl);
+  double lam3 = ur + ar * sqrt(1.0 + kfac * fmax(ps - pr, 0.0) / pr);
+  return fmax(fmax(-lam1, lam3), 0.0);
+}
+
+/* Sample the exact self-similar solution at xi = x/t. */
+void or_riemann_sample(double g, double rl, double ul, double pl, double rr, double ur, double pr,
+                       double xi, double *out /* rho, u, p */) {
+  double ps, us;
+  or_exact_riemann(g, rl, ul, pl, rr, ur, pr, &ps, &us);
+  double al = sqrt(g * pl / rl), ar = sqrt(g * pr / rr);
+  double gm = (g - 1.0) / (g + 1.0);
+  double r, u, p;
+  if (xi <= us) {
+    if (ps > pl) { /* left shock */
+      double sl = ul - al * sqrt((g + 1.0) / (2.0 * g) * ps / pl + (g - 1.0) / (2.0 * g));
+      if (xi <= sl) { r = rl; u = ul; p = pl; }
+      else { r = rl * (ps / pl + gm) / (gm * ps / pl + 1.0); u = us; p = ps; }
+    } else { /* left rarefaction */
+      double head = ul - al, ast = al * pow(ps / pl, (g - 1.0) / (2.0 * g)), tail = us - ast;
+      if (xi <= head) { r = rl; u = ul; p = pl; }
+      else if (xi >= tail) { r = rl * pow(ps / pl, 1.0 / g); u = us; p = ps; }
+      else {
+        u = 2.0 / (g + 1.0) * (al + 0.5 * (g - 1.0) * ul + xi);
+        double c = 2.0 / (g + 1.0) * (al + 0.5 * (g - 1.0) * (ul - xi));
+        r = rl * pow(c / al, 2.0 / (g - 1.0));
+        p = pl * pow(c / al, 2.0 * g / (g - 1.0));
+      }
+    }
+  } else {
+    if (ps > pr) { /* right shock */
+      double sr = ur + ar * sqrt((g + 1.0) / (2.0 * g) * ps / pr + (g - 1.0) / (2.0 * g));
+      if (xi >= sr) { r = rr; u = ur; p = pr; }
+      else { r = rr * (ps / pr + gm) / (gm * ps / pr + 1.0); u = us; p = ps; }
+    } else { /* right rarefaction */
+      double head = ur + ar, ast = ar * pow(ps / pr, (g - 1.0) / (2.0 * g)), tail = us + ast;
+      if (xi >= head) { r = rr; u = ur; p = pr; }
+      else if (xi <= tail) { r = rr * pow(ps / pr, 1.0 / g); u = us; p = ps; }
+      else {
+        u = 2.0 / (g + 1.0) * (-ar + 0.5 * (g - 1.0) * ur + xi);
+        double c = 2.0 / (g + 1.0) * (ar - 0.5 * (g - 1.0) * (ur - xi));
+        r = rr * pow(c / ar, 2.0 / (g - 1.0));
+        p = pr * pow(c / ar, 2.0 * g / (g - 1.0));
+      }
+    }
+  }
+  out[0] = r; out[1] = u; out[2] = p;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Boundary data (Sec. 4.1)                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Ghost state U^{d,k} for boundary part face f of row i.  Outflow is read as
+ * the supersonic-outflow branch U^d := U_i (reading R28); slip reflects the
+ * normal momentum, eq. slip_boundary, with n = c_i^{d,k}/|c_i^{d,k}|. */
+static void ghost_state(const or_setup *S, int bkind, const double *Ui, const double *cb, double *Ug) {
+  int dim = S->dim;
+  for (int c = 0; c < S->m; ++c) Ug[c] = Ui[c];
+  if (bkind == OR_BC_SLIP) {
+    double nn = 0.0;
+    for (int e = 0; e < dim; ++e) nn += cb[e] * cb[e];
+    nn = sqrt(nn);
+    double mn = 0.0;
+    for (int e = 0; e < dim; ++e) mn += Ui[1 + e] * cb[e] / nn;
+    for (int e = 0; e < dim; ++e) Ug[1 + e] = Ui[1 + e] - 2.0 * mn * cb[e] / nn;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* One forward-Euler stage of the scheme                                      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  double tau_max;   /* min_i -m_i/(2 d_ii) of the input state, eq. MaxCFLdt */
+  double *N;        /* N entropy-viscosity ratio per row (may be NULL) */
+  double *rho_min, *rho_max, *s_min; /* relaxed bounds, eq. local_bounds */
+  double *UL;       /* low-order update, m*N SoA */
+  double *dUH;      /* high-order increment U^H - U, m*N SoA */
+  double *U1;       /* after limiter pass 1, m*N SoA */
+  double *dij;      /* d^L per CSR entry */
+  double *lij;      /* l_ij of pass 1 per CSR entry */
+  double *lbd;      /* l_i^d of pass 1 per row */
+  double *Aij;      /* A_ij per CSR entry, m per entry */
+  double *Abd;      /* A_i^d per row, m per row */
+} or_diag;
+
+static void get_state(const or_setup *S, const double *U, long i, double *out) {
+  for (int c = 0; c < S->m; ++c) out[c] = U[c * S->ndofs + i];
+}
+
+static double norm_c(int dim, const double *c) {
+  double s = 0.0;
+  for (int e = 0; e < dim; ++e) s += c[e] * c[e];
+  return sqrt(s);
+}
+
+/* d^L_ij = |c_ij| lambda^+(U_i, U_j, n_ij) evaluated from the lower index
+ * (reading R3), so that d_ij = d_ji holds exactly. */
+static double dij_low(const or_setup *S, double g, const double *U, long i, long j, const double *cij) {
+  int dim = S->dim;
+  double nc = norm_c(dim, cij);
+  if (nc == 0.0) return 0.0;
+  double Ua[OR_MAXM], Ub[OR_MAXM], n[3];
+  long a = i < j ? i : j, b = i < j ? j : i;
+  double sgn = i < j ? 1.0 : -1.0;
+  get_state(S, U, a, Ua);
+  get_state(S, U, b, Ub);
+  for (int e = 0; e < dim; ++e) n[e] = sgn * cij[e] / nc;
+  return nc * or_lambda_max(g, dim, Ua, Ub, n);
+}
+
+/* Line search on the density bounds: largest l in [0, 1] with
+ * rho_min <= rho(U + l P) <= rho_max. */
+static double ls_rho(double r, double pr, double rmin, double rmax) {
+  double l = 1.0;
+  if (r + pr > rmax) l = (rmax - r) / pr;
+  if (r + pr < rmin) l = (rmin - r) / pr;
+  if (!(l > 0.0)) l = 0.0;
+  if (l > 1.0) l = 1.0;
+  return l;
+}
+
+/* psi(l) = eps(U + l P) - s_min rho(U + l P)^gamma, concave in l. */
+static double ls_psi(double g, int dim, const double *U, const double *P, double smin, double l,
+                     double *dpsi) {
+  double V[OR_MAXM];
+  for (int c = 0; c < dim + 2; ++c) V[c] = U[c] + l * P[c];
+  double eps = eps_of(dim, V);
+  double rg = pow(V[0], g);
+  if (dpsi) {
+    double u2 = 0.0, dot = 0.0;
+    for (int e = 0; e < dim; ++e) {
+      double u = V[1 + e] / V[0];
+      u2 += u * u;
+      dot -= u * P[1 + e];
+    }
+    dot += 0.5 * u2 * P[0] + P[dim + 1];
+    *dpsi = dot - smin * g * rg / V[0] * P[0];
+  }
+  return eps - smin * rg;
+}
+
+#define OR_LS_TOL 1e-14
+#define OR_LS_MAXIT 60
+
+/* Reading R16: line search for the rescaled-entropy bound.  Largest l in
+ * [0, lhi] with s~(U + l P) >= s_min, found on the concave psi by a bracket
+ * [l, r] (psi(l) >= 0 > psi(r)) narrowed with a secant step (lands on the
+ * feasible side) and a tangent step at r (lands on the infeasible side) until
+ * r - l <= 1e-14; the feasible end is returned. */
+static double ls_entropy(double g, int dim, const double *U, const double *P, double smin, double lhi) {
+  double ph = ls_psi(g, dim, U, P, smin, lhi, NULL);
+  if (ph >= 0.0) return lhi;
+  double p0 = ls_psi(g, dim, U, P, smin, 0.0, NULL);
+  if (p0 <= 0.0) return 0.0;
+  double l = 0.0, r = lhi, pl = p0, pr = ph;
+  for (int it = 0; it < OR_LS_MAXIT; ++it) {
+    if (r - l <= OR_LS_TOL) break;
+    /* secant */
+    double x = l + pl * (r - l) / (pl - pr);
+    if (!(x > l && x < r)) x = 0.5 * (l + r);
+    double px = ls_psi(g, dim, U, P, smin, x, NULL);
+    if (px >= 0.0) { l = x; pl = px; } else { r = x; pr = px; }
+    if (r - l <= OR_LS_TOL) break;
+    /* tangent at the infeasible end */
+    double dr;
+    ls_psi(g, dim, U, P, smin, r, &dr);
+    x = dr < 0.0 ? r - pr / dr : 0.5 * (l + r);
+    if (!(x > l && x < r)) x = 0.5 * (l + r);
+    px = ls_psi(g, dim, U, P, smin, x, NULL);
+    if (px >= 0.0) { l = x; pl = px; } else { r = x; pr = px; }
+  }
+  return l;
+}
+
+/* Line search LS(U, P, B): the density part, then the entropy part on
+ * [0, l_rho] (Sec. 5.4, Lemma ConsInvariants). */
+static double line_search(double g, int dim, const double *U, const double *P, double rmin,
+                          double rmax, double smin) {
+  double lr = ls_rho(U[0], P[0], rmin, rmax);
+  return ls_entropy(g, dim, U, P, smin, lr);
+}
+
+/* Dense LU solve (partial pivoting) of the n x n cell mass block, reading R6. */
+static void dense_solve(int n, double *A, double *b) {
+  int piv[64];
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    for (int r = k + 1; r < n; ++r) if (fabs(A[r * n + k]) > fabs(A[p * n + k])) p = r;
+    piv[k] = p;
+    if (p != k) {
+      for (int c = 0; c < n; ++c) { double t = A[k * n + c]; A[k * n + c] = A[p * n + c]; A[p * n + c] = t; }
+      double t = b[k]; b[k] = b[p]; b[p] = t;
+    }
+    for (int r = k + 1; r < n; ++r) {
+      double f = A[r * n + k] / A[k * n + k];
+      for (int c = k; c < n; ++c) A[r * n + c] -= f * A[k * n + c];
+      b[r] -= f * b[k];
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    double s = b[k];
+    for (int c = k + 1; c < n; ++c) s -= A[k * n + c] * b[c];
+    b[k] = s / A[k * n + k];
+  }
+  (void)piv;
+}
+
+static double *dalloc(long n) { return (double *)calloc(n > 0 ? n : 1, sizeof(double)); }
+
+/* Phi(U; tau): one forward-Euler step of the scheme selected by P->scheme.
+ * tau <= 0 selects tau = Cr * tau_max of this state (eq. MaxCFLdt).
+ * Returns 0 on success, -2 if the output leaves the admissible set. */
+int or_stage(const or_setup *S, const or_params *P, const double *U, double tau, double *Uout,
+             or_diag *dg) {
+  const int dim = S->dim, m = S->m;
+  const long N = S->ndofs, nnz = S->rowptr[N];
+  const double g = P->gamma;
+  double *dij = dalloc(nnz), *dbd = dalloc(S->bptr[N]), *dii = dalloc(N);
+  double *UL = dalloc(m * N), *Nr = dalloc(N), *dH = dalloc(nnz), *dbH = dalloc(S->bptr[N]);
+  double *dUH = dalloc(m * N), *A = dalloc(nnz * m), *Ab = dalloc(N * m);
+  double *qrmin = dalloc(N), *qrmax = dalloc(N), *qsmin = dalloc(N);
+  double *Brmin = dalloc(N), *Brmax = dalloc(N), *Bsmin = dalloc(N);
+  double *l1 = dalloc(nnz), *lb1 = dalloc(N), *U1 = dalloc(m * N);
+  double *Ug = dalloc((S->bptr[N] + 1) * m);
+  int status = 0;
+
+  /* Sec. 4.1: boundary data per boundary part */
+  for (long i = 0; i < N; ++i) {
+    double Ui[OR_MAXM];
+    get_state(S, U, i, Ui);
+    for (long b = S->bptr[i]; b < S->bptr[i + 1]; ++b)
+      ghost_state(S, S->bc[S->bface[b]], Ui, S->bc_c + b * dim, Ug + b * m);
+  }
+
+  /* eq. dij_low_order, dij_low_order_modified (reading R2: inside state on
+   * the left, outward normal), eq. dij_low_order_supplement */
+  double tmax = INFINITY;
+#pragma omp parallel for schedule(static) reduction(min : tmax)
+  for (long i = 0; i < N; ++i) {
+    double s = 0.0;
+    for (long k = S->rowptr[i]; k < S->rowptr[i + 1]; ++k) {
+      long j = S->col[k];
+      dij[k] = (j == i) ? 0.0 : dij_low(S, g, U, i, j, S->c + k * dim);
+      if (j != i) s += dij[k];
+    }
+    double Ui[OR_MAXM];
+    get_state(S, U, i, Ui);
+    for (long b = S->bptr[i]; b < S->bptr[i + 1]; ++b) {
+      const double *cb = S->bc_c + b * dim;
+      double nc = norm_c(dim, cb), n[3];
+      for (int e = 0; e < dim; ++e) n[e] = cb[e] / nc;
+      dbd[b] = nc * or_lambda_max(g, dim, Ui, Ug + b * m, n);
+      s += dbd[b];
+    }
+    dii[i] = -s;
+    double t = -S->mi[i] / (2.0 * dii[i]);
+    if (t < tmax) tmax = t;
+  }
+  if (tau <= 0.0) tau = P->cfl * tmax;
+
+  /* eq. cijdijscheme / cijdijschememodified: low-order update, with the
+   * flux sums in the difference form sum_j (f(U_j) - f(U_i)) c_ij that the
+   * proof of Lemma ConveRef derives from Lemma LemPart (reading R30) */
+#pragma omp parallel for schedule(static)
+  for (long i = 0; i < N; ++i) {
+    double Ui[OR_MAXM], Uj[OR_MAXM], acc[OR_MAXM] = {0}, fc[OR_MAXM], fi[OR_MAXM];
+    get_state(S, U, i, Ui);
+    for (long k = S->rowptr[i]; k < S->rowptr[i + 1]; ++k) {
+      long j = S->col[k];
+      get_state(S, U, j, Uj);
+      flux_dot(g, dim, Uj, S->c + k * dim, fc);
+      flux_dot(g, dim, Ui, S->c + k * dim, fi);
+      for (int c = 0; c < m; ++c) acc[c] += (fc[c] - fi[c]) - dij[k] * (Uj[c] - Ui[c]);
+    }
+    for (long b = S->bptr[i]; b < S->bptr[i + 1]; ++b) {
+      const double *Ub = Ug + b * m;
+      flux_dot(g, dim, Ub, S->bc_c + b * dim, fc);
+      flux_dot(g, dim, Ui, S->bc_c + b * dim, fi);
+      for (int c = 0; c < m; ++c) acc[c] += (fc[c] - fi[c]) - dbd[b] * (Ub[c] - Ui[c]);
+    }
+    for (int c = 0; c < m; ++c) UL[c * N + i] = Ui[c] - tau / S->mi[i] * acc[c];
+  }
+
+  if (P->scheme == OR_LOW_ORDER) {
+    memcpy(Uout, UL, m * N * sizeof(double));
+    goto finish;
+  }
+
+  /* eq. UsualBarState: ring-1 partial bounds over k in I(j) (reading R18:
+   * the diagonal contributes U_j itself, no bar state; reading R19: pairs
+   * with c = 0 have no bar state) */
+#pragma omp parallel for schedule(static)
+  for (long j = 0; j < N; ++j) {
+    double Uj[OR_MAXM], Uk[OR_MAXM], fj[OR_MAXM], fk[OR_MAXM], Ub[OR_MAXM];
+    get_state(S, U, j, Uj);
+    double rmin = INFINITY, rmax = -INFINITY, smin = INFINITY;
+    for (long k = S->rowptr[j]; k < S->rowptr[j + 1]; ++k) {
+      long kk = S->col[k];
+      get_state(S, U, kk, Uk);
+      rmin = fmin(rmin, Uk[0]);
+      rmax = fmax(rmax, Uk[0]);
+      smin = fmin(smin, stilde(g, dim, Uk));
+      if (kk == j || dij[k] == 0.0) continue;
+      const double *c = S->c + k * dim;
+      flux_dot(g, dim, Uj, c, fj);
+      flux_dot(g, dim, Uk, c, fk);
+      for (int q = 0; q < m; ++q) Ub[q] = 0.5 * (Uj[q] + Uk[q]) - (fk[q] - fj[q]) / (2.0 * dij[k]);
+      rmin = fmin(rmin, Ub[0]);
+      rmax = fmax(rmax, Ub[0]);
+      smin = fmin(smin, stilde(g, dim, Ub));
+    }
+    qrmin[j] = rmin; qrmax[j] = rmax; qsmin[j] = smin;
+  }
+
+  /* Sec. 5.2 entropy viscosity: Harten entropy f(s) = exp(s/(gamma+1))
+   * (reading R8), gradient of the shifted entropy at U_i (reading R9), D_i as
+   * the sum of absolute parts so |N_i| <= 1 (reading R10), the boundary part
+   * included as a ghost neighbour (reading R11), flux sums in the difference
+   * form (reading R30) so a constant state gives R_i = D_i = 0 exactly. */
+#pragma omp parallel for schedule(static)
+  for (long i = 0; i < N; ++i) {
+    double Ui[OR_MAXM], Uj[OR_MAXM], fc[OR_MAXM], fi[OR_MAXM], grad[OR_MAXM], Sk[OR_MAXM] = {0};
+    get_state(S, U, i, Ui);
+    double si = spec_entropy(g, dim, Ui);
+    double fsi = exp(si / (g + 1.0)), dfsi = fsi / (g + 1.0);
+    double rho = Ui[0], p = pres_of(g, dim, Ui), u2 = 0.0;
+    for (int e = 0; e < dim; ++e) u2 += (Ui[1 + e] / rho) * (Ui[1 + e] / rho);
+    /* grad s = (gamma-1)/p (|u|^2/2, -u, 1) - (gamma/rho, 0, 0) */
+    grad[0] = (g - 1.0) / p * 0.5 * u2 - g / rho;
+    for (int e = 0; e < dim; ++e) grad[1 + e] = -(g - 1.0) / p * (Ui[1 + e] / rho);
+    grad[dim + 1] = (g - 1.0) / p;
+    for (int c = 0; c < m; ++c) grad[c] *= rho * dfsi;
+    double T = 0.0;
+    for (long k = S->rowptr[i]; k < S->rowptr[i + 1]; ++k) {
+      long j = S->col[k];
+      get_state(S, U, j, Uj);
+      const double *c = S->c + k * dim;
+      double fsj = exp(spec_entropy(g, dim, Uj) / (g + 1.0));
+      double mc = 0.0;
+      for (int e = 0; e < dim; ++e) mc += Uj[1 + e] * c[e];
+      T += mc * (fsj - fsi);
+      flux_dot(g, dim, Uj, c, fc);
+      flux_dot(g, dim, Ui, c, fi);
+      for (int q = 0; q < m; ++q) Sk[q] += fc[q] - fi[q];
+    }
+    for (long b = S->bptr[i]; b < S->bptr[i + 1]; ++b) {
+      const double *Ub = Ug + b * m, *c = S->bc_c + b * dim;
+      double fsb = exp(spec_entropy(g, dim, Ub) / (g + 1.0));
+      double mc = 0.0;
+      for (int e = 0; e < dim; ++e) mc += Ub[1 + e] * c[e];
+      T += mc * (fsb - fsi);
+      flux_dot(g, dim, Ub, c, fc);
+      flux_dot(g, dim, Ui, c, fi);
+      for (int q = 0; q < m; ++q) Sk[q] += fc[q] - fi[q];
+    }
+    double R = T, D = fabs(T);
+    for (int q = 0; q < m; ++q) { R -= grad[q] * Sk[q]; D += fabs(grad[q]) * fabs(Sk[q]); }
+    Nr[i] = D > 0.0 ? R / D : 0.0;
+  }
+
+  /* eq. HighOrderViscosity with eq. ViscMin (reading R12: collocation is
+   * topological) and the boundary analogue of reading R7 */
+  {
+    const double pk = (S->deg % 2 == 0) ? 0.5 : 0.0;
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < N; ++i) {
+      for (long k = S->rowptr[i]; k < S->rowptr[i + 1]; ++k) {
+        long j = S->col[k];
+        if (j == i) { dH[k] = 0.0; continue; }
+        double dev = dij[k] * fmin(P->c_ev * fmax(fabs(Nr[i]), fabs(Nr[j])), 1.0);
+        double dmin = 0.0;
+        if (S->kind[k] == OR_KIND_FACE_COLLOC) {
+          double hh = pow(0.5 * (S->mi[i] + S->mi[j]) / S->vol, 1.0 / dim);
+          dmin = P->c_k * pow(hh, pk) * dij[k];
+        }
+        dH[k] = fmax(dmin, dev);
+      }
+      for (long b = S->bptr[i]; b < S->bptr[i + 1]; ++b) {
+        double hh = pow(S->mi[i] / S->vol, 1.0 / dim);
+        double dmin = P->c_k * pow(hh, pk) * dbd[b];
+        double dev = dbd[b] * fmin(P->c_ev * fabs(Nr[i]), 1.0);
+        dbH[b] = fmax(dmin, dev);
+      }
+    }
+  }
+
+  /* eq. HighScheme: cell-local consistent-mass solve (reading R6) */
+  {
+    int nloc = S->nloc;
+#pragma omp parallel for schedule(static)
+    for (long K = 0; K < S->ncells; ++K) {
+      double Mk[27 * 27], rhs[OR_MAXM][27];
+      for (int a = 0; a < nloc; ++a) {
+        long i = K * nloc + a;
+        double Ui[OR_MAXM], Uj[OR_MAXM], fc[OR_MAXM], fi[OR_MAXM], acc[OR_MAXM] = {0};
+        get_state(S, U, i, Ui);
+        for (long k = S->rowptr[i]; k < S->rowptr[i + 1]; ++k) {
+          long j = S->col[k];
+          get_state(S, U, j, Uj);
+          flux_dot(g, dim, Uj, S->c + k * dim, fc);
+          flux_dot(g, dim, Ui, S->c + k * dim, fi);
+          for (int c = 0; c < m; ++c) acc[c] += (fc[c] - fi[c]) - dH[k] * (Uj[c] - Ui[c]);
+        }
+        for (long b = S->bptr[i]; b < S->bptr[i + 1]; ++b) {
+          const double *Ub = Ug + b * m;
+          flux_dot(g, dim, Ub, S->bc_c + b * dim, fc);
+          flux_dot(g, dim, Ui, S->bc_c + b * dim, fi);
+          for (int c = 0; c < m; ++c) acc[c] += (fc[c] - fi[c]) - dbH[b] * (Ub[c] - Ui[c]);
+        }
+        for (int c = 0; c < m; ++c) rhs[c][a] = -tau * acc[c];
+      }
+      for (int c = 0; c < m; ++c) {
+        /* m_ij of the cell, taken from the in-cell CSR entries */
+        for (int a = 0; a < nloc; ++a) {
+          long i = K * nloc + a;
+          for (long k = S->rowptr[i]; k < S->rowptr[i + 1]; ++k)
+            if (S->kind[k] == OR_KIND_CELL) Mk[a * nloc + (S->col[k] - K * nloc)] = S->mij[k];
+        }
+        dense_solve(nloc, Mk, rhs[c]);
+        for (int a = 0; a < nloc; ++a) dUH[c * N + K * nloc + a] = rhs[c][a];
+      }
+    }
+  }
+
+  if (P->scheme == OR_HIGH_ORDER) {
+    for (long q = 0; q < m * N; ++q) Uout[q] = U[q] + dUH[q];
+    goto finish;
+  }
+
+  /* eq. HighLowOrderIdentity: A_ij = tau (d^H - d^L)(U_j - U_i)
+   *   - (m_ij - delta_ij m_i)(dU^H_j - dU^H_i),  A_i^d = tau (d^dH - d^dL)(U^d - U_i) */
+#pragma omp parallel for schedule(static)
+  for (long i = 0; i < N; ++i) {
+    double Ui[OR_MAXM], Uj[OR_MAXM];
+    get_state(S, U, i, Ui);
+    for (long k = S->rowptr[i]; k < S->rowptr[i + 1]; ++k) {
+      long j = S->col[k];
+      get_state(S, U, j, Uj);
+      double mm = S->mij[k] - (j == i ? S->mi[i] : 0.0);
+      for (int c = 0; c < m; ++c)
+        A[k * m + c] = tau * (dH[k] - dij[k]) * (Uj[c] - Ui[c]) - mm * (dUH[c * N + j] - dUH[c * N + i]);
+    }
+    for (int c = 0; c < m; ++c) Ab[i * m + c] = 0.0;
+    for (long b = S->bptr[i]; b < S->bptr[i + 1]; ++b)
+      for (int c = 0; c < m; ++c) Ab[i * m + c] += tau * (dbH[b] - dbd[b]) * (Ug[b * m + c] - Ui[c]);
+  }
+
+  /* eq. local_bounds with relaxation r_h^{+-} = 1 +- c_r h_i^{p_r} */
+#pragma omp parallel for schedule(static)
+  for (long i = 0; i < N; ++i) {
+    double rmin = INFINITY, rmax = -INFINITY, smin = INFINITY;
+    double Ui[OR_MAXM], fi[OR_MAXM], fb[OR_MAXM], Ub[OR_MAXM];
+    get_state(S, U, i, Ui);
+    for (long b = S->bptr[i]; b < S->bptr[i + 1]; ++b) {
+      /* eq. BoundaryBarState */
+      const double *Ug_ = Ug + b * m, *c = S->bc_c + b * dim;
+      flux_dot(g, dim, Ui, c, fi);
+      flux_dot(g, dim, Ug_, c, fb);
+      for (int q = 0; q < m; ++q) Ub[q] = 0.5 * (Ug_[q] + Ui[q]) - (fb[q] - fi[q]) / (2.0 * dbd[b]);
+      rmin = fmin(rmin, Ub[0]);
+      rmax = fmax(rmax, Ub[0]);
+      smin = fmin(smin, stilde(g, dim, Ub));
+    }
+    for (long k = S->rowptr[i]; k < S->rowptr[i + 1]; ++k) {
+      long j = S->col[k];
+      rmin = fmin(rmin, qrmin[j]);
+      rmax = fmax(rmax, qrmax[j]);
+      smin = fmin(smin, qsmin[j]);
+    }
+    double hh = pow(S->mi[i] / S->vol, 1.0 / dim);
+    double rel = P->c_r * pow(hh, P->p_r);
+    Brmin[i] = (1.0 - rel) * rmin;
+    Brmax[i] = (1.0 + rel) * rmax;
+    Bsmin[i] = (1.0 - rel) * smin;
+  }
+
+  /* eq. ConvexScheme and Lemma ConsInvariants: kappa_i = 1/(card I(i) + 1)
+   * with I(i) the stored row (reading R4); l_ij = min(l^i_ij, l^j_ji)
+   * (reading R15); the boundary parts share one A_i^d (reading R27).  The
+   * second pass limits the remaining (1 - l) A from U^(1) against the same
+   * bounds (reading R14). */
+  {
+    const double *Ubase = UL;
+    double *Acur = A, *Abcur = Ab;
+    double *A2 = NULL, *Ab2 = NULL;
+    double *Unext = U1;
+    for (int pass = 0; pass < P->passes; ++pass) {
+      if (pass == 1) {
+        A2 = dalloc(nnz * m); Ab2 = dalloc(N * m);
+        for (long k = 0; k < nnz; ++k) for (int c = 0; c < m; ++c) A2[k * m + c] = (1.0 - l1[k]) * A[k * m + c];
+        for (long i = 0; i < N; ++i) for (int c = 0; c < m; ++c) Ab2[i * m + c] = (1.0 - lb1[i]) * Ab[i * m + c];
+        Acur = A2; Abcur = Ab2; Ubase = U1;
+        Unext = Uout;
+      }
+      double *lp = pass == 0 ? l1 : dalloc(nnz);
+      double *lbp = pass == 0 ? lb1 : dalloc(N);
+#pragma omp parallel for schedule(static)
+      for (long i = 0; i < N; ++i) {
+        double Li[OR_MAXM], Lj[OR_MAXM], Pv[OR_MAXM];
+        long leni = S->rowptr[i + 1] - S->rowptr[i];
+        double kap_i = 1.0 / (double)(leni + 1);
+        get_state(S, Ubase, i, Li);
+        double acc[OR_MAXM] = {0};
+        for (long k = S->rowptr[i]; k < S->rowptr[i + 1]; ++k) {
+          long j = S->col[k];
+          double li, lj;
+          for (int c = 0; c < m; ++c) Pv[c] = Acur[k * m + c] / (kap_i * S->mi[i]);
+          li = line_search(g, dim, Li, Pv, Brmin[i], Brmax[i], Bsmin[i]);
+          long lenj = S->rowptr[j + 1] - S->rowptr[j];
+          double kap_j = 1.0 / (double)(lenj + 1);
+          get_state(S, Ubase, j, Lj);
+          for (int c = 0; c < m; ++c) Pv[c] = -Acur[k * m + c] / (kap_j * S->mi[j]);
+          lj = line_search(g, dim, Lj, Pv, Brmin[j], Brmax[j], Bsmin[j]);
+          lp[k] = fmin(li, lj);
+          for (int c = 0; c < m; ++c) acc[c] += lp[k] * Acur[k * m + c];
+        }
+        for (int c = 0; c < m; ++c) Pv[c] = Abcur[i * m + c] / (kap_i * S->mi[i]);
+        lbp[i] = line_search(g, dim, Li, Pv, Brmin[i], Brmax[i], Bsmin[i]);
+        for (int c = 0; c < m; ++c) acc[c] += lbp[i] * Abcur[i * m + c];
+        for (int c = 0; c < m; ++c) Unext[c * N + i] = Li[c] + acc[c] / S->mi[i];
+      }
+      if (pass == 1) { free(lp); free(lbp); }
+    }
+    if (P->passes == 1) memcpy(Uout, U1, m * N * sizeof(double));
+    if (P->passes <= 0) memcpy(Uout, UL, m * N * sizeof(double));
+    free(A2); free(Ab2);
+  }
+
+finish:
+  for (long i = 0; i < N; ++i) {
+    double V[OR_MAXM];
+    get_state(S, Uout, i, V);
+    if (!(V[0] > 0.0) || !(eps_of(dim, V) > 0.0)) status = -2;
+  }
+  if (dg) {
+    dg->tau_max = tmax;
+    if (dg->N) memcpy(dg->N, Nr, N * sizeof(double));
+    if (dg->rho_min) memcpy(dg->rho_min, Brmin, N * sizeof(double));
+    if (dg->rho_max) memcpy(dg->rho_max, Brmax, N * sizeof(double));
+    if (dg->s_min) memcpy(dg->s_min, Bsmin, N * sizeof(double));
+    if (dg->UL) memcpy(dg->UL, UL, m * N * sizeof(double));
+    if (dg->dUH) memcpy(dg->dUH, dUH, m * N * sizeof(double));
+    if (dg->U1) memcpy(dg->U1, U1, m * N * sizeof(double));
+    if (dg->dij) memcpy(dg->dij, dij, nnz * sizeof(double));
+    if (dg->lij) memcpy(dg->lij, l1, nnz * sizeof(double));
+    if (dg->lbd) memcpy(dg->lbd, lb1, N * sizeof(double));
+    if (dg->Aij) memcpy(dg->Aij, A, nnz * m * sizeof(double));
+    if (dg->Abd) memcpy(dg->Abd, Ab, N * m * sizeof(double));
+  }
+  free(dij); free(dbd); free(dii); free(UL); free(Nr); free(dH); free(dbH); free(dUH);
+  free(A); free(Ab); free(qrmin); free(qrmax); free(qsmin); free(Brmin); free(Brmax); free(Bsmin);
+  free(l1); free(lb1); free(U1); free(Ug);
+  return status;
+}
+
+/* Per-row CFL quantity -m_i/(2 d_ii), eq. CFLcond; the global minimum is
+ * tau_max of eq. MaxCFLdt. */
+void or_tau_rows(const or_setup *S, const or_params *P, const double *U, double *out) {
+  const int dim = S->dim, m = S->m;
+  const long N = S->ndofs;
+#pragma omp parallel for schedule(static)
+  for (long i = 0; i < N; ++i) {
+    double s = 0.0, Ui[OR_MAXM], Ug[OR_MAXM];
+    for (long k = S->rowptr[i]; k < S->rowptr[i + 1]; ++k) {
+      long j = S->col[k];
+      if (j != i) s += dij_low(S, P->gamma, U, i, j, S->c + k * dim);
+    }
+    get_state(S, U, i, Ui);
+    for (long b = S->bptr[i]; b < S->bptr[i + 1]; ++b) {
+      const double *cb = S->bc_c + b * dim;
+      double nc = norm_c(dim, cb), n[3];
+      ghost_state(S, S->bc[S->bface[b]], Ui, cb, Ug);
+      for (int e = 0; e < dim; ++e) n[e] = cb[e] / nc;
+      s += nc * or_lambda_max(P->gamma, dim, Ui, Ug, n);
+    }
+    out[i] = S->mi[i] / (2.0 * s);
+  }
+  (void)m;
+}
+
+/* SSP-RK3 in Shu-Osher form (Sec. 6.2).  tau is fixed in stage 1 from the
+ * CFL rule and capped by dt_cap (reading R21); stages 2 and 3 re-check the
+ * CFL condition of their own state and, on violation, the step restarts from
+ * U^n with tau = Cr * tau_max of the violating stage (reading R20).
+ * dt_fixed > 0 replaces the CFL rule for stage 1.
+ * Returns 0, -2 (inadmissible output) or -3 (CFL restarts exhausted). */
+int or_step(const or_setup *S, const or_params *P, double *U, double dt_cap, double dt_fixed,
+            double *dt_taken, int *restarts) {
+  const long M = (long)S->m * S->ndofs;
+  double *Ua = dalloc(M), *Ub = dalloc(M), *Ph = dalloc(M);
+  or_diag dg;
+  memset(&dg, 0, sizeof(dg));
+  int st = 0, nres = 0;
+  double tau;
+  if (dt_fixed > 0.0) {
+    tau = dt_fixed;
+  } else {
+    double *tr = dalloc(S->ndofs);
+    or_tau_rows(S, P, U, tr);
+    double tm = INFINITY;
+    for (long i = 0; i < S->ndofs; ++i) tm = fmin(tm, tr[i]);
+    free(tr);
+    tau = P->cfl * tm;
+  }
+  if (dt_cap > 0.0 && tau > dt_cap) tau = dt_cap;
+  for (;;) {
+    st = or_stage(S, P, U, tau, Ua, &dg);
+    if (st) break;
+    st = or_stage(S, P, Ua, tau, Ph, &dg);
+    if (tau > dg.tau_max) {
+      if (++nres > 8) { st = -3; break; }
+      tau = P->cfl * dg.tau_max;
+      continue;
+    }
+    if (st) break;
+    for (long q = 0; q < M; ++q) Ub[q] = 0.75 * U[q] + 0.25 * Ph[q];
+    st = or_stage(S, P, Ub, tau, Ph, &dg);
+    if (tau > dg.tau_max) {
+      if (++nres > 8) { st = -3; break; }
+      tau = P->cfl * dg.tau_max;
+      continue;
+    }
+    if (st) break;
+    for (long q = 0; q < M; ++q) U[q] = (1.0 / 3.0) * U[q] + (2.0 / 3.0) * Ph[q];
+    break;
+  }
+  *dt_taken = tau;
+  if (restarts) *restarts = nres;
+  free(Ua); free(Ub); free(Ph);
+  return st;
+}

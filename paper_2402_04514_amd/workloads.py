@@ -1,0 +1,213 @@
+"""Seeded synthetic inputs shaped like the paper's test problems.
+
+This module holds no arithmetic of the scheme: it only lays out initial
+states (primitive data converted to conserved variables) on the dof numbering
+that the library documents, so that the GPU path and the CPU oracle can be
+fed bit-identical inputs.  The problems:
+
+* ``sod``      1D shock tube on [0, 1], 200 Q1 cells, outflow (the role of the
+               paper's LeBlanc tube, Sec. 6.2 (iii), with textbook Sod data).
+* ``vortex``   2D isentropic vortex on [-5, 5]^2, periodic (Sec. 6.2 (i)),
+               gamma = 1.4; velocity factor exp((1 - r^2)/2), the steady form.
+* ``quadrant`` 2D four-quadrant Riemann data on [0, 1]^2, states drawn per
+               quadrant from SplitMix64 (seed 240204514 + q).
+* ``blast``    3D blast on [0, 1]^3 with slip walls: p = 100 in the cells whose
+               centre lies within 0.1 of the box centre, p = 0.1 elsewhere.
+
+Numbering: dof = cell * (k+1)^d + local; cells lexicographic with x fastest,
+local Gauss-Lobatto nodes lexicographic with x fastest.  Piecewise data are
+assigned per cell from the cell centre, so duplicated face nodes of
+neighbouring cells keep their own cell's value.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+BC_PERIODIC, BC_OUTFLOW, BC_SLIP = 0, 1, 2
+GAMMA = 1.4
+
+
+@dataclass
+class MeshSpec:
+    dim: int
+    degree: int
+    cells: tuple
+    lo: tuple
+    hi: tuple
+    bc: tuple  # per box face 2*axis+side
+
+    @property
+    def nloc(self) -> int:
+        return (self.degree + 1) ** self.dim
+
+    @property
+    def ncells(self) -> int:
+        return int(np.prod(self.cells))
+
+    @property
+    def ndofs(self) -> int:
+        return self.ncells * self.nloc
+
+
+@dataclass
+class Workload:
+    name: str
+    mesh: MeshSpec
+    U0: np.ndarray = field(repr=False)  # (dim+2, ndofs) conserved SoA
+    t_final: float | None = None
+    steps: int | None = None
+
+
+def gl_nodes(degree: int) -> np.ndarray:
+    return np.array({1: [0.0, 1.0], 2: [0.0, 0.5, 1.0]}[degree])
+
+
+def node_coords(ms: MeshSpec):
+    """Node coordinates (ndofs, dim) and owning cell centres (ndofs, dim)."""
+    d, k = ms.dim, ms.degree
+    nb = k + 1
+    h = [(ms.hi[e] - ms.lo[e]) / ms.cells[e] for e in range(d)]
+    cell = np.arange(ms.ncells)
+    loc = np.arange(ms.nloc)
+    ci, li = [], []
+    r = cell.copy()
+    for e in range(d):
+        ci.append(r % ms.cells[e])
+        r //= ms.cells[e]
+    r = loc.copy()
+    for e in range(d):
+        li.append(r % nb)
+        r //= nb
+    xg = gl_nodes(k)
+    x = np.zeros((ms.ndofs, d))
+    xc = np.zeros((ms.ndofs, d))
+    for e in range(d):
+        xs = ms.lo[e] + (ci[e][:, None] + xg[li[e]][None, :]) * h[e]
+        cs = ms.lo[e] + (ci[e][:, None] + 0.5 + 0.0 * li[e][None, :]) * h[e]
+        x[:, e] = xs.reshape(-1)
+        xc[:, e] = cs.reshape(-1)
+    return x, xc
+
+
+def to_conserved(rho, vel, p, gamma=GAMMA) -> np.ndarray:
+    """[rho, rho u, p/(gamma-1) + rho |u|^2 / 2] as a (d+2, n) array."""
+    rho = np.asarray(rho, dtype=np.float64)
+    vel = np.asarray(vel, dtype=np.float64)
+    d = vel.shape[0]
+    U = np.empty((d + 2, rho.shape[0]))
+    U[0] = rho
+    for e in range(d):
+        U[1 + e] = rho * vel[e]
+    U[d + 1] = p / (gamma - 1.0) + 0.5 * rho * np.sum(vel * vel, axis=0)
+    return U
+
+
+# -- SplitMix64 (Steele, Lea & Flood 2014) -----------------------------------
+_M64 = (1 << 64) - 1
+
+
+class SplitMix64:
+    def __init__(self, seed: int):
+        self.s = seed & _M64
+
+    def next_u64(self) -> int:
+        self.s = (self.s + 0x9E3779B97F4A7C15) & _M64
+        z = self.s
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+        return z ^ (z >> 31)
+
+    def uniform(self) -> float:
+        return (self.next_u64() >> 11) * (1.0 / (1 << 53))
+
+
+def quadrant_states(seed_base: int = 240204514):
+    """rho in [0.1, 2], p in [0.1, 10], u uniform in the unit disk, per quadrant."""
+    out = []
+    for q in range(4):
+        g = SplitMix64(seed_base + q)
+        rho = 0.1 + 1.9 * g.uniform()
+        p = 0.1 + 9.9 * g.uniform()
+        rad = math.sqrt(g.uniform())
+        ang = 2.0 * math.pi * g.uniform()
+        out.append((rho, rad * math.cos(ang), rad * math.sin(ang), p))
+    return out
+
+
+# -- problems ----------------------------------------------------------------
+def sod(cells: int = 200, gamma: float = GAMMA) -> Workload:
+    ms = MeshSpec(1, 1, (cells,), (0.0,), (1.0,), (BC_OUTFLOW, BC_OUTFLOW))
+    _, xc = node_coords(ms)
+    left = xc[:, 0] < 0.5
+    rho = np.where(left, 1.0, 0.125)
+    p = np.where(left, 1.0, 0.1)
+    U = to_conserved(rho, np.zeros((1, ms.ndofs)), p, gamma)
+    return Workload("sod_q1_%d" % cells, ms, U, t_final=0.2)
+
+
+def vortex_exact(x: np.ndarray, t: float, beta=5.0, x0=(-1.0, -1.0), uinf=(1.0, 1.0),
+                 gamma=GAMMA, lo=-5.0, hi=5.0) -> np.ndarray:
+    """Isentropic vortex at time t, periodically wrapped on [lo, hi)^2."""
+    L = hi - lo
+    xb = np.empty_like(x)
+    for e in range(2):
+        xb[:, e] = x[:, e] - x0[e] - t * uinf[e]
+        xb[:, e] = (xb[:, e] - lo) % L + lo
+    r2 = xb[:, 0] ** 2 + xb[:, 1] ** 2
+    T = 1.0 - (gamma - 1.0) * beta ** 2 / (8.0 * gamma * math.pi ** 2) * np.exp(1.0 - r2)
+    rho = T ** (1.0 / (gamma - 1.0))
+    p = rho ** gamma
+    fac = beta / (2.0 * math.pi) * np.exp(0.5 * (1.0 - r2))
+    vel = np.stack([uinf[0] - fac * xb[:, 1], uinf[1] + fac * xb[:, 0]])
+    return to_conserved(rho, vel, p, gamma)
+
+
+def vortex(cells: int = 256, gamma: float = GAMMA) -> Workload:
+    ms = MeshSpec(2, 1, (cells, cells), (-5.0, -5.0), (5.0, 5.0), (BC_PERIODIC,) * 4)
+    x, _ = node_coords(ms)
+    return Workload("vortex_q1_%d" % cells, ms, vortex_exact(x, 0.0, gamma=gamma), t_final=2.0)
+
+
+def quadrant(cells: int = 1024, degree: int = 2, seed_base: int = 240204514,
+             gamma: float = GAMMA) -> Workload:
+    ms = MeshSpec(2, degree, (cells, cells), (0.0, 0.0), (1.0, 1.0), (BC_OUTFLOW,) * 4)
+    _, xc = node_coords(ms)
+    q = (xc[:, 0] >= 0.5).astype(int) + 2 * (xc[:, 1] >= 0.5).astype(int)
+    st = np.array(quadrant_states(seed_base))
+    rho, ux, uy, p = (st[q, c] for c in range(4))
+    U = to_conserved(rho, np.stack([ux, uy]), p, gamma)
+    return Workload("quadrant_q%d_%d" % (degree, cells), ms, U, steps=500)
+
+
+def blast(cells: int = 128, gamma: float = GAMMA) -> Workload:
+    ms = MeshSpec(3, 1, (cells,) * 3, (0.0,) * 3, (1.0,) * 3, (BC_SLIP,) * 6)
+    _, xc = node_coords(ms)
+    r2 = np.sum((xc - 0.5) ** 2, axis=1)
+    p = np.where(r2 <= 0.1 ** 2, 100.0, 0.1)
+    U = to_conserved(np.ones(ms.ndofs), np.zeros((3, ms.ndofs)), p, gamma)
+    return Workload("blast_q1_%d" % cells, ms, U, steps=200)
+
+
+def serving_requests(count: int = 256, seed0: int = 1000, arrival_seed: int = 7,
+                     rate: float = 20.0):
+    """(arrival time, cells per side, quadrant seed base) of each request."""
+    arr = SplitMix64(arrival_seed)
+    t = 0.0
+    out = []
+    for r in range(count):
+        t += -math.log(1.0 - arr.uniform()) / rate
+        g = SplitMix64(seed0 + r)
+        n = int(round(32.0 * 16.0 ** g.uniform()))
+        out.append((t, n, seed0 + r))
+    return out
+
+
+CONFIGS = {
+    "sod": sod,
+    "vortex": vortex,
+    "quadrant": quadrant,
+    "blast": blast,
+}
