@@ -60,7 +60,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build())
+        # GDG_ORACLE_LIB points the pins at another build of this same source
+        # (used to check that planted mistakes make the pins fail)
+        _lib = C.CDLL(os.environ.get("GDG_ORACLE_LIB") or build())
         L = _lib
         L.or_create.restype = C.c_void_p
         L.or_create.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_long), _DP, _DP, C.POINTER(C.c_int)]

@@ -1,0 +1,83 @@
+"""The pins must catch plausible mistakes in the oracle.
+
+Each case plants one mistake (a dropped term, a flipped sign, a wrong index or
+constant) in a copy of the oracle's C source, builds it on the CPU, and runs
+the pin tests named for it against that build; the pins must fail.  Nothing
+here touches the GPU library."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "gdg_oracle.c")
+T = "tests/"
+SETUP, PHYS, SCHEME = T + "test_oracle_setup.py", T + "test_oracle_physics.py", T + "test_oracle_scheme.py"
+
+MUTANTS = {
+    # name: (original text, planted text, pin files that must fail)
+    "bar_state_sign": ("(fk[q] - fj[q]) / (2.0 * dij[k])", "(fj[q] - fk[q]) / (2.0 * dij[k])",
+                       [SCHEME + "::test_low_order_update_inside_unrelaxed_bounds"]),
+    "boundary_term_dropped": (
+        "for (int c = 0; c < m; ++c) acc[c] += (fc[c] - fi[c]) - dbd[b] * (Ub[c] - Ui[c]);", ";",
+        [SCHEME + "::test_constant_state_preserved", SCHEME + "::test_slip_box_mass_energy"]),
+    "kappa_without_plus_one": ("double kap_i = 1.0 / (double)(leni + 1);",
+                               "double kap_i = 1.0 / (double)(leni);",
+                               [SCHEME + "::test_limiter_bounds_symmetry_and_limits"]),
+    "wave_speed_factor": ("double kfac = (g + 1.0) / (2.0 * g);\n  double lam1 = ul",
+                          "double kfac = (g - 1.0) / (2.0 * g);\n  double lam1 = ul", [PHYS]),
+    "wave_speed_exponent": ("double alpha = (g - 1.0) / (2.0 * g);\n  double num",
+                            "double alpha = (g - 1.0) / (g);\n  double num", [PHYS]),
+    "entropy_gradient_sign": ("grad[dim + 1] = (g - 1.0) / p;", "grad[dim + 1] = -(g - 1.0) / p;",
+                              [SCHEME + "::test_entropy_viscosity_ratio"]),
+    "high_order_viscosity_min": ("dH[k] = fmax(dmin, dev);", "dH[k] = fmin(dmin, dev);",
+                                 [SCHEME + "::test_vortex_convergence",
+                                  SCHEME + "::test_limiter_bounds_symmetry_and_limits"]),
+    "limiter_max_not_min": ("lp[k] = fmin(li, lj);", "lp[k] = fmax(li, lj);",
+                            [SCHEME + "::test_limiter_bounds_symmetry_and_limits"]),
+    "residual_sign": ("rhs[c][a] = -tau * acc[c];", "rhs[c][a] = tau * acc[c];",
+                      [SCHEME + "::test_high_low_identity_and_skew_fluxes"]),
+    "relaxation_sign": ("Brmin[i] = (1.0 - rel) * rmin;", "Brmin[i] = (1.0 + rel) * rmin;",
+                        [SCHEME + "::test_limiter_bounds_symmetry_and_limits"]),
+    "cell_boundary_term_sign": ("out[e] = cK - cdK;", "out[e] = cK + cdK;", [SETUP]),
+    "face_coupling_half": ("out[e] = 0.5 * n * face_integral(S, f, a, b, 0);",
+                           "out[e] = n * face_integral(S, f, a, b, 0);", [SETUP]),
+    "slip_half_reflection": ("Ug[1 + e] = Ui[1 + e] - 2.0 * mn * cb[e] / nn;",
+                             "Ug[1 + e] = Ui[1 + e] - 1.0 * mn * cb[e] / nn;",
+                             [SCHEME + "::test_slip_box_mass_energy"]),
+    "mass_flux_sign": ("- mm * (dUH[c * N + j] - dUH[c * N + i]);",
+                       "+ mm * (dUH[c * N + j] - dUH[c * N + i]);",
+                       [SCHEME + "::test_high_low_identity_and_skew_fluxes"]),
+    "density_search_lower_bound": ("if (r + pr < rmin) l = (rmin - r) / pr;", "if (r + pr < rmin) l = 1.0;",
+                                   [SCHEME + "::test_limiter_bounds_symmetry_and_limits"]),
+    "second_pass_full_flux": ("A2[k * m + c] = (1.0 - l1[k]) * A[k * m + c];", "A2[k * m + c] = A[k * m + c];",
+                              [SCHEME + "::test_limiter_bounds_symmetry_and_limits"]),
+    "rescaled_entropy_power": ("return pow(U[0], -g) * eps_of(dim, U);",
+                               "return pow(U[0], -g + 0.1) * eps_of(dim, U);",
+                               [SCHEME + "::test_limiter_bounds_symmetry_and_limits"]),
+    "ssp_coefficients": ("Ub[q] = 0.75 * U[q] + 0.25 * Ph[q];", "Ub[q] = 0.5 * U[q] + 0.5 * Ph[q];",
+                         [SCHEME + "::test_sod_converges_to_exact", SCHEME + "::test_vortex_convergence"]),
+    "min_viscosity_all_faces": ("if (S->kind[k] == OR_KIND_FACE_COLLOC) {", "if (S->kind[k] != OR_KIND_CELL) {",
+                                [SCHEME + "::test_vortex_convergence"]),
+    "gradient_operand_transposed": ("g = dphi(S, p.b, p.dir, xi) * phi(S, p.a, xi);",
+                                    "g = dphi(S, p.a, p.dir, xi) * phi(S, p.b, xi);", [SETUP]),
+    "ev_normalizer_not_abs_sum": ("D += fabs(grad[q]) * fabs(Sk[q]);", "D += fabs(grad[q] * Sk[q]) * 0.5;",
+                                  [SCHEME + "::test_vortex_convergence"]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(name, tmp_path):
+    orig, planted, pins = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(orig) >= 1, "mutation site moved: " + name
+    path = tmp_path / (name + ".c")
+    path.write_text(src.replace(orig, planted, 1))
+    lib = tmp_path / ("lib" + name + ".so")
+    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-std=c11", "-o", str(lib),
+                           str(path), "-lm"])
+    env = dict(os.environ, GDG_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider"] + pins,
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1, "planted mistake %r passed the pins:\n%s" % (name, r.stdout[-800:])

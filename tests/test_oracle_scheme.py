@@ -300,3 +300,24 @@ def test_vortex_convergence(oracle):
     assert 1.7 < r_lim < 2.3, lim
     assert 0.8 < r_low < 1.2, low
     assert lim[2] < 0.1 * low[2]
+
+
+@pytest.mark.parametrize("seed", [240204514, 21, 22])
+def test_low_order_update_inside_unrelaxed_bounds(oracle, seed):
+    """eq. ConvexRef writes U^L_i as a convex combination of U_i and the bar
+    states of eq. UsualBarState / BoundaryBarState, all of which enter the
+    bounds of eq. local_bounds; with the relaxation switched off (c_r = 0)
+    U^L_i therefore lies in B_i."""
+    for ms, U in [quadrant_on(2, 1, 10, (1, 1, 2, 2), seed), quadrant_on(2, 2, 6, (2,) * 4, seed),
+                  quadrant_on(1, 1, 30, (1, 1), seed)]:
+        M = make(oracle, ms)
+        _, dg = M.stage(oracle.params(degree=ms.degree, c_r=0.0), U, diag=True)
+        UL = dg["UL"]
+        d = ms.dim
+        eps = UL[d + 1] - 0.5 * np.sum(UL[1:d + 1] ** 2, 0) / UL[0]
+        st = eps * UL[0] ** (-G)
+        assert np.all(UL[0] >= dg["rho_min"] * (1 - 1e-13))
+        assert np.all(UL[0] <= dg["rho_max"] * (1 + 1e-13))
+        assert np.all(st >= dg["s_min"] * (1 - 1e-12))
+        # the bounds are attained: not a vacuous test
+        assert np.any(UL[0] <= dg["rho_min"] * (1 + 1e-3)) or np.any(st <= dg["s_min"] * (1 + 1e-3))
