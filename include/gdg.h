@@ -1,0 +1,171 @@
+/*
+ * gdg.h -- C-ABI of libgdg, the MI355X (gfx950) implementation of the
+ * per-stage algebraic sweep of the graph-based discontinuous Galerkin scheme
+ * for the compressible Euler equations of Kronbichler, Maier & Tomas,
+ * "Graph-based methods for hyperbolic systems of conservation laws using
+ * discontinuous space discretizations" (arXiv 2402.04514).
+ *
+ * The problem these calls solve (Sec. 3.1, eq. cijdijscheme): given nodal
+ * states U_i^n in the admissible set A (rho > 0, eps > 0, eq. AddSet) of a
+ * DG Q_k space on a mesh, and boundary data built from them (Sec. 4), produce
+ * U^{n+1} with a time step from the CFL rule (eq. MaxCFLdt), using the
+ * low-order update, the entropy-viscosity high-order update and convex
+ * limiting (Sec. 5) inside SSP-RK3 (Sec. 6.2).
+ *
+ * Conventions
+ *  - dofs: cell-major.  Cells lexicographic with x fastest; inside a cell the
+ *    (k+1)^d Gauss-Lobatto nodes lexicographic with x fastest.  Face nodes of
+ *    neighbouring cells are distinct dofs at the same point (Sec. 2.3).
+ *  - states: SoA double arrays of (dim+2) planes of ndofs values,
+ *    plane 0 = rho, planes 1..dim = momentum, plane dim+1 = total energy E.
+ *  - box faces: f = 2*axis + side, side 0 = low end.
+ *  - memory: the caller owns every host buffer and the device workspace;
+ *    the library allocates no device memory.  All device work is enqueued on
+ *    the HIP stream given at creation.
+ *  - errors: every call returns a gdg_status; gdg_last_error() gives text.
+ *    No exception crosses this interface.  Calls on one context are not
+ *    thread-safe.
+ */
+#ifndef GDG_H
+#define GDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gdg_ctx gdg_ctx;
+
+typedef enum {
+  GDG_OK = 0,
+  GDG_E_INVALID = -1,      /* bad argument or mesh description */
+  GDG_E_INADMISSIBLE = -2, /* a state left A: rho <= 0, eps <= 0 or NaN (eq. AddSet) */
+  GDG_E_CFL = -3,          /* the CFL condition eq. CFLcond failed after all restarts */
+  GDG_E_NOMEM = -4,        /* workspace smaller than gdg_workspace_bytes() */
+  GDG_E_DEVICE = -5        /* a HIP runtime call failed */
+} gdg_status;
+
+/* Boundary kinds per box face (Sec. 4.1).  OUTFLOW is the supersonic-outflow
+ * branch U^d := U_i of eq. supersonic_inoutflow ("do nothing"); SLIP is
+ * eq. slip_boundary; PERIODIC must be set on both faces of an axis. */
+typedef enum { GDG_BC_PERIODIC = 0, GDG_BC_OUTFLOW = 1, GDG_BC_SLIP = 2 } gdg_bc;
+
+/* GDG_LOW_ORDER: eq. cijdijscheme only.  GDG_HIGH_ORDER: eq. HighScheme
+ * unlimited.  GDG_LIMITED: eq. LimitedScheme with the bounds of
+ * eq. local_bounds (the paper's method). */
+typedef enum { GDG_LOW_ORDER = 0, GDG_HIGH_ORDER = 1, GDG_LIMITED = 2 } gdg_scheme;
+
+/* GDG_FP64: every operation in double precision. */
+typedef enum { GDG_FP64 = 0 } gdg_precision;
+
+/* Uniform Cartesian mesh of cells[0] x cells[1] x cells[2] cells over the box
+ * [lo, hi] (only the first dim entries are read), Q_degree elements with
+ * degree 1 or 2, dim 1..3, bc[2*dim] boundary kinds. */
+typedef struct {
+  int32_t dim;
+  int32_t degree;
+  int64_t cells[3];
+  double lo[3];
+  double hi[3];
+  int32_t bc[6];
+} gdg_mesh_desc;
+
+/* Scheme constants.  gdg_default_params() gives the paper's values:
+ * gamma 1.4, Cr 0.5 (eq. MaxCFLdt), c_ev 1 / 0.5 for k = 1 / 2 (Sec. 5.2),
+ * c_k 1 (eq. ViscMin), c_r 4 and p_r 1.5 (eq. ViscMinConst2), two limiter
+ * passes (Sec. 6.1), the limited scheme, FP64. */
+typedef struct {
+  double gamma;
+  double cfl;
+  double c_ev;
+  double c_k;
+  double c_r;
+  double p_r;
+  int32_t limiter_passes; /* 0, 1 or 2 */
+  int32_t scheme;         /* gdg_scheme */
+  int32_t precision;      /* gdg_precision */
+  int32_t reserved;
+} gdg_params;
+
+typedef struct {
+  double t;          /* simulated time */
+  int64_t steps;     /* SSP-RK3 steps taken */
+  int64_t restarts;  /* steps restarted after a CFL violation in stage 2 or 3 */
+  double last_dt;    /* tau of the last step */
+} gdg_stats;
+
+/* Intermediate fields of the last forward-Euler stage, for inspection. */
+typedef enum {
+  GDG_FIELD_STATE = 0,  /* current state U, (dim+2) planes */
+  GDG_FIELD_EV_N = 1,   /* normalized entropy residual N_i (Sec. 5.2), 1 plane */
+  GDG_FIELD_BOUNDS = 2, /* rho_min, rho_max, s~_min of eq. local_bounds, 3 planes */
+  GDG_FIELD_UL = 3,     /* low-order update U^L, eq. cijdijscheme, (dim+2) planes */
+  GDG_FIELD_DUH = 4,    /* high-order increment U^H - U, eq. HighScheme, (dim+2) planes */
+  GDG_FIELD_U1 = 5      /* state after limiter pass 1, eq. LimitedScheme, (dim+2) planes */
+} gdg_field;
+
+/* Fills *out with the paper's constants for Q_degree. */
+gdg_status gdg_default_params(int32_t degree, gdg_params *out);
+
+/* Device workspace, in bytes, that gdg_create() needs for this mesh. */
+gdg_status gdg_workspace_bytes(const gdg_mesh_desc *mesh, const gdg_params *prm, size_t *bytes);
+
+/* Builds the stencil of Sec. 2.3 (m_i, m_ij, c_ij, c_i^{d,k} of
+ * eq. mass_matrices, cij_def1, cij_def2 and Sec. 4.2) on the host and copies
+ * it into dev_workspace (caller-owned device memory of ws_bytes bytes, 256-byte
+ * aligned, alive until gdg_destroy).  hip_stream is a hipStream_t (NULL: the
+ * null stream).  *out receives the context; GDG_E_NOMEM if ws_bytes is too
+ * small, GDG_E_INVALID for a bad description. */
+gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *dev_workspace,
+                      size_t ws_bytes, void *hip_stream, gdg_ctx **out);
+
+/* Releases the context (not the workspace).  Synchronizes the stream. */
+void gdg_destroy(gdg_ctx *ctx);
+
+/* Number of dofs N (per component). */
+int64_t gdg_num_dofs(const gdg_ctx *ctx);
+
+/* Collocation points x_i into host_xyz[N * dim] (interleaved per dof). */
+gdg_status gdg_node_coords(const gdg_ctx *ctx, double *host_xyz);
+
+/* Copies a state (SoA, (dim+2) * N doubles) into the context; is_device_ptr
+ * selects device or host memory.  Resets t and the step counters.  Returns
+ * GDG_E_INADMISSIBLE if some U_i is outside A (the paper's guarantees assume
+ * admissible data, Sec. 3.1).  Synchronizes the stream. */
+gdg_status gdg_upload_state(gdg_ctx *ctx, const double *U, int32_t is_device_ptr);
+
+/* Copies the current state out (same layout).  Synchronizes the stream. */
+gdg_status gdg_download_state(gdg_ctx *ctx, double *U, int32_t is_device_ptr);
+
+/* One SSP-RK3 step (Shu-Osher form).  tau = Cr * min_i(-m_i / (2 d_ii))
+ * from stage 1 (eq. MaxCFLdt), or dt_fixed if dt_fixed > 0; then capped by
+ * dt_cap if dt_cap > 0.  Stages 2 and 3 re-check eq. CFLcond on their own
+ * state; on violation the step restarts with tau = Cr * that stage's bound
+ * (at most 8 times, then GDG_E_CFL).  *dt_taken (may be NULL) receives tau.
+ * Returns GDG_E_INADMISSIBLE if a stage output left A. */
+gdg_status gdg_step(gdg_ctx *ctx, double dt_cap, double dt_fixed, double *dt_taken);
+
+/* Steps until t = t_final (last step capped) or max_steps steps. */
+gdg_status gdg_run_to(gdg_ctx *ctx, double t_final, int64_t max_steps, gdg_stats *stats);
+
+/* One forward-Euler stage U <- Phi(U; tau) of the selected scheme (tau <= 0:
+ * the CFL rule), keeping its intermediates for gdg_read_field(). */
+gdg_status gdg_stage(gdg_ctx *ctx, double tau, double *tau_used);
+
+/* Copies a field of the last stage (gdg_field) to dst in dof order, one plane
+ * of N doubles after the other. */
+gdg_status gdg_read_field(gdg_ctx *ctx, int32_t field, double *dst, int32_t is_device_ptr);
+
+/* Simulated time, step and restart counters. */
+gdg_status gdg_get_stats(const gdg_ctx *ctx, gdg_stats *stats);
+
+/* Text of the last error on this context ("" if none). */
+const char *gdg_last_error(const gdg_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GDG_H */

@@ -215,10 +215,11 @@ class Mesh:
         U = np.array(U, dtype=np.float64).reshape(self.m, self.ndofs)
         t, n = 0.0, 0
         while t < t_final and n < max_steps:
-            U, dt, _, st = self.step(prm, U, dt_cap=t_final - t)
+            cap = t_final - t
+            U, dt, _, st = self.step(prm, U, dt_cap=cap)
             if st:
                 raise RuntimeError("oracle step failed with status %d" % st)
-            t += dt
+            t = t_final if dt == cap else t + dt
             n += 1
         return U, t, n
 

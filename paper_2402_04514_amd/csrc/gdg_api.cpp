@@ -1,0 +1,425 @@
+// gdg_api.cpp -- the C-ABI of include/gdg.h: validation, workspace layout,
+// SSP-RK3 driver with CFL restarts, state transfer.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "gdg.h"
+#include "gdg_internal.h"
+
+using namespace gdg;
+
+struct gdg_ctx {
+  gdg_mesh_desc mesh;
+  gdg_params prm;
+  KArgs A;
+  hipStream_t stream;
+  double *U[3];   // three state buffers; U[cur] holds the state
+  int cur;
+  RefTables *dref;
+  std::string err;
+  Ctl hctl;
+  double t;
+  int64_t steps, restarts;
+  double last_dt;
+  int M;
+};
+
+namespace {
+
+struct Layout {
+  int nloc, nb1, R, cpb, W, M;
+  int64_t N, ncells, nblocks, nslots;
+  size_t off_ref, off_ctl, off_col, off_c, off_meta, off_rowlen, off_U[3], off_Wc, off_N, off_q,
+      off_B, off_UL, off_dUH, off_U1, off_dL, off_l1, total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool validate(const gdg_mesh_desc *m, const gdg_params *p, std::string *err) {
+  if (!m || !p) { *err = "null argument"; return false; }
+  if (m->dim < 1 || m->dim > 3) { *err = "dim must be 1, 2 or 3"; return false; }
+  if (m->degree < 1 || m->degree > 2) { *err = "degree must be 1 or 2"; return false; }
+  int64_t ncells = 1;
+  for (int e = 0; e < m->dim; ++e) {
+    if (m->cells[e] < 1) { *err = "cells must be >= 1"; return false; }
+    if (!(m->hi[e] > m->lo[e])) { *err = "hi must exceed lo"; return false; }
+    int b0 = m->bc[2 * e], b1 = m->bc[2 * e + 1];
+    for (int b : {b0, b1})
+      if (b < 0 || b > 2) { *err = "unknown boundary kind"; return false; }
+    if ((b0 == GDG_BC_PERIODIC) != (b1 == GDG_BC_PERIODIC)) {
+      *err = "periodic must be set on both faces of an axis";
+      return false;
+    }
+    if (b0 == GDG_BC_PERIODIC && m->cells[e] < 2) {
+      *err = "a periodic axis needs at least 2 cells";
+      return false;
+    }
+    ncells *= m->cells[e];
+  }
+  int nloc = 1;
+  for (int e = 0; e < m->dim; ++e) nloc *= m->degree + 1;
+  if (ncells * nloc >= (int64_t(1) << 31)) { *err = "too many dofs for 32-bit column indices"; return false; }
+  // the two-rarefaction bound is an upper bound for 1 < gamma <= 5/3
+  if (!(p->gamma > 1.0 && p->gamma <= 5.0 / 3.0 + 1e-12)) { *err = "gamma must lie in (1, 5/3]"; return false; }
+  if (!(p->cfl > 0.0 && p->cfl <= 1.0)) { *err = "cfl must lie in (0, 1]"; return false; }
+  if (!(p->c_ev >= 0.0) || !(p->c_k >= 0.0) || !(p->c_r >= 0.0) || !(p->p_r >= 0.0)) {
+    *err = "scheme constants must be non-negative";
+    return false;
+  }
+  if (p->limiter_passes < 0 || p->limiter_passes > 2) { *err = "limiter_passes must be 0, 1 or 2"; return false; }
+  if (p->scheme < 0 || p->scheme > 2) { *err = "unknown scheme"; return false; }
+  if (p->precision != GDG_FP64) { *err = "unknown precision"; return false; }
+  return true;
+}
+
+Layout layout(const gdg_mesh_desc *m) {
+  Layout L;
+  L.nb1 = m->degree + 1;
+  L.nloc = 1;
+  int nface = 1;
+  for (int e = 0; e < m->dim; ++e) L.nloc *= L.nb1;
+  for (int e = 0; e < m->dim - 1; ++e) nface *= L.nb1;
+  L.M = m->dim + 2;
+  L.cpb = kBlockThreads / L.nloc;
+  L.R = L.cpb * L.nloc;
+  L.W = L.nloc + m->dim * nface;
+  L.ncells = 1;
+  for (int e = 0; e < m->dim; ++e) L.ncells *= m->cells[e];
+  L.N = L.ncells * L.nloc;
+  L.nblocks = (L.ncells + L.cpb - 1) / L.cpb;
+  L.nslots = L.nblocks * L.W * L.R;
+  const size_t N = (size_t)L.N, S = (size_t)L.nslots, d = (size_t)m->dim, M = (size_t)L.M;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+  L.off_ref = take(sizeof(RefTables));
+  L.off_ctl = take(sizeof(Ctl));
+  L.off_col = take(S * 4);
+  L.off_c = take(S * d * 8);
+  L.off_meta = take(S);
+  L.off_rowlen = take(N * 4);
+  for (int k = 0; k < 3; ++k) L.off_U[k] = take(M * N * 8);
+  L.off_Wc = take((d + 5) * N * 8);
+  L.off_N = take(N * 8);
+  L.off_q = take(3 * N * 8);
+  L.off_B = take(3 * N * 8);
+  L.off_UL = take(M * N * 8);
+  L.off_dUH = take(M * N * 8);
+  L.off_U1 = take(M * N * 8);
+  L.off_dL = take(S * 8);
+  L.off_l1 = take(S * 8);
+  L.total = o;
+  return L;
+}
+
+#define HIPCHK(ctx, call)                                                     \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess) {                                                   \
+      (ctx)->err = std::string(#call) + ": " + hipGetErrorString(e_);         \
+      return GDG_E_DEVICE;                                                    \
+    }                                                                         \
+  } while (0)
+
+gdg_status launched(gdg_ctx *ctx, int rc, const char *what) {
+  if (rc == 0) return GDG_OK;
+  ctx->err = std::string("kernel launch failed: ") + what;
+  return GDG_E_DEVICE;
+}
+
+gdg_status read_ctl(gdg_ctx *ctx) {
+  HIPCHK(ctx, hipMemcpyAsync(&ctx->hctl, ctx->A.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return GDG_OK;
+}
+
+double bits_to_double(unsigned long long b) {
+  double d;
+  std::memcpy(&d, &b, sizeof d);
+  return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+gdg_status gdg_default_params(int32_t degree, gdg_params *out) {
+  if (!out || degree < 1 || degree > 3) return GDG_E_INVALID;
+  std::memset(out, 0, sizeof *out);
+  out->gamma = 1.4;
+  out->cfl = 0.5;
+  out->c_ev = degree == 1 ? 1.0 : (degree == 2 ? 0.5 : 0.25);
+  out->c_k = 1.0;
+  out->c_r = 4.0;
+  out->p_r = 1.5;
+  out->limiter_passes = 2;
+  out->scheme = GDG_LIMITED;
+  out->precision = GDG_FP64;
+  return GDG_OK;
+}
+
+gdg_status gdg_workspace_bytes(const gdg_mesh_desc *mesh, const gdg_params *prm, size_t *bytes) {
+  std::string err;
+  if (!bytes || !validate(mesh, prm, &err)) return GDG_E_INVALID;
+  *bytes = layout(mesh).total;
+  return GDG_OK;
+}
+
+gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *dev_workspace,
+                      size_t ws_bytes, void *hip_stream, gdg_ctx **out) {
+  if (!out) return GDG_E_INVALID;
+  *out = nullptr;
+  std::string err;
+  if (!validate(mesh, prm, &err)) return GDG_E_INVALID;
+  Layout L = layout(mesh);
+  if (!dev_workspace || ws_bytes < L.total) return GDG_E_NOMEM;
+  if (((uintptr_t)dev_workspace & 255) != 0) return GDG_E_INVALID;
+  gdg_ctx *ctx = new gdg_ctx();
+  ctx->mesh = *mesh;
+  ctx->prm = *prm;
+  ctx->stream = (hipStream_t)hip_stream;
+  ctx->M = L.M;
+  char *ws = (char *)dev_workspace;
+  KArgs &A = ctx->A;
+  std::memset(&A, 0, sizeof A);
+  A.N = L.N;
+  A.nblocks = L.nblocks;
+  A.ncells = L.ncells;
+  A.R = L.R;
+  A.W = L.W;
+  A.nloc = L.nloc;
+  A.nb1 = L.nb1;
+  A.deg = mesh->degree;
+  A.dim = mesh->dim;
+  A.cpb = L.cpb;
+  double h[3] = {1, 1, 1}, vol = 1.0;
+  for (int e = 0; e < 3; ++e) A.cells[e] = e < mesh->dim ? mesh->cells[e] : 1;
+  for (int e = 0; e < mesh->dim; ++e) {
+    h[e] = (mesh->hi[e] - mesh->lo[e]) / (double)mesh->cells[e];
+    vol *= mesh->hi[e] - mesh->lo[e];
+  }
+  for (int f = 0; f < 6; ++f) A.bc[f] = f < 2 * mesh->dim ? mesh->bc[f] : GDG_BC_OUTFLOW;
+  A.gamma = prm->gamma;
+  A.cfl = prm->cfl;
+  A.c_ev = prm->c_ev;
+  A.c_k = prm->c_k;
+  A.pk = mesh->degree % 2 == 0 ? 0.5 : 0.0;
+  A.c_r = prm->c_r;
+  A.p_r = prm->p_r;
+  A.vol = vol;
+  A.alpha = (prm->gamma - 1.0) / (2.0 * prm->gamma);
+  A.inv_alpha = 1.0 / A.alpha;
+  double ri = std::round(A.inv_alpha);
+  A.ipow = (std::fabs(A.inv_alpha - ri) < 1e-9 && ri >= 1 && ri <= 32) ? (int)ri : 0;
+  A.scheme = prm->scheme;
+  A.passes = prm->limiter_passes;
+  A.nslots = L.nslots;
+  A.ref = (const RefTables *)(ws + L.off_ref);
+  ctx->dref = (RefTables *)(ws + L.off_ref);
+  A.ctl = (Ctl *)(ws + L.off_ctl);
+  A.col = (int32_t *)(ws + L.off_col);
+  A.c = (double *)(ws + L.off_c);
+  A.meta = (uint8_t *)(ws + L.off_meta);
+  A.rowlen = (int32_t *)(ws + L.off_rowlen);
+  for (int k = 0; k < 3; ++k) ctx->U[k] = (double *)(ws + L.off_U[k]);
+  ctx->cur = 0;
+  A.Wc = (double *)(ws + L.off_Wc);
+  A.Nev = (double *)(ws + L.off_N);
+  A.q = (double *)(ws + L.off_q);
+  A.B = (double *)(ws + L.off_B);
+  A.UL = (double *)(ws + L.off_UL);
+  A.dUH = (double *)(ws + L.off_dUH);
+  A.U1 = (double *)(ws + L.off_U1);
+  A.dL = (double *)(ws + L.off_dL);
+  A.l1 = (double *)(ws + L.off_l1);
+
+  RefTables *T = new RefTables();
+  if (!build_ref_tables(mesh->dim, mesh->degree, h, T, &err)) {
+    delete T;
+    delete ctx;
+    return GDG_E_INVALID;
+  }
+  for (int a = 0; a < L.nloc; ++a) {
+    double hh = std::pow(T->mlump[a] / vol, 1.0 / mesh->dim);
+    T->hpk[a] = prm->c_k * std::pow(hh, A.pk);
+    T->relax[a] = prm->c_r * std::pow(hh, prm->p_r);
+    if (!(T->relax[a] < 1.0)) {
+      delete T;
+      delete ctx;
+      return GDG_E_INVALID;  // r^- = 1 - c_r h^p_r must stay positive
+    }
+  }
+  std::memset(&ctx->hctl, 0, sizeof(Ctl));
+  hipError_t e1 = hipMemcpyAsync(ctx->dref, T, sizeof(RefTables), hipMemcpyHostToDevice, ctx->stream);
+  hipError_t e2 = hipMemcpyAsync(A.ctl, &ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream);
+  int rc = (e1 == hipSuccess && e2 == hipSuccess) ? launch_fill(A, ctx->stream) : -1;
+  hipError_t e3 = hipStreamSynchronize(ctx->stream);
+  delete T;
+  if (rc != 0 || e3 != hipSuccess) {
+    delete ctx;
+    return GDG_E_DEVICE;
+  }
+  *out = ctx;
+  return GDG_OK;
+}
+
+void gdg_destroy(gdg_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+}
+
+int64_t gdg_num_dofs(const gdg_ctx *ctx) { return ctx ? ctx->A.N : -1; }
+
+gdg_status gdg_node_coords(const gdg_ctx *ctx, double *xyz) {
+  if (!ctx || !xyz) return GDG_E_INVALID;
+  const gdg_mesh_desc &m = ctx->mesh;
+  const int d = m.dim, nb = m.degree + 1, nloc = ctx->A.nloc;
+  const double xg2[3] = {0.0, 0.5, 1.0}, xg1[2] = {0.0, 1.0};
+  const double *xg = m.degree == 1 ? xg1 : xg2;
+  for (int64_t i = 0; i < ctx->A.N; ++i) {
+    int64_t K = i / nloc;
+    int a = (int)(i % nloc);
+    for (int e = 0; e < d; ++e) {
+      int64_t ke = K % m.cells[e];
+      K /= m.cells[e];
+      int ae = a % nb;
+      a /= nb;
+      double h = (m.hi[e] - m.lo[e]) / (double)m.cells[e];
+      xyz[i * d + e] = m.lo[e] + ((double)ke + xg[ae]) * h;
+    }
+  }
+  return GDG_OK;
+}
+
+gdg_status gdg_upload_state(gdg_ctx *ctx, const double *U, int32_t is_device_ptr) {
+  if (!ctx || !U) return GDG_E_INVALID;
+  (void)is_device_ptr;
+  const size_t bytes = (size_t)ctx->M * ctx->A.N * sizeof(double);
+  HIPCHK(ctx, hipMemcpyAsync(ctx->U[ctx->cur], U, bytes, hipMemcpyDefault, ctx->stream));
+  if (gdg_status s = launched(ctx, launch_begin(ctx->A, 0.0, 0.0, ctx->stream), "begin")) return s;
+  if (gdg_status s = launched(ctx, launch_prim(ctx->A, ctx->U[ctx->cur], ctx->stream), "prim")) return s;
+  if (gdg_status s = read_ctl(ctx)) return s;
+  ctx->t = 0.0;
+  ctx->steps = ctx->restarts = 0;
+  ctx->last_dt = 0.0;
+  if (ctx->hctl.bad_flag) {
+    ctx->err = "uploaded state is not admissible (rho <= 0, eps <= 0 or NaN)";
+    return GDG_E_INADMISSIBLE;
+  }
+  ctx->err.clear();
+  return GDG_OK;
+}
+
+gdg_status gdg_download_state(gdg_ctx *ctx, double *U, int32_t is_device_ptr) {
+  if (!ctx || !U) return GDG_E_INVALID;
+  (void)is_device_ptr;
+  const size_t bytes = (size_t)ctx->M * ctx->A.N * sizeof(double);
+  HIPCHK(ctx, hipMemcpyAsync(U, ctx->U[ctx->cur], bytes, hipMemcpyDefault, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return GDG_OK;
+}
+
+gdg_status gdg_step(gdg_ctx *ctx, double dt_cap, double dt_fixed, double *dt_taken) {
+  if (!ctx) return GDG_E_INVALID;
+  double tau_fixed = dt_fixed > 0.0 ? dt_fixed : 0.0;
+  const int c0 = ctx->cur, c1 = (c0 + 1) % 3, c2 = (c0 + 2) % 3;
+  for (int attempt = 0; attempt <= 8; ++attempt) {
+    const KArgs &A = ctx->A;
+    if (gdg_status s = launched(ctx, launch_begin(A, dt_cap, tau_fixed, ctx->stream), "begin")) return s;
+    StageBufs b1 = {ctx->U[c0], ctx->U[c1], ctx->U[c0], 0.0, 1.0};
+    StageBufs b2 = {ctx->U[c1], ctx->U[c2], ctx->U[c0], 0.75, 0.25};
+    StageBufs b3 = {ctx->U[c2], ctx->U[c0], ctx->U[c0], 1.0 / 3.0, 2.0 / 3.0};
+    if (gdg_status s = launched(ctx, launch_stage(A, b1, 0, ctx->stream), "stage 1")) return s;
+    if (gdg_status s = launched(ctx, launch_stage(A, b2, 1, ctx->stream), "stage 2")) return s;
+    if (gdg_status s = launched(ctx, launch_stage(A, b3, 2, ctx->stream), "stage 3")) return s;
+    if (gdg_status s = launched(ctx, launch_end(A, ctx->stream), "end")) return s;
+    if (gdg_status s = read_ctl(ctx)) return s;
+    const Ctl &h = ctx->hctl;
+    if (h.cfl_flag) {
+      const int vs = h.viol_stage < 1 ? 1 : h.viol_stage;
+      tau_fixed = ctx->prm.cfl * bits_to_double(h.taumin_bits[vs]);
+      ++ctx->restarts;
+      continue;
+    }
+    if (h.bad_flag) {
+      ctx->err = "a stage output left the admissible set";
+      return GDG_E_INADMISSIBLE;
+    }
+    ctx->last_dt = h.tau;
+    if (dt_cap > 0.0 && h.tau == dt_cap) ctx->t = ctx->t + dt_cap;
+    else ctx->t += h.tau;
+    ++ctx->steps;
+    if (dt_taken) *dt_taken = h.tau;
+    return GDG_OK;
+  }
+  ctx->err = "CFL condition violated after 8 restarts";
+  return GDG_E_CFL;
+}
+
+gdg_status gdg_run_to(gdg_ctx *ctx, double t_final, int64_t max_steps, gdg_stats *stats) {
+  if (!ctx) return GDG_E_INVALID;
+  int64_t n = 0;
+  while (ctx->t < t_final && n < max_steps) {
+    double dt = 0.0, cap = t_final - ctx->t;
+    gdg_status s = gdg_step(ctx, cap, 0.0, &dt);
+    if (s != GDG_OK) return s;
+    if (dt == cap) ctx->t = t_final;
+    ++n;
+  }
+  return gdg_get_stats(ctx, stats);
+}
+
+gdg_status gdg_stage(gdg_ctx *ctx, double tau, double *tau_used) {
+  if (!ctx) return GDG_E_INVALID;
+  const int c0 = ctx->cur, c1 = (c0 + 1) % 3;
+  if (gdg_status s = launched(ctx, launch_begin(ctx->A, 0.0, tau > 0.0 ? tau : 0.0, ctx->stream), "begin")) return s;
+  StageBufs b = {ctx->U[c0], ctx->U[c1], ctx->U[c0], 0.0, 1.0};
+  if (gdg_status s = launched(ctx, launch_stage(ctx->A, b, 0, ctx->stream), "stage")) return s;
+  if (gdg_status s = read_ctl(ctx)) return s;
+  if (ctx->hctl.bad_flag) {
+    ctx->err = "the stage output left the admissible set";
+    return GDG_E_INADMISSIBLE;
+  }
+  ctx->cur = c1;
+  if (tau_used) *tau_used = ctx->hctl.tau;
+  return GDG_OK;
+}
+
+gdg_status gdg_read_field(gdg_ctx *ctx, int32_t field, double *dst, int32_t is_device_ptr) {
+  if (!ctx || !dst) return GDG_E_INVALID;
+  (void)is_device_ptr;
+  const size_t N = (size_t)ctx->A.N, M = (size_t)ctx->M;
+  const double *src = nullptr;
+  size_t planes = 0;
+  switch (field) {
+    case GDG_FIELD_STATE: src = ctx->U[ctx->cur]; planes = M; break;
+    case GDG_FIELD_EV_N: src = ctx->A.Nev; planes = 1; break;
+    case GDG_FIELD_BOUNDS: src = ctx->A.B; planes = 3; break;
+    case GDG_FIELD_UL: src = ctx->A.UL; planes = M; break;
+    case GDG_FIELD_DUH: src = ctx->A.dUH; planes = M; break;
+    case GDG_FIELD_U1: src = ctx->A.U1; planes = M; break;
+    default: ctx->err = "unknown field"; return GDG_E_INVALID;
+  }
+  HIPCHK(ctx, hipMemcpyAsync(dst, src, planes * N * sizeof(double), hipMemcpyDefault, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return GDG_OK;
+}
+
+gdg_status gdg_get_stats(const gdg_ctx *ctx, gdg_stats *stats) {
+  if (!ctx) return GDG_E_INVALID;
+  if (stats) {
+    stats->t = ctx->t;
+    stats->steps = ctx->steps;
+    stats->restarts = ctx->restarts;
+    stats->last_dt = ctx->last_dt;
+  }
+  return GDG_OK;
+}
+
+const char *gdg_last_error(const gdg_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+}  // extern "C"

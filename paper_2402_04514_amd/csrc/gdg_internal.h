@@ -1,0 +1,109 @@
+// gdg_internal.h -- data layout shared by the host setup and the HIP kernels
+// of libgdg.  Not part of the public interface (include/gdg.h is).
+//
+// Stencil layout on the device: row-blocked ELL.  A block is R = C * nloc
+// consecutive rows (C whole cells), the rows of one workgroup, so a cell's
+// dofs are always in one workgroup (its consistent-mass block can be solved
+// in LDS).  Every block has the same width W = nloc + dim * (k+1)^(dim-1), the
+// widest row (a cell corner with all neighbours); narrower rows are padded.
+// Slot t of row lane r in block b lives at index (b * W + t) * R + r, so the
+// lanes of a wavefront read consecutive addresses for every slot.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+
+namespace gdg {
+
+// slot kinds (low 3 bits of the meta byte)
+enum : uint8_t {
+  SK_PAD = 0,
+  SK_CELL = 1,        // j in the same cell (the diagonal included); aux = local index of j
+  SK_FACE_COLLOC = 2, // j across a face, x_j = x_i (topologically)
+  SK_FACE = 3,        // j across a face, other node of that face
+  SK_GHOST = 4        // boundary part: col = i, c = c_i^{d,k}; aux = boundary kind
+};
+static inline int meta_kind(uint8_t m) { return m & 7; }
+static inline int meta_aux(uint8_t m) { return m >> 3; }
+
+constexpr int kBlockThreads = 256;
+constexpr int kMaxD = 3;
+constexpr int kMaxNloc = 27;
+
+// Per-step control block in device memory.
+struct Ctl {
+  unsigned long long taumin_bits[3]; // per stage: min_i m_i / (2 |d_ii|) as IEEE bits
+  double tau;                        // tau of the current step
+  double dt_cap;                     // cap on tau (<= 0: none)
+  double tau_fixed;                  // > 0: replaces the CFL rule in stage 1
+  double t;                          // simulated time
+  long long steps;
+  // Set when stage 2 or 3 finds tau above its CFL bound.  Every block of the
+  // detecting kernel reaches the same decision from the same data, and later
+  // kernels read it only at their start, so exits stay uniform.
+  int cfl_flag;
+  int bad_flag;                      // a state left A; read by the host only
+  int viol_stage;
+};
+
+// Reference tables of one cell class (every cell of a uniform mesh).
+struct RefTables {
+  double mlump[kMaxNloc];                   // m_a
+  double mblk[kMaxNloc * kMaxNloc];         // m_ab
+  double minv[kMaxNloc * kMaxNloc];         // (M_K^{-1})_ab
+  double cin[kMaxNloc * kMaxNloc * kMaxD];  // in-cell c_ab (a row, b column, axis)
+  // across face f (0..5): for row a on face f and t-th node b of the touching
+  // face of the neighbour: c vector, local index of b, collocation flag
+  double cface[6 * kMaxNloc * 9 * kMaxD];
+  int32_t bface[6 * 9];
+  int32_t colloc[6 * kMaxNloc * 9];
+  double cghost[6 * kMaxNloc * kMaxD];      // c_a^{d,f}
+  int32_t onface[6 * kMaxNloc];             // 1 if node a lies on face f
+  // per node a, from the scheme constants
+  double hpk[kMaxNloc];    // c_k * hhat_a^{p_k}, hhat_a = (m_a/|Omega|)^{1/d} (eq. ViscMin)
+  double relax[kMaxNloc];  // c_r * hhat_a^{p_r} (eq. ViscMinConst2)
+};
+
+// Everything a kernel needs, passed by value.
+struct KArgs {
+  int64_t N, nblocks, ncells;
+  int32_t R, W, nloc, nb1, deg, dim, cpb;
+  int64_t cells[3];
+  int32_t bc[6];
+  double gamma, cfl, c_ev, c_k, pk, c_r, p_r, vol;
+  double alpha, inv_alpha;
+  int32_t ipow;     // > 0: 1/alpha equals this integer, the p* power is taken by multiplies
+  int32_t scheme, passes;
+  // stencil
+  int32_t *col;
+  double *c;        // dim planes of nslots
+  uint8_t *meta;
+  int32_t *rowlen;
+  const RefTables *ref;
+  int64_t nslots;
+  // per-dof fields
+  double *Wc;       // node cache: dim velocities, p, a, p^-alpha, f(s), s~  (dim+5 planes)
+  double *Nev;      // entropy-viscosity ratio
+  double *q;        // ring-1 bound partials: rho_min, rho_max, s~_min
+  double *B;        // relaxed bounds
+  double *UL, *dUH, *U1;
+  double *dL;       // d^L (and d^{d,L} on ghost slots) per slot
+  double *l1;       // l of limiter pass 1 per slot (the ghost slot of a row holds l_i^d)
+  Ctl *ctl;
+};
+
+// host-side entry points of the kernels (gdg_kernels.hip)
+struct StageBufs {
+  const double *in;   // stage input state
+  double *out;        // stage output (may alias Un)
+  const double *Un;   // state at the start of the step (SSP combination)
+  double ca, cb;      // out = ca * Un + cb * Phi(in)
+};
+bool build_ref_tables(int dim, int deg, const double *h, RefTables *T, std::string *err);
+int launch_fill(const KArgs &A, void *stream);
+int launch_begin(const KArgs &A, double dt_cap, double tau_fixed, void *stream);
+int launch_end(const KArgs &A, void *stream);
+int launch_prim(const KArgs &A, const double *U, void *stream);
+int launch_stage(const KArgs &A, const StageBufs &b, int stage, void *stream);
+
+}  // namespace gdg

@@ -1,0 +1,701 @@
+// gdg_kernels.hip -- the per-stage sweeps of the graph-based DG scheme on
+// gfx950 (FP64).  One thread owns one row i of the stencil; a workgroup owns
+// whole cells (R rows), so the cell-local consistent-mass solve runs in LDS.
+//
+// Sweeps of one forward-Euler stage Phi(U; tau):
+//   k_prim    per node: velocity, pressure, sound speed, p^-alpha, Harten
+//             entropy f(s), rescaled entropy s~ (Sec. 2.2, Sec. 5.2, 5.4)
+//   k_sweep1  d^L_ij, d_i^{d,k} (eq. dij_low_order, dij_low_order_modified),
+//             min_i m_i/(2|d_ii|) (eq. MaxCFLdt), the entropy-viscosity ratio
+//             N_i (Sec. 5.2) and ring-1 partial bounds over bar states
+//             (eq. UsualBarState)
+//   k_sweep2  tau, U^L (eq. cijdijschememodified), the relaxed bounds
+//             (eq. local_bounds), d^H (eq. HighOrderViscosity, ViscMin), the
+//             high-order residual and the cell solve (eq. HighScheme)
+//   k_limit   the antidiffusive fluxes A_ij (eq. HighLowOrderIdentity) and
+//             one limiter pass (eq. ConvexScheme, Lemma ConsInvariants); run
+//             twice (Sec. 6.1), the second pass on the remaining (1 - l) A
+// Every grid-wide dependency (tau, neighbours' N_j and bound partials, their
+// U^L_j / B_j / dU^H_j, the symmetric l_ij) is a kernel boundary.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "gdg_internal.h"
+
+namespace gdg {
+
+__device__ __forceinline__ double ipow_d(double x, int n) {
+  double r = 1.0, b = x;
+  while (n > 0) {
+    if (n & 1) r *= b;
+    b *= b;
+    n >>= 1;
+  }
+  return r;
+}
+
+// Two-rarefaction upper bound of the maximum wave speed of the projected
+// Riemann problem (Guermond & Popov 2016), valid for 1 < gamma <= 5/3.
+// Left state (rl, ul, pl, al, pal = pl^-alpha), right state likewise; ul, ur
+// are the velocities projected on the unit normal.
+__device__ __forceinline__ double lambda_plus(const KArgs &A, double rl, double ul, double pl,
+                                              double al, double pal, double rr, double ur,
+                                              double pr, double ar, double par) {
+  (void)rl;
+  (void)rr;
+  const double g = A.gamma;
+  double num = al + ar - 0.5 * (g - 1.0) * (ur - ul);
+  double pstar = 0.0;
+  if (num > 0.0) {
+    double x = num / (al * pal + ar * par);
+    pstar = A.ipow > 0 ? ipow_d(x, A.ipow) : pow(x, A.inv_alpha);
+  }
+  double kf = (g + 1.0) / (2.0 * g);
+  double l1 = ul - al * sqrt(1.0 + kf * fmax(pstar - pl, 0.0) / pl);
+  double l3 = ur + ar * sqrt(1.0 + kf * fmax(pstar - pr, 0.0) / pr);
+  return fmax(fmax(-l1, l3), 0.0);
+}
+
+// f(U) c for the Euler flux of eq. euler_flux, from conserved U and the
+// velocity u and pressure p of the node.
+template <int D>
+__device__ __forceinline__ void flux_dot(const double *U, const double *u, double p, const double *c,
+                                         double *out) {
+  double uc = 0.0;
+  for (int e = 0; e < D; ++e) uc += u[e] * c[e];
+  out[0] = U[0] * uc;
+  for (int e = 0; e < D; ++e) out[1 + e] = U[1 + e] * uc + p * c[e];
+  out[D + 1] = (U[D + 1] + p) * uc;
+}
+
+template <int D>
+__device__ __forceinline__ double eps_of(const double *V) {
+  double m2 = 0.0;
+  for (int e = 0; e < D; ++e) m2 += V[1 + e] * V[1 + e];
+  return V[D + 1] - 0.5 * m2 / V[0];
+}
+
+// ---------------------------------------------------------------------------
+// Line search of Sec. 5.4: the largest l in [0, 1] with U + l P in B_i.
+// Density part in closed form; rescaled-entropy part on the concave
+// psi(l) = eps(U + l P) - s_min rho(U + l P)^gamma by a bracket narrowed with a
+// secant step (feasible side) and a tangent step at the infeasible end, until
+// the bracket is 1e-14 wide; the feasible end is returned.
+template <int D>
+__device__ double ls_psi(double g, const double *U, const double *P, double smin, double l,
+                         double *dpsi) {
+  double V[D + 2];
+  for (int c = 0; c < D + 2; ++c) V[c] = U[c] + l * P[c];
+  double eps = eps_of<D>(V);
+  double rg = pow(V[0], g);
+  if (dpsi) {
+    double u2 = 0.0, dot = 0.0;
+    for (int e = 0; e < D; ++e) {
+      double u = V[1 + e] / V[0];
+      u2 += u * u;
+      dot -= u * P[1 + e];
+    }
+    dot += 0.5 * u2 * P[0] + P[D + 1];
+    *dpsi = dot - smin * g * rg / V[0] * P[0];
+  }
+  return eps - smin * rg;
+}
+
+template <int D>
+__device__ double line_search(double g, const double *U, const double *P, double rmin, double rmax,
+                              double smin) {
+  const double r = U[0], pr = P[0];
+  double lhi = 1.0;
+  if (r + pr > rmax) lhi = (rmax - r) / pr;
+  if (r + pr < rmin) lhi = (rmin - r) / pr;
+  if (!(lhi > 0.0)) lhi = 0.0;
+  if (lhi > 1.0) lhi = 1.0;
+  double ph = ls_psi<D>(g, U, P, smin, lhi, nullptr);
+  if (ph >= 0.0) return lhi;
+  double p0 = ls_psi<D>(g, U, P, smin, 0.0, nullptr);
+  if (p0 <= 0.0) return 0.0;
+  double l = 0.0, rr = lhi, pl = p0, prr = ph;
+  for (int it = 0; it < 60; ++it) {
+    if (rr - l <= 1e-14) break;
+    double x = l + pl * (rr - l) / (pl - prr);
+    if (!(x > l && x < rr)) x = 0.5 * (l + rr);
+    double px = ls_psi<D>(g, U, P, smin, x, nullptr);
+    if (px >= 0.0) { l = x; pl = px; } else { rr = x; prr = px; }
+    if (rr - l <= 1e-14) break;
+    double dr;
+    ls_psi<D>(g, U, P, smin, rr, &dr);
+    x = dr < 0.0 ? rr - prr / dr : 0.5 * (l + rr);
+    if (!(x > l && x < rr)) x = 0.5 * (l + rr);
+    px = ls_psi<D>(g, U, P, smin, x, nullptr);
+    if (px >= 0.0) { l = x; pl = px; } else { rr = x; prr = px; }
+  }
+  return l;
+}
+
+// ---------------------------------------------------------------------------
+// Setup: expand the cell-class tables into the row-blocked ELL stencil.
+template <int D, int DEG>
+__global__ __launch_bounds__(kBlockThreads) void k_fill(KArgs A) {
+  constexpr int NB = DEG + 1;
+  constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
+  constexpr int NFACE = NLOC / NB;
+  const int lane = threadIdx.x;
+  if (lane >= A.R) return;
+  const int64_t blk = blockIdx.x;
+  const int64_t i = blk * A.R + lane;
+  const RefTables *T = A.ref;
+  int t = 0;
+  auto put = [&](int32_t col, const double *c, uint8_t meta) {
+    int64_t s = (blk * A.W + t) * A.R + lane;
+    A.col[s] = col;
+    for (int e = 0; e < D; ++e) A.c[e * A.nslots + s] = c ? c[e] : 0.0;
+    A.meta[s] = meta;
+    ++t;
+  };
+  int graph = 0;
+  if (i < A.N) {
+    const int64_t K = i / NLOC;
+    const int a = (int)(i % NLOC);
+    int64_t ki[3] = {0, 0, 0};
+    int64_t r = K;
+    for (int e = 0; e < D; ++e) { ki[e] = r % A.cells[e]; r /= A.cells[e]; }
+    for (int b = 0; b < NLOC; ++b) {
+      put((int32_t)(K * NLOC + b), &T->cin[(a * NLOC + b) * kMaxD], (uint8_t)(SK_CELL | (b << 3)));
+      ++graph;
+    }
+    for (int f = 0; f < 2 * D; ++f) {
+      if (!T->onface[f * kMaxNloc + a]) continue;
+      const int e = f / 2, side = f % 2;
+      int64_t kn[3] = {ki[0], ki[1], ki[2]};
+      kn[e] += side ? 1 : -1;
+      bool bnd = false;
+      if (kn[e] < 0 || kn[e] >= A.cells[e]) {
+        if (A.bc[f] == 0) kn[e] = (kn[e] + A.cells[e]) % A.cells[e];
+        else bnd = true;
+      }
+      if (bnd) {
+        put((int32_t)i, &T->cghost[(f * kMaxNloc + a) * kMaxD], (uint8_t)(SK_GHOST | (A.bc[f] << 3)));
+        continue;
+      }
+      int64_t Kn = 0, stride = 1;
+      for (int e2 = 0; e2 < D; ++e2) { Kn += kn[e2] * stride; stride *= A.cells[e2]; }
+      for (int tt = 0; tt < NFACE; ++tt) {
+        int b = T->bface[f * 9 + tt];
+        int co = T->colloc[(f * kMaxNloc + a) * 9 + tt];
+        put((int32_t)(Kn * NLOC + b), &T->cface[((f * kMaxNloc + a) * 9 + tt) * kMaxD],
+            (uint8_t)(co ? SK_FACE_COLLOC : SK_FACE));
+        ++graph;
+      }
+    }
+    A.rowlen[i] = graph;
+  }
+  while (t < A.W) put((int32_t)(i < A.N ? i : 0), nullptr, SK_PAD);
+}
+
+__global__ void k_begin(Ctl *ctl, double dt_cap, double tau_fixed) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    for (int s = 0; s < 3; ++s) ctl->taumin_bits[s] = 0x7ff0000000000000ull;  // +inf
+    ctl->cfl_flag = 0;
+    ctl->bad_flag = 0;
+    ctl->viol_stage = -1;
+    ctl->dt_cap = dt_cap;
+    ctl->tau_fixed = tau_fixed;
+  }
+}
+
+__global__ void k_end(Ctl *ctl) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && ctl->cfl_flag == 0 && ctl->bad_flag == 0) {
+    ctl->t += ctl->tau;
+    ctl->steps += 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(kBlockThreads) void k_prim(KArgs A, const double *__restrict__ U) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.N) return;
+  const int64_t N = A.N;
+  const double g = A.gamma;
+  double V[D + 2];
+  for (int c = 0; c < D + 2; ++c) V[c] = U[c * N + i];
+  double rho = V[0];
+  double eps = eps_of<D>(V);
+  if (!(rho > 0.0) || !(eps > 0.0)) atomicOr(&A.ctl->bad_flag, 1);
+  double p = (g - 1.0) * eps;
+  double rg = pow(rho, -g);
+  for (int e = 0; e < D; ++e) A.Wc[e * N + i] = V[1 + e] / rho;
+  A.Wc[(D + 0) * N + i] = p;
+  A.Wc[(D + 1) * N + i] = sqrt(g * p / rho);
+  A.Wc[(D + 2) * N + i] = pow(p, -A.alpha);
+  A.Wc[(D + 3) * N + i] = exp(log(rg * p) / (g + 1.0));  // Harten entropy f(s) = e^{s/(gamma+1)}
+  A.Wc[(D + 4) * N + i] = rg * eps;                      // s~ = rho^-gamma eps
+}
+
+template <int D>
+struct Node {
+  double U[D + 2];
+  double u[D];
+  double p, a, pal, fs, st;
+};
+
+template <int D>
+__device__ __forceinline__ void load_node(const KArgs &A, const double *__restrict__ U, int64_t j,
+                                          Node<D> &n) {
+  const int64_t N = A.N;
+  for (int c = 0; c < D + 2; ++c) n.U[c] = U[c * N + j];
+  for (int e = 0; e < D; ++e) n.u[e] = A.Wc[e * N + j];
+  n.p = A.Wc[(D + 0) * N + j];
+  n.a = A.Wc[(D + 1) * N + j];
+  n.pal = A.Wc[(D + 2) * N + j];
+  n.fs = A.Wc[(D + 3) * N + j];
+  n.st = A.Wc[(D + 4) * N + j];
+}
+
+// Boundary data of Sec. 4.1: outflow keeps U_i; slip reflects the normal
+// momentum (eq. slip_boundary).  Pressure, sound speed and entropy are those
+// of U_i in both cases.
+template <int D>
+__device__ __forceinline__ void ghost_node(const Node<D> &ni, int kind, const double *n, Node<D> &gh) {
+  gh = ni;
+  if (kind == 2) {
+    double mn = 0.0, un = 0.0;
+    for (int e = 0; e < D; ++e) { mn += ni.U[1 + e] * n[e]; un += ni.u[e] * n[e]; }
+    for (int e = 0; e < D; ++e) {
+      gh.U[1 + e] = ni.U[1 + e] - 2.0 * mn * n[e];
+      gh.u[e] = ni.u[e] - 2.0 * un * n[e];
+    }
+  }
+}
+
+__device__ __forceinline__ double block_min_atomic(double v, unsigned long long *dst) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMin(dst, (unsigned long long)__double_as_longlong(v));
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+template <int D, int DEG>
+__global__ __launch_bounds__(kBlockThreads) void k_sweep1(KArgs A, const double *__restrict__ U,
+                                                          int stage) {
+  constexpr int M = D + 2;
+  constexpr int NB = DEG + 1;
+  constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
+  if (A.ctl->cfl_flag) return;  // set by an earlier kernel or never
+  const int lane = threadIdx.x;
+  const int64_t blk = blockIdx.x;
+  const int64_t i = blk * A.R + lane;
+  const bool active = lane < A.R && i < A.N;
+  double tau_i = INFINITY;
+  if (active) {
+    const double g = A.gamma;
+    Node<D> ni;
+    load_node<D>(A, U, i, ni);
+    // gradient of the shifted Harten entropy at U_i, rho_i f'(s_i) grad s(U_i)
+    double grad[M];
+    {
+      double u2 = 0.0;
+      for (int e = 0; e < D; ++e) u2 += ni.u[e] * ni.u[e];
+      double gp = (g - 1.0) / ni.p;
+      grad[0] = gp * 0.5 * u2 - g / ni.U[0];
+      for (int e = 0; e < D; ++e) grad[1 + e] = -gp * ni.u[e];
+      grad[M - 1] = gp;
+      double sc = ni.U[0] * ni.fs / (g + 1.0);
+      for (int c = 0; c < M; ++c) grad[c] *= sc;
+    }
+    double T = 0.0, S[M];
+    for (int c = 0; c < M; ++c) S[c] = 0.0;
+    double dsum = 0.0;
+    double rmin = INFINITY, rmax = -INFINITY, smin = INFINITY;
+    for (int t = 0; t < A.W; ++t) {
+      const int64_t s = (blk * A.W + t) * A.R + lane;
+      const uint8_t meta = A.meta[s];
+      const int kind = meta & 7;
+      if (kind == SK_PAD) { A.dL[s] = 0.0; continue; }
+      double c[D];
+      for (int e = 0; e < D; ++e) c[e] = A.c[e * A.nslots + s];
+      double nc2 = 0.0;
+      for (int e = 0; e < D; ++e) nc2 += c[e] * c[e];
+      const double nc = sqrt(nc2);
+      if (kind == SK_GHOST) {
+        double n[D];
+        for (int e = 0; e < D; ++e) n[e] = c[e] / nc;
+        Node<D> gh;
+        ghost_node<D>(ni, meta >> 3, n, gh);
+        double ul = 0.0, ur = 0.0;
+        for (int e = 0; e < D; ++e) { ul += ni.u[e] * n[e]; ur += gh.u[e] * n[e]; }
+        double d = nc * lambda_plus(A, ni.U[0], ul, ni.p, ni.a, ni.pal, gh.U[0], ur, gh.p, gh.a, gh.pal);
+        A.dL[s] = d;
+        dsum += d;
+        double fj[M], fi[M];
+        flux_dot<D>(gh.U, gh.u, gh.p, c, fj);
+        flux_dot<D>(ni.U, ni.u, ni.p, c, fi);
+        double mc = 0.0;
+        for (int e = 0; e < D; ++e) mc += gh.U[1 + e] * c[e];
+        T += mc * (gh.fs - ni.fs);
+        for (int q = 0; q < M; ++q) S[q] += fj[q] - fi[q];
+        continue;
+      }
+      const int64_t j = A.col[s];
+      Node<D> nj;
+      load_node<D>(A, U, j, nj);
+      rmin = fmin(rmin, nj.U[0]);
+      rmax = fmax(rmax, nj.U[0]);
+      smin = fmin(smin, nj.st);
+      if (j == i || nc == 0.0) { A.dL[s] = 0.0; continue; }
+      // d^L_ij from the lower index, so d_ij = d_ji bitwise
+      const bool lo = i < j;
+      const Node<D> &na = lo ? ni : nj;
+      const Node<D> &nb = lo ? nj : ni;
+      const double sg = lo ? 1.0 : -1.0;
+      double ua = 0.0, ub = 0.0;
+      for (int e = 0; e < D; ++e) {
+        double ne = sg * c[e] / nc;
+        ua += na.u[e] * ne;
+        ub += nb.u[e] * ne;
+      }
+      const double d = nc * lambda_plus(A, na.U[0], ua, na.p, na.a, na.pal, nb.U[0], ub, nb.p, nb.a, nb.pal);
+      A.dL[s] = d;
+      dsum += d;
+      double fj[M], fi[M];
+      flux_dot<D>(nj.U, nj.u, nj.p, c, fj);
+      flux_dot<D>(ni.U, ni.u, ni.p, c, fi);
+      double mc = 0.0;
+      for (int e = 0; e < D; ++e) mc += nj.U[1 + e] * c[e];
+      T += mc * (nj.fs - ni.fs);
+      double bar[M];
+      for (int q = 0; q < M; ++q) {
+        double df = fj[q] - fi[q];
+        S[q] += df;
+        bar[q] = 0.5 * (ni.U[q] + nj.U[q]) - df / (2.0 * d);
+      }
+      rmin = fmin(rmin, bar[0]);
+      rmax = fmax(rmax, bar[0]);
+      smin = fmin(smin, pow(bar[0], -g) * eps_of<D>(bar));
+    }
+    double R = T, Dn = fabs(T);
+    for (int q = 0; q < M; ++q) { R -= grad[q] * S[q]; Dn += fabs(grad[q]) * fabs(S[q]); }
+    A.Nev[i] = Dn > 0.0 ? R / Dn : 0.0;
+    A.q[i] = rmin;
+    A.q[A.N + i] = rmax;
+    A.q[2 * A.N + i] = smin;
+    const double mi = A.ref->mlump[i % NLOC];
+    tau_i = mi / (2.0 * dsum);
+  }
+  block_min_atomic(tau_i, &A.ctl->taumin_bits[stage]);
+}
+
+// high-order viscosity of eq. HighOrderViscosity / ViscMin for a graph pair
+__device__ __forceinline__ double visc_high(const KArgs &A, double d, double Ni, double Nj, int kind,
+                                           double hpk) {
+  double dev = d * fmin(A.c_ev * fmax(fabs(Ni), fabs(Nj)), 1.0);
+  double dmin = kind == SK_FACE_COLLOC ? A.c_k * hpk * d : 0.0;
+  return fmax(dmin, dev);
+}
+
+// ---------------------------------------------------------------------------
+// Resolves tau of this stage; returns false (uniformly) if the stage must stop.
+__device__ __forceinline__ bool stage_tau(const KArgs &A, int stage, double *tau) {
+  if (A.ctl->cfl_flag) return false;
+  const double tm = __longlong_as_double((long long)A.ctl->taumin_bits[stage]);
+  if (stage == 0) {
+    double t = A.ctl->tau_fixed > 0.0 ? A.ctl->tau_fixed : A.cfl * tm;
+    if (A.ctl->dt_cap > 0.0 && t > A.ctl->dt_cap) t = A.ctl->dt_cap;
+    *tau = t;
+    return true;
+  }
+  *tau = A.ctl->tau;
+  return !(*tau > tm);
+}
+
+template <int D, int DEG>
+__global__ __launch_bounds__(kBlockThreads) void k_sweep2(KArgs A, StageBufs sb, int stage) {
+  constexpr int M = D + 2;
+  constexpr int NB = DEG + 1;
+  constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
+  __shared__ double rs[M][kBlockThreads];
+  double tau;
+  if (!stage_tau(A, stage, &tau)) {
+    if (stage > 0 && blockIdx.x == 0 && threadIdx.x == 0 && A.ctl->cfl_flag == 0) {
+      A.ctl->viol_stage = stage;
+      atomicOr(&A.ctl->cfl_flag, 1);
+    }
+    return;
+  }
+  if (stage == 0 && blockIdx.x == 0 && threadIdx.x == 0) A.ctl->tau = tau;
+  const double *__restrict__ U = sb.in;
+  const int lane = threadIdx.x;
+  const int64_t blk = blockIdx.x;
+  const int64_t i = blk * A.R + lane;
+  const bool active = lane < A.R && i < A.N;
+  const int64_t N = A.N;
+  const double g = A.gamma;
+  Node<D> ni;
+  int a = 0;
+  if (active) {
+    a = (int)(i % NLOC);
+    load_node<D>(A, U, i, ni);
+    const double Ni = A.Nev[i];
+    const double hpk = A.ref->hpk[a];
+    const double mi = A.ref->mlump[a];
+    double accL[M], accH[M];
+    for (int c = 0; c < M; ++c) accL[c] = accH[c] = 0.0;
+    double rmin = INFINITY, rmax = -INFINITY, smin = INFINITY;
+    for (int t = 0; t < A.W; ++t) {
+      const int64_t s = (blk * A.W + t) * A.R + lane;
+      const uint8_t meta = A.meta[s];
+      const int kind = meta & 7;
+      if (kind == SK_PAD) continue;
+      double c[D];
+      for (int e = 0; e < D; ++e) c[e] = A.c[e * A.nslots + s];
+      const double d = A.dL[s];
+      if (kind == SK_GHOST) {
+        double nc2 = 0.0;
+        for (int e = 0; e < D; ++e) nc2 += c[e] * c[e];
+        const double nc = sqrt(nc2);
+        double n[D];
+        for (int e = 0; e < D; ++e) n[e] = c[e] / nc;
+        Node<D> gh;
+        ghost_node<D>(ni, meta >> 3, n, gh);
+        double fj[M], fi[M];
+        flux_dot<D>(gh.U, gh.u, gh.p, c, fj);
+        flux_dot<D>(ni.U, ni.u, ni.p, c, fi);
+        // boundary analogue of eq. HighOrderViscosity: the ghost is collocated
+        const double dH = fmax(hpk * d, d * fmin(A.c_ev * fabs(Ni), 1.0));
+        double bar[M];
+        for (int q = 0; q < M; ++q) {
+          double df = fj[q] - fi[q];
+          double du = gh.U[q] - ni.U[q];
+          accL[q] += df - d * du;
+          accH[q] += df - dH * du;
+          bar[q] = 0.5 * (gh.U[q] + ni.U[q]) - df / (2.0 * d);  // eq. BoundaryBarState
+        }
+        rmin = fmin(rmin, bar[0]);
+        rmax = fmax(rmax, bar[0]);
+        smin = fmin(smin, pow(bar[0], -g) * eps_of<D>(bar));
+        continue;
+      }
+      const int64_t j = A.col[s];
+      rmin = fmin(rmin, A.q[j]);
+      rmax = fmax(rmax, A.q[N + j]);
+      smin = fmin(smin, A.q[2 * N + j]);
+      if (j == i) continue;
+      double Uj[M], uj[D];
+      for (int q = 0; q < M; ++q) Uj[q] = U[q * N + j];
+      for (int e = 0; e < D; ++e) uj[e] = A.Wc[e * N + j];
+      const double pj = A.Wc[D * N + j];
+      double fj[M], fi[M];
+      flux_dot<D>(Uj, uj, pj, c, fj);
+      flux_dot<D>(ni.U, ni.u, ni.p, c, fi);
+      const double dH = visc_high(A, d, Ni, A.Nev[j], kind, hpk);
+      for (int q = 0; q < M; ++q) {
+        double df = fj[q] - fi[q];
+        double du = Uj[q] - ni.U[q];
+        accL[q] += df - d * du;
+        accH[q] += df - dH * du;
+      }
+    }
+    // eq. cijdijschememodified in the difference form
+    double UL[M];
+    for (int q = 0; q < M; ++q) {
+      UL[q] = ni.U[q] - tau / mi * accL[q];
+      A.UL[q * N + i] = UL[q];
+    }
+    // eq. local_bounds with r^-+ = 1 -+ c_r hhat_i^{p_r}
+    const double rel = A.ref->relax[a];
+    A.B[i] = (1.0 - rel) * rmin;
+    A.B[N + i] = (1.0 + rel) * rmax;
+    A.B[2 * N + i] = (1.0 - rel) * smin;
+    for (int q = 0; q < M; ++q) rs[q][lane] = -accH[q];
+    if (A.scheme == 0 || (A.scheme == 2 && A.passes == 0)) {
+      for (int q = 0; q < M; ++q)
+        sb.out[q * N + i] = sb.ca == 0.0 ? UL[q] : sb.ca * sb.Un[q * N + i] + sb.cb * UL[q];
+      if (!(UL[0] > 0.0) || !(eps_of<D>(UL) > 0.0)) atomicOr(&A.ctl->bad_flag, 1);
+    }
+  }
+  __syncthreads();
+  if (!active) return;
+  // eq. HighScheme: M_K dU^H_K = tau r^H_K for the cell of row i, from LDS
+  const int cellbase = lane - a;
+  double V[M];
+  for (int q = 0; q < M; ++q) {
+    double s = 0.0;
+    for (int b = 0; b < NLOC; ++b) s += A.ref->minv[a * NLOC + b] * rs[q][cellbase + b];
+    const double du = tau * s;
+    A.dUH[q * N + i] = du;
+    V[q] = ni.U[q] + du;
+  }
+  if (A.scheme == 1) {
+    for (int q = 0; q < M; ++q)
+      sb.out[q * N + i] = sb.ca == 0.0 ? V[q] : sb.ca * sb.Un[q * N + i] + sb.cb * V[q];
+    if (!(V[0] > 0.0) || !(eps_of<D>(V) > 0.0)) atomicOr(&A.ctl->bad_flag, 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One limiter pass.  pass 0: base = U^L, fluxes A_ij, writes l per slot and
+// U^(1).  pass 1: base = U^(1), fluxes (1 - l^(1)) A_ij.  The final pass writes
+// the stage output (SSP combination).
+template <int D, int DEG>
+__global__ __launch_bounds__(kBlockThreads) void k_limit(KArgs A, StageBufs sb, int pass, int final_pass) {
+  constexpr int M = D + 2;
+  constexpr int NB = DEG + 1;
+  constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
+  if (A.ctl->cfl_flag) return;
+  const int lane = threadIdx.x;
+  const int64_t blk = blockIdx.x;
+  const int64_t i = blk * A.R + lane;
+  if (lane >= A.R || i >= A.N) return;
+  const double *__restrict__ U = sb.in;
+  const double *__restrict__ base = pass == 0 ? A.UL : A.U1;
+  const int64_t N = A.N;
+  const double g = A.gamma;
+  const double tau = A.ctl->tau;
+  const int a = (int)(i % NLOC);
+  const double mi = A.ref->mlump[a];
+  const double hpk = A.ref->hpk[a];
+  const double kap_i = 1.0 / (double)(A.rowlen[i] + 1);
+  const double Ni = A.Nev[i];
+  double Ui[M], Li[M], dUi[M];
+  for (int q = 0; q < M; ++q) {
+    Ui[q] = U[q * N + i];
+    Li[q] = base[q * N + i];
+    dUi[q] = A.dUH[q * N + i];
+  }
+  const double bi_rmin = A.B[i], bi_rmax = A.B[N + i], bi_smin = A.B[2 * N + i];
+  double acc[M], Ab[M];
+  for (int q = 0; q < M; ++q) acc[q] = Ab[q] = 0.0;
+  int64_t gslot = -1;
+  for (int t = 0; t < A.W; ++t) {
+    const int64_t s = (blk * A.W + t) * A.R + lane;
+    const uint8_t meta = A.meta[s];
+    const int kind = meta & 7;
+    if (kind == SK_PAD) continue;
+    const double d = A.dL[s];
+    if (kind == SK_GHOST) {
+      double c[D], nc2 = 0.0;
+      for (int e = 0; e < D; ++e) { c[e] = A.c[e * A.nslots + s]; nc2 += c[e] * c[e]; }
+      const double nc = sqrt(nc2);
+      double Ug[M];
+      for (int q = 0; q < M; ++q) Ug[q] = Ui[q];
+      if ((meta >> 3) == 2) {
+        double mn = 0.0;
+        for (int e = 0; e < D; ++e) mn += Ui[1 + e] * (c[e] / nc);
+        for (int e = 0; e < D; ++e) Ug[1 + e] = Ui[1 + e] - 2.0 * mn * (c[e] / nc);
+      }
+      const double dH = fmax(hpk * d, d * fmin(A.c_ev * fabs(Ni), 1.0));
+      for (int q = 0; q < M; ++q) Ab[q] += tau * (dH - d) * (Ug[q] - Ui[q]);
+      if (gslot < 0) gslot = s;
+      continue;
+    }
+    const int64_t j = A.col[s];
+    if (j == i) continue;  // A_ii = 0
+    const double dH = visc_high(A, d, Ni, A.Nev[j], kind, hpk);
+    const double mij = kind == SK_CELL ? A.ref->mblk[a * NLOC + (meta >> 3)] : 0.0;
+    double Aij[M];
+    for (int q = 0; q < M; ++q)
+      Aij[q] = tau * (dH - d) * (U[q * N + j] - Ui[q]) - mij * (A.dUH[q * N + j] - dUi[q]);
+    if (pass == 1) {
+      const double rest = 1.0 - A.l1[s];
+      for (int q = 0; q < M; ++q) Aij[q] = rest * Aij[q];
+    }
+    double P[M], Lj[M];
+    for (int q = 0; q < M; ++q) P[q] = Aij[q] / (kap_i * mi);
+    const double li = line_search<D>(g, Li, P, bi_rmin, bi_rmax, bi_smin);
+    const double kap_j = 1.0 / (double)(A.rowlen[j] + 1);
+    const double mj = A.ref->mlump[j % NLOC];
+    for (int q = 0; q < M; ++q) {
+      Lj[q] = base[q * N + j];
+      P[q] = -Aij[q] / (kap_j * mj);
+    }
+    const double lj = line_search<D>(g, Lj, P, A.B[j], A.B[N + j], A.B[2 * N + j]);
+    const double l = fmin(li, lj);
+    for (int q = 0; q < M; ++q) acc[q] += l * Aij[q];
+    if (pass == 0) A.l1[s] = l;
+  }
+  if (gslot >= 0) {
+    if (pass == 1) {
+      const double rest = 1.0 - A.l1[gslot];
+      for (int q = 0; q < M; ++q) Ab[q] = rest * Ab[q];
+    }
+    double P[M];
+    for (int q = 0; q < M; ++q) P[q] = Ab[q] / (kap_i * mi);
+    const double lb = line_search<D>(g, Li, P, bi_rmin, bi_rmax, bi_smin);
+    for (int q = 0; q < M; ++q) acc[q] += lb * Ab[q];
+    if (pass == 0) A.l1[gslot] = lb;
+  }
+  double V[M];
+  for (int q = 0; q < M; ++q) V[q] = Li[q] + acc[q] / mi;
+  if (pass == 0)
+    for (int q = 0; q < M; ++q) A.U1[q * N + i] = V[q];
+  if (final_pass) {
+    for (int q = 0; q < M; ++q)
+      sb.out[q * N + i] = sb.ca == 0.0 ? V[q] : sb.ca * sb.Un[q * N + i] + sb.cb * V[q];
+    if (!(V[0] > 0.0) || !(eps_of<D>(V) > 0.0)) atomicOr(&A.ctl->bad_flag, 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+static inline hipStream_t S(void *s) { return (hipStream_t)s; }
+
+template <int D, int DEG>
+static int stage_impl(const KArgs &A, const StageBufs &b, int stage, void *stream) {
+  const dim3 grid((unsigned)A.nblocks), blk(kBlockThreads);
+  const unsigned gp = (unsigned)((A.N + kBlockThreads - 1) / kBlockThreads);
+  hipLaunchKernelGGL(k_prim<D>, dim3(gp), blk, 0, S(stream), A, b.in);
+  hipLaunchKernelGGL((k_sweep1<D, DEG>), grid, blk, 0, S(stream), A, b.in, stage);
+  hipLaunchKernelGGL((k_sweep2<D, DEG>), grid, blk, 0, S(stream), A, b, stage);
+  if (A.scheme == 2 && A.passes >= 1)
+    hipLaunchKernelGGL((k_limit<D, DEG>), grid, blk, 0, S(stream), A, b, 0, A.passes == 1 ? 1 : 0);
+  if (A.scheme == 2 && A.passes >= 2)
+    hipLaunchKernelGGL((k_limit<D, DEG>), grid, blk, 0, S(stream), A, b, 1, 1);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int D, int DEG>
+static int fill_impl(const KArgs &A, void *stream) {
+  hipLaunchKernelGGL((k_fill<D, DEG>), dim3((unsigned)A.nblocks), dim3(kBlockThreads), 0, S(stream), A);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+#define GDG_DISPATCH(FN, ...)                                   \
+  switch (A.dim * 10 + A.deg) {                                 \
+    case 11: return FN<1, 1>(__VA_ARGS__);                      \
+    case 12: return FN<1, 2>(__VA_ARGS__);                      \
+    case 21: return FN<2, 1>(__VA_ARGS__);                      \
+    case 22: return FN<2, 2>(__VA_ARGS__);                      \
+    case 31: return FN<3, 1>(__VA_ARGS__);                      \
+    case 32: return FN<3, 2>(__VA_ARGS__);                      \
+    default: return -2;                                         \
+  }
+
+int launch_stage(const KArgs &A, const StageBufs &b, int stage, void *stream) {
+  GDG_DISPATCH(stage_impl, A, b, stage, stream)
+}
+
+int launch_fill(const KArgs &A, void *stream) { GDG_DISPATCH(fill_impl, A, stream) }
+
+int launch_begin(const KArgs &A, double dt_cap, double tau_fixed, void *stream) {
+  hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, S(stream), A.ctl, dt_cap, tau_fixed);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_end(const KArgs &A, void *stream) {
+  hipLaunchKernelGGL(k_end, dim3(1), dim3(64), 0, S(stream), A.ctl);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_prim(const KArgs &A, const double *U, void *stream) {
+  const unsigned gp = (unsigned)((A.N + kBlockThreads - 1) / kBlockThreads);
+  switch (A.dim) {
+    case 1: hipLaunchKernelGGL(k_prim<1>, dim3(gp), dim3(kBlockThreads), 0, S(stream), A, U); break;
+    case 2: hipLaunchKernelGGL(k_prim<2>, dim3(gp), dim3(kBlockThreads), 0, S(stream), A, U); break;
+    case 3: hipLaunchKernelGGL(k_prim<3>, dim3(gp), dim3(kBlockThreads), 0, S(stream), A, U); break;
+    default: return -2;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace gdg

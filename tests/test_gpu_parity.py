@@ -1,0 +1,215 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle on the
+same seeded inputs, element by element.
+
+Tolerance (FP64 path): |gpu - oracle| <= 1e-11 * scale_c per dof, scale_c the
+largest |oracle| value of component c (the overall largest if that component
+is identically zero).  Both sides compute in double precision with different
+summation orders, FMA contraction and libm/ocml transcendentals, so results
+agree to a few ulps per operation; 1e-11 leaves room for the ~10^3 operations
+in a dof's dependency cone.  Line searches end on brackets of width 1e-14.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2402_04514_amd import gdg
+from paper_2402_04514_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+def _say(msg):
+    print("[gpu-parity] " + msg, flush=True)
+
+
+def quadrant_on(dim, k, cells, bc, seed=240204514):
+    ms = W.MeshSpec(dim, k, tuple(cells), (0.0,) * dim, (1.0,) * dim, bc)
+    _, xc = W.node_coords(ms)
+    q = np.zeros(ms.ndofs, dtype=int)
+    for e in range(min(dim, 2)):
+        q += (xc[:, e] >= 0.5).astype(int) << e
+    if dim == 3:
+        q = (q + (xc[:, 2] >= 0.5).astype(int)) % 4
+    st = np.array(W.quadrant_states(seed))
+    vel = np.zeros((dim, ms.ndofs))
+    vel[0] = st[q, 1]
+    if dim > 1:
+        vel[1] = st[q, 2]
+    return ms, W.to_conserved(st[q, 0], vel, st[q, 3])
+
+
+CASES = {
+    "sod_q1_40": lambda: (W.sod(40).mesh, W.sod(40).U0),
+    "q1_1d_slip": lambda: quadrant_on(1, 1, (33,), (2, 2)),
+    "q2_1d_periodic": lambda: quadrant_on(1, 2, (17,), (0, 0)),
+    "q1_2d_outflow_ragged": lambda: quadrant_on(2, 1, (11, 9), (1,) * 4),
+    "q1_2d_periodic": lambda: quadrant_on(2, 1, (12, 12), (0,) * 4),
+    "q1_2d_mixed": lambda: quadrant_on(2, 1, (10, 14), (2, 2, 0, 0), seed=5),
+    "q2_2d_outflow": lambda: quadrant_on(2, 2, (9, 8), (1,) * 4),
+    "q2_2d_slip": lambda: quadrant_on(2, 2, (7, 7), (2,) * 4, seed=9),
+    "q1_3d_slip": lambda: quadrant_on(3, 1, (5, 4, 6), (2,) * 6),
+    "q1_3d_mixed": lambda: quadrant_on(3, 1, (4, 4, 4), (0, 0, 1, 1, 2, 2), seed=3),
+    "vortex_q1_32": lambda: (W.vortex(32).mesh, W.vortex(32).U0),
+}
+
+
+def _close(a, b, tol=TOL, what=""):
+    a = np.asarray(a).reshape(b.shape)
+    scale = np.abs(b).max(axis=-1, keepdims=True) if b.ndim > 1 else np.abs(b).max()
+    scale = np.where(scale > 0, scale, max(np.abs(b).max(), 1e-300))
+    err = np.abs(a - b) / scale
+    worst = float(err.max())
+    assert worst <= tol, "%s: worst relative error %.3e (tol %.1e) at %s" % (
+        what, worst, tol, np.unravel_index(np.argmax(err), err.shape))
+    return worst
+
+
+def _pair(oracle, name, params=None):
+    ms, U = CASES[name]()
+    M = oracle.Mesh(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc)
+    p = gdg.gdg_default_params(ms.degree) if params is None else params
+    S = gdg.Solver.from_spec(ms, p)
+    S.upload(U)
+    op = oracle.params(gamma=p.gamma, cfl=p.cfl, c_ev=p.c_ev, c_k=p.c_k, c_r=p.c_r, p_r=p.p_r,
+                       passes=p.limiter_passes, scheme=p.scheme, degree=ms.degree)
+    return ms, U, M, S, op
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_stage_fields(oracle, name):
+    """One forward-Euler stage: tau, U^L, bounds, dU^H, U^(1) and Phi(U)."""
+    _say("stage fields " + name)
+    ms, U, M, S, op = _pair(oracle, name)
+    out, dg = M.stage(op, U, diag=True)
+    tau_o = op.cfl * dg["tau_max"]
+    tau_g = S.stage(0.0)
+    assert tau_g == pytest.approx(tau_o, rel=1e-13)
+    _close(S.field(gdg.GDG_FIELD_UL), dg["UL"], what="U^L")
+    B = S.field(gdg.GDG_FIELD_BOUNDS)
+    _close(B, np.stack([dg["rho_min"], dg["rho_max"], dg["s_min"]]), what="bounds")
+    _close(S.field(gdg.GDG_FIELD_DUH), dg["dUH"], what="dU^H")
+    _close(S.field(gdg.GDG_FIELD_U1), dg["U1"], what="U^(1)")
+    _close(S.download(), out, what="Phi(U)")
+    Ng = S.field(gdg.GDG_FIELD_EV_N)[0]
+    assert np.all(np.abs(Ng) <= 1 + 1e-14)
+    assert np.max(np.abs(Ng - dg["N"])) < 1e-7, np.max(np.abs(Ng - dg["N"]))
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_ssprk3_step(oracle, name):
+    """One SSP-RK3 step with the CFL time step: same tau, state to 1e-11."""
+    _say("ssp step " + name)
+    ms, U, M, S, op = _pair(oracle, name)
+    Uo, dt_o, nres, st = M.step(op, U)
+    assert st == 0
+    dt_g = S.step()
+    assert dt_g == pytest.approx(dt_o, rel=1e-13)
+    _close(S.download(), Uo, what="U^{n+1}")
+
+
+@pytest.mark.parametrize("scheme", [gdg.GDG_LOW_ORDER, gdg.GDG_HIGH_ORDER])
+@pytest.mark.parametrize("name", ["q1_2d_mixed", "q2_2d_outflow", "q1_3d_slip"])
+def test_scheme_modes(oracle, name, scheme):
+    _say("scheme %d %s" % (scheme, name))
+    ms, _, _, _, _ = _pair(oracle, name)
+    p = gdg.gdg_default_params(ms.degree)
+    p.scheme = scheme
+    ms, U, M, S, op = _pair(oracle, name, p)
+    Uo, dt_o, _, st = M.step(op, U)
+    dt_g = S.step()
+    assert dt_g == pytest.approx(dt_o, rel=1e-13)
+    _close(S.download(), Uo, what="U^{n+1}")
+
+
+@pytest.mark.parametrize("passes", [0, 1])
+def test_limiter_passes(oracle, passes):
+    p = gdg.gdg_default_params(1)
+    p.limiter_passes = passes
+    ms, U, M, S, op = _pair(oracle, "q1_2d_outflow_ragged", p)
+    Uo, dt_o, _, _ = M.step(op, U)
+    S.step()
+    _close(S.download(), Uo, what="U^{n+1}")
+
+
+def test_several_steps_and_time(oracle):
+    """Ten steps with a cap on the final time: same states and same t."""
+    ms, U, M, S, op = _pair(oracle, "q2_2d_slip")
+    Uo, t_o, n_o = M.run_to(op, U, 0.01, max_steps=10)
+    st = S.run_to(0.01, max_steps=10)
+    assert st.steps == n_o and st.t == pytest.approx(t_o, rel=1e-12)
+    _close(S.download(), Uo, tol=1e-10, what="U after 10 steps")
+
+
+def test_fixed_dt_and_cfl_restart(oracle):
+    """A fixed tau above the CFL bound: stage 2 or 3 detects the violation and
+    the step restarts with Cr times that stage's bound, as in the oracle."""
+    ms, U, M, S, op = _pair(oracle, "sod_q1_40")
+    tm = M.tau_rows(op, U).min()
+    Uo, dt_o, nres, st = M.step(op, U, dt_fixed=1.9 * tm)
+    dt_g = S.step(dt_fixed=1.9 * tm)
+    assert dt_g == pytest.approx(dt_o, rel=1e-12)
+    assert S.stats().restarts == nres
+    _close(S.download(), Uo, what="U^{n+1}")
+    # a tau under the bound is taken as given
+    ms, U, M, S, op = _pair(oracle, "sod_q1_40")
+    Uo, dt_o, nres, st = M.step(op, U, dt_fixed=0.3 * tm)
+    assert S.step(dt_fixed=0.3 * tm) == 0.3 * tm and nres == 0
+    _close(S.download(), Uo, what="U^{n+1}")
+
+
+def test_constant_state_exact():
+    """A uniform state is a fixed point in every sweep (difference form)."""
+    ms = W.MeshSpec(2, 2, (6, 5), (0, 0), (1, 1), (1, 1, 2, 2))
+    U = W.to_conserved(np.full(ms.ndofs, 1.2), np.stack([np.full(ms.ndofs, 0.3), np.zeros(ms.ndofs)]),
+                       np.full(ms.ndofs, 0.8))
+    ms_slip = W.MeshSpec(2, 2, (6, 5), (0, 0), (1, 1), (2,) * 4)
+    Ur = W.to_conserved(np.full(ms.ndofs, 1.2), np.zeros((2, ms.ndofs)), np.full(ms.ndofs, 0.8))
+    for spec, V in ((ms, U), (ms_slip, Ur)):
+        S = gdg.Solver.from_spec(spec)
+        S.upload(V)
+        for _ in range(3):
+            S.step()
+        out = S.download()
+        # every flux difference and state difference is exactly zero; only the
+        # SSP combination (3/4 U + 1/4 U, 1/3 U + 2/3 U) rounds
+        assert np.max(np.abs(out - V)) <= 1e-15 * np.abs(V).max()
+
+
+def test_inadmissible_upload_rejected():
+    ms = W.MeshSpec(1, 1, (8,), (0,), (1,), (1, 1))
+    U = W.to_conserved(np.ones(16), np.zeros((1, 16)), np.ones(16))
+    U[2, 5] = -1.0  # negative total energy: eps < 0
+    S = gdg.Solver.from_spec(ms)
+    with pytest.raises(gdg.GdgError) as ei:
+        S.upload(U)
+    assert ei.value.status == gdg.GDG_E_INADMISSIBLE
+    U[2, 5] = 2.5
+    U[0, 3] = float("nan")
+    with pytest.raises(gdg.GdgError):
+        S.upload(U)
+
+
+def test_invariants_quadrant_q2(oracle):
+    """On the GPU output: rho > 0, eps > 0, conservation on a periodic mesh,
+    and the limited state within the relaxed bounds of the stage."""
+    ms, U = quadrant_on(2, 2, (10, 10), (0,) * 4, seed=17)
+    S = gdg.Solver.from_spec(ms)
+    S.upload(U)
+    mi = oracle.Mesh(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc).lumped()
+    tot0 = (U * mi).sum(1)
+    for _ in range(5):
+        S.step()
+    out = S.download()
+    eps = out[3] - 0.5 * (out[1] ** 2 + out[2] ** 2) / out[0]
+    assert np.all(out[0] > 0) and np.all(eps > 0)
+    tot1 = (out * mi).sum(1)
+    assert np.all(np.abs(tot1 - tot0) <= 1e-13 * (np.abs(U) * mi).sum(1))
+    S.stage(0.0)
+    B = S.field(gdg.GDG_FIELD_BOUNDS)
+    V = S.download()
+    st = (V[3] - 0.5 * (V[1] ** 2 + V[2] ** 2) / V[0]) * V[0] ** -1.4
+    assert np.all(V[0] >= B[0] * (1 - 1e-12)) and np.all(V[0] <= B[1] * (1 + 1e-12))
+    assert np.all(st >= B[2] * (1 - 1e-11))

@@ -1,0 +1,89 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point that
+include/gdg.h declares, and its host-only calls (defaults, workspace sizing,
+validation) behave as documented.  No GPU work is issued here."""
+import os
+import re
+
+import pytest
+
+from paper_2402_04514_amd import gdg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "gdg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gdg_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = gdg.load()
+    names = declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_default_params_are_the_papers():
+    p = gdg.gdg_default_params(1)
+    assert (p.gamma, p.cfl, p.c_ev, p.c_k, p.c_r, p.p_r) == (1.4, 0.5, 1.0, 1.0, 4.0, 1.5)
+    assert (p.limiter_passes, p.scheme, p.precision) == (2, gdg.GDG_LIMITED, gdg.GDG_FP64)
+    assert gdg.gdg_default_params(2).c_ev == 0.5
+    with pytest.raises(gdg.GdgError):
+        gdg.gdg_default_params(7)
+
+
+def test_workspace_bytes_scale_with_mesh():
+    p = gdg.gdg_default_params(1)
+    small = gdg.gdg_workspace_bytes(gdg.mesh_desc(2, 1, (8, 8), (0, 0), (1, 1), (1,) * 4), p)
+    big = gdg.gdg_workspace_bytes(gdg.mesh_desc(2, 1, (64, 64), (0, 0), (1, 1), (1,) * 4), p)
+    assert 40 * small < big < 80 * small
+    # 2D Q1: per dof at least the state buffers, the ELL stencil and the slot fields
+    n = 64 * 64 * 4
+    assert big > n * (3 * 4 * 8 + 8 * (4 + 16 + 1 + 16))
+
+
+@pytest.mark.parametrize("desc", [
+    (4, 1, (8,), (0,), (1,), (1, 1)),           # dim out of range
+    (2, 3, (8, 8), (0, 0), (1, 1), (1,) * 4),   # degree out of range
+    (2, 1, (1, 8), (0, 0), (1, 1), (0, 0, 1, 1)),  # periodic axis with one cell
+    (2, 1, (8, 8), (0, 0), (1, 1), (0, 1, 1, 1)),  # half-periodic axis
+    (2, 1, (8, 8), (0, 0), (0, 1), (1,) * 4),   # empty box
+    (2, 1, (0, 8), (0, 0), (1, 1), (1,) * 4),   # no cells
+    (2, 1, (8, 8), (0, 0), (1, 1), (1, 1, 1, 7)),  # unknown boundary kind
+])
+def test_invalid_mesh_rejected(desc):
+    dim = desc[0]
+    m = gdg.gdg_mesh_desc()
+    m.dim, m.degree = dim, desc[1]
+    for e in range(len(desc[2])):
+        m.cells[e], m.lo[e], m.hi[e] = desc[2][e], desc[3][e], desc[4][e]
+    for f in range(len(desc[5])):
+        m.bc[f] = desc[5][f]
+    with pytest.raises(gdg.GdgError) as ei:
+        gdg.gdg_workspace_bytes(m, gdg.gdg_default_params(1))
+    assert ei.value.status == gdg.GDG_E_INVALID
+
+
+@pytest.mark.parametrize("field,value", [("gamma", 2.0), ("gamma", 1.0), ("cfl", 0.0), ("cfl", 1.5),
+                                         ("limiter_passes", 3), ("scheme", 5), ("precision", 9)])
+def test_invalid_params_rejected(field, value):
+    p = gdg.gdg_default_params(1)
+    setattr(p, field, value)
+    with pytest.raises(gdg.GdgError):
+        gdg.gdg_workspace_bytes(gdg.mesh_desc(2, 1, (8, 8), (0, 0), (1, 1), (1,) * 4), p)
+
+
+def test_too_many_dofs_rejected():
+    with pytest.raises(gdg.GdgError):
+        gdg.gdg_workspace_bytes(gdg.mesh_desc(3, 2, (1000, 1000, 1000), (0,) * 3, (1,) * 3, (1,) * 6),
+                                gdg.gdg_default_params(2))
+
+
+def test_create_rejects_small_or_null_workspace():
+    m = gdg.mesh_desc(2, 1, (8, 8), (0, 0), (1, 1), (1,) * 4)
+    p = gdg.gdg_default_params(1)
+    with pytest.raises(gdg.GdgError) as ei:
+        gdg.gdg_create(m, p, 0, 0, 0)
+    assert ei.value.status == gdg.GDG_E_NOMEM
