@@ -161,7 +161,24 @@ gdg_status gdg_read_field(gdg_ctx *ctx, int32_t field, double *dst, int32_t is_d
 /* Simulated time, step and restart counters. */
 gdg_status gdg_get_stats(const gdg_ctx *ctx, gdg_stats *stats);
 
-/* Text of the last error on this context ("" if none). */
+/* Kernel timing.  gdg_profile(ctx, 1) starts bracketing every sweep launch
+ * with HIP events on the context's stream (and clears the sums); 0 stops.
+ * gdg_profile_read() returns, per kernel, the summed device time in ms and
+ * the number of launches since the last gdg_profile() call, in the order
+ * GDG_KERNEL_*. */
+typedef enum {
+  GDG_KERNEL_PRIM = 0,   /* per-node primitives */
+  GDG_KERNEL_SWEEP1 = 1, /* d^L, CFL bound, entropy-viscosity ratio, ring-1 bounds */
+  GDG_KERNEL_SWEEP2 = 2, /* U^L, bounds, d^H, high-order residual, cell solve */
+  GDG_KERNEL_LIMIT1 = 3, /* limiter pass 1 */
+  GDG_KERNEL_LIMIT2 = 4, /* limiter pass 2 and the SSP combination */
+  GDG_KERNEL_COUNT = 5
+} gdg_kernel;
+gdg_status gdg_profile(gdg_ctx *ctx, int32_t enable);
+gdg_status gdg_profile_read(const gdg_ctx *ctx, double *ms_total, int64_t *launches);
+
+/* Text of the last error on this context ("" if none); with ctx == NULL, the
+ * reason of the last failed gdg_create() on the calling thread. */
 const char *gdg_last_error(const gdg_ctx *ctx);
 
 #ifdef __cplusplus

@@ -51,7 +51,7 @@ _DP = C.POINTER(C.c_double)
 class _Diag(C.Structure):
     _fields_ = [("tau_max", C.c_double), ("N", _DP), ("rho_min", _DP), ("rho_max", _DP),
                 ("s_min", _DP), ("UL", _DP), ("dUH", _DP), ("U1", _DP), ("dij", _DP),
-                ("lij", _DP), ("lbd", _DP), ("Aij", _DP), ("Abd", _DP)]
+                ("lij", _DP), ("lbd", _DP), ("Aij", _DP), ("Abd", _DP), ("Ncond", _DP)]
 
 
 _lib = None
@@ -67,6 +67,8 @@ def lib():
         L.or_create.restype = C.c_void_p
         L.or_create.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_long), _DP, _DP, C.POINTER(C.c_int)]
         L.or_destroy.argtypes = [C.c_void_p]
+        L.or_num_threads.restype = C.c_int
+        L.or_num_threads.argtypes = []
         for fn in ("or_num_dofs", "or_nnz", "or_nbnd"):
             getattr(L, fn).restype = C.c_long
             getattr(L, fn).argtypes = [C.c_void_p]
@@ -187,7 +189,7 @@ class Mesh:
             N, nnz, m = self.ndofs, lib().or_nnz(self._h), self.m
             shapes = {"N": (N,), "rho_min": (N,), "rho_max": (N,), "s_min": (N,),
                       "UL": (m, N), "dUH": (m, N), "U1": (m, N), "dij": (nnz,),
-                      "lij": (nnz,), "lbd": (N,), "Aij": (nnz, m), "Abd": (N, m)}
+                      "lij": (nnz,), "lbd": (N,), "Aij": (nnz, m), "Abd": (N, m), "Ncond": (N,)}
             for k, shp in shapes.items():
                 arrs[k] = np.zeros(shp)
                 setattr(d, k, _dp(arrs[k]))
@@ -222,6 +224,11 @@ class Mesh:
             t = t_final if dt == cap else t + dt
             n += 1
         return U, t, n
+
+
+def num_threads() -> int:
+    """Threads the oracle's row loops run on."""
+    return lib().or_num_threads()
 
 
 # -- physics helpers -------------------------------------------------------

@@ -23,6 +23,7 @@
  * identities, limits l=0 / l=1, exact solutions).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -358,6 +359,9 @@ or_setup *or_create(int dim, int deg, const long *cells, const double *lo, const
   return S;
 }
 
+/* threads the row loops use (OpenMP) */
+int or_num_threads(void) { return omp_get_max_threads(); }
+
 long or_num_dofs(const or_setup *S) { return S->ndofs; }
 long or_nnz(const or_setup *S) { return S->rowptr[S->ndofs]; }
 long or_nbnd(const or_setup *S) { return S->bptr[S->ndofs]; }
@@ -584,6 +588,7 @@ typedef struct {
   double *lbd;      /* l_i^d of pass 1 per row */
   double *Aij;      /* A_ij per CSR entry, m per entry */
   double *Abd;      /* A_i^d per row, m per row */
+  double *Ncond;    /* sum of |terms| of R_i and D_i over D_i: N_i's sensitivity to rounding */
 } or_diag;
 
 static void get_state(const or_setup *S, const double *U, long i, double *out) {
@@ -725,6 +730,7 @@ int or_stage(const or_setup *S, const or_params *P, const double *U, double tau,
   double *Brmin = dalloc(N), *Brmax = dalloc(N), *Bsmin = dalloc(N);
   double *l1 = dalloc(nnz), *lb1 = dalloc(N), *U1 = dalloc(m * N);
   double *Ug = dalloc((S->bptr[N] + 1) * m);
+  double *Ncd = (dg && dg->Ncond) ? dg->Ncond : NULL;
   int status = 0;
 
   /* Sec. 4.1: boundary data per boundary part */
@@ -859,6 +865,31 @@ int or_stage(const or_setup *S, const or_params *P, const double *U, double tau,
     double R = T, D = fabs(T);
     for (int q = 0; q < m; ++q) { R -= grad[q] * Sk[q]; D += fabs(grad[q]) * fabs(Sk[q]); }
     Nr[i] = D > 0.0 ? R / D : 0.0;
+    if (Ncd) {
+      /* magnitude of the summed terms (before cancellation) over D_i */
+      double mag = 0.0, Sabs[OR_MAXM] = {0};
+      for (long k = S->rowptr[i]; k < S->rowptr[i + 1]; ++k) {
+        get_state(S, U, S->col[k], Uj);
+        const double *c = S->c + k * dim;
+        double fsj = exp(spec_entropy(g, dim, Uj) / (g + 1.0)), mc = 0.0;
+        for (int e = 0; e < dim; ++e) mc += Uj[1 + e] * c[e];
+        mag += fabs(mc) * (fabs(fsj) + fabs(fsi));
+        flux_dot(g, dim, Uj, c, fc);
+        flux_dot(g, dim, Ui, c, fi);
+        for (int q = 0; q < m; ++q) Sabs[q] += fabs(fc[q]) + fabs(fi[q]);
+      }
+      for (long b = S->bptr[i]; b < S->bptr[i + 1]; ++b) {
+        const double *Ub = Ug + b * m, *c = S->bc_c + b * dim;
+        double fsb = exp(spec_entropy(g, dim, Ub) / (g + 1.0)), mc = 0.0;
+        for (int e = 0; e < dim; ++e) mc += Ub[1 + e] * c[e];
+        mag += fabs(mc) * (fabs(fsb) + fabs(fsi));
+        flux_dot(g, dim, Ub, c, fc);
+        flux_dot(g, dim, Ui, c, fi);
+        for (int q = 0; q < m; ++q) Sabs[q] += fabs(fc[q]) + fabs(fi[q]);
+      }
+      for (int q = 0; q < m; ++q) mag += fabs(grad[q]) * Sabs[q];
+      Ncd[i] = D > 0.0 ? mag / D : (mag > 0.0 ? INFINITY : 0.0);
+    }
   }
 
   /* eq. HighOrderViscosity with eq. ViscMin (reading R12: collocation is

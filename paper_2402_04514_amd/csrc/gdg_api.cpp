@@ -26,9 +26,17 @@ struct gdg_ctx {
   int64_t steps, restarts;
   double last_dt;
   int M;
+  // kernel timing (gdg_profile)
+  bool prof_on;
+  Prof prof;
+  double prof_ms[KID_COUNT];
+  int64_t prof_launches[KID_COUNT];
 };
 
 namespace {
+
+// message of the last failed gdg_create on this thread (no context exists)
+thread_local std::string g_create_err;
 
 struct Layout {
   int nloc, nb1, R, cpb, W, M;
@@ -136,6 +144,21 @@ gdg_status read_ctl(gdg_ctx *ctx) {
   return GDG_OK;
 }
 
+// Folds the bracketed launches of the synchronized stream into the sums.
+gdg_status harvest(gdg_ctx *ctx) {
+  if (!ctx->prof_on) return GDG_OK;
+  for (int k = 0; k < ctx->prof.n; ++k) {
+    float ms = 0.0f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, (hipEvent_t)ctx->prof.ev[2 * k], (hipEvent_t)ctx->prof.ev[2 * k + 1]));
+    ctx->prof_ms[ctx->prof.kid[k]] += ms;
+    ctx->prof_launches[ctx->prof.kid[k]] += 1;
+  }
+  ctx->prof.n = 0;
+  return GDG_OK;
+}
+
+Prof *prof_of(gdg_ctx *ctx) { return ctx->prof_on ? &ctx->prof : nullptr; }
+
 double bits_to_double(unsigned long long b) {
   double d;
   std::memcpy(&d, &b, sizeof d);
@@ -170,13 +193,20 @@ gdg_status gdg_workspace_bytes(const gdg_mesh_desc *mesh, const gdg_params *prm,
 
 gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *dev_workspace,
                       size_t ws_bytes, void *hip_stream, gdg_ctx **out) {
-  if (!out) return GDG_E_INVALID;
+  g_create_err.clear();
+  if (!out) { g_create_err = "null output pointer"; return GDG_E_INVALID; }
   *out = nullptr;
   std::string err;
-  if (!validate(mesh, prm, &err)) return GDG_E_INVALID;
+  if (!validate(mesh, prm, &err)) { g_create_err = err; return GDG_E_INVALID; }
   Layout L = layout(mesh);
-  if (!dev_workspace || ws_bytes < L.total) return GDG_E_NOMEM;
-  if (((uintptr_t)dev_workspace & 255) != 0) return GDG_E_INVALID;
+  if (!dev_workspace || ws_bytes < L.total) {
+    g_create_err = "workspace smaller than gdg_workspace_bytes()";
+    return GDG_E_NOMEM;
+  }
+  if (((uintptr_t)dev_workspace & 255) != 0) {
+    g_create_err = "workspace not 256-byte aligned";
+    return GDG_E_INVALID;
+  }
   gdg_ctx *ctx = new gdg_ctx();
   ctx->mesh = *mesh;
   ctx->prm = *prm;
@@ -238,6 +268,7 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
 
   RefTables *T = new RefTables();
   if (!build_ref_tables(mesh->dim, mesh->degree, h, T, &err)) {
+    g_create_err = err;
     delete T;
     delete ctx;
     return GDG_E_INVALID;
@@ -247,18 +278,24 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
     T->hpk[a] = prm->c_k * std::pow(hh, A.pk);
     T->relax[a] = prm->c_r * std::pow(hh, prm->p_r);
     if (!(T->relax[a] < 1.0)) {
+      g_create_err = "relaxation c_r h^p_r >= 1: the lower bounds would not be positive";
       delete T;
       delete ctx;
-      return GDG_E_INVALID;  // r^- = 1 - c_r h^p_r must stay positive
+      return GDG_E_INVALID;
     }
   }
   std::memset(&ctx->hctl, 0, sizeof(Ctl));
   hipError_t e1 = hipMemcpyAsync(ctx->dref, T, sizeof(RefTables), hipMemcpyHostToDevice, ctx->stream);
   hipError_t e2 = hipMemcpyAsync(A.ctl, &ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream);
   int rc = (e1 == hipSuccess && e2 == hipSuccess) ? launch_fill(A, ctx->stream) : -1;
+  hipError_t e4 = rc == 0 ? hipSuccess : hipGetLastError();
   hipError_t e3 = hipStreamSynchronize(ctx->stream);
   delete T;
   if (rc != 0 || e3 != hipSuccess) {
+    hipError_t e = e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : (e4 != hipSuccess ? e4 : e3));
+    g_create_err = std::string(e1 != hipSuccess || e2 != hipSuccess ? "copy of the setup tables"
+                                                                     : (rc ? "stencil fill launch" : "stream sync")) +
+                   " failed: " + hipGetErrorString(e);
     delete ctx;
     return GDG_E_DEVICE;
   }
@@ -269,6 +306,8 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
 void gdg_destroy(gdg_ctx *ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->prof_on)
+    for (int k = 0; k < 64; ++k) (void)hipEventDestroy((hipEvent_t)ctx->prof.ev[k]);
   delete ctx;
 }
 
@@ -333,11 +372,12 @@ gdg_status gdg_step(gdg_ctx *ctx, double dt_cap, double dt_fixed, double *dt_tak
     StageBufs b1 = {ctx->U[c0], ctx->U[c1], ctx->U[c0], 0.0, 1.0};
     StageBufs b2 = {ctx->U[c1], ctx->U[c2], ctx->U[c0], 0.75, 0.25};
     StageBufs b3 = {ctx->U[c2], ctx->U[c0], ctx->U[c0], 1.0 / 3.0, 2.0 / 3.0};
-    if (gdg_status s = launched(ctx, launch_stage(A, b1, 0, ctx->stream), "stage 1")) return s;
-    if (gdg_status s = launched(ctx, launch_stage(A, b2, 1, ctx->stream), "stage 2")) return s;
-    if (gdg_status s = launched(ctx, launch_stage(A, b3, 2, ctx->stream), "stage 3")) return s;
+    if (gdg_status s = launched(ctx, launch_stage(A, b1, 0, ctx->stream, prof_of(ctx)), "stage 1")) return s;
+    if (gdg_status s = launched(ctx, launch_stage(A, b2, 1, ctx->stream, prof_of(ctx)), "stage 2")) return s;
+    if (gdg_status s = launched(ctx, launch_stage(A, b3, 2, ctx->stream, prof_of(ctx)), "stage 3")) return s;
     if (gdg_status s = launched(ctx, launch_end(A, ctx->stream), "end")) return s;
     if (gdg_status s = read_ctl(ctx)) return s;
+    if (gdg_status s = harvest(ctx)) return s;
     const Ctl &h = ctx->hctl;
     if (h.cfl_flag) {
       const int vs = h.viol_stage < 1 ? 1 : h.viol_stage;
@@ -378,8 +418,9 @@ gdg_status gdg_stage(gdg_ctx *ctx, double tau, double *tau_used) {
   const int c0 = ctx->cur, c1 = (c0 + 1) % 3;
   if (gdg_status s = launched(ctx, launch_begin(ctx->A, 0.0, tau > 0.0 ? tau : 0.0, ctx->stream), "begin")) return s;
   StageBufs b = {ctx->U[c0], ctx->U[c1], ctx->U[c0], 0.0, 1.0};
-  if (gdg_status s = launched(ctx, launch_stage(ctx->A, b, 0, ctx->stream), "stage")) return s;
+  if (gdg_status s = launched(ctx, launch_stage(ctx->A, b, 0, ctx->stream, prof_of(ctx)), "stage")) return s;
   if (gdg_status s = read_ctl(ctx)) return s;
+  if (gdg_status s = harvest(ctx)) return s;
   if (ctx->hctl.bad_flag) {
     ctx->err = "the stage output left the admissible set";
     return GDG_E_INADMISSIBLE;
@@ -420,6 +461,37 @@ gdg_status gdg_get_stats(const gdg_ctx *ctx, gdg_stats *stats) {
   return GDG_OK;
 }
 
-const char *gdg_last_error(const gdg_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+gdg_status gdg_profile(gdg_ctx *ctx, int32_t enable) {
+  if (!ctx) return GDG_E_INVALID;
+  if (enable && !ctx->prof_on) {
+    for (int k = 0; k < 64; ++k) {
+      hipEvent_t e;
+      HIPCHK(ctx, hipEventCreate(&e));
+      ctx->prof.ev[k] = (void *)e;
+    }
+    ctx->prof.n = 0;
+    ctx->prof_on = true;
+  } else if (!enable && ctx->prof_on) {
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < 64; ++k) (void)hipEventDestroy((hipEvent_t)ctx->prof.ev[k]);
+    ctx->prof_on = false;
+  }
+  for (int k = 0; k < KID_COUNT; ++k) {
+    ctx->prof_ms[k] = 0.0;
+    ctx->prof_launches[k] = 0;
+  }
+  return GDG_OK;
+}
+
+gdg_status gdg_profile_read(const gdg_ctx *ctx, double *ms_total, int64_t *launches) {
+  if (!ctx || !ms_total || !launches) return GDG_E_INVALID;
+  for (int k = 0; k < KID_COUNT; ++k) {
+    ms_total[k] = ctx->prof_ms[k];
+    launches[k] = ctx->prof_launches[k];
+  }
+  return GDG_OK;
+}
+
+const char *gdg_last_error(const gdg_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
 
 }  // extern "C"

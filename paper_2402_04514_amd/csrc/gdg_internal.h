@@ -99,11 +99,20 @@ struct StageBufs {
   const double *Un;   // state at the start of the step (SSP combination)
   double ca, cb;      // out = ca * Un + cb * Phi(in)
 };
+// Optional kernel timing: when a Prof is passed, each launch is bracketed by
+// HIP events on the same stream; the host folds them into per-kernel sums
+// after the stream has synchronized.
+enum { KID_PRIM = 0, KID_SWEEP1, KID_SWEEP2, KID_LIMIT1, KID_LIMIT2, KID_COUNT };
+struct Prof {
+  void *ev[64];   // hipEvent_t, created by the host
+  int kid[32];    // kernel id of each bracketed launch
+  int n;          // bracketed launches since the last harvest
+};
 bool build_ref_tables(int dim, int deg, const double *h, RefTables *T, std::string *err);
 int launch_fill(const KArgs &A, void *stream);
 int launch_begin(const KArgs &A, double dt_cap, double tau_fixed, void *stream);
 int launch_end(const KArgs &A, void *stream);
 int launch_prim(const KArgs &A, const double *U, void *stream);
-int launch_stage(const KArgs &A, const StageBufs &b, int stage, void *stream);
+int launch_stage(const KArgs &A, const StageBufs &b, int stage, void *stream, Prof *prof);
 
 }  // namespace gdg

@@ -59,9 +59,13 @@ __device__ __forceinline__ double lambda_plus(const KArgs &A, double rl, double 
 
 // f(U) c for the Euler flux of eq. euler_flux, from conserved U and the
 // velocity u and pressure p of the node.
+// Contraction stays off here: f(U_j) c - f(U_i) c must be exactly zero for
+// equal states (x*y - x*y under a fused multiply-add leaves the rounding
+// error of x*y), so constant states give R_i = D_i = 0 and no flux.
 template <int D>
 __device__ __forceinline__ void flux_dot(const double *U, const double *u, double p, const double *c,
                                          double *out) {
+#pragma clang fp contract(off)
   double uc = 0.0;
   for (int e = 0; e < D; ++e) uc += u[e] * c[e];
   out[0] = U[0] * uc;
@@ -640,22 +644,49 @@ __global__ __launch_bounds__(kBlockThreads) void k_limit(KArgs A, StageBufs sb, 
 // host launchers
 static inline hipStream_t S(void *s) { return (hipStream_t)s; }
 
+static inline void prof_mark(Prof *p, int kid, int end, void *stream) {
+  if (!p || p->n >= 32) return;
+  hipEventRecord((hipEvent_t)p->ev[2 * p->n + end], S(stream));
+  if (end) {
+    p->kid[p->n] = kid;
+    ++p->n;
+  }
+}
+
+// Errors left in the thread's HIP error state by other code (for instance a
+// "not ready" stream query) must not be mistaken for a failed launch.
+static inline void clear_stale() { (void)hipGetLastError(); }
+
 template <int D, int DEG>
-static int stage_impl(const KArgs &A, const StageBufs &b, int stage, void *stream) {
+static int stage_impl(const KArgs &A, const StageBufs &b, int stage, void *stream, Prof *prof) {
+  clear_stale();
   const dim3 grid((unsigned)A.nblocks), blk(kBlockThreads);
   const unsigned gp = (unsigned)((A.N + kBlockThreads - 1) / kBlockThreads);
+  prof_mark(prof, KID_PRIM, 0, stream);
   hipLaunchKernelGGL(k_prim<D>, dim3(gp), blk, 0, S(stream), A, b.in);
+  prof_mark(prof, KID_PRIM, 1, stream);
+  prof_mark(prof, KID_SWEEP1, 0, stream);
   hipLaunchKernelGGL((k_sweep1<D, DEG>), grid, blk, 0, S(stream), A, b.in, stage);
+  prof_mark(prof, KID_SWEEP1, 1, stream);
+  prof_mark(prof, KID_SWEEP2, 0, stream);
   hipLaunchKernelGGL((k_sweep2<D, DEG>), grid, blk, 0, S(stream), A, b, stage);
-  if (A.scheme == 2 && A.passes >= 1)
+  prof_mark(prof, KID_SWEEP2, 1, stream);
+  if (A.scheme == 2 && A.passes >= 1) {
+    prof_mark(prof, KID_LIMIT1, 0, stream);
     hipLaunchKernelGGL((k_limit<D, DEG>), grid, blk, 0, S(stream), A, b, 0, A.passes == 1 ? 1 : 0);
-  if (A.scheme == 2 && A.passes >= 2)
+    prof_mark(prof, KID_LIMIT1, 1, stream);
+  }
+  if (A.scheme == 2 && A.passes >= 2) {
+    prof_mark(prof, KID_LIMIT2, 0, stream);
     hipLaunchKernelGGL((k_limit<D, DEG>), grid, blk, 0, S(stream), A, b, 1, 1);
+    prof_mark(prof, KID_LIMIT2, 1, stream);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <int D, int DEG>
 static int fill_impl(const KArgs &A, void *stream) {
+  clear_stale();
   hipLaunchKernelGGL((k_fill<D, DEG>), dim3((unsigned)A.nblocks), dim3(kBlockThreads), 0, S(stream), A);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -671,23 +702,26 @@ static int fill_impl(const KArgs &A, void *stream) {
     default: return -2;                                         \
   }
 
-int launch_stage(const KArgs &A, const StageBufs &b, int stage, void *stream) {
-  GDG_DISPATCH(stage_impl, A, b, stage, stream)
+int launch_stage(const KArgs &A, const StageBufs &b, int stage, void *stream, Prof *prof) {
+  GDG_DISPATCH(stage_impl, A, b, stage, stream, prof)
 }
 
 int launch_fill(const KArgs &A, void *stream) { GDG_DISPATCH(fill_impl, A, stream) }
 
 int launch_begin(const KArgs &A, double dt_cap, double tau_fixed, void *stream) {
+  clear_stale();
   hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, S(stream), A.ctl, dt_cap, tau_fixed);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_end(const KArgs &A, void *stream) {
+  clear_stale();
   hipLaunchKernelGGL(k_end, dim3(1), dim3(64), 0, S(stream), A.ctl);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_prim(const KArgs &A, const double *U, void *stream) {
+  clear_stale();
   const unsigned gp = (unsigned)((A.N + kBlockThreads - 1) / kBlockThreads);
   switch (A.dim) {
     case 1: hipLaunchKernelGGL(k_prim<1>, dim3(gp), dim3(kBlockThreads), 0, S(stream), A, U); break;

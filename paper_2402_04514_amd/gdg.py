@@ -62,6 +62,9 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise GdgError(GDG_E_DEVICE, "libgdg.so not built (run __graft_entry__.build())")
+    # torch ships its own HIP runtime under the same soname; loading it first
+    # makes libgdg bind to that one runtime instead of a second copy
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     L.gdg_default_params.argtypes = [C.c_int32, C.POINTER(gdg_params)]
     L.gdg_workspace_bytes.argtypes = [C.POINTER(gdg_mesh_desc), C.POINTER(gdg_params),
@@ -80,11 +83,13 @@ def load():
     L.gdg_stage.argtypes = [_P, C.c_double, _DP]
     L.gdg_read_field.argtypes = [_P, C.c_int32, _P, C.c_int32]
     L.gdg_get_stats.argtypes = [_P, C.POINTER(gdg_stats)]
+    L.gdg_profile.argtypes = [_P, C.c_int32]
+    L.gdg_profile_read.argtypes = [_P, _DP, C.POINTER(C.c_int64)]
     L.gdg_last_error.argtypes = [_P]
     L.gdg_last_error.restype = C.c_char_p
     for fn in ("gdg_default_params", "gdg_workspace_bytes", "gdg_create", "gdg_node_coords",
                "gdg_upload_state", "gdg_download_state", "gdg_step", "gdg_run_to", "gdg_stage",
-               "gdg_read_field", "gdg_get_stats"):
+               "gdg_read_field", "gdg_get_stats", "gdg_profile", "gdg_profile_read"):
         getattr(L, fn).restype = C.c_int
     _lib = L
     return L
@@ -92,7 +97,7 @@ def load():
 
 def _check(st, ctx=None):
     if st != GDG_OK:
-        msg = load().gdg_last_error(ctx).decode() if ctx else ""
+        msg = load().gdg_last_error(ctx).decode()
         raise GdgError(st, msg)
 
 
@@ -124,7 +129,7 @@ def gdg_workspace_bytes(mesh: gdg_mesh_desc, prm: gdg_params) -> int:
 def gdg_create(mesh, prm, workspace_ptr: int, ws_bytes: int, stream_ptr: int):
     ctx = _P()
     _check(load().gdg_create(C.byref(mesh), C.byref(prm), _P(workspace_ptr), ws_bytes,
-                             _P(stream_ptr), C.byref(ctx)))
+                             _P(stream_ptr), C.byref(ctx)), None)
     return ctx
 
 
@@ -190,6 +195,21 @@ def gdg_get_stats(ctx) -> gdg_stats:
     s = gdg_stats()
     _check(load().gdg_get_stats(ctx, C.byref(s)))
     return s
+
+
+KERNEL_NAMES = ("prim", "sweep1", "sweep2", "limit1", "limit2")
+
+
+def gdg_profile(ctx, enable: bool):
+    _check(load().gdg_profile(ctx, int(bool(enable))), ctx)
+
+
+def gdg_profile_read(ctx):
+    """{kernel name: (summed ms, launches)} since the last gdg_profile()."""
+    ms = np.zeros(len(KERNEL_NAMES))
+    n = np.zeros(len(KERNEL_NAMES), dtype=np.int64)
+    _check(load().gdg_profile_read(ctx, ms.ctypes.data_as(_DP), n.ctypes.data_as(C.POINTER(C.c_int64))), ctx)
+    return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_NAMES)}
 
 
 def gdg_last_error(ctx) -> str:
