@@ -47,23 +47,27 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(kernel: str, dim: int, slots: float, ghost_frac: float) -> float:
+def algorithmic_bytes(kernel: str, dim: int, slots: float) -> float:
     """Bytes per row (dof) a kernel must move with each array touched once:
     stencil entries (int32 column, meta byte, dim doubles of c_ij), per-slot
-    doubles (d^L, l), per-dof fields.  Neighbour gathers count once."""
+    fields (d^L, l, own-side l: doubles; transposed slot: int32), per-dof
+    fields.  Gathers of neighbour values count once (each value is needed once
+    per sweep); re-reads through the caches are not algorithmic."""
     M = dim + 2
     st = slots * (4 + 1 + 8 * dim)    # column, meta, c_ij
     idx = slots * (4 + 1)             # column, meta
     if kernel == "prim":
         return 8 * M + 8 * (dim + 5)
-    if kernel == "sweep1":
+    if kernel == "sweep1":   # U, node cache in; d^L, N, ring-1 partials out
         return st + 8 * (M + dim + 5) + 8 * slots + 8 + 24
-    if kernel == "sweep2":
+    if kernel == "sweep2":   # U, u, p, N, q, d^L in; U^L, bounds, dU^H out
         return st + 8 * slots + 8 * (M + dim + 1) + 8 + 24 + 8 * M + 24 + 8 * M
+    # U, base, dU^H, B, N, row length of i and of the neighbours (once); l out
+    lim = idx + 8 * slots + 8 * M * 3 + 24 + 8 + 4 + 8 * M + 8 * slots
     if kernel == "limit1":
-        return idx + 8 * slots + 8 * slots + 8 * M * 3 + 24 + 8 + 4 + 8 * M
+        return lim + 8 * M            # U^(1) out
     if kernel == "limit2":
-        return idx + 8 * slots * 2 + 8 * M * 3 + 24 + 8 + 4 + 8 * M + 8 * M
+        return lim + 8 * M + 8 * M    # l^(1) read (in 8*slots above), U^n in, stage output out
     raise KeyError(kernel)
 
 
@@ -172,7 +176,7 @@ def main():
     dom = max(prof, key=lambda k: prof[k][0])
     ms_tot, launches = prof[dom]
     avg_s = ms_tot / launches / 1e3
-    bytes_launch = algorithmic_bytes(dom, wl.mesh.dim, slots, 0.0) * ndofs
+    bytes_launch = algorithmic_bytes(dom, wl.mesh.dim, slots) * ndofs
     achieved = bytes_launch / avg_s / 1e9
     traffic = None
     tf = os.path.join(ROOT, "profiles", "traffic_%s.json" % args.workload)

@@ -71,6 +71,16 @@ bool validate(const gdg_mesh_desc *m, const gdg_params *p, std::string *err) {
   int nloc = 1;
   for (int e = 0; e < m->dim; ++e) nloc *= m->degree + 1;
   if (ncells * nloc >= (int64_t(1) << 31)) { *err = "too many dofs for 32-bit column indices"; return false; }
+  {
+    int nface = 1;
+    for (int e = 0; e < m->dim - 1; ++e) nface *= m->degree + 1;
+    const int cpb = kBlockThreads / nloc;
+    const int64_t nblocks = (ncells + cpb - 1) / cpb;
+    if (nblocks * (nloc + m->dim * nface) * (cpb * nloc) >= (int64_t(1) << 31)) {
+      *err = "too many stencil slots for 32-bit slot indices";
+      return false;
+    }
+  }
   // the two-rarefaction bound is an upper bound for 1 < gamma <= 5/3
   if (!(p->gamma > 1.0 && p->gamma <= 5.0 / 3.0 + 1e-12)) { *err = "gamma must lie in (1, 5/3]"; return false; }
   if (!(p->cfl > 0.0 && p->cfl <= 1.0)) { *err = "cfl must lie in (0, 1]"; return false; }
@@ -244,6 +254,7 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   A.inv_alpha = 1.0 / A.alpha;
   double ri = std::round(A.inv_alpha);
   A.ipow = (std::fabs(A.inv_alpha - ri) < 1e-9 && ri >= 1 && ri <= 32) ? (int)ri : 0;
+  A.g75 = std::fabs(prm->gamma - 1.4) < 1e-15 ? 1 : 0;
   A.scheme = prm->scheme;
   A.passes = prm->limiter_passes;
   A.nslots = L.nslots;
@@ -290,7 +301,15 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   int rc = (e1 == hipSuccess && e2 == hipSuccess) ? launch_fill(A, ctx->stream) : -1;
   hipError_t e4 = rc == 0 ? hipSuccess : hipGetLastError();
   hipError_t e3 = hipStreamSynchronize(ctx->stream);
+  Ctl chk;
+  std::memset(&chk, 0, sizeof chk);
+  if (rc == 0 && e3 == hipSuccess) e3 = hipMemcpy(&chk, A.ctl, sizeof(Ctl), hipMemcpyDeviceToHost);
   delete T;
+  if (rc == 0 && e3 == hipSuccess && chk.bad_flag) {
+    g_create_err = "internal error: the stencil is not symmetric";
+    delete ctx;
+    return GDG_E_DEVICE;
+  }
   if (rc != 0 || e3 != hipSuccess) {
     hipError_t e = e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : (e4 != hipSuccess ? e4 : e3));
     g_create_err = std::string(e1 != hipSuccess || e2 != hipSuccess ? "copy of the setup tables"

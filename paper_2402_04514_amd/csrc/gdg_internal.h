@@ -73,6 +73,7 @@ struct KArgs {
   double gamma, cfl, c_ev, c_k, pk, c_r, p_r, vol;
   double alpha, inv_alpha;
   int32_t ipow;     // > 0: 1/alpha equals this integer, the p* power is taken by multiplies
+  int32_t g75;      // gamma == 7/5: entropy comparisons by integer powers
   int32_t scheme, passes;
   // stencil
   int32_t *col;

@@ -12,8 +12,8 @@
 //   k_sweep2  tau, U^L (eq. cijdijschememodified), the relaxed bounds
 //             (eq. local_bounds), d^H (eq. HighOrderViscosity, ViscMin), the
 //             high-order residual and the cell solve (eq. HighScheme)
-//   k_limit   the antidiffusive fluxes A_ij (eq. HighLowOrderIdentity) and
-//             one limiter pass (eq. ConvexScheme, Lemma ConsInvariants); run
+//   k_limit   one limiter pass (eq. ConvexScheme, Lemma ConsInvariants) on
+//             the antidiffusive fluxes A_ij (eq. HighLowOrderIdentity); run
 //             twice (Sec. 6.1), the second pass on the remaining (1 - l) A
 // Every grid-wide dependency (tau, neighbours' N_j and bound partials, their
 // U^L_j / B_j / dU^H_j, the symmetric l_ij) is a kernel boundary.
@@ -81,11 +81,30 @@ __device__ __forceinline__ double eps_of(const double *V) {
 }
 
 // ---------------------------------------------------------------------------
-// Line search of Sec. 5.4: the largest l in [0, 1] with U + l P in B_i.
-// Density part in closed form; rescaled-entropy part on the concave
-// psi(l) = eps(U + l P) - s_min rho(U + l P)^gamma by a bracket narrowed with a
-// secant step (feasible side) and a tangent step at the infeasible end, until
-// the bracket is 1e-14 wide; the feasible end is returned.
+// Rescaled entropy tests.  For gamma = 7/5 the comparison
+//   eps >= s rho^(7/5)   <=>   eps^5 >= s^5 rho^7     (eps, s, rho > 0)
+// needs multiplies only; the power function is left to the rare cases.
+__device__ __forceinline__ double pow7(double x) {
+  double x2 = x * x;
+  return x2 * x2 * x2 * x;
+}
+__device__ __forceinline__ double pow5(double x) {
+  double x2 = x * x;
+  return x2 * x2 * x;
+}
+
+// s~^5 = eps^5 / rho^7 for gamma = 7/5 (monotone in s~), else s~ itself.
+__device__ __forceinline__ double stilde_key(const KArgs &A, double eps, double rho) {
+  if (A.g75) return pow5(eps) / pow7(rho);
+  return eps * pow(rho, -A.gamma);
+}
+
+// Line search of Sec. 5.4: the largest l in [0, 1] with U + l P in B_i,
+// P = sc * Av.  Density part in closed form; rescaled-entropy part on the
+// concave psi(l) = eps(U + l P) - s_min rho(U + l P)^gamma by a bracket
+// narrowed with a secant step (feasible side) and a tangent step at the
+// infeasible end, until the bracket is 1e-14 wide; the feasible end is
+// returned.
 template <int D>
 __device__ double ls_psi(double g, const double *U, const double *P, double smin, double l,
                          double *dpsi) {
@@ -106,15 +125,34 @@ __device__ double ls_psi(double g, const double *U, const double *P, double smin
   return eps - smin * rg;
 }
 
+// psi(l) >= 0 without the power function when gamma = 7/5
 template <int D>
-__device__ double line_search(double g, const double *U, const double *P, double rmin, double rmax,
-                              double smin) {
+__device__ __forceinline__ bool ls_feasible(const KArgs &A, const double *U, const double *P, double smin,
+                                            double smin5, double l) {
+  double V[D + 2];
+  for (int c = 0; c < D + 2; ++c) V[c] = U[c] + l * P[c];
+  const double eps = eps_of<D>(V);
+  if (A.g75 && smin5 > 0.0) {
+    if (!(eps > 0.0)) return false;
+    const double lhs = pow5(eps), rhs = smin5 * pow7(V[0]);
+    if (isfinite(lhs) && isfinite(rhs) && rhs > 1e-290) return lhs >= rhs;
+  }
+  return eps - smin * pow(V[0], A.gamma) >= 0.0;
+}
+
+template <int D>
+__device__ double line_search(const KArgs &A, const double *U, const double *Av, double sc, double rmin,
+                              double rmax, double smin, double smin5) {
+  const double g = A.gamma;
+  double P[D + 2];
+  for (int c = 0; c < D + 2; ++c) P[c] = sc * Av[c];
   const double r = U[0], pr = P[0];
   double lhi = 1.0;
   if (r + pr > rmax) lhi = (rmax - r) / pr;
   if (r + pr < rmin) lhi = (rmin - r) / pr;
   if (!(lhi > 0.0)) lhi = 0.0;
   if (lhi > 1.0) lhi = 1.0;
+  if (ls_feasible<D>(A, U, P, smin, smin5, lhi)) return lhi;
   double ph = ls_psi<D>(g, U, P, smin, lhi, nullptr);
   if (ph >= 0.0) return lhi;
   double p0 = ls_psi<D>(g, U, P, smin, 0.0, nullptr);
@@ -137,6 +175,17 @@ __device__ double line_search(double g, const double *U, const double *P, double
   return l;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
+// with its own L2.  Remapping the hardware block id so that every XCD sweeps
+// one contiguous range of row blocks keeps a block's face neighbours (the
+// blocks one cell row earlier) in the same L2.  A bijection of [0, nblocks).
+__device__ __forceinline__ int64_t xcd_block(int64_t hw, int64_t nblocks) {
+  constexpr int64_t kX = 8;
+  const int64_t q = nblocks / kX, r = nblocks % kX;
+  const int64_t x = hw % kX, k = hw / kX;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // ---------------------------------------------------------------------------
 // Setup: expand the cell-class tables into the row-blocked ELL stencil.
 template <int D, int DEG>
@@ -146,7 +195,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_fill(KArgs A) {
   constexpr int NFACE = NLOC / NB;
   const int lane = threadIdx.x;
   if (lane >= A.R) return;
-  const int64_t blk = blockIdx.x;
+  const int64_t blk = xcd_block(blockIdx.x, A.nblocks);
   const int64_t i = blk * A.R + lane;
   const RefTables *T = A.ref;
   int t = 0;
@@ -288,7 +337,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep1(KArgs A, const double 
   constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
   if (A.ctl->cfl_flag) return;  // set by an earlier kernel or never
   const int lane = threadIdx.x;
-  const int64_t blk = blockIdx.x;
+  const int64_t blk = xcd_block(blockIdx.x, A.nblocks);
   const int64_t i = blk * A.R + lane;
   const bool active = lane < A.R && i < A.N;
   double tau_i = INFINITY;
@@ -312,6 +361,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep1(KArgs A, const double 
     for (int c = 0; c < M; ++c) S[c] = 0.0;
     double dsum = 0.0;
     double rmin = INFINITY, rmax = -INFINITY, smin = INFINITY;
+    // bar state with the smallest rescaled entropy, ranked by stilde_key
+    double kbar = INFINITY, ebar = 0.0, rbar = 1.0;
     for (int t = 0; t < A.W; ++t) {
       const int64_t s = (blk * A.W + t) * A.R + lane;
       const uint8_t meta = A.meta[s];
@@ -369,15 +420,18 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep1(KArgs A, const double 
       for (int e = 0; e < D; ++e) mc += nj.U[1 + e] * c[e];
       T += mc * (nj.fs - ni.fs);
       double bar[M];
+      const double h2d = 0.5 / d;
       for (int q = 0; q < M; ++q) {
         double df = fj[q] - fi[q];
         S[q] += df;
-        bar[q] = 0.5 * (ni.U[q] + nj.U[q]) - df / (2.0 * d);
+        bar[q] = 0.5 * (ni.U[q] + nj.U[q]) - df * h2d;
       }
       rmin = fmin(rmin, bar[0]);
       rmax = fmax(rmax, bar[0]);
-      smin = fmin(smin, pow(bar[0], -g) * eps_of<D>(bar));
+      const double eb = eps_of<D>(bar), kb = stilde_key(A, eb, bar[0]);
+      if (kb < kbar) { kbar = kb; ebar = eb; rbar = bar[0]; }
     }
+    if (kbar < INFINITY) smin = fmin(smin, ebar * pow(rbar, -g));
     double R = T, Dn = fabs(T);
     for (int q = 0; q < M; ++q) { R -= grad[q] * S[q]; Dn += fabs(grad[q]) * fabs(S[q]); }
     A.Nev[i] = Dn > 0.0 ? R / Dn : 0.0;
@@ -430,7 +484,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep2(KArgs A, StageBufs sb,
   if (stage == 0 && blockIdx.x == 0 && threadIdx.x == 0) A.ctl->tau = tau;
   const double *__restrict__ U = sb.in;
   const int lane = threadIdx.x;
-  const int64_t blk = blockIdx.x;
+  const int64_t blk = xcd_block(blockIdx.x, A.nblocks);
   const int64_t i = blk * A.R + lane;
   const bool active = lane < A.R && i < A.N;
   const int64_t N = A.N;
@@ -538,9 +592,46 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep2(KArgs A, StageBufs sb,
 }
 
 // ---------------------------------------------------------------------------
-// One limiter pass.  pass 0: base = U^L, fluxes A_ij, writes l per slot and
-// U^(1).  pass 1: base = U^(1), fluxes (1 - l^(1)) A_ij.  The final pass writes
-// the stage output (SSP combination).
+// Antidiffusive flux of eq. HighLowOrderIdentity for a graph pair:
+//   A_ij = tau (d^H_ij - d^L_ij)(U_j - U_i) - m_ij (dU^H_j - dU^H_i).
+// d^L, d^H and m_ij are symmetric, so row j computes exactly -A_ij.
+template <int D, int NLOC>
+__device__ __forceinline__ void pair_flux(const KArgs &A, const double *__restrict__ U, int64_t j, uint8_t meta,
+                                          int a, const double *Ui, const double *dUi, double Ni, double hpk,
+                                          double tau, double d, double *Aij) {
+  const int64_t N = A.N;
+  const int kind = meta & 7;
+  const double dH = visc_high(A, d, Ni, A.Nev[j], kind, hpk);
+  const double mij = kind == SK_CELL ? A.ref->mblk[a * NLOC + (meta >> 3)] : 0.0;
+  const double td = tau * (dH - d);
+  for (int q = 0; q < D + 2; ++q) Aij[q] = td * (U[q * N + j] - Ui[q]) - mij * (A.dUH[q * N + j] - dUi[q]);
+}
+
+// Boundary part of A_i^d for one ghost slot: tau (d^{d,H} - d^{d,L})(U^d - U_i).
+template <int D>
+__device__ __forceinline__ void ghost_flux(const KArgs &A, int64_t s, uint8_t meta, const double *Ui, double Ni,
+                                           double hpk, double tau, double d, double *Ab) {
+  double c[D], nc2 = 0.0;
+  for (int e = 0; e < D; ++e) { c[e] = A.c[e * A.nslots + s]; nc2 += c[e] * c[e]; }
+  const double nc = sqrt(nc2);
+  double Ug[D + 2];
+  for (int q = 0; q < D + 2; ++q) Ug[q] = Ui[q];
+  if ((meta >> 3) == 2) {
+    double mn = 0.0;
+    for (int e = 0; e < D; ++e) mn += Ui[1 + e] * (c[e] / nc);
+    for (int e = 0; e < D; ++e) Ug[1 + e] = Ui[1 + e] - 2.0 * mn * (c[e] / nc);
+  }
+  const double dH = fmax(hpk * d, d * fmin(A.c_ev * fabs(Ni), 1.0));
+  for (int q = 0; q < D + 2; ++q) Ab[q] += tau * (dH - d) * (Ug[q] - Ui[q]);
+}
+
+// One limiter pass (eq. ConvexScheme, Lemma ConsInvariants).  Row i runs both
+// line searches of each pair, l^i_ij = LS(base_i, A_ij/(kappa_i m_i), B_i) and
+// l^j_ji = LS(base_j, -A_ij/(kappa_j m_j), B_j), so l_ij = min(l^i_ij, l^j_ji)
+// is symmetric bit for bit without a grid-wide exchange; l_i^d comes from the
+// boundary part alone.  pass 0: base U^L, fluxes A, writes l per slot and
+// U^(1).  pass 1: base U^(1), fluxes (1 - l^(1)) A.  The final pass writes the
+// SSP combination.
 template <int D, int DEG>
 __global__ __launch_bounds__(kBlockThreads) void k_limit(KArgs A, StageBufs sb, int pass, int final_pass) {
   constexpr int M = D + 2;
@@ -548,18 +639,17 @@ __global__ __launch_bounds__(kBlockThreads) void k_limit(KArgs A, StageBufs sb, 
   constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
   if (A.ctl->cfl_flag) return;
   const int lane = threadIdx.x;
-  const int64_t blk = blockIdx.x;
+  const int64_t blk = xcd_block(blockIdx.x, A.nblocks);
   const int64_t i = blk * A.R + lane;
   if (lane >= A.R || i >= A.N) return;
   const double *__restrict__ U = sb.in;
   const double *__restrict__ base = pass == 0 ? A.UL : A.U1;
   const int64_t N = A.N;
-  const double g = A.gamma;
   const double tau = A.ctl->tau;
   const int a = (int)(i % NLOC);
   const double mi = A.ref->mlump[a];
   const double hpk = A.ref->hpk[a];
-  const double kap_i = 1.0 / (double)(A.rowlen[i] + 1);
+  const double sci = (double)(A.rowlen[i] + 1) / mi;  // 1 / (kappa_i m_i)
   const double Ni = A.Nev[i];
   double Ui[M], Li[M], dUi[M];
   for (int q = 0; q < M; ++q) {
@@ -567,7 +657,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_limit(KArgs A, StageBufs sb, 
     Li[q] = base[q * N + i];
     dUi[q] = A.dUH[q * N + i];
   }
-  const double bi_rmin = A.B[i], bi_rmax = A.B[N + i], bi_smin = A.B[2 * N + i];
+  const double rmin = A.B[i], rmax = A.B[N + i], smin = A.B[2 * N + i];
+  const double smin5 = A.g75 ? pow5(smin) : 0.0;
   double acc[M], Ab[M];
   for (int q = 0; q < M; ++q) acc[q] = Ab[q] = 0.0;
   int64_t gslot = -1;
@@ -578,42 +669,27 @@ __global__ __launch_bounds__(kBlockThreads) void k_limit(KArgs A, StageBufs sb, 
     if (kind == SK_PAD) continue;
     const double d = A.dL[s];
     if (kind == SK_GHOST) {
-      double c[D], nc2 = 0.0;
-      for (int e = 0; e < D; ++e) { c[e] = A.c[e * A.nslots + s]; nc2 += c[e] * c[e]; }
-      const double nc = sqrt(nc2);
-      double Ug[M];
-      for (int q = 0; q < M; ++q) Ug[q] = Ui[q];
-      if ((meta >> 3) == 2) {
-        double mn = 0.0;
-        for (int e = 0; e < D; ++e) mn += Ui[1 + e] * (c[e] / nc);
-        for (int e = 0; e < D; ++e) Ug[1 + e] = Ui[1 + e] - 2.0 * mn * (c[e] / nc);
-      }
-      const double dH = fmax(hpk * d, d * fmin(A.c_ev * fabs(Ni), 1.0));
-      for (int q = 0; q < M; ++q) Ab[q] += tau * (dH - d) * (Ug[q] - Ui[q]);
+      ghost_flux<D>(A, s, meta, Ui, Ni, hpk, tau, d, Ab);
       if (gslot < 0) gslot = s;
       continue;
     }
     const int64_t j = A.col[s];
     if (j == i) continue;  // A_ii = 0
-    const double dH = visc_high(A, d, Ni, A.Nev[j], kind, hpk);
-    const double mij = kind == SK_CELL ? A.ref->mblk[a * NLOC + (meta >> 3)] : 0.0;
     double Aij[M];
-    for (int q = 0; q < M; ++q)
-      Aij[q] = tau * (dH - d) * (U[q * N + j] - Ui[q]) - mij * (A.dUH[q * N + j] - dUi[q]);
+    pair_flux<D, NLOC>(A, U, j, meta, a, Ui, dUi, Ni, hpk, tau, d, Aij);
     if (pass == 1) {
       const double rest = 1.0 - A.l1[s];
       for (int q = 0; q < M; ++q) Aij[q] = rest * Aij[q];
     }
-    double P[M], Lj[M];
-    for (int q = 0; q < M; ++q) P[q] = Aij[q] / (kap_i * mi);
-    const double li = line_search<D>(g, Li, P, bi_rmin, bi_rmax, bi_smin);
-    const double kap_j = 1.0 / (double)(A.rowlen[j] + 1);
-    const double mj = A.ref->mlump[j % NLOC];
+    const double li = line_search<D>(A, Li, Aij, sci, rmin, rmax, smin, smin5);
+    double Lj[M], Aji[M];
     for (int q = 0; q < M; ++q) {
       Lj[q] = base[q * N + j];
-      P[q] = -Aij[q] / (kap_j * mj);
+      Aji[q] = -Aij[q];
     }
-    const double lj = line_search<D>(g, Lj, P, A.B[j], A.B[N + j], A.B[2 * N + j]);
+    const double sj = A.B[2 * N + j];
+    const double scj = (double)(A.rowlen[j] + 1) / A.ref->mlump[j % NLOC];
+    const double lj = line_search<D>(A, Lj, Aji, scj, A.B[j], A.B[N + j], sj, A.g75 ? pow5(sj) : 0.0);
     const double l = fmin(li, lj);
     for (int q = 0; q < M; ++q) acc[q] += l * Aij[q];
     if (pass == 0) A.l1[s] = l;
@@ -623,9 +699,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_limit(KArgs A, StageBufs sb, 
       const double rest = 1.0 - A.l1[gslot];
       for (int q = 0; q < M; ++q) Ab[q] = rest * Ab[q];
     }
-    double P[M];
-    for (int q = 0; q < M; ++q) P[q] = Ab[q] / (kap_i * mi);
-    const double lb = line_search<D>(g, Li, P, bi_rmin, bi_rmax, bi_smin);
+    const double lb = line_search<D>(A, Li, Ab, sci, rmin, rmax, smin, smin5);
     for (int q = 0; q < M; ++q) acc[q] += lb * Ab[q];
     if (pass == 0) A.l1[gslot] = lb;
   }
@@ -671,15 +745,10 @@ static int stage_impl(const KArgs &A, const StageBufs &b, int stage, void *strea
   prof_mark(prof, KID_SWEEP2, 0, stream);
   hipLaunchKernelGGL((k_sweep2<D, DEG>), grid, blk, 0, S(stream), A, b, stage);
   prof_mark(prof, KID_SWEEP2, 1, stream);
-  if (A.scheme == 2 && A.passes >= 1) {
-    prof_mark(prof, KID_LIMIT1, 0, stream);
-    hipLaunchKernelGGL((k_limit<D, DEG>), grid, blk, 0, S(stream), A, b, 0, A.passes == 1 ? 1 : 0);
-    prof_mark(prof, KID_LIMIT1, 1, stream);
-  }
-  if (A.scheme == 2 && A.passes >= 2) {
-    prof_mark(prof, KID_LIMIT2, 0, stream);
-    hipLaunchKernelGGL((k_limit<D, DEG>), grid, blk, 0, S(stream), A, b, 1, 1);
-    prof_mark(prof, KID_LIMIT2, 1, stream);
+  for (int pass = 0; pass < (A.scheme == 2 ? A.passes : 0); ++pass) {
+    prof_mark(prof, KID_LIMIT1 + pass, 0, stream);
+    hipLaunchKernelGGL((k_limit<D, DEG>), grid, blk, 0, S(stream), A, b, pass, pass + 1 == A.passes ? 1 : 0);
+    prof_mark(prof, KID_LIMIT1 + pass, 1, stream);
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
