@@ -41,7 +41,7 @@ thread_local std::string g_create_err;
 struct Layout {
   int nloc, nb1, R, cpb, W, M;
   int64_t N, ncells, nblocks, nslots;
-  size_t off_ref, off_ctl, off_col, off_c, off_meta, off_rowlen, off_U[3], off_Wc, off_N, off_q,
+  size_t off_ref, off_ctl, off_col, off_c, off_meta, off_kscale, off_U[3], off_Wc, off_N, off_q,
       off_B, off_UL, off_dUH, off_U1, off_dL, off_l1, total;
 };
 
@@ -118,9 +118,9 @@ Layout layout(const gdg_mesh_desc *m) {
   L.off_col = take(S * 4);
   L.off_c = take(S * d * 8);
   L.off_meta = take(S);
-  L.off_rowlen = take(N * 4);
+  L.off_kscale = take(N * 8);
   for (int k = 0; k < 3; ++k) L.off_U[k] = take(M * N * 8);
-  L.off_Wc = take((d + 5) * N * 8);
+  L.off_Wc = take((d + 6) * N * 8);
   L.off_N = take(N * 8);
   L.off_q = take(3 * N * 8);
   L.off_B = take(3 * N * 8);
@@ -264,7 +264,7 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   A.col = (int32_t *)(ws + L.off_col);
   A.c = (double *)(ws + L.off_c);
   A.meta = (uint8_t *)(ws + L.off_meta);
-  A.rowlen = (int32_t *)(ws + L.off_rowlen);
+  A.kscale = (double *)(ws + L.off_kscale);
   for (int k = 0; k < 3; ++k) ctx->U[k] = (double *)(ws + L.off_U[k]);
   ctx->cur = 0;
   A.Wc = (double *)(ws + L.off_Wc);

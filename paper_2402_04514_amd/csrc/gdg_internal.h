@@ -79,11 +79,11 @@ struct KArgs {
   int32_t *col;
   double *c;        // dim planes of nslots
   uint8_t *meta;
-  int32_t *rowlen;
+  double *kscale;   // 1 / (kappa_i m_i) per row, kappa_i = 1/(card I(i) + 1)
   const RefTables *ref;
   int64_t nslots;
   // per-dof fields
-  double *Wc;       // node cache: dim velocities, p, a, p^-alpha, f(s), s~  (dim+5 planes)
+  double *Wc;       // node cache: dim velocities, p, a, p^-alpha, f(s), s~, 1/p  (dim+6 planes)
   double *Nev;      // entropy-viscosity ratio
   double *q;        // ring-1 bound partials: rho_min, rho_max, s~_min
   double *B;        // relaxed bounds

@@ -23,6 +23,15 @@
 
 #include "gdg_internal.h"
 
+// Occupancy targets (waves per SIMD) chosen by measurement: the sweeps gain
+// from a third wave, the limiter loses more to spills than it gains.
+#ifndef GDG_WPE_LIMIT
+#define GDG_WPE_LIMIT 1
+#endif
+#ifndef GDG_WPE_SWEEP
+#define GDG_WPE_SWEEP 3
+#endif
+
 namespace gdg {
 
 __device__ __forceinline__ double ipow_d(double x, int n) {
@@ -39,11 +48,10 @@ __device__ __forceinline__ double ipow_d(double x, int n) {
 // Riemann problem (Guermond & Popov 2016), valid for 1 < gamma <= 5/3.
 // Left state (rl, ul, pl, al, pal = pl^-alpha), right state likewise; ul, ur
 // are the velocities projected on the unit normal.
-__device__ __forceinline__ double lambda_plus(const KArgs &A, double rl, double ul, double pl,
-                                              double al, double pal, double rr, double ur,
-                                              double pr, double ar, double par) {
-  (void)rl;
-  (void)rr;
+// ipl, ipr are 1/p of the two states.
+__device__ __forceinline__ double lambda_plus(const KArgs &A, double ul, double pl, double al, double pal,
+                                              double ipl, double ur, double pr, double ar, double par,
+                                              double ipr) {
   const double g = A.gamma;
   double num = al + ar - 0.5 * (g - 1.0) * (ur - ul);
   double pstar = 0.0;
@@ -52,8 +60,8 @@ __device__ __forceinline__ double lambda_plus(const KArgs &A, double rl, double 
     pstar = A.ipow > 0 ? ipow_d(x, A.ipow) : pow(x, A.inv_alpha);
   }
   double kf = (g + 1.0) / (2.0 * g);
-  double l1 = ul - al * sqrt(1.0 + kf * fmax(pstar - pl, 0.0) / pl);
-  double l3 = ur + ar * sqrt(1.0 + kf * fmax(pstar - pr, 0.0) / pr);
+  double l1 = ul - al * sqrt(1.0 + kf * fmax(pstar - pl, 0.0) * ipl);
+  double l3 = ur + ar * sqrt(1.0 + kf * fmax(pstar - pr, 0.0) * ipr);
   return fmax(fmax(-l1, l3), 0.0);
 }
 
@@ -93,10 +101,14 @@ __device__ __forceinline__ double pow5(double x) {
   return x2 * x2 * x;
 }
 
-// s~^5 = eps^5 / rho^7 for gamma = 7/5 (monotone in s~), else s~ itself.
-__device__ __forceinline__ double stilde_key(const KArgs &A, double eps, double rho) {
-  if (A.g75) return pow5(eps) / pow7(rho);
-  return eps * pow(rho, -A.gamma);
+// s~^5 = (rho eps)^5 / rho^12 for gamma = 7/5 (monotone in s~), else s~
+// itself; reps = rho eps = rho E - |m|^2/2.
+__device__ __forceinline__ double stilde_key(const KArgs &A, double reps, double rho) {
+  if (A.g75) {
+    const double r3 = rho * rho * rho, r6 = r3 * r3;
+    return pow5(reps) / (r6 * r6);
+  }
+  return reps / rho * pow(rho, -A.gamma);
 }
 
 // Line search of Sec. 5.4: the largest l in [0, 1] with U + l P in B_i,
@@ -131,28 +143,50 @@ __device__ __forceinline__ bool ls_feasible(const KArgs &A, const double *U, con
                                             double smin5, double l) {
   double V[D + 2];
   for (int c = 0; c < D + 2; ++c) V[c] = U[c] + l * P[c];
-  const double eps = eps_of<D>(V);
   if (A.g75 && smin5 > 0.0) {
-    if (!(eps > 0.0)) return false;
-    const double lhs = pow5(eps), rhs = smin5 * pow7(V[0]);
+    // rho eps = rho E - |m|^2/2; eps^5 >= s^5 rho^7 <=> (rho eps)^5 >= s^5 rho^12
+    double m2 = 0.0;
+    for (int e = 0; e < D; ++e) m2 += V[1 + e] * V[1 + e];
+    const double re = V[0] * V[D + 1] - 0.5 * m2;
+    if (!(re > 0.0)) return false;
+    const double r3 = V[0] * V[0] * V[0], r6 = r3 * r3;
+    const double lhs = pow5(re), rhs = smin5 * (r6 * r6);
     if (isfinite(lhs) && isfinite(rhs) && rhs > 1e-290) return lhs >= rhs;
   }
-  return eps - smin * pow(V[0], A.gamma) >= 0.0;
+  return eps_of<D>(V) - smin * pow(V[0], A.gamma) >= 0.0;
+}
+
+// Common path of the line search, branch free: the density limit
+// l_rho and whether the rescaled-entropy bound holds there.  When it holds,
+// LS = l_rho; otherwise ls_slow() brackets the root.
+template <int D>
+__device__ __forceinline__ bool ls_fast(const KArgs &A, const double *U, const double *P, double rmin,
+                                        double rmax, double smin, double smin5, double *lhi_out) {
+  const double r = U[0], pr = P[0], rp = r + pr;
+  // only one of the two limits can be active: rho + P_rho > rho_max needs P_rho > 0
+  const double lim = (rp > rmax ? rmax : rmin) - r;
+  const double t = lim / pr;
+  double lhi = (rp > rmax || rp < rmin) ? t : 1.0;
+  lhi = lhi > 0.0 ? lhi : 0.0;  // also maps NaN to 0
+  lhi = lhi < 1.0 ? lhi : 1.0;
+  *lhi_out = lhi;
+  double V[D + 2];
+  for (int c = 0; c < D + 2; ++c) V[c] = U[c] + lhi * P[c];
+  if (A.g75) {
+    double m2 = 0.0;
+    for (int e = 0; e < D; ++e) m2 += V[1 + e] * V[1 + e];
+    const double re = V[0] * V[D + 1] - 0.5 * m2;  // rho eps
+    const double r3 = V[0] * V[0] * V[0], r6 = r3 * r3;
+    const double lhs = pow5(re), rhs = smin5 * (r6 * r6);
+    // inside the range where the integer powers are exact enough to decide
+    const bool decided = isfinite(lhs) && isfinite(rhs) && rhs > 1e-290 && smin5 > 0.0;
+    return decided && re > 0.0 && lhs >= rhs;
+  }
+  return eps_of<D>(V) - smin * pow(V[0], A.gamma) >= 0.0;
 }
 
 template <int D>
-__device__ double line_search(const KArgs &A, const double *U, const double *Av, double sc, double rmin,
-                              double rmax, double smin, double smin5) {
-  const double g = A.gamma;
-  double P[D + 2];
-  for (int c = 0; c < D + 2; ++c) P[c] = sc * Av[c];
-  const double r = U[0], pr = P[0];
-  double lhi = 1.0;
-  if (r + pr > rmax) lhi = (rmax - r) / pr;
-  if (r + pr < rmin) lhi = (rmin - r) / pr;
-  if (!(lhi > 0.0)) lhi = 0.0;
-  if (lhi > 1.0) lhi = 1.0;
-  if (ls_feasible<D>(A, U, P, smin, smin5, lhi)) return lhi;
+__device__ __forceinline__ double ls_slow(double g, const double *U, const double *P, double smin, double lhi) {
   double ph = ls_psi<D>(g, U, P, smin, lhi, nullptr);
   if (ph >= 0.0) return lhi;
   double p0 = ls_psi<D>(g, U, P, smin, 0.0, nullptr);
@@ -173,6 +207,16 @@ __device__ double line_search(const KArgs &A, const double *U, const double *Av,
     if (px >= 0.0) { l = x; pl = px; } else { rr = x; prr = px; }
   }
   return l;
+}
+
+// Line search of Sec. 5.4: the largest l in [0, 1] with U + l P in B, P = sc Av.
+template <int D>
+__device__ __forceinline__ double line_search(const KArgs &A, const double *U, const double *Av, double sc,
+                                              double rmin, double rmax, double smin, double smin5) {
+  double P[D + 2], lhi;
+  for (int c = 0; c < D + 2; ++c) P[c] = sc * Av[c];
+  if (ls_fast<D>(A, U, P, rmin, rmax, smin, smin5, &lhi)) return lhi;
+  return ls_slow<D>(A.gamma, U, P, smin, lhi);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
@@ -241,7 +285,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_fill(KArgs A) {
         ++graph;
       }
     }
-    A.rowlen[i] = graph;
+    A.kscale[i] = (double)(graph + 1) / T->mlump[a];  // 1 / (kappa_i m_i), kappa_i = 1/(card I(i) + 1)
   }
   while (t < A.W) put((int32_t)(i < A.N ? i : 0), nullptr, SK_PAD);
 }
@@ -284,13 +328,14 @@ __global__ __launch_bounds__(kBlockThreads) void k_prim(KArgs A, const double *_
   A.Wc[(D + 2) * N + i] = pow(p, -A.alpha);
   A.Wc[(D + 3) * N + i] = exp(log(rg * p) / (g + 1.0));  // Harten entropy f(s) = e^{s/(gamma+1)}
   A.Wc[(D + 4) * N + i] = rg * eps;                      // s~ = rho^-gamma eps
+  A.Wc[(D + 5) * N + i] = 1.0 / p;
 }
 
 template <int D>
 struct Node {
   double U[D + 2];
   double u[D];
-  double p, a, pal, fs, st;
+  double p, a, pal, fs, st, ip;
 };
 
 template <int D>
@@ -304,6 +349,7 @@ __device__ __forceinline__ void load_node(const KArgs &A, const double *__restri
   n.pal = A.Wc[(D + 2) * N + j];
   n.fs = A.Wc[(D + 3) * N + j];
   n.st = A.Wc[(D + 4) * N + j];
+  n.ip = A.Wc[(D + 5) * N + j];
 }
 
 // Boundary data of Sec. 4.1: outflow keeps U_i; slip reflects the normal
@@ -330,7 +376,7 @@ __device__ __forceinline__ double block_min_atomic(double v, unsigned long long 
 
 // ---------------------------------------------------------------------------
 template <int D, int DEG>
-__global__ __launch_bounds__(kBlockThreads) void k_sweep1(KArgs A, const double *__restrict__ U,
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_SWEEP))) void k_sweep1(KArgs A, const double *__restrict__ U,
                                                           int stage) {
   constexpr int M = D + 2;
   constexpr int NB = DEG + 1;
@@ -375,12 +421,13 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep1(KArgs A, const double 
       const double nc = sqrt(nc2);
       if (kind == SK_GHOST) {
         double n[D];
-        for (int e = 0; e < D; ++e) n[e] = c[e] / nc;
+        const double inc = 1.0 / nc;
+        for (int e = 0; e < D; ++e) n[e] = c[e] * inc;
         Node<D> gh;
         ghost_node<D>(ni, meta >> 3, n, gh);
         double ul = 0.0, ur = 0.0;
         for (int e = 0; e < D; ++e) { ul += ni.u[e] * n[e]; ur += gh.u[e] * n[e]; }
-        double d = nc * lambda_plus(A, ni.U[0], ul, ni.p, ni.a, ni.pal, gh.U[0], ur, gh.p, gh.a, gh.pal);
+        double d = nc * lambda_plus(A, ul, ni.p, ni.a, ni.pal, ni.ip, ur, gh.p, gh.a, gh.pal, gh.ip);
         A.dL[s] = d;
         dsum += d;
         double fj[M], fi[M];
@@ -404,13 +451,14 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep1(KArgs A, const double 
       const Node<D> &na = lo ? ni : nj;
       const Node<D> &nb = lo ? nj : ni;
       const double sg = lo ? 1.0 : -1.0;
+      const double inc = sg / nc;
       double ua = 0.0, ub = 0.0;
       for (int e = 0; e < D; ++e) {
-        double ne = sg * c[e] / nc;
+        double ne = c[e] * inc;
         ua += na.u[e] * ne;
         ub += nb.u[e] * ne;
       }
-      const double d = nc * lambda_plus(A, na.U[0], ua, na.p, na.a, na.pal, nb.U[0], ub, nb.p, nb.a, nb.pal);
+      const double d = nc * lambda_plus(A, ua, na.p, na.a, na.pal, na.ip, ub, nb.p, nb.a, nb.pal, nb.ip);
       A.dL[s] = d;
       dsum += d;
       double fj[M], fi[M];
@@ -428,10 +476,13 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep1(KArgs A, const double 
       }
       rmin = fmin(rmin, bar[0]);
       rmax = fmax(rmax, bar[0]);
-      const double eb = eps_of<D>(bar), kb = stilde_key(A, eb, bar[0]);
-      if (kb < kbar) { kbar = kb; ebar = eb; rbar = bar[0]; }
+      double m2 = 0.0;
+      for (int e = 0; e < D; ++e) m2 += bar[1 + e] * bar[1 + e];
+      const double rb = bar[0] * bar[M - 1] - 0.5 * m2;  // rho eps of the bar state
+      const double kb = stilde_key(A, rb, bar[0]);
+      if (kb < kbar) { kbar = kb; ebar = rb; rbar = bar[0]; }
     }
-    if (kbar < INFINITY) smin = fmin(smin, ebar * pow(rbar, -g));
+    if (kbar < INFINITY) smin = fmin(smin, ebar / rbar * pow(rbar, -g));
     double R = T, Dn = fabs(T);
     for (int q = 0; q < M; ++q) { R -= grad[q] * S[q]; Dn += fabs(grad[q]) * fabs(S[q]); }
     A.Nev[i] = Dn > 0.0 ? R / Dn : 0.0;
@@ -468,7 +519,7 @@ __device__ __forceinline__ bool stage_tau(const KArgs &A, int stage, double *tau
 }
 
 template <int D, int DEG>
-__global__ __launch_bounds__(kBlockThreads) void k_sweep2(KArgs A, StageBufs sb, int stage) {
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_SWEEP))) void k_sweep2(KArgs A, StageBufs sb, int stage) {
   constexpr int M = D + 2;
   constexpr int NB = DEG + 1;
   constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
@@ -513,7 +564,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep2(KArgs A, StageBufs sb,
         for (int e = 0; e < D; ++e) nc2 += c[e] * c[e];
         const double nc = sqrt(nc2);
         double n[D];
-        for (int e = 0; e < D; ++e) n[e] = c[e] / nc;
+        const double inc = 1.0 / nc;
+        for (int e = 0; e < D; ++e) n[e] = c[e] * inc;
         Node<D> gh;
         ghost_node<D>(ni, meta >> 3, n, gh);
         double fj[M], fi[M];
@@ -613,13 +665,13 @@ __device__ __forceinline__ void ghost_flux(const KArgs &A, int64_t s, uint8_t me
                                            double hpk, double tau, double d, double *Ab) {
   double c[D], nc2 = 0.0;
   for (int e = 0; e < D; ++e) { c[e] = A.c[e * A.nslots + s]; nc2 += c[e] * c[e]; }
-  const double nc = sqrt(nc2);
+  const double inc = 1.0 / sqrt(nc2);
   double Ug[D + 2];
   for (int q = 0; q < D + 2; ++q) Ug[q] = Ui[q];
   if ((meta >> 3) == 2) {
     double mn = 0.0;
-    for (int e = 0; e < D; ++e) mn += Ui[1 + e] * (c[e] / nc);
-    for (int e = 0; e < D; ++e) Ug[1 + e] = Ui[1 + e] - 2.0 * mn * (c[e] / nc);
+    for (int e = 0; e < D; ++e) mn += Ui[1 + e] * (c[e] * inc);
+    for (int e = 0; e < D; ++e) Ug[1 + e] = Ui[1 + e] - 2.0 * mn * (c[e] * inc);
   }
   const double dH = fmax(hpk * d, d * fmin(A.c_ev * fabs(Ni), 1.0));
   for (int q = 0; q < D + 2; ++q) Ab[q] += tau * (dH - d) * (Ug[q] - Ui[q]);
@@ -633,7 +685,7 @@ __device__ __forceinline__ void ghost_flux(const KArgs &A, int64_t s, uint8_t me
 // U^(1).  pass 1: base U^(1), fluxes (1 - l^(1)) A.  The final pass writes the
 // SSP combination.
 template <int D, int DEG>
-__global__ __launch_bounds__(kBlockThreads) void k_limit(KArgs A, StageBufs sb, int pass, int final_pass) {
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_LIMIT))) void k_limit(KArgs A, StageBufs sb, int pass, int final_pass) {
   constexpr int M = D + 2;
   constexpr int NB = DEG + 1;
   constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
@@ -649,7 +701,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_limit(KArgs A, StageBufs sb, 
   const int a = (int)(i % NLOC);
   const double mi = A.ref->mlump[a];
   const double hpk = A.ref->hpk[a];
-  const double sci = (double)(A.rowlen[i] + 1) / mi;  // 1 / (kappa_i m_i)
+  const double sci = A.kscale[i];  // 1 / (kappa_i m_i)
   const double Ni = A.Nev[i];
   double Ui[M], Li[M], dUi[M];
   for (int q = 0; q < M; ++q) {
@@ -681,15 +733,19 @@ __global__ __launch_bounds__(kBlockThreads) void k_limit(KArgs A, StageBufs sb, 
       const double rest = 1.0 - A.l1[s];
       for (int q = 0; q < M; ++q) Aij[q] = rest * Aij[q];
     }
-    const double li = line_search<D>(A, Li, Aij, sci, rmin, rmax, smin, smin5);
-    double Lj[M], Aji[M];
+    double Lj[M], Pi[M], Pj[M];
+    const double scj = A.kscale[j];
     for (int q = 0; q < M; ++q) {
       Lj[q] = base[q * N + j];
-      Aji[q] = -Aij[q];
+      Pi[q] = sci * Aij[q];
+      Pj[q] = -(scj * Aij[q]);
     }
-    const double sj = A.B[2 * N + j];
-    const double scj = (double)(A.rowlen[j] + 1) / A.ref->mlump[j % NLOC];
-    const double lj = line_search<D>(A, Lj, Aji, scj, A.B[j], A.B[N + j], sj, A.g75 ? pow5(sj) : 0.0);
+    const double rminj = A.B[j], rmaxj = A.B[N + j], sj = A.B[2 * N + j];
+    double li, lj;
+    const bool oki = ls_fast<D>(A, Li, Pi, rmin, rmax, smin, smin5, &li);
+    const bool okj = ls_fast<D>(A, Lj, Pj, rminj, rmaxj, sj, A.g75 ? pow5(sj) : 0.0, &lj);
+    if (!oki) li = ls_slow<D>(A.gamma, Li, Pi, smin, li);
+    if (!okj) lj = ls_slow<D>(A.gamma, Lj, Pj, sj, lj);
     const double l = fmin(li, lj);
     for (int q = 0; q < M; ++q) acc[q] += l * Aij[q];
     if (pass == 0) A.l1[s] = l;
