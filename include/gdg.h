@@ -147,7 +147,11 @@ gdg_status gdg_download_state(gdg_ctx *ctx, double *U, int32_t is_device_ptr);
  * Returns GDG_E_INADMISSIBLE if a stage output left A. */
 gdg_status gdg_step(gdg_ctx *ctx, double dt_cap, double dt_fixed, double *dt_taken);
 
-/* Steps until t = t_final (last step capped) or max_steps steps. */
+/* Steps until t = t_final (last step capped) or max_steps steps.  The time
+ * loop runs on the device: captured HIP graphs of several steps, the host
+ * synchronizing once per graph; a step whose stage 2 or 3 violates the CFL
+ * condition is redone host-driven with the restart rule of gdg_step().  With
+ * kernel timing on (gdg_profile) every step runs host-driven. */
 gdg_status gdg_run_to(gdg_ctx *ctx, double t_final, int64_t max_steps, gdg_stats *stats);
 
 /* One forward-Euler stage U <- Phi(U; tau) of the selected scheme (tau <= 0:

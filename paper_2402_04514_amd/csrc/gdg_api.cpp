@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "gdg.h"
 #include "gdg_internal.h"
@@ -28,9 +29,14 @@ struct gdg_ctx {
   int M;
   // kernel timing (gdg_profile)
   bool prof_on;
+  std::vector<void *> prof_ev;   // events of the host-driven path
+  std::vector<int> prof_kid;
   Prof prof;
   double prof_ms[KID_COUNT];
   int64_t prof_launches[KID_COUNT];
+  // device-driven runs: a captured graph of kGraphSteps steps
+  hipStream_t cap_stream;
+  hipGraphExec_t graph_exec;
 };
 
 namespace {
@@ -154,20 +160,99 @@ gdg_status read_ctl(gdg_ctx *ctx) {
   return GDG_OK;
 }
 
-// Folds the bracketed launches of the synchronized stream into the sums.
-gdg_status harvest(gdg_ctx *ctx) {
-  if (!ctx->prof_on) return GDG_OK;
-  for (int k = 0; k < ctx->prof.n; ++k) {
+// Folds the bracketed launches of a synchronized stream into the sums.
+gdg_status harvest_prof(gdg_ctx *ctx, const Prof &p) {
+  for (int k = 0; k < p.n; ++k) {
     float ms = 0.0f;
-    HIPCHK(ctx, hipEventElapsedTime(&ms, (hipEvent_t)ctx->prof.ev[2 * k], (hipEvent_t)ctx->prof.ev[2 * k + 1]));
-    ctx->prof_ms[ctx->prof.kid[k]] += ms;
-    ctx->prof_launches[ctx->prof.kid[k]] += 1;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, (hipEvent_t)p.ev[2 * k], (hipEvent_t)p.ev[2 * k + 1]));
+    ctx->prof_ms[p.kid[k]] += ms;
+    ctx->prof_launches[p.kid[k]] += 1;
   }
-  ctx->prof.n = 0;
   return GDG_OK;
 }
 
+gdg_status harvest(gdg_ctx *ctx) {
+  if (!ctx->prof_on) return GDG_OK;
+  gdg_status s = harvest_prof(ctx, ctx->prof);
+  ctx->prof.n = 0;
+  return s;
+}
+
 Prof *prof_of(gdg_ctx *ctx) { return ctx->prof_on ? &ctx->prof : nullptr; }
+
+gdg_status make_events(gdg_ctx *ctx, std::vector<void *> &ev, std::vector<int> &kid, int launches, Prof &p) {
+  ev.resize(2 * (size_t)launches);
+  kid.resize((size_t)launches);
+  for (auto &e : ev) {
+    hipEvent_t h;
+    HIPCHK(ctx, hipEventCreate(&h));
+    e = (void *)h;
+  }
+  p.ev = ev.data();
+  p.kid = kid.data();
+  p.cap = launches;
+  p.n = 0;
+  return GDG_OK;
+}
+
+void free_events(std::vector<void *> &ev) {
+  for (void *e : ev) (void)hipEventDestroy((hipEvent_t)e);
+  ev.clear();
+}
+
+void drop_graph(gdg_ctx *ctx) {
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  ctx->graph_exec = nullptr;
+}
+
+// One SSP-RK3 step on a stream: begin, three stages, end.
+int enqueue_step(gdg_ctx *ctx, hipStream_t st, int device_driven, double dt_cap, double tau_fixed, Prof *prof) {
+  const KArgs &A = ctx->A;
+  const int c0 = ctx->cur, c1 = (c0 + 1) % 3, c2 = (c0 + 2) % 3;
+  StageBufs b1 = {ctx->U[c0], ctx->U[c1], ctx->U[c0], 0.0, 1.0};
+  StageBufs b2 = {ctx->U[c1], ctx->U[c2], ctx->U[c0], 0.75, 0.25};
+  StageBufs b3 = {ctx->U[c2], ctx->U[c0], ctx->U[c0], 1.0 / 3.0, 2.0 / 3.0};
+  int rc = launch_begin(A, dt_cap, tau_fixed, device_driven, st);
+  rc |= launch_stage(A, b1, 0, st, prof);
+  rc |= launch_stage(A, b2, 1, st, prof);
+  rc |= launch_stage(A, b3, 2, st, prof);
+  rc |= launch_end(A, st);
+  return rc;
+}
+
+constexpr int kGraphSteps = 8;
+
+// Captures kGraphSteps device-driven steps into a graph (once per context
+// and profiling mode).  Capture runs on a private stream; launches go to the
+// context's stream.
+gdg_status ensure_graph(gdg_ctx *ctx) {
+  if (ctx->graph_exec) return GDG_OK;
+  if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  Prof *pp = nullptr;
+  HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc = 0;
+  for (int k = 0; k < kGraphSteps; ++k) rc |= enqueue_step(ctx, ctx->cap_stream, 1, 0.0, 0.0, pp);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+  if (rc != 0 || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    ctx->err = std::string("graph capture failed: ") + hipGetErrorString(e);
+    return GDG_E_DEVICE;
+  }
+  e = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    ctx->graph_exec = nullptr;
+    ctx->err = std::string("graph instantiation failed: ") + hipGetErrorString(e);
+    return GDG_E_DEVICE;
+  }
+  return GDG_OK;
+}
+
+void sync_time(gdg_ctx *ctx) {
+  ctx->t = ctx->hctl.t;
+  ctx->steps = ctx->hctl.steps;
+}
 
 double bits_to_double(unsigned long long b) {
   double d;
@@ -325,8 +410,9 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
 void gdg_destroy(gdg_ctx *ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
-  if (ctx->prof_on)
-    for (int k = 0; k < 64; ++k) (void)hipEventDestroy((hipEvent_t)ctx->prof.ev[k]);
+  drop_graph(ctx);
+  free_events(ctx->prof_ev);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
 }
 
@@ -358,7 +444,9 @@ gdg_status gdg_upload_state(gdg_ctx *ctx, const double *U, int32_t is_device_ptr
   (void)is_device_ptr;
   const size_t bytes = (size_t)ctx->M * ctx->A.N * sizeof(double);
   HIPCHK(ctx, hipMemcpyAsync(ctx->U[ctx->cur], U, bytes, hipMemcpyDefault, ctx->stream));
-  if (gdg_status s = launched(ctx, launch_begin(ctx->A, 0.0, 0.0, ctx->stream), "begin")) return s;
+  std::memset(&ctx->hctl, 0, sizeof(Ctl));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->A.ctl, &ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
+  if (gdg_status s = launched(ctx, launch_begin(ctx->A, 0.0, 0.0, 0, ctx->stream), "begin")) return s;
   if (gdg_status s = launched(ctx, launch_prim(ctx->A, ctx->U[ctx->cur], ctx->stream), "prim")) return s;
   if (gdg_status s = read_ctl(ctx)) return s;
   ctx->t = 0.0;
@@ -384,17 +472,9 @@ gdg_status gdg_download_state(gdg_ctx *ctx, double *U, int32_t is_device_ptr) {
 gdg_status gdg_step(gdg_ctx *ctx, double dt_cap, double dt_fixed, double *dt_taken) {
   if (!ctx) return GDG_E_INVALID;
   double tau_fixed = dt_fixed > 0.0 ? dt_fixed : 0.0;
-  const int c0 = ctx->cur, c1 = (c0 + 1) % 3, c2 = (c0 + 2) % 3;
   for (int attempt = 0; attempt <= 8; ++attempt) {
-    const KArgs &A = ctx->A;
-    if (gdg_status s = launched(ctx, launch_begin(A, dt_cap, tau_fixed, ctx->stream), "begin")) return s;
-    StageBufs b1 = {ctx->U[c0], ctx->U[c1], ctx->U[c0], 0.0, 1.0};
-    StageBufs b2 = {ctx->U[c1], ctx->U[c2], ctx->U[c0], 0.75, 0.25};
-    StageBufs b3 = {ctx->U[c2], ctx->U[c0], ctx->U[c0], 1.0 / 3.0, 2.0 / 3.0};
-    if (gdg_status s = launched(ctx, launch_stage(A, b1, 0, ctx->stream, prof_of(ctx)), "stage 1")) return s;
-    if (gdg_status s = launched(ctx, launch_stage(A, b2, 1, ctx->stream, prof_of(ctx)), "stage 2")) return s;
-    if (gdg_status s = launched(ctx, launch_stage(A, b3, 2, ctx->stream, prof_of(ctx)), "stage 3")) return s;
-    if (gdg_status s = launched(ctx, launch_end(A, ctx->stream), "end")) return s;
+    if (gdg_status s = launched(ctx, enqueue_step(ctx, ctx->stream, 0, dt_cap, tau_fixed, prof_of(ctx)), "step"))
+      return s;
     if (gdg_status s = read_ctl(ctx)) return s;
     if (gdg_status s = harvest(ctx)) return s;
     const Ctl &h = ctx->hctl;
@@ -409,9 +489,7 @@ gdg_status gdg_step(gdg_ctx *ctx, double dt_cap, double dt_fixed, double *dt_tak
       return GDG_E_INADMISSIBLE;
     }
     ctx->last_dt = h.tau;
-    if (dt_cap > 0.0 && h.tau == dt_cap) ctx->t = ctx->t + dt_cap;
-    else ctx->t += h.tau;
-    ++ctx->steps;
+    sync_time(ctx);
     if (dt_taken) *dt_taken = h.tau;
     return GDG_OK;
   }
@@ -419,15 +497,45 @@ gdg_status gdg_step(gdg_ctx *ctx, double dt_cap, double dt_fixed, double *dt_tak
   return GDG_E_CFL;
 }
 
+// Device-driven time loop: captured graphs of several steps, one host
+// synchronization per graph.  A CFL violation halts the rest of that graph;
+// the step is then redone on the host-driven path with its restart rule.
 gdg_status gdg_run_to(gdg_ctx *ctx, double t_final, int64_t max_steps, gdg_stats *stats) {
   if (!ctx) return GDG_E_INVALID;
-  int64_t n = 0;
-  while (ctx->t < t_final && n < max_steps) {
-    double dt = 0.0, cap = t_final - ctx->t;
-    gdg_status s = gdg_step(ctx, cap, 0.0, &dt);
-    if (s != GDG_OK) return s;
-    if (dt == cap) ctx->t = t_final;
-    ++n;
+  if (max_steps <= 0 || !(ctx->t < t_final)) return gdg_get_stats(ctx, stats);
+  const int64_t limit = ctx->steps + (max_steps > (int64_t(1) << 60) ? (int64_t(1) << 60) : max_steps);
+  if (ctx->prof_on) {
+    // HIP events recorded inside a graph carry no timestamps: with kernel
+    // timing on, the same steps run host-driven.
+    while (ctx->steps < limit && ctx->t < t_final) {
+      double dt = 0.0;
+      if (gdg_status s = gdg_step(ctx, t_final - ctx->t, 0.0, &dt)) return s;
+    }
+    return gdg_get_stats(ctx, stats);
+  }
+  if (gdg_status s = ensure_graph(ctx)) return s;
+  if (gdg_status s = launched(ctx, launch_set_run(ctx->A, t_final, limit, ctx->stream), "set run")) return s;
+  for (;;) {
+    HIPCHK(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
+    if (gdg_status s = read_ctl(ctx)) return s;
+    const Ctl h = ctx->hctl;
+    if (h.bad_flag) {
+      ctx->err = "a stage output left the admissible set";
+      return GDG_E_INADMISSIBLE;
+    }
+    ctx->last_dt = h.tau;
+    sync_time(ctx);
+    if (h.cfl_flag) {
+      const int vs = h.viol_stage < 1 ? 1 : h.viol_stage;
+      const double tau = ctx->prm.cfl * bits_to_double(h.taumin_bits[vs]);
+      ++ctx->restarts;
+      double dt = 0.0;
+      if (gdg_status s = gdg_step(ctx, t_final - ctx->t, tau, &dt)) return s;
+      if (ctx->steps >= limit || !(ctx->t < t_final)) break;
+      if (gdg_status s = launched(ctx, launch_set_run(ctx->A, t_final, limit, ctx->stream), "set run")) return s;
+      continue;
+    }
+    if (h.halt || ctx->steps >= limit || !(ctx->t < t_final)) break;
   }
   return gdg_get_stats(ctx, stats);
 }
@@ -435,7 +543,8 @@ gdg_status gdg_run_to(gdg_ctx *ctx, double t_final, int64_t max_steps, gdg_stats
 gdg_status gdg_stage(gdg_ctx *ctx, double tau, double *tau_used) {
   if (!ctx) return GDG_E_INVALID;
   const int c0 = ctx->cur, c1 = (c0 + 1) % 3;
-  if (gdg_status s = launched(ctx, launch_begin(ctx->A, 0.0, tau > 0.0 ? tau : 0.0, ctx->stream), "begin")) return s;
+  if (gdg_status s = launched(ctx, launch_begin(ctx->A, 0.0, tau > 0.0 ? tau : 0.0, 0, ctx->stream), "begin"))
+    return s;
   StageBufs b = {ctx->U[c0], ctx->U[c1], ctx->U[c0], 0.0, 1.0};
   if (gdg_status s = launched(ctx, launch_stage(ctx->A, b, 0, ctx->stream, prof_of(ctx)), "stage")) return s;
   if (gdg_status s = read_ctl(ctx)) return s;
@@ -445,6 +554,7 @@ gdg_status gdg_stage(gdg_ctx *ctx, double tau, double *tau_used) {
     return GDG_E_INADMISSIBLE;
   }
   ctx->cur = c1;
+  drop_graph(ctx);  // the captured graph names the old buffer roles
   if (tau_used) *tau_used = ctx->hctl.tau;
   return GDG_OK;
 }
@@ -482,17 +592,12 @@ gdg_status gdg_get_stats(const gdg_ctx *ctx, gdg_stats *stats) {
 
 gdg_status gdg_profile(gdg_ctx *ctx, int32_t enable) {
   if (!ctx) return GDG_E_INVALID;
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   if (enable && !ctx->prof_on) {
-    for (int k = 0; k < 64; ++k) {
-      hipEvent_t e;
-      HIPCHK(ctx, hipEventCreate(&e));
-      ctx->prof.ev[k] = (void *)e;
-    }
-    ctx->prof.n = 0;
+    if (gdg_status s = make_events(ctx, ctx->prof_ev, ctx->prof_kid, 32, ctx->prof)) return s;
     ctx->prof_on = true;
   } else if (!enable && ctx->prof_on) {
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    for (int k = 0; k < 64; ++k) (void)hipEventDestroy((hipEvent_t)ctx->prof.ev[k]);
+    free_events(ctx->prof_ev);
     ctx->prof_on = false;
   }
   for (int k = 0; k < KID_COUNT; ++k) {

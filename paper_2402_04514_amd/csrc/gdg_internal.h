@@ -30,22 +30,25 @@ constexpr int kBlockThreads = 256;
 constexpr int kMaxD = 3;
 constexpr int kMaxNloc = 27;
 
-// Per-step control block in device memory.
+// Control block in device memory.  In a device-driven run (captured graphs
+// of several steps) the time loop state lives here too.
 struct Ctl {
   unsigned long long taumin_bits[3]; // per stage: min_i m_i / (2 |d_ii|) as IEEE bits
   double tau;                        // tau of the current step
   double dt_cap;                     // cap on tau (<= 0: none)
   double tau_fixed;                  // > 0: replaces the CFL rule in stage 1
   double t;                          // simulated time
-  long long steps;
+  double t_final;                    // device-driven runs: end time
+  long long steps;                   // steps completed
+  long long step_limit;              // device-driven runs: stop after this many steps
   // Set when stage 2 or 3 finds tau above its CFL bound.  Every block of the
   // detecting kernel reaches the same decision from the same data, and later
   // kernels read it only at their start, so exits stay uniform.
   int cfl_flag;
   int bad_flag;                      // a state left A; read by the host only
   int viol_stage;
+  int halt;                          // set by the step's first kernel: skip this step
 };
-
 // Reference tables of one cell class (every cell of a uniform mesh).
 struct RefTables {
   double mlump[kMaxNloc];                   // m_a
@@ -101,18 +104,20 @@ struct StageBufs {
   double ca, cb;      // out = ca * Un + cb * Phi(in)
 };
 // Optional kernel timing: when a Prof is passed, each launch is bracketed by
-// HIP events on the same stream; the host folds them into per-kernel sums
-// after the stream has synchronized.
+// HIP events on the same stream (also inside a captured graph); the host folds
+// them into per-kernel sums after the stream has synchronized.
 enum { KID_PRIM = 0, KID_SWEEP1, KID_SWEEP2, KID_LIMIT1, KID_LIMIT2, KID_COUNT };
 struct Prof {
-  void *ev[64];   // hipEvent_t, created by the host
-  int kid[32];    // kernel id of each bracketed launch
+  void **ev;      // hipEvent_t pairs, created by the host
+  int *kid;       // kernel id of each bracketed launch
+  int cap;        // capacity in launches
   int n;          // bracketed launches since the last harvest
 };
 bool build_ref_tables(int dim, int deg, const double *h, RefTables *T, std::string *err);
 int launch_fill(const KArgs &A, void *stream);
-int launch_begin(const KArgs &A, double dt_cap, double tau_fixed, void *stream);
+int launch_begin(const KArgs &A, double dt_cap, double tau_fixed, int device_driven, void *stream);
 int launch_end(const KArgs &A, void *stream);
+int launch_set_run(const KArgs &A, double t_final, long long step_limit, void *stream);
 int launch_prim(const KArgs &A, const double *U, void *stream);
 int launch_stage(const KArgs &A, const StageBufs &b, int stage, void *stream, Prof *prof);
 

@@ -290,22 +290,40 @@ __global__ __launch_bounds__(kBlockThreads) void k_fill(KArgs A) {
   while (t < A.W) put((int32_t)(i < A.N ? i : 0), nullptr, SK_PAD);
 }
 
-__global__ void k_begin(Ctl *ctl, double dt_cap, double tau_fixed) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    for (int s = 0; s < 3; ++s) ctl->taumin_bits[s] = 0x7ff0000000000000ull;  // +inf
-    ctl->cfl_flag = 0;
-    ctl->bad_flag = 0;
-    ctl->viol_stage = -1;
-    ctl->dt_cap = dt_cap;
-    ctl->tau_fixed = tau_fixed;
+// First kernel of a step.  Host-driven: the host passes the cap and a fixed
+// tau and has cleared the flags' causes.  Device-driven (graphs): the cap is
+// t_final - t, and a finished run, a step limit or a flag left by an earlier
+// step of the graph halts the step.
+__global__ void k_begin(Ctl *ctl, double dt_cap, double tau_fixed, int device_driven) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (device_driven) {
+    if (ctl->cfl_flag || ctl->bad_flag || ctl->halt || !(ctl->t < ctl->t_final) ||
+        ctl->steps >= ctl->step_limit) {
+      ctl->halt = 1;
+      return;
+    }
+    dt_cap = ctl->t_final - ctl->t;
+    tau_fixed = 0.0;
+  } else {
+    ctl->t_final = dt_cap > 0.0 ? ctl->t + dt_cap : 0.0;
   }
+  for (int s = 0; s < 3; ++s) ctl->taumin_bits[s] = 0x7ff0000000000000ull;  // +inf
+  ctl->cfl_flag = 0;
+  ctl->bad_flag = 0;
+  ctl->halt = 0;
+  ctl->viol_stage = -1;
+  ctl->dt_cap = dt_cap;
+  ctl->tau_fixed = tau_fixed;
 }
 
+// Last kernel of a step: advance t (exactly to the cap's end on a capped step).
 __global__ void k_end(Ctl *ctl) {
-  if (threadIdx.x == 0 && blockIdx.x == 0 && ctl->cfl_flag == 0 && ctl->bad_flag == 0) {
-    ctl->t += ctl->tau;
-    ctl->steps += 1;
-  }
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (ctl->halt || ctl->cfl_flag || ctl->bad_flag) return;
+  const bool capped = ctl->dt_cap > 0.0 && ctl->tau == ctl->dt_cap;
+  ctl->t = capped ? ctl->t + ctl->dt_cap : ctl->t + ctl->tau;
+  if (capped && ctl->t_final > 0.0 && ctl->t_final - ctl->t < 1e-14 * ctl->t_final) ctl->t = ctl->t_final;
+  ctl->steps += 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -381,7 +399,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(G
   constexpr int M = D + 2;
   constexpr int NB = DEG + 1;
   constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
-  if (A.ctl->cfl_flag) return;  // set by an earlier kernel or never
+  if (A.ctl->halt || A.ctl->cfl_flag) return;  // set by an earlier kernel or never
   const int lane = threadIdx.x;
   const int64_t blk = xcd_block(blockIdx.x, A.nblocks);
   const int64_t i = blk * A.R + lane;
@@ -506,7 +524,7 @@ __device__ __forceinline__ double visc_high(const KArgs &A, double d, double Ni,
 // ---------------------------------------------------------------------------
 // Resolves tau of this stage; returns false (uniformly) if the stage must stop.
 __device__ __forceinline__ bool stage_tau(const KArgs &A, int stage, double *tau) {
-  if (A.ctl->cfl_flag) return false;
+  if (A.ctl->halt || A.ctl->cfl_flag) return false;
   const double tm = __longlong_as_double((long long)A.ctl->taumin_bits[stage]);
   if (stage == 0) {
     double t = A.ctl->tau_fixed > 0.0 ? A.ctl->tau_fixed : A.cfl * tm;
@@ -526,7 +544,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(G
   __shared__ double rs[M][kBlockThreads];
   double tau;
   if (!stage_tau(A, stage, &tau)) {
-    if (stage > 0 && blockIdx.x == 0 && threadIdx.x == 0 && A.ctl->cfl_flag == 0) {
+    if (stage > 0 && blockIdx.x == 0 && threadIdx.x == 0 && A.ctl->cfl_flag == 0 && A.ctl->halt == 0) {
       A.ctl->viol_stage = stage;
       atomicOr(&A.ctl->cfl_flag, 1);
     }
@@ -689,7 +707,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(G
   constexpr int M = D + 2;
   constexpr int NB = DEG + 1;
   constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
-  if (A.ctl->cfl_flag) return;
+  if (A.ctl->halt || A.ctl->cfl_flag) return;
   const int lane = threadIdx.x;
   const int64_t blk = xcd_block(blockIdx.x, A.nblocks);
   const int64_t i = blk * A.R + lane;
@@ -775,7 +793,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(G
 static inline hipStream_t S(void *s) { return (hipStream_t)s; }
 
 static inline void prof_mark(Prof *p, int kid, int end, void *stream) {
-  if (!p || p->n >= 32) return;
+  if (!p || p->n >= p->cap) return;
   hipEventRecord((hipEvent_t)p->ev[2 * p->n + end], S(stream));
   if (end) {
     p->kid[p->n] = kid;
@@ -833,9 +851,25 @@ int launch_stage(const KArgs &A, const StageBufs &b, int stage, void *stream, Pr
 
 int launch_fill(const KArgs &A, void *stream) { GDG_DISPATCH(fill_impl, A, stream) }
 
-int launch_begin(const KArgs &A, double dt_cap, double tau_fixed, void *stream) {
+int launch_begin(const KArgs &A, double dt_cap, double tau_fixed, int device_driven, void *stream) {
   clear_stale();
-  hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, S(stream), A.ctl, dt_cap, tau_fixed);
+  hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, S(stream), A.ctl, dt_cap, tau_fixed, device_driven);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// Start of a device-driven run: end time, step limit, cleared flags.
+__global__ void k_set_run(Ctl *ctl, double t_final, long long step_limit) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  ctl->t_final = t_final;
+  ctl->step_limit = step_limit;
+  ctl->halt = 0;
+  ctl->cfl_flag = 0;
+  ctl->bad_flag = 0;
+}
+
+int launch_set_run(const KArgs &A, double t_final, long long step_limit, void *stream) {
+  clear_stale();
+  hipLaunchKernelGGL(k_set_run, dim3(1), dim3(64), 0, S(stream), A.ctl, t_final, step_limit);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -254,3 +254,36 @@ def test_invariants_quadrant_q2(oracle):
     st = (V[3] - 0.5 * (V[1] ** 2 + V[2] ** 2) / V[0]) * V[0] ** -1.4
     assert np.all(V[0] >= B[0] * (1 - 1e-12)) and np.all(V[0] <= B[1] * (1 + 1e-12))
     assert np.all(st >= B[2] * (1 - 1e-11))
+
+
+def test_graph_run_matches_eager_steps(oracle):
+    """run_to (captured graphs of several steps, one host sync per graph) gives
+    bit-identical states to host-driven single steps, across graph replays
+    with host work and eager steps in between."""
+    ms, U = quadrant_on(2, 2, (10, 9), (1, 1, 2, 2), seed=31)
+    A = gdg.Solver.from_spec(ms)
+    B = gdg.Solver.from_spec(ms)
+    A.upload(U)
+    B.upload(U)
+    for rep in range(3):            # 3 x 11 steps: full and partial graphs
+        for _ in range(11):
+            A.step()
+        st = B.run_to(1e9, max_steps=11)
+        assert st.steps == 11 * (rep + 1) + rep  # plus the eager steps in between
+        a, b = A.download(), B.download()
+        assert np.array_equal(a, b), rep
+        B.step()                    # an eager step between replays
+        A.step()
+    assert np.array_equal(A.download(), B.download())
+    assert A.stats().t == B.stats().t
+
+
+def test_graph_run_to_final_time(oracle):
+    """run_to a final time through graphs: the last step is capped and t lands
+    on t_final; the state matches the oracle's run to the same time."""
+    ms, U, M, S, op = _pair(oracle, "q1_2d_mixed")
+    tf = 0.0123
+    Uo, t_o, n_o = M.run_to(op, U, tf)
+    st = S.run_to(tf)
+    assert st.t == tf and st.steps == n_o
+    _close(S.download(), Uo, tol=1e-10, what="U(t_final)")
