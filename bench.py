@@ -88,7 +88,7 @@ def stencil_slots(ms) -> tuple[float, float]:
     return nb ** d + tot, 0.0
 
 
-def run_gpu(name, steps, warmup):
+def run_gpu(name, steps, warmup, host_driven=False):
     import numpy as np
     import torch
 
@@ -99,6 +99,8 @@ def run_gpu(name, steps, warmup):
     wl = W.CONFIGS[name](**kw)
     S = gdg.Solver.from_spec(wl.mesh, device="cuda:0")
     S.upload(wl.U0)
+    if host_driven:   # every step host-driven, no graph (for counter collection)
+        gdg.gdg_profile(S.ctx, True)
     if warmup:
         S.run_to(1e30, max_steps=warmup)   # also captures the step graph
     torch.cuda.synchronize()
@@ -167,6 +169,8 @@ def main():
     ap.add_argument("--workload", default="vortex", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--host-driven", action="store_true",
+                    help="run every step host-driven (no captured graphs), e.g. under counter collection")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -179,7 +183,7 @@ def main():
     steps = args.steps if args.steps is not None else dsteps
     warmup = args.warmup if args.warmup is not None else dwarm
 
-    wl, desc, ndofs, secs, prof, admissible, stats = run_gpu(args.workload, steps, warmup)
+    wl, desc, ndofs, secs, prof, admissible, stats = run_gpu(args.workload, steps, warmup, args.host_driven)
     value = ndofs * 3 * steps / secs
     slots, _ = stencil_slots(wl.mesh)
     prof_steps, prof_ms_step = prof.pop("_region")
@@ -192,8 +196,8 @@ def main():
     tf = os.path.join(ROOT, "profiles", "traffic_%s.json" % args.workload)
     if os.path.exists(tf):
         rec = json.load(open(tf))
-        if rec.get("kernel_source_hash") == kernel_source_hash() and rec.get("kernel") == dom:
-            traffic = rec.get("bytes_per_launch")
+        if rec.get("kernel_source_hash") == kernel_source_hash() and dom in rec.get("kernels", {}):
+            traffic = rec["kernels"][dom]["bytes_per_launch"]
     if args.calib_copy_gib > 0:
         import torch
         n = int(args.calib_copy_gib * (1 << 30)) // 8
