@@ -88,7 +88,13 @@ def stencil_slots(ms) -> tuple[float, float]:
     return nb ** d + tot, 0.0
 
 
-def run_gpu(name, steps, warmup, host_driven=False):
+def _params(gdg, degree, precision):
+    p = gdg.gdg_default_params(degree)
+    p.precision = precision
+    return p
+
+
+def run_gpu(name, steps, warmup, host_driven=False, precision=0):
     import numpy as np
     import torch
 
@@ -97,7 +103,7 @@ def run_gpu(name, steps, warmup, host_driven=False):
 
     kw, desc, _, _ = WORKLOADS[name]
     wl = W.CONFIGS[name](**kw)
-    S = gdg.Solver.from_spec(wl.mesh, device="cuda:0")
+    S = gdg.Solver.from_spec(wl.mesh, _params(gdg, wl.mesh.degree, precision), device="cuda:0")
     S.upload(wl.U0)
     if host_driven:   # every step host-driven, no graph (for counter collection)
         gdg.gdg_profile(S.ctx, True)
@@ -126,6 +132,60 @@ def run_gpu(name, steps, warmup, host_driven=False):
     eps = out[dim + 1] - 0.5 * np.sum(out[1:dim + 1] ** 2, 0) / out[0]
     admissible = bool(np.all(out[0] > 0) and np.all(eps > 0))
     return wl, desc, S.ndofs, t1 - t0, prof, admissible, S.stats()
+
+
+def mixed_vs_fp64(name, steps):
+    """Mixed-precision against FP64 on the GPU at equal time levels: the FP64
+    path takes `steps` CFL steps (host-driven, recording tau), the mixed path
+    replays the same taus.  Reported per component and in the paper's
+    consolidated norm (relative density + relative momentum, Euclidean per
+    node, + relative energy error, all L1 with the lumped masses, which are
+    equal per local node on a uniform mesh).  Beside it, the same measure for
+    the FP64 path fed the input with a 1e-13 relative density perturbation:
+    how far rounding-level differences grow on this workload by themselves."""
+    import numpy as np
+
+    from paper_2402_04514_amd import gdg
+    from paper_2402_04514_amd import workloads as W
+
+    kw = WORKLOADS[name][0]
+    wl = W.CONFIGS[name](**kw)
+    dim = wl.mesh.dim
+
+    def solver(prec, U):
+        S = gdg.Solver.from_spec(wl.mesh, _params(gdg, wl.mesh.degree, prec), device="cuda:0")
+        S.upload(U)
+        return S
+
+    def norms(a, b):
+        num = np.abs(a - b).sum(1)
+        den = np.abs(b).sum(1)
+        comp = num / np.maximum(den, 1e-300)
+        mom = np.sqrt(((a[1:dim + 1] - b[1:dim + 1]) ** 2).sum(0)).sum() / max(
+            np.sqrt((b[1:dim + 1] ** 2).sum(0)).sum(), 1e-300)
+        return [float(x) for x in comp], float(comp[0] + mom + comp[dim + 1])
+
+    S = solver(gdg.GDG_FP64, wl.U0)
+    dts = [S.step() for _ in range(steps)]
+    ref = S.download()
+    S.close()
+    M = solver(gdg.GDG_MIXED, wl.U0)
+    for dt in dts:
+        M.step(dt_fixed=dt)
+    mix = M.download()
+    M.close()
+    rng = np.random.default_rng(2402)
+    Up = wl.U0.copy()
+    Up[0] *= 1.0 + 1e-13 * rng.standard_normal(Up.shape[1])
+    P = solver(gdg.GDG_FP64, Up)
+    for dt in dts:
+        P.step(dt_fixed=dt)
+    per = P.download()
+    P.close()
+    comp, cons = norms(mix, ref)
+    pcomp, pcons = norms(per, ref)
+    return {"steps": steps, "t": float(sum(dts)), "l1_rel_per_component": comp, "l1_consolidated": cons,
+            "fp64_perturbed_1e-13": {"l1_rel_per_component": pcomp, "l1_consolidated": pcons}}
 
 
 def cpu_baseline(name, budget_s):
@@ -169,6 +229,7 @@ def main():
     ap.add_argument("--workload", default="vortex", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision line")
     ap.add_argument("--host-driven", action="store_true",
                     help="run every step host-driven (no captured graphs), e.g. under counter collection")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
@@ -230,6 +291,17 @@ def main():
                                "steps right after the timed region (%.3f ms/step)" % (prof_steps, prof_ms_step)},
         "kernels_ms_per_launch": {k: (v[0] / v[1] if v[1] else None) for k, v in prof.items()},
     }
+    if not args.no_mixed:
+        from paper_2402_04514_amd import gdg
+        _, _, _, msecs, mprof, madm, _ = run_gpu(args.workload, steps, warmup, args.host_driven, gdg.GDG_MIXED)
+        cmp = mixed_vs_fp64(args.workload, min(steps, 50))
+        line["mixed"] = {"value": ndofs * 3 * steps / msecs, "unit": "dof-stage updates/s",
+                         "ms_per_step": msecs / steps * 1e3, "admissible_after": madm,
+                         "precision": "c_ij, flux and entropy-viscosity sums FP32; state, d_ij, bounds, "
+                                      "line search FP64",
+                         "kernels_ms_per_launch": {k: (v[0] / v[1] if v[1] else None)
+                                                   for k, v in mprof.items() if not k.startswith("_")},
+                         "vs_fp64_gpu": cmp}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -57,8 +57,18 @@ typedef enum { GDG_BC_PERIODIC = 0, GDG_BC_OUTFLOW = 1, GDG_BC_SLIP = 2 } gdg_bc
  * eq. local_bounds (the paper's method). */
 typedef enum { GDG_LOW_ORDER = 0, GDG_HIGH_ORDER = 1, GDG_LIMITED = 2 } gdg_scheme;
 
-/* GDG_FP64: every operation in double precision. */
-typedef enum { GDG_FP64 = 0 } gdg_precision;
+/* GDG_FP64: every operation in double precision.
+ * GDG_MIXED: the stencil coefficients c_ij are stored in single precision and
+ * the flux sums sum_j (f(U_j) - f(U_i)) c_ij of the low- and high-order
+ * updates (each flux difference by the product rule from the state
+ * differences rounded to single precision) and the sums of the entropy
+ * residual (Sec. 5.2) are taken in single precision with single-precision
+ * accumulation; the state and its updates,
+ * the wave-speed bound and d_ij (eq. dij_low_order), the bar states and local
+ * bounds (eq. local_bounds) and the limiter line search (Sec. 5.4) stay in
+ * double precision, so every stage output is still checked against A.  The
+ * boundary parts use the double-precision flux that their bar state needs. */
+typedef enum { GDG_FP64 = 0, GDG_MIXED = 1 } gdg_precision;
 
 /* Uniform Cartesian mesh of cells[0] x cells[1] x cells[2] cells over the box
  * [lo, hi] (only the first dim entries are read), Q_degree elements with

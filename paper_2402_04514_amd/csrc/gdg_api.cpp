@@ -96,11 +96,11 @@ bool validate(const gdg_mesh_desc *m, const gdg_params *p, std::string *err) {
   }
   if (p->limiter_passes < 0 || p->limiter_passes > 2) { *err = "limiter_passes must be 0, 1 or 2"; return false; }
   if (p->scheme < 0 || p->scheme > 2) { *err = "unknown scheme"; return false; }
-  if (p->precision != GDG_FP64) { *err = "unknown precision"; return false; }
+  if (p->precision != GDG_FP64 && p->precision != GDG_MIXED) { *err = "unknown precision"; return false; }
   return true;
 }
 
-Layout layout(const gdg_mesh_desc *m) {
+Layout layout(const gdg_mesh_desc *m, const gdg_params *p) {
   Layout L;
   L.nb1 = m->degree + 1;
   L.nloc = 1;
@@ -122,7 +122,7 @@ Layout layout(const gdg_mesh_desc *m) {
   L.off_ref = take(sizeof(RefTables));
   L.off_ctl = take(sizeof(Ctl));
   L.off_col = take(S * 4);
-  L.off_c = take(S * d * 8);
+  L.off_c = take(S * d * (p->precision == GDG_MIXED ? 4 : 8));
   L.off_meta = take(S);
   L.off_kscale = take(N * 8);
   for (int k = 0; k < 3; ++k) L.off_U[k] = take(M * N * 8);
@@ -282,7 +282,7 @@ gdg_status gdg_default_params(int32_t degree, gdg_params *out) {
 gdg_status gdg_workspace_bytes(const gdg_mesh_desc *mesh, const gdg_params *prm, size_t *bytes) {
   std::string err;
   if (!bytes || !validate(mesh, prm, &err)) return GDG_E_INVALID;
-  *bytes = layout(mesh).total;
+  *bytes = layout(mesh, prm).total;
   return GDG_OK;
 }
 
@@ -293,7 +293,7 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   *out = nullptr;
   std::string err;
   if (!validate(mesh, prm, &err)) { g_create_err = err; return GDG_E_INVALID; }
-  Layout L = layout(mesh);
+  Layout L = layout(mesh, prm);
   if (!dev_workspace || ws_bytes < L.total) {
     g_create_err = "workspace smaller than gdg_workspace_bytes()";
     return GDG_E_NOMEM;
@@ -347,7 +347,9 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   ctx->dref = (RefTables *)(ws + L.off_ref);
   A.ctl = (Ctl *)(ws + L.off_ctl);
   A.col = (int32_t *)(ws + L.off_col);
-  A.c = (double *)(ws + L.off_c);
+  A.mixed = prm->precision == GDG_MIXED ? 1 : 0;
+  A.c = A.mixed ? nullptr : (double *)(ws + L.off_c);
+  A.cf = A.mixed ? (float *)(ws + L.off_c) : nullptr;
   A.meta = (uint8_t *)(ws + L.off_meta);
   A.kscale = (double *)(ws + L.off_kscale);
   for (int k = 0; k < 3; ++k) ctx->U[k] = (double *)(ws + L.off_U[k]);

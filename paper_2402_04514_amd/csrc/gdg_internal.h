@@ -26,7 +26,13 @@ enum : uint8_t {
 static inline int meta_kind(uint8_t m) { return m & 7; }
 static inline int meta_aux(uint8_t m) { return m >> 3; }
 
-constexpr int kBlockThreads = 256;
+// One wavefront per workgroup: whole cells per block (the cell solve stays in
+// LDS), and a finished wave's slot is refilled at once, which matters where
+// the line searches of shock regions make the work per row uneven.
+#ifndef GDG_BLOCK
+#define GDG_BLOCK 64
+#endif
+constexpr int kBlockThreads = GDG_BLOCK;
 constexpr int kMaxD = 3;
 constexpr int kMaxNloc = 27;
 
@@ -78,9 +84,11 @@ struct KArgs {
   int32_t ipow;     // > 0: 1/alpha equals this integer, the p* power is taken by multiplies
   int32_t g75;      // gamma == 7/5: entropy comparisons by integer powers
   int32_t scheme, passes;
+  int32_t mixed;    // 1: c_ij stored in FP32 and the flux / entropy-viscosity sums taken in FP32
   // stencil
   int32_t *col;
-  double *c;        // dim planes of nslots
+  double *c;        // dim planes of nslots (FP64 precision)
+  float *cf;        // dim planes of nslots (mixed precision)
   uint8_t *meta;
   double *kscale;   // 1 / (kappa_i m_i) per row, kappa_i = 1/(card I(i) + 1)
   const RefTables *ref;

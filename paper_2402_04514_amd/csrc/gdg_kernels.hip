@@ -70,15 +70,37 @@ __device__ __forceinline__ double lambda_plus(const KArgs &A, double ul, double 
 // Contraction stays off here: f(U_j) c - f(U_i) c must be exactly zero for
 // equal states (x*y - x*y under a fused multiply-add leaves the rounding
 // error of x*y), so constant states give R_i = D_i = 0 and no flux.
-template <int D>
-__device__ __forceinline__ void flux_dot(const double *U, const double *u, double p, const double *c,
-                                         double *out) {
+template <int D, typename T>
+__device__ __forceinline__ void flux_dot(const T *U, const T *u, T p, const T *c, T *out) {
 #pragma clang fp contract(off)
-  double uc = 0.0;
+  T uc = 0;
   for (int e = 0; e < D; ++e) uc += u[e] * c[e];
   out[0] = U[0] * uc;
   for (int e = 0; e < D; ++e) out[1 + e] = U[1 + e] * uc + p * c[e];
   out[D + 1] = (U[D + 1] + p) * uc;
+}
+
+// (f(U_j) - f(U_i)) c in FP32 by the product rule,
+//   d(m u^T) = dm u_j^T + m_i du^T,  d((E + p) u) = d(E + p) u_j + (E_i + p_i) du,
+// from the FP64 differences dU, du, dp rounded once to FP32.  Its error is
+// relative to the difference (not to the flux), and equal states give exact
+// zeros.
+template <int D>
+__device__ __forceinline__ void flux_diff32(const double *Uj, const double *uj, double pj, const double *Ui,
+                                            const double *ui, double pi, const float *c, float *out) {
+  float dU[D + 2], du[D];
+  for (int q = 0; q < D + 2; ++q) dU[q] = (float)(Uj[q] - Ui[q]);
+  for (int e = 0; e < D; ++e) du[e] = (float)(uj[e] - ui[e]);
+  const float dp = (float)(pj - pi);
+  float ucj = 0.0f, duc = 0.0f, dmc = 0.0f;
+  for (int e = 0; e < D; ++e) {
+    ucj += (float)uj[e] * c[e];
+    duc += du[e] * c[e];
+    dmc += dU[1 + e] * c[e];
+  }
+  out[0] = dmc;
+  for (int e = 0; e < D; ++e) out[1 + e] = dU[1 + e] * ucj + (float)Ui[1 + e] * duc + dp * c[e];
+  out[D + 1] = (dU[D + 1] + dp) * ucj + (float)(Ui[D + 1] + pi) * duc;
 }
 
 template <int D>
@@ -86,6 +108,19 @@ __device__ __forceinline__ double eps_of(const double *V) {
   double m2 = 0.0;
   for (int e = 0; e < D; ++e) m2 += V[1 + e] * V[1 + e];
   return V[D + 1] - 0.5 * m2 / V[0];
+}
+
+// Accumulator type of the flux and entropy-viscosity sums: FP32 in the mixed
+// precision variant, FP64 otherwise.
+template <bool MX>
+struct AccT { using type = double; };
+template <>
+struct AccT<true> { using type = float; };
+
+// c_ij of slot s, widened to FP64 (FP32 storage in the mixed variant)
+template <int D, bool MX>
+__device__ __forceinline__ void load_c(const KArgs &A, int64_t s, double *c) {
+  for (int e = 0; e < D; ++e) c[e] = MX ? (double)A.cf[e * A.nslots + s] : A.c[e * A.nslots + s];
 }
 
 // ---------------------------------------------------------------------------
@@ -246,7 +281,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_fill(KArgs A) {
   auto put = [&](int32_t col, const double *c, uint8_t meta) {
     int64_t s = (blk * A.W + t) * A.R + lane;
     A.col[s] = col;
-    for (int e = 0; e < D; ++e) A.c[e * A.nslots + s] = c ? c[e] : 0.0;
+    for (int e = 0; e < D; ++e) {
+      if (A.mixed) A.cf[e * A.nslots + s] = c ? (float)c[e] : 0.0f;
+      else A.c[e * A.nslots + s] = c ? c[e] : 0.0;
+    }
     A.meta[s] = meta;
     ++t;
   };
@@ -393,9 +431,10 @@ __device__ __forceinline__ double block_min_atomic(double v, unsigned long long 
 }
 
 // ---------------------------------------------------------------------------
-template <int D, int DEG>
+template <int D, int DEG, bool MX>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_SWEEP))) void k_sweep1(KArgs A, const double *__restrict__ U,
                                                           int stage) {
+  using Acc = typename AccT<MX>::type;
   constexpr int M = D + 2;
   constexpr int NB = DEG + 1;
   constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
@@ -421,8 +460,11 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(G
       double sc = ni.U[0] * ni.fs / (g + 1.0);
       for (int c = 0; c < M; ++c) grad[c] *= sc;
     }
-    double T = 0.0, S[M];
-    for (int c = 0; c < M; ++c) S[c] = 0.0;
+    // entropy-residual sums (Sec. 5.2): FP32 with FP32 accumulation in the
+    // mixed variant; the flux differences come from the FP64 evaluation that
+    // the bar states need
+    Acc T = 0, S[M];
+    for (int c = 0; c < M; ++c) S[c] = 0;
     double dsum = 0.0;
     double rmin = INFINITY, rmax = -INFINITY, smin = INFINITY;
     // bar state with the smallest rescaled entropy, ranked by stilde_key
@@ -433,7 +475,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(G
       const int kind = meta & 7;
       if (kind == SK_PAD) { A.dL[s] = 0.0; continue; }
       double c[D];
-      for (int e = 0; e < D; ++e) c[e] = A.c[e * A.nslots + s];
+      load_c<D, MX>(A, s, c);
       double nc2 = 0.0;
       for (int e = 0; e < D; ++e) nc2 += c[e] * c[e];
       const double nc = sqrt(nc2);
@@ -451,10 +493,10 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(G
         double fj[M], fi[M];
         flux_dot<D>(gh.U, gh.u, gh.p, c, fj);
         flux_dot<D>(ni.U, ni.u, ni.p, c, fi);
-        double mc = 0.0;
-        for (int e = 0; e < D; ++e) mc += gh.U[1 + e] * c[e];
-        T += mc * (gh.fs - ni.fs);
-        for (int q = 0; q < M; ++q) S[q] += fj[q] - fi[q];
+        Acc mc = 0;
+        for (int e = 0; e < D; ++e) mc += (Acc)gh.U[1 + e] * (Acc)c[e];
+        T += mc * (Acc)(gh.fs - ni.fs);
+        for (int q = 0; q < M; ++q) S[q] += (Acc)(fj[q] - fi[q]);
         continue;
       }
       const int64_t j = A.col[s];
@@ -482,14 +524,14 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(G
       double fj[M], fi[M];
       flux_dot<D>(nj.U, nj.u, nj.p, c, fj);
       flux_dot<D>(ni.U, ni.u, ni.p, c, fi);
-      double mc = 0.0;
-      for (int e = 0; e < D; ++e) mc += nj.U[1 + e] * c[e];
-      T += mc * (nj.fs - ni.fs);
+      Acc mc = 0;
+      for (int e = 0; e < D; ++e) mc += (Acc)nj.U[1 + e] * (Acc)c[e];
+      T += mc * (Acc)(nj.fs - ni.fs);
       double bar[M];
       const double h2d = 0.5 / d;
       for (int q = 0; q < M; ++q) {
         double df = fj[q] - fi[q];
-        S[q] += df;
+        S[q] += (Acc)df;
         bar[q] = 0.5 * (ni.U[q] + nj.U[q]) - df * h2d;
       }
       rmin = fmin(rmin, bar[0]);
@@ -501,9 +543,13 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(G
       if (kb < kbar) { kbar = kb; ebar = rb; rbar = bar[0]; }
     }
     if (kbar < INFINITY) smin = fmin(smin, ebar / rbar * pow(rbar, -g));
-    double R = T, Dn = fabs(T);
-    for (int q = 0; q < M; ++q) { R -= grad[q] * S[q]; Dn += fabs(grad[q]) * fabs(S[q]); }
-    A.Nev[i] = Dn > 0.0 ? R / Dn : 0.0;
+    Acc R = T, Dn = fabs(T);
+    for (int q = 0; q < M; ++q) {
+      const Acc gq = (Acc)grad[q];
+      R -= gq * S[q];
+      Dn += fabs(gq) * fabs(S[q]);
+    }
+    A.Nev[i] = Dn > 0 ? (double)(R / Dn) : 0.0;
     A.q[i] = rmin;
     A.q[A.N + i] = rmax;
     A.q[2 * A.N + i] = smin;
@@ -536,8 +582,9 @@ __device__ __forceinline__ bool stage_tau(const KArgs &A, int stage, double *tau
   return !(*tau > tm);
 }
 
-template <int D, int DEG>
+template <int D, int DEG, bool MX>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_SWEEP))) void k_sweep2(KArgs A, StageBufs sb, int stage) {
+  using Acc = typename AccT<MX>::type;
   constexpr int M = D + 2;
   constexpr int NB = DEG + 1;
   constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
@@ -566,8 +613,11 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(G
     const double Ni = A.Nev[i];
     const double hpk = A.ref->hpk[a];
     const double mi = A.ref->mlump[a];
+    // accL / accH: the viscous terms (and, in FP64, the flux sums); accF: the
+    // graph flux sum sum_j (f(U_j) - f(U_i)) c_ij in the mixed variant (FP32)
     double accL[M], accH[M];
-    for (int c = 0; c < M; ++c) accL[c] = accH[c] = 0.0;
+    Acc accF[M];
+    for (int c = 0; c < M; ++c) { accL[c] = accH[c] = 0.0; accF[c] = 0; }
     double rmin = INFINITY, rmax = -INFINITY, smin = INFINITY;
     for (int t = 0; t < A.W; ++t) {
       const int64_t s = (blk * A.W + t) * A.R + lane;
@@ -575,7 +625,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(G
       const int kind = meta & 7;
       if (kind == SK_PAD) continue;
       double c[D];
-      for (int e = 0; e < D; ++e) c[e] = A.c[e * A.nslots + s];
+      load_c<D, MX>(A, s, c);
       const double d = A.dL[s];
       if (kind == SK_GHOST) {
         double nc2 = 0.0;
@@ -613,17 +663,34 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(G
       for (int q = 0; q < M; ++q) Uj[q] = U[q * N + j];
       for (int e = 0; e < D; ++e) uj[e] = A.Wc[e * N + j];
       const double pj = A.Wc[D * N + j];
-      double fj[M], fi[M];
-      flux_dot<D>(Uj, uj, pj, c, fj);
-      flux_dot<D>(ni.U, ni.u, ni.p, c, fi);
       const double dH = visc_high(A, d, Ni, A.Nev[j], kind, hpk);
-      for (int q = 0; q < M; ++q) {
-        double df = fj[q] - fi[q];
-        double du = Uj[q] - ni.U[q];
-        accL[q] += df - d * du;
-        accH[q] += df - dH * du;
+      if (MX) {
+        float c32[D], df[M];
+        for (int e = 0; e < D; ++e) c32[e] = (float)c[e];
+        flux_diff32<D>(Uj, uj, pj, ni.U, ni.u, ni.p, c32, df);
+        for (int q = 0; q < M; ++q) {
+          const double du = Uj[q] - ni.U[q];
+          accF[q] += (Acc)df[q];
+          accL[q] -= d * du;
+          accH[q] -= dH * du;
+        }
+      } else {
+        double fj[M], fi[M];
+        flux_dot<D>(Uj, uj, pj, c, fj);
+        flux_dot<D>(ni.U, ni.u, ni.p, c, fi);
+        for (int q = 0; q < M; ++q) {
+          double df = fj[q] - fi[q];
+          double du = Uj[q] - ni.U[q];
+          accL[q] += df - d * du;
+          accH[q] += df - dH * du;
+        }
       }
     }
+    if (MX)
+      for (int q = 0; q < M; ++q) {
+        accL[q] += (double)accF[q];
+        accH[q] += (double)accF[q];
+      }
     // eq. cijdijschememodified in the difference form
     double UL[M];
     for (int q = 0; q < M; ++q) {
@@ -682,7 +749,10 @@ template <int D>
 __device__ __forceinline__ void ghost_flux(const KArgs &A, int64_t s, uint8_t meta, const double *Ui, double Ni,
                                            double hpk, double tau, double d, double *Ab) {
   double c[D], nc2 = 0.0;
-  for (int e = 0; e < D; ++e) { c[e] = A.c[e * A.nslots + s]; nc2 += c[e] * c[e]; }
+  for (int e = 0; e < D; ++e) {
+    c[e] = A.mixed ? (double)A.cf[e * A.nslots + s] : A.c[e * A.nslots + s];
+    nc2 += c[e] * c[e];
+  }
   const double inc = 1.0 / sqrt(nc2);
   double Ug[D + 2];
   for (int q = 0; q < D + 2; ++q) Ug[q] = Ui[q];
@@ -805,7 +875,7 @@ static inline void prof_mark(Prof *p, int kid, int end, void *stream) {
 // "not ready" stream query) must not be mistaken for a failed launch.
 static inline void clear_stale() { (void)hipGetLastError(); }
 
-template <int D, int DEG>
+template <int D, int DEG, bool MX>
 static int stage_impl(const KArgs &A, const StageBufs &b, int stage, void *stream, Prof *prof) {
   clear_stale();
   const dim3 grid((unsigned)A.nblocks), blk(kBlockThreads);
@@ -814,10 +884,10 @@ static int stage_impl(const KArgs &A, const StageBufs &b, int stage, void *strea
   hipLaunchKernelGGL(k_prim<D>, dim3(gp), blk, 0, S(stream), A, b.in);
   prof_mark(prof, KID_PRIM, 1, stream);
   prof_mark(prof, KID_SWEEP1, 0, stream);
-  hipLaunchKernelGGL((k_sweep1<D, DEG>), grid, blk, 0, S(stream), A, b.in, stage);
+  hipLaunchKernelGGL((k_sweep1<D, DEG, MX>), grid, blk, 0, S(stream), A, b.in, stage);
   prof_mark(prof, KID_SWEEP1, 1, stream);
   prof_mark(prof, KID_SWEEP2, 0, stream);
-  hipLaunchKernelGGL((k_sweep2<D, DEG>), grid, blk, 0, S(stream), A, b, stage);
+  hipLaunchKernelGGL((k_sweep2<D, DEG, MX>), grid, blk, 0, S(stream), A, b, stage);
   prof_mark(prof, KID_SWEEP2, 1, stream);
   for (int pass = 0; pass < (A.scheme == 2 ? A.passes : 0); ++pass) {
     prof_mark(prof, KID_LIMIT1 + pass, 0, stream);
@@ -846,7 +916,30 @@ static int fill_impl(const KArgs &A, void *stream) {
   }
 
 int launch_stage(const KArgs &A, const StageBufs &b, int stage, void *stream, Prof *prof) {
-  GDG_DISPATCH(stage_impl, A, b, stage, stream, prof)
+  if (A.mixed) {
+#define GDG_STAGE_MX(D_, K_) stage_impl<D_, K_, true>
+    switch (A.dim * 10 + A.deg) {
+      case 11: return GDG_STAGE_MX(1, 1)(A, b, stage, stream, prof);
+      case 12: return GDG_STAGE_MX(1, 2)(A, b, stage, stream, prof);
+      case 21: return GDG_STAGE_MX(2, 1)(A, b, stage, stream, prof);
+      case 22: return GDG_STAGE_MX(2, 2)(A, b, stage, stream, prof);
+      case 31: return GDG_STAGE_MX(3, 1)(A, b, stage, stream, prof);
+      case 32: return GDG_STAGE_MX(3, 2)(A, b, stage, stream, prof);
+      default: return -2;
+    }
+#undef GDG_STAGE_MX
+  }
+#define GDG_STAGE_64(D_, K_) stage_impl<D_, K_, false>
+  switch (A.dim * 10 + A.deg) {
+    case 11: return GDG_STAGE_64(1, 1)(A, b, stage, stream, prof);
+    case 12: return GDG_STAGE_64(1, 2)(A, b, stage, stream, prof);
+    case 21: return GDG_STAGE_64(2, 1)(A, b, stage, stream, prof);
+    case 22: return GDG_STAGE_64(2, 2)(A, b, stage, stream, prof);
+    case 31: return GDG_STAGE_64(3, 1)(A, b, stage, stream, prof);
+    case 32: return GDG_STAGE_64(3, 2)(A, b, stage, stream, prof);
+    default: return -2;
+  }
+#undef GDG_STAGE_64
 }
 
 int launch_fill(const KArgs &A, void *stream) { GDG_DISPATCH(fill_impl, A, stream) }

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libgdg.so")
 GDG_OK, GDG_E_INVALID, GDG_E_INADMISSIBLE, GDG_E_CFL, GDG_E_NOMEM, GDG_E_DEVICE = 0, -1, -2, -3, -4, -5
 GDG_BC_PERIODIC, GDG_BC_OUTFLOW, GDG_BC_SLIP = 0, 1, 2
 GDG_LOW_ORDER, GDG_HIGH_ORDER, GDG_LIMITED = 0, 1, 2
-GDG_FP64 = 0
+GDG_FP64, GDG_MIXED = 0, 1
 (GDG_FIELD_STATE, GDG_FIELD_EV_N, GDG_FIELD_BOUNDS, GDG_FIELD_UL, GDG_FIELD_DUH,
  GDG_FIELD_U1) = range(6)
 _FIELD_PLANES = {GDG_FIELD_EV_N: 1, GDG_FIELD_BOUNDS: 3}

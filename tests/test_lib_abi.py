@@ -87,3 +87,19 @@ def test_create_rejects_small_or_null_workspace():
     with pytest.raises(gdg.GdgError) as ei:
         gdg.gdg_create(m, p, 0, 0, 0)
     assert ei.value.status == gdg.GDG_E_NOMEM
+
+
+def test_mixed_precision_accepted_and_smaller():
+    """The mixed variant stores c_ij in FP32: its workspace is smaller by
+    4 bytes per stored coefficient and otherwise the same."""
+    m = gdg.mesh_desc(2, 2, (16, 16), (0, 0), (1, 1), (1,) * 4)
+    p64 = gdg.gdg_default_params(2)
+    pmx = gdg.gdg_default_params(2)
+    pmx.precision = gdg.GDG_MIXED
+    b64 = gdg.gdg_workspace_bytes(m, p64)
+    bmx = gdg.gdg_workspace_bytes(m, pmx)
+    # stored slots: at least one per (row, stencil width), padding at most one
+    # block of whole cells per 256 rows; each saves 4 bytes per coordinate
+    nloc, W, N = 9, 9 + 2 * 3, 256 * 9
+    lo, hi = 4 * 2 * N * W, 4 * 2 * (N + 256) * W
+    assert lo - 256 <= b64 - bmx <= hi + 256
