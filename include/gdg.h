@@ -44,7 +44,8 @@ typedef enum {
   GDG_E_INADMISSIBLE = -2, /* a state left A: rho <= 0, eps <= 0 or NaN (eq. AddSet) */
   GDG_E_CFL = -3,          /* the CFL condition eq. CFLcond failed after all restarts */
   GDG_E_NOMEM = -4,        /* workspace smaller than gdg_workspace_bytes() */
-  GDG_E_DEVICE = -5        /* a HIP runtime call failed */
+  GDG_E_DEVICE = -5,       /* a HIP runtime call failed */
+  GDG_E_BUDGET = -6        /* a request can never fit the server's memory pool */
 } gdg_status;
 
 /* Boundary kinds per box face (Sec. 4.1).  OUTFLOW is the supersonic-outflow
@@ -194,6 +195,91 @@ gdg_status gdg_profile_read(const gdg_ctx *ctx, double *ms_total, int64_t *launc
 /* Text of the last error on this context ("" if none); with ctx == NULL, the
  * reason of the last failed gdg_create() on the calling thread. */
 const char *gdg_last_error(const gdg_ctx *ctx);
+
+/* ---------------------------------------------------------------------------
+ * Serving: many independent simulations on one GPU with continuous batching.
+ *
+ * A server owns a caller-provided device memory pool (its HBM budget) and a
+ * stream.  gdg_server_submit() queues a request (mesh, scheme constants,
+ * initial state, final time) without touching the GPU.  Each
+ * gdg_server_pump() call
+ *   1. waits for the previous batched launch and reads every resident
+ *      request's time and flags (one small copy),
+ *   2. retires finished requests: their state is copied to host memory held
+ *      by the server and their workspace returns to the pool,
+ *   3. redoes, host-driven, a step that a CFL violation halted (the restart
+ *      rule of gdg_step),
+ *   4. admits queued requests in arrival order while a slot is free and the
+ *      pool has room for the request's workspace (gdg_workspace_bytes), and
+ *   5. launches one captured graph of steps_per_graph SSP-RK3 steps of all
+ *      resident requests and returns without waiting.
+ * The graph's kernels are persistent: one grid walks the row blocks of every
+ * resident request from a work list in device memory, so requests admitted
+ * later join the next launch without a new capture.  Each request steps with
+ * its own time step and stops at its own final time, as gdg_run_to() on a
+ * context of its own would (same steps; results equal to rounding, since the
+ * batched kernels are compiled apart and may contract other multiply-adds),
+ * and its result does not depend on the other requests: it is bit-identical
+ * alone and in any mix.  All requests of a server share one class: dim,
+ * degree and precision (gdg_server_desc); the scheme constants may differ.
+ * Calls on one server are not thread-safe.
+ * ------------------------------------------------------------------------- */
+typedef struct gdg_server gdg_server;
+
+typedef struct {
+  int32_t dim, degree, precision; /* the request class */
+  int32_t max_slots;              /* resident requests at most, 1 .. 256 */
+  int32_t steps_per_graph;        /* SSP-RK3 steps per batched launch, >= 1 */
+  int32_t reserved;
+} gdg_server_desc;
+
+typedef enum { GDG_REQ_PENDING = 0, GDG_REQ_RUNNING = 1, GDG_REQ_DONE = 2, GDG_REQ_FAILED = 3 } gdg_req_state;
+
+typedef struct {
+  int32_t state;    /* gdg_req_state */
+  int32_t status;   /* gdg_status of a failed request, else GDG_OK */
+  double t;         /* simulated time reached */
+  int64_t steps;    /* SSP-RK3 steps taken */
+  int64_t restarts; /* CFL restarts */
+  int64_t ndofs;
+  double submit_s;  /* host clock of submission, admission and completion, */
+  double admit_s;   /* seconds since the server's creation (0 if not yet) */
+  double done_s;
+} gdg_request_info;
+
+/* Device bytes of the pool that the server keeps for its work list; a pool
+ * must be larger than this by at least one request's workspace. */
+gdg_status gdg_server_overhead_bytes(const gdg_server_desc *desc, size_t *bytes);
+
+/* Creates a server over dev_pool (caller-owned device memory of pool_bytes,
+ * 256-byte aligned, alive until gdg_server_destroy) and hip_stream. */
+gdg_status gdg_server_create(const gdg_server_desc *desc, void *dev_pool, size_t pool_bytes, void *hip_stream,
+                             gdg_server **out);
+
+/* Queues a request; U0 is a host state (SoA, (dim+2) * N doubles), copied.
+ * GDG_E_INVALID for a description outside the server's class or bad
+ * constants, GDG_E_BUDGET if its workspace exceeds the whole pool. */
+gdg_status gdg_server_submit(gdg_server *srv, const gdg_mesh_desc *mesh, const gdg_params *prm, const double *U0,
+                             double t_final, uint64_t *ticket);
+
+/* One round of the serving loop (above).  *resident and *pending (may be
+ * NULL) receive the requests on the GPU and still queued after the call. */
+gdg_status gdg_server_pump(gdg_server *srv, int32_t *resident, int32_t *pending);
+
+/* Waits for the launch in flight and processes it (steps 1-3 of a pump), without admitting or launching. */
+gdg_status gdg_server_sync(gdg_server *srv);
+
+/* State, counters and host timestamps of a request. */
+gdg_status gdg_server_poll(const gdg_server *srv, uint64_t ticket, gdg_request_info *info);
+
+/* Copies a finished request's final state to U (host, SoA) and forgets the
+ * request.  GDG_E_INVALID if the ticket is unknown or not finished. */
+gdg_status gdg_server_result(gdg_server *srv, uint64_t ticket, double *U);
+
+/* Waits for the stream, releases every context and the server (not the pool). */
+void gdg_server_destroy(gdg_server *srv);
+
+const char *gdg_server_last_error(const gdg_server *srv);
 
 #ifdef __cplusplus
 }

@@ -542,6 +542,45 @@ gdg_status gdg_run_to(gdg_ctx *ctx, double t_final, int64_t max_steps, gdg_stats
   return gdg_get_stats(ctx, stats);
 }
 
+}  // extern "C"
+
+namespace gdg {
+
+const KArgs &ctx_kargs(const gdg_ctx *ctx) { return ctx->A; }
+
+void ctx_stage_bufs(const gdg_ctx *ctx, StageBufs sb[3]) {
+  const int c0 = ctx->cur, c1 = (c0 + 1) % 3, c2 = (c0 + 2) % 3;
+  sb[0] = {ctx->U[c0], ctx->U[c1], ctx->U[c0], 0.0, 1.0};
+  sb[1] = {ctx->U[c1], ctx->U[c2], ctx->U[c0], 0.75, 0.25};
+  sb[2] = {ctx->U[c2], ctx->U[c0], ctx->U[c0], 1.0 / 3.0, 2.0 / 3.0};
+}
+
+int ctx_arm(gdg_ctx *ctx, double t_final) {
+  return launch_set_run(ctx->A, t_final, (long long)(int64_t(1) << 60), ctx->stream);
+}
+
+void ctx_sync(gdg_ctx *ctx, const Ctl &c) {
+  ctx->hctl = c;
+  ctx->last_dt = c.tau;
+  sync_time(ctx);
+}
+
+gdg_status ctx_restart(gdg_ctx *ctx, const Ctl &c, double t_final) {
+  ctx_sync(ctx, c);
+  const int vs = c.viol_stage < 1 ? 1 : c.viol_stage;
+  const double tau = ctx->prm.cfl * bits_to_double(c.taumin_bits[vs]);
+  ++ctx->restarts;
+  double dt = 0.0;
+  if (gdg_status s = gdg_step(ctx, t_final - ctx->t, tau, &dt)) return s;
+  return launched(ctx, ctx_arm(ctx, t_final), "set run");
+}
+
+const char *ctx_error(const gdg_ctx *ctx) { return ctx->err.c_str(); }
+
+}  // namespace gdg
+
+extern "C" {
+
 gdg_status gdg_stage(gdg_ctx *ctx, double tau, double *tau_used) {
   if (!ctx) return GDG_E_INVALID;
   const int c0 = ctx->cur, c1 = (c0 + 1) % 3;

@@ -13,6 +13,8 @@
 
 #include <string>
 
+#include "gdg.h"
+
 namespace gdg {
 
 // slot kinds (low 3 bits of the meta byte)
@@ -121,6 +123,24 @@ struct Prof {
   int cap;        // capacity in launches
   int n;          // bracketed launches since the last harvest
 };
+// Work list of the request server: the resident requests of one class
+// (dim, degree, precision), each with its kernel arguments and the buffers of
+// the three SSP-RK3 stages, and the prefix sums of their row blocks.  The
+// batched kernels walk all row blocks of all entries with one persistent grid,
+// so a graph captured once serves every later mix of requests.
+constexpr int kMaxBatch = 256;
+struct BatchEntry {
+  KArgs A;
+  StageBufs sb[3];
+};
+struct BatchList {
+  int32_t nreq;
+  int32_t pad;
+  int64_t ntiles;                      // sum of the entries' row blocks
+  int64_t tile_begin[kMaxBatch + 1];   // first row block of each entry
+  BatchEntry e[kMaxBatch];
+};
+
 bool build_ref_tables(int dim, int deg, const double *h, RefTables *T, std::string *err);
 int launch_fill(const KArgs &A, void *stream);
 int launch_begin(const KArgs &A, double dt_cap, double tau_fixed, int device_driven, void *stream);
@@ -128,5 +148,22 @@ int launch_end(const KArgs &A, void *stream);
 int launch_set_run(const KArgs &A, double t_final, long long step_limit, void *stream);
 int launch_prim(const KArgs &A, const double *U, void *stream);
 int launch_stage(const KArgs &A, const StageBufs &b, int stage, void *stream, Prof *prof);
+// ksteps device-driven SSP-RK3 steps of every request in L (persistent grid of
+// `grid` workgroups, a multiple of 8), then a copy of each request's control
+// block into status[0 .. nreq).
+int launch_batch_steps(int dim, int deg, int mixed, const BatchList *L, Ctl *status, int ksteps, int grid,
+                       void *stream);
+
+// Access to a context for the request server (gdg_api.cpp).
+const KArgs &ctx_kargs(const gdg_ctx *ctx);
+void ctx_stage_bufs(const gdg_ctx *ctx, StageBufs sb[3]);
+// Arms the device-driven loop: run to t_final with no step limit, flags cleared.
+int ctx_arm(gdg_ctx *ctx, double t_final);
+// Takes the time and counters of a control block copied after device-driven steps.
+void ctx_sync(gdg_ctx *ctx, const Ctl &c);
+// Redoes the step that a CFL violation halted (host-driven, with the restart
+// rule of gdg_step), then re-arms the device-driven loop.
+gdg_status ctx_restart(gdg_ctx *ctx, const Ctl &c, double t_final);
+const char *ctx_error(const gdg_ctx *ctx);
 
 }  // namespace gdg

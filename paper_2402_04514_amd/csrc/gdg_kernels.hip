@@ -332,8 +332,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_fill(KArgs A) {
 // tau and has cleared the flags' causes.  Device-driven (graphs): the cap is
 // t_final - t, and a finished run, a step limit or a flag left by an earlier
 // step of the graph halts the step.
-__global__ void k_begin(Ctl *ctl, double dt_cap, double tau_fixed, int device_driven) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ __forceinline__ void begin_step(Ctl *ctl, double dt_cap, double tau_fixed, int device_driven) {
   if (device_driven) {
     if (ctl->cfl_flag || ctl->bad_flag || ctl->halt || !(ctl->t < ctl->t_final) ||
         ctl->steps >= ctl->step_limit) {
@@ -354,9 +353,13 @@ __global__ void k_begin(Ctl *ctl, double dt_cap, double tau_fixed, int device_dr
   ctl->tau_fixed = tau_fixed;
 }
 
-// Last kernel of a step: advance t (exactly to the cap's end on a capped step).
-__global__ void k_end(Ctl *ctl) {
+__global__ void k_begin(Ctl *ctl, double dt_cap, double tau_fixed, int device_driven) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  begin_step(ctl, dt_cap, tau_fixed, device_driven);
+}
+
+// Last kernel of a step: advance t (exactly to the cap's end on a capped step).
+__device__ __forceinline__ void end_step(Ctl *ctl) {
   if (ctl->halt || ctl->cfl_flag || ctl->bad_flag) return;
   const bool capped = ctl->dt_cap > 0.0 && ctl->tau == ctl->dt_cap;
   ctl->t = capped ? ctl->t + ctl->dt_cap : ctl->t + ctl->tau;
@@ -364,10 +367,14 @@ __global__ void k_end(Ctl *ctl) {
   ctl->steps += 1;
 }
 
+__global__ void k_end(Ctl *ctl) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  end_step(ctl);
+}
+
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ __launch_bounds__(kBlockThreads) void k_prim(KArgs A, const double *__restrict__ U) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void prim_row(const KArgs &A, const double *__restrict__ U, int64_t i) {
   if (i >= A.N) return;
   const int64_t N = A.N;
   const double g = A.gamma;
@@ -385,6 +392,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_prim(KArgs A, const double *_
   A.Wc[(D + 3) * N + i] = exp(log(rg * p) / (g + 1.0));  // Harten entropy f(s) = e^{s/(gamma+1)}
   A.Wc[(D + 4) * N + i] = rg * eps;                      // s~ = rho^-gamma eps
   A.Wc[(D + 5) * N + i] = 1.0 / p;
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlockThreads) void k_prim(KArgs A, const double *__restrict__ U) {
+  prim_row<D>(A, U, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 template <int D>
@@ -432,15 +444,14 @@ __device__ __forceinline__ double block_min_atomic(double v, unsigned long long 
 
 // ---------------------------------------------------------------------------
 template <int D, int DEG, bool MX>
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_SWEEP))) void k_sweep1(KArgs A, const double *__restrict__ U,
-                                                          int stage) {
+__device__ __forceinline__ void sweep1_body(const KArgs &A, const double *__restrict__ U, int stage,
+                                            int64_t blk) {
   using Acc = typename AccT<MX>::type;
   constexpr int M = D + 2;
   constexpr int NB = DEG + 1;
   constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
   if (A.ctl->halt || A.ctl->cfl_flag) return;  // set by an earlier kernel or never
   const int lane = threadIdx.x;
-  const int64_t blk = xcd_block(blockIdx.x, A.nblocks);
   const int64_t i = blk * A.R + lane;
   const bool active = lane < A.R && i < A.N;
   double tau_i = INFINITY;
@@ -559,6 +570,12 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(G
   block_min_atomic(tau_i, &A.ctl->taumin_bits[stage]);
 }
 
+template <int D, int DEG, bool MX>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_SWEEP))) void k_sweep1(
+    KArgs A, const double *__restrict__ U, int stage) {
+  sweep1_body<D, DEG, MX>(A, U, stage, xcd_block(blockIdx.x, A.nblocks));
+}
+
 // high-order viscosity of eq. HighOrderViscosity / ViscMin for a graph pair
 __device__ __forceinline__ double visc_high(const KArgs &A, double d, double Ni, double Nj, int kind,
                                            double hpk) {
@@ -583,7 +600,7 @@ __device__ __forceinline__ bool stage_tau(const KArgs &A, int stage, double *tau
 }
 
 template <int D, int DEG, bool MX>
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_SWEEP))) void k_sweep2(KArgs A, StageBufs sb, int stage) {
+__device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb, int stage, int64_t blk) {
   using Acc = typename AccT<MX>::type;
   constexpr int M = D + 2;
   constexpr int NB = DEG + 1;
@@ -591,16 +608,15 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(G
   __shared__ double rs[M][kBlockThreads];
   double tau;
   if (!stage_tau(A, stage, &tau)) {
-    if (stage > 0 && blockIdx.x == 0 && threadIdx.x == 0 && A.ctl->cfl_flag == 0 && A.ctl->halt == 0) {
+    if (stage > 0 && blk == 0 && threadIdx.x == 0 && A.ctl->cfl_flag == 0 && A.ctl->halt == 0) {
       A.ctl->viol_stage = stage;
       atomicOr(&A.ctl->cfl_flag, 1);
     }
     return;
   }
-  if (stage == 0 && blockIdx.x == 0 && threadIdx.x == 0) A.ctl->tau = tau;
+  if (stage == 0 && blk == 0 && threadIdx.x == 0) A.ctl->tau = tau;
   const double *__restrict__ U = sb.in;
   const int lane = threadIdx.x;
-  const int64_t blk = xcd_block(blockIdx.x, A.nblocks);
   const int64_t i = blk * A.R + lane;
   const bool active = lane < A.R && i < A.N;
   const int64_t N = A.N;
@@ -728,6 +744,12 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(G
   }
 }
 
+template <int D, int DEG, bool MX>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_SWEEP))) void k_sweep2(
+    KArgs A, StageBufs sb, int stage) {
+  sweep2_body<D, DEG, MX>(A, sb, stage, xcd_block(blockIdx.x, A.nblocks));
+}
+
 // ---------------------------------------------------------------------------
 // Antidiffusive flux of eq. HighLowOrderIdentity for a graph pair:
 //   A_ij = tau (d^H_ij - d^L_ij)(U_j - U_i) - m_ij (dU^H_j - dU^H_i).
@@ -773,13 +795,13 @@ __device__ __forceinline__ void ghost_flux(const KArgs &A, int64_t s, uint8_t me
 // U^(1).  pass 1: base U^(1), fluxes (1 - l^(1)) A.  The final pass writes the
 // SSP combination.
 template <int D, int DEG>
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_LIMIT))) void k_limit(KArgs A, StageBufs sb, int pass, int final_pass) {
+__device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, int pass, int final_pass,
+                                           int64_t blk) {
   constexpr int M = D + 2;
   constexpr int NB = DEG + 1;
   constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
   if (A.ctl->halt || A.ctl->cfl_flag) return;
   const int lane = threadIdx.x;
-  const int64_t blk = xcd_block(blockIdx.x, A.nblocks);
   const int64_t i = blk * A.R + lane;
   if (lane >= A.R || i >= A.N) return;
   const double *__restrict__ U = sb.in;
@@ -858,13 +880,96 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(G
   }
 }
 
+template <int D, int DEG>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_LIMIT))) void k_limit(
+    KArgs A, StageBufs sb, int pass, int final_pass) {
+  limit_body<D, DEG>(A, sb, pass, final_pass, xcd_block(blockIdx.x, A.nblocks));
+}
+
+// ---------------------------------------------------------------------------
+// Batched steps of the request server.  One persistent grid walks the row
+// blocks of all resident requests listed in device memory; each XCD takes one
+// contiguous range of the concatenated blocks (as xcd_block does for one
+// mesh).  Every row block runs the same body as the single-mesh kernels, with
+// that request's arguments, so a request's arithmetic does not depend on what
+// else is resident.
+__device__ __forceinline__ int find_req(const BatchList *L, int64_t tile) {
+  int lo = 0, hi = L->nreq - 1;  // the entry with tile_begin[r] <= tile < tile_begin[r + 1]
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (L->tile_begin[mid] <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename F>
+__device__ __forceinline__ void for_tiles(const BatchList *L, F &&f) {
+  constexpr int64_t kX = 8;
+  const int64_t nt = L->ntiles;
+  const int64_t per = gridDim.x / kX;
+  const int64_t x = blockIdx.x % kX, k = blockIdx.x / kX;
+  const int64_t lo = nt * x / kX, hi = nt * (x + 1) / kX;
+  for (int64_t t = lo + k; t < hi; t += per) {
+    const int r = find_req(L, t);
+    f(L->e[r], t - L->tile_begin[r]);
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlockThreads) void kb_prim(const BatchList *L, int stage) {
+  for_tiles(L, [&](const BatchEntry &E, int64_t blk) {
+    if (E.A.ctl->halt || E.A.ctl->cfl_flag) return;
+    if ((int)threadIdx.x < E.A.R) prim_row<D>(E.A, E.sb[stage].in, blk * E.A.R + threadIdx.x);
+  });
+}
+
+template <int D, int DEG, bool MX>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_SWEEP))) void kb_sweep1(
+    const BatchList *L, int stage) {
+  for_tiles(L, [&](const BatchEntry &E, int64_t blk) { sweep1_body<D, DEG, MX>(E.A, E.sb[stage].in, stage, blk); });
+}
+
+template <int D, int DEG, bool MX>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_SWEEP))) void kb_sweep2(
+    const BatchList *L, int stage) {
+  for_tiles(L, [&](const BatchEntry &E, int64_t blk) {
+    __syncthreads();  // the previous block's cell solve has read its LDS rows
+    sweep2_body<D, DEG, MX>(E.A, E.sb[stage], stage, blk);
+  });
+}
+
+template <int D, int DEG>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_LIMIT))) void kb_limit(
+    const BatchList *L, int stage, int pass) {
+  for_tiles(L, [&](const BatchEntry &E, int64_t blk) {
+    if (E.A.scheme != 2 || pass >= E.A.passes) return;
+    limit_body<D, DEG>(E.A, E.sb[stage], pass, pass + 1 == E.A.passes ? 1 : 0, blk);
+  });
+}
+
+__global__ void kb_begin(const BatchList *L) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < L->nreq) begin_step(L->e[r].A.ctl, 0.0, 0.0, 1);
+}
+
+__global__ void kb_end(const BatchList *L) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < L->nreq) end_step(L->e[r].A.ctl);
+}
+
+__global__ void kb_status(const BatchList *L, Ctl *status) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < L->nreq) status[r] = *L->e[r].A.ctl;
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 static inline hipStream_t S(void *s) { return (hipStream_t)s; }
 
 static inline void prof_mark(Prof *p, int kid, int end, void *stream) {
   if (!p || p->n >= p->cap) return;
-  hipEventRecord((hipEvent_t)p->ev[2 * p->n + end], S(stream));
+  (void)hipEventRecord((hipEvent_t)p->ev[2 * p->n + end], S(stream));
   if (end) {
     p->kid[p->n] = kid;
     ++p->n;
@@ -943,6 +1048,44 @@ int launch_stage(const KArgs &A, const StageBufs &b, int stage, void *stream, Pr
 }
 
 int launch_fill(const KArgs &A, void *stream) { GDG_DISPATCH(fill_impl, A, stream) }
+
+template <int D, int DEG, bool MX>
+static int batch_impl(const BatchList *L, Ctl *status, int ksteps, int grid, void *stream) {
+  clear_stale();
+  const dim3 g((unsigned)grid), b(kBlockThreads), gr((kMaxBatch + 63) / 64), br(64);
+  for (int k = 0; k < ksteps; ++k) {
+    hipLaunchKernelGGL(kb_begin, gr, br, 0, S(stream), L);
+    for (int stage = 0; stage < 3; ++stage) {
+      hipLaunchKernelGGL(kb_prim<D>, g, b, 0, S(stream), L, stage);
+      hipLaunchKernelGGL((kb_sweep1<D, DEG, MX>), g, b, 0, S(stream), L, stage);
+      hipLaunchKernelGGL((kb_sweep2<D, DEG, MX>), g, b, 0, S(stream), L, stage);
+      for (int pass = 0; pass < 2; ++pass) hipLaunchKernelGGL((kb_limit<D, DEG>), g, b, 0, S(stream), L, stage, pass);
+    }
+    hipLaunchKernelGGL(kb_end, gr, br, 0, S(stream), L);
+  }
+  hipLaunchKernelGGL(kb_status, gr, br, 0, S(stream), L, status);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_batch_steps(int dim, int deg, int mixed, const BatchList *L, Ctl *status, int ksteps, int grid,
+                       void *stream) {
+  if (grid <= 0 || grid % 8 != 0) return -2;
+  switch (dim * 100 + deg * 10 + (mixed ? 1 : 0)) {
+    case 110: return batch_impl<1, 1, false>(L, status, ksteps, grid, stream);
+    case 111: return batch_impl<1, 1, true>(L, status, ksteps, grid, stream);
+    case 120: return batch_impl<1, 2, false>(L, status, ksteps, grid, stream);
+    case 121: return batch_impl<1, 2, true>(L, status, ksteps, grid, stream);
+    case 210: return batch_impl<2, 1, false>(L, status, ksteps, grid, stream);
+    case 211: return batch_impl<2, 1, true>(L, status, ksteps, grid, stream);
+    case 220: return batch_impl<2, 2, false>(L, status, ksteps, grid, stream);
+    case 221: return batch_impl<2, 2, true>(L, status, ksteps, grid, stream);
+    case 310: return batch_impl<3, 1, false>(L, status, ksteps, grid, stream);
+    case 311: return batch_impl<3, 1, true>(L, status, ksteps, grid, stream);
+    case 320: return batch_impl<3, 2, false>(L, status, ksteps, grid, stream);
+    case 321: return batch_impl<3, 2, true>(L, status, ksteps, grid, stream);
+    default: return -2;
+  }
+}
 
 int launch_begin(const KArgs &A, double dt_cap, double tau_fixed, int device_driven, void *stream) {
   clear_stale();

@@ -15,7 +15,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgdg.so")
 
-GDG_OK, GDG_E_INVALID, GDG_E_INADMISSIBLE, GDG_E_CFL, GDG_E_NOMEM, GDG_E_DEVICE = 0, -1, -2, -3, -4, -5
+GDG_OK, GDG_E_INVALID, GDG_E_INADMISSIBLE, GDG_E_CFL, GDG_E_NOMEM, GDG_E_DEVICE, GDG_E_BUDGET = (
+    0, -1, -2, -3, -4, -5, -6)
+GDG_REQ_PENDING, GDG_REQ_RUNNING, GDG_REQ_DONE, GDG_REQ_FAILED = 0, 1, 2, 3
 GDG_BC_PERIODIC, GDG_BC_OUTFLOW, GDG_BC_SLIP = 0, 1, 2
 GDG_LOW_ORDER, GDG_HIGH_ORDER, GDG_LIMITED = 0, 1, 2
 GDG_FP64, GDG_MIXED = 0, 1
@@ -24,7 +26,7 @@ GDG_FP64, GDG_MIXED = 0, 1
 _FIELD_PLANES = {GDG_FIELD_EV_N: 1, GDG_FIELD_BOUNDS: 3}
 
 _NAMES = {0: "GDG_OK", -1: "GDG_E_INVALID", -2: "GDG_E_INADMISSIBLE", -3: "GDG_E_CFL",
-          -4: "GDG_E_NOMEM", -5: "GDG_E_DEVICE"}
+          -4: "GDG_E_NOMEM", -5: "GDG_E_DEVICE", -6: "GDG_E_BUDGET"}
 
 
 class GdgError(RuntimeError):
@@ -48,6 +50,17 @@ class gdg_params(C.Structure):
 class gdg_stats(C.Structure):
     _fields_ = [("t", C.c_double), ("steps", C.c_int64), ("restarts", C.c_int64),
                 ("last_dt", C.c_double)]
+
+
+class gdg_server_desc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("degree", C.c_int32), ("precision", C.c_int32),
+                ("max_slots", C.c_int32), ("steps_per_graph", C.c_int32), ("reserved", C.c_int32)]
+
+
+class gdg_request_info(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("t", C.c_double), ("steps", C.c_int64),
+                ("restarts", C.c_int64), ("ndofs", C.c_int64), ("submit_s", C.c_double),
+                ("admit_s", C.c_double), ("done_s", C.c_double)]
 
 
 _lib = None
@@ -87,9 +100,23 @@ def load():
     L.gdg_profile_read.argtypes = [_P, _DP, C.POINTER(C.c_int64)]
     L.gdg_last_error.argtypes = [_P]
     L.gdg_last_error.restype = C.c_char_p
+    L.gdg_server_overhead_bytes.argtypes = [C.POINTER(gdg_server_desc), C.POINTER(C.c_size_t)]
+    L.gdg_server_create.argtypes = [C.POINTER(gdg_server_desc), _P, C.c_size_t, _P, C.POINTER(_P)]
+    L.gdg_server_submit.argtypes = [_P, C.POINTER(gdg_mesh_desc), C.POINTER(gdg_params), _DP, C.c_double,
+                                    C.POINTER(C.c_uint64)]
+    L.gdg_server_pump.argtypes = [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.gdg_server_sync.argtypes = [_P]
+    L.gdg_server_poll.argtypes = [_P, C.c_uint64, C.POINTER(gdg_request_info)]
+    L.gdg_server_result.argtypes = [_P, C.c_uint64, _DP]
+    L.gdg_server_destroy.argtypes = [_P]
+    L.gdg_server_destroy.restype = None
+    L.gdg_server_last_error.argtypes = [_P]
+    L.gdg_server_last_error.restype = C.c_char_p
     for fn in ("gdg_default_params", "gdg_workspace_bytes", "gdg_create", "gdg_node_coords",
                "gdg_upload_state", "gdg_download_state", "gdg_step", "gdg_run_to", "gdg_stage",
-               "gdg_read_field", "gdg_get_stats", "gdg_profile", "gdg_profile_read"):
+               "gdg_read_field", "gdg_get_stats", "gdg_profile", "gdg_profile_read",
+               "gdg_server_overhead_bytes", "gdg_server_create", "gdg_server_submit", "gdg_server_pump",
+               "gdg_server_sync", "gdg_server_poll", "gdg_server_result"):
         getattr(L, fn).restype = C.c_int
     _lib = L
     return L
@@ -277,3 +304,112 @@ class Solver:
 
     def stats(self) -> gdg_stats:
         return gdg_get_stats(self.ctx)
+
+
+# -- serving -------------------------------------------------------------------
+def _scheck(st, srv):
+    if st != GDG_OK:
+        raise GdgError(st, load().gdg_server_last_error(srv).decode())
+
+
+def server_desc(dim, degree, precision=GDG_FP64, max_slots=64, steps_per_graph=8) -> gdg_server_desc:
+    d = gdg_server_desc()
+    d.dim, d.degree, d.precision, d.max_slots, d.steps_per_graph = dim, degree, precision, max_slots, steps_per_graph
+    return d
+
+
+def gdg_server_overhead_bytes(desc: gdg_server_desc) -> int:
+    n = C.c_size_t(0)
+    _check(load().gdg_server_overhead_bytes(C.byref(desc), C.byref(n)))
+    return n.value
+
+
+def gdg_server_create(desc, pool_ptr: int, pool_bytes: int, stream_ptr: int):
+    srv = _P()
+    st = load().gdg_server_create(C.byref(desc), _P(pool_ptr), pool_bytes, _P(stream_ptr), C.byref(srv))
+    if st != GDG_OK:
+        raise GdgError(st, "server creation failed")
+    return srv
+
+
+def gdg_server_submit(srv, mesh, prm, U0: np.ndarray, t_final: float) -> int:
+    U0 = np.ascontiguousarray(U0, dtype=np.float64)
+    t = C.c_uint64(0)
+    _scheck(load().gdg_server_submit(srv, C.byref(mesh), C.byref(prm), U0.ctypes.data_as(_DP), t_final,
+                                     C.byref(t)), srv)
+    return t.value
+
+
+def gdg_server_pump(srv):
+    r, p = C.c_int32(0), C.c_int32(0)
+    _scheck(load().gdg_server_pump(srv, C.byref(r), C.byref(p)), srv)
+    return r.value, p.value
+
+
+def gdg_server_sync(srv):
+    _scheck(load().gdg_server_sync(srv), srv)
+
+
+def gdg_server_poll(srv, ticket: int) -> gdg_request_info:
+    info = gdg_request_info()
+    _scheck(load().gdg_server_poll(srv, ticket, C.byref(info)), srv)
+    return info
+
+
+def gdg_server_result(srv, ticket: int, out: np.ndarray) -> np.ndarray:
+    assert out.dtype == np.float64 and out.flags.c_contiguous
+    _scheck(load().gdg_server_result(srv, ticket, out.ctypes.data_as(_DP)), srv)
+    return out
+
+
+def gdg_server_destroy(srv):
+    load().gdg_server_destroy(srv)
+
+
+def gdg_server_last_error(srv) -> str:
+    return load().gdg_server_last_error(srv).decode()
+
+
+class Server:
+    """A request server whose memory pool (the HBM budget) is a torch uint8
+    tensor on ``device`` and whose stream is torch's current stream there."""
+
+    def __init__(self, dim, degree, precision=GDG_FP64, budget_bytes=4 << 30, max_slots=64,
+                 steps_per_graph=8, device="cuda:0", stream=None):
+        import torch
+        self.desc = server_desc(dim, degree, precision, max_slots, steps_per_graph)
+        self.device = torch.device(device)
+        self.pool = torch.empty(budget_bytes + 256, dtype=torch.uint8, device=self.device)
+        self.pool_ptr = (self.pool.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.srv = gdg_server_create(self.desc, self.pool_ptr, budget_bytes, self.stream.cuda_stream)
+        self.m = dim + 2
+
+    def submit(self, ms, U0, t_final, params=None) -> int:
+        prm = params if params is not None else gdg_default_params(ms.degree)
+        if params is None:
+            prm.precision = self.desc.precision
+        mesh = mesh_desc(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc)
+        return gdg_server_submit(self.srv, mesh, prm, U0, t_final)
+
+    def pump(self):
+        return gdg_server_pump(self.srv)
+
+    def sync(self):
+        gdg_server_sync(self.srv)
+
+    def poll(self, ticket) -> gdg_request_info:
+        return gdg_server_poll(self.srv, ticket)
+
+    def result(self, ticket) -> np.ndarray:
+        info = self.poll(ticket)
+        out = np.zeros((self.m, info.ndofs))
+        return gdg_server_result(self.srv, ticket, out)
+
+    def close(self):
+        if getattr(self, "srv", None):
+            gdg_server_destroy(self.srv)
+            self.srv = None
+
+    def __del__(self):
+        self.close()

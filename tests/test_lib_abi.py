@@ -103,3 +103,44 @@ def test_mixed_precision_accepted_and_smaller():
     nloc, W, N = 9, 9 + 2 * 3, 256 * 9
     lo, hi = 4 * 2 * N * W, 4 * 2 * (N + 256) * W
     assert lo - 256 <= b64 - bmx <= hi + 256
+
+
+def test_server_host_side_validation():
+    """Server creation and submission touch no device: class checks, the
+    budget rule and the overhead query run on the host."""
+    import numpy as np
+    d = gdg.server_desc(2, 1, gdg.GDG_MIXED, max_slots=4)
+    over = gdg.gdg_server_overhead_bytes(d)
+    assert over >= 64 * 1024
+    bad = gdg.server_desc(2, 1, 7)
+    with pytest.raises(gdg.GdgError):
+        gdg.gdg_server_overhead_bytes(bad)
+    fake_pool = 1 << 40  # an aligned address that is never dereferenced here
+    m = gdg.mesh_desc(2, 1, (16, 16), (0, 0), (1, 1), (1,) * 4)
+    p = gdg.gdg_default_params(1)
+    p.precision = gdg.GDG_MIXED
+    need = gdg.gdg_workspace_bytes(m, p)
+    srv = gdg.gdg_server_create(d, fake_pool, over + need + 4096, 0)
+    try:
+        U = np.ones((4, 16 * 16 * 4))
+        t1 = gdg.gdg_server_submit(srv, m, p, U, 0.1)
+        t2 = gdg.gdg_server_submit(srv, m, p, U, 0.1)
+        assert t2 == t1 + 1
+        info = gdg.gdg_server_poll(srv, t1)
+        assert info.state == gdg.GDG_REQ_PENDING and info.ndofs == 16 * 16 * 4
+        big = gdg.mesh_desc(2, 1, (64, 64), (0, 0), (1, 1), (1,) * 4)
+        with pytest.raises(gdg.GdgError) as ei:
+            gdg.gdg_server_submit(srv, big, p, np.ones((4, 64 * 64 * 4)), 0.1)
+        assert ei.value.status == gdg.GDG_E_BUDGET
+        q2 = gdg.mesh_desc(2, 2, (8, 8), (0, 0), (1, 1), (1,) * 4)
+        with pytest.raises(gdg.GdgError) as ei:
+            gdg.gdg_server_submit(srv, q2, gdg.gdg_default_params(2), np.ones((4, 8 * 8 * 9)), 0.1)
+        assert ei.value.status == gdg.GDG_E_INVALID
+        p64 = gdg.gdg_default_params(1)
+        with pytest.raises(gdg.GdgError) as ei:
+            gdg.gdg_server_submit(srv, m, p64, U, 0.1)
+        assert ei.value.status == gdg.GDG_E_INVALID
+        with pytest.raises(gdg.GdgError):
+            gdg.gdg_server_result(srv, t1, np.zeros((4, 16 * 16 * 4)))  # not finished
+    finally:
+        gdg.gdg_server_destroy(srv)
