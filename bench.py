@@ -188,6 +188,92 @@ def mixed_vs_fp64(name, steps):
             "fp64_perturbed_1e-13": {"l1_rel_per_component": pcomp, "l1_consolidated": pcons}}
 
 
+def serving(count, n_max, t_final, budget_gib, max_slots, spg):
+    """The serving workload on a trace of `count` requests (2D Q1 four-quadrant
+    Riemann problems of n x n cells, n log-uniform in [32, n_max], outflow,
+    run to t_final; Poisson arrivals at 20 per second), served in real time by
+    the batched server (mixed precision), and the same trace served FIFO one at
+    a time on the FP64 single-mesh path (each request's service time measured
+    back to back; queueing replayed on the arrival clock)."""
+    import numpy as np
+    import torch
+
+    from paper_2402_04514_amd import gdg
+    from paper_2402_04514_amd import workloads as W
+
+    trace = W.serving_trace(count, n_max=n_max)
+    reqs = [(a, W.quadrant(cells=n, degree=1, seed_base=sb)) for a, n, sb in trace]
+    # -- batched, continuous admission, real time
+    S = gdg.Server(2, 1, gdg.GDG_MIXED, budget_bytes=int(budget_gib * (1 << 30)), max_slots=max_slots,
+                   steps_per_graph=spg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tickets = [None] * count
+    done = [None] * count
+    nsub = 0
+    last_note = 0.0
+    while True:
+        now = time.perf_counter() - t0
+        if now - last_note > 5.0:
+            last_note = now
+            print("[serving] %.1f s: %d submitted, %d finished" % (now, nsub, sum(d is not None for d in done)),
+                  file=sys.stderr, flush=True)
+        while nsub < count and reqs[nsub][0] <= now:
+            wl = reqs[nsub][1]
+            tickets[nsub] = S.submit(wl.mesh, wl.U0, t_final)
+            nsub += 1
+        res, pend = S.pump()
+        for r in range(nsub):
+            if done[r] is None:
+                info = S.poll(tickets[r])
+                if info.state >= gdg.GDG_REQ_DONE:
+                    done[r] = info
+        if nsub == count and all(d is not None for d in done):
+            break
+        if res == 0 and pend == 0 and nsub < count:
+            time.sleep(max(0.0, reqs[nsub][0] - (time.perf_counter() - t0)))
+    makespan = time.perf_counter() - t0
+    failed = sum(1 for d in done if d.state != gdg.GDG_REQ_DONE)
+    # server clock starts at creation, just before t0: its done times are
+    # on the same clock as the arrivals up to that gap
+    tts = np.array([d.done_s - a for d, (a, _) in zip(done, reqs)])
+    steps = np.array([d.steps for d in done])
+    work = float(sum(d.ndofs * 3 * d.steps for d in done))
+    served = {"requests": count, "failed": failed, "makespan_s": makespan,
+              "p50_s": float(np.percentile(tts, 50)), "p99_s": float(np.percentile(tts, 99)),
+              "dof_stage_per_s": work / makespan, "steps_total": int(steps.sum()),
+              "precision": "mixed", "max_slots": max_slots, "steps_per_graph": spg,
+              "budget_gib": budget_gib}
+    S.close()
+    # -- one at a time, FP64, FIFO
+    service, work1 = [], 0.0
+    for k, (a, wl) in enumerate(reqs):
+        if k % 16 == 0:
+            print("[serving] one at a time: request %d of %d" % (k, count), file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        Sv = gdg.Solver.from_spec(wl.mesh, device="cuda:0")
+        Sv.upload(wl.U0)
+        st = Sv.run_to(t_final)
+        work1 += wl.mesh.ndofs * 3 * st.steps
+        Sv.download()
+        Sv.close()
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - s0)
+    end, tts1 = 0.0, []
+    for (a, _), sv in zip(reqs, service):
+        start = max(a, end)
+        end = start + sv
+        tts1.append(end - a)
+    tts1 = np.array(tts1)
+    single = {"p50_s": float(np.percentile(tts1, 50)), "p99_s": float(np.percentile(tts1, 99)),
+              "makespan_s": end, "dof_stage_per_s": work1 / end, "precision": "fp64",
+              "busy_s": float(sum(service))}
+    return {"trace": "%d requests, 2D Q1 n x n cells with n log-uniform in [32, %d], four-quadrant Riemann data, "
+                     "outflow, t_final %.3g, Poisson arrivals at 20/s" % (count, n_max, t_final),
+            "batched": served, "one_at_a_time_fp64": single}
+
+
 def cpu_baseline(name, budget_s):
     """The oracle, as it stands, on a bounded sample of the same workload."""
     import oracle
@@ -230,6 +316,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision line")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--serving-requests", type=int, default=32)
+    ap.add_argument("--serving-nmax", type=int, default=96)
+    ap.add_argument("--serving-tfinal", type=float, default=0.1)
+    ap.add_argument("--serving-budget-gib", type=float, default=4.0)
+    ap.add_argument("--serving-slots", type=int, default=64)
     ap.add_argument("--host-driven", action="store_true",
                     help="run every step host-driven (no captured graphs), e.g. under counter collection")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
@@ -302,6 +394,9 @@ def main():
                          "kernels_ms_per_launch": {k: (v[0] / v[1] if v[1] else None)
                                                    for k, v in mprof.items() if not k.startswith("_")},
                          "vs_fp64_gpu": cmp}
+    if not args.no_serving:
+        line["serving"] = serving(args.serving_requests, args.serving_nmax, args.serving_tfinal,
+                                  args.serving_budget_gib, args.serving_slots, 8)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     print(json.dumps(line), flush=True)

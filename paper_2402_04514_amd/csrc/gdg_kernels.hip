@@ -244,6 +244,79 @@ __device__ __forceinline__ double ls_slow(double g, const double *U, const doubl
   return l;
 }
 
+// For gamma = 7/5 the bracket is narrowed on
+//   phi(l) = (rho eps)^5 - s^5 rho^12,   rho eps = rho E - |m|^2 / 2,
+// at V = U + l P, which has the sign of psi wherever rho > 0 (both sides of
+// eps >= s rho^(7/5) multiplied by rho and raised to the fifth power), so the
+// same feasible interval [0, l*] is found with multiplies instead of the
+// power function.  phi is not concave, so the steps are those of the Illinois
+// variant of regula falsi (the end kept twice in a row has its value halved),
+// with a bisection whenever two steps did not halve the bracket; the bracket
+// is kept by sign down to a width of 1e-14 and its feasible end returned.
+// Returns false when the powers leave the range where they decide the sign
+// reliably; the caller then uses psi.
+template <int D>
+__device__ __forceinline__ double ls_phi75(const double *U, const double *P, double s5, double l) {
+  double V[D + 2];
+  for (int c = 0; c < D + 2; ++c) V[c] = U[c] + l * P[c];
+  double m2 = 0.0;
+  for (int e = 0; e < D; ++e) m2 += V[1 + e] * V[1 + e];
+  const double re = V[0] * V[D + 1] - 0.5 * m2;
+  const double r3 = V[0] * V[0] * V[0], r6 = r3 * r3;
+  return pow5(re) - s5 * (r6 * r6);
+}
+
+template <int D>
+__device__ __forceinline__ bool ls_slow75(const double *U, const double *P, double s5, double lhi, double *out) {
+  double pr = ls_phi75<D>(U, P, s5, lhi);
+  double pl = ls_phi75<D>(U, P, s5, 0.0);
+  // both ends must be decided: finite, and s^5 rho^12 at both ends well above the underflow range
+  const double rl = U[0], rh = U[0] + lhi * P[0];
+  const double rm = rl < rh ? rl : rh;
+  const double rm3 = rm * rm * rm, rm6 = rm3 * rm3;
+  if (!(isfinite(pr) && isfinite(pl)) || !(s5 * rm6 * rm6 > 1e-290)) return false;
+  if (pr >= 0.0) { *out = lhi; return true; }
+  if (pl <= 0.0) { *out = 0.0; return true; }
+  double l = 0.0, r = lhi, w2 = lhi;
+  int side = 0;
+  for (int it = 0; it < 100; ++it) {
+    const double w = r - l;
+    if (w <= 1e-14) break;
+    double x;
+    if ((it & 1) == 0 && it > 0 && w > 0.5 * w2) {
+      x = 0.5 * (l + r);  // two steps without halving the bracket
+    } else {
+      x = (l * pr - r * pl) / (pr - pl);
+      if (!(x > l && x < r)) x = 0.5 * (l + r);
+    }
+    if ((it & 1) == 0) w2 = w;
+    const double px = ls_phi75<D>(U, P, s5, x);
+    if (px >= 0.0) {
+      l = x;
+      pl = px;
+      if (side == 1) pr *= 0.5;
+      side = 1;
+    } else {
+      r = x;
+      pr = px;
+      if (side == -1) pl *= 0.5;
+      side = -1;
+    }
+  }
+  *out = l;
+  return true;
+}
+
+// Bracketing part of the line search after ls_fast found the density limit
+// lhi infeasible for the entropy bound.
+template <int D>
+__device__ __forceinline__ double ls_root(const KArgs &A, const double *U, const double *P, double smin, double smin5,
+                                          double lhi) {
+  double l;
+  if (A.g75 && smin5 > 0.0 && ls_slow75<D>(U, P, smin5, lhi, &l)) return l;
+  return ls_slow<D>(A.gamma, U, P, smin, lhi);
+}
+
 // Line search of Sec. 5.4: the largest l in [0, 1] with U + l P in B, P = sc Av.
 template <int D>
 __device__ __forceinline__ double line_search(const KArgs &A, const double *U, const double *Av, double sc,
@@ -251,7 +324,7 @@ __device__ __forceinline__ double line_search(const KArgs &A, const double *U, c
   double P[D + 2], lhi;
   for (int c = 0; c < D + 2; ++c) P[c] = sc * Av[c];
   if (ls_fast<D>(A, U, P, rmin, rmax, smin, smin5, &lhi)) return lhi;
-  return ls_slow<D>(A.gamma, U, P, smin, lhi);
+  return ls_root<D>(A, U, P, smin, smin5, lhi);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
@@ -854,8 +927,8 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
     double li, lj;
     const bool oki = ls_fast<D>(A, Li, Pi, rmin, rmax, smin, smin5, &li);
     const bool okj = ls_fast<D>(A, Lj, Pj, rminj, rmaxj, sj, A.g75 ? pow5(sj) : 0.0, &lj);
-    if (!oki) li = ls_slow<D>(A.gamma, Li, Pi, smin, li);
-    if (!okj) lj = ls_slow<D>(A.gamma, Lj, Pj, sj, lj);
+    if (!oki) li = ls_root<D>(A, Li, Pi, smin, smin5, li);
+    if (!okj) lj = ls_root<D>(A, Lj, Pj, sj, A.g75 ? pow5(sj) : 0.0, lj);
     const double l = fmin(li, lj);
     for (int q = 0; q < M; ++q) acc[q] += l * Aij[q];
     if (pass == 0) A.l1[s] = l;

@@ -191,17 +191,22 @@ def blast(cells: int = 128, gamma: float = GAMMA) -> Workload:
     return Workload("blast_q1_%d" % cells, ms, U, steps=200)
 
 
-def serving_requests(count: int = 256, seed0: int = 1000, arrival_seed: int = 7,
-                     rate: float = 20.0):
-    """(arrival time, cells per side, quadrant seed base) of each request."""
+def serving_trace(count: int = 256, n_min: int = 32, n_max: int = 512, seed0: int = 1000,
+                  arrival_seed: int = 7, rate: float = 20.0):
+    """Requests of the serving workload: (arrival time, cells per side, state
+    seed base).  Arrivals are a Poisson process of the given rate (cumulative
+    Exp(1/rate) gaps from SplitMix64(arrival_seed)); request r draws its size
+    log-uniformly in [n_min, n_max] from SplitMix64(seed0 + r), and its four
+    quadrant states from seed base 4 (seed0 + r), so that no two requests share
+    a quadrant's generator."""
     arr = SplitMix64(arrival_seed)
     t = 0.0
     out = []
     for r in range(count):
         t += -math.log(1.0 - arr.uniform()) / rate
         g = SplitMix64(seed0 + r)
-        n = int(round(32.0 * 16.0 ** g.uniform()))
-        out.append((t, n, seed0 + r))
+        n = int(round(n_min * (n_max / n_min) ** g.uniform()))
+        out.append((t, n, 4 * (seed0 + r)))
     return out
 
 
