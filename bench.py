@@ -10,8 +10,16 @@ state resident in HBM before the timed region starts.
 
 Prints one JSON line.  Besides the contract fields it carries
   roofline      the dominant kernel's algorithmic bytes per launch over its
-                average duration (HIP events on the library's stream, timed
-                region only), against the 8 TB/s HBM peak;
+                average duration (HIP events on the library's stream, over a
+                region of host-driven steps right after the timed one),
+                against the 8 TB/s HBM peak; `traffic` from the committed
+                FETCH_SIZE / WRITE_SIZE profile of the same kernel source;
+  mixed         the mixed-precision variant on the same workload, and its L1
+                difference from FP64 at equal time levels, beside the growth
+                of a 1e-13 input perturbation under FP64 alone;
+  serving       p50 / p99 time to solution and aggregate throughput of the
+                batched request server on a Poisson trace of small 2D
+                problems, against FIFO one-at-a-time FP64;
   cpu_baseline  the CPU oracle timed on this host's cores on a bounded sample.
 """
 from __future__ import annotations
@@ -190,7 +198,7 @@ def mixed_vs_fp64(name, steps):
 
 def serving(count, n_max, t_final, budget_gib, max_slots, spg):
     """The serving workload on a trace of `count` requests (2D Q1 four-quadrant
-    Riemann problems of n x n cells, n log-uniform in [32, n_max], outflow,
+    Riemann problems of n x n cells, n log-uniform in [32, n_max], slip walls,
     run to t_final; Poisson arrivals at 20 per second), served in real time by
     the batched server (mixed precision), and the same trace served FIFO one at
     a time on the FP64 single-mesh path (each request's service time measured
@@ -202,7 +210,7 @@ def serving(count, n_max, t_final, budget_gib, max_slots, spg):
     from paper_2402_04514_amd import workloads as W
 
     trace = W.serving_trace(count, n_max=n_max)
-    reqs = [(a, W.quadrant(cells=n, degree=1, seed_base=sb)) for a, n, sb in trace]
+    reqs = [(a, W.quadrant(cells=n, degree=1, seed_base=sb, bc=W.BC_SLIP)) for a, n, sb in trace]
     # -- batched, continuous admission, real time
     S = gdg.Server(2, 1, gdg.GDG_MIXED, budget_bytes=int(budget_gib * (1 << 30)), max_slots=max_slots,
                    steps_per_graph=spg)
@@ -248,7 +256,7 @@ def serving(count, n_max, t_final, budget_gib, max_slots, spg):
     # -- one at a time, FP64, FIFO
     service, work1 = [], 0.0
     for k, (a, wl) in enumerate(reqs):
-        if k % 16 == 0:
+        if k % 8 == 0:
             print("[serving] one at a time: request %d of %d" % (k, count), file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         s0 = time.perf_counter()
@@ -270,7 +278,7 @@ def serving(count, n_max, t_final, budget_gib, max_slots, spg):
               "makespan_s": end, "dof_stage_per_s": work1 / end, "precision": "fp64",
               "busy_s": float(sum(service))}
     return {"trace": "%d requests, 2D Q1 n x n cells with n log-uniform in [32, %d], four-quadrant Riemann data, "
-                     "outflow, t_final %.3g, Poisson arrivals at 20/s" % (count, n_max, t_final),
+                     "slip walls, t_final %.3g, Poisson arrivals at 20/s" % (count, n_max, t_final),
             "batched": served, "one_at_a_time_fp64": single}
 
 
@@ -318,8 +326,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision line")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--serving-requests", type=int, default=32)
-    ap.add_argument("--serving-nmax", type=int, default=96)
-    ap.add_argument("--serving-tfinal", type=float, default=0.1)
+    ap.add_argument("--serving-nmax", type=int, default=128)
+    ap.add_argument("--serving-tfinal", type=float, default=0.25)
     ap.add_argument("--serving-budget-gib", type=float, default=4.0)
     ap.add_argument("--serving-slots", type=int, default=64)
     ap.add_argument("--host-driven", action="store_true",

@@ -172,8 +172,8 @@ def vortex(cells: int = 256, gamma: float = GAMMA) -> Workload:
 
 
 def quadrant(cells: int = 1024, degree: int = 2, seed_base: int = 240204514,
-             gamma: float = GAMMA) -> Workload:
-    ms = MeshSpec(2, degree, (cells, cells), (0.0, 0.0), (1.0, 1.0), (BC_OUTFLOW,) * 4)
+             gamma: float = GAMMA, bc: int = BC_OUTFLOW) -> Workload:
+    ms = MeshSpec(2, degree, (cells, cells), (0.0, 0.0), (1.0, 1.0), (bc,) * 4)
     _, xc = node_coords(ms)
     q = (xc[:, 0] >= 0.5).astype(int) + 2 * (xc[:, 1] >= 0.5).astype(int)
     st = np.array(quadrant_states(seed_base))
@@ -198,7 +198,11 @@ def serving_trace(count: int = 256, n_min: int = 32, n_max: int = 512, seed0: in
     Exp(1/rate) gaps from SplitMix64(arrival_seed)); request r draws its size
     log-uniformly in [n_min, n_max] from SplitMix64(seed0 + r), and its four
     quadrant states from seed base 4 (seed0 + r), so that no two requests share
-    a quadrant's generator."""
+    a quadrant's generator.  The requests are run in a closed box (slip walls):
+    with do-nothing outflow boundaries, random quadrant velocities that point
+    into the box at a corner keep injecting mass there (density grows without
+    bound well before t = 0.25), which is a property of that boundary data,
+    not of a solver."""
     arr = SplitMix64(arrival_seed)
     t = 0.0
     out = []
