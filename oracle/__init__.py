@@ -74,6 +74,8 @@ def lib():
             getattr(L, fn).argtypes = [C.c_void_p]
         L.or_volume.restype = C.c_double
         L.or_volume.argtypes = [C.c_void_p]
+        L.or_set_reference_volume.restype = None
+        L.or_set_reference_volume.argtypes = [C.c_void_p, C.c_double]
         L.or_csr.argtypes = [C.c_void_p, C.POINTER(C.c_long), C.POINTER(C.c_long), _DP, _DP,
                              C.POINTER(C.c_int)]
         L.or_lumped.argtypes = [C.c_void_p, _DP]
@@ -139,6 +141,11 @@ class Mesh:
     @property
     def volume(self) -> float:
         return lib().or_volume(self._h)
+
+    def set_reference_volume(self, vol: float):
+        """|Omega| in hhat_i = (m_i/|Omega|)^(1/d) (eq. ViscMin, ViscMinConst2):
+        a sub-box of a larger domain passes that domain's volume."""
+        lib().or_set_reference_volume(self._h, float(vol))
 
     def coords(self) -> np.ndarray:
         x = np.zeros((self.ndofs, self.dim))

@@ -308,13 +308,27 @@ or_setup *or_create(int dim, int deg, const long *cells, const double *lo, const
     }
   }
 
-  long nnz = 0, nb = 0;
+  /* row lengths first, so that the rows can be filled independently */
   for (long i = 0; i < N; ++i) {
     long K = i / nloc;
     int a = (int)(i % nloc), ai[3];
     local_multi(S, a, ai);
-    S->rowptr[i] = nnz;
-    S->bptr[i] = nb;
+    long g = nloc, bnd = 0;
+    for (int f = 0; f < 2 * dim; ++f) {
+      int e = f / 2, side = f % 2;
+      if (ai[e] != side * deg) continue;
+      if (neighbour(S, K, f) >= 0) g += nloc / S->nb1;
+      else ++bnd;
+    }
+    S->rowptr[i + 1] = S->rowptr[i] + g;
+    S->bptr[i + 1] = S->bptr[i] + bnd;
+  }
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (long i = 0; i < N; ++i) {
+    long K = i / nloc;
+    int a = (int)(i % nloc), ai[3];
+    local_multi(S, a, ai);
+    long nnz = S->rowptr[i], nb = S->bptr[i];
     S->mi[i] = mloc[a];
     for (int b = 0; b < nloc; ++b) {
       long j = K * nloc + b;
@@ -352,8 +366,6 @@ or_setup *or_create(int dim, int deg, const long *cells, const double *lo, const
       }
     }
   }
-  S->rowptr[N] = nnz;
-  S->bptr[N] = nb;
   free(Mloc);
   free(mloc);
   return S;
@@ -366,6 +378,14 @@ long or_num_dofs(const or_setup *S) { return S->ndofs; }
 long or_nnz(const or_setup *S) { return S->rowptr[S->ndofs]; }
 long or_nbnd(const or_setup *S) { return S->bptr[S->ndofs]; }
 double or_volume(const or_setup *S) { return S->vol; }
+
+/* The volume |Omega| that the mesh-size measure hhat_i = (m_i / |Omega|)^(1/d)
+ * of eq. ViscMin and eq. ViscMinConst2 refers to.  By default the box itself;
+ * a sub-box cut out of a larger domain passes that domain's volume, so that
+ * its rows get the constants of the full problem. */
+void or_set_reference_volume(or_setup *S, double vol) {
+  if (vol > 0.0) S->vol = vol;
+}
 
 void or_csr(const or_setup *S, long *rowptr, long *col, double *c, double *mij, int *kind) {
   long N = S->ndofs, nnz = S->rowptr[N];

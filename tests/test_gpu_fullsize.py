@@ -1,0 +1,157 @@
+"""GPU parity at the full sizes of the benchmark workloads, in the launch
+configuration that bench.py times (gdg_run_to: device-driven captured graphs).
+
+* vortex, 256 x 256 Q1 (262,144 dofs): the oracle runs the whole mesh, so
+  every dof is compared after several steps (1e-10 of the component scale).
+* four-quadrant Riemann data, 1024 x 1024 Q2 (9.4 M dofs), and the 3D blast,
+  128^3 Q1 (16.8 M dofs): one step on the GPU over the whole mesh.  The time
+  step is checked against the oracle's CFL rule over the whole mesh
+  (or_tau_rows on every row, 1e-13).  The state is checked on sampled patches:
+  the oracle runs a sub-box of cells around each sample with the oracle's
+  time step as a fixed step and the full domain's volume in the mesh-size
+  measure of the minimal viscosity and the bound relaxation (eq. ViscMin,
+  ViscMinConst2); a dof of one SSP-RK3 step depends only on the
+  cells within a few stencil rings (each stage reaches through the limiter,
+  the bounds and the cell solve about four cells), so the cells at least
+  HALO cells away from every cut side of the sub-box carry the full-mesh
+  result and are compared with the GPU's, to 1e-11 of the component scale.
+  Samples cover the centre, the boundary (corners, edges, faces) and seeded
+  interior points.
+"""
+import numpy as np
+import pytest
+
+from paper_2402_04514_amd import gdg
+from paper_2402_04514_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+HALO = 14
+CORE = 4
+
+
+def _say(msg):
+    print("[gpu-fullsize] " + msg, flush=True)
+
+
+def _scale(U):
+    s = np.abs(U).max(axis=1, keepdims=True)
+    return np.maximum(s, 1e-3 * s.max())
+
+
+def _gpu_steps(ms, U0, steps):
+    S = gdg.Solver.from_spec(ms)
+    S.upload(U0)
+    st = S.run_to(1e30, max_steps=steps)
+    out = S.download()
+    S.close()
+    return out, st
+
+
+def _patch(ms, lo_cell, width):
+    """Sub-box of `width` cells per axis starting at cell lo_cell: its mesh
+    spec (true boundary kinds where it touches the box, outflow on cut sides),
+    the global dof index of each patch dof, and a mask of the core dofs."""
+    d, nloc = ms.dim, ms.nloc
+    h = [(ms.hi[e] - ms.lo[e]) / ms.cells[e] for e in range(d)]
+    bc, lo, hi = [], [], []
+    for e in range(d):
+        lo.append(ms.lo[e] + lo_cell[e] * h[e])
+        hi.append(lo[e] + width[e] * h[e])
+        full = width[e] == ms.cells[e]
+        for side in range(2):
+            touches = lo_cell[e] == 0 if side == 0 else lo_cell[e] + width[e] == ms.cells[e]
+            kind = ms.bc[2 * e + side]
+            if full or (touches and kind != W.BC_PERIODIC):
+                bc.append(kind)
+            else:
+                bc.append(W.BC_OUTFLOW)
+    pm = W.MeshSpec(d, ms.degree, tuple(width), tuple(lo), tuple(hi), tuple(bc))
+    pc = np.arange(pm.ncells)
+    gcell = np.zeros(pm.ncells, dtype=np.int64)
+    core = np.ones(pm.ncells, dtype=bool)
+    stride = 1
+    r = pc.copy()
+    for e in range(d):
+        k = r % width[e]
+        r //= width[e]
+        gcell += (lo_cell[e] + k) * stride
+        stride *= ms.cells[e]
+        cut_lo = not (width[e] == ms.cells[e] or (lo_cell[e] == 0 and ms.bc[2 * e] != W.BC_PERIODIC))
+        cut_hi = not (width[e] == ms.cells[e] or
+                      (lo_cell[e] + width[e] == ms.cells[e] and ms.bc[2 * e + 1] != W.BC_PERIODIC))
+        if cut_lo:
+            core &= k >= HALO
+        if cut_hi:
+            core &= k < width[e] - HALO
+    gdof = (gcell[:, None] * nloc + np.arange(nloc)[None, :]).reshape(-1)
+    return pm, gdof, np.repeat(core, nloc)
+
+
+def _samples(ms, rng, extra):
+    """Cell corners of the sample sub-boxes: the centre, the low and high
+    corners of the box, the middle of each low face, the centre shifted along
+    each axis, and seeded interior points."""
+    d, n = ms.dim, ms.cells
+    w = 2 * HALO + CORE
+    clip = lambda v, e: int(min(max(v, 0), n[e] - w))
+    out = [tuple(clip(n[e] // 2 - w // 2, e) for e in range(d)),
+           tuple(0 for e in range(d)),
+           tuple(n[e] - w for e in range(d))]
+    for f in range(d):
+        out.append(tuple(0 if e == f else clip(n[e] // 2 - w // 2, e) for e in range(d)))
+        # the centre shifted along one axis: the fronts leaving the centre
+        out.append(tuple(clip(n[e] // 2 - w // 2 + (3 * CORE if e == f else 0), e) for e in range(d)))
+    for _ in range(extra):
+        out.append(tuple(int(rng.integers(0, n[e] - w + 1)) for e in range(d)))
+    return out, (w,) * d
+
+
+def _check_patches(oracle, ms, U0, Ug, tau, samples, width):
+    prm = oracle.params(degree=ms.degree)
+    sc = _scale(U0)
+    worst = 0.0
+    for lo_cell in samples:
+        pm, gdof, core = _patch(ms, lo_cell, width)
+        Mp = oracle.Mesh(pm.dim, pm.degree, pm.cells, pm.lo, pm.hi, pm.bc)
+        Mp.set_reference_volume(float(np.prod(np.subtract(ms.hi, ms.lo))))
+        Up, dtp, nres, st = Mp.step(prm, np.ascontiguousarray(U0[:, gdof]), dt_fixed=tau)
+        assert st == 0 and nres == 0 and dtp == tau, (lo_cell, st, nres)
+        err = (np.abs(Ug[:, gdof[core]] - Up[:, core]) / sc).max()
+        _say("  patch at %s: %d core dofs, worst %.2e" % (lo_cell, int(core.sum()), err))
+        assert err <= 1e-11, (lo_cell, err)
+        worst = max(worst, err)
+    return worst
+
+
+def test_vortex_full_mesh_several_steps(oracle):
+    wl = W.vortex(256)
+    ms = wl.mesh
+    _say("vortex 256^2: 10 steps through run_to, whole mesh")
+    Ug, st = _gpu_steps(ms, wl.U0, 10)
+    M = oracle.Mesh(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc)
+    Uo, t_o, n_o = M.run_to(oracle.params(degree=1), wl.U0, 1e30, max_steps=10)
+    assert st.steps == n_o == 10
+    assert st.t == pytest.approx(t_o, rel=1e-13)
+    err = (np.abs(Ug - Uo) / _scale(wl.U0)).max()
+    _say("  worst %.2e" % err)
+    assert err <= 1e-10
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", ["quadrant", "blast"])
+def test_full_size_one_step_sampled(oracle, name):
+    wl = W.CONFIGS[name]()
+    ms = wl.mesh
+    _say("%s: one GPU step through run_to on %d dofs" % (wl.name, ms.ndofs))
+    Ug, st = _gpu_steps(ms, wl.U0, 1)
+    assert st.steps == 1 and st.restarts == 0
+    eps = Ug[-1] - 0.5 * np.sum(Ug[1:-1] ** 2, 0) / Ug[0]
+    assert np.all(Ug[0] > 0) and np.all(eps > 0)
+    _say("  oracle CFL bound over the whole mesh")
+    M = oracle.Mesh(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc)
+    prm = oracle.params(degree=ms.degree)
+    tau = prm.cfl * M.tau_rows(prm, wl.U0).min()
+    del M
+    assert st.last_dt == pytest.approx(tau, rel=1e-13)
+    samples, width = _samples(ms, np.random.default_rng(240204514), extra=3)
+    _check_patches(oracle, ms, wl.U0, Ug, tau, samples, width)
