@@ -35,6 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "dof-stage updates/s FP64 vs mixed at stated L1 error; p50/p99 solve latency"
+CELLS_OVERRIDE = 0  # --cells: the same problem on another mesh (not a benchmark line)
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
@@ -110,6 +111,9 @@ def run_gpu(name, steps, warmup, host_driven=False, precision=0):
     from paper_2402_04514_amd import workloads as W
 
     kw, desc, _, _ = WORKLOADS[name]
+    if CELLS_OVERRIDE:
+        kw = dict(kw, cells=CELLS_OVERRIDE)
+        desc = desc + " [cells per side overridden: %d]" % CELLS_OVERRIDE
     wl = W.CONFIGS[name](**kw)
     S = gdg.Solver.from_spec(wl.mesh, _params(gdg, wl.mesh.degree, precision), device="cuda:0")
     S.upload(wl.U0)
@@ -330,11 +334,15 @@ def main():
     ap.add_argument("--serving-tfinal", type=float, default=0.25)
     ap.add_argument("--serving-budget-gib", type=float, default=4.0)
     ap.add_argument("--serving-slots", type=int, default=64)
+    ap.add_argument("--cells", type=int, default=0,
+                    help="run the workload on another number of cells per side (scaling study only)")
     ap.add_argument("--host-driven", action="store_true",
                     help="run every step host-driven (no captured graphs), e.g. under counter collection")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
+    global CELLS_OVERRIDE
+    CELLS_OVERRIDE = args.cells
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build runs the hot path on a single MI355X; "

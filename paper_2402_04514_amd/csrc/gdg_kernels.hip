@@ -553,9 +553,19 @@ __device__ __forceinline__ void sweep1_body(const KArgs &A, const double *__rest
     double rmin = INFINITY, rmax = -INFINITY, smin = INFINITY;
     // bar state with the smallest rescaled entropy, ranked by stilde_key
     double kbar = INFINITY, ebar = 0.0, rbar = 1.0;
+    // the next slot's kind and column are loaded one slot ahead, so that the
+    // dependent gather of the neighbour does not wait for them
+    const int64_t s0 = blk * A.W * A.R + lane;
+    uint8_t meta_n = A.meta[s0];
+    int32_t col_n = A.col[s0];
     for (int t = 0; t < A.W; ++t) {
-      const int64_t s = (blk * A.W + t) * A.R + lane;
-      const uint8_t meta = A.meta[s];
+      const int64_t s = s0 + (int64_t)t * A.R;
+      const uint8_t meta = meta_n;
+      const int32_t colv = col_n;
+      if (t + 1 < A.W) {
+        meta_n = A.meta[s + A.R];
+        col_n = A.col[s + A.R];
+      }
       const int kind = meta & 7;
       if (kind == SK_PAD) { A.dL[s] = 0.0; continue; }
       double c[D];
@@ -583,7 +593,7 @@ __device__ __forceinline__ void sweep1_body(const KArgs &A, const double *__rest
         for (int q = 0; q < M; ++q) S[q] += (Acc)(fj[q] - fi[q]);
         continue;
       }
-      const int64_t j = A.col[s];
+      const int64_t j = colv;
       Node<D> nj;
       load_node<D>(A, U, j, nj);
       rmin = fmin(rmin, nj.U[0]);
@@ -708,9 +718,17 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
     Acc accF[M];
     for (int c = 0; c < M; ++c) { accL[c] = accH[c] = 0.0; accF[c] = 0; }
     double rmin = INFINITY, rmax = -INFINITY, smin = INFINITY;
+    const int64_t s0 = blk * A.W * A.R + lane;
+    uint8_t meta_n = A.meta[s0];
+    int32_t col_n = A.col[s0];
     for (int t = 0; t < A.W; ++t) {
-      const int64_t s = (blk * A.W + t) * A.R + lane;
-      const uint8_t meta = A.meta[s];
+      const int64_t s = s0 + (int64_t)t * A.R;
+      const uint8_t meta = meta_n;
+      const int32_t colv = col_n;
+      if (t + 1 < A.W) {
+        meta_n = A.meta[s + A.R];
+        col_n = A.col[s + A.R];
+      }
       const int kind = meta & 7;
       if (kind == SK_PAD) continue;
       double c[D];
@@ -743,7 +761,7 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
         smin = fmin(smin, pow(bar[0], -g) * eps_of<D>(bar));
         continue;
       }
-      const int64_t j = A.col[s];
+      const int64_t j = colv;
       rmin = fmin(rmin, A.q[j]);
       rmax = fmax(rmax, A.q[N + j]);
       smin = fmin(smin, A.q[2 * N + j]);
@@ -897,9 +915,17 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
   double acc[M], Ab[M];
   for (int q = 0; q < M; ++q) acc[q] = Ab[q] = 0.0;
   int64_t gslot = -1;
+  const int64_t s0 = blk * A.W * A.R + lane;
+  uint8_t meta_n = A.meta[s0];
+  int32_t col_n = A.col[s0];
   for (int t = 0; t < A.W; ++t) {
-    const int64_t s = (blk * A.W + t) * A.R + lane;
-    const uint8_t meta = A.meta[s];
+    const int64_t s = s0 + (int64_t)t * A.R;
+    const uint8_t meta = meta_n;
+    const int32_t colv = col_n;
+    if (t + 1 < A.W) {
+      meta_n = A.meta[s + A.R];
+      col_n = A.col[s + A.R];
+    }
     const int kind = meta & 7;
     if (kind == SK_PAD) continue;
     const double d = A.dL[s];
@@ -908,7 +934,7 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
       if (gslot < 0) gslot = s;
       continue;
     }
-    const int64_t j = A.col[s];
+    const int64_t j = colv;
     if (j == i) continue;  // A_ii = 0
     double Aij[M];
     pair_flux<D, NLOC>(A, U, j, meta, a, Ui, dUi, Ni, hpk, tau, d, Aij);
