@@ -23,13 +23,17 @@
 
 #include "gdg_internal.h"
 
-// Occupancy targets (waves per SIMD) chosen by measurement: the sweeps gain
-// from a third wave, the limiter loses more to spills than it gains.
+// Occupancy targets (waves per SIMD) chosen by measurement: sweep 2 gains
+// from a third wave; sweep 1 keeps its neighbour prefetch in registers at
+// two; the limiter loses more to spills than it would gain.
 #ifndef GDG_WPE_LIMIT
 #define GDG_WPE_LIMIT 1
 #endif
 #ifndef GDG_WPE_SWEEP
 #define GDG_WPE_SWEEP 3
+#endif
+#ifndef GDG_WPE_SWEEP1
+#define GDG_WPE_SWEEP1 2
 #endif
 
 namespace gdg {
@@ -553,23 +557,42 @@ __device__ __forceinline__ void sweep1_body(const KArgs &A, const double *__rest
     double rmin = INFINITY, rmax = -INFINITY, smin = INFINITY;
     // bar state with the smallest rescaled entropy, ranked by stilde_key
     double kbar = INFINITY, ebar = 0.0, rbar = 1.0;
-    // the next slot's kind and column are loaded one slot ahead, so that the
-    // dependent gather of the neighbour does not wait for them
+    // software pipeline over the slots: the kind and column two slots ahead,
+    // the coefficients and the neighbour's node data one slot ahead, so that
+    // the gathers overlap the arithmetic of the current slot (pad and ghost
+    // slots name a valid row, so their prefetch is harmless)
     const int64_t s0 = blk * A.W * A.R + lane;
     uint8_t meta_n = A.meta[s0];
     int32_t col_n = A.col[s0];
+    double c_n[D];
+    load_c<D, MX>(A, s0, c_n);
+    Node<D> nj_n;
+    load_node<D>(A, U, col_n, nj_n);
+    uint8_t meta_nn = 0;
+    int32_t col_nn = 0;
+    if (A.W > 1) {
+      meta_nn = A.meta[s0 + A.R];
+      col_nn = A.col[s0 + A.R];
+    }
     for (int t = 0; t < A.W; ++t) {
       const int64_t s = s0 + (int64_t)t * A.R;
       const uint8_t meta = meta_n;
       const int32_t colv = col_n;
+      double c[D];
+      for (int e = 0; e < D; ++e) c[e] = c_n[e];
+      const Node<D> nj = nj_n;
       if (t + 1 < A.W) {
-        meta_n = A.meta[s + A.R];
-        col_n = A.col[s + A.R];
+        meta_n = meta_nn;
+        col_n = col_nn;
+        load_c<D, MX>(A, s + A.R, c_n);
+        load_node<D>(A, U, col_n, nj_n);
+        if (t + 2 < A.W) {
+          meta_nn = A.meta[s + 2 * A.R];
+          col_nn = A.col[s + 2 * A.R];
+        }
       }
       const int kind = meta & 7;
       if (kind == SK_PAD) { A.dL[s] = 0.0; continue; }
-      double c[D];
-      load_c<D, MX>(A, s, c);
       double nc2 = 0.0;
       for (int e = 0; e < D; ++e) nc2 += c[e] * c[e];
       const double nc = sqrt(nc2);
@@ -594,8 +617,6 @@ __device__ __forceinline__ void sweep1_body(const KArgs &A, const double *__rest
         continue;
       }
       const int64_t j = colv;
-      Node<D> nj;
-      load_node<D>(A, U, j, nj);
       rmin = fmin(rmin, nj.U[0]);
       rmax = fmax(rmax, nj.U[0]);
       smin = fmin(smin, nj.st);
@@ -654,7 +675,7 @@ __device__ __forceinline__ void sweep1_body(const KArgs &A, const double *__rest
 }
 
 template <int D, int DEG, bool MX>
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_SWEEP))) void k_sweep1(
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_SWEEP1))) void k_sweep1(
     KArgs A, const double *__restrict__ U, int stage) {
   sweep1_body<D, DEG, MX>(A, U, stage, xcd_block(blockIdx.x, A.nblocks));
 }
@@ -718,6 +739,8 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
     Acc accF[M];
     for (int c = 0; c < M; ++c) { accL[c] = accH[c] = 0.0; accF[c] = 0; }
     double rmin = INFINITY, rmax = -INFINITY, smin = INFINITY;
+    // the next slot's kind and column are loaded one slot ahead, so that the
+    // dependent gather of the neighbour does not wait for them
     const int64_t s0 = blk * A.W * A.R + lane;
     uint8_t meta_n = A.meta[s0];
     int32_t col_n = A.col[s0];
@@ -1024,7 +1047,7 @@ __global__ __launch_bounds__(kBlockThreads) void kb_prim(const BatchList *L, int
 }
 
 template <int D, int DEG, bool MX>
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_SWEEP))) void kb_sweep1(
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_SWEEP1))) void kb_sweep1(
     const BatchList *L, int stage) {
   for_tiles(L, [&](const BatchEntry &E, int64_t blk) { sweep1_body<D, DEG, MX>(E.A, E.sb[stage].in, stage, blk); });
 }
