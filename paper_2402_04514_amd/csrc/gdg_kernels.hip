@@ -959,12 +959,24 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
     }
     const int64_t j = colv;
     if (j == i) continue;  // A_ii = 0
+    // A pair whose flux is exactly zero adds l * 0 whatever l is: pass 1
+    // records l = 1 for it and skips its searches, pass 2 skips every pair
+    // that pass 1 accepted whole (nothing of it remains).
+    double rest = 1.0;
+    if (pass == 1) {
+      rest = 1.0 - A.l1[s];
+      if (rest == 0.0) continue;
+    }
     double Aij[M];
     pair_flux<D, NLOC>(A, U, j, meta, a, Ui, dUi, Ni, hpk, tau, d, Aij);
-    if (pass == 1) {
-      const double rest = 1.0 - A.l1[s];
-      for (int q = 0; q < M; ++q) Aij[q] = rest * Aij[q];
+    bool zero = true;
+    for (int q = 0; q < M; ++q) zero = zero && Aij[q] == 0.0;
+    if (zero) {
+      if (pass == 0) A.l1[s] = 1.0;
+      continue;
     }
+    if (pass == 1)
+      for (int q = 0; q < M; ++q) Aij[q] = rest * Aij[q];
     double Lj[M], Pi[M], Pj[M];
     const double scj = A.kscale[j];
     for (int q = 0; q < M; ++q) {
@@ -982,7 +994,10 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
     for (int q = 0; q < M; ++q) acc[q] += l * Aij[q];
     if (pass == 0) A.l1[s] = l;
   }
-  if (gslot >= 0) {
+  bool bzero = true;
+  for (int q = 0; q < M; ++q) bzero = bzero && Ab[q] == 0.0;
+  if (gslot >= 0 && bzero && pass == 0) A.l1[gslot] = 1.0;
+  if (gslot >= 0 && !bzero) {
     if (pass == 1) {
       const double rest = 1.0 - A.l1[gslot];
       for (int q = 0; q < M; ++q) Ab[q] = rest * Ab[q];
