@@ -87,6 +87,12 @@ struct KArgs {
   int32_t g75;      // gamma == 7/5: entropy comparisons by integer powers
   int32_t scheme, passes;
   int32_t mixed;    // 1: c_ij stored in FP32 and the flux / entropy-viscosity sums taken in FP32
+  // Order in which the row blocks of a 3D mesh are swept (0: block order).
+  // With whole x-lines of blocks, tiles of ty y-rows are swept z-plane by
+  // z-plane, so the block one z-plane back was swept nbx * ty blocks earlier
+  // (still in the XCD's L2) instead of a whole plane earlier.
+  int32_t tiled;
+  int64_t t_nbx, t_ny, t_nz, t_ty;
   // stencil
   int32_t *col;
   double *c;        // dim planes of nslots (FP64 precision)

@@ -335,11 +335,27 @@ __device__ __forceinline__ double line_search(const KArgs &A, const double *U, c
 // with its own L2.  Remapping the hardware block id so that every XCD sweeps
 // one contiguous range of row blocks keeps a block's face neighbours (the
 // blocks one cell row earlier) in the same L2.  A bijection of [0, nblocks).
-__device__ __forceinline__ int64_t xcd_block(int64_t hw, int64_t nblocks) {
+__device__ __forceinline__ int64_t xcd_position(int64_t hw, int64_t nblocks) {
   constexpr int64_t kX = 8;
   const int64_t q = nblocks / kX, r = nblocks % kX;
   const int64_t x = hw % kX, k = hw / kX;
   return x * q + (x < r ? x : r) + k;
+}
+
+// Row block at position L of the sweep order (a bijection of [0, nblocks)):
+// the block order itself, or for a tiled 3D mesh (KArgs::tiled) the order
+// tile by tile, z-plane by z-plane, y-row by y-row, x-block by x-block.
+__device__ __forceinline__ int64_t sweep_block(const KArgs &A, int64_t L) {
+  if (!A.tiled) return L;
+  const int64_t plane = A.t_nbx * A.t_ty;  // blocks of one tile in one z-plane
+  const int64_t tile = L / (plane * A.t_nz), rem = L % (plane * A.t_nz);
+  const int64_t z = rem / plane, rem2 = rem % plane;
+  const int64_t y = tile * A.t_ty + rem2 / A.t_nbx, bx = rem2 % A.t_nbx;
+  return bx + A.t_nbx * (y + A.t_ny * z);
+}
+
+__device__ __forceinline__ int64_t xcd_block(const KArgs &A, int64_t hw) {
+  return sweep_block(A, xcd_position(hw, A.nblocks));
 }
 
 // ---------------------------------------------------------------------------
@@ -351,7 +367,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_fill(KArgs A) {
   constexpr int NFACE = NLOC / NB;
   const int lane = threadIdx.x;
   if (lane >= A.R) return;
-  const int64_t blk = xcd_block(blockIdx.x, A.nblocks);
+  const int64_t blk = xcd_block(A, blockIdx.x);
   const int64_t i = blk * A.R + lane;
   const RefTables *T = A.ref;
   int t = 0;
@@ -677,7 +693,7 @@ __device__ __forceinline__ void sweep1_body(const KArgs &A, const double *__rest
 template <int D, int DEG, bool MX>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_SWEEP1))) void k_sweep1(
     KArgs A, const double *__restrict__ U, int stage) {
-  sweep1_body<D, DEG, MX>(A, U, stage, xcd_block(blockIdx.x, A.nblocks));
+  sweep1_body<D, DEG, MX>(A, U, stage, xcd_block(A, blockIdx.x));
 }
 
 // high-order viscosity of eq. HighOrderViscosity / ViscMin for a graph pair
@@ -861,7 +877,7 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
 template <int D, int DEG, bool MX>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_SWEEP))) void k_sweep2(
     KArgs A, StageBufs sb, int stage) {
-  sweep2_body<D, DEG, MX>(A, sb, stage, xcd_block(blockIdx.x, A.nblocks));
+  sweep2_body<D, DEG, MX>(A, sb, stage, xcd_block(A, blockIdx.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -1020,13 +1036,13 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
 template <int D, int DEG>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_LIMIT))) void k_limit(
     KArgs A, StageBufs sb, int pass, int final_pass) {
-  limit_body<D, DEG>(A, sb, pass, final_pass, xcd_block(blockIdx.x, A.nblocks));
+  limit_body<D, DEG>(A, sb, pass, final_pass, xcd_block(A, blockIdx.x));
 }
 
 // ---------------------------------------------------------------------------
 // Batched steps of the request server.  One persistent grid walks the row
 // blocks of all resident requests listed in device memory; each XCD takes one
-// contiguous range of the concatenated blocks (as xcd_block does for one
+// contiguous range of the concatenated blocks (as xcd_position does for one
 // mesh).  Every row block runs the same body as the single-mesh kernels, with
 // that request's arguments, so a request's arithmetic does not depend on what
 // else is resident.
@@ -1049,7 +1065,7 @@ __device__ __forceinline__ void for_tiles(const BatchList *L, F &&f) {
   const int64_t lo = nt * x / kX, hi = nt * (x + 1) / kX;
   for (int64_t t = lo + k; t < hi; t += per) {
     const int r = find_req(L, t);
-    f(L->e[r], t - L->tile_begin[r]);
+    f(L->e[r], sweep_block(L->e[r].A, t - L->tile_begin[r]));
   }
 }
 

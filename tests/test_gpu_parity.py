@@ -53,6 +53,9 @@ CASES = {
     "q1_3d_slip": lambda: quadrant_on(3, 1, (5, 4, 6), (2,) * 6),
     "q1_3d_mixed": lambda: quadrant_on(3, 1, (4, 4, 4), (0, 0, 1, 1, 2, 2), seed=3),
     "vortex_q1_32": lambda: (W.vortex(32).mesh, W.vortex(32).U0),
+    # whole x-lines of blocks: the 3D meshes swept tile by tile
+    "q1_3d_tiled": lambda: quadrant_on(3, 1, (16, 6, 5), (2, 2, 1, 1, 0, 0), seed=41),
+    "q2_3d_tiled": lambda: quadrant_on(3, 2, (4, 3, 3), (1,) * 6, seed=43),
 }
 
 
