@@ -607,70 +607,65 @@ __device__ __forceinline__ void sweep1_body(const KArgs &A, const double *__rest
           col_nn = A.col[s + 2 * A.R];
         }
       }
+      // One path for every slot kind, so that the loads of the next slot stay
+      // in flight across it: pad and diagonal slots have c = 0 (no flux, d = 0)
+      // and name row i (harmless in the extrema); a ghost slot's right state
+      // is the boundary state of Sec. 4.1.
       const int kind = meta & 7;
-      if (kind == SK_PAD) { A.dL[s] = 0.0; continue; }
+      const bool ghost = kind == SK_GHOST;
+      const int64_t j = colv;
       double nc2 = 0.0;
       for (int e = 0; e < D; ++e) nc2 += c[e] * c[e];
       const double nc = sqrt(nc2);
-      if (kind == SK_GHOST) {
-        double n[D];
-        const double inc = 1.0 / nc;
-        for (int e = 0; e < D; ++e) n[e] = c[e] * inc;
-        Node<D> gh;
-        ghost_node<D>(ni, meta >> 3, n, gh);
-        double ul = 0.0, ur = 0.0;
-        for (int e = 0; e < D; ++e) { ul += ni.u[e] * n[e]; ur += gh.u[e] * n[e]; }
-        double d = nc * lambda_plus(A, ul, ni.p, ni.a, ni.pal, ni.ip, ur, gh.p, gh.a, gh.pal, gh.ip);
-        A.dL[s] = d;
-        dsum += d;
-        double fj[M], fi[M];
-        flux_dot<D>(gh.U, gh.u, gh.p, c, fj);
-        flux_dot<D>(ni.U, ni.u, ni.p, c, fi);
-        Acc mc = 0;
-        for (int e = 0; e < D; ++e) mc += (Acc)gh.U[1 + e] * (Acc)c[e];
-        T += mc * (Acc)(gh.fs - ni.fs);
-        for (int q = 0; q < M; ++q) S[q] += (Acc)(fj[q] - fi[q]);
-        continue;
-      }
-      const int64_t j = colv;
+      const bool graph = kind != SK_PAD && !ghost && j != i && nc2 > 0.0;
+      const bool pair = graph || (ghost && nc2 > 0.0);
       rmin = fmin(rmin, nj.U[0]);
       rmax = fmax(rmax, nj.U[0]);
       smin = fmin(smin, nj.st);
-      if (j == i || nc == 0.0) { A.dL[s] = 0.0; continue; }
-      // d^L_ij from the lower index, so d_ij = d_ji bitwise
-      const bool lo = i < j;
-      const Node<D> &na = lo ? ni : nj;
-      const Node<D> &nb = lo ? nj : ni;
-      const double sg = lo ? 1.0 : -1.0;
-      const double inc = sg / nc;
+      const double inv = nc2 > 0.0 ? 1.0 / nc : 0.0;
+      Node<D> nr = nj;
+      if (ghost) {
+        double n[D];
+        for (int e = 0; e < D; ++e) n[e] = c[e] * inv;
+        ghost_node<D>(ni, meta >> 3, n, nr);
+      }
+      // d^L_ij from the lower index for a graph pair, so d_ij = d_ji bitwise;
+      // the inside state on the left for a boundary part
+      const bool lo = ghost || i < j;
+      const Node<D> &na = lo ? ni : nr;
+      const Node<D> &nb = lo ? nr : ni;
+      const double inc = lo ? inv : -inv;
       double ua = 0.0, ub = 0.0;
       for (int e = 0; e < D; ++e) {
         double ne = c[e] * inc;
         ua += na.u[e] * ne;
         ub += nb.u[e] * ne;
       }
-      const double d = nc * lambda_plus(A, ua, na.p, na.a, na.pal, na.ip, ub, nb.p, nb.a, nb.pal, nb.ip);
+      const double lam = lambda_plus(A, ua, na.p, na.a, na.pal, na.ip, ub, nb.p, nb.a, nb.pal, nb.ip);
+      const double d = pair ? nc * lam : 0.0;
       A.dL[s] = d;
       dsum += d;
       double fj[M], fi[M];
-      flux_dot<D>(nj.U, nj.u, nj.p, c, fj);
+      flux_dot<D>(nr.U, nr.u, nr.p, c, fj);
       flux_dot<D>(ni.U, ni.u, ni.p, c, fi);
       Acc mc = 0;
-      for (int e = 0; e < D; ++e) mc += (Acc)nj.U[1 + e] * (Acc)c[e];
-      T += mc * (Acc)(nj.fs - ni.fs);
+      for (int e = 0; e < D; ++e) mc += (Acc)nr.U[1 + e] * (Acc)c[e];
+      T += mc * (Acc)(nr.fs - ni.fs);
       double bar[M];
-      const double h2d = 0.5 / d;
+      const double h2d = graph ? 0.5 / d : 0.0;
       for (int q = 0; q < M; ++q) {
         double df = fj[q] - fi[q];
         S[q] += (Acc)df;
-        bar[q] = 0.5 * (ni.U[q] + nj.U[q]) - df * h2d;
+        bar[q] = 0.5 * (ni.U[q] + nr.U[q]) - df * h2d;
       }
-      rmin = fmin(rmin, bar[0]);
-      rmax = fmax(rmax, bar[0]);
+      if (graph) {
+        rmin = fmin(rmin, bar[0]);
+        rmax = fmax(rmax, bar[0]);
+      }
       double m2 = 0.0;
       for (int e = 0; e < D; ++e) m2 += bar[1 + e] * bar[1 + e];
       const double rb = bar[0] * bar[M - 1] - 0.5 * m2;  // rho eps of the bar state
-      const double kb = stilde_key(A, rb, bar[0]);
+      const double kb = graph ? stilde_key(A, rb, bar[0]) : INFINITY;
       if (kb < kbar) { kbar = kb; ebar = rb; rbar = bar[0]; }
     }
     if (kbar < INFINITY) smin = fmin(smin, ebar / rbar * pow(rbar, -g));

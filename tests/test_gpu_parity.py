@@ -41,6 +41,18 @@ def quadrant_on(dim, k, cells, bc, seed=240204514):
     return ms, W.to_conserved(st[q, 0], vel, st[q, 3])
 
 
+def smooth_on(dim, k, cells, bc, seed=7):
+    """Smooth seeded data at the nodes (distinct values at the duplicated
+    face nodes of neighbouring cells): rho, p > 0 from sums of sines."""
+    ms = W.MeshSpec(dim, k, tuple(cells), (0.0,) * dim, (1.0,) * dim, bc)
+    x, _ = W.node_coords(ms)
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0, 2 * np.pi, size=(4, dim))
+    f = lambda r: np.sum(np.sin(2 * np.pi * x + ph[r]), axis=1) / dim
+    vel = np.stack([0.4 * f(1 + (e % 2)) for e in range(dim)])
+    return ms, W.to_conserved(1.0 + 0.4 * f(0), vel, 1.0 + 0.5 * f(3))
+
+
 CASES = {
     "sod_q1_40": lambda: (W.sod(40).mesh, W.sod(40).U0),
     "q1_1d_slip": lambda: quadrant_on(1, 1, (33,), (2, 2)),
@@ -53,6 +65,10 @@ CASES = {
     "q1_3d_slip": lambda: quadrant_on(3, 1, (5, 4, 6), (2,) * 6),
     "q1_3d_mixed": lambda: quadrant_on(3, 1, (4, 4, 4), (0, 0, 1, 1, 2, 2), seed=3),
     "vortex_q1_32": lambda: (W.vortex(32).mesh, W.vortex(32).U0),
+    # degenerate meshes: one or two cells per axis, every cell on the boundary
+    "two_cells_1d": lambda: smooth_on(1, 1, (2,), (1, 1)),
+    "two_cells_2d_q2_slip": lambda: smooth_on(2, 2, (2, 2), (2,) * 4),
+    "two_cells_3d_mixed": lambda: smooth_on(3, 1, (2, 2, 2), (1, 1, 2, 2, 1, 2)),
     # whole x-lines of blocks: the 3D meshes swept tile by tile
     "q1_3d_tiled": lambda: quadrant_on(3, 1, (16, 6, 5), (2, 2, 1, 1, 0, 0), seed=41),
     "q2_3d_tiled": lambda: quadrant_on(3, 2, (4, 3, 3), (1,) * 6, seed=43),
@@ -290,3 +306,14 @@ def test_graph_run_to_final_time(oracle):
     st = S.run_to(tf)
     assert st.t == tf and st.steps == n_o
     _close(S.download(), Uo, tol=1e-10, what="U(t_final)")
+
+
+@pytest.mark.parametrize("dim", [1, 3])
+def test_relaxation_too_coarse_rejected(dim):
+    """A single Q1 cell has hhat = (m_i/|Omega|)^(1/d) = 1/2, so
+    c_r hhat^p_r = 4 * 0.354 > 1 and the relaxed lower bounds would not be
+    positive: creation is refused (the check of eq. ViscMinConst2 at setup)."""
+    ms, U = smooth_on(dim, 1, (1,) * dim, (1,) * (2 * dim))
+    with pytest.raises(gdg.GdgError) as ei:
+        gdg.Solver.from_spec(ms)
+    assert ei.value.status == gdg.GDG_E_INVALID
