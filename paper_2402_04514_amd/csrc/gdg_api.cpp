@@ -213,9 +213,13 @@ int enqueue_step(gdg_ctx *ctx, hipStream_t st, int device_driven, double dt_cap,
   StageBufs b2 = {ctx->U[c1], ctx->U[c2], ctx->U[c0], 0.75, 0.25};
   StageBufs b3 = {ctx->U[c2], ctx->U[c0], ctx->U[c0], 1.0 / 3.0, 2.0 / 3.0};
   int rc = launch_begin(A, dt_cap, tau_fixed, device_driven, st);
-  rc |= launch_stage(A, b1, 0, st, prof);
-  rc |= launch_stage(A, b2, 1, st, prof);
-  rc |= launch_stage(A, b3, 2, st, prof);
+  // host-driven steps recompute the node cache of U^n: after a restart it
+  // holds the state of an abandoned stage; device-driven steps follow a
+  // completed step (or the upload, or a host-driven step) whose last stage
+  // wrote it
+  rc |= launch_stage(A, b1, 0, st, prof, device_driven ? 0 : 1);
+  rc |= launch_stage(A, b2, 1, st, prof, 0);
+  rc |= launch_stage(A, b3, 2, st, prof, 0);
   rc |= launch_end(A, st);
   return rc;
 }
@@ -602,7 +606,7 @@ gdg_status gdg_stage(gdg_ctx *ctx, double tau, double *tau_used) {
   if (gdg_status s = launched(ctx, launch_begin(ctx->A, 0.0, tau > 0.0 ? tau : 0.0, 0, ctx->stream), "begin"))
     return s;
   StageBufs b = {ctx->U[c0], ctx->U[c1], ctx->U[c0], 0.0, 1.0};
-  if (gdg_status s = launched(ctx, launch_stage(ctx->A, b, 0, ctx->stream, prof_of(ctx)), "stage")) return s;
+  if (gdg_status s = launched(ctx, launch_stage(ctx->A, b, 0, ctx->stream, prof_of(ctx), 1), "stage")) return s;
   if (gdg_status s = read_ctl(ctx)) return s;
   if (gdg_status s = harvest(ctx)) return s;
   if (ctx->hctl.bad_flag) {

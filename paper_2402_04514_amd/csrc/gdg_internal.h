@@ -153,7 +153,10 @@ int launch_begin(const KArgs &A, double dt_cap, double tau_fixed, int device_dri
 int launch_end(const KArgs &A, void *stream);
 int launch_set_run(const KArgs &A, double t_final, long long step_limit, void *stream);
 int launch_prim(const KArgs &A, const double *U, void *stream);
-int launch_stage(const KArgs &A, const StageBufs &b, int stage, void *stream, Prof *prof);
+// need_prim: launch the primitives sweep even when the last limiter pass of
+// the previous stage wrote the node cache (the stage input was not produced by
+// a completed stage of this context)
+int launch_stage(const KArgs &A, const StageBufs &b, int stage, void *stream, Prof *prof, int need_prim);
 // ksteps device-driven SSP-RK3 steps of every request in L (persistent grid of
 // `grid` workgroups, a multiple of 8), then a copy of each request's control
 // block into status[0 .. nreq).

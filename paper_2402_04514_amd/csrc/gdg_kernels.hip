@@ -466,13 +466,11 @@ __global__ void k_end(Ctl *ctl) {
 }
 
 // ---------------------------------------------------------------------------
+// Node cache of row i from its state V (and the admissibility flag).
 template <int D>
-__device__ __forceinline__ void prim_row(const KArgs &A, const double *__restrict__ U, int64_t i) {
-  if (i >= A.N) return;
+__device__ __forceinline__ void store_prim(const KArgs &A, int64_t i, const double *V) {
   const int64_t N = A.N;
   const double g = A.gamma;
-  double V[D + 2];
-  for (int c = 0; c < D + 2; ++c) V[c] = U[c * N + i];
   double rho = V[0];
   double eps = eps_of<D>(V);
   if (!(rho > 0.0) || !(eps > 0.0)) atomicOr(&A.ctl->bad_flag, 1);
@@ -485,6 +483,14 @@ __device__ __forceinline__ void prim_row(const KArgs &A, const double *__restric
   A.Wc[(D + 3) * N + i] = exp(log(rg * p) / (g + 1.0));  // Harten entropy f(s) = e^{s/(gamma+1)}
   A.Wc[(D + 4) * N + i] = rg * eps;                      // s~ = rho^-gamma eps
   A.Wc[(D + 5) * N + i] = 1.0 / p;
+}
+
+template <int D>
+__device__ __forceinline__ void prim_row(const KArgs &A, const double *__restrict__ U, int64_t i) {
+  if (i >= A.N) return;
+  double V[D + 2];
+  for (int c = 0; c < D + 2; ++c) V[c] = U[c * A.N + i];
+  store_prim<D>(A, i, V);
 }
 
 template <int D>
@@ -1022,9 +1028,16 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
   if (pass == 0)
     for (int q = 0; q < M; ++q) A.U1[q * N + i] = V[q];
   if (final_pass) {
-    for (int q = 0; q < M; ++q)
-      sb.out[q * N + i] = sb.ca == 0.0 ? V[q] : sb.ca * sb.Un[q * N + i] + sb.cb * V[q];
+    // the stage output, and its node cache for the next stage: no kernel of
+    // this pass reads the cache, so it is rewritten here instead of by a
+    // separate primitives launch
+    double O[M];
+    for (int q = 0; q < M; ++q) {
+      O[q] = sb.ca == 0.0 ? V[q] : sb.ca * sb.Un[q * N + i] + sb.cb * V[q];
+      sb.out[q * N + i] = O[q];
+    }
     if (!(V[0] > 0.0) || !(eps_of<D>(V) > 0.0)) atomicOr(&A.ctl->bad_flag, 1);
+    store_prim<D>(A, i, O);
   }
 }
 
@@ -1068,6 +1081,7 @@ template <int D>
 __global__ __launch_bounds__(kBlockThreads) void kb_prim(const BatchList *L, int stage) {
   for_tiles(L, [&](const BatchEntry &E, int64_t blk) {
     if (E.A.ctl->halt || E.A.ctl->cfl_flag) return;
+    if (E.A.scheme == 2 && E.A.passes > 0) return;  // cache written by the last limiter pass
     if ((int)threadIdx.x < E.A.R) prim_row<D>(E.A, E.sb[stage].in, blk * E.A.R + threadIdx.x);
   });
 }
@@ -1129,13 +1143,17 @@ static inline void prof_mark(Prof *p, int kid, int end, void *stream) {
 static inline void clear_stale() { (void)hipGetLastError(); }
 
 template <int D, int DEG, bool MX>
-static int stage_impl(const KArgs &A, const StageBufs &b, int stage, void *stream, Prof *prof) {
+static int stage_impl(const KArgs &A, const StageBufs &b, int stage, void *stream, Prof *prof, int need_prim) {
   clear_stale();
   const dim3 grid((unsigned)A.nblocks), blk(kBlockThreads);
   const unsigned gp = (unsigned)((A.N + kBlockThreads - 1) / kBlockThreads);
-  prof_mark(prof, KID_PRIM, 0, stream);
-  hipLaunchKernelGGL(k_prim<D>, dim3(gp), blk, 0, S(stream), A, b.in);
-  prof_mark(prof, KID_PRIM, 1, stream);
+  // with the limiter's last pass the node cache of a stage's output is written
+  // there; otherwise it is computed at the start of the next stage
+  if (need_prim || !(A.scheme == 2 && A.passes > 0)) {
+    prof_mark(prof, KID_PRIM, 0, stream);
+    hipLaunchKernelGGL(k_prim<D>, dim3(gp), blk, 0, S(stream), A, b.in);
+    prof_mark(prof, KID_PRIM, 1, stream);
+  }
   prof_mark(prof, KID_SWEEP1, 0, stream);
   hipLaunchKernelGGL((k_sweep1<D, DEG, MX>), grid, blk, 0, S(stream), A, b.in, stage);
   prof_mark(prof, KID_SWEEP1, 1, stream);
@@ -1168,28 +1186,28 @@ static int fill_impl(const KArgs &A, void *stream) {
     default: return -2;                                         \
   }
 
-int launch_stage(const KArgs &A, const StageBufs &b, int stage, void *stream, Prof *prof) {
+int launch_stage(const KArgs &A, const StageBufs &b, int stage, void *stream, Prof *prof, int need_prim) {
   if (A.mixed) {
 #define GDG_STAGE_MX(D_, K_) stage_impl<D_, K_, true>
     switch (A.dim * 10 + A.deg) {
-      case 11: return GDG_STAGE_MX(1, 1)(A, b, stage, stream, prof);
-      case 12: return GDG_STAGE_MX(1, 2)(A, b, stage, stream, prof);
-      case 21: return GDG_STAGE_MX(2, 1)(A, b, stage, stream, prof);
-      case 22: return GDG_STAGE_MX(2, 2)(A, b, stage, stream, prof);
-      case 31: return GDG_STAGE_MX(3, 1)(A, b, stage, stream, prof);
-      case 32: return GDG_STAGE_MX(3, 2)(A, b, stage, stream, prof);
+      case 11: return GDG_STAGE_MX(1, 1)(A, b, stage, stream, prof, need_prim);
+      case 12: return GDG_STAGE_MX(1, 2)(A, b, stage, stream, prof, need_prim);
+      case 21: return GDG_STAGE_MX(2, 1)(A, b, stage, stream, prof, need_prim);
+      case 22: return GDG_STAGE_MX(2, 2)(A, b, stage, stream, prof, need_prim);
+      case 31: return GDG_STAGE_MX(3, 1)(A, b, stage, stream, prof, need_prim);
+      case 32: return GDG_STAGE_MX(3, 2)(A, b, stage, stream, prof, need_prim);
       default: return -2;
     }
 #undef GDG_STAGE_MX
   }
 #define GDG_STAGE_64(D_, K_) stage_impl<D_, K_, false>
   switch (A.dim * 10 + A.deg) {
-    case 11: return GDG_STAGE_64(1, 1)(A, b, stage, stream, prof);
-    case 12: return GDG_STAGE_64(1, 2)(A, b, stage, stream, prof);
-    case 21: return GDG_STAGE_64(2, 1)(A, b, stage, stream, prof);
-    case 22: return GDG_STAGE_64(2, 2)(A, b, stage, stream, prof);
-    case 31: return GDG_STAGE_64(3, 1)(A, b, stage, stream, prof);
-    case 32: return GDG_STAGE_64(3, 2)(A, b, stage, stream, prof);
+    case 11: return GDG_STAGE_64(1, 1)(A, b, stage, stream, prof, need_prim);
+    case 12: return GDG_STAGE_64(1, 2)(A, b, stage, stream, prof, need_prim);
+    case 21: return GDG_STAGE_64(2, 1)(A, b, stage, stream, prof, need_prim);
+    case 22: return GDG_STAGE_64(2, 2)(A, b, stage, stream, prof, need_prim);
+    case 31: return GDG_STAGE_64(3, 1)(A, b, stage, stream, prof, need_prim);
+    case 32: return GDG_STAGE_64(3, 2)(A, b, stage, stream, prof, need_prim);
     default: return -2;
   }
 #undef GDG_STAGE_64
