@@ -109,6 +109,7 @@ struct KArgs {
   double *UL, *dUH, *U1;
   double *dL;       // d^L (and d^{d,L} on ghost slots) per slot
   double *l1;       // l of limiter pass 1 per slot (the ghost slot of a row holds l_i^d)
+  uint8_t *accepted;  // per row: limiter pass 1 accepted every flux of the row whole
   Ctl *ctl;
 };
 

@@ -940,6 +940,21 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
   const int64_t N = A.N;
   const double tau = A.ctl->tau;
   const int a = (int)(i % NLOC);
+  if (pass == 1 && final_pass && A.accepted[i]) {
+    // pass 1 accepted every pair and the boundary part of this row whole:
+    // nothing is left to limit (every remaining flux is 0 A), and the result
+    // is U^(1) itself
+    {
+      double O[M];
+      for (int q = 0; q < M; ++q) {
+        const double v = base[q * N + i];
+        O[q] = sb.ca == 0.0 ? v : sb.ca * sb.Un[q * N + i] + sb.cb * v;
+        sb.out[q * N + i] = O[q];
+      }
+      store_prim<D>(A, i, O);
+      return;
+    }
+  }
   const double mi = A.ref->mlump[a];
   const double hpk = A.ref->hpk[a];
   const double sci = A.kscale[i];  // 1 / (kappa_i m_i)
@@ -955,6 +970,7 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
   double acc[M], Ab[M];
   for (int q = 0; q < M; ++q) acc[q] = Ab[q] = 0.0;
   int64_t gslot = -1;
+  bool allone = true;  // every l of the row is 1
   const int64_t s0 = blk * A.W * A.R + lane;
   uint8_t meta_n = A.meta[s0];
   int32_t col_n = A.col[s0];
@@ -1010,6 +1026,7 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
     const double l = fmin(li, lj);
     for (int q = 0; q < M; ++q) acc[q] += l * Aij[q];
     if (pass == 0) A.l1[s] = l;
+    allone = allone && l == 1.0;
   }
   bool bzero = true;
   for (int q = 0; q < M; ++q) bzero = bzero && Ab[q] == 0.0;
@@ -1022,11 +1039,14 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
     const double lb = line_search<D>(A, Li, Ab, sci, rmin, rmax, smin, smin5);
     for (int q = 0; q < M; ++q) acc[q] += lb * Ab[q];
     if (pass == 0) A.l1[gslot] = lb;
+    allone = allone && lb == 1.0;
   }
   double V[M];
   for (int q = 0; q < M; ++q) V[q] = Li[q] + acc[q] / mi;
-  if (pass == 0)
+  if (pass == 0) {
     for (int q = 0; q < M; ++q) A.U1[q * N + i] = V[q];
+    A.accepted[i] = allone ? 1 : 0;
+  }
   if (final_pass) {
     // the stage output, and its node cache for the next stage: no kernel of
     // this pass reads the cache, so it is rewritten here instead of by a
