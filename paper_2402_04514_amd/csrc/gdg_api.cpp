@@ -492,10 +492,16 @@ gdg_status gdg_download_state(gdg_ctx *ctx, double *U, int32_t is_device_ptr) {
   return GDG_OK;
 }
 
-gdg_status gdg_step(gdg_ctx *ctx, double dt_cap, double dt_fixed, double *dt_taken) {
-  if (!ctx) return GDG_E_INVALID;
+}  // extern "C"
+
+namespace {
+constexpr int kMaxRestarts = 8;
+
+// One SSP-RK3 step with the restart rule; `used` restarts of this step were
+// already spent (a device-driven attempt that halted on a violation).
+gdg_status step_impl(gdg_ctx *ctx, double dt_cap, double dt_fixed, double *dt_taken, int used) {
   double tau_fixed = dt_fixed > 0.0 ? dt_fixed : 0.0;
-  for (int attempt = 0; attempt <= 8; ++attempt) {
+  for (int attempt = used; attempt <= kMaxRestarts; ++attempt) {
     if (gdg_status s = launched(ctx, enqueue_step(ctx, ctx->stream, 0, dt_cap, tau_fixed, prof_of(ctx)), "step"))
       return s;
     if (gdg_status s = read_ctl(ctx)) return s;
@@ -518,6 +524,14 @@ gdg_status gdg_step(gdg_ctx *ctx, double dt_cap, double dt_fixed, double *dt_tak
   }
   ctx->err = "CFL condition violated after 8 restarts";
   return GDG_E_CFL;
+}
+}  // namespace
+
+extern "C" {
+
+gdg_status gdg_step(gdg_ctx *ctx, double dt_cap, double dt_fixed, double *dt_taken) {
+  if (!ctx) return GDG_E_INVALID;
+  return step_impl(ctx, dt_cap, dt_fixed, dt_taken, 0);
 }
 
 // Device-driven time loop: captured graphs of several steps, one host
@@ -553,7 +567,7 @@ gdg_status gdg_run_to(gdg_ctx *ctx, double t_final, int64_t max_steps, gdg_stats
       const double tau = ctx->prm.cfl * bits_to_double(h.taumin_bits[vs]);
       ++ctx->restarts;
       double dt = 0.0;
-      if (gdg_status s = gdg_step(ctx, t_final - ctx->t, tau, &dt)) return s;
+      if (gdg_status s = step_impl(ctx, t_final - ctx->t, tau, &dt, 1)) return s;
       if (ctx->steps >= limit || !(ctx->t < t_final)) break;
       if (gdg_status s = launched(ctx, launch_set_run(ctx->A, t_final, limit, ctx->stream), "set run")) return s;
       continue;
@@ -592,7 +606,7 @@ gdg_status ctx_restart(gdg_ctx *ctx, const Ctl &c, double t_final) {
   const double tau = ctx->prm.cfl * bits_to_double(c.taumin_bits[vs]);
   ++ctx->restarts;
   double dt = 0.0;
-  if (gdg_status s = gdg_step(ctx, t_final - ctx->t, tau, &dt)) return s;
+  if (gdg_status s = step_impl(ctx, t_final - ctx->t, tau, &dt, 1)) return s;
   return launched(ctx, ctx_arm(ctx, t_final), "set run");
 }
 

@@ -317,3 +317,44 @@ def test_relaxation_too_coarse_rejected(dim):
     with pytest.raises(gdg.GdgError) as ei:
         gdg.Solver.from_spec(ms)
     assert ei.value.status == gdg.GDG_E_INVALID
+
+
+@pytest.mark.parametrize("name", ["q2_2d_slip", "sod_q1_40", "q1_3d_slip"])
+def test_graph_run_with_cfl_restarts(oracle, name):
+    """Cr = 1 makes stages 2 and 3 violate eq. CFLcond whenever the wave
+    speeds grow within a step: the device-driven loop halts its graph, the
+    step is redone host-driven with the restart rule, and states, times and
+    restart counts match the oracle's run."""
+    _say("graph run with restarts " + name)
+    ms, _, _, _, _ = _pair(oracle, name)
+    p = gdg.gdg_default_params(ms.degree)
+    p.cfl = 1.0
+    ms, U, M, S, op = _pair(oracle, name, p)
+    V, t_o, res_o = U, 0.0, 0
+    for _ in range(15):
+        V, dt, nres, st = M.step(op, V)
+        assert st == 0
+        t_o += dt
+        res_o += nres
+    assert res_o > 0
+    st = S.run_to(1e30, max_steps=15)
+    assert st.steps == 15 and st.restarts == res_o
+    assert st.t == pytest.approx(t_o, rel=1e-12)
+    _close(S.download(), V, tol=1e-10, what="U after 15 steps")
+
+
+def test_cfl_failure_reported(oracle):
+    """When eight restarts do not satisfy the CFL condition both sides give
+    up: GDG_E_CFL, as the oracle's status."""
+    ms, _, _, _, _ = _pair(oracle, "q1_2d_mixed")
+    p = gdg.gdg_default_params(1)
+    p.cfl = 1.0
+    ms, U, M, S, op = _pair(oracle, "q1_2d_mixed", p)
+    V, _, _, st = M.step(op, U)
+    assert st == 0
+    _, _, _, st = M.step(op, V)
+    assert st == -3  # the second step gives up
+    with pytest.raises(gdg.GdgError) as ei:
+        S.run_to(1e30, max_steps=2)
+    assert ei.value.status == gdg.GDG_E_CFL
+    assert S.stats().steps == 1

@@ -152,3 +152,36 @@ def test_one_dimensional_class_and_errors():
         S.submit(ms, U, 0.01)
     assert ei.value.status == gdg.GDG_E_INVALID
     S.close()
+
+
+def test_served_requests_with_cfl_restarts():
+    """Cr = 1: served requests go through the server's restart path; each
+    result equals its run through gdg_run_to (same steps and restarts)."""
+    reqs = _requests(2, 2, 3, seed0=120)
+    S = gdg.Server(2, 2, gdg.GDG_FP64, budget_bytes=256 << 20, max_slots=4, steps_per_graph=4)
+    tickets = []
+    for ms, U, tf in reqs:
+        p = gdg.gdg_default_params(2)
+        p.cfl = 1.0
+        tickets.append(S.submit(ms, U, tf, params=p))
+    while True:
+        res, pend = S.pump()
+        if res == 0 and pend == 0:
+            break
+    S.sync()
+    total_restarts = 0
+    for (ms, U, tf), tk in zip(reqs, tickets):
+        info = S.poll(tk)
+        assert info.state == gdg.GDG_REQ_DONE, info.state
+        out = S.result(tk)
+        p = gdg.gdg_default_params(2)
+        p.cfl = 1.0
+        A = gdg.Solver.from_spec(ms, p)
+        A.upload(U)
+        st = A.run_to(tf)
+        assert info.steps == st.steps and info.restarts == st.restarts
+        total_restarts += st.restarts
+        ref = A.download()
+        assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
+    S.close()
+    assert total_restarts > 0
