@@ -361,12 +361,13 @@ def main():
     avg_s = ms_tot / launches / 1e3
     bytes_launch = algorithmic_bytes(dom, wl.mesh.dim, slots) * ndofs
     achieved = bytes_launch / avg_s / 1e9
-    traffic = None
+    traffic, valu = None, None
     tf = os.path.join(ROOT, "profiles", "traffic_%s.json" % args.workload)
     if os.path.exists(tf):
         rec = json.load(open(tf))
         if rec.get("kernel_source_hash") == kernel_source_hash() and dom in rec.get("kernels", {}):
             traffic = rec["kernels"][dom]["bytes_per_launch"]
+            valu = rec["kernels"][dom].get("valu_instructions")
     if args.calib_copy_gib > 0:
         import torch
         n = int(args.calib_copy_gib * (1 << 30)) // 8
@@ -393,6 +394,11 @@ def main():
                    "simulated_time": stats.t},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_gbs": traffic / avg_s / 1e9 if traffic else None,
+                     "traffic_frac": traffic / avg_s / 1e9 / HBM_PEAK_GBS if traffic else None,
+                     # FP64 VALU: wave64 instructions x 4 cycles (16 lanes per SIMD per
+                     # cycle) over the cycles of 1024 SIMDs at 2.4 GHz
+                     "valu_busy_est": (valu * 4.0 / (avg_s * 2.4e9 * 1024)) if valu else None,
                      "algorithmic_bytes_per_launch": bytes_launch,
                      "avg_launch_ms": avg_s * 1e3,
                      "timing": "HIP events on the library stream around each launch, %d host-driven "

@@ -1,10 +1,14 @@
 // gdg_kernels.hip -- the per-stage sweeps of the graph-based DG scheme on
-// gfx950 (FP64).  One thread owns one row i of the stencil; a workgroup owns
+// gfx950 (FP64, and the mixed-precision variant of sweeps 1 and 2).  One
+// thread owns one row i of the stencil; a workgroup (one wavefront) owns
 // whole cells (R rows), so the cell-local consistent-mass solve runs in LDS.
 //
 // Sweeps of one forward-Euler stage Phi(U; tau):
 //   k_prim    per node: velocity, pressure, sound speed, p^-alpha, Harten
-//             entropy f(s), rescaled entropy s~ (Sec. 2.2, Sec. 5.2, 5.4)
+//             entropy f(s), rescaled entropy s~ (Sec. 2.2, Sec. 5.2, 5.4);
+//             with the limiter, the last limiter pass writes this node cache
+//             for the stage output, and k_prim runs only at the start of a
+//             host-driven step
 //   k_sweep1  d^L_ij, d_i^{d,k} (eq. dij_low_order, dij_low_order_modified),
 //             min_i m_i/(2|d_ii|) (eq. MaxCFLdt), the entropy-viscosity ratio
 //             N_i (Sec. 5.2) and ring-1 partial bounds over bar states
@@ -16,7 +20,9 @@
 //             the antidiffusive fluxes A_ij (eq. HighLowOrderIdentity); run
 //             twice (Sec. 6.1), the second pass on the remaining (1 - l) A
 // Every grid-wide dependency (tau, neighbours' N_j and bound partials, their
-// U^L_j / B_j / dU^H_j, the symmetric l_ij) is a kernel boundary.
+// U^L_j / B_j / dU^H_j, the symmetric l_ij) is a kernel boundary.  The kb_*
+// kernels run the same per-block bodies for every request resident in the
+// request server, from a work list in device memory.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -129,12 +135,8 @@ __device__ __forceinline__ void load_c(const KArgs &A, int64_t s, double *c) {
 
 // ---------------------------------------------------------------------------
 // Rescaled entropy tests.  For gamma = 7/5 the comparison
-//   eps >= s rho^(7/5)   <=>   eps^5 >= s^5 rho^7     (eps, s, rho > 0)
+//   eps >= s rho^(7/5)   <=>   (rho eps)^5 >= s^5 rho^12     (eps, s, rho > 0)
 // needs multiplies only; the power function is left to the rare cases.
-__device__ __forceinline__ double pow7(double x) {
-  double x2 = x * x;
-  return x2 * x2 * x2 * x;
-}
 __device__ __forceinline__ double pow5(double x) {
   double x2 = x * x;
   return x2 * x2 * x;
@@ -174,25 +176,6 @@ __device__ double ls_psi(double g, const double *U, const double *P, double smin
     *dpsi = dot - smin * g * rg / V[0] * P[0];
   }
   return eps - smin * rg;
-}
-
-// psi(l) >= 0 without the power function when gamma = 7/5
-template <int D>
-__device__ __forceinline__ bool ls_feasible(const KArgs &A, const double *U, const double *P, double smin,
-                                            double smin5, double l) {
-  double V[D + 2];
-  for (int c = 0; c < D + 2; ++c) V[c] = U[c] + l * P[c];
-  if (A.g75 && smin5 > 0.0) {
-    // rho eps = rho E - |m|^2/2; eps^5 >= s^5 rho^7 <=> (rho eps)^5 >= s^5 rho^12
-    double m2 = 0.0;
-    for (int e = 0; e < D; ++e) m2 += V[1 + e] * V[1 + e];
-    const double re = V[0] * V[D + 1] - 0.5 * m2;
-    if (!(re > 0.0)) return false;
-    const double r3 = V[0] * V[0] * V[0], r6 = r3 * r3;
-    const double lhs = pow5(re), rhs = smin5 * (r6 * r6);
-    if (isfinite(lhs) && isfinite(rhs) && rhs > 1e-290) return lhs >= rhs;
-  }
-  return eps_of<D>(V) - smin * pow(V[0], A.gamma) >= 0.0;
 }
 
 // Common path of the line search, branch free: the density limit
