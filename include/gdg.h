@@ -61,10 +61,9 @@ typedef enum { GDG_LOW_ORDER = 0, GDG_HIGH_ORDER = 1, GDG_LIMITED = 2 } gdg_sche
 /* GDG_FP64: every operation in double precision.
  * GDG_MIXED: the stencil coefficients c_ij are stored in single precision and
  * the flux sums sum_j (f(U_j) - f(U_i)) c_ij of the low- and high-order
- * updates (each flux difference by the product rule from the state
- * differences rounded to single precision) and the sums of the entropy
- * residual (Sec. 5.2) are taken in single precision with single-precision
- * accumulation; the state and its updates,
+ * updates and the sums of the entropy residual (Sec. 5.2) are accumulated in
+ * single precision (each term rounded once from the double-precision flux
+ * difference that the bar state needs); the state and its updates,
  * the wave-speed bound and d_ij (eq. dij_low_order), the bar states and local
  * bounds (eq. local_bounds) and the limiter line search (Sec. 5.4) stay in
  * double precision, so every stage output is still checked against A.  The

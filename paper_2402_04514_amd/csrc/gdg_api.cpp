@@ -48,7 +48,7 @@ struct Layout {
   int nloc, nb1, R, cpb, W, M;
   int64_t N, ncells, nblocks, nslots;
   size_t off_ref, off_ctl, off_col, off_c, off_meta, off_kscale, off_U[3], off_Wc, off_N, off_q,
-      off_B, off_UL, off_dUH, off_U1, off_dL, off_l1, off_acc, total;
+      off_B, off_UL, off_dUH, off_U1, off_dL, off_l1, off_acc, off_fsum, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -136,6 +136,7 @@ Layout layout(const gdg_mesh_desc *m, const gdg_params *p) {
   L.off_dL = take(S * 8);
   L.off_l1 = take(S * 8);
   L.off_acc = take(N);
+  L.off_fsum = take(M * N * 8);
   L.total = o;
   return L;
 }
@@ -384,6 +385,7 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   A.dL = (double *)(ws + L.off_dL);
   A.l1 = (double *)(ws + L.off_l1);
   A.accepted = (uint8_t *)(ws + L.off_acc);
+  A.fsum = (double *)(ws + L.off_fsum);
 
   RefTables *T = new RefTables();
   if (!build_ref_tables(mesh->dim, mesh->degree, h, T, &err)) {

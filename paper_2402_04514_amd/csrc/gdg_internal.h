@@ -104,6 +104,7 @@ struct KArgs {
   // per-dof fields
   double *Wc;       // node cache: dim velocities, p, a, p^-alpha, f(s), s~, 1/p  (dim+6 planes)
   double *Nev;      // entropy-viscosity ratio
+  double *fsum;     // per row, (dim+2) planes: sum_j (f(U_j) - f(U_i)) c_ij with the boundary parts
   double *q;        // ring-1 bound partials: rho_min, rho_max, s~_min
   double *B;        // relaxed bounds
   double *UL, *dUH, *U1;

@@ -90,29 +90,6 @@ __device__ __forceinline__ void flux_dot(const T *U, const T *u, T p, const T *c
   out[D + 1] = (U[D + 1] + p) * uc;
 }
 
-// (f(U_j) - f(U_i)) c in FP32 by the product rule,
-//   d(m u^T) = dm u_j^T + m_i du^T,  d((E + p) u) = d(E + p) u_j + (E_i + p_i) du,
-// from the FP64 differences dU, du, dp rounded once to FP32.  Its error is
-// relative to the difference (not to the flux), and equal states give exact
-// zeros.
-template <int D>
-__device__ __forceinline__ void flux_diff32(const double *Uj, const double *uj, double pj, const double *Ui,
-                                            const double *ui, double pi, const float *c, float *out) {
-  float dU[D + 2], du[D];
-  for (int q = 0; q < D + 2; ++q) dU[q] = (float)(Uj[q] - Ui[q]);
-  for (int e = 0; e < D; ++e) du[e] = (float)(uj[e] - ui[e]);
-  const float dp = (float)(pj - pi);
-  float ucj = 0.0f, duc = 0.0f, dmc = 0.0f;
-  for (int e = 0; e < D; ++e) {
-    ucj += (float)uj[e] * c[e];
-    duc += du[e] * c[e];
-    dmc += dU[1 + e] * c[e];
-  }
-  out[0] = dmc;
-  for (int e = 0; e < D; ++e) out[1 + e] = dU[1 + e] * ucj + (float)Ui[1 + e] * duc + dp * c[e];
-  out[D + 1] = (dU[D + 1] + dp) * ucj + (float)(Ui[D + 1] + pi) * duc;
-}
-
 template <int D>
 __device__ __forceinline__ double eps_of(const double *V) {
   double m2 = 0.0;
@@ -665,6 +642,9 @@ __device__ __forceinline__ void sweep1_body(const KArgs &A, const double *__rest
       Dn += fabs(gq) * fabs(S[q]);
     }
     A.Nev[i] = Dn > 0 ? (double)(R / Dn) : 0.0;
+    // the flux sum of the row (graph and boundary parts, difference form) is
+    // the one the low- and high-order updates of sweep 2 need
+    for (int q = 0; q < M; ++q) A.fsum[q * A.N + i] = (double)S[q];
     A.q[i] = rmin;
     A.q[A.N + i] = rmax;
     A.q[2 * A.N + i] = smin;
@@ -705,7 +685,6 @@ __device__ __forceinline__ bool stage_tau(const KArgs &A, int stage, double *tau
 
 template <int D, int DEG, bool MX>
 __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb, int stage, int64_t blk) {
-  using Acc = typename AccT<MX>::type;
   constexpr int M = D + 2;
   constexpr int NB = DEG + 1;
   constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
@@ -733,11 +712,11 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
     const double Ni = A.Nev[i];
     const double hpk = A.ref->hpk[a];
     const double mi = A.ref->mlump[a];
-    // accL / accH: the viscous terms (and, in FP64, the flux sums); accF: the
-    // graph flux sum sum_j (f(U_j) - f(U_i)) c_ij in the mixed variant (FP32)
+    // accL / accH: the viscous terms sum_j d_ij (U_j - U_i) of the low- and
+    // high-order updates (with their boundary parts); the flux sum comes from
+    // sweep 1
     double accL[M], accH[M];
-    Acc accF[M];
-    for (int c = 0; c < M; ++c) { accL[c] = accH[c] = 0.0; accF[c] = 0; }
+    for (int c = 0; c < M; ++c) accL[c] = accH[c] = 0.0;
     double rmin = INFINITY, rmax = -INFINITY, smin = INFINITY;
     // the next slot's kind and column are loaded one slot ahead, so that the
     // dependent gather of the neighbour does not wait for them
@@ -754,10 +733,10 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
       }
       const int kind = meta & 7;
       if (kind == SK_PAD) continue;
-      double c[D];
-      load_c<D, MX>(A, s, c);
       const double d = A.dL[s];
       if (kind == SK_GHOST) {
+        double c[D];
+        load_c<D, MX>(A, s, c);
         double nc2 = 0.0;
         for (int e = 0; e < D; ++e) nc2 += c[e] * c[e];
         const double nc = sqrt(nc2);
@@ -775,8 +754,8 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
         for (int q = 0; q < M; ++q) {
           double df = fj[q] - fi[q];
           double du = gh.U[q] - ni.U[q];
-          accL[q] += df - d * du;
-          accH[q] += df - dH * du;
+          accL[q] -= d * du;
+          accH[q] -= dH * du;
           bar[q] = 0.5 * (gh.U[q] + ni.U[q]) - df / (2.0 * d);  // eq. BoundaryBarState
         }
         rmin = fmin(rmin, bar[0]);
@@ -789,38 +768,18 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
       rmax = fmax(rmax, A.q[N + j]);
       smin = fmin(smin, A.q[2 * N + j]);
       if (j == i) continue;
-      double Uj[M], uj[D];
-      for (int q = 0; q < M; ++q) Uj[q] = U[q * N + j];
-      for (int e = 0; e < D; ++e) uj[e] = A.Wc[e * N + j];
-      const double pj = A.Wc[D * N + j];
       const double dH = visc_high(A, d, Ni, A.Nev[j], kind, hpk);
-      if (MX) {
-        float c32[D], df[M];
-        for (int e = 0; e < D; ++e) c32[e] = (float)c[e];
-        flux_diff32<D>(Uj, uj, pj, ni.U, ni.u, ni.p, c32, df);
-        for (int q = 0; q < M; ++q) {
-          const double du = Uj[q] - ni.U[q];
-          accF[q] += (Acc)df[q];
-          accL[q] -= d * du;
-          accH[q] -= dH * du;
-        }
-      } else {
-        double fj[M], fi[M];
-        flux_dot<D>(Uj, uj, pj, c, fj);
-        flux_dot<D>(ni.U, ni.u, ni.p, c, fi);
-        for (int q = 0; q < M; ++q) {
-          double df = fj[q] - fi[q];
-          double du = Uj[q] - ni.U[q];
-          accL[q] += df - d * du;
-          accH[q] += df - dH * du;
-        }
+      for (int q = 0; q < M; ++q) {
+        const double du = U[q * N + j] - ni.U[q];
+        accL[q] -= d * du;
+        accH[q] -= dH * du;
       }
     }
-    if (MX)
-      for (int q = 0; q < M; ++q) {
-        accL[q] += (double)accF[q];
-        accH[q] += (double)accF[q];
-      }
+    for (int q = 0; q < M; ++q) {
+      const double f = A.fsum[q * N + i];
+      accL[q] += f;
+      accH[q] += f;
+    }
     // eq. cijdijschememodified in the difference form
     double UL[M];
     for (int q = 0; q < M; ++q) {

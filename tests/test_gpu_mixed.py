@@ -1,9 +1,8 @@
 """GPU mixed-precision variant (GDG_MIXED) against the FP64 CPU oracle.
 
-The variant stores c_ij in FP32 and takes the flux sums of the low- and
-high-order updates and the entropy-residual sums in FP32 with FP32
-accumulation; the state, d_ij, bar states, bounds and the line search stay in
-FP64.  Its results therefore differ from the FP64 scheme by FP32 rounding of
+The variant stores c_ij in FP32 and accumulates the flux sums of the low-
+and high-order updates and the entropy-residual sums in FP32; the state,
+d_ij, bar states, bounds and the line search stay in FP64.  Its results therefore differ from the FP64 scheme by FP32 rounding of
 those sums, about 1e-7 of the flux scale per stage, and the stated bound is an
 L1 (mass-weighted, per component) error of at most 1e-5 relative to the FP64
 oracle, after whole runs.  Invariant-set properties hold exactly: every stage

@@ -319,16 +319,17 @@ def test_relaxation_too_coarse_rejected(dim):
     assert ei.value.status == gdg.GDG_E_INVALID
 
 
-@pytest.mark.parametrize("name", ["q2_2d_slip", "sod_q1_40", "q1_3d_slip"])
+@pytest.mark.parametrize("name", ["sod_q1_40", "q1_3d_slip", "q1_2d_outflow_ragged"])
 def test_graph_run_with_cfl_restarts(oracle, name):
-    """Cr = 1 makes stages 2 and 3 violate eq. CFLcond whenever the wave
-    speeds grow within a step: the device-driven loop halts its graph, the
-    step is redone host-driven with the restart rule, and states, times and
-    restart counts match the oracle's run."""
+    """Cr = 0.95 makes stages 2 and 3 violate eq. CFLcond where the wave
+    speeds grow by more than 5% within a step (a margin well above rounding):
+    the device-driven loop halts its graph, the step is redone host-driven
+    with the restart rule, and states, times and restart counts match the
+    oracle's run."""
     _say("graph run with restarts " + name)
     ms, _, _, _, _ = _pair(oracle, name)
     p = gdg.gdg_default_params(ms.degree)
-    p.cfl = 1.0
+    p.cfl = 0.95
     ms, U, M, S, op = _pair(oracle, name, p)
     V, t_o, res_o = U, 0.0, 0
     for _ in range(15):
