@@ -57,21 +57,22 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(kernel: str, dim: int, slots: float) -> float:
+def algorithmic_bytes(kernel: str, dim: int, slots: float, ghosts: float = 0.0) -> float:
     """Bytes per row (dof) a kernel must move with each array touched once:
     stencil entries (int32 column, meta byte, dim doubles of c_ij), per-slot
-    fields (d^L, l, own-side l: doubles; transposed slot: int32), per-dof
-    fields.  Gathers of neighbour values count once (each value is needed once
-    per sweep); re-reads through the caches are not algorithmic."""
+    fields (d^L, l: doubles), per-dof fields.  Gathers of neighbour values
+    count once (each value is needed once per sweep); re-reads through the
+    caches are not algorithmic.  `ghosts` is the mean number of boundary parts
+    per row, the only slots whose c_ij sweep 2 reads."""
     M = dim + 2
     st = slots * (4 + 1 + 8 * dim)    # column, meta, c_ij
     idx = slots * (4 + 1)             # column, meta
     if kernel == "prim":
         return 8 * M + 8 * (dim + 5)
-    if kernel == "sweep1":   # U, node cache in; d^L, N, ring-1 partials out
-        return st + 8 * (M + dim + 5) + 8 * slots + 8 + 24
-    if kernel == "sweep2":   # U, u, p, N, q, d^L in; U^L, bounds, dU^H out
-        return st + 8 * slots + 8 * (M + dim + 1) + 8 + 24 + 8 * M + 24 + 8 * M
+    if kernel == "sweep1":   # U, node cache in; d^L, N, ring-1 partials, flux sums out
+        return st + 8 * (M + dim + 5) + 8 * slots + 8 + 24 + 8 * M
+    if kernel == "sweep2":   # U, u, p, N, q, d^L, flux sums in; U^L, bounds, dU^H out
+        return idx + 8 * dim * ghosts + 8 * slots + 8 * (M + dim + 1) + 8 + 24 + 8 * M + 8 * M + 24 + 8 * M
     # U, base, dU^H, B, N, row length of i and of the neighbours (once); l out
     lim = idx + 8 * slots + 8 * M * 3 + 24 + 8 + 4 + 8 * M + 8 * slots
     if kernel == "limit1":
@@ -82,11 +83,12 @@ def algorithmic_bytes(kernel: str, dim: int, slots: float) -> float:
 
 
 def stencil_slots(ms) -> tuple[float, float]:
-    """Average stored slots per row (graph entries + boundary parts)."""
-    import numpy as np
+    """Average stored slots per row (graph entries + boundary parts) and
+    average boundary parts per row."""
     d, k = ms.dim, ms.degree
     nb = k + 1
     tot = 0.0
+    ghost = 0.0
     for e in range(d):
         n = ms.cells[e]
         periodic = ms.bc[2 * e] == 0
@@ -94,7 +96,8 @@ def stencil_slots(ms) -> tuple[float, float]:
         face_nodes_frac = 2.0 / nb
         interior = 1.0 if periodic else (n - 1) / n
         tot += face_nodes_frac * (interior * nb ** (d - 1) + (1 - interior) * 1)
-    return nb ** d + tot, 0.0
+        ghost += face_nodes_frac * (1 - interior)
+    return nb ** d + tot, ghost
 
 
 def _params(gdg, degree, precision):
@@ -354,12 +357,12 @@ def main():
 
     wl, desc, ndofs, secs, prof, admissible, stats = run_gpu(args.workload, steps, warmup, args.host_driven)
     value = ndofs * 3 * steps / secs
-    slots, _ = stencil_slots(wl.mesh)
+    slots, ghosts = stencil_slots(wl.mesh)
     prof_steps, prof_ms_step = prof.pop("_region")
     dom = max(prof, key=lambda k: prof[k][0])
     ms_tot, launches = prof[dom]
     avg_s = ms_tot / launches / 1e3
-    bytes_launch = algorithmic_bytes(dom, wl.mesh.dim, slots) * ndofs
+    bytes_launch = algorithmic_bytes(dom, wl.mesh.dim, slots, ghosts) * ndofs
     achieved = bytes_launch / avg_s / 1e9
     traffic, valu = None, None
     tf = os.path.join(ROOT, "profiles", "traffic_%s.json" % args.workload)
