@@ -76,6 +76,8 @@ def lib():
         L.or_volume.argtypes = [C.c_void_p]
         L.or_set_reference_volume.restype = None
         L.or_set_reference_volume.argtypes = [C.c_void_p, C.c_double]
+        L.or_set_boundary_state.restype = None
+        L.or_set_boundary_state.argtypes = [C.c_void_p, C.c_int, _DP]
         L.or_csr.argtypes = [C.c_void_p, C.POINTER(C.c_long), C.POINTER(C.c_long), _DP, _DP,
                              C.POINTER(C.c_int)]
         L.or_lumped.argtypes = [C.c_void_p, _DP]
@@ -115,7 +117,10 @@ def params(gamma=1.4, cfl=0.5, degree=1, c_ev=None, c_k=1.0, c_r=4.0, p_r=1.5, p
 class Mesh:
     """Uniform Cartesian DG Q_k mesh with the stencil of Sec. 2.3."""
 
-    def __init__(self, dim, degree, cells, lo, hi, bc):
+    def __init__(self, dim, degree, cells, lo, hi, bc, bstate=None):
+        """bc: kinds per box face 2*axis+side (0 periodic, 1 outflow, 2 slip,
+        3 Dirichlet, 4 supersonic in/outflow).  bstate: per face the
+        conserved Dirichlet data U^d of kinds 3 and 4 (None elsewhere)."""
         self.dim, self.degree = dim, degree
         self.cells = tuple(int(c) for c in cells)
         self.lo = tuple(float(x) for x in lo)
@@ -131,6 +136,13 @@ class Mesh:
             raise ValueError("invalid mesh description")
         self.ndofs = L.or_num_dofs(self._h)
         self.m = dim + 2
+        for f in range(2 * dim):
+            if self.bc[f] in (3, 4):
+                if bstate is None or bstate[f] is None:
+                    raise ValueError("face %d needs Dirichlet data" % f)
+                v = np.ascontiguousarray(bstate[f], dtype=np.float64)
+                assert v.shape == (self.m,)
+                L.or_set_boundary_state(self._h, f, _dp(v))
 
     def __del__(self):
         h = getattr(self, "_h", None)

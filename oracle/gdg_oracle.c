@@ -32,7 +32,7 @@
 #define OR_MAXD 3
 #define OR_MAXM 5
 
-enum { OR_BC_PERIODIC = 0, OR_BC_OUTFLOW = 1, OR_BC_SLIP = 2 };
+enum { OR_BC_PERIODIC = 0, OR_BC_OUTFLOW = 1, OR_BC_SLIP = 2, OR_BC_DIRICHLET = 3, OR_BC_SUPERSONIC = 4 };
 enum { OR_LOW_ORDER = 0, OR_HIGH_ORDER = 1, OR_LIMITED = 2 };
 enum { OR_KIND_CELL = 0, OR_KIND_FACE_COLLOC = 1, OR_KIND_FACE = 2 };
 
@@ -52,6 +52,7 @@ typedef struct {
   long n[3];
   double lo[3], hi[3], h[3];
   int bc[6];
+  double bstate[6][OR_MAXM];  /* Dirichlet data U^d per box face (Sec. 4.1) */
   long ncells, ndofs;
   double vol;
   /* CSR of the stencil I(i), diagonal included (reading R4) */
@@ -264,6 +265,8 @@ or_setup *or_create(int dim, int deg, const long *cells, const double *lo, const
     if (e < dim) { S->ncells *= S->n[e]; S->vol *= S->hi[e] - S->lo[e]; }
   }
   for (int f = 0; f < 6; ++f) S->bc[f] = f < 2 * dim ? bc[f] : OR_BC_OUTFLOW;
+  for (int f = 0; f < 2 * dim; ++f)
+    if (S->bc[f] < OR_BC_PERIODIC || S->bc[f] > OR_BC_SUPERSONIC) { free(S); return NULL; }
   for (int e = 0; e < dim; ++e) {
     int p0 = S->bc[2 * e] == OR_BC_PERIODIC, p1 = S->bc[2 * e + 1] == OR_BC_PERIODIC;
     if (p0 != p1 || (p0 && S->n[e] < 2) || S->n[e] < 1) { free(S); return NULL; }
@@ -576,20 +579,45 @@ void or_riemann_sample(double g, double rl, double ul, double pl, double rr, dou
 /* Boundary data (Sec. 4.1)                                                   */
 /* ------------------------------------------------------------------------ */
 
-/* Ghost state U^{d,k} for boundary part face f of row i.  Outflow is read as
- * the supersonic-outflow branch U^d := U_i (reading R28); slip reflects the
- * normal momentum, eq. slip_boundary, with n = c_i^{d,k}/|c_i^{d,k}|. */
-static void ghost_state(const or_setup *S, int bkind, const double *Ui, const double *cb, double *Ug) {
-  int dim = S->dim;
+/* Ghost state U^{d,k} for the boundary part on box face f of row i, with
+ * n = c_i^{d,k}/|c_i^{d,k}|:
+ *  - outflow: the supersonic-outflow branch U^d := U_i (reading R28);
+ *  - slip: the normal momentum reflected, eq. slip_boundary;
+ *  - Dirichlet: the face's data U^d;
+ *  - supersonic in/outflow, eq. supersonic_inoutflow: U^d if u_i.n < -a_i
+ *    (inflow), U_i if u_i.n >= a_i (outflow).  The subsonic range between
+ *    needs the characteristic construction, which is not built: there the
+ *    function returns -4 (and U_i as the ghost).
+ * Returns 0 or -4. */
+static int ghost_state(const or_setup *S, double gamma, int f, const double *Ui, const double *cb, double *Ug) {
+  int dim = S->dim, bkind = S->bc[f];
+  double nn = 0.0;
+  for (int e = 0; e < dim; ++e) nn += cb[e] * cb[e];
+  nn = sqrt(nn);
   for (int c = 0; c < S->m; ++c) Ug[c] = Ui[c];
   if (bkind == OR_BC_SLIP) {
-    double nn = 0.0;
-    for (int e = 0; e < dim; ++e) nn += cb[e] * cb[e];
-    nn = sqrt(nn);
     double mn = 0.0;
     for (int e = 0; e < dim; ++e) mn += Ui[1 + e] * cb[e] / nn;
     for (int e = 0; e < dim; ++e) Ug[1 + e] = Ui[1 + e] - 2.0 * mn * cb[e] / nn;
+  } else if (bkind == OR_BC_DIRICHLET) {
+    for (int c = 0; c < S->m; ++c) Ug[c] = S->bstate[f][c];
+  } else if (bkind == OR_BC_SUPERSONIC) {
+    double un = 0.0;
+    for (int e = 0; e < dim; ++e) un += (Ui[1 + e] / Ui[0]) * cb[e] / nn;
+    double a = sqrt(gamma * (gamma - 1.0) * eps_of(dim, Ui) / Ui[0]);
+    if (un < -a) {
+      for (int c = 0; c < S->m; ++c) Ug[c] = S->bstate[f][c];
+    } else if (!(un >= a)) {
+      return -4;
+    }
   }
+  return 0;
+}
+
+/* Dirichlet data U^d (conserved, m components) of box face f, used by the
+ * Dirichlet and supersonic kinds. */
+void or_set_boundary_state(or_setup *S, int f, const double *U) {
+  for (int c = 0; c < S->m; ++c) S->bstate[f][c] = U[c];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -737,7 +765,8 @@ static double *dalloc(long n) { return (double *)calloc(n > 0 ? n : 1, sizeof(do
 
 /* Phi(U; tau): one forward-Euler step of the scheme selected by P->scheme.
  * tau <= 0 selects tau = Cr * tau_max of this state (eq. MaxCFLdt).
- * Returns 0 on success, -2 if the output leaves the admissible set. */
+ * Returns 0 on success, -2 if the output leaves the admissible set, -4 if a
+ * node of a supersonic in/outflow face sees subsonic normal flow. */
 int or_stage(const or_setup *S, const or_params *P, const double *U, double tau, double *Uout,
              or_diag *dg) {
   const int dim = S->dim, m = S->m;
@@ -754,11 +783,12 @@ int or_stage(const or_setup *S, const or_params *P, const double *U, double tau,
   int status = 0;
 
   /* Sec. 4.1: boundary data per boundary part */
+  int subsonic = 0;
   for (long i = 0; i < N; ++i) {
     double Ui[OR_MAXM];
     get_state(S, U, i, Ui);
     for (long b = S->bptr[i]; b < S->bptr[i + 1]; ++b)
-      ghost_state(S, S->bc[S->bface[b]], Ui, S->bc_c + b * dim, Ug + b * m);
+      if (ghost_state(S, g, S->bface[b], Ui, S->bc_c + b * dim, Ug + b * m)) subsonic = 1;
   }
 
   /* eq. dij_low_order, dij_low_order_modified (reading R2: inside state on
@@ -1104,7 +1134,7 @@ finish:
   free(dij); free(dbd); free(dii); free(UL); free(Nr); free(dH); free(dbH); free(dUH);
   free(A); free(Ab); free(qrmin); free(qrmax); free(qsmin); free(Brmin); free(Brmax); free(Bsmin);
   free(l1); free(lb1); free(U1); free(Ug);
-  return status;
+  return subsonic ? -4 : status;
 }
 
 /* Per-row CFL quantity -m_i/(2 d_ii), eq. CFLcond; the global minimum is
@@ -1123,7 +1153,7 @@ void or_tau_rows(const or_setup *S, const or_params *P, const double *U, double 
     for (long b = S->bptr[i]; b < S->bptr[i + 1]; ++b) {
       const double *cb = S->bc_c + b * dim;
       double nc = norm_c(dim, cb), n[3];
-      ghost_state(S, S->bc[S->bface[b]], Ui, cb, Ug);
+      ghost_state(S, P->gamma, S->bface[b], Ui, cb, Ug);
       for (int e = 0; e < dim; ++e) n[e] = cb[e] / nc;
       s += nc * or_lambda_max(P->gamma, dim, Ui, Ug, n);
     }
@@ -1137,7 +1167,8 @@ void or_tau_rows(const or_setup *S, const or_params *P, const double *U, double 
  * CFL condition of their own state and, on violation, the step restarts from
  * U^n with tau = Cr * tau_max of the violating stage (reading R20).
  * dt_fixed > 0 replaces the CFL rule for stage 1.
- * Returns 0, -2 (inadmissible output) or -3 (CFL restarts exhausted). */
+ * Returns 0, -2 (inadmissible output), -3 (CFL restarts exhausted) or -4
+ * (subsonic normal flow at a supersonic in/outflow face). */
 int or_step(const or_setup *S, const or_params *P, double *U, double dt_cap, double dt_fixed,
             double *dt_taken, int *restarts) {
   const long M = (long)S->m * S->ndofs;

@@ -26,7 +26,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-BC_PERIODIC, BC_OUTFLOW, BC_SLIP = 0, 1, 2
+BC_PERIODIC, BC_OUTFLOW, BC_SLIP, BC_DIRICHLET, BC_SUPERSONIC = 0, 1, 2, 3, 4
 GAMMA = 1.4
 
 
@@ -38,6 +38,9 @@ class MeshSpec:
     lo: tuple
     hi: tuple
     bc: tuple  # per box face 2*axis+side
+    # per box face: the conserved Dirichlet data U^d of the Dirichlet and
+    # supersonic kinds (None elsewhere, or None for no such face)
+    bstate: tuple | None = None
 
     @property
     def nloc(self) -> int:
@@ -189,6 +192,41 @@ def blast(cells: int = 128, gamma: float = GAMMA) -> Workload:
     p = np.where(r2 <= 0.1 ** 2, 100.0, 0.1)
     U = to_conserved(np.ones(ms.ndofs), np.zeros((3, ms.ndofs)), p, gamma)
     return Workload("blast_q1_%d" % cells, ms, U, steps=200)
+
+
+# Supersonic inflow problem: a uniform supersonic stream (DOWNSTREAM) fills
+# the box; from t = 0 the inflow face feeds a different supersonic state
+# (INFLOW).  Every wave of the Riemann problem INFLOW | DOWNSTREAM moves into
+# the box (slowest: the rarefaction head at u - a = 1.32), so the exact
+# solution is that Riemann fan centred on the inflow face.  (rho, u_n, p).
+INFLOW = (1.0, 2.5, 1.0)
+DOWNSTREAM = (0.5, 2.5, 0.6)
+
+
+def inflow(cells: int = 200, dim: int = 1, axis: int = 0, degree: int = 1, cross: int = 4,
+           kind: int = BC_SUPERSONIC) -> Workload:
+    """Unit box, `cells` cells along the flow axis and `cross` across it
+    (periodic), flow along +axis; both faces of the flow axis of boundary kind
+    `kind` with the INFLOW state as data on the inflow face and DOWNSTREAM on
+    the outflow face."""
+    n = tuple(cells if e == axis else cross for e in range(dim))
+    bc = []
+    bstate = []
+    for e in range(dim):
+        for side in range(2):
+            bc.append(kind if e == axis else BC_PERIODIC)
+            if e != axis:
+                bstate.append(None)
+                continue
+            rho, un, p = INFLOW if side == 0 else DOWNSTREAM
+            vel = np.zeros((dim, 1))
+            vel[axis] = un
+            bstate.append(tuple(to_conserved(np.array([rho]), vel, np.array([p]))[:, 0]))
+    ms = MeshSpec(dim, degree, n, (0.0,) * dim, (1.0,) * dim, tuple(bc), tuple(bstate))
+    vel = np.zeros((dim, ms.ndofs))
+    vel[axis] = DOWNSTREAM[1]
+    U = to_conserved(np.full(ms.ndofs, DOWNSTREAM[0]), vel, np.full(ms.ndofs, DOWNSTREAM[2]))
+    return Workload("inflow_%dd_q%d_%d" % (dim, degree, cells), ms, U, t_final=0.2)
 
 
 def serving_trace(count: int = 256, n_min: int = 32, n_max: int = 512, seed0: int = 1000,
