@@ -45,13 +45,30 @@ typedef enum {
   GDG_E_CFL = -3,          /* the CFL condition eq. CFLcond failed after all restarts */
   GDG_E_NOMEM = -4,        /* workspace smaller than gdg_workspace_bytes() */
   GDG_E_DEVICE = -5,       /* a HIP runtime call failed */
-  GDG_E_BUDGET = -6        /* a request can never fit the server's memory pool */
+  GDG_E_BUDGET = -6,       /* a request can never fit the server's memory pool */
+  GDG_E_BOUNDARY = -7      /* a node of a GDG_BC_SUPERSONIC face saw subsonic normal flow */
 } gdg_status;
 
-/* Boundary kinds per box face (Sec. 4.1).  OUTFLOW is the supersonic-outflow
- * branch U^d := U_i of eq. supersonic_inoutflow ("do nothing"); SLIP is
- * eq. slip_boundary; PERIODIC must be set on both faces of an axis. */
-typedef enum { GDG_BC_PERIODIC = 0, GDG_BC_OUTFLOW = 1, GDG_BC_SLIP = 2 } gdg_bc;
+/* Boundary kinds per box face (Sec. 4.1), with n the outward unit normal
+ * c_i^{d}/|c_i^{d}| of the boundary part:
+ *  - OUTFLOW: the supersonic-outflow branch U^d := U_i of
+ *    eq. supersonic_inoutflow ("do nothing");
+ *  - SLIP: eq. slip_boundary, the normal momentum reflected;
+ *  - DIRICHLET: U^d := the face's data bc_state[f] (Sec. 4.1, Dirichlet
+ *    boundary conditions; data constant in space and time);
+ *  - SUPERSONIC: eq. supersonic_inoutflow, U^d := bc_state[f] where
+ *    u_i.n < -a_i (inflow) and U^d := U_i where u_i.n >= a_i (outflow).  In
+ *    the subsonic range between, the paper blends in the characteristic
+ *    construction of another work, which this library does not provide: a
+ *    step that meets it fails with GDG_E_BOUNDARY;
+ *  - PERIODIC: must be set on both faces of an axis. */
+typedef enum {
+  GDG_BC_PERIODIC = 0,
+  GDG_BC_OUTFLOW = 1,
+  GDG_BC_SLIP = 2,
+  GDG_BC_DIRICHLET = 3,
+  GDG_BC_SUPERSONIC = 4
+} gdg_bc;
 
 /* GDG_LOW_ORDER: eq. cijdijscheme only.  GDG_HIGH_ORDER: eq. HighScheme
  * unlimited.  GDG_LIMITED: eq. LimitedScheme with the bounds of
@@ -72,7 +89,10 @@ typedef enum { GDG_FP64 = 0, GDG_MIXED = 1 } gdg_precision;
 
 /* Uniform Cartesian mesh of cells[0] x cells[1] x cells[2] cells over the box
  * [lo, hi] (only the first dim entries are read), Q_degree elements with
- * degree 1 or 2, dim 1..3, bc[2*dim] boundary kinds. */
+ * degree 1 or 2, dim 1..3, bc[2*dim] boundary kinds.  bc_state[f] holds the
+ * conserved data (rho, momentum, E: the first dim+2 entries) of face f for
+ * the DIRICHLET and SUPERSONIC kinds; it must be admissible (rho > 0,
+ * eps > 0) on those faces and is ignored elsewhere. */
 typedef struct {
   int32_t dim;
   int32_t degree;
@@ -80,6 +100,7 @@ typedef struct {
   double lo[3];
   double hi[3];
   int32_t bc[6];
+  double bc_state[6][5];
 } gdg_mesh_desc;
 
 /* Scheme constants.  gdg_default_params() gives the paper's values:

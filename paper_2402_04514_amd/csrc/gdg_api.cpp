@@ -63,7 +63,20 @@ bool validate(const gdg_mesh_desc *m, const gdg_params *p, std::string *err) {
     if (!(m->hi[e] > m->lo[e])) { *err = "hi must exceed lo"; return false; }
     int b0 = m->bc[2 * e], b1 = m->bc[2 * e + 1];
     for (int b : {b0, b1})
-      if (b < 0 || b > 2) { *err = "unknown boundary kind"; return false; }
+      if (b < GDG_BC_PERIODIC || b > GDG_BC_SUPERSONIC) { *err = "unknown boundary kind"; return false; }
+    for (int side = 0; side < 2; ++side) {
+      const int f = 2 * e + side;
+      if (m->bc[f] != GDG_BC_DIRICHLET && m->bc[f] != GDG_BC_SUPERSONIC) continue;
+      // the face's data must lie in A (eq. AddSet)
+      const double *V = m->bc_state[f];
+      double m2 = 0.0;
+      for (int k = 0; k < m->dim; ++k) m2 += V[1 + k] * V[1 + k];
+      const double rho = V[0], eps = V[m->dim + 1] - 0.5 * m2 / rho;
+      if (!(rho > 0.0) || !(eps > 0.0) || !std::isfinite(rho) || !std::isfinite(V[m->dim + 1])) {
+        *err = "Dirichlet data of a face is not admissible (rho <= 0, eps <= 0 or not finite)";
+        return false;
+      }
+    }
     if ((b0 == GDG_BC_PERIODIC) != (b1 == GDG_BC_PERIODIC)) {
       *err = "periodic must be set on both faces of an axis";
       return false;
@@ -347,7 +360,11 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
     h[e] = (mesh->hi[e] - mesh->lo[e]) / (double)mesh->cells[e];
     vol *= mesh->hi[e] - mesh->lo[e];
   }
-  for (int f = 0; f < 6; ++f) A.bc[f] = f < 2 * mesh->dim ? mesh->bc[f] : GDG_BC_OUTFLOW;
+  A.bcbits = 0;
+  for (int f = 0; f < 6; ++f) {
+    A.bc[f] = f < 2 * mesh->dim ? mesh->bc[f] : GDG_BC_OUTFLOW;
+    A.bcbits |= (A.bc[f] & 7) << (3 * f);
+  }
   A.gamma = prm->gamma;
   A.cfl = prm->cfl;
   A.c_ev = prm->c_ev;
@@ -405,6 +422,9 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
       return GDG_E_INVALID;
     }
   }
+  for (int f = 0; f < 2 * mesh->dim; ++f)
+    if (A.bc[f] == GDG_BC_DIRICHLET || A.bc[f] == GDG_BC_SUPERSONIC)
+      for (int q = 0; q < L.M; ++q) T->bstate[f][q] = mesh->bc_state[f][q];
   std::memset(&ctx->hctl, 0, sizeof(Ctl));
   hipError_t e1 = hipMemcpyAsync(ctx->dref, T, sizeof(RefTables), hipMemcpyHostToDevice, ctx->stream);
   hipError_t e2 = hipMemcpyAsync(A.ctl, &ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream);
@@ -515,10 +535,7 @@ gdg_status step_impl(gdg_ctx *ctx, double dt_cap, double dt_fixed, double *dt_ta
       ++ctx->restarts;
       continue;
     }
-    if (h.bad_flag) {
-      ctx->err = "a stage output left the admissible set";
-      return GDG_E_INADMISSIBLE;
-    }
+    if (h.bad_flag) return gdg::flag_status(ctx, h.bad_flag, "a stage output left the admissible set");
     ctx->last_dt = h.tau;
     sync_time(ctx);
     if (dt_taken) *dt_taken = h.tau;
@@ -558,10 +575,7 @@ gdg_status gdg_run_to(gdg_ctx *ctx, double t_final, int64_t max_steps, gdg_stats
     HIPCHK(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
     if (gdg_status s = read_ctl(ctx)) return s;
     const Ctl h = ctx->hctl;
-    if (h.bad_flag) {
-      ctx->err = "a stage output left the admissible set";
-      return GDG_E_INADMISSIBLE;
-    }
+    if (h.bad_flag) return gdg::flag_status(ctx, h.bad_flag, "a stage output left the admissible set");
     ctx->last_dt = h.tau;
     sync_time(ctx);
     if (h.cfl_flag) {
@@ -614,6 +628,15 @@ gdg_status ctx_restart(gdg_ctx *ctx, const Ctl &c, double t_final) {
 
 const char *ctx_error(const gdg_ctx *ctx) { return ctx->err.c_str(); }
 
+gdg_status flag_status(gdg_ctx *ctx, int flag, const char *what) {
+  if (flag & 2) {
+    ctx->err = "subsonic normal flow at a node of a supersonic in/outflow face";
+    return GDG_E_BOUNDARY;
+  }
+  ctx->err = what;
+  return GDG_E_INADMISSIBLE;
+}
+
 }  // namespace gdg
 
 extern "C" {
@@ -627,10 +650,7 @@ gdg_status gdg_stage(gdg_ctx *ctx, double tau, double *tau_used) {
   if (gdg_status s = launched(ctx, launch_stage(ctx->A, b, 0, ctx->stream, prof_of(ctx), 1), "stage")) return s;
   if (gdg_status s = read_ctl(ctx)) return s;
   if (gdg_status s = harvest(ctx)) return s;
-  if (ctx->hctl.bad_flag) {
-    ctx->err = "the stage output left the admissible set";
-    return GDG_E_INADMISSIBLE;
-  }
+  if (ctx->hctl.bad_flag) return gdg::flag_status(ctx, ctx->hctl.bad_flag, "the stage output left the admissible set");
   ctx->cur = c1;
   drop_graph(ctx);  // the captured graph names the old buffer roles
   if (tau_used) *tau_used = ctx->hctl.tau;

@@ -73,6 +73,11 @@ struct RefTables {
   // per node a, from the scheme constants
   double hpk[kMaxNloc];    // c_k * hhat_a^{p_k}, hhat_a = (m_a/|Omega|)^{1/d} (eq. ViscMin)
   double relax[kMaxNloc];  // c_r * hhat_a^{p_r} (eq. ViscMinConst2)
+  // Dirichlet data U^d of each box face (Dirichlet and supersonic kinds), and
+  // its node fields as a node cache row holds them, written on the device at
+  // set-up: U (dim+2), velocity (dim), p, a, p^-alpha, f(s), s~, 1/p
+  double bstate[6][kMaxD + 2];
+  double bnode[6][2 * kMaxD + 8];
 };
 
 // Everything a kernel needs, passed by value.
@@ -81,6 +86,7 @@ struct KArgs {
   int32_t R, W, nloc, nb1, deg, dim, cpb;
   int64_t cells[3];
   int32_t bc[6];
+  int32_t bcbits;   // the boundary kind of face f in bits 3f..3f+2
   double gamma, cfl, c_ev, c_k, pk, c_r, p_r, vol;
   double alpha, inv_alpha;
   int32_t ipow;     // > 0: 1/alpha equals this integer, the p* power is taken by multiplies
@@ -176,5 +182,9 @@ void ctx_sync(gdg_ctx *ctx, const Ctl &c);
 // rule of gdg_step), then re-arms the device-driven loop.
 gdg_status ctx_restart(gdg_ctx *ctx, const Ctl &c, double t_final);
 const char *ctx_error(const gdg_ctx *ctx);
+// Status of a control block's bad_flag: GDG_E_BOUNDARY for bit 2 (subsonic
+// flow at a supersonic face), else GDG_E_INADMISSIBLE with the text `what`;
+// sets the context's error text.
+gdg_status flag_status(gdg_ctx *ctx, int flag, const char *what);
 
 }  // namespace gdg

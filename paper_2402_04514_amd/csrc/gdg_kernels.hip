@@ -363,7 +363,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_fill(KArgs A) {
         else bnd = true;
       }
       if (bnd) {
-        put((int32_t)i, &T->cghost[(f * kMaxNloc + a) * kMaxD], (uint8_t)(SK_GHOST | (A.bc[f] << 3)));
+        put((int32_t)i, &T->cghost[(f * kMaxNloc + a) * kMaxD], (uint8_t)(SK_GHOST | (f << 3)));
         continue;
       }
       int64_t Kn = 0, stride = 1;
@@ -426,23 +426,53 @@ __global__ void k_end(Ctl *ctl) {
 }
 
 // ---------------------------------------------------------------------------
+// Node-cache fields of a state V: velocity (D), p, a, p^-alpha, f(s), s~,
+// 1/p.  Returns whether V lies in A.
+template <int D>
+__device__ __forceinline__ bool node_fields(const KArgs &A, const double *V, double *W) {
+  // no contraction: every kernel that builds node fields (the node cache, the
+  // boundary data) rounds them alike, so equal states give equal fields
+#pragma clang fp contract(off)
+  const double g = A.gamma;
+  double rho = V[0];
+  double m2 = 0.0;
+  for (int e = 0; e < D; ++e) m2 += V[1 + e] * V[1 + e];
+  double eps = V[D + 1] - 0.5 * m2 / rho;
+  double p = (g - 1.0) * eps;
+  double rg = pow(rho, -g);
+  for (int e = 0; e < D; ++e) W[e] = V[1 + e] / rho;
+  W[D + 0] = p;
+  W[D + 1] = sqrt(g * p / rho);
+  W[D + 2] = pow(p, -A.alpha);
+  W[D + 3] = exp(log(rg * p) / (g + 1.0));  // Harten entropy f(s) = e^{s/(gamma+1)}
+  W[D + 4] = rg * eps;                      // s~ = rho^-gamma eps
+  W[D + 5] = 1.0 / p;
+  return rho > 0.0 && eps > 0.0;
+}
+
 // Node cache of row i from its state V (and the admissibility flag).
 template <int D>
 __device__ __forceinline__ void store_prim(const KArgs &A, int64_t i, const double *V) {
   const int64_t N = A.N;
-  const double g = A.gamma;
-  double rho = V[0];
-  double eps = eps_of<D>(V);
-  if (!(rho > 0.0) || !(eps > 0.0)) atomicOr(&A.ctl->bad_flag, 1);
-  double p = (g - 1.0) * eps;
-  double rg = pow(rho, -g);
-  for (int e = 0; e < D; ++e) A.Wc[e * N + i] = V[1 + e] / rho;
-  A.Wc[(D + 0) * N + i] = p;
-  A.Wc[(D + 1) * N + i] = sqrt(g * p / rho);
-  A.Wc[(D + 2) * N + i] = pow(p, -A.alpha);
-  A.Wc[(D + 3) * N + i] = exp(log(rg * p) / (g + 1.0));  // Harten entropy f(s) = e^{s/(gamma+1)}
-  A.Wc[(D + 4) * N + i] = rg * eps;                      // s~ = rho^-gamma eps
-  A.Wc[(D + 5) * N + i] = 1.0 / p;
+  double W[D + 6];
+  if (!node_fields<D>(A, V, W)) atomicOr(&A.ctl->bad_flag, 1);
+  for (int k = 0; k < D + 6; ++k) A.Wc[k * N + i] = W[k];
+}
+
+// Set-up: the node fields of each face's Dirichlet data, computed by the same
+// code as the node cache, so that data equal to a node's state gives that
+// node's fields bit for bit.
+template <int D>
+__global__ void k_bnodes(KArgs A, RefTables *T) {
+  const int f = threadIdx.x;
+  if (f >= 2 * D) return;
+  const int kind = (A.bcbits >> (3 * f)) & 7;
+  if (kind != GDG_BC_DIRICHLET && kind != GDG_BC_SUPERSONIC) return;
+  double V[D + 2], W[D + 6];
+  for (int q = 0; q < D + 2; ++q) V[q] = T->bstate[f][q];
+  if (!node_fields<D>(A, V, W)) atomicOr(&A.ctl->bad_flag, 1);
+  for (int q = 0; q < D + 2; ++q) T->bnode[f][q] = V[q];
+  for (int k = 0; k < D + 6; ++k) T->bnode[f][D + 2 + k] = W[k];
 }
 
 template <int D>
@@ -479,18 +509,47 @@ __device__ __forceinline__ void load_node(const KArgs &A, const double *__restri
   n.ip = A.Wc[(D + 5) * N + j];
 }
 
-// Boundary data of Sec. 4.1: outflow keeps U_i; slip reflects the normal
-// momentum (eq. slip_boundary).  Pressure, sound speed and entropy are those
-// of U_i in both cases.
-template <int D>
-__device__ __forceinline__ void ghost_node(const Node<D> &ni, int kind, const double *n, Node<D> &gh) {
+// Boundary data of Sec. 4.1 for a boundary part of row i on box face f, with
+// outward unit normal n: outflow keeps U_i; slip reflects the normal momentum
+// (eq. slip_boundary; pressure, sound speed and entropy stay those of U_i);
+// Dirichlet takes the face's data; supersonic in/outflow
+// (eq. supersonic_inoutflow) takes the data where u_i.n < -a_i and U_i where
+// u_i.n >= a_i, and flags the subsonic range between (bit 2 of bad_flag: the
+// step fails, its boundary construction is not provided).  BD = false: the
+// mesh has no face with data (the caller knows), and that code is left out.
+template <int D, bool BD = true>
+__device__ __forceinline__ void ghost_node(const KArgs &A, const Node<D> &ni, int f, const double *n,
+                                           Node<D> &gh) {
+  const int kind = (A.bcbits >> (3 * f)) & 7;
   gh = ni;
-  if (kind == 2) {
+  if (kind == GDG_BC_SLIP) {
     double mn = 0.0, un = 0.0;
-    for (int e = 0; e < D; ++e) { mn += ni.U[1 + e] * n[e]; un += ni.u[e] * n[e]; }
+    for (int e = 0; e < D; ++e) {
+      mn += ni.U[1 + e] * n[e];
+      un += ni.u[e] * n[e];
+    }
     for (int e = 0; e < D; ++e) {
       gh.U[1 + e] = ni.U[1 + e] - 2.0 * mn * n[e];
       gh.u[e] = ni.u[e] - 2.0 * un * n[e];
+    }
+  }
+  if constexpr (BD) {
+    if (kind == GDG_BC_DIRICHLET || kind == GDG_BC_SUPERSONIC) {
+      double un = 0.0;
+      for (int e = 0; e < D; ++e) un += ni.u[e] * n[e];
+      const bool data = kind == GDG_BC_DIRICHLET || un < -ni.a;
+      if (!data && !(un >= ni.a)) atomicOr(&A.ctl->bad_flag, 2);
+      if (data) {
+        const double *b = A.ref->bnode[f];
+        for (int q = 0; q < D + 2; ++q) gh.U[q] = b[q];
+        for (int e = 0; e < D; ++e) gh.u[e] = b[D + 2 + e];
+        gh.p = b[2 * D + 2];
+        gh.a = b[2 * D + 3];
+        gh.pal = b[2 * D + 4];
+        gh.fs = b[2 * D + 5];
+        gh.st = b[2 * D + 6];
+        gh.ip = b[2 * D + 7];
+      }
     }
   }
 }
@@ -502,7 +561,7 @@ __device__ __forceinline__ double block_min_atomic(double v, unsigned long long 
 }
 
 // ---------------------------------------------------------------------------
-template <int D, int DEG, bool MX>
+template <int D, int DEG, bool MX, bool BD = true>
 __device__ __forceinline__ void sweep1_body(const KArgs &A, const double *__restrict__ U, int stage,
                                             int64_t blk) {
   using Acc = typename AccT<MX>::type;
@@ -593,7 +652,7 @@ __device__ __forceinline__ void sweep1_body(const KArgs &A, const double *__rest
       if (ghost) {
         double n[D];
         for (int e = 0; e < D; ++e) n[e] = c[e] * inv;
-        ghost_node<D>(ni, meta >> 3, n, nr);
+        ghost_node<D, BD>(A, ni, meta >> 3, n, nr);
       }
       // d^L_ij from the lower index for a graph pair, so d_ij = d_ji bitwise;
       // the inside state on the left for a boundary part
@@ -654,10 +713,10 @@ __device__ __forceinline__ void sweep1_body(const KArgs &A, const double *__rest
   block_min_atomic(tau_i, &A.ctl->taumin_bits[stage]);
 }
 
-template <int D, int DEG, bool MX>
+template <int D, int DEG, bool MX, bool BD>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_SWEEP1))) void k_sweep1(
     KArgs A, const double *__restrict__ U, int stage) {
-  sweep1_body<D, DEG, MX>(A, U, stage, xcd_block(A, blockIdx.x));
+  sweep1_body<D, DEG, MX, BD>(A, U, stage, xcd_block(A, blockIdx.x));
 }
 
 // high-order viscosity of eq. HighOrderViscosity / ViscMin for a graph pair
@@ -744,7 +803,7 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
         const double inc = 1.0 / nc;
         for (int e = 0; e < D; ++e) n[e] = c[e] * inc;
         Node<D> gh;
-        ghost_node<D>(ni, meta >> 3, n, gh);
+        ghost_node<D>(A, ni, meta >> 3, n, gh);
         double fj[M], fi[M];
         flux_dot<D>(gh.U, gh.u, gh.p, c, fj);
         flux_dot<D>(ni.U, ni.u, ni.p, c, fi);
@@ -839,25 +898,25 @@ __device__ __forceinline__ void pair_flux(const KArgs &A, const double *__restri
   for (int q = 0; q < D + 2; ++q) Aij[q] = td * (U[q * N + j] - Ui[q]) - mij * (A.dUH[q * N + j] - dUi[q]);
 }
 
-// Boundary part of A_i^d for one ghost slot: tau (d^{d,H} - d^{d,L})(U^d - U_i).
+// Boundary part of A_i^d for one ghost slot: tau (d^{d,H} - d^{d,L})(U^d - U_i),
+// with U^d built from the node of row i as in the sweeps.
 template <int D>
-__device__ __forceinline__ void ghost_flux(const KArgs &A, int64_t s, uint8_t meta, const double *Ui, double Ni,
-                                           double hpk, double tau, double d, double *Ab) {
+__device__ __forceinline__ void ghost_flux(const KArgs &A, const double *__restrict__ U, int64_t i, int64_t s,
+                                           uint8_t meta, const double *Ui, double Ni, double hpk, double tau,
+                                           double d, double *Ab) {
   double c[D], nc2 = 0.0;
   for (int e = 0; e < D; ++e) {
     c[e] = A.mixed ? (double)A.cf[e * A.nslots + s] : A.c[e * A.nslots + s];
     nc2 += c[e] * c[e];
   }
   const double inc = 1.0 / sqrt(nc2);
-  double Ug[D + 2];
-  for (int q = 0; q < D + 2; ++q) Ug[q] = Ui[q];
-  if ((meta >> 3) == 2) {
-    double mn = 0.0;
-    for (int e = 0; e < D; ++e) mn += Ui[1 + e] * (c[e] * inc);
-    for (int e = 0; e < D; ++e) Ug[1 + e] = Ui[1 + e] - 2.0 * mn * (c[e] * inc);
-  }
+  double n[D];
+  for (int e = 0; e < D; ++e) n[e] = c[e] * inc;
+  Node<D> ni, gh;
+  load_node<D>(A, U, i, ni);
+  ghost_node<D>(A, ni, meta >> 3, n, gh);
   const double dH = fmax(hpk * d, d * fmin(A.c_ev * fabs(Ni), 1.0));
-  for (int q = 0; q < D + 2; ++q) Ab[q] += tau * (dH - d) * (Ug[q] - Ui[q]);
+  for (int q = 0; q < D + 2; ++q) Ab[q] += tau * (dH - d) * (gh.U[q] - Ui[q]);
 }
 
 // One limiter pass (eq. ConvexScheme, Lemma ConsInvariants).  Row i runs both
@@ -928,7 +987,7 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
     if (kind == SK_PAD) continue;
     const double d = A.dL[s];
     if (kind == SK_GHOST) {
-      ghost_flux<D>(A, s, meta, Ui, Ni, hpk, tau, d, Ab);
+      ghost_flux<D>(A, U, i, s, meta, Ui, Ni, hpk, tau, d, Ab);
       if (gslot < 0) gslot = s;
       continue;
     }
@@ -1116,8 +1175,18 @@ static int stage_impl(const KArgs &A, const StageBufs &b, int stage, void *strea
     hipLaunchKernelGGL(k_prim<D>, dim3(gp), blk, 0, S(stream), A, b.in);
     prof_mark(prof, KID_PRIM, 1, stream);
   }
+  // sweep 1 without the boundary-data code where no face has data: its
+  // registers set the occupancy of the hottest kernel
+  bool bd = false;
+  for (int f = 0; f < 2 * D; ++f) {
+    const int kind = (A.bcbits >> (3 * f)) & 7;
+    bd = bd || kind == GDG_BC_DIRICHLET || kind == GDG_BC_SUPERSONIC;
+  }
   prof_mark(prof, KID_SWEEP1, 0, stream);
-  hipLaunchKernelGGL((k_sweep1<D, DEG, MX>), grid, blk, 0, S(stream), A, b.in, stage);
+  if (bd)
+    hipLaunchKernelGGL((k_sweep1<D, DEG, MX, true>), grid, blk, 0, S(stream), A, b.in, stage);
+  else
+    hipLaunchKernelGGL((k_sweep1<D, DEG, MX, false>), grid, blk, 0, S(stream), A, b.in, stage);
   prof_mark(prof, KID_SWEEP1, 1, stream);
   prof_mark(prof, KID_SWEEP2, 0, stream);
   hipLaunchKernelGGL((k_sweep2<D, DEG, MX>), grid, blk, 0, S(stream), A, b, stage);
@@ -1134,6 +1203,7 @@ template <int D, int DEG>
 static int fill_impl(const KArgs &A, void *stream) {
   clear_stale();
   hipLaunchKernelGGL((k_fill<D, DEG>), dim3((unsigned)A.nblocks), dim3(kBlockThreads), 0, S(stream), A);
+  hipLaunchKernelGGL(k_bnodes<D>, dim3(1), dim3(kBlockThreads), 0, S(stream), A, const_cast<RefTables *>(A.ref));
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -188,7 +188,8 @@ gdg_status process(gdg_server *s) {
     Req *q = s->launched[r];
     const Ctl c = s->hstat[r];
     if (c.bad_flag) {
-      fail_req(s, q, GDG_E_INADMISSIBLE, "a stage output left the admissible set");
+      const gdg_status st = flag_status(q->ctx, c.bad_flag, "a stage output left the admissible set");
+      fail_req(s, q, st, ctx_error(q->ctx));
       continue;
     }
     ctx_sync(q->ctx, c);

@@ -15,10 +15,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgdg.so")
 
-GDG_OK, GDG_E_INVALID, GDG_E_INADMISSIBLE, GDG_E_CFL, GDG_E_NOMEM, GDG_E_DEVICE, GDG_E_BUDGET = (
-    0, -1, -2, -3, -4, -5, -6)
+(GDG_OK, GDG_E_INVALID, GDG_E_INADMISSIBLE, GDG_E_CFL, GDG_E_NOMEM, GDG_E_DEVICE, GDG_E_BUDGET,
+ GDG_E_BOUNDARY) = (0, -1, -2, -3, -4, -5, -6, -7)
 GDG_REQ_PENDING, GDG_REQ_RUNNING, GDG_REQ_DONE, GDG_REQ_FAILED = 0, 1, 2, 3
-GDG_BC_PERIODIC, GDG_BC_OUTFLOW, GDG_BC_SLIP = 0, 1, 2
+GDG_BC_PERIODIC, GDG_BC_OUTFLOW, GDG_BC_SLIP, GDG_BC_DIRICHLET, GDG_BC_SUPERSONIC = 0, 1, 2, 3, 4
 GDG_LOW_ORDER, GDG_HIGH_ORDER, GDG_LIMITED = 0, 1, 2
 GDG_FP64, GDG_MIXED = 0, 1
 (GDG_FIELD_STATE, GDG_FIELD_EV_N, GDG_FIELD_BOUNDS, GDG_FIELD_UL, GDG_FIELD_DUH,
@@ -26,7 +26,7 @@ GDG_FP64, GDG_MIXED = 0, 1
 _FIELD_PLANES = {GDG_FIELD_EV_N: 1, GDG_FIELD_BOUNDS: 3}
 
 _NAMES = {0: "GDG_OK", -1: "GDG_E_INVALID", -2: "GDG_E_INADMISSIBLE", -3: "GDG_E_CFL",
-          -4: "GDG_E_NOMEM", -5: "GDG_E_DEVICE", -6: "GDG_E_BUDGET"}
+          -4: "GDG_E_NOMEM", -5: "GDG_E_DEVICE", -6: "GDG_E_BUDGET", -7: "GDG_E_BOUNDARY"}
 
 
 class GdgError(RuntimeError):
@@ -37,7 +37,8 @@ class GdgError(RuntimeError):
 
 class gdg_mesh_desc(C.Structure):
     _fields_ = [("dim", C.c_int32), ("degree", C.c_int32), ("cells", C.c_int64 * 3),
-                ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("bc", C.c_int32 * 6)]
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("bc", C.c_int32 * 6),
+                ("bc_state", (C.c_double * 5) * 6)]
 
 
 class gdg_params(C.Structure):
@@ -128,7 +129,9 @@ def _check(st, ctx=None):
         raise GdgError(st, msg)
 
 
-def mesh_desc(dim, degree, cells, lo, hi, bc) -> gdg_mesh_desc:
+def mesh_desc(dim, degree, cells, lo, hi, bc, bstate=None) -> gdg_mesh_desc:
+    """bstate: per face the conserved Dirichlet data of the DIRICHLET and
+    SUPERSONIC kinds (None, or None entries, elsewhere)."""
     m = gdg_mesh_desc()
     m.dim, m.degree = dim, degree
     for e in range(3):
@@ -137,6 +140,9 @@ def mesh_desc(dim, degree, cells, lo, hi, bc) -> gdg_mesh_desc:
         m.hi[e] = float(hi[e]) if e < dim else 1.0
     for f in range(6):
         m.bc[f] = int(bc[f]) if f < 2 * dim else GDG_BC_OUTFLOW
+        if bstate is not None and f < 2 * dim and bstate[f] is not None:
+            for q, v in enumerate(bstate[f]):
+                m.bc_state[f][q] = float(v)
     return m
 
 
@@ -249,11 +255,11 @@ class Solver:
     and whose stream is torch's current stream there (or ``stream``)."""
 
     def __init__(self, dim, degree, cells, lo, hi, bc, params: gdg_params | None = None,
-                 device="cuda:0", stream=None):
+                 device="cuda:0", stream=None, bstate=None):
         import torch
         self.torch = torch
         self.dim, self.m = dim, dim + 2
-        self.mesh = mesh_desc(dim, degree, cells, lo, hi, bc)
+        self.mesh = mesh_desc(dim, degree, cells, lo, hi, bc, bstate)
         self.params = params if params is not None else gdg_default_params(degree)
         self.device = torch.device(device)
         nbytes = gdg_workspace_bytes(self.mesh, self.params)
@@ -266,7 +272,8 @@ class Solver:
 
     @classmethod
     def from_spec(cls, ms, params=None, **kw):
-        return cls(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc, params, **kw)
+        return cls(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc, params,
+                   bstate=getattr(ms, "bstate", None), **kw)
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -389,7 +396,7 @@ class Server:
         prm = params if params is not None else gdg_default_params(ms.degree)
         if params is None:
             prm.precision = self.desc.precision
-        mesh = mesh_desc(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc)
+        mesh = mesh_desc(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc, getattr(ms, "bstate", None))
         return gdg_server_submit(self.srv, mesh, prm, U0, t_final)
 
     def pump(self):

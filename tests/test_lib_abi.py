@@ -4,6 +4,8 @@ validation) behave as documented.  No GPU work is issued here."""
 import os
 import re
 
+import ctypes as C
+
 import pytest
 
 from paper_2402_04514_amd import gdg
@@ -64,6 +66,32 @@ def test_invalid_mesh_rejected(desc):
     with pytest.raises(gdg.GdgError) as ei:
         gdg.gdg_workspace_bytes(m, gdg.gdg_default_params(1))
     assert ei.value.status == gdg.GDG_E_INVALID
+
+
+def test_mesh_desc_layout():
+    """The ctypes mirror of gdg_mesh_desc has the C layout of include/gdg.h."""
+    assert gdg.gdg_mesh_desc.bc.offset == 80
+    assert gdg.gdg_mesh_desc.bc_state.offset == 104
+    assert C.sizeof(gdg.gdg_mesh_desc) == 344
+
+
+@pytest.mark.parametrize("kind", [gdg.GDG_BC_DIRICHLET, gdg.GDG_BC_SUPERSONIC])
+@pytest.mark.parametrize("state,ok", [
+    (None, False),                         # no data: rho = 0
+    ((1.0, 0.5, 0.0, 2.0), True),
+    ((1.0, 3.0, 0.0, 2.0), False),         # eps < 0
+    ((-1.0, 0.0, 0.0, 2.0), False),
+    ((1.0, 0.0, 0.0, float("nan")), False),
+])
+def test_dirichlet_data_validated(kind, state, ok):
+    bstate = (state, None, None, None)
+    m = gdg.mesh_desc(2, 1, (8, 8), (0, 0), (1, 1), (kind, 1, 1, 1), bstate)
+    if ok:
+        assert gdg.gdg_workspace_bytes(m, gdg.gdg_default_params(1)) > 0
+    else:
+        with pytest.raises(gdg.GdgError) as ei:
+            gdg.gdg_workspace_bytes(m, gdg.gdg_default_params(1))
+        assert ei.value.status == gdg.GDG_E_INVALID
 
 
 @pytest.mark.parametrize("field,value", [("gamma", 2.0), ("gamma", 1.0), ("cfl", 0.0), ("cfl", 1.5),

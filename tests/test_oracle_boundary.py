@@ -94,9 +94,9 @@ def test_data_equal_to_boundary_state_matches_outflow(oracle, kind):
         ms = W.MeshSpec(1, 1, ms0.cells, ms0.lo, ms0.hi, (kind, kind), bstate)
         U0, tf = wl.U0, 0.2
     else:
-        w0 = W.inflow(100)
+        w0 = W.inflow(128)
         U0 = w0.U0.copy()
-        U0[:, : U0.shape[1] // 2] = np.array(w0.mesh.bstate[0])[:, None]  # a step in the interior
+        U0[:, : 3 * U0.shape[1] // 4] = np.array(w0.mesh.bstate[0])[:, None]  # a step at x = 3/4
         ms, tf = w0.mesh, 0.1
     Ma = make(oracle, ms)
     Mb = make(oracle, W.MeshSpec(1, 1, ms.cells, ms.lo, ms.hi, (W.BC_OUTFLOW, W.BC_OUTFLOW)))
