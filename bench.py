@@ -47,6 +47,10 @@ WORKLOADS = {
     "blast": ({}, "3D Euler DG Q1, 128^3 cells on [0,1]^3 (16,777,216 dofs), blast p=100 in r<0.1, "
                   "slip walls, FP64, convex-limited, SSP-RK3", 10, 2),
     "sod": ({}, "1D Euler DG Q1, 200 cells on [0,1] (400 dofs), Sod shock tube, outflow, FP64", 700, 20),
+    "inflow": ({"cells": 1024, "dim": 2, "axis": 0, "degree": 2, "cross": 1024},
+               "2D Euler DG Q2, 1024x1024 cells on [0,1]^2 (9,437,184 dofs), supersonic inflow (Dirichlet data "
+               "rho,u,p = 1,2.5,1) into a supersonic stream (0.5,2.5,0.6), supersonic in/outflow faces in x, "
+               "periodic in y, FP64, convex-limited, SSP-RK3", 20, 3),
 }
 
 
@@ -295,17 +299,20 @@ def cpu_baseline(name, budget_s):
     from paper_2402_04514_amd import workloads as W
 
     oracle.build()
-    full = W.CONFIGS[name]()
+    base = WORKLOADS[name][0]
+    full = W.CONFIGS[name](**base)
     wl = full
     note = ""
     if full.mesh.ndofs > 300_000:  # one oracle step would exceed the budget: same problem, coarser
         f = {2: 8, 3: 4}.get(full.mesh.dim, 1)
-        kw = {"cells": full.mesh.cells[0] // f}
+        kw = dict(base, cells=full.mesh.cells[0] // f)
+        if "cross" in kw:
+            kw["cross"] = kw["cross"] // f
         wl = W.CONFIGS[name](**kw)
         note = "; the same problem on %s cells (1/%d per axis) to bound the CPU time" % (
             "x".join(str(c) for c in wl.mesh.cells), f)
     ms = wl.mesh
-    M = oracle.Mesh(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc)
+    M = oracle.Mesh(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc, bstate=ms.bstate)
     prm = oracle.params(degree=ms.degree)
     U = wl.U0
     n, t0 = 0, time.perf_counter()

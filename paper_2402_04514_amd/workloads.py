@@ -257,4 +257,5 @@ CONFIGS = {
     "vortex": vortex,
     "quadrant": quadrant,
     "blast": blast,
+    "inflow": inflow,
 }
