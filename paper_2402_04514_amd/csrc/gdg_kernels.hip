@@ -912,11 +912,26 @@ __device__ __forceinline__ void ghost_flux(const KArgs &A, const double *__restr
   const double inc = 1.0 / sqrt(nc2);
   double n[D];
   for (int e = 0; e < D; ++e) n[e] = c[e] * inc;
-  Node<D> ni, gh;
-  load_node<D>(A, U, i, ni);
-  ghost_node<D>(A, ni, meta >> 3, n, gh);
+  const int f = meta >> 3;
+  const int kind = (A.bcbits >> (3 * f)) & 7;
+  double Ug[D + 2];
+  if (kind == GDG_BC_DIRICHLET || kind == GDG_BC_SUPERSONIC) {
+    // the data kinds decide from the node of row i, as the sweeps do
+    Node<D> ni, gh;
+    load_node<D>(A, U, i, ni);
+    ghost_node<D>(A, ni, f, n, gh);
+    for (int q = 0; q < D + 2; ++q) Ug[q] = gh.U[q];
+  } else {
+    // outflow and slip need U_i alone (the same arithmetic as ghost_node)
+    for (int q = 0; q < D + 2; ++q) Ug[q] = Ui[q];
+    if (kind == GDG_BC_SLIP) {
+      double mn = 0.0;
+      for (int e = 0; e < D; ++e) mn += Ui[1 + e] * n[e];
+      for (int e = 0; e < D; ++e) Ug[1 + e] = Ui[1 + e] - 2.0 * mn * n[e];
+    }
+  }
   const double dH = fmax(hpk * d, d * fmin(A.c_ev * fabs(Ni), 1.0));
-  for (int q = 0; q < D + 2; ++q) Ab[q] += tau * (dH - d) * (gh.U[q] - Ui[q]);
+  for (int q = 0; q < D + 2; ++q) Ab[q] += tau * (dH - d) * (Ug[q] - Ui[q]);
 }
 
 // One limiter pass (eq. ConvexScheme, Lemma ConsInvariants).  Row i runs both
