@@ -220,6 +220,49 @@ def test_fixed_dt_and_cfl_restart(oracle):
     _close(S.download(), Uo, what="U^{n+1}")
 
 
+@pytest.mark.parametrize("gamma", [5.0 / 3.0, 1.3])
+@pytest.mark.parametrize("name", ["sod_q1_40", "q1_2d_outflow_ragged", "q2_2d_slip", "q1_3d_mixed"])
+def test_other_gamma(oracle, name, gamma):
+    """gamma other than 7/5 takes the general code paths: the p* power by
+    multiplies for gamma = 5/3 (1/alpha = 5) and by pow for 1.3, and the
+    line search on the rescaled entropy psi instead of the integer-power
+    test.  One stage's fields, then ten steps through captured graphs."""
+    _say("gamma %.4f %s" % (gamma, name))
+    p = gdg.gdg_default_params(CASES[name]()[0].degree)
+    p.gamma = gamma
+    ms, U, M, S, op = _pair(oracle, name, params=p)
+    out, dg = M.stage(op, U, diag=True)
+    tau_g = S.stage(0.0)
+    assert tau_g == pytest.approx(op.cfl * dg["tau_max"], rel=1e-13)
+    _close(S.field(gdg.GDG_FIELD_UL), dg["UL"], what="U^L")
+    B = S.field(gdg.GDG_FIELD_BOUNDS)
+    _close(B, np.stack([dg["rho_min"], dg["rho_max"], dg["s_min"]]), what="bounds")
+    _check_ev(S.field(gdg.GDG_FIELD_EV_N)[0], dg)
+    _close(S.field(gdg.GDG_FIELD_DUH), dg["dUH"], what="dU^H")
+    _close(S.field(gdg.GDG_FIELD_U1), dg["U1"], what="U^(1)")
+    _close(S.download(), out, what="Phi(U)")
+    S.upload(U)
+    Uo, t_o, n_o = M.run_to(op, U, 1e30, max_steps=10)
+    st = S.run_to(1e30, max_steps=10)
+    assert st.steps == n_o == 10 and st.t == pytest.approx(t_o, rel=1e-12)
+    _close(S.download(), Uo, tol=1e-10, what="U after 10 steps")
+
+
+def test_vortex_gamma_five_thirds(oracle):
+    """The vortex at gamma = 5/3 (state and scheme): 10 graph steps."""
+    wl = W.vortex(32, gamma=5.0 / 3.0)
+    ms = wl.mesh
+    p = gdg.gdg_default_params(1)
+    p.gamma = 5.0 / 3.0
+    S = gdg.Solver.from_spec(ms, p)
+    S.upload(wl.U0)
+    M = oracle.Mesh(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc)
+    Uo, t_o, n_o = M.run_to(oracle.params(gamma=5.0 / 3.0), wl.U0, 1e30, max_steps=10)
+    st = S.run_to(1e30, max_steps=10)
+    assert st.steps == n_o and st.t == pytest.approx(t_o, rel=1e-12)
+    _close(S.download(), Uo, tol=1e-10, what="U after 10 steps")
+
+
 def test_constant_state_exact():
     """A uniform state is a fixed point in every sweep (difference form)."""
     ms = W.MeshSpec(2, 2, (6, 5), (0, 0), (1, 1), (1, 1, 2, 2))

@@ -108,3 +108,26 @@ def test_exact_solution_conserves(oracle):
     rho = s[:, 0]
     mass = np.trapezoid(rho, x)
     assert mass == pytest.approx(1.0 * 2 + 0.125 * 2, rel=2e-5)
+
+
+@pytest.mark.parametrize("gamma", [5.0 / 3.0, 1.3, 1.1])
+def test_bound_brute_force_other_gamma(oracle, gamma):
+    """The two-rarefaction bound is an upper bound for 1 < gamma <= 5/3
+    (eq. dij_low_order): lambda^+ >= exact lambda_max on random pairs at other
+    gamma too, with equality when both waves are rarefactions."""
+    def c(rho, u, p):
+        return np.array([rho, rho * u, p / (gamma - 1) + 0.5 * rho * u * u])
+
+    rng = np.random.default_rng(int(gamma * 1000))
+    n_rare = 0
+    for _ in range(1500):
+        rl, rr, pl, pr = 10 ** rng.uniform(-3, 3, 4)
+        ul, ur = rng.uniform(-10, 10, 2)
+        lam = oracle.lambda_max(gamma, c(rl, ul, pl), c(rr, ur, pr), np.array([1.0]))
+        ex = oracle.exact_lambda(gamma, rl, ul, pl, rr, ur, pr)
+        assert lam >= ex * (1 - 1e-12) - 1e-13, (gamma, rl, ul, pl, rr, ur, pr)
+        ps, us, vac = oracle.exact_riemann(gamma, rl, ul, pl, rr, ur, pr)
+        if vac == 0 and ps < min(pl, pr):
+            n_rare += 1
+            assert lam == pytest.approx(ex, rel=1e-9)
+    assert n_rare > 50

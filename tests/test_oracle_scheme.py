@@ -302,6 +302,23 @@ def test_vortex_convergence(oracle):
     assert lim[2] < 0.1 * low[2]
 
 
+def test_vortex_convergence_gamma_five_thirds(oracle):
+    """gamma = 5/3 (the paper's vortex runs use it): the limited Q1 scheme is
+    second order on the smooth vortex too, so the gamma-dependent parts
+    (wave-speed bound, entropy, line search) are consistent at other gamma."""
+    g = 5.0 / 3.0
+    tf = 0.5
+    errs = []
+    for n in (16, 32, 64):
+        wl = W.vortex(n, gamma=g)
+        M = make(oracle, wl.mesh)
+        Uex = W.vortex_exact(M.coords(), tf, gamma=g)
+        U, _, _ = M.run_to(oracle.params(gamma=g), wl.U0, tf)
+        errs.append(_l1(M, U, Uex))
+    r = math.log2(errs[1] / errs[2])
+    assert 1.6 < r < 2.4, errs
+
+
 @pytest.mark.parametrize("seed", [240204514, 21, 22])
 def test_low_order_update_inside_unrelaxed_bounds(oracle, seed):
     """eq. ConvexRef writes U^L_i as a convex combination of U_i and the bar
