@@ -3,8 +3,10 @@ configuration that bench.py times (gdg_run_to: device-driven captured graphs).
 
 * vortex, 256 x 256 Q1 (262,144 dofs): the oracle runs the whole mesh, so
   every dof is compared after several steps (1e-10 of the component scale).
-* four-quadrant Riemann data, 1024 x 1024 Q2 (9.4 M dofs), and the 3D blast,
-  128^3 Q1 (16.8 M dofs): one step on the GPU over the whole mesh.  The time
+* four-quadrant Riemann data, 1024 x 1024 Q2 (9.4 M dofs), the 3D blast,
+  128^3 Q1 (16.8 M dofs), and the supersonic inflow, 1024 x 1024 Q2 with
+  Dirichlet data entering through a supersonic face: one step on the GPU over
+  the whole mesh.  The time
   step is checked against the oracle's CFL rule over the whole mesh
   (or_tau_rows on every row, 1e-13).  The state is checked on sampled patches:
   the oracle runs a sub-box of cells around each sample with the oracle's
@@ -53,7 +55,7 @@ def _patch(ms, lo_cell, width):
     the global dof index of each patch dof, and a mask of the core dofs."""
     d, nloc = ms.dim, ms.nloc
     h = [(ms.hi[e] - ms.lo[e]) / ms.cells[e] for e in range(d)]
-    bc, lo, hi = [], [], []
+    bc, lo, hi, bstate = [], [], [], []
     for e in range(d):
         lo.append(ms.lo[e] + lo_cell[e] * h[e])
         hi.append(lo[e] + width[e] * h[e])
@@ -63,9 +65,11 @@ def _patch(ms, lo_cell, width):
             kind = ms.bc[2 * e + side]
             if full or (touches and kind != W.BC_PERIODIC):
                 bc.append(kind)
+                bstate.append(ms.bstate[2 * e + side] if ms.bstate is not None else None)
             else:
                 bc.append(W.BC_OUTFLOW)
-    pm = W.MeshSpec(d, ms.degree, tuple(width), tuple(lo), tuple(hi), tuple(bc))
+                bstate.append(None)
+    pm = W.MeshSpec(d, ms.degree, tuple(width), tuple(lo), tuple(hi), tuple(bc), tuple(bstate))
     pc = np.arange(pm.ncells)
     gcell = np.zeros(pm.ncells, dtype=np.int64)
     core = np.ones(pm.ncells, dtype=bool)
@@ -112,7 +116,7 @@ def _check_patches(oracle, ms, U0, Ug, tau, samples, width):
     worst = 0.0
     for lo_cell in samples:
         pm, gdof, core = _patch(ms, lo_cell, width)
-        Mp = oracle.Mesh(pm.dim, pm.degree, pm.cells, pm.lo, pm.hi, pm.bc)
+        Mp = oracle.Mesh(pm.dim, pm.degree, pm.cells, pm.lo, pm.hi, pm.bc, bstate=pm.bstate)
         Mp.set_reference_volume(float(np.prod(np.subtract(ms.hi, ms.lo))))
         Up, dtp, nres, st = Mp.step(prm, np.ascontiguousarray(U0[:, gdof]), dt_fixed=tau)
         assert st == 0 and nres == 0 and dtp == tau, (lo_cell, st, nres)
@@ -138,9 +142,10 @@ def test_vortex_full_mesh_several_steps(oracle):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("name", ["quadrant", "blast"])
+@pytest.mark.parametrize("name", ["quadrant", "blast", "inflow"])
 def test_full_size_one_step_sampled(oracle, name):
-    wl = W.CONFIGS[name]()
+    kw = {"inflow": {"cells": 1024, "dim": 2, "axis": 0, "degree": 2, "cross": 1024}}.get(name, {})
+    wl = W.CONFIGS[name](**kw)
     ms = wl.mesh
     _say("%s: one GPU step through run_to on %d dofs" % (wl.name, ms.ndofs))
     Ug, st = _gpu_steps(ms, wl.U0, 1)
@@ -148,7 +153,7 @@ def test_full_size_one_step_sampled(oracle, name):
     eps = Ug[-1] - 0.5 * np.sum(Ug[1:-1] ** 2, 0) / Ug[0]
     assert np.all(Ug[0] > 0) and np.all(eps > 0)
     _say("  oracle CFL bound over the whole mesh")
-    M = oracle.Mesh(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc)
+    M = oracle.Mesh(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc, bstate=ms.bstate)
     prm = oracle.params(degree=ms.degree)
     tau = prm.cfl * M.tau_rows(prm, wl.U0).min()
     del M
