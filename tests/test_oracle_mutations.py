@@ -15,8 +15,18 @@ SRC = os.path.join(ROOT, "oracle", "gdg_oracle.c")
 T = "tests/"
 SETUP, PHYS, SCHEME = T + "test_oracle_setup.py", T + "test_oracle_physics.py", T + "test_oracle_scheme.py"
 
+BND = T + "test_oracle_boundary.py"
+
 MUTANTS = {
     # name: (original text, planted text, pin files that must fail)
+    "supersonic_inflow_keeps_state": ("if (un < -a) {\n      for (int c = 0; c < S->m; ++c) Ug[c] = S->bstate[f][c];",
+                                      "if (un < -1e300) {\n      for (int c = 0; c < S->m; ++c) Ug[c] = S->bstate[f][c];",
+                                      [BND + "::test_supersonic_inflow_converges_to_riemann_fan"]),
+    "supersonic_normal_sign": ("un += (Ui[1 + e] / Ui[0]) * cb[e] / nn;", "un -= (Ui[1 + e] / Ui[0]) * cb[e] / nn;",
+                               [BND]),
+    "dirichlet_other_face": ("for (int c = 0; c < S->m; ++c) Ug[c] = S->bstate[f][c];\n  } else if",
+                             "for (int c = 0; c < S->m; ++c) Ug[c] = S->bstate[f ^ 1][c];\n  } else if",
+                             [BND + "::test_dirichlet_inflow_equals_supersonic"]),
     "bar_state_sign": ("(fk[q] - fj[q]) / (2.0 * dij[k])", "(fj[q] - fk[q]) / (2.0 * dij[k])",
                        [SCHEME + "::test_low_order_update_inside_unrelaxed_bounds"]),
     "boundary_term_dropped": (
