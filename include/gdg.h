@@ -175,18 +175,23 @@ gdg_status gdg_download_state(gdg_ctx *ctx, double *U, int32_t is_device_ptr);
  * dt_cap if dt_cap > 0.  Stages 2 and 3 re-check eq. CFLcond on their own
  * state; on violation the step restarts with tau = Cr * that stage's bound
  * (at most 8 times, then GDG_E_CFL).  *dt_taken (may be NULL) receives tau.
- * Returns GDG_E_INADMISSIBLE if a stage output left A. */
+ * Returns GDG_E_INADMISSIBLE if a stage output left A, GDG_E_BOUNDARY if a
+ * node of a GDG_BC_SUPERSONIC face saw subsonic normal flow; after either
+ * error the context's state is not a valid step result: upload a state
+ * before stepping again. */
 gdg_status gdg_step(gdg_ctx *ctx, double dt_cap, double dt_fixed, double *dt_taken);
 
 /* Steps until t = t_final (last step capped) or max_steps steps.  The time
  * loop runs on the device: captured HIP graphs of several steps, the host
  * synchronizing once per graph; a step whose stage 2 or 3 violates the CFL
  * condition is redone host-driven with the restart rule of gdg_step().  With
- * kernel timing on (gdg_profile) every step runs host-driven. */
+ * kernel timing on (gdg_profile) every step runs host-driven.  Errors as for
+ * gdg_step(); stats (may be NULL) receives the counters. */
 gdg_status gdg_run_to(gdg_ctx *ctx, double t_final, int64_t max_steps, gdg_stats *stats);
 
 /* One forward-Euler stage U <- Phi(U; tau) of the selected scheme (tau <= 0:
- * the CFL rule), keeping its intermediates for gdg_read_field(). */
+ * the CFL rule), keeping its intermediates for gdg_read_field().  Returns
+ * GDG_E_INADMISSIBLE or GDG_E_BOUNDARY as gdg_step() does. */
 gdg_status gdg_stage(gdg_ctx *ctx, double tau, double *tau_used);
 
 /* Copies a field of the last stage (gdg_field) to dst in dof order, one plane
