@@ -344,6 +344,8 @@ def main():
     ap.add_argument("--serving-tfinal", type=float, default=0.25)
     ap.add_argument("--serving-budget-gib", type=float, default=4.0)
     ap.add_argument("--serving-slots", type=int, default=64)
+    ap.add_argument("--serving-steps-per-graph", type=int, default=8,
+                    help="device-driven steps per server launch (host pump once per launch)")
     ap.add_argument("--cells", type=int, default=0,
                     help="run the workload on another number of cells per side (scaling study only)")
     ap.add_argument("--host-driven", action="store_true",
@@ -428,7 +430,7 @@ def main():
                          "vs_fp64_gpu": cmp}
     if not args.no_serving:
         line["serving"] = serving(args.serving_requests, args.serving_nmax, args.serving_tfinal,
-                                  args.serving_budget_gib, args.serving_slots, 8)
+                                  args.serving_budget_gib, args.serving_slots, args.serving_steps_per_graph)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     print(json.dumps(line), flush=True)
