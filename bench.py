@@ -357,7 +357,7 @@ def main():
     CELLS_OVERRIDE = args.cells
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs the hot path on a single MI355X; "
+        print("bench.py measures one GPU only: the library runs the hot path on a single MI355X; "
               "sharding across GPUs is a design note, not built", file=sys.stderr)
         sys.exit(2)
     _, desc, dsteps, dwarm = WORKLOADS[args.workload]

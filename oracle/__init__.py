@@ -10,7 +10,8 @@ Conventions (the same interface conventions as the library, written
 independently): dofs are numbered cell-major, cells lexicographic with x
 fastest, local nodes lexicographic with x fastest; states are SoA arrays of
 shape ``(dim + 2, ndofs)`` holding ``rho, m_1..m_d, E``; box face ``f = 2*axis
-+ side`` (side 0 = low); boundary kinds 0 periodic, 1 outflow, 2 slip.
++ side`` (side 0 = low); boundary kinds 0 periodic, 1 outflow, 2 slip,
+3 Dirichlet, 4 supersonic in/outflow (the last two with per-face data).
 """
 from __future__ import annotations
 
@@ -24,7 +25,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gdg_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-BC_PERIODIC, BC_OUTFLOW, BC_SLIP = 0, 1, 2
+BC_PERIODIC, BC_OUTFLOW, BC_SLIP, BC_DIRICHLET, BC_SUPERSONIC = 0, 1, 2, 3, 4
 LOW_ORDER, HIGH_ORDER, LIMITED = 0, 1, 2
 KIND_CELL, KIND_FACE_COLLOC, KIND_FACE = 0, 1, 2
 
