@@ -6,7 +6,8 @@ a component that is zero up to rounding is 1e-3 of the largest).
 
 Cases: the supersonic inflow problem in 1D, along y in 2D (Q2) and along x in
 3D; quadrant data with Dirichlet faces (each face its own data) in 1D, 2D and
-3D next to outflow, slip and periodic faces; an oblique supersonic stream with
+3D next to outflow, slip and periodic faces; the smallest meshes (two cells
+per axis, every row a boundary row) with Dirichlet faces; an oblique supersonic stream with
 a smooth perturbation and supersonic kinds on every face.  Also: equivalence
 with outflow bit for bit upstream of a supersonic stream (the data's node
 fields equal the node cache of the same state), the subsonic report
@@ -82,6 +83,9 @@ CASES = {
     "dirichlet_2d_q2_all": lambda: _with_data(*quadrant_on(2, 2, (7, 8), (3,) * 4, seed=9), faces=(0, 1, 2, 3)),
     "dirichlet_3d_q1_mixed": lambda: _with_data(*quadrant_on(3, 1, (5, 4, 4), (3, 1, 0, 0, 2, 3), seed=3),
                                                 faces=(0, 5)),
+    "two_cells_2d_dirichlet": lambda: _with_data(*smooth_on(2, 1, (2, 2), (3, 3, 3, 3)), faces=(0, 1, 2, 3)),
+    "two_cells_3d_q2_dirichlet": lambda: _with_data(*smooth_on(3, 2, (2, 2, 2), (3, 1, 2, 3, 3, 2)),
+                                                    faces=(0, 3, 4)),
     "supersonic_2d_oblique": lambda: _oblique(2, 1, (9, 8)),
     "supersonic_3d_q2_oblique": lambda: _oblique(3, 2, (3, 3, 2)),
 }
