@@ -221,13 +221,16 @@ void drop_graph(gdg_ctx *ctx) {
 }
 
 // One SSP-RK3 step on a stream: begin, three stages, end.
-int enqueue_step(gdg_ctx *ctx, hipStream_t st, int device_driven, double dt_cap, double tau_fixed, Prof *prof) {
+// first / last: whether this step opens / closes a sequence of device-driven
+// steps (inside a sequence, one launch ends a step and starts the next).
+int enqueue_step(gdg_ctx *ctx, hipStream_t st, int device_driven, double dt_cap, double tau_fixed, Prof *prof,
+                 bool first = true, bool last = true) {
   const KArgs &A = ctx->A;
   const int c0 = ctx->cur, c1 = (c0 + 1) % 3, c2 = (c0 + 2) % 3;
   StageBufs b1 = {ctx->U[c0], ctx->U[c1], ctx->U[c0], 0.0, 1.0};
   StageBufs b2 = {ctx->U[c1], ctx->U[c2], ctx->U[c0], 0.75, 0.25};
   StageBufs b3 = {ctx->U[c2], ctx->U[c0], ctx->U[c0], 1.0 / 3.0, 2.0 / 3.0};
-  int rc = launch_begin(A, dt_cap, tau_fixed, device_driven, st);
+  int rc = first ? launch_begin(A, dt_cap, tau_fixed, device_driven, st) : 0;
   // host-driven steps recompute the node cache of U^n: after a restart it
   // holds the state of an abandoned stage; device-driven steps follow a
   // completed step (or the upload, or a host-driven step) whose last stage
@@ -235,7 +238,7 @@ int enqueue_step(gdg_ctx *ctx, hipStream_t st, int device_driven, double dt_cap,
   rc |= launch_stage(A, b1, 0, st, prof, device_driven ? 0 : 1);
   rc |= launch_stage(A, b2, 1, st, prof, 0);
   rc |= launch_stage(A, b3, 2, st, prof, 0);
-  rc |= launch_end(A, st);
+  rc |= last ? launch_end(A, st) : launch_end_begin(A, st);
   return rc;
 }
 
@@ -250,7 +253,8 @@ gdg_status ensure_graph(gdg_ctx *ctx) {
   Prof *pp = nullptr;
   HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
   int rc = 0;
-  for (int k = 0; k < kGraphSteps; ++k) rc |= enqueue_step(ctx, ctx->cap_stream, 1, 0.0, 0.0, pp);
+  for (int k = 0; k < kGraphSteps; ++k)
+    rc |= enqueue_step(ctx, ctx->cap_stream, 1, 0.0, 0.0, pp, k == 0, k + 1 == kGraphSteps);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
   if (rc != 0 || e != hipSuccess) {

@@ -159,6 +159,8 @@ bool build_ref_tables(int dim, int deg, const double *h, RefTables *T, std::stri
 int launch_fill(const KArgs &A, void *stream);
 int launch_begin(const KArgs &A, double dt_cap, double tau_fixed, int device_driven, void *stream);
 int launch_end(const KArgs &A, void *stream);
+// the end of a device-driven step and the start of the next, in one launch
+int launch_end_begin(const KArgs &A, void *stream);
 int launch_set_run(const KArgs &A, double t_final, long long step_limit, void *stream);
 int launch_prim(const KArgs &A, const double *U, void *stream);
 // need_prim: launch the primitives sweep even when the last limiter pass of

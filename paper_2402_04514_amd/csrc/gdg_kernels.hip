@@ -425,6 +425,14 @@ __global__ void k_end(Ctl *ctl) {
   end_step(ctl);
 }
 
+// Between two device-driven steps of a graph: the end of one and the start of
+// the next in one launch.
+__global__ void k_end_begin(Ctl *ctl) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  end_step(ctl);
+  begin_step(ctl, 0.0, 0.0, 1);
+}
+
 // ---------------------------------------------------------------------------
 // Node-cache fields of a state V: velocity (D), p, a, p^-alpha, f(s), s~,
 // 1/p.  Returns whether V lies in A.
@@ -1156,6 +1164,14 @@ __global__ void kb_end(const BatchList *L) {
   if (r < L->nreq) end_step(L->e[r].A.ctl);
 }
 
+__global__ void kb_end_begin(const BatchList *L) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < L->nreq) {
+    end_step(L->e[r].A.ctl);
+    begin_step(L->e[r].A.ctl, 0.0, 0.0, 1);
+  }
+}
+
 __global__ void kb_status(const BatchList *L, Ctl *status) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < L->nreq) status[r] = *L->e[r].A.ctl;
@@ -1266,15 +1282,18 @@ template <int D, int DEG, bool MX>
 static int batch_impl(const BatchList *L, Ctl *status, int ksteps, int grid, void *stream) {
   clear_stale();
   const dim3 g((unsigned)grid), b(kBlockThreads), gr((kMaxBatch + 63) / 64), br(64);
+  hipLaunchKernelGGL(kb_begin, gr, br, 0, S(stream), L);
   for (int k = 0; k < ksteps; ++k) {
-    hipLaunchKernelGGL(kb_begin, gr, br, 0, S(stream), L);
     for (int stage = 0; stage < 3; ++stage) {
       hipLaunchKernelGGL(kb_prim<D>, g, b, 0, S(stream), L, stage);
       hipLaunchKernelGGL((kb_sweep1<D, DEG, MX>), g, b, 0, S(stream), L, stage);
       hipLaunchKernelGGL((kb_sweep2<D, DEG, MX>), g, b, 0, S(stream), L, stage);
       for (int pass = 0; pass < 2; ++pass) hipLaunchKernelGGL((kb_limit<D, DEG>), g, b, 0, S(stream), L, stage, pass);
     }
-    hipLaunchKernelGGL(kb_end, gr, br, 0, S(stream), L);
+    if (k + 1 < ksteps)
+      hipLaunchKernelGGL(kb_end_begin, gr, br, 0, S(stream), L);
+    else
+      hipLaunchKernelGGL(kb_end, gr, br, 0, S(stream), L);
   }
   hipLaunchKernelGGL(kb_status, gr, br, 0, S(stream), L, status);
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -1325,6 +1344,12 @@ int launch_set_run(const KArgs &A, double t_final, long long step_limit, void *s
 int launch_end(const KArgs &A, void *stream) {
   clear_stale();
   hipLaunchKernelGGL(k_end, dim3(1), dim3(64), 0, S(stream), A.ctl);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_end_begin(const KArgs &A, void *stream) {
+  clear_stale();
+  hipLaunchKernelGGL(k_end_begin, dim3(1), dim3(64), 0, S(stream), A.ctl);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
