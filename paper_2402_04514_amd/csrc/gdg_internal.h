@@ -116,7 +116,8 @@ struct KArgs {
   double *UL, *dUH, *U1;
   double *dL;       // d^L (and d^{d,L} on ghost slots) per slot
   double *l1;       // l of limiter pass 1 per slot (the ghost slot of a row holds l_i^d)
-  uint8_t *accepted;  // per row: limiter pass 1 accepted every flux of the row whole
+  uint8_t *accepted;  // per row: set by sweep 2 for rows of quiet cells (every flux zero), then by
+                      // limiter pass 1: it accepted every flux of the row whole
   Ctl *ctl;
 };
 

@@ -756,6 +756,7 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
   constexpr int NB = DEG + 1;
   constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
   __shared__ double rs[M][kBlockThreads];
+  __shared__ int qs[kBlockThreads];
   double tau;
   if (!stage_tau(A, stage, &tau)) {
     if (stage > 0 && blk == 0 && threadIdx.x == 0 && A.ctl->cfl_flag == 0 && A.ctl->halt == 0) {
@@ -785,6 +786,10 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
     double accL[M], accH[M];
     for (int c = 0; c < M; ++c) accL[c] = accH[c] = 0.0;
     double rmin = INFINITY, rmax = -INFINITY, smin = INFINITY;
+    // dev = sum of |U_j - U_i| over the neighbours and boundary states: zero
+    // exactly when all of them equal U_i bit for bit (the row is quiet); a
+    // NaN keeps it nonzero
+    double dev = 0.0;
     // the next slot's kind and column are loaded one slot ahead, so that the
     // dependent gather of the neighbour does not wait for them
     const int64_t s0 = blk * A.W * A.R + lane;
@@ -821,6 +826,7 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
         for (int q = 0; q < M; ++q) {
           double df = fj[q] - fi[q];
           double du = gh.U[q] - ni.U[q];
+          dev += fabs(du);
           accL[q] -= d * du;
           accH[q] -= dH * du;
           bar[q] = 0.5 * (gh.U[q] + ni.U[q]) - df / (2.0 * d);  // eq. BoundaryBarState
@@ -838,10 +844,12 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
       const double dH = visc_high(A, d, Ni, A.Nev[j], kind, hpk);
       for (int q = 0; q < M; ++q) {
         const double du = U[q * N + j] - ni.U[q];
+        dev += fabs(du);
         accL[q] -= d * du;
         accH[q] -= dH * du;
       }
     }
+    qs[lane] = dev == 0.0 ? 1 : 0;
     for (int q = 0; q < M; ++q) {
       const double f = A.fsum[q * N + i];
       accL[q] += f;
@@ -869,6 +877,15 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
   if (!active) return;
   // eq. HighScheme: M_K dU^H_K = tau r^H_K for the cell of row i, from LDS
   const int cellbase = lane - a;
+  // A cell whose rows are all quiet has a zero residual and dU^H = 0 in every
+  // row, so every antidiffusive flux of its rows (eq. HighLowOrderIdentity)
+  // is exactly zero: the limiter's first pass accepts the row as it stands
+  // without visiting its pairs.
+  {
+    int cq = 1;
+    for (int b = 0; b < NLOC; ++b) cq &= qs[cellbase + b];
+    A.accepted[i] = (uint8_t)cq;
+  }
   double V[M];
   for (int q = 0; q < M; ++q) {
     double s = 0.0;
@@ -995,10 +1012,14 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
   for (int q = 0; q < M; ++q) acc[q] = Ab[q] = 0.0;
   int64_t gslot = -1;
   bool allone = true;  // every l of the row is 1
+  // pass 0 of a row that sweep 2 found quiet (all its fluxes are exactly
+  // zero): no pair to visit; its l are never read, since pass 1 returns U^(1)
+  // for an accepted row
+  const bool quiet = pass == 0 && A.accepted[i];
   const int64_t s0 = blk * A.W * A.R + lane;
   uint8_t meta_n = A.meta[s0];
   int32_t col_n = A.col[s0];
-  for (int t = 0; t < A.W; ++t) {
+  for (int t = 0; t < (quiet ? 0 : A.W); ++t) {
     const int64_t s = s0 + (int64_t)t * A.R;
     const uint8_t meta = meta_n;
     const int32_t colv = col_n;
