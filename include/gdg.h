@@ -120,11 +120,31 @@ typedef struct {
   int32_t reserved;
 } gdg_params;
 
+/* Counters and measures of a run (Sec. 3 and 5: the properties the scheme
+ * guarantees, so that a caller can check them without downloading the state).
+ * The state measures are reduced on the device in a fixed order (the same
+ * state gives the same bits); the counters are integer totals since the last
+ * gdg_upload_state(), and include the stages of steps that a CFL violation
+ * restarted. */
 typedef struct {
   double t;          /* simulated time */
   int64_t steps;     /* SSP-RK3 steps taken */
   int64_t restarts;  /* steps restarted after a CFL violation in stage 2 or 3 */
   double last_dt;    /* tau of the last step */
+  double min_rho;    /* min_i rho_i of the current state (eq. AddSet: > 0) */
+  double min_eps;    /* min_i eps_i = E_i - |m_i|^2 / (2 rho_i) (eq. AddSet: > 0) */
+  double total[5];   /* sum_i m_i U_i per component (rho, momentum, E; dim + 2
+                        entries): conserved on periodic meshes (Sec. 3.2,
+                        Lemma TotBalLemma),
+                        mass and energy also in slip boxes */
+  int64_t bound_violations; /* limiter-pass outputs outside their relaxed bounds
+                               of eq. local_bounds (beyond 1e-12 relative on rho,
+                               1e-11 on the rescaled entropy); 0 by Lemma
+                               ConsInvariants */
+  int64_t limited_pairs;    /* pairs (i, j) that limiter pass 1 cut, l_ij < 1,
+                               summed over stages */
+  int64_t quiet_rows;       /* rows of cells whose whole stencil held one state
+                               (every flux exactly zero), summed over stages */
 } gdg_stats;
 
 /* Intermediate fields of the last forward-Euler stage, for inspection. */
@@ -198,8 +218,9 @@ gdg_status gdg_stage(gdg_ctx *ctx, double tau, double *tau_used);
  * of N doubles after the other. */
 gdg_status gdg_read_field(gdg_ctx *ctx, int32_t field, double *dst, int32_t is_device_ptr);
 
-/* Simulated time, step and restart counters. */
-gdg_status gdg_get_stats(const gdg_ctx *ctx, gdg_stats *stats);
+/* Time, counters and the measures of the current state (gdg_stats).  Enqueues
+ * the state reduction on the context's stream and synchronizes it. */
+gdg_status gdg_get_stats(gdg_ctx *ctx, gdg_stats *stats);
 
 /* Kernel timing.  gdg_profile(ctx, 1) starts bracketing every sweep launch
  * with HIP events on the context's stream (and clears the sums); 0 stops.

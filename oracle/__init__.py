@@ -70,6 +70,10 @@ def lib():
         L.or_destroy.argtypes = [C.c_void_p]
         L.or_num_threads.restype = C.c_int
         L.or_num_threads.argtypes = []
+        L.or_default_cev.restype = C.c_double
+        L.or_default_cev.argtypes = [C.c_int]
+        L.or_set_num_threads.restype = None
+        L.or_set_num_threads.argtypes = [C.c_int]
         for fn in ("or_num_dofs", "or_nnz", "or_nbnd"):
             getattr(L, fn).restype = C.c_long
             getattr(L, fn).argtypes = [C.c_void_p]
@@ -111,7 +115,7 @@ def params(gamma=1.4, cfl=0.5, degree=1, c_ev=None, c_k=1.0, c_r=4.0, p_r=1.5, p
            scheme=LIMITED) -> _Params:
     """Scheme constants of Sec. 5 (c_ev = 1, 0.5, 0.25 for k = 1, 2, 3)."""
     if c_ev is None:
-        c_ev = {1: 1.0, 2: 0.5, 3: 0.25}[degree]
+        c_ev = lib().or_default_cev(degree)
     return _Params(gamma, cfl, c_ev, c_k, c_r, p_r, passes, scheme)
 
 
@@ -246,9 +250,27 @@ class Mesh:
         return U, t, n
 
 
+_THREADS0 = None
+
+
 def num_threads() -> int:
     """Threads the oracle's row loops run on."""
     return lib().or_num_threads()
+
+
+def num_threads_available() -> int:
+    """Threads the row loops ran on before any set_num_threads() call (the
+    OpenMP default of this process: OMP_NUM_THREADS, else the cores)."""
+    global _THREADS0
+    if _THREADS0 is None:
+        _THREADS0 = lib().or_num_threads()
+    return _THREADS0
+
+
+def set_num_threads(n: int):
+    """Threads of the row loops (results do not depend on it)."""
+    num_threads_available()
+    lib().or_set_num_threads(int(n))
 
 
 # -- physics helpers -------------------------------------------------------

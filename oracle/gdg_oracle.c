@@ -377,6 +377,22 @@ or_setup *or_create(int dim, int deg, const long *cells, const double *lo, const
 /* threads the row loops use (OpenMP) */
 int or_num_threads(void) { return omp_get_max_threads(); }
 
+/* The entropy-viscosity constant c_ev of Sec. 5.2 for degree k (the paper's
+ * choice: 1, 0.5, 0.25 for k = 1, 2, 3); 0 for a degree it gives none. */
+double or_default_cev(int degree) {
+  switch (degree) {
+    case 1: return 1.0;
+    case 2: return 0.5;
+    case 3: return 0.25;
+    default: return 0.0;
+  }
+}
+
+/* sets the threads of the row loops (timing on one core and on all) */
+void or_set_num_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+}
+
 long or_num_dofs(const or_setup *S) { return S->ndofs; }
 long or_nnz(const or_setup *S) { return S->rowptr[S->ndofs]; }
 long or_nbnd(const or_setup *S) { return S->bptr[S->ndofs]; }

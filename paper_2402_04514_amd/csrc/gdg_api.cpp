@@ -48,7 +48,7 @@ struct Layout {
   int nloc, nb1, R, cpb, W, M;
   int64_t N, ncells, nblocks, nslots;
   size_t off_ref, off_ctl, off_col, off_c, off_meta, off_kscale, off_U[3], off_Wc, off_N, off_q,
-      off_B, off_UL, off_dUH, off_U1, off_dL, off_l1, off_acc, off_fsum, total;
+      off_B, off_UL, off_dUH, off_U1, off_dL, off_l1, off_acc, off_fsum, off_red, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -150,6 +150,7 @@ Layout layout(const gdg_mesh_desc *m, const gdg_params *p) {
   L.off_l1 = take(S * 8);
   L.off_acc = take(N);
   L.off_fsum = take(M * N * 8);
+  L.off_red = take((size_t)(kRedBlocks + 1) * kRedFields * 8);
   L.total = o;
   return L;
 }
@@ -407,6 +408,7 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   A.l1 = (double *)(ws + L.off_l1);
   A.accepted = (uint8_t *)(ws + L.off_acc);
   A.fsum = (double *)(ws + L.off_fsum);
+  A.red = (double *)(ws + L.off_red);
 
   RefTables *T = new RefTables();
   if (!build_ref_tables(mesh->dim, mesh->degree, h, T, &err)) {
@@ -557,10 +559,15 @@ gdg_status gdg_step(gdg_ctx *ctx, double dt_cap, double dt_fixed, double *dt_tak
   return step_impl(ctx, dt_cap, dt_fixed, dt_taken, 0);
 }
 
-// Device-driven time loop: captured graphs of several steps, one host
-// synchronization per graph.  A CFL violation halts the rest of that graph;
+}  // extern "C"
+
+namespace gdg {
+
+// Device-driven time loop: kGraphSteps steps per round (a captured graph, or
+// with use_graph = false the same launches enqueued directly), one host
+// synchronization per round.  A CFL violation halts the rest of that round;
 // the step is then redone on the host-driven path with its restart rule.
-gdg_status gdg_run_to(gdg_ctx *ctx, double t_final, int64_t max_steps, gdg_stats *stats) {
+gdg_status run_loop(gdg_ctx *ctx, double t_final, int64_t max_steps, gdg_stats *stats, bool use_graph) {
   if (!ctx) return GDG_E_INVALID;
   if (max_steps <= 0 || !(ctx->t < t_final)) return gdg_get_stats(ctx, stats);
   const int64_t limit = ctx->steps + (max_steps > (int64_t(1) << 60) ? (int64_t(1) << 60) : max_steps);
@@ -573,10 +580,18 @@ gdg_status gdg_run_to(gdg_ctx *ctx, double t_final, int64_t max_steps, gdg_stats
     }
     return gdg_get_stats(ctx, stats);
   }
-  if (gdg_status s = ensure_graph(ctx)) return s;
+  if (use_graph)
+    if (gdg_status s = ensure_graph(ctx)) return s;
   if (gdg_status s = launched(ctx, launch_set_run(ctx->A, t_final, limit, ctx->stream), "set run")) return s;
   for (;;) {
-    HIPCHK(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
+    if (use_graph) {
+      HIPCHK(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
+    } else {
+      int rc = 0;
+      for (int k = 0; k < kGraphSteps; ++k)
+        rc |= enqueue_step(ctx, ctx->stream, 1, 0.0, 0.0, nullptr, k == 0, k + 1 == kGraphSteps);
+      if (gdg_status s = launched(ctx, rc, "device-driven steps")) return s;
+    }
     if (gdg_status s = read_ctl(ctx)) return s;
     const Ctl h = ctx->hctl;
     if (h.bad_flag) return gdg::flag_status(ctx, h.bad_flag, "a stage output left the admissible set");
@@ -595,6 +610,14 @@ gdg_status gdg_run_to(gdg_ctx *ctx, double t_final, int64_t max_steps, gdg_stats
     if (h.halt || ctx->steps >= limit || !(ctx->t < t_final)) break;
   }
   return gdg_get_stats(ctx, stats);
+}
+
+}  // namespace gdg
+
+extern "C" {
+
+gdg_status gdg_run_to(gdg_ctx *ctx, double t_final, int64_t max_steps, gdg_stats *stats) {
+  return gdg::run_loop(ctx, t_final, max_steps, stats, true);
 }
 
 }  // extern "C"
@@ -631,6 +654,14 @@ gdg_status ctx_restart(gdg_ctx *ctx, const Ctl &c, double t_final) {
 }
 
 const char *ctx_error(const gdg_ctx *ctx) { return ctx->err.c_str(); }
+
+void set_create_error(const std::string &msg) { g_create_err = msg; }
+
+void ctx_counts(const gdg_ctx *ctx, double *t, int64_t *steps, int64_t *restarts) {
+  *t = ctx->t;
+  *steps = ctx->steps;
+  *restarts = ctx->restarts;
+}
 
 gdg_status flag_status(gdg_ctx *ctx, int flag, const char *what) {
   if (flag & 2) {
@@ -681,14 +712,26 @@ gdg_status gdg_read_field(gdg_ctx *ctx, int32_t field, double *dst, int32_t is_d
   return GDG_OK;
 }
 
-gdg_status gdg_get_stats(const gdg_ctx *ctx, gdg_stats *stats) {
+gdg_status gdg_get_stats(gdg_ctx *ctx, gdg_stats *stats) {
   if (!ctx) return GDG_E_INVALID;
-  if (stats) {
-    stats->t = ctx->t;
-    stats->steps = ctx->steps;
-    stats->restarts = ctx->restarts;
-    stats->last_dt = ctx->last_dt;
-  }
+  if (!stats) return GDG_OK;
+  std::memset(stats, 0, sizeof *stats);
+  stats->t = ctx->t;
+  stats->steps = ctx->steps;
+  stats->restarts = ctx->restarts;
+  stats->last_dt = ctx->last_dt;
+  double r[kRedFields];
+  if (gdg_status s = launched(ctx, launch_state_stats(ctx->A, ctx->U[ctx->cur], ctx->stream), "state statistics"))
+    return s;
+  HIPCHK(ctx, hipMemcpyAsync(r, ctx->A.red + (size_t)kRedBlocks * kRedFields, sizeof r, hipMemcpyDeviceToHost,
+                             ctx->stream));
+  if (gdg_status s = read_ctl(ctx)) return s;  // also waits for the copy above
+  stats->min_rho = r[0];
+  stats->min_eps = r[1];
+  for (int c = 0; c < ctx->M; ++c) stats->total[c] = r[2 + c];
+  stats->bound_violations = (int64_t)ctx->hctl.bound_violations;
+  stats->limited_pairs = (int64_t)ctx->hctl.limited_pairs;
+  stats->quiet_rows = (int64_t)ctx->hctl.quiet_rows;
   return GDG_OK;
 }
 

@@ -56,7 +56,19 @@ struct Ctl {
   int bad_flag;                      // a state left A; read by the host only
   int viol_stage;
   int halt;                          // set by the step's first kernel: skip this step
+  // Counters since the last upload (integer atomics, so their values do not
+  // depend on the order of the blocks): stage outputs of the limited scheme
+  // outside their relaxed bounds (eq. local_bounds), pairs that limiter pass 1
+  // cut (l_ij < 1), rows of quiet cells (every flux of the row exactly zero).
+  unsigned long long bound_violations;
+  unsigned long long limited_pairs;
+  unsigned long long quiet_rows;
 };
+// Reduction of a state for the statistics call: per block partials, then one
+// block combines them in a fixed order.  min rho, min eps, sum_i m_i U_i.
+constexpr int kRedBlocks = 512;
+constexpr int kRedThreads = 256;
+constexpr int kRedFields = 2 + kMaxD + 2;
 // Reference tables of one cell class (every cell of a uniform mesh).
 struct RefTables {
   double mlump[kMaxNloc];                   // m_a
@@ -118,6 +130,7 @@ struct KArgs {
   double *l1;       // l of limiter pass 1 per slot (the ghost slot of a row holds l_i^d)
   uint8_t *accepted;  // per row: set by sweep 2 for rows of quiet cells (every flux zero), then by
                       // limiter pass 1: it accepted every flux of the row whole
+  double *red;        // kRedBlocks * kRedFields partials of the state reduction, then kRedFields results
   Ctl *ctl;
 };
 
@@ -164,6 +177,9 @@ int launch_end(const KArgs &A, void *stream);
 int launch_end_begin(const KArgs &A, void *stream);
 int launch_set_run(const KArgs &A, double t_final, long long step_limit, void *stream);
 int launch_prim(const KArgs &A, const double *U, void *stream);
+// min rho, min eps and sum_i m_i U_i (per component) of the state U into
+// A.red[kRedBlocks * kRedFields ...], deterministically
+int launch_state_stats(const KArgs &A, const double *U, void *stream);
 // need_prim: launch the primitives sweep even when the last limiter pass of
 // the previous stage wrote the node cache (the stage input was not produced by
 // a completed stage of this context)
@@ -185,6 +201,13 @@ void ctx_sync(gdg_ctx *ctx, const Ctl &c);
 // rule of gdg_step), then re-arms the device-driven loop.
 gdg_status ctx_restart(gdg_ctx *ctx, const Ctl &c, double t_final);
 const char *ctx_error(const gdg_ctx *ctx);
+// The device-driven time loop of gdg_run_to(); use_graph = false enqueues
+// the same launches directly instead of replaying a captured graph.
+gdg_status run_loop(gdg_ctx *ctx, double t_final, int64_t max_steps, gdg_stats *stats, bool use_graph);
+// Sets the text that gdg_last_error(NULL) returns on the calling thread.
+void set_create_error(const std::string &msg);
+// Time and step counters as the host last took them (no device work).
+void ctx_counts(const gdg_ctx *ctx, double *t, int64_t *steps, int64_t *restarts);
 // Status of a control block's bad_flag: GDG_E_BOUNDARY for bit 2 (subsonic
 // flow at a supersonic face), else GDG_E_INADMISSIBLE with the text `what`;
 // sets the context's error text.

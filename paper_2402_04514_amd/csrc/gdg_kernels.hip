@@ -568,6 +568,16 @@ __device__ __forceinline__ double block_min_atomic(double v, unsigned long long 
   return v;
 }
 
+// Adds the counts v (0 .. 127) of the wave's active lanes to *dst: the sum is
+// assembled bit by bit from ballots, and the first active lane issues one
+// atomic (none if the sum is zero).
+__device__ __forceinline__ void wave_count_add(unsigned long long *dst, unsigned v) {
+  const unsigned long long act = __ballot(1);
+  unsigned long long tot = 0;
+  for (int b = 0; b < 7; ++b) tot += (unsigned long long)__popcll(__ballot((v >> b) & 1u)) << b;
+  if (tot != 0 && (int)__lane_id() == __ffsll((long long)act) - 1) atomicAdd(dst, tot);
+}
+
 // ---------------------------------------------------------------------------
 template <int D, int DEG, bool MX, bool BD = true>
 __device__ __forceinline__ void sweep1_body(const KArgs &A, const double *__restrict__ U, int stage,
@@ -727,11 +737,12 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(G
   sweep1_body<D, DEG, MX, BD>(A, U, stage, xcd_block(A, blockIdx.x));
 }
 
-// high-order viscosity of eq. HighOrderViscosity / ViscMin for a graph pair
+// high-order viscosity of eq. HighOrderViscosity / ViscMin for a graph pair;
+// hpk = c_k hhat_i^{p_k} of row i (the constant c_k is already in it)
 __device__ __forceinline__ double visc_high(const KArgs &A, double d, double Ni, double Nj, int kind,
                                            double hpk) {
   double dev = d * fmin(A.c_ev * fmax(fabs(Ni), fabs(Nj)), 1.0);
-  double dmin = kind == SK_FACE_COLLOC ? A.c_k * hpk * d : 0.0;
+  double dmin = kind == SK_FACE_COLLOC ? hpk * d : 0.0;
   return fmax(dmin, dev);
 }
 
@@ -885,6 +896,7 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
     int cq = 1;
     for (int b = 0; b < NLOC; ++b) cq &= qs[cellbase + b];
     A.accepted[i] = (uint8_t)cq;
+    wave_count_add(&A.ctl->quiet_rows, (unsigned)cq);
   }
   double V[M];
   for (int q = 0; q < M; ++q) {
@@ -1012,6 +1024,7 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
   for (int q = 0; q < M; ++q) acc[q] = Ab[q] = 0.0;
   int64_t gslot = -1;
   bool allone = true;  // every l of the row is 1
+  unsigned ncut = 0;   // pairs of the row with l < 1
   // pass 0 of a row that sweep 2 found quiet (all its fluxes are exactly
   // zero): no pair to visit; its l are never read, since pass 1 returns U^(1)
   // for an accepted row
@@ -1072,6 +1085,7 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
     for (int q = 0; q < M; ++q) acc[q] += l * Aij[q];
     if (pass == 0) A.l1[s] = l;
     allone = allone && l == 1.0;
+    ncut += l < 1.0 ? 1u : 0u;
   }
   bool bzero = true;
   for (int q = 0; q < M; ++q) bzero = bzero && Ab[q] == 0.0;
@@ -1091,6 +1105,24 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
   if (pass == 0) {
     for (int q = 0; q < M; ++q) A.U1[q * N + i] = V[q];
     A.accepted[i] = allone ? 1 : 0;
+    wave_count_add(&A.ctl->limited_pairs, ncut);
+  }
+  // Lemma ConsInvariants: the pass's output lies in B_i.  Counted with the
+  // tolerances of rounding (1e-12 relative on rho, 1e-11 on s~), so that a
+  // nonzero count means a defect, not the last bits of the line search.  Rows
+  // that the last pass returns as U^(1) were counted in pass 0.
+  {
+    bool in = V[0] >= rmin * (1.0 - 1e-12) && V[0] <= rmax * (1.0 + 1e-12);
+    double m2 = 0.0;
+    for (int e = 0; e < D; ++e) m2 += V[1 + e] * V[1 + e];
+    const double re = V[0] * V[M - 1] - 0.5 * m2;  // rho eps
+    if (A.g75) {
+      const double r3 = V[0] * V[0] * V[0], r6 = r3 * r3;
+      in = in && re > 0.0 && pow5(re) >= smin5 * (1.0 - 5e-11) * (r6 * r6);
+    } else {
+      in = in && re > 0.0 && re / V[0] * pow(V[0], -A.gamma) >= smin * (1.0 - 1e-11);
+    }
+    wave_count_add(&A.ctl->bound_violations, in ? 0u : 1u);
   }
   if (final_pass) {
     // the stage output, and its node cache for the next stage: no kernel of
@@ -1196,6 +1228,60 @@ __global__ void kb_end_begin(const BatchList *L) {
 __global__ void kb_status(const BatchList *L, Ctl *status) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < L->nreq) status[r] = *L->e[r].A.ctl;
+}
+
+// ---------------------------------------------------------------------------
+// Statistics of a state: min rho, min eps = min (E - |m|^2 / (2 rho)), and the
+// conserved totals sum_i m_i U_i (Sec. 3, the quantities the scheme keeps),
+// as kRedBlocks per-block partials (grid-stride rows, a fixed tree in LDS)
+// combined by one block in a fixed order: the same state gives the same bits.
+template <int D>
+__global__ __launch_bounds__(kRedThreads) void k_state_stats1(KArgs A, const double *__restrict__ U) {
+  constexpr int M = D + 2, F = 2 + M;
+  __shared__ double sh[F][kRedThreads];
+  double v[F];
+  v[0] = INFINITY;
+  v[1] = INFINITY;
+  for (int c = 0; c < M; ++c) v[2 + c] = 0.0;
+  const int64_t N = A.N;
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < N; i += (int64_t)kRedBlocks * kRedThreads) {
+    double V[M];
+    for (int c = 0; c < M; ++c) V[c] = U[c * N + i];
+    v[0] = fmin(v[0], V[0]);
+    v[1] = fmin(v[1], eps_of<D>(V));
+    const double mi = A.ref->mlump[i % A.nloc];
+    for (int c = 0; c < M; ++c) v[2 + c] += mi * V[c];
+  }
+  for (int f = 0; f < F; ++f) sh[f][threadIdx.x] = v[f];
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sh[0][threadIdx.x] = fmin(sh[0][threadIdx.x], sh[0][threadIdx.x + w]);
+      sh[1][threadIdx.x] = fmin(sh[1][threadIdx.x], sh[1][threadIdx.x + w]);
+      for (int f = 2; f < F; ++f) sh[f][threadIdx.x] += sh[f][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int f = 0; f < F; ++f) A.red[blockIdx.x * kRedFields + f] = sh[f][0];
+}
+
+template <int D>
+__global__ __launch_bounds__(kRedBlocks) void k_state_stats2(KArgs A) {
+  constexpr int M = D + 2, F = 2 + M;
+  __shared__ double sh[F][kRedBlocks];
+  for (int f = 0; f < F; ++f) sh[f][threadIdx.x] = A.red[threadIdx.x * kRedFields + f];
+  __syncthreads();
+  for (int w = kRedBlocks / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sh[0][threadIdx.x] = fmin(sh[0][threadIdx.x], sh[0][threadIdx.x + w]);
+      sh[1][threadIdx.x] = fmin(sh[1][threadIdx.x], sh[1][threadIdx.x + w]);
+      for (int f = 2; f < F; ++f) sh[f][threadIdx.x] += sh[f][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int f = 0; f < F; ++f) A.red[kRedBlocks * kRedFields + f] = sh[f][0];
 }
 
 // ---------------------------------------------------------------------------
@@ -1371,6 +1457,24 @@ int launch_end(const KArgs &A, void *stream) {
 int launch_end_begin(const KArgs &A, void *stream) {
   clear_stale();
   hipLaunchKernelGGL(k_end_begin, dim3(1), dim3(64), 0, S(stream), A.ctl);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int D>
+static int stats_impl(const KArgs &A, const double *U, void *stream) {
+  hipLaunchKernelGGL(k_state_stats1<D>, dim3(kRedBlocks), dim3(kRedThreads), 0, S(stream), A, U);
+  hipLaunchKernelGGL(k_state_stats2<D>, dim3(1), dim3(kRedBlocks), 0, S(stream), A);
+  return 0;
+}
+
+int launch_state_stats(const KArgs &A, const double *U, void *stream) {
+  clear_stale();
+  switch (A.dim) {
+    case 1: stats_impl<1>(A, U, stream); break;
+    case 2: stats_impl<2>(A, U, stream); break;
+    case 3: stats_impl<3>(A, U, stream); break;
+    default: return -2;
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

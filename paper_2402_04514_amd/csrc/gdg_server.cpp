@@ -156,13 +156,7 @@ void fail_req(gdg_server *s, Req *q, gdg_status st, const std::string &why) {
   std::vector<double>().swap(q->U);
 }
 
-void take_stats(Req *q) {
-  gdg_stats st{};
-  gdg_get_stats(q->ctx, &st);
-  q->t = st.t;
-  q->steps = st.steps;
-  q->restarts = st.restarts;
-}
+void take_stats(Req *q) { ctx_counts(q->ctx, &q->t, &q->steps, &q->restarts); }
 
 // Copies the final state to the request's host buffer and frees its range.
 gdg_status finish_req(gdg_server *s, Req *q) {

@@ -50,7 +50,9 @@ class gdg_params(C.Structure):
 
 class gdg_stats(C.Structure):
     _fields_ = [("t", C.c_double), ("steps", C.c_int64), ("restarts", C.c_int64),
-                ("last_dt", C.c_double)]
+                ("last_dt", C.c_double), ("min_rho", C.c_double), ("min_eps", C.c_double),
+                ("total", C.c_double * 5), ("bound_violations", C.c_int64),
+                ("limited_pairs", C.c_int64), ("quiet_rows", C.c_int64)]
 
 
 class gdg_server_desc(C.Structure):

@@ -178,14 +178,21 @@ def test_scheme_modes(oracle, name, scheme):
     _close(S.download(), Uo, what="U^{n+1}")
 
 
-@pytest.mark.parametrize("name", ["q1_3d_slip", "q1_3d_mixed", "q1_2d_mixed"])
-def test_high_order_without_entropy_viscosity(oracle, name):
+@pytest.mark.parametrize("c_k", [1.0, 0.5])
+@pytest.mark.parametrize("name", ["q1_3d_slip", "q1_3d_mixed", "q1_2d_mixed", "q2_2d_outflow", "q2_2d_slip",
+                                  "q2_3d_tiled"])
+def test_high_order_without_entropy_viscosity(oracle, name, c_k):
     """c_ev = 0 makes d^H = d^min, independent of N_i: isolates the
-    consistent-mass solve and the minimal viscosity."""
+    consistent-mass solve and the minimal viscosity of eq. ViscMin.  On Q2
+    (p_k = 1/2) d^min = c_k hhat^{1/2} d^L differs from d^L on collocated
+    pairs and boundary parts, so c_k enters; c_k = 0.5 checks that it enters
+    once, as the equation has it."""
+    _say("c_ev = 0, c_k = %g, %s" % (c_k, name))
     ms, _, _, _, _ = _pair(oracle, name)
     p = gdg.gdg_default_params(ms.degree)
     p.scheme = gdg.GDG_HIGH_ORDER
     p.c_ev = 0.0
+    p.c_k = c_k
     ms, U, M, S, op = _pair(oracle, name, p)
     out, dg = M.stage(op, U, diag=True)
     if dg["status"] == -2:

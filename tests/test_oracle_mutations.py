@@ -16,6 +16,7 @@ T = "tests/"
 SETUP, PHYS, SCHEME = T + "test_oracle_setup.py", T + "test_oracle_physics.py", T + "test_oracle_scheme.py"
 
 BND = T + "test_oracle_boundary.py"
+VISC = T + "test_oracle_viscosity.py"
 
 MUTANTS = {
     # name: (original text, planted text, pin files that must fail)
@@ -72,6 +73,18 @@ MUTANTS = {
                                 [SCHEME + "::test_vortex_convergence"]),
     "gradient_operand_transposed": ("g = dphi(S, p.b, p.dir, xi) * phi(S, p.a, xi);",
                                     "g = dphi(S, p.a, p.dir, xi) * phi(S, p.b, xi);", [SETUP]),
+    "min_viscosity_even_power_zero": ("const double pk = (S->deg % 2 == 0) ? 0.5 : 0.0;",
+                                      "const double pk = (S->deg % 2 == 0) ? 0.0 : 0.0;",
+                                      [VISC + "::test_face_pair_viscosity_is_the_papers",
+                                       VISC + "::test_boundary_viscosity_even_degree"]),
+    "min_viscosity_even_power_one": ("const double pk = (S->deg % 2 == 0) ? 0.5 : 0.0;",
+                                     "const double pk = (S->deg % 2 == 0) ? 1.0 : 0.0;",
+                                     [VISC + "::test_face_pair_viscosity_is_the_papers",
+                                      VISC + "::test_boundary_viscosity_even_degree"]),
+    "entropy_viscosity_q2_constant": ("case 2: return 0.5;", "case 2: return 1.0;",
+                                      [VISC + "::test_face_pair_viscosity_is_the_papers"]),
+    "boundary_min_viscosity_dropped": ("double dmin = P->c_k * pow(hh, pk) * dbd[b];", "double dmin = 0.0 * dbd[b];",
+                                       [VISC + "::test_boundary_viscosity_even_degree"]),
     "ev_normalizer_not_abs_sum": ("D += fabs(grad[q]) * fabs(Sk[q]);", "D += fabs(grad[q] * Sk[q]) * 0.5;",
                                   [SCHEME + "::test_vortex_convergence"]),
 }
