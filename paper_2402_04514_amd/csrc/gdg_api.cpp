@@ -47,8 +47,8 @@ thread_local std::string g_create_err;
 struct Layout {
   int nloc, nb1, R, cpb, W, M;
   int64_t N, ncells, nblocks, nslots;
-  size_t off_ref, off_ctl, off_col, off_c, off_meta, off_kscale, off_U[3], off_Wc, off_N, off_q,
-      off_B, off_UL, off_dUH, off_U1, off_dL, off_l1, off_acc, off_fsum, off_red, total;
+  size_t off_ref, off_ctl, off_col, off_c, off_meta, off_kscale, off_U[3], off_Nd, off_Qd, off_Ld, off_U1d,
+      off_dL, off_l1, off_acc, off_fsum, off_red, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -139,13 +139,10 @@ Layout layout(const gdg_mesh_desc *m, const gdg_params *p) {
   L.off_meta = take(S);
   L.off_kscale = take(N * 8);
   for (int k = 0; k < 3; ++k) L.off_U[k] = take(M * N * 8);
-  L.off_Wc = take((d + 6) * N * 8);
-  L.off_N = take(N * 8);
-  L.off_q = take(3 * N * 8);
-  L.off_B = take(3 * N * 8);
-  L.off_UL = take(M * N * 8);
-  L.off_dUH = take(M * N * 8);
-  L.off_U1 = take(M * N * 8);
+  L.off_Nd = take(2 * N * kNodeStride * 8);
+  L.off_Qd = take(N * kQStride * 8);
+  L.off_Ld = take(N * kLimStride * 8);
+  L.off_U1d = take(N * kU1Stride * 8);
   L.off_dL = take(S * 8);
   L.off_l1 = take(S * 8);
   L.off_acc = take(N);
@@ -397,13 +394,10 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   A.kscale = (double *)(ws + L.off_kscale);
   for (int k = 0; k < 3; ++k) ctx->U[k] = (double *)(ws + L.off_U[k]);
   ctx->cur = 0;
-  A.Wc = (double *)(ws + L.off_Wc);
-  A.Nev = (double *)(ws + L.off_N);
-  A.q = (double *)(ws + L.off_q);
-  A.B = (double *)(ws + L.off_B);
-  A.UL = (double *)(ws + L.off_UL);
-  A.dUH = (double *)(ws + L.off_dUH);
-  A.U1 = (double *)(ws + L.off_U1);
+  A.Nd = (double *)(ws + L.off_Nd);
+  A.Qd = (double *)(ws + L.off_Qd);
+  A.Ld = (double *)(ws + L.off_Ld);
+  A.U1d = (double *)(ws + L.off_U1d);
   A.dL = (double *)(ws + L.off_dL);
   A.l1 = (double *)(ws + L.off_l1);
   A.accepted = (uint8_t *)(ws + L.off_acc);
@@ -498,7 +492,7 @@ gdg_status gdg_upload_state(gdg_ctx *ctx, const double *U, int32_t is_device_ptr
   std::memset(&ctx->hctl, 0, sizeof(Ctl));
   HIPCHK(ctx, hipMemcpyAsync(ctx->A.ctl, &ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
   if (gdg_status s = launched(ctx, launch_begin(ctx->A, 0.0, 0.0, 0, ctx->stream), "begin")) return s;
-  if (gdg_status s = launched(ctx, launch_prim(ctx->A, ctx->U[ctx->cur], ctx->stream), "prim")) return s;
+  if (gdg_status s = launched(ctx, launch_prim(ctx->A, ctx->U[ctx->cur], 0, ctx->stream), "prim")) return s;
   if (gdg_status s = read_ctl(ctx)) return s;
   ctx->t = 0.0;
   ctx->steps = ctx->restarts = 0;
@@ -688,6 +682,9 @@ gdg_status gdg_stage(gdg_ctx *ctx, double tau, double *tau_used) {
   if (ctx->hctl.bad_flag) return gdg::flag_status(ctx, ctx->hctl.bad_flag, "the stage output left the admissible set");
   ctx->cur = c1;
   drop_graph(ctx);  // the captured graph names the old buffer roles
+  // the node records of the next stage input: the step counter did not move,
+  // so the next step reads the buffer this stage read
+  if (gdg_status s = launched(ctx, launch_prim(ctx->A, ctx->U[ctx->cur], 0, ctx->stream), "prim")) return s;
   if (tau_used) *tau_used = ctx->hctl.tau;
   return GDG_OK;
 }
@@ -696,18 +693,26 @@ gdg_status gdg_read_field(gdg_ctx *ctx, int32_t field, double *dst, int32_t is_d
   if (!ctx || !dst) return GDG_E_INVALID;
   (void)is_device_ptr;
   const size_t N = (size_t)ctx->A.N, M = (size_t)ctx->M;
-  const double *src = nullptr;
-  size_t planes = 0;
+  if (field == GDG_FIELD_STATE) {
+    HIPCHK(ctx, hipMemcpyAsync(dst, ctx->U[ctx->cur], M * N * sizeof(double), hipMemcpyDefault, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return GDG_OK;
+  }
+  // the other fields sit in per-dof records: plane k is the column at
+  // `first + k` of records of `stride` doubles
+  const double *rec = nullptr;
+  size_t planes = 0, first = 0, stride = 0;
   switch (field) {
-    case GDG_FIELD_STATE: src = ctx->U[ctx->cur]; planes = M; break;
-    case GDG_FIELD_EV_N: src = ctx->A.Nev; planes = 1; break;
-    case GDG_FIELD_BOUNDS: src = ctx->A.B; planes = 3; break;
-    case GDG_FIELD_UL: src = ctx->A.UL; planes = M; break;
-    case GDG_FIELD_DUH: src = ctx->A.dUH; planes = M; break;
-    case GDG_FIELD_U1: src = ctx->A.U1; planes = M; break;
+    case GDG_FIELD_EV_N: rec = ctx->A.Qd; stride = kQStride; first = 3; planes = 1; break;
+    case GDG_FIELD_BOUNDS: rec = ctx->A.Ld; stride = kLimStride; first = 2 * M; planes = 3; break;
+    case GDG_FIELD_UL: rec = ctx->A.Ld; stride = kLimStride; first = M; planes = M; break;
+    case GDG_FIELD_DUH: rec = ctx->A.Ld; stride = kLimStride; first = 0; planes = M; break;
+    case GDG_FIELD_U1: rec = ctx->A.U1d; stride = kU1Stride; first = 0; planes = M; break;
     default: ctx->err = "unknown field"; return GDG_E_INVALID;
   }
-  HIPCHK(ctx, hipMemcpyAsync(dst, src, planes * N * sizeof(double), hipMemcpyDefault, ctx->stream));
+  for (size_t k = 0; k < planes; ++k)
+    HIPCHK(ctx, hipMemcpy2DAsync(dst + k * N, sizeof(double), rec + first + k, stride * sizeof(double),
+                                 sizeof(double), N, hipMemcpyDefault, ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   return GDG_OK;
 }

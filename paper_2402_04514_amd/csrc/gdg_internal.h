@@ -69,6 +69,27 @@ struct Ctl {
 constexpr int kRedBlocks = 512;
 constexpr int kRedThreads = 256;
 constexpr int kRedFields = 2 + kMaxD + 2;
+// Per-dof records (arrays of structures): the fields that a row gathers from
+// its neighbours sit together, so that a neighbour costs one or two cache
+// lines and a few wide loads instead of one line per field.
+//  node record (kNodeStride doubles), two buffers: the stage input's and the
+//  stage output's, chosen by the parity of 3 * steps + stage (node_buffer):
+//    [0, M) U, [M, M+D) velocity, then p, a, p^-alpha, f(s), s~, 1/p
+//  bound record (kQStride): rho_min, rho_max, s~_min of the ring-1 partials, N_i
+//  limiter record (kLimStride): [0, M) dU^H, [M, 2M) U^L, then rho_min,
+//    rho_max, s~_min of the relaxed bounds, 1/(kappa_i m_i), N_i
+//  U^(1) record (kU1Stride): [0, M) the state after limiter pass 1
+constexpr int kNodeStride = 16, kQStride = 4, kLimStride = 16, kU1Stride = 8;
+template <int D> struct Rec {
+  static constexpr int M = D + 2;
+  // node record
+  static constexpr int U = 0, u = M, p = 2 * D + 2, a = 2 * D + 3, pal = 2 * D + 4, fs = 2 * D + 5,
+                       st = 2 * D + 6, ip = 2 * D + 7, nwide = D + 4;  // nwide: 16-byte loads of the whole record
+  // limiter record
+  static constexpr int dUH = 0, UL = M, B = 2 * M, ks = 2 * M + 3, N = 2 * M + 4;
+  static_assert(ip < kNodeStride && N < kLimStride && M <= kU1Stride, "record strides");
+};
+
 // Reference tables of one cell class (every cell of a uniform mesh).
 struct RefTables {
   double mlump[kMaxNloc];                   // m_a
@@ -120,12 +141,11 @@ struct KArgs {
   const RefTables *ref;
   int64_t nslots;
   // per-dof fields
-  double *Wc;       // node cache: dim velocities, p, a, p^-alpha, f(s), s~, 1/p  (dim+6 planes)
-  double *Nev;      // entropy-viscosity ratio
+  double *Nd;       // node records, two buffers of N * kNodeStride
+  double *Qd;       // bound records (N * kQStride)
+  double *Ld;       // limiter records (N * kLimStride)
+  double *U1d;      // U^(1) records (N * kU1Stride)
   double *fsum;     // per row, (dim+2) planes: sum_j (f(U_j) - f(U_i)) c_ij with the boundary parts
-  double *q;        // ring-1 bound partials: rho_min, rho_max, s~_min
-  double *B;        // relaxed bounds
-  double *UL, *dUH, *U1;
   double *dL;       // d^L (and d^{d,L} on ghost slots) per slot
   double *l1;       // l of limiter pass 1 per slot (the ghost slot of a row holds l_i^d)
   uint8_t *accepted;  // per row: set by sweep 2 for rows of quiet cells (every flux zero), then by
@@ -176,7 +196,8 @@ int launch_end(const KArgs &A, void *stream);
 // the end of a device-driven step and the start of the next, in one launch
 int launch_end_begin(const KArgs &A, void *stream);
 int launch_set_run(const KArgs &A, double t_final, long long step_limit, void *stream);
-int launch_prim(const KArgs &A, const double *U, void *stream);
+// node records of the input of `stage` (of the current step) from the SoA state U
+int launch_prim(const KArgs &A, const double *U, int stage, void *stream);
 // min rho, min eps and sum_i m_i U_i (per component) of the state U into
 // A.red[kRedBlocks * kRedFields ...], deterministically
 int launch_state_stats(const KArgs &A, const double *U, void *stream);

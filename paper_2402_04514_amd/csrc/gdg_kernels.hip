@@ -5,10 +5,10 @@
 //
 // Sweeps of one forward-Euler stage Phi(U; tau):
 //   k_prim    per node: velocity, pressure, sound speed, p^-alpha, Harten
-//             entropy f(s), rescaled entropy s~ (Sec. 2.2, Sec. 5.2, 5.4);
-//             with the limiter, the last limiter pass writes this node cache
-//             for the stage output, and k_prim runs only at the start of a
-//             host-driven step
+//             entropy f(s), rescaled entropy s~ (Sec. 2.2, Sec. 5.2, 5.4),
+//             with the state, as the node record the sweeps gather; with the
+//             limiter, the last limiter pass writes the stage output's
+//             records, and k_prim runs only at the start of a host-driven step
 //   k_sweep1  d^L_ij, d_i^{d,k} (eq. dij_low_order, dij_low_order_modified),
 //             min_i m_i/(2|d_ii|) (eq. MaxCFLdt), the entropy-viscosity ratio
 //             N_i (Sec. 5.2) and ring-1 partial bounds over bar states
@@ -458,13 +458,24 @@ __device__ __forceinline__ bool node_fields(const KArgs &A, const double *V, dou
   return rho > 0.0 && eps > 0.0;
 }
 
-// Node cache of row i from its state V (and the admissibility flag).
+// Node record of the stage input (buffer 0 or 1 by the parity of
+// 3 * steps + stage: each stage reads one buffer and its last sweep writes the
+// other, which the next stage reads).
+__device__ __forceinline__ double *node_buffer(const KArgs &A, int stage) {
+  const long long k = 3 * A.ctl->steps + stage;
+  return A.Nd + (size_t)(k & 1) * (size_t)A.N * kNodeStride;
+}
+
+// Node record of row i from its state V (and the admissibility flag).
 template <int D>
-__device__ __forceinline__ void store_prim(const KArgs &A, int64_t i, const double *V) {
-  const int64_t N = A.N;
+__device__ __forceinline__ void store_node(const KArgs &A, double *nd, int64_t i, const double *V) {
   double W[D + 6];
   if (!node_fields<D>(A, V, W)) atomicOr(&A.ctl->bad_flag, 1);
-  for (int k = 0; k < D + 6; ++k) A.Wc[k * N + i] = W[k];
+  double r[2 * (D + 4)];
+  for (int c = 0; c < D + 2; ++c) r[c] = V[c];
+  for (int k = 0; k < D + 6; ++k) r[D + 2 + k] = W[k];
+  double2 *o = reinterpret_cast<double2 *>(nd + (size_t)i * kNodeStride);
+  for (int k = 0; k < D + 4; ++k) o[k] = make_double2(r[2 * k], r[2 * k + 1]);
 }
 
 // Set-up: the node fields of each face's Dirichlet data, computed by the same
@@ -484,16 +495,16 @@ __global__ void k_bnodes(KArgs A, RefTables *T) {
 }
 
 template <int D>
-__device__ __forceinline__ void prim_row(const KArgs &A, const double *__restrict__ U, int64_t i) {
+__device__ __forceinline__ void prim_row(const KArgs &A, const double *__restrict__ U, int64_t i, double *nd) {
   if (i >= A.N) return;
   double V[D + 2];
   for (int c = 0; c < D + 2; ++c) V[c] = U[c * A.N + i];
-  store_prim<D>(A, i, V);
+  store_node<D>(A, nd, i, V);
 }
 
 template <int D>
-__global__ __launch_bounds__(kBlockThreads) void k_prim(KArgs A, const double *__restrict__ U) {
-  prim_row<D>(A, U, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+__global__ __launch_bounds__(kBlockThreads) void k_prim(KArgs A, const double *__restrict__ U, int stage) {
+  prim_row<D>(A, U, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, node_buffer(A, stage));
 }
 
 template <int D>
@@ -503,18 +514,37 @@ struct Node {
   double p, a, pal, fs, st, ip;
 };
 
+// The whole node record of dof j: D + 4 loads of 16 bytes from one 128-byte line.
 template <int D>
-__device__ __forceinline__ void load_node(const KArgs &A, const double *__restrict__ U, int64_t j,
-                                          Node<D> &n) {
-  const int64_t N = A.N;
-  for (int c = 0; c < D + 2; ++c) n.U[c] = U[c * N + j];
-  for (int e = 0; e < D; ++e) n.u[e] = A.Wc[e * N + j];
-  n.p = A.Wc[(D + 0) * N + j];
-  n.a = A.Wc[(D + 1) * N + j];
-  n.pal = A.Wc[(D + 2) * N + j];
-  n.fs = A.Wc[(D + 3) * N + j];
-  n.st = A.Wc[(D + 4) * N + j];
-  n.ip = A.Wc[(D + 5) * N + j];
+__device__ __forceinline__ void load_node(const double *__restrict__ nd, int64_t j, Node<D> &n) {
+  using R = Rec<D>;
+  const double2 *r = reinterpret_cast<const double2 *>(nd + (size_t)j * kNodeStride);
+  double v[2 * (D + 4)];
+  for (int k = 0; k < D + 4; ++k) {
+    const double2 t = r[k];
+    v[2 * k] = t.x;
+    v[2 * k + 1] = t.y;
+  }
+  for (int c = 0; c < D + 2; ++c) n.U[c] = v[R::U + c];
+  for (int e = 0; e < D; ++e) n.u[e] = v[R::u + e];
+  n.p = v[R::p];
+  n.a = v[R::a];
+  n.pal = v[R::pal];
+  n.fs = v[R::fs];
+  n.st = v[R::st];
+  n.ip = v[R::ip];
+}
+
+// The first n doubles of a record (n even or odd), by 16-byte loads.
+template <int NV>
+__device__ __forceinline__ void load_rec(const double *__restrict__ rec, double *out) {
+  const double2 *r = reinterpret_cast<const double2 *>(rec);
+  for (int k = 0; k < NV / 2; ++k) {
+    const double2 t = r[k];
+    out[2 * k] = t.x;
+    out[2 * k + 1] = t.y;
+  }
+  if (NV % 2) out[NV - 1] = rec[NV - 1];
 }
 
 // Boundary data of Sec. 4.1 for a boundary part of row i on box face f, with
@@ -590,11 +620,12 @@ __device__ __forceinline__ void sweep1_body(const KArgs &A, const double *__rest
   const int lane = threadIdx.x;
   const int64_t i = blk * A.R + lane;
   const bool active = lane < A.R && i < A.N;
+  const double *__restrict__ nd = node_buffer(A, stage);
   double tau_i = INFINITY;
   if (active) {
     const double g = A.gamma;
     Node<D> ni;
-    load_node<D>(A, U, i, ni);
+    load_node<D>(nd, i, ni);
     // gradient of the shifted Harten entropy at U_i, rho_i f'(s_i) grad s(U_i)
     double grad[M];
     {
@@ -626,7 +657,7 @@ __device__ __forceinline__ void sweep1_body(const KArgs &A, const double *__rest
     double c_n[D];
     load_c<D, MX>(A, s0, c_n);
     Node<D> nj_n;
-    load_node<D>(A, U, col_n, nj_n);
+    load_node<D>(nd, col_n, nj_n);
     uint8_t meta_nn = 0;
     int32_t col_nn = 0;
     if (A.W > 1) {
@@ -644,7 +675,7 @@ __device__ __forceinline__ void sweep1_body(const KArgs &A, const double *__rest
         meta_n = meta_nn;
         col_n = col_nn;
         load_c<D, MX>(A, s + A.R, c_n);
-        load_node<D>(A, U, col_n, nj_n);
+        load_node<D>(nd, col_n, nj_n);
         if (t + 2 < A.W) {
           meta_nn = A.meta[s + 2 * A.R];
           col_nn = A.col[s + 2 * A.R];
@@ -718,13 +749,13 @@ __device__ __forceinline__ void sweep1_body(const KArgs &A, const double *__rest
       R -= gq * S[q];
       Dn += fabs(gq) * fabs(S[q]);
     }
-    A.Nev[i] = Dn > 0 ? (double)(R / Dn) : 0.0;
+    const double Nval = Dn > 0 ? (double)(R / Dn) : 0.0;
     // the flux sum of the row (graph and boundary parts, difference form) is
     // the one the low- and high-order updates of sweep 2 need
     for (int q = 0; q < M; ++q) A.fsum[q * A.N + i] = (double)S[q];
-    A.q[i] = rmin;
-    A.q[A.N + i] = rmax;
-    A.q[2 * A.N + i] = smin;
+    double2 *qr = reinterpret_cast<double2 *>(A.Qd + (size_t)i * kQStride);
+    qr[0] = make_double2(rmin, rmax);
+    qr[1] = make_double2(smin, Nval);
     const double mi = A.ref->mlump[i % NLOC];
     tau_i = mi / (2.0 * dsum);
   }
@@ -777,18 +808,20 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
     return;
   }
   if (stage == 0 && blk == 0 && threadIdx.x == 0) A.ctl->tau = tau;
-  const double *__restrict__ U = sb.in;
+  using R = Rec<D>;
+  const double *__restrict__ nd = node_buffer(A, stage);
   const int lane = threadIdx.x;
   const int64_t i = blk * A.R + lane;
   const bool active = lane < A.R && i < A.N;
   const int64_t N = A.N;
   const double g = A.gamma;
+  double *__restrict__ lr = A.Ld + (size_t)i * kLimStride;  // this row's limiter record
   Node<D> ni;
   int a = 0;
   if (active) {
     a = (int)(i % NLOC);
-    load_node<D>(A, U, i, ni);
-    const double Ni = A.Nev[i];
+    load_node<D>(nd, i, ni);
+    const double Ni = A.Qd[(size_t)i * kQStride + 3];
     const double hpk = A.ref->hpk[a];
     const double mi = A.ref->mlump[a];
     // accL / accH: the viscous terms sum_j d_ij (U_j - U_i) of the low- and
@@ -848,13 +881,17 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
         continue;
       }
       const int64_t j = colv;
-      rmin = fmin(rmin, A.q[j]);
-      rmax = fmax(rmax, A.q[N + j]);
-      smin = fmin(smin, A.q[2 * N + j]);
+      double qj[4];
+      load_rec<4>(A.Qd + (size_t)j * kQStride, qj);
+      rmin = fmin(rmin, qj[0]);
+      rmax = fmax(rmax, qj[1]);
+      smin = fmin(smin, qj[2]);
       if (j == i) continue;
-      const double dH = visc_high(A, d, Ni, A.Nev[j], kind, hpk);
+      const double dH = visc_high(A, d, Ni, qj[3], kind, hpk);
+      double Uj[M];
+      load_rec<M>(nd + (size_t)j * kNodeStride, Uj);
       for (int q = 0; q < M; ++q) {
-        const double du = U[q * N + j] - ni.U[q];
+        const double du = Uj[q] - ni.U[q];
         dev += fabs(du);
         accL[q] -= d * du;
         accH[q] -= dH * du;
@@ -870,13 +907,15 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
     double UL[M];
     for (int q = 0; q < M; ++q) {
       UL[q] = ni.U[q] - tau / mi * accL[q];
-      A.UL[q * N + i] = UL[q];
+      lr[R::UL + q] = UL[q];
     }
     // eq. local_bounds with r^-+ = 1 -+ c_r hhat_i^{p_r}
     const double rel = A.ref->relax[a];
-    A.B[i] = (1.0 - rel) * rmin;
-    A.B[N + i] = (1.0 + rel) * rmax;
-    A.B[2 * N + i] = (1.0 - rel) * smin;
+    lr[R::B] = (1.0 - rel) * rmin;
+    lr[R::B + 1] = (1.0 + rel) * rmax;
+    lr[R::B + 2] = (1.0 - rel) * smin;
+    lr[R::ks] = A.kscale[i];
+    lr[R::N] = Ni;
     for (int q = 0; q < M; ++q) rs[q][lane] = -accH[q];
     if (A.scheme == 0 || (A.scheme == 2 && A.passes == 0)) {
       for (int q = 0; q < M; ++q)
@@ -903,7 +942,7 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
     double s = 0.0;
     for (int b = 0; b < NLOC; ++b) s += A.ref->minv[a * NLOC + b] * rs[q][cellbase + b];
     const double du = tau * s;
-    A.dUH[q * N + i] = du;
+    lr[R::dUH + q] = du;
     V[q] = ni.U[q] + du;
   }
   if (A.scheme == 1) {
@@ -924,21 +963,20 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(G
 //   A_ij = tau (d^H_ij - d^L_ij)(U_j - U_i) - m_ij (dU^H_j - dU^H_i).
 // d^L, d^H and m_ij are symmetric, so row j computes exactly -A_ij.
 template <int D, int NLOC>
-__device__ __forceinline__ void pair_flux(const KArgs &A, const double *__restrict__ U, int64_t j, uint8_t meta,
+__device__ __forceinline__ void pair_flux(const KArgs &A, const double *Uj, const double *dUj, double Nj, uint8_t meta,
                                           int a, const double *Ui, const double *dUi, double Ni, double hpk,
                                           double tau, double d, double *Aij) {
-  const int64_t N = A.N;
   const int kind = meta & 7;
-  const double dH = visc_high(A, d, Ni, A.Nev[j], kind, hpk);
+  const double dH = visc_high(A, d, Ni, Nj, kind, hpk);
   const double mij = kind == SK_CELL ? A.ref->mblk[a * NLOC + (meta >> 3)] : 0.0;
   const double td = tau * (dH - d);
-  for (int q = 0; q < D + 2; ++q) Aij[q] = td * (U[q * N + j] - Ui[q]) - mij * (A.dUH[q * N + j] - dUi[q]);
+  for (int q = 0; q < D + 2; ++q) Aij[q] = td * (Uj[q] - Ui[q]) - mij * (dUj[q] - dUi[q]);
 }
 
 // Boundary part of A_i^d for one ghost slot: tau (d^{d,H} - d^{d,L})(U^d - U_i),
 // with U^d built from the node of row i as in the sweeps.
 template <int D>
-__device__ __forceinline__ void ghost_flux(const KArgs &A, const double *__restrict__ U, int64_t i, int64_t s,
+__device__ __forceinline__ void ghost_flux(const KArgs &A, const double *__restrict__ nd, int64_t i, int64_t s,
                                            uint8_t meta, const double *Ui, double Ni, double hpk, double tau,
                                            double d, double *Ab) {
   double c[D], nc2 = 0.0;
@@ -955,7 +993,7 @@ __device__ __forceinline__ void ghost_flux(const KArgs &A, const double *__restr
   if (kind == GDG_BC_DIRICHLET || kind == GDG_BC_SUPERSONIC) {
     // the data kinds decide from the node of row i, as the sweeps do
     Node<D> ni, gh;
-    load_node<D>(A, U, i, ni);
+    load_node<D>(nd, i, ni);
     ghost_node<D>(A, ni, f, n, gh);
     for (int q = 0; q < D + 2; ++q) Ug[q] = gh.U[q];
   } else {
@@ -979,17 +1017,18 @@ __device__ __forceinline__ void ghost_flux(const KArgs &A, const double *__restr
 // U^(1).  pass 1: base U^(1), fluxes (1 - l^(1)) A.  The final pass writes the
 // SSP combination.
 template <int D, int DEG>
-__device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, int pass, int final_pass,
+__device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, int stage, int pass, int final_pass,
                                            int64_t blk) {
   constexpr int M = D + 2;
   constexpr int NB = DEG + 1;
   constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
+  constexpr int NL = 2 * M + 5;  // limiter record: dU^H, U^L, bounds, 1/(kappa m), N
+  using R = Rec<D>;
   if (A.ctl->halt || A.ctl->cfl_flag) return;
   const int lane = threadIdx.x;
   const int64_t i = blk * A.R + lane;
   if (lane >= A.R || i >= A.N) return;
-  const double *__restrict__ U = sb.in;
-  const double *__restrict__ base = pass == 0 ? A.UL : A.U1;
+  const double *__restrict__ nd = node_buffer(A, stage);
   const int64_t N = A.N;
   const double tau = A.ctl->tau;
   const int a = (int)(i % NLOC);
@@ -997,28 +1036,29 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
     // pass 1 accepted every pair and the boundary part of this row whole:
     // nothing is left to limit (every remaining flux is 0 A), and the result
     // is U^(1) itself
-    {
-      double O[M];
-      for (int q = 0; q < M; ++q) {
-        const double v = base[q * N + i];
-        O[q] = sb.ca == 0.0 ? v : sb.ca * sb.Un[q * N + i] + sb.cb * v;
-        sb.out[q * N + i] = O[q];
-      }
-      store_prim<D>(A, i, O);
-      return;
+    double V[M], O[M];
+    load_rec<M>(A.U1d + (size_t)i * kU1Stride, V);
+    for (int q = 0; q < M; ++q) {
+      O[q] = sb.ca == 0.0 ? V[q] : sb.ca * sb.Un[q * N + i] + sb.cb * V[q];
+      sb.out[q * N + i] = O[q];
     }
+    store_node<D>(A, node_buffer(A, stage + 1), i, O);
+    return;
   }
   const double mi = A.ref->mlump[a];
   const double hpk = A.ref->hpk[a];
-  const double sci = A.kscale[i];  // 1 / (kappa_i m_i)
-  const double Ni = A.Nev[i];
-  double Ui[M], Li[M], dUi[M];
-  for (int q = 0; q < M; ++q) {
-    Ui[q] = U[q * N + i];
-    Li[q] = base[q * N + i];
-    dUi[q] = A.dUH[q * N + i];
+  double Ui[M], Li[M], dUi[M], lri[NL];
+  load_rec<M>(nd + (size_t)i * kNodeStride, Ui);
+  load_rec<NL>(A.Ld + (size_t)i * kLimStride, lri);
+  for (int q = 0; q < M; ++q) dUi[q] = lri[R::dUH + q];
+  if (pass == 0) {
+    for (int q = 0; q < M; ++q) Li[q] = lri[R::UL + q];
+  } else {
+    load_rec<M>(A.U1d + (size_t)i * kU1Stride, Li);
   }
-  const double rmin = A.B[i], rmax = A.B[N + i], smin = A.B[2 * N + i];
+  const double rmin = lri[R::B], rmax = lri[R::B + 1], smin = lri[R::B + 2];
+  const double sci = lri[R::ks];  // 1 / (kappa_i m_i)
+  const double Ni = lri[R::N];
   const double smin5 = A.g75 ? pow5(smin) : 0.0;
   double acc[M], Ab[M];
   for (int q = 0; q < M; ++q) acc[q] = Ab[q] = 0.0;
@@ -1044,7 +1084,7 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
     if (kind == SK_PAD) continue;
     const double d = A.dL[s];
     if (kind == SK_GHOST) {
-      ghost_flux<D>(A, U, i, s, meta, Ui, Ni, hpk, tau, d, Ab);
+      ghost_flux<D>(A, nd, i, s, meta, Ui, Ni, hpk, tau, d, Ab);
       if (gslot < 0) gslot = s;
       continue;
     }
@@ -1058,8 +1098,12 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
       rest = 1.0 - A.l1[s];
       if (rest == 0.0) continue;
     }
+    // the neighbour's state and limiter record: two cache lines
+    double Uj[M], lrj[NL];
+    load_rec<M>(nd + (size_t)j * kNodeStride, Uj);
+    load_rec<NL>(A.Ld + (size_t)j * kLimStride, lrj);
     double Aij[M];
-    pair_flux<D, NLOC>(A, U, j, meta, a, Ui, dUi, Ni, hpk, tau, d, Aij);
+    pair_flux<D, NLOC>(A, Uj, lrj + R::dUH, lrj[R::N], meta, a, Ui, dUi, Ni, hpk, tau, d, Aij);
     bool zero = true;
     for (int q = 0; q < M; ++q) zero = zero && Aij[q] == 0.0;
     if (zero) {
@@ -1069,13 +1113,17 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
     if (pass == 1)
       for (int q = 0; q < M; ++q) Aij[q] = rest * Aij[q];
     double Lj[M], Pi[M], Pj[M];
-    const double scj = A.kscale[j];
+    const double scj = lrj[R::ks];
+    if (pass == 0) {
+      for (int q = 0; q < M; ++q) Lj[q] = lrj[R::UL + q];
+    } else {
+      load_rec<M>(A.U1d + (size_t)j * kU1Stride, Lj);
+    }
     for (int q = 0; q < M; ++q) {
-      Lj[q] = base[q * N + j];
       Pi[q] = sci * Aij[q];
       Pj[q] = -(scj * Aij[q]);
     }
-    const double rminj = A.B[j], rmaxj = A.B[N + j], sj = A.B[2 * N + j];
+    const double rminj = lrj[R::B], rmaxj = lrj[R::B + 1], sj = lrj[R::B + 2];
     double li, lj;
     const bool oki = ls_fast<D>(A, Li, Pi, rmin, rmax, smin, smin5, &li);
     const bool okj = ls_fast<D>(A, Lj, Pj, rminj, rmaxj, sj, A.g75 ? pow5(sj) : 0.0, &lj);
@@ -1103,7 +1151,8 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
   double V[M];
   for (int q = 0; q < M; ++q) V[q] = Li[q] + acc[q] / mi;
   if (pass == 0) {
-    for (int q = 0; q < M; ++q) A.U1[q * N + i] = V[q];
+    double *u1 = A.U1d + (size_t)i * kU1Stride;
+    for (int q = 0; q < M; ++q) u1[q] = V[q];
     A.accepted[i] = allone ? 1 : 0;
     wave_count_add(&A.ctl->limited_pairs, ncut);
   }
@@ -1125,23 +1174,22 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
     wave_count_add(&A.ctl->bound_violations, in ? 0u : 1u);
   }
   if (final_pass) {
-    // the stage output, and its node cache for the next stage: no kernel of
-    // this pass reads the cache, so it is rewritten here instead of by a
-    // separate primitives launch
+    // the stage output, and its node record for the next stage (the other
+    // buffer: this pass still reads the stage input's records)
     double O[M];
     for (int q = 0; q < M; ++q) {
       O[q] = sb.ca == 0.0 ? V[q] : sb.ca * sb.Un[q * N + i] + sb.cb * V[q];
       sb.out[q * N + i] = O[q];
     }
     if (!(V[0] > 0.0) || !(eps_of<D>(V) > 0.0)) atomicOr(&A.ctl->bad_flag, 1);
-    store_prim<D>(A, i, O);
+    store_node<D>(A, node_buffer(A, stage + 1), i, O);
   }
 }
 
 template <int D, int DEG>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_LIMIT))) void k_limit(
-    KArgs A, StageBufs sb, int pass, int final_pass) {
-  limit_body<D, DEG>(A, sb, pass, final_pass, xcd_block(A, blockIdx.x));
+    KArgs A, StageBufs sb, int stage, int pass, int final_pass) {
+  limit_body<D, DEG>(A, sb, stage, pass, final_pass, xcd_block(A, blockIdx.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -1179,7 +1227,8 @@ __global__ __launch_bounds__(kBlockThreads) void kb_prim(const BatchList *L, int
   for_tiles(L, [&](const BatchEntry &E, int64_t blk) {
     if (E.A.ctl->halt || E.A.ctl->cfl_flag) return;
     if (E.A.scheme == 2 && E.A.passes > 0) return;  // cache written by the last limiter pass
-    if ((int)threadIdx.x < E.A.R) prim_row<D>(E.A, E.sb[stage].in, blk * E.A.R + threadIdx.x);
+    if ((int)threadIdx.x < E.A.R)
+      prim_row<D>(E.A, E.sb[stage].in, blk * E.A.R + threadIdx.x, node_buffer(E.A, stage));
   });
 }
 
@@ -1203,7 +1252,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(G
     const BatchList *L, int stage, int pass) {
   for_tiles(L, [&](const BatchEntry &E, int64_t blk) {
     if (E.A.scheme != 2 || pass >= E.A.passes) return;
-    limit_body<D, DEG>(E.A, E.sb[stage], pass, pass + 1 == E.A.passes ? 1 : 0, blk);
+    limit_body<D, DEG>(E.A, E.sb[stage], stage, pass, pass + 1 == E.A.passes ? 1 : 0, blk);
   });
 }
 
@@ -1310,7 +1359,7 @@ static int stage_impl(const KArgs &A, const StageBufs &b, int stage, void *strea
   // there; otherwise it is computed at the start of the next stage
   if (need_prim || !(A.scheme == 2 && A.passes > 0)) {
     prof_mark(prof, KID_PRIM, 0, stream);
-    hipLaunchKernelGGL(k_prim<D>, dim3(gp), blk, 0, S(stream), A, b.in);
+    hipLaunchKernelGGL(k_prim<D>, dim3(gp), blk, 0, S(stream), A, b.in, stage);
     prof_mark(prof, KID_PRIM, 1, stream);
   }
   // sweep 1 without the boundary-data code where no face has data: its
@@ -1331,7 +1380,7 @@ static int stage_impl(const KArgs &A, const StageBufs &b, int stage, void *strea
   prof_mark(prof, KID_SWEEP2, 1, stream);
   for (int pass = 0; pass < (A.scheme == 2 ? A.passes : 0); ++pass) {
     prof_mark(prof, KID_LIMIT1 + pass, 0, stream);
-    hipLaunchKernelGGL((k_limit<D, DEG>), grid, blk, 0, S(stream), A, b, pass, pass + 1 == A.passes ? 1 : 0);
+    hipLaunchKernelGGL((k_limit<D, DEG>), grid, blk, 0, S(stream), A, b, stage, pass, pass + 1 == A.passes ? 1 : 0);
     prof_mark(prof, KID_LIMIT1 + pass, 1, stream);
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -1478,13 +1527,13 @@ int launch_state_stats(const KArgs &A, const double *U, void *stream) {
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_prim(const KArgs &A, const double *U, void *stream) {
+int launch_prim(const KArgs &A, const double *U, int stage, void *stream) {
   clear_stale();
   const unsigned gp = (unsigned)((A.N + kBlockThreads - 1) / kBlockThreads);
   switch (A.dim) {
-    case 1: hipLaunchKernelGGL(k_prim<1>, dim3(gp), dim3(kBlockThreads), 0, S(stream), A, U); break;
-    case 2: hipLaunchKernelGGL(k_prim<2>, dim3(gp), dim3(kBlockThreads), 0, S(stream), A, U); break;
-    case 3: hipLaunchKernelGGL(k_prim<3>, dim3(gp), dim3(kBlockThreads), 0, S(stream), A, U); break;
+    case 1: hipLaunchKernelGGL(k_prim<1>, dim3(gp), dim3(kBlockThreads), 0, S(stream), A, U, stage); break;
+    case 2: hipLaunchKernelGGL(k_prim<2>, dim3(gp), dim3(kBlockThreads), 0, S(stream), A, U, stage); break;
+    case 3: hipLaunchKernelGGL(k_prim<3>, dim3(gp), dim3(kBlockThreads), 0, S(stream), A, U, stage); break;
     default: return -2;
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -10,6 +10,11 @@
 // single-mesh path.  What the server adds is the batched launch: one captured
 // graph of several device-driven steps whose persistent kernels walk the row
 // blocks of all resident requests.
+//
+// Streams: the batched graph runs on the caller's stream; admissions (set-up,
+// state upload) and the host-driven redo of a halted step run on a second
+// stream of the same priority, so that a request is admitted while a launch
+// is in flight; the next launch waits for that stream through an event.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -101,8 +106,11 @@ struct gdg_server {
   gdg_server_desc d{};
   char *pool = nullptr;
   size_t pool_bytes = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;      // batched launches
+  hipStream_t adm_stream = nullptr;  // admissions, restarts, retirements (the requests' contexts)
   hipStream_t cap_stream = nullptr;
+  hipEvent_t done_ev = nullptr;      // after the status copy of the launch in flight
+  hipEvent_t adm_ev = nullptr;       // joins the admission stream into the next launch
   hipGraphExec_t gexec = nullptr;
   BatchList *dlist = nullptr;  // device work list (pool start)
   Ctl *dstat = nullptr;        // device status copies
@@ -113,6 +121,7 @@ struct gdg_server {
   int grid = 0;
   std::deque<Req *> pending;
   std::vector<Req *> resident;  // admitted, in work-list order
+  std::vector<Req *> staged;    // admitted while a launch was in flight: join the next work list
   std::vector<Req *> launched;  // the work list of the launch in flight
   bool list_dirty = true;
   bool in_flight = false;
@@ -172,11 +181,10 @@ gdg_status finish_req(gdg_server *s, Req *q) {
   return GDG_OK;
 }
 
-// Steps 1-3 of a pump: wait for the launch in flight, take every request's
-// control block, redo halted steps, retire finished requests.
+// Steps 1-3 of a pump, once the launch in flight has completed: take every
+// request's control block, redo halted steps, retire finished requests.
 gdg_status process(gdg_server *s) {
   if (!s->in_flight) return GDG_OK;
-  SRVCHK(s, hipStreamSynchronize(s->stream));
   s->in_flight = false;
   for (size_t r = 0; r < s->launched.size(); ++r) {
     Req *q = s->launched[r];
@@ -206,16 +214,17 @@ gdg_status process(gdg_server *s) {
   return GDG_OK;
 }
 
-// Step 4: admission in arrival order while a slot and pool room are free.
+// Step 4: admission in arrival order while a slot and pool room are free, on
+// the admission stream (the batched launch may still be running).
 void admit(gdg_server *s) {
-  while (!s->pending.empty() && (int)s->resident.size() < s->d.max_slots) {
+  while (!s->pending.empty() && (int)(s->resident.size() + s->staged.size()) < s->d.max_slots) {
     Req *q = s->pending.front();
     size_t off = 0;
     if (!s->alloc.alloc(q->bytes, &off)) break;  // the head waits for room
     s->pending.pop_front();
     q->off = s->base + off;
     q->admit_s = s->now();
-    gdg_status st = gdg_create(&q->mesh, &q->prm, s->pool + q->off, q->bytes, s->stream, &q->ctx);
+    gdg_status st = gdg_create(&q->mesh, &q->prm, s->pool + q->off, q->bytes, s->adm_stream, &q->ctx);
     if (st != GDG_OK) {
       q->ctx = nullptr;
       s->alloc.release(off, q->bytes);
@@ -238,9 +247,16 @@ void admit(gdg_server *s) {
       fail_req(s, q, GDG_E_DEVICE, "kernel launch failed: set run");
       continue;
     }
-    s->resident.push_back(q);
-    s->list_dirty = true;
+    s->staged.push_back(q);
   }
+}
+
+// Staged admissions join the work list of the next launch.
+void merge_staged(gdg_server *s) {
+  if (s->staged.empty()) return;
+  for (Req *q : s->staged) s->resident.push_back(q);
+  s->staged.clear();
+  s->list_dirty = true;
 }
 
 gdg_status ensure_graph(gdg_server *s) {
@@ -272,6 +288,10 @@ gdg_status ensure_device(gdg_server *s) {
   int dev = 0, cus = 0;
   SRVCHK(s, hipGetDevice(&dev));
   SRVCHK(s, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  // a plain stream: the default priority, as the caller's
+  SRVCHK(s, hipStreamCreateWithFlags(&s->adm_stream, hipStreamNonBlocking));
+  SRVCHK(s, hipEventCreateWithFlags(&s->done_ev, hipEventDisableTiming));
+  SRVCHK(s, hipEventCreateWithFlags(&s->adm_ev, hipEventDisableTiming));
   SRVCHK(s, hipHostMalloc((void **)&s->hstat, sizeof(Ctl) * kMaxBatch, hipHostMallocDefault));
   // one-wavefront workgroups: eight per CU keep every SIMD busy with two
   // waves while leaving room for the register budget of the sweeps
@@ -280,7 +300,8 @@ gdg_status ensure_device(gdg_server *s) {
 }
 
 // Step 5: refresh the device work list if the resident set changed, launch
-// the graph and queue the status copy.
+// the graph after the admission stream's work and queue the status copy.
+// Called only when no launch is in flight, so the caller's stream is idle.
 gdg_status launch(gdg_server *s) {
   if (s->resident.empty()) return GDG_OK;
   if (gdg_status st = ensure_device(s)) return st;
@@ -302,10 +323,27 @@ gdg_status launch(gdg_server *s) {
     s->list_dirty = false;
   }
   if (gdg_status st = ensure_graph(s)) return st;
+  SRVCHK(s, hipEventRecord(s->adm_ev, s->adm_stream));
+  SRVCHK(s, hipStreamWaitEvent(s->stream, s->adm_ev, 0));
   SRVCHK(s, hipGraphLaunch(s->gexec, s->stream));
   SRVCHK(s, hipMemcpyAsync(s->hstat, s->dstat, sizeof(Ctl) * (size_t)n, hipMemcpyDeviceToHost, s->stream));
+  SRVCHK(s, hipEventRecord(s->done_ev, s->stream));
   s->launched = s->resident;
   s->in_flight = true;
+  return GDG_OK;
+}
+
+// Whether the launch in flight (if any) has completed, without waiting.
+gdg_status flight_done(gdg_server *s, bool *done) {
+  *done = true;
+  if (!s->in_flight) return GDG_OK;
+  const hipError_t e = hipEventQuery(s->done_ev);
+  if (e == hipErrorNotReady) {
+    (void)hipGetLastError();  // not an error: clear it for later calls
+    *done = false;
+    return GDG_OK;
+  }
+  if (e != hipSuccess) return fail_hip(s, "hipEventQuery", e);
   return GDG_OK;
 }
 
@@ -384,15 +422,24 @@ gdg_status gdg_server_submit(gdg_server *s, const gdg_mesh_desc *mesh, const gdg
 
 gdg_status gdg_server_sync(gdg_server *s) {
   if (!s) return GDG_E_INVALID;
+  if (s->in_flight) SRVCHK(s, hipEventSynchronize(s->done_ev));
   return process(s);
 }
 
 gdg_status gdg_server_pump(gdg_server *s, int32_t *resident, int32_t *pending) {
   if (!s) return GDG_E_INVALID;
-  if (gdg_status st = process(s)) return st;
-  admit(s);
-  if (gdg_status st = launch(s)) return st;
-  if (resident) *resident = (int32_t)s->resident.size();
+  if (gdg_status st = ensure_device(s)) return st;
+  bool done = true;
+  if (gdg_status st = flight_done(s, &done)) return st;
+  if (done) {
+    if (gdg_status st = process(s)) return st;
+    admit(s);
+    merge_staged(s);
+    if (gdg_status st = launch(s)) return st;
+  } else {
+    admit(s);  // overlaps the launch in flight; joins the next one
+  }
+  if (resident) *resident = (int32_t)(s->resident.size() + s->staged.size());
   if (pending) *pending = (int32_t)s->pending.size();
   return GDG_OK;
 }
@@ -428,12 +475,16 @@ gdg_status gdg_server_result(gdg_server *s, uint64_t ticket, double *U) {
 void gdg_server_destroy(gdg_server *s) {
   if (!s) return;
   if (s->hstat || !s->resident.empty()) (void)hipStreamSynchronize(s->stream);
+  if (s->adm_stream) (void)hipStreamSynchronize(s->adm_stream);
   for (auto &kv : s->reqs) {
     if (kv.second->ctx) gdg_destroy(kv.second->ctx);
     delete kv.second;
   }
   if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  if (s->done_ev) (void)hipEventDestroy(s->done_ev);
+  if (s->adm_ev) (void)hipEventDestroy(s->adm_ev);
+  if (s->adm_stream) (void)hipStreamDestroy(s->adm_stream);
   if (s->hstat) (void)hipHostFree(s->hstat);
   delete s->hlist;
   delete s;

@@ -13,6 +13,8 @@ steps).  On
 the FP64 class they also match the oracle at the final time (1e-10, as for
 the oracle runs of several steps).
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -51,6 +53,7 @@ def _run_server(reqs, precision, max_slots=8, budget=None, arrivals=None, spg=4)
     arrivals = arrivals or [0] * len(reqs)
     tickets = [None] * len(reqs)
     peak, k = 0, 0
+    t0 = time.perf_counter()
     while True:
         for r, (ms, U, tf) in enumerate(reqs):
             if tickets[r] is None and arrivals[r] <= k:
@@ -60,7 +63,8 @@ def _run_server(reqs, precision, max_slots=8, budget=None, arrivals=None, spg=4)
         k += 1
         if all(t is not None for t in tickets) and res == 0 and pend == 0:
             break
-        assert k < 100000
+        # a pump returns at once while a launch is in flight: bound the time
+        assert time.perf_counter() - t0 < 300
     S.sync()
     infos = [S.poll(t) for t in tickets]
     outs = [S.result(t) for t in tickets]
@@ -185,3 +189,32 @@ def test_served_requests_with_cfl_restarts():
         assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
     S.close()
     assert total_restarts > 0
+
+
+def test_admission_overlaps_the_launch_in_flight():
+    """A request submitted while a long batched launch runs is admitted (set
+    up and uploaded on the admission stream) before that launch is processed,
+    joins the next launch, and its result is still the same as served alone."""
+    big_ms, big_U = quadrant_on(2, 1, (256, 256), (2,) * 4, seed=3)
+    small_ms, small_U = quadrant_on(2, 1, (24, 20), (2,) * 4, seed=4)
+    S = gdg.Server(2, 1, gdg.GDG_FP64, budget_bytes=1 << 30, max_slots=4, steps_per_graph=64)
+    tb = S.submit(big_ms, big_U, 0.002)
+    res, _ = S.pump()                       # admits the big request and launches 64 of its steps
+    assert res == 1
+    ts = S.submit(small_ms, small_U, 0.002)
+    res, pend = S.pump()                    # the launch is still running: admission only
+    info_big, info_small = S.poll(tb), S.poll(ts)
+    _say("while in flight: resident %d, big steps %d, small state %d" % (res, info_big.steps, info_small.state))
+    assert res == 2 and pend == 0
+    assert info_small.state == gdg.GDG_REQ_RUNNING and info_small.admit_s > 0
+    assert info_big.steps == 0              # the launch in flight has not been processed
+    while True:
+        res, pend = S.pump()
+        if res == 0 and pend == 0:
+            break
+    S.sync()
+    out_big, out_small = S.result(tb), S.result(ts)
+    S.close()
+    alone_big, _, _ = _run_server([(big_ms, big_U, 0.002)], gdg.GDG_FP64, max_slots=1)
+    alone_small, _, _ = _run_server([(small_ms, small_U, 0.002)], gdg.GDG_FP64, max_slots=1)
+    assert np.array_equal(out_big, alone_big[0]) and np.array_equal(out_small, alone_small[0])
