@@ -239,8 +239,32 @@ gdg_status gdg_profile(gdg_ctx *ctx, int32_t enable);
 gdg_status gdg_profile_read(const gdg_ctx *ctx, double *ms_total, int64_t *launches);
 
 /* Text of the last error on this context ("" if none); with ctx == NULL, the
- * reason of the last failed gdg_create() on the calling thread. */
+ * reason of the last failed gdg_create() or gdg_solve_noalloc() on the
+ * calling thread. */
 const char *gdg_last_error(const gdg_ctx *ctx);
+
+/* ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture of their own, tight serving loops, harnesses that forbid hipMalloc):
+ * gdg_create() + gdg_upload_state() + gdg_run_to() + gdg_download_state() in
+ * one call, with the workspace taken from a static device array of the
+ * library instead of the caller.  The array holds GDG_NOALLOC_MAX_BYTES on
+ * every GPU the library runs on, from the library's load until the process
+ * ends; meshes whose gdg_workspace_bytes() exceed it are refused with
+ * GDG_E_NOMEM.  The call allocates no device memory and captures no graph
+ * (its device-driven steps are launched directly on hip_stream); it
+ * synchronizes the stream before it returns.
+ *
+ * U0 (initial state) and U (final state) are SoA, (dim+2) * N doubles, host or
+ * device memory, owned by the caller; t_final, max_steps and stats as for
+ * gdg_run_to().  Every call on one GPU uses that GPU's one array: calls that
+ * overlap on one GPU (other threads, other streams) race and corrupt each
+ * other; calls in sequence are independent (the array's contents are
+ * rewritten by each call before they are read).  Errors as for gdg_create()
+ * and gdg_run_to(); the text is in gdg_last_error(NULL). */
+#define GDG_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+gdg_status gdg_solve_noalloc(const gdg_mesh_desc *mesh, const gdg_params *prm, const double *U0, double *U,
+                             double t_final, int64_t max_steps, void *hip_stream, gdg_stats *stats);
 
 /* ---------------------------------------------------------------------------
  * Serving: many independent simulations on one GPU with continuous batching.

@@ -115,11 +115,13 @@ def load():
     L.gdg_server_destroy.restype = None
     L.gdg_server_last_error.argtypes = [_P]
     L.gdg_server_last_error.restype = C.c_char_p
+    L.gdg_solve_noalloc.argtypes = [C.POINTER(gdg_mesh_desc), C.POINTER(gdg_params), _P, _P, C.c_double,
+                                    C.c_int64, _P, C.POINTER(gdg_stats)]
     for fn in ("gdg_default_params", "gdg_workspace_bytes", "gdg_create", "gdg_node_coords",
                "gdg_upload_state", "gdg_download_state", "gdg_step", "gdg_run_to", "gdg_stage",
                "gdg_read_field", "gdg_get_stats", "gdg_profile", "gdg_profile_read",
                "gdg_server_overhead_bytes", "gdg_server_create", "gdg_server_submit", "gdg_server_pump",
-               "gdg_server_sync", "gdg_server_poll", "gdg_server_result"):
+               "gdg_server_sync", "gdg_server_poll", "gdg_server_result", "gdg_solve_noalloc"):
         getattr(L, fn).restype = C.c_int
     _lib = L
     return L
@@ -249,6 +251,19 @@ def gdg_profile_read(ctx):
 
 def gdg_last_error(ctx) -> str:
     return load().gdg_last_error(ctx).decode()
+
+
+def gdg_solve_noalloc(mesh, prm, U0, out, t_final: float, max_steps: int = 2 ** 62,
+                      stream_ptr: int = 0) -> gdg_stats:
+    """The whole solve in the library's static device workspace (no device
+    allocation): U0 and out are float64 SoA arrays, numpy or torch (host or
+    device)."""
+    s = gdg_stats()
+    p0, _ = _ptr(U0)
+    p1, _ = _ptr(out)
+    _check(load().gdg_solve_noalloc(C.byref(mesh), C.byref(prm), _P(p0), _P(p1), t_final, max_steps,
+                                    _P(stream_ptr), C.byref(s)), None)
+    return s
 
 
 # -- convenience owner of workspace + context ----------------------------------
