@@ -251,7 +251,7 @@ void or_destroy(or_setup *S) {
  * Sec. 4.2).  Exact Gauss-Legendre integration with k+1 points (reading R5). */
 or_setup *or_create(int dim, int deg, const long *cells, const double *lo, const double *hi,
                     const int *bc) {
-  if (dim < 1 || dim > 3 || deg < 1 || deg > 2) return NULL;
+  if (dim < 1 || dim > 3 || deg < 1 || deg > 3) return NULL;
   or_setup *S = (or_setup *)calloc(1, sizeof(or_setup));
   S->dim = dim; S->deg = deg; S->nb1 = deg + 1; S->m = dim + 2;
   S->nloc = 1;
@@ -272,16 +272,30 @@ or_setup *or_create(int dim, int deg, const long *cells, const double *lo, const
     if (p0 != p1 || (p0 && S->n[e] < 2) || S->n[e] < 1) { free(S); return NULL; }
   }
   S->ndofs = S->ncells * S->nloc;
+  /* Gauss-Lobatto nodes on [0, 1]: the end points and, for k = 2, 3, the
+   * roots of the derivative of the Legendre polynomial of degree k */
   if (deg == 1) { S->xg[0] = 0.0; S->xg[1] = 1.0; }
-  else { S->xg[0] = 0.0; S->xg[1] = 0.5; S->xg[2] = 1.0; }
+  else if (deg == 2) { S->xg[0] = 0.0; S->xg[1] = 0.5; S->xg[2] = 1.0; }
+  else {
+    double r = 0.5 / sqrt(5.0);
+    S->xg[0] = 0.0; S->xg[1] = 0.5 - r; S->xg[2] = 0.5 + r; S->xg[3] = 1.0;
+  }
+  /* Gauss-Legendre rule with k + 1 points on [0, 1] (exact to degree 2k + 1) */
   S->nq = deg + 1;
   if (deg == 1) {
     double r = 0.5 / sqrt(3.0);
     S->xq[0] = 0.5 - r; S->xq[1] = 0.5 + r; S->wq[0] = S->wq[1] = 0.5;
-  } else {
+  } else if (deg == 2) {
     double r = 0.5 * sqrt(0.6);
     S->xq[0] = 0.5 - r; S->xq[1] = 0.5; S->xq[2] = 0.5 + r;
     S->wq[0] = S->wq[2] = 5.0 / 18.0; S->wq[1] = 8.0 / 18.0;
+  } else {
+    /* on [-1, 1]: x = +-sqrt(3/7 -+ (2/7) sqrt(6/5)), w = (18 +- sqrt(30)) / 36 */
+    double xi = sqrt(3.0 / 7.0 - 2.0 / 7.0 * sqrt(1.2)), xo = sqrt(3.0 / 7.0 + 2.0 / 7.0 * sqrt(1.2));
+    double wi = (18.0 + sqrt(30.0)) / 36.0, wo = (18.0 - sqrt(30.0)) / 36.0;
+    S->xq[0] = 0.5 * (1.0 - xo); S->xq[1] = 0.5 * (1.0 - xi);
+    S->xq[2] = 0.5 * (1.0 + xi); S->xq[3] = 0.5 * (1.0 + xo);
+    S->wq[0] = S->wq[3] = 0.5 * wo; S->wq[1] = S->wq[2] = 0.5 * wi;
   }
 
   long N = S->ndofs;
@@ -989,7 +1003,7 @@ int or_stage(const or_setup *S, const or_params *P, const double *U, double tau,
     int nloc = S->nloc;
 #pragma omp parallel for schedule(static)
     for (long K = 0; K < S->ncells; ++K) {
-      double Mk[27 * 27], rhs[OR_MAXM][27];
+      double Mk[64 * 64], rhs[OR_MAXM][64];
       for (int a = 0; a < nloc; ++a) {
         long i = K * nloc + a;
         double Ui[OR_MAXM], Uj[OR_MAXM], fc[OR_MAXM], fi[OR_MAXM], acc[OR_MAXM] = {0};

@@ -65,7 +65,8 @@ class Workload:
 
 
 def gl_nodes(degree: int) -> np.ndarray:
-    return np.array({1: [0.0, 1.0], 2: [0.0, 0.5, 1.0]}[degree])
+    r = 0.5 / math.sqrt(5.0)
+    return np.array({1: [0.0, 1.0], 2: [0.0, 0.5, 1.0], 3: [0.0, 0.5 - r, 0.5 + r, 1.0]}[degree])
 
 
 def node_coords(ms: MeshSpec):

@@ -85,6 +85,13 @@ MUTANTS = {
                                       [VISC + "::test_face_pair_viscosity_is_the_papers"]),
     "boundary_min_viscosity_dropped": ("double dmin = P->c_k * pow(hh, pk) * dbd[b];", "double dmin = 0.0 * dbd[b];",
                                        [VISC + "::test_boundary_viscosity_even_degree"]),
+    "q3_equispaced_nodes": ("double r = 0.5 / sqrt(5.0);\n    S->xg[0] = 0.0;", "double r = 1.0 / 6.0;\n    S->xg[0] = 0.0;",
+                            [SETUP + "::test_q3_1d_closed_form"]),
+    "entropy_viscosity_q3_constant": ("case 3: return 0.25;", "case 3: return 0.5;",
+                                      [VISC + "::test_face_pair_viscosity_is_the_papers"]),
+    "q3_quadrature_weights_swapped": ("S->wq[0] = S->wq[3] = 0.5 * wo; S->wq[1] = S->wq[2] = 0.5 * wi;",
+                                      "S->wq[0] = S->wq[3] = 0.5 * wi; S->wq[1] = S->wq[2] = 0.5 * wo;",
+                                      [SETUP + "::test_q3_1d_closed_form"]),
     "ev_normalizer_not_abs_sum": ("D += fabs(grad[q]) * fabs(Sk[q]);", "D += fabs(grad[q] * Sk[q]) * 0.5;",
                                   [SCHEME + "::test_vortex_convergence"]),
 }

@@ -19,6 +19,9 @@ MESHES = [
     (2, 2, (3, 3), (0.0, 0.0), (1.0, 1.0), (0, 0, 1, 1)),
     (3, 1, (3, 2, 3), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), (2, 2, 2, 2, 2, 2)),
     (3, 1, (2, 2, 2), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), (0, 0, 1, 1, 2, 2)),
+    (1, 3, (5,), (0.0,), (1.5,), (1, 1)),
+    (2, 3, (3, 2), (0.0, 0.0), (1.0, 2.0), (1, 1, 2, 2)),
+    (2, 3, (2, 3), (-1.0, -1.0), (1.0, 1.0), (0, 0, 0, 0)),
 ]
 
 
@@ -112,6 +115,64 @@ def test_q2_1d_closed_form(oracle):
     got = {int(col[k]): c[k, 0] for k in range(rp[i], rp[i + 1])}
     assert got[3 * (K - 1) + 2] == pytest.approx(-0.5, abs=1e-15)
     assert len(got) == 4
+
+
+def test_q3_1d_closed_form(oracle):
+    """1D Q3 on Gauss-Lobatto nodes {0, 1/2 -+ 1/(2 sqrt 5), 1}: the lumped
+    masses are h times the four-point Gauss-Lobatto weights 1/12, 5/12, 5/12,
+    1/12; m_ab and the in-cell c_ab = int phi_b' phi_a - (1/2)[phi_a phi_b n]
+    over the cell's ends come from the Lagrange polynomials integrated exactly
+    with an eight-point Gauss-Legendre rule from numpy (exact to degree 15,
+    where these integrands have degree 6), independent of the oracle's
+    four-point rule."""
+    r = 0.5 / math.sqrt(5.0)
+    x = [0.0, 0.5 - r, 0.5 + r, 1.0]
+    gx, gw = np.polynomial.legendre.leggauss(8)
+    gx, gw = 0.5 * (gx + 1.0), 0.5 * gw
+
+    def val(a, t):
+        v = np.ones_like(t)
+        for b in range(4):
+            if b != a:
+                v = v * (t - x[b]) / (x[a] - x[b])
+        return v
+
+    def der(a, t):
+        v = np.zeros_like(t)
+        for c in range(4):
+            if c == a:
+                continue
+            w = np.full_like(t, 1.0 / (x[a] - x[c]))
+            for b in range(4):
+                if b != a and b != c:
+                    w = w * (t - x[b]) / (x[a] - x[b])
+            v = v + w
+        return v
+
+    one, zero = np.array([1.0]), np.array([0.0])
+    mass = lambda a, b: float(np.sum(gw * val(a, gx) * val(b, gx)))
+    grad = lambda a, b: float(np.sum(gw * val(a, gx) * der(b, gx)))   # int phi_b' phi_a
+    lump = lambda a: float(np.sum(gw * val(a, gx)))
+    ends = lambda a, b: float(val(a, one)[0] * val(b, one)[0] - val(a, zero)[0] * val(b, zero)[0])
+    h = 0.3
+    M = oracle.Mesh(1, 3, (5,), (0.0,), (1.5,), (1, 1))
+    rp, col, c, mij, kind = M.csr()
+    mi = M.lumped()
+    K = 2
+    for a in range(4):
+        i = 4 * K + a
+        assert mi[i] / h == pytest.approx([1 / 12, 5 / 12, 5 / 12, 1 / 12][a], abs=1e-15)
+        assert mi[i] / h == pytest.approx(lump(a), abs=1e-15)
+        got = {int(col[k]): (c[k, 0], mij[k]) for k in range(rp[i], rp[i + 1])}
+        for b in range(4):
+            cc, mm = got[4 * K + b]
+            assert cc == pytest.approx(grad(a, b) - 0.5 * ends(a, b), abs=5e-15)
+            assert mm / h == pytest.approx(mass(a, b), abs=2e-15)
+    # the end nodes couple across the faces with -+1/2 (phi_a = 1 there)
+    got = {int(col[k]): c[k, 0] for k in range(rp[4 * K], rp[4 * K + 1])}
+    assert got[4 * (K - 1) + 3] == pytest.approx(-0.5, abs=1e-15) and len(got) == 5
+    got = {int(col[k]): c[k, 0] for k in range(rp[4 * K + 3], rp[4 * K + 4])}
+    assert got[4 * (K + 1)] == pytest.approx(0.5, abs=1e-15) and len(got) == 5
 
 
 def test_q1_2d_corner(oracle):
