@@ -25,7 +25,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gdg_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-BC_PERIODIC, BC_OUTFLOW, BC_SLIP, BC_DIRICHLET, BC_SUPERSONIC = 0, 1, 2, 3, 4
+BC_PERIODIC, BC_OUTFLOW, BC_SLIP, BC_DIRICHLET, BC_SUPERSONIC, BC_INOUTFLOW = 0, 1, 2, 3, 4, 5
 LOW_ORDER, HIGH_ORDER, LIMITED = 0, 1, 2
 KIND_CELL, KIND_FACE_COLLOC, KIND_FACE = 0, 1, 2
 
@@ -83,6 +83,12 @@ def lib():
         L.or_set_reference_volume.argtypes = [C.c_void_p, C.c_double]
         L.or_set_boundary_state.restype = None
         L.or_set_boundary_state.argtypes = [C.c_void_p, C.c_int, _DP]
+        L.or_inoutflow_state.restype = C.c_int
+        L.or_inoutflow_state.argtypes = [C.c_int, C.c_double, _DP, _DP, _DP, _DP]
+        L.or_set_time.restype = None
+        L.or_set_time.argtypes = [C.c_void_p, C.c_double]
+        L.or_set_vortex_data.restype = C.c_int
+        L.or_set_vortex_data.argtypes = [C.c_void_p, _DP]
         L.or_csr.argtypes = [C.c_void_p, C.POINTER(C.c_long), C.POINTER(C.c_long), _DP, _DP,
                              C.POINTER(C.c_int)]
         L.or_lumped.argtypes = [C.c_void_p, _DP]
@@ -122,10 +128,13 @@ def params(gamma=1.4, cfl=0.5, degree=1, c_ev=None, c_k=1.0, c_r=4.0, p_r=1.5, p
 class Mesh:
     """Uniform Cartesian DG Q_k mesh with the stencil of Sec. 2.3."""
 
-    def __init__(self, dim, degree, cells, lo, hi, bc, bstate=None):
+    def __init__(self, dim, degree, cells, lo, hi, bc, bstate=None, vortex=None):
         """bc: kinds per box face 2*axis+side (0 periodic, 1 outflow, 2 slip,
-        3 Dirichlet, 4 supersonic in/outflow).  bstate: per face the
-        conserved Dirichlet data U^d of kinds 3 and 4 (None elsewhere)."""
+        3 Dirichlet, 4 supersonic in/outflow, 5 sub- and supersonic
+        in/outflow).  bstate: per face the conserved Dirichlet data U^d of
+        kinds 3-5 (None elsewhere).  vortex: (beta, x0_1, x0_2, u_1, u_2,
+        gamma) to take the data of kinds 3-5 from the isentropic vortex at the
+        node and the stage time instead (2D)."""
         self.dim, self.degree = dim, degree
         self.cells = tuple(int(c) for c in cells)
         self.lo = tuple(float(x) for x in lo)
@@ -141,8 +150,13 @@ class Mesh:
             raise ValueError("invalid mesh description")
         self.ndofs = L.or_num_dofs(self._h)
         self.m = dim + 2
+        if vortex is not None:
+            v = np.ascontiguousarray(vortex, dtype=np.float64)
+            assert v.shape == (6,)
+            if L.or_set_vortex_data(self._h, _dp(v)) != 0:
+                raise ValueError("vortex boundary data needs a 2D mesh")
         for f in range(2 * dim):
-            if self.bc[f] in (3, 4):
+            if self.bc[f] in (3, 4, 5) and vortex is None:
                 if bstate is None or bstate[f] is None:
                     raise ValueError("face %d needs Dirichlet data" % f)
                 v = np.ascontiguousarray(bstate[f], dtype=np.float64)
@@ -228,6 +242,10 @@ class Mesh:
         lib().or_tau_rows(self._h, C.byref(prm), _dp(U), _dp(out))
         return out
 
+    def set_time(self, t: float):
+        """Time of the step's start, for time-dependent boundary data."""
+        lib().or_set_time(self._h, float(t))
+
     def step(self, prm: _Params, U: np.ndarray, dt_cap: float = 0.0, dt_fixed: float = 0.0):
         """One SSP-RK3 step.  Returns (U_new, dt_taken, restarts, status)."""
         U = np.array(U, dtype=np.float64).reshape(self.m, self.ndofs)
@@ -242,6 +260,7 @@ class Mesh:
         t, n = 0.0, 0
         while t < t_final and n < max_steps:
             cap = t_final - t
+            self.set_time(t)
             U, dt, _, st = self.step(prm, U, dt_cap=cap)
             if st:
                 raise RuntimeError("oracle step failed with status %d" % st)
@@ -289,6 +308,17 @@ def exact_riemann(gamma, rl, ul, pl, rr, ur, pr):
 
 def exact_lambda(gamma, rl, ul, pl, rr, ur, pr) -> float:
     return lib().or_exact_lambda(gamma, rl, ul, pl, rr, ur, pr)
+
+
+def inoutflow_state(gamma, Ui, Ud, n):
+    """Boundary state of the sub- and supersonic in/outflow kind for node
+    state Ui, data Ud and outward unit normal n: (state, status)."""
+    Ui = np.ascontiguousarray(Ui, dtype=np.float64)
+    Ud = np.ascontiguousarray(Ud, dtype=np.float64)
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    out = np.zeros_like(Ui)
+    st = lib().or_inoutflow_state(len(n), gamma, _dp(Ui), _dp(Ud), _dp(n), _dp(out))
+    return out, st
 
 
 def riemann_sample(gamma, left, right, xi):

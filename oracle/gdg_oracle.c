@@ -31,8 +31,10 @@
 
 #define OR_MAXD 3
 #define OR_MAXM 5
+#define OR_PI 3.14159265358979323846
 
-enum { OR_BC_PERIODIC = 0, OR_BC_OUTFLOW = 1, OR_BC_SLIP = 2, OR_BC_DIRICHLET = 3, OR_BC_SUPERSONIC = 4 };
+enum { OR_BC_PERIODIC = 0, OR_BC_OUTFLOW = 1, OR_BC_SLIP = 2, OR_BC_DIRICHLET = 3, OR_BC_SUPERSONIC = 4,
+       OR_BC_INOUTFLOW = 5 };
 enum { OR_LOW_ORDER = 0, OR_HIGH_ORDER = 1, OR_LIMITED = 2 };
 enum { OR_KIND_CELL = 0, OR_KIND_FACE_COLLOC = 1, OR_KIND_FACE = 2 };
 
@@ -53,6 +55,12 @@ typedef struct {
   double lo[3], hi[3], h[3];
   int bc[6];
   double bstate[6][OR_MAXM];  /* Dirichlet data U^d per box face (Sec. 4.1) */
+  /* Dirichlet data from the isentropic vortex of Sec. 6.2 instead (2D):
+   * beta, x0 (2), u_inf (2), gamma of the data; evaluated at the node and the
+   * stage time */
+  int vortex_data;
+  double vortex[6];
+  double t0;                  /* time at the start of the step (boundary data) */
   long ncells, ndofs;
   double vol;
   /* CSR of the stencil I(i), diagonal included (reading R4) */
@@ -266,7 +274,7 @@ or_setup *or_create(int dim, int deg, const long *cells, const double *lo, const
   }
   for (int f = 0; f < 6; ++f) S->bc[f] = f < 2 * dim ? bc[f] : OR_BC_OUTFLOW;
   for (int f = 0; f < 2 * dim; ++f)
-    if (S->bc[f] < OR_BC_PERIODIC || S->bc[f] > OR_BC_SUPERSONIC) { free(S); return NULL; }
+    if (S->bc[f] < OR_BC_PERIODIC || S->bc[f] > OR_BC_INOUTFLOW) { free(S); return NULL; }
   for (int e = 0; e < dim; ++e) {
     int p0 = S->bc[2 * e] == OR_BC_PERIODIC, p1 = S->bc[2 * e + 1] == OR_BC_PERIODIC;
     if (p0 != p1 || (p0 && S->n[e] < 2) || S->n[e] < 1) { free(S); return NULL; }
@@ -619,7 +627,110 @@ void or_riemann_sample(double g, double rl, double ul, double pl, double rr, dou
  *    needs the characteristic construction, which is not built: there the
  *    function returns -4 (and U_i as the ghost).
  * Returns 0 or -4. */
-static int ghost_state(const or_setup *S, double gamma, int f, const double *Ui, const double *cb, double *Ug) {
+/* Node coordinates x_i. */
+static void node_x(const or_setup *S, long i, double *x) {
+  long ki[3];
+  int ai[3];
+  cell_multi(S, i / S->nloc, ki);
+  local_multi(S, (int)(i % S->nloc), ai);
+  for (int e = 0; e < S->dim; ++e) x[e] = S->lo[e] + (ki[e] + S->xg[ai[e]]) * S->h[e];
+}
+
+/* The isentropic vortex of Sec. 6.2 at point x and time t (free space, no
+ * periodic images): with xb = x - x0 - t u_inf, r = |xb|,
+ * rho = (1 - (gamma-1) beta^2 / (8 gamma pi^2) e^{1-r^2})^{1/(gamma-1)},
+ * p = rho^gamma, u = u_inf + beta / (2 pi) e^{(1-r^2)/2} (-xb_2, xb_1)
+ * (the velocity factor with the exponent halved: reading R23, the form in
+ * radial balance). */
+static void vortex_at(const double *vp, const double *x, double t, double *U) {
+  const double beta = vp[0], g = vp[5];
+  const double xb0 = x[0] - vp[1] - t * vp[3], xb1 = x[1] - vp[2] - t * vp[4];
+  const double r2 = xb0 * xb0 + xb1 * xb1;
+  const double T = 1.0 - (g - 1.0) * beta * beta / (8.0 * g * OR_PI * OR_PI) * exp(1.0 - r2);
+  const double rho = pow(T, 1.0 / (g - 1.0)), p = pow(rho, g);
+  const double fac = beta / (2.0 * OR_PI) * exp(0.5 * (1.0 - r2));
+  const double u0 = vp[3] - fac * xb1, u1 = vp[4] + fac * xb0;
+  U[0] = rho;
+  U[1] = rho * u0;
+  U[2] = rho * u1;
+  U[3] = p / (g - 1.0) + 0.5 * rho * (u0 * u0 + u1 * u1);
+}
+
+/* Dirichlet data U^d of box face f at node i and time t (Sec. 4.1: the data
+ * at position x_i for time t). */
+static void data_state(const or_setup *S, int f, long i, double t, double *Ud) {
+  if (S->vortex_data) {
+    double x[3];
+    node_x(S, i, x);
+    vortex_at(S->vortex, x, t, Ud);
+    return;
+  }
+  for (int c = 0; c < S->m; ++c) Ud[c] = S->bstate[f][c];
+}
+
+/* Sub- and supersonic in/outflow (Sec. 4.1): eq. supersonic_inoutflow where
+ * |u_i.n| >= a_i, and in the subsonic range the state whose characteristic
+ * variables of eq. characteristics equal those of the data U^d for the
+ * incoming characteristics (speed lambda_k(U_i, n) <= 0) and those of U_i for
+ * the others.  The state follows from its four variables
+ * R1 = v_n - 2a/(gamma-1), R2 = p / rho^gamma, R3 = v - v_n n,
+ * R4 = v_n + 2a/(gamma-1):  v_n = (R1 + R4)/2, a = (gamma-1)(R4 - R1)/4,
+ * rho = (a^2 / (gamma R2))^{1/(gamma-1)}, p = R2 rho^gamma (reading R35).
+ * Returns -4 if that state has no positive sound speed. */
+static int inoutflow_state(int dim, double g, const double *Ui, const double *Ud, const double *n, double *Ug) {
+  double vi[3], vd[3], vni = 0.0, vnd = 0.0;
+  for (int e = 0; e < dim; ++e) {
+    vi[e] = Ui[1 + e] / Ui[0];
+    vd[e] = Ud[1 + e] / Ud[0];
+    vni += vi[e] * n[e];
+    vnd += vd[e] * n[e];
+  }
+  const double pi = (g - 1.0) * eps_of(dim, Ui), pd = (g - 1.0) * eps_of(dim, Ud);
+  const double ai = sqrt(g * pi / Ui[0]), ad = sqrt(g * pd / Ud[0]);
+  if (vni < -ai) {
+    for (int c = 0; c < dim + 2; ++c) Ug[c] = Ud[c];
+    return 0;
+  }
+  if (vni >= ai) {
+    for (int c = 0; c < dim + 2; ++c) Ug[c] = Ui[c];
+    return 0;
+  }
+  /* characteristic speeds at U_i: v_n - a < 0, v_n, v_n, v_n + a > 0 */
+  const int in23 = vni <= 0.0;
+  const double R1 = vnd - 2.0 * ad / (g - 1.0);
+  const double R4 = vni + 2.0 * ai / (g - 1.0);
+  const double R2 = in23 ? pd / pow(Ud[0], g) : pi / pow(Ui[0], g);
+  double R3[3];
+  for (int e = 0; e < dim; ++e) R3[e] = in23 ? vd[e] - vnd * n[e] : vi[e] - vni * n[e];
+  const double vn = 0.5 * (R1 + R4), a = 0.25 * (g - 1.0) * (R4 - R1);
+  if (!(a > 0.0)) {
+    for (int c = 0; c < dim + 2; ++c) Ug[c] = Ui[c];
+    return -4;
+  }
+  const double rho = pow(a * a / (g * R2), 1.0 / (g - 1.0)), p = R2 * pow(rho, g);
+  double u2 = 0.0;
+  Ug[0] = rho;
+  for (int e = 0; e < dim; ++e) {
+    const double v = R3[e] + vn * n[e];
+    Ug[1 + e] = rho * v;
+    u2 += v * v;
+  }
+  Ug[dim + 1] = p / (g - 1.0) + 0.5 * rho * u2;
+  return 0;
+}
+
+/* Boundary state U^d of one boundary part (Sec. 4.1) of node i, face f,
+ * c_i^{d,f} = cb, at time t:
+ *  - outflow: U_i (the supersonic-outflow branch of eq. supersonic_inoutflow);
+ *  - slip: eq. slip_boundary;
+ *  - Dirichlet: the data U^d;
+ *  - supersonic in/outflow, eq. supersonic_inoutflow: U^d if u_i.n < -a_i
+ *    (inflow), U_i if u_i.n >= a_i (outflow); the subsonic range between
+ *    returns -4 (and U_i as the ghost);
+ *  - sub- and supersonic in/outflow: inoutflow_state().
+ * Returns 0 or -4. */
+static int ghost_state(const or_setup *S, double gamma, int f, long i, double t, const double *Ui, const double *cb,
+                       double *Ug) {
   int dim = S->dim, bkind = S->bc[f];
   double nn = 0.0;
   for (int e = 0; e < dim; ++e) nn += cb[e] * cb[e];
@@ -630,17 +741,40 @@ static int ghost_state(const or_setup *S, double gamma, int f, const double *Ui,
     for (int e = 0; e < dim; ++e) mn += Ui[1 + e] * cb[e] / nn;
     for (int e = 0; e < dim; ++e) Ug[1 + e] = Ui[1 + e] - 2.0 * mn * cb[e] / nn;
   } else if (bkind == OR_BC_DIRICHLET) {
-    for (int c = 0; c < S->m; ++c) Ug[c] = S->bstate[f][c];
+    data_state(S, f, i, t, Ug);
   } else if (bkind == OR_BC_SUPERSONIC) {
     double un = 0.0;
     for (int e = 0; e < dim; ++e) un += (Ui[1 + e] / Ui[0]) * cb[e] / nn;
     double a = sqrt(gamma * (gamma - 1.0) * eps_of(dim, Ui) / Ui[0]);
     if (un < -a) {
-      for (int c = 0; c < S->m; ++c) Ug[c] = S->bstate[f][c];
+      data_state(S, f, i, t, Ug);
     } else if (!(un >= a)) {
       return -4;
     }
+  } else if (bkind == OR_BC_INOUTFLOW) {
+    double Ud[OR_MAXM], n[3];
+    data_state(S, f, i, t, Ud);
+    for (int e = 0; e < dim; ++e) n[e] = cb[e] / nn;
+    return inoutflow_state(dim, gamma, Ui, Ud, n, Ug);
   }
+  return 0;
+}
+
+/* inoutflow_state() for the pins of eq. characteristics. */
+int or_inoutflow_state(int dim, double gamma, const double *Ui, const double *Ud, const double *n, double *Ug) {
+  return inoutflow_state(dim, gamma, Ui, Ud, n, Ug);
+}
+
+/* Time of the boundary data at the start of the next step. */
+void or_set_time(or_setup *S, double t) { S->t0 = t; }
+
+/* Boundary data of every Dirichlet-type face from the isentropic vortex
+ * (beta, x0[2], u_inf[2], gamma) instead of the constant face states; 2D
+ * meshes only.  Returns 0, or -1 for another dimension. */
+int or_set_vortex_data(or_setup *S, const double *params) {
+  if (S->dim != 2) return -1;
+  S->vortex_data = 1;
+  for (int k = 0; k < 6; ++k) S->vortex[k] = params[k];
   return 0;
 }
 
@@ -797,8 +931,18 @@ static double *dalloc(long n) { return (double *)calloc(n > 0 ? n : 1, sizeof(do
  * tau <= 0 selects tau = Cr * tau_max of this state (eq. MaxCFLdt).
  * Returns 0 on success, -2 if the output leaves the admissible set, -4 if a
  * node of a supersonic in/outflow face sees subsonic normal flow. */
+static int stage_at(const or_setup *S, const or_params *P, const double *U, double tau, double t, double *Uout,
+                    or_diag *dg);
+
+/* One stage at the time of the step's start (or_set_time). */
 int or_stage(const or_setup *S, const or_params *P, const double *U, double tau, double *Uout,
              or_diag *dg) {
+  return stage_at(S, P, U, tau, S->t0, Uout, dg);
+}
+
+/* The stage with boundary data at time t. */
+static int stage_at(const or_setup *S, const or_params *P, const double *U, double tau, double t, double *Uout,
+                    or_diag *dg) {
   const int dim = S->dim, m = S->m;
   const long N = S->ndofs, nnz = S->rowptr[N];
   const double g = P->gamma;
@@ -818,7 +962,7 @@ int or_stage(const or_setup *S, const or_params *P, const double *U, double tau,
     double Ui[OR_MAXM];
     get_state(S, U, i, Ui);
     for (long b = S->bptr[i]; b < S->bptr[i + 1]; ++b)
-      if (ghost_state(S, g, S->bface[b], Ui, S->bc_c + b * dim, Ug + b * m)) subsonic = 1;
+      if (ghost_state(S, g, S->bface[b], i, t, Ui, S->bc_c + b * dim, Ug + b * m)) subsonic = 1;
   }
 
   /* eq. dij_low_order, dij_low_order_modified (reading R2: inside state on
@@ -1183,7 +1327,7 @@ void or_tau_rows(const or_setup *S, const or_params *P, const double *U, double 
     for (long b = S->bptr[i]; b < S->bptr[i + 1]; ++b) {
       const double *cb = S->bc_c + b * dim;
       double nc = norm_c(dim, cb), n[3];
-      ghost_state(S, P->gamma, S->bface[b], Ui, cb, Ug);
+      ghost_state(S, P->gamma, S->bface[b], i, S->t0, Ui, cb, Ug);
       for (int e = 0; e < dim; ++e) n[e] = cb[e] / nc;
       s += nc * or_lambda_max(P->gamma, dim, Ui, Ug, n);
     }
@@ -1218,10 +1362,12 @@ int or_step(const or_setup *S, const or_params *P, double *U, double dt_cap, dou
     tau = P->cfl * tm;
   }
   if (dt_cap > 0.0 && tau > dt_cap) tau = dt_cap;
+  /* stage times of the Shu-Osher form: t0, t0 + tau, t0 + tau / 2 (the
+   * boundary data of each stage at its own time, reading R29) */
   for (;;) {
-    st = or_stage(S, P, U, tau, Ua, &dg);
+    st = stage_at(S, P, U, tau, S->t0, Ua, &dg);
     if (st) break;
-    st = or_stage(S, P, Ua, tau, Ph, &dg);
+    st = stage_at(S, P, Ua, tau, S->t0 + tau, Ph, &dg);
     if (tau > dg.tau_max) {
       if (++nres > 8) { st = -3; break; }
       tau = P->cfl * dg.tau_max;
@@ -1229,7 +1375,7 @@ int or_step(const or_setup *S, const or_params *P, double *U, double dt_cap, dou
     }
     if (st) break;
     for (long q = 0; q < M; ++q) Ub[q] = 0.75 * U[q] + 0.25 * Ph[q];
-    st = or_stage(S, P, Ub, tau, Ph, &dg);
+    st = stage_at(S, P, Ub, tau, S->t0 + 0.5 * tau, Ph, &dg);
     if (tau > dg.tau_max) {
       if (++nres > 8) { st = -3; break; }
       tau = P->cfl * dg.tau_max;

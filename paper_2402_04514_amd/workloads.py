@@ -153,13 +153,15 @@ def sod(cells: int = 200, gamma: float = GAMMA) -> Workload:
 
 
 def vortex_exact(x: np.ndarray, t: float, beta=5.0, x0=(-1.0, -1.0), uinf=(1.0, 1.0),
-                 gamma=GAMMA, lo=-5.0, hi=5.0) -> np.ndarray:
-    """Isentropic vortex at time t, periodically wrapped on [lo, hi)^2."""
+                 gamma=GAMMA, lo=-5.0, hi=5.0, periodic=True) -> np.ndarray:
+    """Isentropic vortex at time t, periodically wrapped on [lo, hi)^2 (or in
+    free space with periodic=False)."""
     L = hi - lo
     xb = np.empty_like(x)
     for e in range(2):
         xb[:, e] = x[:, e] - x0[e] - t * uinf[e]
-        xb[:, e] = (xb[:, e] - lo) % L + lo
+        if periodic:
+            xb[:, e] = (xb[:, e] - lo) % L + lo
     r2 = xb[:, 0] ** 2 + xb[:, 1] ** 2
     T = 1.0 - (gamma - 1.0) * beta ** 2 / (8.0 * gamma * math.pi ** 2) * np.exp(1.0 - r2)
     rho = T ** (1.0 / (gamma - 1.0))

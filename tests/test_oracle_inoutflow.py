@@ -1,0 +1,168 @@
+"""Pins of the oracle's sub- and supersonic in/outflow boundary data
+(Sec. 4.1: eq. supersonic_inoutflow and eq. characteristics) and of the
+time-dependent Dirichlet data taken from the isentropic vortex (Sec. 6.2 and
+6.3: boundary data set to the exact solution at the node and the time).
+
+* Supersonic normal flow: the state is the data (inflow) or U_i (outflow),
+  as eq. supersonic_inoutflow.
+* Subsonic normal flow: the characteristic variables of eq. characteristics
+  of the constructed state equal the data's for the incoming characteristics
+  (speed v_n - a, and v_n, v_n where v_n <= 0) and U_i's for the others; the
+  state is admissible.  Data equal to U_i give U_i.
+* On the inflow problem (every face supersonic) the kind gives the
+  supersonic kind's result bit for bit.
+* The vortex moving out of the box across its top and right edges (the setting
+  of Sec. 6.3): with exact Dirichlet data on every face (strategy (a)) and
+  with in/outflow faces fed the exact data (strategy (b)) the limited Q1
+  scheme converges at second order (context: Table ErrorBoundaryConditions,
+  rates about 2 for (a) and (b)).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2402_04514_amd import workloads as W
+
+from test_oracle_scheme import _l1
+
+G = 1.4
+G53 = 5.0 / 3.0
+
+
+def _prim(U, g):
+    rho = U[0]
+    v = U[1:-1] / rho
+    p = (g - 1.0) * (U[-1] - 0.5 * rho * np.dot(v, v))
+    return rho, v, p
+
+
+def _cons(rho, v, p, g):
+    return np.concatenate([[rho], rho * v, [p / (g - 1.0) + 0.5 * rho * np.dot(v, v)]])
+
+
+def _characteristics(U, n, g):
+    """eq. characteristics: R1 = v_n - 2a/(g-1), R2 = p / rho^g, R3 = v - v_n n,
+    R4 = v_n + 2a/(g-1)."""
+    rho, v, p = _prim(U, g)
+    vn = np.dot(v, n)
+    a = math.sqrt(g * p / rho)
+    return vn - 2 * a / (g - 1), p / rho ** g, v - vn * n, vn + 2 * a / (g - 1)
+
+
+def _random_state(rng, dim, g, speed):
+    rho = rng.uniform(0.3, 2.0)
+    p = rng.uniform(0.3, 3.0)
+    v = rng.normal(size=dim)
+    v *= speed / np.linalg.norm(v)
+    return _cons(rho, v, p, g)
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+@pytest.mark.parametrize("g", [G, G53])
+def test_supersonic_branches(oracle, dim, g):
+    rng = np.random.default_rng(10 + dim)
+    for _ in range(200):
+        n = rng.normal(size=dim)
+        n /= np.linalg.norm(n)
+        Ud = _random_state(rng, dim, g, 0.5)
+        rho = rng.uniform(0.3, 2.0)
+        p = rng.uniform(0.3, 3.0)
+        a = math.sqrt(g * p / rho)
+        sign = rng.choice([-1.0, 1.0])
+        v = sign * a * rng.uniform(1.0, 3.0) * n
+        if dim > 1:
+            t = rng.normal(size=dim)
+            v = v + (t - np.dot(t, n) * n)
+        Ui = _cons(rho, v, p, g)
+        Ug, st = oracle.inoutflow_state(g, Ui, Ud, n)
+        assert st == 0
+        assert np.array_equal(Ug, Ud if sign < 0 else Ui)
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+@pytest.mark.parametrize("g", [G, G53])
+def test_subsonic_characteristics(oracle, dim, g):
+    rng = np.random.default_rng(20 + dim)
+    checked = {True: 0, False: 0}
+    for _ in range(400):
+        n = rng.normal(size=dim)
+        n /= np.linalg.norm(n)
+        Ud = _random_state(rng, dim, g, rng.uniform(0.0, 1.0))
+        rho = rng.uniform(0.3, 2.0)
+        p = rng.uniform(0.3, 3.0)
+        a = math.sqrt(g * p / rho)
+        v = a * rng.uniform(-0.99, 0.99) * n
+        if dim > 1:
+            t = rng.normal(size=dim)
+            v = v + 0.7 * (t - np.dot(t, n) * n)
+        Ui = _cons(rho, v, p, g)
+        Ug, st = oracle.inoutflow_state(g, Ui, Ud, n)
+        vni = np.dot(v, n)
+        if st != 0:
+            continue  # no state with a positive sound speed: reported, not invented
+        rg, vg, pg = _prim(Ug, g)
+        assert rg > 0 and pg > 0
+        Ri, Rd, Rg = (_characteristics(X, n, g) for X in (Ui, Ud, Ug))
+        inflow = vni <= 0.0
+        expect = (Rd[0], Rd[1] if inflow else Ri[1], Rd[2] if inflow else Ri[2], Ri[3])
+        scale = max(abs(Ri[0]), abs(Ri[3]), 1.0)
+        assert abs(Rg[0] - expect[0]) <= 1e-12 * scale
+        assert abs(Rg[1] - expect[1]) <= 1e-12 * abs(expect[1])
+        assert np.all(np.abs(Rg[2] - expect[2]) <= 1e-12 * scale)
+        assert abs(Rg[3] - expect[3]) <= 1e-12 * scale
+        checked[inflow] += 1
+    assert checked[True] > 100 and checked[False] > 100
+    # data equal to the node's state give that state
+    Ui = _random_state(rng, dim, g, 0.3)
+    n = np.eye(dim)[0]
+    Ug, st = oracle.inoutflow_state(g, Ui, Ui, n)
+    assert st == 0 and np.allclose(Ug, Ui, rtol=1e-13, atol=0)
+
+
+def test_inoutflow_equals_supersonic_on_the_inflow_problem(oracle):
+    wl = W.inflow(60, dim=2, axis=0, cross=4)
+    ms = wl.mesh
+    bc5 = tuple(5 if b == W.BC_SUPERSONIC else b for b in ms.bc)
+    A = oracle.Mesh(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc, bstate=ms.bstate)
+    B = oracle.Mesh(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, bc5, bstate=ms.bstate)
+    Ua, ta, na = A.run_to(oracle.params(), wl.U0, 0.05)
+    Ub, tb, nb = B.run_to(oracle.params(), wl.U0, 0.05)
+    assert na == nb and ta == tb
+    assert np.array_equal(Ua, Ub)
+
+
+def vortex_box(oracle, n, M, bc, far=False, g=G53, x0=(2.0, 2.0)):
+    """The vortex of Sec. 6.2 (beta 5, rho_inf = p_inf = 1) moving with
+    u_inf = (M, M) on [-5, 5]^2, Q1, with every face of kind bc fed the
+    exact solution (or the far-field state if far)."""
+    ms = W.MeshSpec(2, 1, (n, n), (-5.0, -5.0), (5.0, 5.0), (bc,) * 4)
+    x, _ = W.node_coords(ms)
+    U0 = W.vortex_exact(x, 0.0, x0=x0, uinf=(M, M), gamma=g, periodic=False)
+    vp = (5.0, x0[0], x0[1], M, M, g)
+    if far:
+        Uf = W.to_conserved(np.array([1.0]), np.array([[M], [M]]), np.array([1.0]), g)[:, 0]
+        mesh = oracle.Mesh(2, 1, ms.cells, ms.lo, ms.hi, ms.bc, bstate=[Uf] * 4)
+    else:
+        mesh = oracle.Mesh(2, 1, ms.cells, ms.lo, ms.hi, ms.bc, vortex=vp)
+    return ms, mesh, U0
+
+
+@pytest.mark.parametrize("M,bc", [(2.0, 3), (2.0, 5), (1.0, 5)])
+def test_vortex_leaving_the_box_converges_with_exact_data(oracle, M, bc):
+    """Strategies (a) (Dirichlet, bc 3) and (b) (in/outflow with exact data,
+    bc 5) of Sec. 6.3 at vortex speeds M = 2 (supersonic outflow) and M = 1
+    (subsonic outflow on the top and right edges: the characteristic
+    construction): the vortex starts at (2, 2) and has moved its core across
+    the top right corner region by t = 1.5 / M.  Measured rates 1.75 and 1.9
+    at M = 2, 1.5 and 1.73 at M = 1 (pre-asymptotic, rising)."""
+    tf = 1.5 / M
+    errs = []
+    for n in (16, 32, 64):
+        ms, mesh, U0 = vortex_box(oracle, n, M, bc)
+        prm = oracle.params(gamma=G53)
+        U, t, _ = mesh.run_to(prm, U0, tf)
+        Uex = W.vortex_exact(mesh.coords(), tf, x0=(2.0, 2.0), uinf=(M, M), gamma=G53, periodic=False)
+        errs.append(_l1(mesh, U, Uex))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert rates[0] < rates[1] and 1.6 < rates[1] < 2.4, (errs, rates)

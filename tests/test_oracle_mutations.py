@@ -17,16 +17,17 @@ SETUP, PHYS, SCHEME = T + "test_oracle_setup.py", T + "test_oracle_physics.py", 
 
 BND = T + "test_oracle_boundary.py"
 VISC = T + "test_oracle_viscosity.py"
+INOUT = T + "test_oracle_inoutflow.py"
 
 MUTANTS = {
     # name: (original text, planted text, pin files that must fail)
-    "supersonic_inflow_keeps_state": ("if (un < -a) {\n      for (int c = 0; c < S->m; ++c) Ug[c] = S->bstate[f][c];",
-                                      "if (un < -1e300) {\n      for (int c = 0; c < S->m; ++c) Ug[c] = S->bstate[f][c];",
+    "supersonic_inflow_keeps_state": ("if (un < -a) {\n      data_state(S, f, i, t, Ug);",
+                                      "if (un < -1e300) {\n      data_state(S, f, i, t, Ug);",
                                       [BND + "::test_supersonic_inflow_converges_to_riemann_fan"]),
     "supersonic_normal_sign": ("un += (Ui[1 + e] / Ui[0]) * cb[e] / nn;", "un -= (Ui[1 + e] / Ui[0]) * cb[e] / nn;",
                                [BND]),
-    "dirichlet_other_face": ("for (int c = 0; c < S->m; ++c) Ug[c] = S->bstate[f][c];\n  } else if",
-                             "for (int c = 0; c < S->m; ++c) Ug[c] = S->bstate[f ^ 1][c];\n  } else if",
+    "dirichlet_other_face": ("for (int c = 0; c < S->m; ++c) Ud[c] = S->bstate[f][c];",
+                             "for (int c = 0; c < S->m; ++c) Ud[c] = S->bstate[f ^ 1][c];",
                              [BND + "::test_dirichlet_inflow_equals_supersonic"]),
     "bar_state_sign": ("(fk[q] - fj[q]) / (2.0 * dij[k])", "(fj[q] - fk[q]) / (2.0 * dij[k])",
                        [SCHEME + "::test_low_order_update_inside_unrelaxed_bounds"]),
@@ -92,6 +93,13 @@ MUTANTS = {
     "q3_quadrature_weights_swapped": ("S->wq[0] = S->wq[3] = 0.5 * wo; S->wq[1] = S->wq[2] = 0.5 * wi;",
                                       "S->wq[0] = S->wq[3] = 0.5 * wi; S->wq[1] = S->wq[2] = 0.5 * wo;",
                                       [SETUP + "::test_q3_1d_closed_form"]),
+    "inoutflow_entropy_side_flipped": ("const int in23 = vni <= 0.0;", "const int in23 = vni >= 0.0;",
+                                       [INOUT + "::test_subsonic_characteristics"]),
+    "inoutflow_outgoing_invariant_from_data": ("const double R4 = vni + 2.0 * ai / (g - 1.0);",
+                                               "const double R4 = vnd + 2.0 * ad / (g - 1.0);",
+                                               [INOUT + "::test_subsonic_characteristics"]),
+    "vortex_data_frozen_in_time": ("vortex_at(S->vortex, x, t, Ud);", "vortex_at(S->vortex, x, 0.0, Ud);",
+                                   [INOUT + "::test_vortex_leaving_the_box_converges_with_exact_data"]),
     "ev_normalizer_not_abs_sum": ("D += fabs(grad[q]) * fabs(Sk[q]);", "D += fabs(grad[q] * Sk[q]) * 0.5;",
                                   [SCHEME + "::test_vortex_convergence"]),
 }
