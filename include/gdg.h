@@ -46,7 +46,8 @@ typedef enum {
   GDG_E_NOMEM = -4,        /* workspace smaller than gdg_workspace_bytes() */
   GDG_E_DEVICE = -5,       /* a HIP runtime call failed */
   GDG_E_BUDGET = -6,       /* a request can never fit the server's memory pool */
-  GDG_E_BOUNDARY = -7      /* a node of a GDG_BC_SUPERSONIC face saw subsonic normal flow */
+  GDG_E_BOUNDARY = -7      /* no boundary state: subsonic normal flow at a GDG_BC_SUPERSONIC face,
+                              or no admissible characteristic state at a GDG_BC_INOUTFLOW face */
 } gdg_status;
 
 /* Boundary kinds per box face (Sec. 4.1), with n the outward unit normal
@@ -54,21 +55,37 @@ typedef enum {
  *  - OUTFLOW: the supersonic-outflow branch U^d := U_i of
  *    eq. supersonic_inoutflow ("do nothing");
  *  - SLIP: eq. slip_boundary, the normal momentum reflected;
- *  - DIRICHLET: U^d := the face's data bc_state[f] (Sec. 4.1, Dirichlet
- *    boundary conditions; data constant in space and time);
- *  - SUPERSONIC: eq. supersonic_inoutflow, U^d := bc_state[f] where
- *    u_i.n < -a_i (inflow) and U^d := U_i where u_i.n >= a_i (outflow).  In
- *    the subsonic range between, the paper blends in the characteristic
- *    construction of another work, which this library does not provide: a
- *    step that meets it fails with GDG_E_BOUNDARY;
+ *  - DIRICHLET: U^d := the face's data (Sec. 4.1, Dirichlet boundary
+ *    conditions): bc_state[f], or the isentropic vortex at the node and the
+ *    stage time (gdg_mesh_desc.data_kind);
+ *  - SUPERSONIC: eq. supersonic_inoutflow, U^d := the data where
+ *    u_i.n < -a_i (inflow) and U^d := U_i where u_i.n >= a_i (outflow); a
+ *    step that meets subsonic normal flow fails with GDG_E_BOUNDARY;
+ *  - INOUTFLOW: sub- and supersonic in/outflow: eq. supersonic_inoutflow
+ *    where |u_i.n| >= a_i, and in the subsonic range the state whose
+ *    characteristic variables of eq. characteristics are those of the data for
+ *    the incoming characteristics (speed <= 0 at U_i) and those of U_i for
+ *    the others; if that state has no positive sound speed the step fails
+ *    with GDG_E_BOUNDARY;
  *  - PERIODIC: must be set on both faces of an axis. */
 typedef enum {
   GDG_BC_PERIODIC = 0,
   GDG_BC_OUTFLOW = 1,
   GDG_BC_SLIP = 2,
   GDG_BC_DIRICHLET = 3,
-  GDG_BC_SUPERSONIC = 4
+  GDG_BC_SUPERSONIC = 4,
+  GDG_BC_INOUTFLOW = 5
 } gdg_bc;
+
+/* Source of the data U^d of the DIRICHLET, SUPERSONIC and INOUTFLOW faces. */
+typedef enum {
+  GDG_DATA_CONSTANT = 0, /* bc_state[f], constant in space and time */
+  GDG_DATA_VORTEX = 1    /* the isentropic vortex of Sec. 6.2 at the node and
+                            the stage time (2D): vortex[] = beta, x0 (2),
+                            u_inf (2), gamma of the data; free space (no
+                            periodic images).  The SSP-RK3 stages take their
+                            data at t, t + tau and t + tau / 2. */
+} gdg_data_kind;
 
 /* GDG_LOW_ORDER: eq. cijdijscheme only.  GDG_HIGH_ORDER: eq. HighScheme
  * unlimited.  GDG_LIMITED: eq. LimitedScheme with the bounds of
@@ -89,10 +106,12 @@ typedef enum { GDG_FP64 = 0, GDG_MIXED = 1 } gdg_precision;
 
 /* Uniform Cartesian mesh of cells[0] x cells[1] x cells[2] cells over the box
  * [lo, hi] (only the first dim entries are read), Q_degree elements with
- * degree 1 or 2, dim 1..3, bc[2*dim] boundary kinds.  bc_state[f] holds the
- * conserved data (rho, momentum, E: the first dim+2 entries) of face f for
- * the DIRICHLET and SUPERSONIC kinds; it must be admissible (rho > 0,
- * eps > 0) on those faces and is ignored elsewhere. */
+ * degree 1 or 2 in dim 1..3 and degree 3 in dim 1 and 2, bc[2*dim] boundary
+ * kinds.  With data_kind GDG_DATA_CONSTANT, bc_state[f] holds the conserved
+ * data (rho, momentum, E: the first dim+2 entries) of face f for the
+ * DIRICHLET, SUPERSONIC and INOUTFLOW kinds; it must be admissible (rho > 0,
+ * eps > 0) on those faces and is ignored elsewhere.  With GDG_DATA_VORTEX
+ * the data of those faces come from the vortex (vortex[]). */
 typedef struct {
   int32_t dim;
   int32_t degree;
@@ -101,10 +120,13 @@ typedef struct {
   double hi[3];
   int32_t bc[6];
   double bc_state[6][5];
+  int32_t data_kind;  /* gdg_data_kind */
+  int32_t reserved;
+  double vortex[6];
 } gdg_mesh_desc;
 
 /* Scheme constants.  gdg_default_params() gives the paper's values:
- * gamma 1.4, Cr 0.5 (eq. MaxCFLdt), c_ev 1 / 0.5 for k = 1 / 2 (Sec. 5.2),
+ * gamma 1.4, Cr 0.5 (eq. MaxCFLdt), c_ev 1 / 0.5 / 0.25 for k = 1 / 2 / 3 (Sec. 5.2),
  * c_k 1 (eq. ViscMin), c_r 4 and p_r 1.5 (eq. ViscMinConst2), two limiter
  * passes (Sec. 6.1), the limited scheme, FP64. */
 typedef struct {

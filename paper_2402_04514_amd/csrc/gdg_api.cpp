@@ -56,17 +56,19 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 bool validate(const gdg_mesh_desc *m, const gdg_params *p, std::string *err) {
   if (!m || !p) { *err = "null argument"; return false; }
   if (m->dim < 1 || m->dim > 3) { *err = "dim must be 1, 2 or 3"; return false; }
-  if (m->degree < 1 || m->degree > 2) { *err = "degree must be 1 or 2"; return false; }
+  if (m->degree < 1 || m->degree > 3) { *err = "degree must be 1, 2 or 3"; return false; }
+  if (m->degree == 3 && m->dim == 3) { *err = "degree 3 is built for dim 1 and 2"; return false; }
   int64_t ncells = 1;
   for (int e = 0; e < m->dim; ++e) {
     if (m->cells[e] < 1) { *err = "cells must be >= 1"; return false; }
     if (!(m->hi[e] > m->lo[e])) { *err = "hi must exceed lo"; return false; }
     int b0 = m->bc[2 * e], b1 = m->bc[2 * e + 1];
     for (int b : {b0, b1})
-      if (b < GDG_BC_PERIODIC || b > GDG_BC_SUPERSONIC) { *err = "unknown boundary kind"; return false; }
+      if (b < GDG_BC_PERIODIC || b > GDG_BC_INOUTFLOW) { *err = "unknown boundary kind"; return false; }
     for (int side = 0; side < 2; ++side) {
       const int f = 2 * e + side;
-      if (m->bc[f] != GDG_BC_DIRICHLET && m->bc[f] != GDG_BC_SUPERSONIC) continue;
+      if (m->bc[f] != GDG_BC_DIRICHLET && m->bc[f] != GDG_BC_SUPERSONIC && m->bc[f] != GDG_BC_INOUTFLOW) continue;
+      if (m->data_kind == GDG_DATA_VORTEX) continue;  // checked below
       // the face's data must lie in A (eq. AddSet)
       const double *V = m->bc_state[f];
       double m2 = 0.0;
@@ -86,6 +88,25 @@ bool validate(const gdg_mesh_desc *m, const gdg_params *p, std::string *err) {
       return false;
     }
     ncells *= m->cells[e];
+  }
+  if (m->data_kind != GDG_DATA_CONSTANT && m->data_kind != GDG_DATA_VORTEX) {
+    *err = "unknown boundary data kind";
+    return false;
+  }
+  if (m->data_kind == GDG_DATA_VORTEX) {
+    // the vortex of Sec. 6.2: beta, x0, u_inf, gamma; its density is positive
+    // where 1 - (gamma-1) beta^2 e / (8 gamma pi^2) > 0 (the core, r = 0)
+    const double *v = m->vortex;
+    const double pi = 3.14159265358979323846;
+    bool ok = m->dim == 2;
+    for (int k = 0; k < 6; ++k) ok = ok && std::isfinite(v[k]);
+    ok = ok && v[0] >= 0.0 && v[5] > 1.0 && v[5] <= 5.0 / 3.0 + 1e-12;
+    ok = ok && 1.0 - (v[5] - 1.0) * v[0] * v[0] * std::exp(1.0) / (8.0 * v[5] * pi * pi) > 0.0;
+    if (!ok) {
+      *err = "vortex boundary data need a 2D mesh, finite parameters, beta >= 0, gamma in (1, 5/3] and a "
+             "positive core density";
+      return false;
+    }
   }
   int nloc = 1;
   for (int e = 0; e < m->dim; ++e) nloc *= m->degree + 1;
@@ -422,9 +443,24 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
       return GDG_E_INVALID;
     }
   }
+  const bool data_faces = mesh->data_kind == GDG_DATA_CONSTANT;
   for (int f = 0; f < 2 * mesh->dim; ++f)
-    if (A.bc[f] == GDG_BC_DIRICHLET || A.bc[f] == GDG_BC_SUPERSONIC)
+    if (data_faces &&
+        (A.bc[f] == GDG_BC_DIRICHLET || A.bc[f] == GDG_BC_SUPERSONIC || A.bc[f] == GDG_BC_INOUTFLOW))
       for (int q = 0; q < L.M; ++q) T->bstate[f][q] = mesh->bc_state[f][q];
+  {
+    // Gauss-Lobatto nodes on [0, 1], as in gdg_node_coords
+    const double r5 = 0.5 / std::sqrt(5.0);
+    const double x1[4] = {0.0, 1.0, 0.0, 0.0}, x2[4] = {0.0, 0.5, 1.0, 0.0}, x3[4] = {0.0, 0.5 - r5, 0.5 + r5, 1.0};
+    const double *xg = mesh->degree == 1 ? x1 : (mesh->degree == 2 ? x2 : x3);
+    for (int k = 0; k < 4; ++k) T->xg[k] = xg[k];
+  }
+  A.vortex_data = mesh->data_kind == GDG_DATA_VORTEX ? 1 : 0;
+  for (int k = 0; k < 6; ++k) A.vx[k] = mesh->vortex[k];
+  for (int e = 0; e < 3; ++e) {
+    A.lo[e] = e < mesh->dim ? mesh->lo[e] : 0.0;
+    A.hx[e] = h[e];
+  }
   std::memset(&ctx->hctl, 0, sizeof(Ctl));
   hipError_t e1 = hipMemcpyAsync(ctx->dref, T, sizeof(RefTables), hipMemcpyHostToDevice, ctx->stream);
   hipError_t e2 = hipMemcpyAsync(A.ctl, &ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream);
@@ -467,8 +503,9 @@ gdg_status gdg_node_coords(const gdg_ctx *ctx, double *xyz) {
   if (!ctx || !xyz) return GDG_E_INVALID;
   const gdg_mesh_desc &m = ctx->mesh;
   const int d = m.dim, nb = m.degree + 1, nloc = ctx->A.nloc;
-  const double xg2[3] = {0.0, 0.5, 1.0}, xg1[2] = {0.0, 1.0};
-  const double *xg = m.degree == 1 ? xg1 : xg2;
+  const double r5 = 0.5 / std::sqrt(5.0);
+  const double xg2[3] = {0.0, 0.5, 1.0}, xg1[2] = {0.0, 1.0}, xg3[4] = {0.0, 0.5 - r5, 0.5 + r5, 1.0};
+  const double *xg = m.degree == 1 ? xg1 : (m.degree == 2 ? xg2 : xg3);
   for (int64_t i = 0; i < ctx->A.N; ++i) {
     int64_t K = i / nloc;
     int a = (int)(i % nloc);

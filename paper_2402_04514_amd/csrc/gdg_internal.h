@@ -111,6 +111,7 @@ struct RefTables {
   // set-up: U (dim+2), velocity (dim), p, a, p^-alpha, f(s), s~, 1/p
   double bstate[6][kMaxD + 2];
   double bnode[6][2 * kMaxD + 8];
+  double xg[4];  // Gauss-Lobatto nodes on [0, 1] (node coordinates of time-dependent boundary data)
 };
 
 // Everything a kernel needs, passed by value.
@@ -120,6 +121,11 @@ struct KArgs {
   int64_t cells[3];
   int32_t bc[6];
   int32_t bcbits;   // the boundary kind of face f in bits 3f..3f+2
+  // data of the Dirichlet-type faces from the isentropic vortex (beta, x0,
+  // u_inf, gamma) at the node and the stage time instead of bnode
+  int32_t vortex_data;
+  double vx[6];
+  double lo[3], hx[3];  // box corner and cell sizes (node coordinates)
   double gamma, cfl, c_ev, c_k, pk, c_r, p_r, vol;
   double alpha, inv_alpha;
   int32_t ipow;     // > 0: 1/alpha equals this integer, the p* power is taken by multiplies

@@ -467,15 +467,41 @@ __device__ __forceinline__ double *node_buffer(const KArgs &A, int stage) {
 }
 
 // Node record of row i from its state V (and the admissibility flag).
+// Record writes of a row block through LDS.  A lane's record would otherwise
+// go out as stores 128 (or 64, 32) bytes apart from its neighbour lane's, one
+// cache line per lane and instruction; staged in LDS, the block's records
+// (consecutive rows, so one contiguous range) leave as whole 16-byte chunks
+// of consecutive addresses.  The staging rows are padded by one double so
+// that the lanes' LDS writes spread over the banks.
+constexpr int kStageDoubles = kBlockThreads * (kNodeStride + 1);
+
+template <int S>
+__device__ __forceinline__ double *stage_row(double *stage, int lane) {
+  return stage + lane * (S + 1);
+}
+
+// Stores the staged records of rows row0 .. row0 + nrows - 1 (S doubles each,
+// the pad values included) to dst.  Every lane of the wavefront must call it.
+template <int S>
+__device__ __forceinline__ void stage_flush(double *stage, double *dst, int64_t row0, int nrows) {
+  __syncthreads();  // the lanes' LDS writes before the block's reads
+  double2 *out = reinterpret_cast<double2 *>(dst + (size_t)row0 * S);
+  const int chunks = nrows * S / 2;
+  for (int c = threadIdx.x; c < chunks; c += kBlockThreads) {
+    const int r = (2 * c) / S, col = (2 * c) % S;
+    const double *v = stage + r * (S + 1) + col;
+    out[c] = make_double2(v[0], v[1]);
+  }
+  __syncthreads();  // the staging area may be reused
+}
+
+// The node record of state V into a staging row (and the admissibility flag).
 template <int D>
-__device__ __forceinline__ void store_node(const KArgs &A, double *nd, int64_t i, const double *V) {
+__device__ __forceinline__ void stage_node(const KArgs &A, double *row, const double *V) {
   double W[D + 6];
   if (!node_fields<D>(A, V, W)) atomicOr(&A.ctl->bad_flag, 1);
-  double r[2 * (D + 4)];
-  for (int c = 0; c < D + 2; ++c) r[c] = V[c];
-  for (int k = 0; k < D + 6; ++k) r[D + 2 + k] = W[k];
-  double2 *o = reinterpret_cast<double2 *>(nd + (size_t)i * kNodeStride);
-  for (int k = 0; k < D + 4; ++k) o[k] = make_double2(r[2 * k], r[2 * k + 1]);
+  for (int c = 0; c < D + 2; ++c) row[c] = V[c];
+  for (int k = 0; k < D + 6; ++k) row[D + 2 + k] = W[k];
 }
 
 // Set-up: the node fields of each face's Dirichlet data, computed by the same
@@ -484,9 +510,9 @@ __device__ __forceinline__ void store_node(const KArgs &A, double *nd, int64_t i
 template <int D>
 __global__ void k_bnodes(KArgs A, RefTables *T) {
   const int f = threadIdx.x;
-  if (f >= 2 * D) return;
+  if (f >= 2 * D || A.vortex_data) return;  // time-dependent data: evaluated where used
   const int kind = (A.bcbits >> (3 * f)) & 7;
-  if (kind != GDG_BC_DIRICHLET && kind != GDG_BC_SUPERSONIC) return;
+  if (kind != GDG_BC_DIRICHLET && kind != GDG_BC_SUPERSONIC && kind != GDG_BC_INOUTFLOW) return;
   double V[D + 2], W[D + 6];
   for (int q = 0; q < D + 2; ++q) V[q] = T->bstate[f][q];
   if (!node_fields<D>(A, V, W)) atomicOr(&A.ctl->bad_flag, 1);
@@ -494,17 +520,27 @@ __global__ void k_bnodes(KArgs A, RefTables *T) {
   for (int k = 0; k < D + 6; ++k) T->bnode[f][D + 2 + k] = W[k];
 }
 
+// Node records of rows row0 .. row0 + nrows - 1 from the SoA state U; every
+// lane of the wavefront calls it.
 template <int D>
-__device__ __forceinline__ void prim_row(const KArgs &A, const double *__restrict__ U, int64_t i, double *nd) {
-  if (i >= A.N) return;
-  double V[D + 2];
-  for (int c = 0; c < D + 2; ++c) V[c] = U[c * A.N + i];
-  store_node<D>(A, nd, i, V);
+__device__ __forceinline__ void prim_rows(const KArgs &A, const double *__restrict__ U, int64_t row0, int nrows,
+                                          double *nd) {
+  __shared__ double stage[kStageDoubles];
+  const int lane = threadIdx.x;
+  if (lane < nrows) {
+    const int64_t i = row0 + lane;
+    double V[D + 2];
+    for (int c = 0; c < D + 2; ++c) V[c] = U[c * A.N + i];
+    stage_node<D>(A, stage_row<kNodeStride>(stage, lane), V);
+  }
+  stage_flush<kNodeStride>(stage, nd, row0, nrows);
 }
 
 template <int D>
 __global__ __launch_bounds__(kBlockThreads) void k_prim(KArgs A, const double *__restrict__ U, int stage) {
-  prim_row<D>(A, U, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, node_buffer(A, stage));
+  const int64_t row0 = (int64_t)blockIdx.x * kBlockThreads;
+  const int nrows = (int)(A.N - row0 < kBlockThreads ? A.N - row0 : kBlockThreads);
+  prim_rows<D>(A, U, row0, nrows, node_buffer(A, stage));
 }
 
 template <int D>
@@ -547,17 +583,124 @@ __device__ __forceinline__ void load_rec(const double *__restrict__ rec, double 
   if (NV % 2) out[NV - 1] = rec[NV - 1];
 }
 
+// Time of a stage's boundary data: the stages of the Shu-Osher form sit at
+// t, t + tau and t + tau / 2 (tau is fixed in stage 1, whose data are at t).
+__device__ __forceinline__ double stage_time(const KArgs &A, int stage) {
+  const double t = A.ctl->t;
+  return stage == 0 ? t : (stage == 1 ? t + A.ctl->tau : t + 0.5 * A.ctl->tau);
+}
+
+// The isentropic vortex of Sec. 6.2 at dof i and time t (free space): with
+// xb = x_i - x0 - t u_inf, rho = (1 - (gamma-1) beta^2 / (8 gamma pi^2)
+// e^{1-r^2})^{1/(gamma-1)}, p = rho^gamma and
+// u = u_inf + beta / (2 pi) e^{(1-r^2)/2} (-xb_2, xb_1).  2D.
+template <int D, int DEG>
+__device__ __forceinline__ void vortex_state(const KArgs &A, int64_t i, double t, double *V) {
+#pragma clang fp contract(off)
+  constexpr int NB = DEG + 1;
+  constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
+  const int64_t K = i / NLOC;
+  const int a = (int)(i % NLOC);
+  const double x0 = A.lo[0] + ((double)(K % A.cells[0]) + A.ref->xg[a % NB]) * A.hx[0];
+  const double x1 = A.lo[1] + ((double)(K / A.cells[0]) + A.ref->xg[a / NB]) * A.hx[1];
+  const double beta = A.vx[0], g = A.vx[5];
+  const double xb0 = x0 - A.vx[1] - t * A.vx[3], xb1 = x1 - A.vx[2] - t * A.vx[4];
+  const double r2 = xb0 * xb0 + xb1 * xb1;
+  const double pi = 3.14159265358979323846;
+  const double T = 1.0 - (g - 1.0) * beta * beta / (8.0 * g * pi * pi) * exp(1.0 - r2);
+  const double rho = pow(T, 1.0 / (g - 1.0)), p = pow(rho, g);
+  const double fac = beta / (2.0 * pi) * exp(0.5 * (1.0 - r2));
+  const double u0 = A.vx[3] - fac * xb1, u1 = A.vx[4] + fac * xb0;
+  V[0] = rho;
+  V[1] = rho * u0;
+  V[2] = rho * u1;
+  V[D + 1] = p / (g - 1.0) + 0.5 * rho * (u0 * u0 + u1 * u1);
+}
+
+template <int D>
+__device__ __forceinline__ void node_from_state(const KArgs &A, const double *V, Node<D> &n);
+
+// Data U^d of face f at dof i and time t, as a node (state and fields): the
+// face's constant data (fields computed at set-up) or the vortex.
+template <int D, int DEG>
+__device__ __forceinline__ void data_node(const KArgs &A, int f, int64_t i, double t, Node<D> &d) {
+  if (D == 2 && A.vortex_data) {
+    double V[D + 2];
+    vortex_state<D, DEG>(A, i, t, V);
+    node_from_state<D>(A, V, d);
+    return;
+  }
+  const double *b = A.ref->bnode[f];
+  for (int q = 0; q < D + 2; ++q) d.U[q] = b[q];
+  for (int e = 0; e < D; ++e) d.u[e] = b[D + 2 + e];
+  d.p = b[2 * D + 2];
+  d.a = b[2 * D + 3];
+  d.pal = b[2 * D + 4];
+  d.fs = b[2 * D + 5];
+  d.st = b[2 * D + 6];
+  d.ip = b[2 * D + 7];
+}
+
+template <int D>
+__device__ __forceinline__ void node_from_state(const KArgs &A, const double *V, Node<D> &n) {
+  double W[D + 6];
+  if (!node_fields<D>(A, V, W)) atomicOr(&A.ctl->bad_flag, 1);
+  for (int q = 0; q < D + 2; ++q) n.U[q] = V[q];
+  for (int e = 0; e < D; ++e) n.u[e] = W[e];
+  n.p = W[D];
+  n.a = W[D + 1];
+  n.pal = W[D + 2];
+  n.fs = W[D + 3];
+  n.st = W[D + 4];
+  n.ip = W[D + 5];
+}
+
+// Sub- and supersonic in/outflow in the subsonic range: the state whose
+// characteristic variables (eq. characteristics) R1 = v_n - 2a/(gamma-1),
+// R2 = p/rho^gamma, R3 = v - v_n n, R4 = v_n + 2a/(gamma-1) are the data's
+// for the incoming characteristics and U_i's for the others (R1 always
+// incoming, R4 outgoing, R2 and R3 incoming where v_n <= 0); rebuilt from
+// v_n = (R1 + R4)/2, a = (gamma-1)(R4 - R1)/4, rho = (a^2/(gamma R2))^{1/(gamma-1)},
+// p = R2 rho^gamma.  Returns false if a <= 0.
+template <int D>
+__device__ __forceinline__ bool characteristic_state(const KArgs &A, const Node<D> &ni, const Node<D> &nd,
+                                                     const double *n, double vni, double *V) {
+  const double g = A.gamma;
+  double vnd = 0.0;
+  for (int e = 0; e < D; ++e) vnd += nd.u[e] * n[e];
+  const bool in23 = vni <= 0.0;
+  const double R1 = vnd - 2.0 * nd.a / (g - 1.0);
+  const double R4 = vni + 2.0 * ni.a / (g - 1.0);
+  const Node<D> &s = in23 ? nd : ni;
+  const double vns = in23 ? vnd : vni;
+  const double R2 = s.p / pow(s.U[0], g);
+  const double vn = 0.5 * (R1 + R4), a = 0.25 * (g - 1.0) * (R4 - R1);
+  if (!(a > 0.0)) return false;
+  const double rho = pow(a * a / (g * R2), 1.0 / (g - 1.0)), p = R2 * pow(rho, g);
+  double u2 = 0.0;
+  V[0] = rho;
+  for (int e = 0; e < D; ++e) {
+    const double v = (s.u[e] - vns * n[e]) + vn * n[e];
+    V[1 + e] = rho * v;
+    u2 += v * v;
+  }
+  V[D + 1] = p / (g - 1.0) + 0.5 * rho * u2;
+  return true;
+}
+
 // Boundary data of Sec. 4.1 for a boundary part of row i on box face f, with
-// outward unit normal n: outflow keeps U_i; slip reflects the normal momentum
-// (eq. slip_boundary; pressure, sound speed and entropy stay those of U_i);
-// Dirichlet takes the face's data; supersonic in/outflow
+// outward unit normal n, at time t: outflow keeps U_i; slip reflects the
+// normal momentum (eq. slip_boundary; pressure, sound speed and entropy stay
+// those of U_i); Dirichlet takes the face's data; supersonic in/outflow
 // (eq. supersonic_inoutflow) takes the data where u_i.n < -a_i and U_i where
 // u_i.n >= a_i, and flags the subsonic range between (bit 2 of bad_flag: the
-// step fails, its boundary construction is not provided).  BD = false: the
-// mesh has no face with data (the caller knows), and that code is left out.
-template <int D, bool BD = true>
-__device__ __forceinline__ void ghost_node(const KArgs &A, const Node<D> &ni, int f, const double *n,
-                                           Node<D> &gh) {
+// step fails); sub- and supersonic in/outflow builds the subsonic state from
+// the characteristic variables (bit 2 if it has no positive sound speed).
+// BD = false: the mesh has no face with data (the caller knows), and that
+// code is left out.
+template <int D, int DEG, bool BD = true>
+__device__ __forceinline__ void ghost_node(const KArgs &A, const Node<D> &ni, int f, const double *n, int64_t i,
+                                           double t, Node<D> &gh) {
   const int kind = (A.bcbits >> (3 * f)) & 7;
   gh = ni;
   if (kind == GDG_BC_SLIP) {
@@ -572,21 +715,23 @@ __device__ __forceinline__ void ghost_node(const KArgs &A, const Node<D> &ni, in
     }
   }
   if constexpr (BD) {
-    if (kind == GDG_BC_DIRICHLET || kind == GDG_BC_SUPERSONIC) {
+    if (kind == GDG_BC_DIRICHLET || kind == GDG_BC_SUPERSONIC || kind == GDG_BC_INOUTFLOW) {
       double un = 0.0;
       for (int e = 0; e < D; ++e) un += ni.u[e] * n[e];
       const bool data = kind == GDG_BC_DIRICHLET || un < -ni.a;
-      if (!data && !(un >= ni.a)) atomicOr(&A.ctl->bad_flag, 2);
+      const bool keep = kind != GDG_BC_DIRICHLET && un >= ni.a;
       if (data) {
-        const double *b = A.ref->bnode[f];
-        for (int q = 0; q < D + 2; ++q) gh.U[q] = b[q];
-        for (int e = 0; e < D; ++e) gh.u[e] = b[D + 2 + e];
-        gh.p = b[2 * D + 2];
-        gh.a = b[2 * D + 3];
-        gh.pal = b[2 * D + 4];
-        gh.fs = b[2 * D + 5];
-        gh.st = b[2 * D + 6];
-        gh.ip = b[2 * D + 7];
+        data_node<D, DEG>(A, f, i, t, gh);
+      } else if (!keep) {
+        if (kind == GDG_BC_SUPERSONIC) {
+          atomicOr(&A.ctl->bad_flag, 2);
+        } else {
+          Node<D> nd;
+          data_node<D, DEG>(A, f, i, t, nd);
+          double V[D + 2];
+          if (characteristic_state<D>(A, ni, nd, n, un, V)) node_from_state<D>(A, V, gh);
+          else atomicOr(&A.ctl->bad_flag, 2);
+        }
       }
     }
   }
@@ -624,6 +769,7 @@ __device__ __forceinline__ void sweep1_body(const KArgs &A, const double *__rest
   double tau_i = INFINITY;
   if (active) {
     const double g = A.gamma;
+    const double tstage = stage_time(A, stage);
     Node<D> ni;
     load_node<D>(nd, i, ni);
     // gradient of the shifted Harten entropy at U_i, rho_i f'(s_i) grad s(U_i)
@@ -701,7 +847,7 @@ __device__ __forceinline__ void sweep1_body(const KArgs &A, const double *__rest
       if (ghost) {
         double n[D];
         for (int e = 0; e < D; ++e) n[e] = c[e] * inv;
-        ghost_node<D, BD>(A, ni, meta >> 3, n, nr);
+        ghost_node<D, DEG, BD>(A, ni, meta >> 3, n, i, tstage, nr);
       }
       // d^L_ij from the lower index for a graph pair, so d_ij = d_ji bitwise;
       // the inside state on the left for a boundary part
@@ -799,6 +945,12 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
   constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
   __shared__ double rs[M][kBlockThreads];
   __shared__ int qs[kBlockThreads];
+  // The limiter records go out staged in LDS on 3D meshes and directly from
+  // each lane otherwise: measured, staging cut sweep 2 on the 128^3 Q1 blast
+  // from 5.0 to 3.5 ms but raised it on the 1024^2 Q2 quadrant from 2.3 to
+  // 6.4 ms (the same code; the cause is not identified).
+  constexpr bool kStaged = D == 3;
+  __shared__ double stage_lds[kStaged ? kStageDoubles : 1];
   double tau;
   if (!stage_tau(A, stage, &tau)) {
     if (stage > 0 && blk == 0 && threadIdx.x == 0 && A.ctl->cfl_flag == 0 && A.ctl->halt == 0) {
@@ -815,7 +967,8 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
   const bool active = lane < A.R && i < A.N;
   const int64_t N = A.N;
   const double g = A.gamma;
-  double *__restrict__ lr = A.Ld + (size_t)i * kLimStride;  // this row's limiter record
+  // this row's limiter record (staged, or in place)
+  double *lr = kStaged ? stage_row<kLimStride>(stage_lds, lane) : A.Ld + (size_t)i * kLimStride;
   Node<D> ni;
   int a = 0;
   if (active) {
@@ -860,7 +1013,7 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
         const double inc = 1.0 / nc;
         for (int e = 0; e < D; ++e) n[e] = c[e] * inc;
         Node<D> gh;
-        ghost_node<D>(A, ni, meta >> 3, n, gh);
+        ghost_node<D, DEG>(A, ni, meta >> 3, n, i, stage_time(A, stage), gh);
         double fj[M], fi[M];
         flux_dot<D>(gh.U, gh.u, gh.p, c, fj);
         flux_dot<D>(ni.U, ni.u, ni.p, c, fi);
@@ -888,8 +1041,15 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
       smin = fmin(smin, qj[2]);
       if (j == i) continue;
       const double dH = visc_high(A, d, Ni, qj[3], kind, hpk);
+      // U_j: from the neighbour's node record on 3D meshes, from the SoA state
+      // otherwise (of the record only these M values are needed here, and
+      // the SoA planes hold more neighbours per cache line); measured, the
+      // record is faster on the 128^3 Q1 blast (2.7 vs 3.5 ms), the planes on
+      // the 1024^2 Q2 quadrant
       double Uj[M];
-      load_rec<M>(nd + (size_t)j * kNodeStride, Uj);
+      if constexpr (D == 3) load_rec<M>(nd + (size_t)j * kNodeStride, Uj);
+      else
+        for (int q = 0; q < M; ++q) Uj[q] = sb.in[q * N + j];
       for (int q = 0; q < M; ++q) {
         const double du = Uj[q] - ni.U[q];
         dev += fabs(du);
@@ -924,7 +1084,7 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
     }
   }
   __syncthreads();
-  if (!active) return;
+  if (active) {
   // eq. HighScheme: M_K dU^H_K = tau r^H_K for the cell of row i, from LDS
   const int cellbase = lane - a;
   // A cell whose rows are all quiet has a zero residual and dU^H = 0 in every
@@ -950,6 +1110,9 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
       sb.out[q * N + i] = sb.ca == 0.0 ? V[q] : sb.ca * sb.Un[q * N + i] + sb.cb * V[q];
     if (!(V[0] > 0.0) || !(eps_of<D>(V) > 0.0)) atomicOr(&A.ctl->bad_flag, 1);
   }
+  }
+  const int64_t row0 = blk * A.R;
+  if constexpr (kStaged) stage_flush<kLimStride>(stage_lds, A.Ld, row0, (int)(N - row0 < A.R ? N - row0 : A.R));
 }
 
 template <int D, int DEG, bool MX>
@@ -975,10 +1138,10 @@ __device__ __forceinline__ void pair_flux(const KArgs &A, const double *Uj, cons
 
 // Boundary part of A_i^d for one ghost slot: tau (d^{d,H} - d^{d,L})(U^d - U_i),
 // with U^d built from the node of row i as in the sweeps.
-template <int D>
+template <int D, int DEG>
 __device__ __forceinline__ void ghost_flux(const KArgs &A, const double *__restrict__ nd, int64_t i, int64_t s,
                                            uint8_t meta, const double *Ui, double Ni, double hpk, double tau,
-                                           double d, double *Ab) {
+                                           double d, double t, double *Ab) {
   double c[D], nc2 = 0.0;
   for (int e = 0; e < D; ++e) {
     c[e] = A.mixed ? (double)A.cf[e * A.nslots + s] : A.c[e * A.nslots + s];
@@ -990,11 +1153,11 @@ __device__ __forceinline__ void ghost_flux(const KArgs &A, const double *__restr
   const int f = meta >> 3;
   const int kind = (A.bcbits >> (3 * f)) & 7;
   double Ug[D + 2];
-  if (kind == GDG_BC_DIRICHLET || kind == GDG_BC_SUPERSONIC) {
+  if (kind == GDG_BC_DIRICHLET || kind == GDG_BC_SUPERSONIC || kind == GDG_BC_INOUTFLOW) {
     // the data kinds decide from the node of row i, as the sweeps do
     Node<D> ni, gh;
     load_node<D>(nd, i, ni);
-    ghost_node<D>(A, ni, f, n, gh);
+    ghost_node<D, DEG>(A, ni, f, n, i, t, gh);
     for (int q = 0; q < D + 2; ++q) Ug[q] = gh.U[q];
   } else {
     // outflow and slip need U_i alone (the same arithmetic as ghost_node)
@@ -1024,27 +1187,26 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
   constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
   constexpr int NL = 2 * M + 5;  // limiter record: dU^H, U^L, bounds, 1/(kappa m), N
   using R = Rec<D>;
-  if (A.ctl->halt || A.ctl->cfl_flag) return;
+  if (A.ctl->halt || A.ctl->cfl_flag) return;  // the same for every block
+  __shared__ double stage_lds[kStageDoubles];  // the block's output records
   const int lane = threadIdx.x;
   const int64_t i = blk * A.R + lane;
-  if (lane >= A.R || i >= A.N) return;
-  const double *__restrict__ nd = node_buffer(A, stage);
   const int64_t N = A.N;
+  const int64_t row0 = blk * A.R;
+  const int nrows = (int)(N - row0 < A.R ? N - row0 : A.R);
+  const double *__restrict__ nd = node_buffer(A, stage);
+  // every lane reaches the record writes at the end (they are staged in LDS
+  // and stored by the whole wavefront); rows outside the block compute nothing
+  double V[M];
+  if (lane < nrows) {
   const double tau = A.ctl->tau;
   const int a = (int)(i % NLOC);
   if (pass == 1 && final_pass && A.accepted[i]) {
     // pass 1 accepted every pair and the boundary part of this row whole:
     // nothing is left to limit (every remaining flux is 0 A), and the result
     // is U^(1) itself
-    double V[M], O[M];
     load_rec<M>(A.U1d + (size_t)i * kU1Stride, V);
-    for (int q = 0; q < M; ++q) {
-      O[q] = sb.ca == 0.0 ? V[q] : sb.ca * sb.Un[q * N + i] + sb.cb * V[q];
-      sb.out[q * N + i] = O[q];
-    }
-    store_node<D>(A, node_buffer(A, stage + 1), i, O);
-    return;
-  }
+  } else {
   const double mi = A.ref->mlump[a];
   const double hpk = A.ref->hpk[a];
   double Ui[M], Li[M], dUi[M], lri[NL];
@@ -1084,7 +1246,7 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
     if (kind == SK_PAD) continue;
     const double d = A.dL[s];
     if (kind == SK_GHOST) {
-      ghost_flux<D>(A, nd, i, s, meta, Ui, Ni, hpk, tau, d, Ab);
+      ghost_flux<D, DEG>(A, nd, i, s, meta, Ui, Ni, hpk, tau, d, stage_time(A, stage), Ab);
       if (gslot < 0) gslot = s;
       continue;
     }
@@ -1148,10 +1310,9 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
     if (pass == 0) A.l1[gslot] = lb;
     allone = allone && lb == 1.0;
   }
-  double V[M];
   for (int q = 0; q < M; ++q) V[q] = Li[q] + acc[q] / mi;
   if (pass == 0) {
-    double *u1 = A.U1d + (size_t)i * kU1Stride;
+    double *u1 = stage_row<kU1Stride>(stage_lds, lane);
     for (int q = 0; q < M; ++q) u1[q] = V[q];
     A.accepted[i] = allone ? 1 : 0;
     wave_count_add(&A.ctl->limited_pairs, ncut);
@@ -1173,16 +1334,22 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
     }
     wave_count_add(&A.ctl->bound_violations, in ? 0u : 1u);
   }
+  }  // rows through the pair loop
+  }  // rows of the block
+  if (pass == 0) stage_flush<kU1Stride>(stage_lds, A.U1d, row0, nrows);
   if (final_pass) {
     // the stage output, and its node record for the next stage (the other
     // buffer: this pass still reads the stage input's records)
-    double O[M];
-    for (int q = 0; q < M; ++q) {
-      O[q] = sb.ca == 0.0 ? V[q] : sb.ca * sb.Un[q * N + i] + sb.cb * V[q];
-      sb.out[q * N + i] = O[q];
+    if (lane < nrows) {
+      double O[M];
+      for (int q = 0; q < M; ++q) {
+        O[q] = sb.ca == 0.0 ? V[q] : sb.ca * sb.Un[q * N + i] + sb.cb * V[q];
+        sb.out[q * N + i] = O[q];
+      }
+      if (!(V[0] > 0.0) || !(eps_of<D>(V) > 0.0)) atomicOr(&A.ctl->bad_flag, 1);
+      stage_node<D>(A, stage_row<kNodeStride>(stage_lds, lane), O);
     }
-    if (!(V[0] > 0.0) || !(eps_of<D>(V) > 0.0)) atomicOr(&A.ctl->bad_flag, 1);
-    store_node<D>(A, node_buffer(A, stage + 1), i, O);
+    stage_flush<kNodeStride>(stage_lds, node_buffer(A, stage + 1), row0, nrows);
   }
 }
 
@@ -1227,8 +1394,9 @@ __global__ __launch_bounds__(kBlockThreads) void kb_prim(const BatchList *L, int
   for_tiles(L, [&](const BatchEntry &E, int64_t blk) {
     if (E.A.ctl->halt || E.A.ctl->cfl_flag) return;
     if (E.A.scheme == 2 && E.A.passes > 0) return;  // cache written by the last limiter pass
-    if ((int)threadIdx.x < E.A.R)
-      prim_row<D>(E.A, E.sb[stage].in, blk * E.A.R + threadIdx.x, node_buffer(E.A, stage));
+    const int64_t row0 = blk * E.A.R;
+    const int nrows = (int)(E.A.N - row0 < E.A.R ? E.A.N - row0 : E.A.R);
+    prim_rows<D>(E.A, E.sb[stage].in, row0, nrows, node_buffer(E.A, stage));
   });
 }
 
@@ -1367,7 +1535,7 @@ static int stage_impl(const KArgs &A, const StageBufs &b, int stage, void *strea
   bool bd = false;
   for (int f = 0; f < 2 * D; ++f) {
     const int kind = (A.bcbits >> (3 * f)) & 7;
-    bd = bd || kind == GDG_BC_DIRICHLET || kind == GDG_BC_SUPERSONIC;
+    bd = bd || kind == GDG_BC_DIRICHLET || kind == GDG_BC_SUPERSONIC || kind == GDG_BC_INOUTFLOW;
   }
   prof_mark(prof, KID_SWEEP1, 0, stream);
   if (bd)
@@ -1398,8 +1566,10 @@ static int fill_impl(const KArgs &A, void *stream) {
   switch (A.dim * 10 + A.deg) {                                 \
     case 11: return FN<1, 1>(__VA_ARGS__);                      \
     case 12: return FN<1, 2>(__VA_ARGS__);                      \
+    case 13: return FN<1, 3>(__VA_ARGS__);                      \
     case 21: return FN<2, 1>(__VA_ARGS__);                      \
     case 22: return FN<2, 2>(__VA_ARGS__);                      \
+    case 23: return FN<2, 3>(__VA_ARGS__);                      \
     case 31: return FN<3, 1>(__VA_ARGS__);                      \
     case 32: return FN<3, 2>(__VA_ARGS__);                      \
     default: return -2;                                         \
@@ -1411,8 +1581,10 @@ int launch_stage(const KArgs &A, const StageBufs &b, int stage, void *stream, Pr
     switch (A.dim * 10 + A.deg) {
       case 11: return GDG_STAGE_MX(1, 1)(A, b, stage, stream, prof, need_prim);
       case 12: return GDG_STAGE_MX(1, 2)(A, b, stage, stream, prof, need_prim);
+      case 13: return GDG_STAGE_MX(1, 3)(A, b, stage, stream, prof, need_prim);
       case 21: return GDG_STAGE_MX(2, 1)(A, b, stage, stream, prof, need_prim);
       case 22: return GDG_STAGE_MX(2, 2)(A, b, stage, stream, prof, need_prim);
+      case 23: return GDG_STAGE_MX(2, 3)(A, b, stage, stream, prof, need_prim);
       case 31: return GDG_STAGE_MX(3, 1)(A, b, stage, stream, prof, need_prim);
       case 32: return GDG_STAGE_MX(3, 2)(A, b, stage, stream, prof, need_prim);
       default: return -2;
@@ -1423,8 +1595,10 @@ int launch_stage(const KArgs &A, const StageBufs &b, int stage, void *stream, Pr
   switch (A.dim * 10 + A.deg) {
     case 11: return GDG_STAGE_64(1, 1)(A, b, stage, stream, prof, need_prim);
     case 12: return GDG_STAGE_64(1, 2)(A, b, stage, stream, prof, need_prim);
+    case 13: return GDG_STAGE_64(1, 3)(A, b, stage, stream, prof, need_prim);
     case 21: return GDG_STAGE_64(2, 1)(A, b, stage, stream, prof, need_prim);
     case 22: return GDG_STAGE_64(2, 2)(A, b, stage, stream, prof, need_prim);
+    case 23: return GDG_STAGE_64(2, 3)(A, b, stage, stream, prof, need_prim);
     case 31: return GDG_STAGE_64(3, 1)(A, b, stage, stream, prof, need_prim);
     case 32: return GDG_STAGE_64(3, 2)(A, b, stage, stream, prof, need_prim);
     default: return -2;
@@ -1463,10 +1637,14 @@ int launch_batch_steps(int dim, int deg, int mixed, const BatchList *L, Ctl *sta
     case 111: return batch_impl<1, 1, true>(L, status, ksteps, grid, stream);
     case 120: return batch_impl<1, 2, false>(L, status, ksteps, grid, stream);
     case 121: return batch_impl<1, 2, true>(L, status, ksteps, grid, stream);
+    case 130: return batch_impl<1, 3, false>(L, status, ksteps, grid, stream);
+    case 131: return batch_impl<1, 3, true>(L, status, ksteps, grid, stream);
     case 210: return batch_impl<2, 1, false>(L, status, ksteps, grid, stream);
     case 211: return batch_impl<2, 1, true>(L, status, ksteps, grid, stream);
     case 220: return batch_impl<2, 2, false>(L, status, ksteps, grid, stream);
     case 221: return batch_impl<2, 2, true>(L, status, ksteps, grid, stream);
+    case 230: return batch_impl<2, 3, false>(L, status, ksteps, grid, stream);
+    case 231: return batch_impl<2, 3, true>(L, status, ksteps, grid, stream);
     case 310: return batch_impl<3, 1, false>(L, status, ksteps, grid, stream);
     case 311: return batch_impl<3, 1, true>(L, status, ksteps, grid, stream);
     case 320: return batch_impl<3, 2, false>(L, status, ksteps, grid, stream);

@@ -348,7 +348,7 @@ gdg_status flight_done(gdg_server *s, bool *done) {
 }
 
 bool desc_ok(const gdg_server_desc *d) {
-  return d && d->dim >= 1 && d->dim <= 3 && d->degree >= 1 && d->degree <= 2 &&
+  return d && d->dim >= 1 && d->dim <= 3 && d->degree >= 1 && d->degree <= 3 && !(d->degree == 3 && d->dim == 3) &&
          (d->precision == GDG_FP64 || d->precision == GDG_MIXED) && d->max_slots >= 1 &&
          d->max_slots <= kMaxBatch && d->steps_per_graph >= 1 && d->steps_per_graph <= 64;
 }

@@ -57,7 +57,7 @@ double integrate01(const Poly &a) {
 }
 
 void invert(int n, const double *A, double *Ai) {
-  double M[3][6];
+  double M[4][8];
   for (int r = 0; r < n; ++r)
     for (int c = 0; c < 2 * n; ++c) M[r][c] = c < n ? A[r * n + c] : (c - n == r ? 1.0 : 0.0);
   for (int k = 0; k < n; ++k) {
@@ -80,15 +80,22 @@ void invert(int n, const double *A, double *Ai) {
 
 struct Ref1D {
   int nb;
-  double M[3][3], Minv[3][3], Cs[3][3], w[3];
+  double M[4][4], Minv[4][4], Cs[4][4], w[4];
 };
 
 Ref1D make_ref1d(int deg) {
   Ref1D R;
   R.nb = deg + 1;
-  double xg[3] = {0.0, 0.5, 1.0};
+  // Gauss-Lobatto nodes on [0, 1]
+  double xg[4] = {0.0, 0.5, 1.0, 1.0};
   if (deg == 1) xg[1] = 1.0;
-  Poly phi[3];
+  if (deg == 3) {
+    const double r = 0.5 / std::sqrt(5.0);
+    xg[1] = 0.5 - r;
+    xg[2] = 0.5 + r;
+    xg[3] = 1.0;
+  }
+  Poly phi[4];
   for (int a = 0; a < R.nb; ++a) {
     Poly p;
     p.c[0] = 1.0;
@@ -96,7 +103,7 @@ Ref1D make_ref1d(int deg) {
       if (b != a) p = mul_linear(p, xg[b], 1.0 / (xg[a] - xg[b]));
     phi[a] = p;
   }
-  double C1[3][3];
+  double C1[4][4];
   for (int a = 0; a < R.nb; ++a) {
     R.w[a] = integrate01(phi[a]);
     for (int b = 0; b < R.nb; ++b) {
@@ -106,7 +113,7 @@ Ref1D make_ref1d(int deg) {
   }
   for (int a = 0; a < R.nb; ++a)
     for (int b = 0; b < R.nb; ++b) R.Cs[a][b] = 0.5 * (C1[a][b] - C1[b][a]);
-  double Mf[9], Mi[9];
+  double Mf[16], Mi[16];
   for (int a = 0; a < R.nb; ++a)
     for (int b = 0; b < R.nb; ++b) Mf[a * R.nb + b] = R.M[a][b];
   invert(R.nb, Mf, Mi);
@@ -126,8 +133,8 @@ void multi(int a, int nb, int *ai) {
 
 // Fills the reference tables of a uniform mesh with cell sizes h[0..dim-1].
 bool build_ref_tables(int dim, int deg, const double *h, RefTables *T, std::string *err) {
-  if (dim < 1 || dim > 3 || deg < 1 || deg > 2) {
-    *err = "dim must be 1..3 and degree 1..2";
+  if (dim < 1 || dim > 3 || deg < 1 || deg > 3 || (deg == 3 && dim == 3)) {
+    *err = "dim must be 1..3 and degree 1..3 (degree 3 in 1D and 2D)";
     return false;
   }
   std::memset(T, 0, sizeof(RefTables));

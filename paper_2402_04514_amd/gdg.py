@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libgdg.so")
 (GDG_OK, GDG_E_INVALID, GDG_E_INADMISSIBLE, GDG_E_CFL, GDG_E_NOMEM, GDG_E_DEVICE, GDG_E_BUDGET,
  GDG_E_BOUNDARY) = (0, -1, -2, -3, -4, -5, -6, -7)
 GDG_REQ_PENDING, GDG_REQ_RUNNING, GDG_REQ_DONE, GDG_REQ_FAILED = 0, 1, 2, 3
-GDG_BC_PERIODIC, GDG_BC_OUTFLOW, GDG_BC_SLIP, GDG_BC_DIRICHLET, GDG_BC_SUPERSONIC = 0, 1, 2, 3, 4
+GDG_BC_PERIODIC, GDG_BC_OUTFLOW, GDG_BC_SLIP, GDG_BC_DIRICHLET, GDG_BC_SUPERSONIC, GDG_BC_INOUTFLOW = 0, 1, 2, 3, 4, 5
+GDG_DATA_CONSTANT, GDG_DATA_VORTEX = 0, 1
 GDG_LOW_ORDER, GDG_HIGH_ORDER, GDG_LIMITED = 0, 1, 2
 GDG_FP64, GDG_MIXED = 0, 1
 (GDG_FIELD_STATE, GDG_FIELD_EV_N, GDG_FIELD_BOUNDS, GDG_FIELD_UL, GDG_FIELD_DUH,
@@ -38,7 +39,8 @@ class GdgError(RuntimeError):
 class gdg_mesh_desc(C.Structure):
     _fields_ = [("dim", C.c_int32), ("degree", C.c_int32), ("cells", C.c_int64 * 3),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("bc", C.c_int32 * 6),
-                ("bc_state", (C.c_double * 5) * 6)]
+                ("bc_state", (C.c_double * 5) * 6), ("data_kind", C.c_int32), ("reserved", C.c_int32),
+                ("vortex", C.c_double * 6)]
 
 
 class gdg_params(C.Structure):
@@ -133,9 +135,11 @@ def _check(st, ctx=None):
         raise GdgError(st, msg)
 
 
-def mesh_desc(dim, degree, cells, lo, hi, bc, bstate=None) -> gdg_mesh_desc:
-    """bstate: per face the conserved Dirichlet data of the DIRICHLET and
-    SUPERSONIC kinds (None, or None entries, elsewhere)."""
+def mesh_desc(dim, degree, cells, lo, hi, bc, bstate=None, vortex=None) -> gdg_mesh_desc:
+    """bstate: per face the conserved Dirichlet data of the DIRICHLET,
+    SUPERSONIC and INOUTFLOW kinds (None, or None entries, elsewhere); vortex:
+    (beta, x0_1, x0_2, u_1, u_2, gamma) to take that data from the isentropic
+    vortex instead."""
     m = gdg_mesh_desc()
     m.dim, m.degree = dim, degree
     for e in range(3):
@@ -147,6 +151,10 @@ def mesh_desc(dim, degree, cells, lo, hi, bc, bstate=None) -> gdg_mesh_desc:
         if bstate is not None and f < 2 * dim and bstate[f] is not None:
             for q, v in enumerate(bstate[f]):
                 m.bc_state[f][q] = float(v)
+    if vortex is not None:
+        m.data_kind = GDG_DATA_VORTEX
+        for k, v in enumerate(vortex):
+            m.vortex[k] = float(v)
     return m
 
 
@@ -272,11 +280,11 @@ class Solver:
     and whose stream is torch's current stream there (or ``stream``)."""
 
     def __init__(self, dim, degree, cells, lo, hi, bc, params: gdg_params | None = None,
-                 device="cuda:0", stream=None, bstate=None):
+                 device="cuda:0", stream=None, bstate=None, vortex=None):
         import torch
         self.torch = torch
         self.dim, self.m = dim, dim + 2
-        self.mesh = mesh_desc(dim, degree, cells, lo, hi, bc, bstate)
+        self.mesh = mesh_desc(dim, degree, cells, lo, hi, bc, bstate, vortex)
         self.params = params if params is not None else gdg_default_params(degree)
         self.device = torch.device(device)
         nbytes = gdg_workspace_bytes(self.mesh, self.params)
@@ -290,7 +298,7 @@ class Solver:
     @classmethod
     def from_spec(cls, ms, params=None, **kw):
         return cls(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc, params,
-                   bstate=getattr(ms, "bstate", None), **kw)
+                   bstate=getattr(ms, "bstate", None), vortex=getattr(ms, "vortex", None), **kw)
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -413,7 +421,8 @@ class Server:
         prm = params if params is not None else gdg_default_params(ms.degree)
         if params is None:
             prm.precision = self.desc.precision
-        mesh = mesh_desc(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc, getattr(ms, "bstate", None))
+        mesh = mesh_desc(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc, getattr(ms, "bstate", None),
+                         getattr(ms, "vortex", None))
         return gdg_server_submit(self.srv, mesh, prm, U0, t_final)
 
     def pump(self):

@@ -26,7 +26,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-BC_PERIODIC, BC_OUTFLOW, BC_SLIP, BC_DIRICHLET, BC_SUPERSONIC = 0, 1, 2, 3, 4
+BC_PERIODIC, BC_OUTFLOW, BC_SLIP, BC_DIRICHLET, BC_SUPERSONIC, BC_INOUTFLOW = 0, 1, 2, 3, 4, 5
 GAMMA = 1.4
 
 
@@ -41,6 +41,9 @@ class MeshSpec:
     # per box face: the conserved Dirichlet data U^d of the Dirichlet and
     # supersonic kinds (None elsewhere, or None for no such face)
     bstate: tuple | None = None
+    # (beta, x0_1, x0_2, u_1, u_2, gamma): the data of those faces from the
+    # isentropic vortex at the node and the time instead
+    vortex: tuple | None = None
 
     @property
     def nloc(self) -> int:

@@ -99,6 +99,43 @@ def test_vortex_convergence_to_t2(oracle):
     assert rates[0] > 1.5, (errs, rates)
 
 
+def test_vortex_q3_convergence_to_t2(oracle):
+    """Q3 (c_ev = 0.25, p_k = 0, 16 dofs per cell) on the periodic vortex to
+    t = 2 at 16^2 / 32^2 / 64^2 cells: the 16^2 limited run against the
+    oracle's, and fourth-order rates of the unlimited scheme and of the
+    limited scheme with the bounds relaxed by p_r = 1.  With the paper's
+    p_r = 1.5 the rescaled-entropy bound binds at every level here (measured
+    L1 1.4e-3, 3.1e-4, 1.0e-4): printed, not asserted beyond its decrease."""
+    errs = {}
+    variants = {"unlimited": {"scheme": gdg.GDG_HIGH_ORDER}, "limited": {}, "limited_pr1": {"p_r": 1.0}}
+    for name, over in variants.items():
+        for n in (16, 32, 64):
+            ms = W.MeshSpec(2, 3, (n, n), (-5.0, -5.0), (5.0, 5.0), (0,) * 4)
+            x, _ = W.node_coords(ms)
+            U0 = W.vortex_exact(x, 0.0)
+            p = gdg.gdg_default_params(3)
+            for a, b in over.items():
+                setattr(p, a, b)
+            S = gdg.Solver.from_spec(ms, p)
+            S.upload(U0)
+            st = S.run_to(2.0)
+            U = S.download()
+            S.close()
+            M = _mesh(oracle, ms)
+            errs[name, n] = l1_consolidated(U, W.vortex_exact(M.coords(), 2.0), M.lumped(), 2)
+            _say("vortex Q3 %d^2 %s: %d steps, L1 %.4e" % (n, name, st.steps, errs[name, n]))
+            if name != "unlimited":
+                assert st.bound_violations == 0
+            if name == "limited" and n == 16:
+                Uo, t_o, n_o = M.run_to(oracle.params(degree=3), U0, 2.0)
+                assert st.steps == n_o
+                _close(U, Uo, tol=1e-10, what="vortex Q3 16^2 at t = 2")
+    for name in variants:
+        rates = [math.log2(errs[name, a] / errs[name, b]) for a, b in ((16, 32), (32, 64))]
+        _say("vortex Q3 %s rates %s" % (name, rates))
+        assert min(rates) > (1.2 if name == "limited" else 3.3), (name, errs, rates)
+
+
 def _steps_fixed(ms, prm, U, dts):
     S = gdg.Solver.from_spec(ms, prm)
     S.upload(U)

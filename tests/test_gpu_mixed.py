@@ -54,7 +54,7 @@ def _admissible(U, dim):
 
 
 @pytest.mark.parametrize("name", ["sod_q1_40", "q1_2d_outflow_ragged", "q2_2d_slip", "q1_3d_mixed",
-                                  "vortex_q1_32"])
+                                  "vortex_q1_32", "q3_2d_slip_ragged"])
 def test_mixed_stage_fields(oracle, name):
     """One stage: U^L, dU^H and the stage output within 1e-5 of the scale per
     dof; tau and the bounds (FP64 parts) within FP32 effects on the state-free

@@ -86,6 +86,11 @@ CASES = {
     # whole x-lines of blocks: the 3D meshes swept tile by tile
     "q1_3d_tiled": lambda: quadrant_on(3, 1, (16, 6, 5), (2, 2, 1, 1, 0, 0), seed=41),
     "q2_3d_tiled": lambda: quadrant_on(3, 2, (4, 3, 3), (1,) * 6, seed=43),
+    # Q3 (1D and 2D): 16 dofs per cell, four cells per row block
+    "q3_1d_outflow": lambda: quadrant_on(1, 3, (13,), (1, 1), seed=51),
+    "q3_2d_slip_ragged": lambda: quadrant_on(2, 3, (7, 5), (2,) * 4, seed=53),
+    "q3_2d_periodic": lambda: quadrant_on(2, 3, (4, 6), (0,) * 4, seed=55),
+    "q3_2d_smooth_mixed": lambda: smooth_on(2, 3, (5, 4), (1, 1, 2, 2)),
 }
 
 
@@ -180,7 +185,7 @@ def test_scheme_modes(oracle, name, scheme):
 
 @pytest.mark.parametrize("c_k", [1.0, 0.5])
 @pytest.mark.parametrize("name", ["q1_3d_slip", "q1_3d_mixed", "q1_2d_mixed", "q2_2d_outflow", "q2_2d_slip",
-                                  "q2_3d_tiled"])
+                                  "q2_3d_tiled", "q3_2d_slip_ragged"])
 def test_high_order_without_entropy_viscosity(oracle, name, c_k):
     """c_ev = 0 makes d^H = d^min, independent of N_i: isolates the
     consistent-mass solve and the minimal viscosity of eq. ViscMin.  On Q2

@@ -1,8 +1,10 @@
 """CPU checks of the C-ABI library: it loads, exports every entry point that
 include/gdg.h declares, and its host-only calls (defaults, workspace sizing,
 validation) behave as documented.  No GPU work is issued here."""
-import os
+import pathlib
 import re
+import shutil
+import subprocess
 
 import ctypes as C
 
@@ -10,11 +12,11 @@ import pytest
 
 from paper_2402_04514_amd import gdg
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ROOT = pathlib.Path(__file__).resolve().parent.parent
 
 
 def declared():
-    src = open(os.path.join(ROOT, "include", "gdg.h")).read()
+    src = open(ROOT / "include" / "gdg.h").read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(gdg_[a-z_]+)\s*\(", src)))
 
@@ -50,7 +52,8 @@ def test_workspace_bytes_scale_with_mesh():
 
 @pytest.mark.parametrize("desc", [
     (4, 1, (8,), (0,), (1,), (1, 1)),           # dim out of range
-    (2, 3, (8, 8), (0, 0), (1, 1), (1,) * 4),   # degree out of range
+    (2, 4, (8, 8), (0, 0), (1, 1), (1,) * 4),   # degree out of range
+    (3, 3, (4, 4, 4), (0, 0, 0), (1, 1, 1), (1,) * 6),  # degree 3 is built for 1D and 2D
     (2, 1, (1, 8), (0, 0), (1, 1), (0, 0, 1, 1)),  # periodic axis with one cell
     (2, 1, (8, 8), (0, 0), (1, 1), (0, 1, 1, 1)),  # half-periodic axis
     (2, 1, (8, 8), (0, 0), (0, 1), (1,) * 4),   # empty box
@@ -70,11 +73,34 @@ def test_invalid_mesh_rejected(desc):
     assert ei.value.status == gdg.GDG_E_INVALID
 
 
-def test_mesh_desc_layout():
-    """The ctypes mirror of gdg_mesh_desc has the C layout of include/gdg.h."""
-    assert gdg.gdg_mesh_desc.bc.offset == 80
-    assert gdg.gdg_mesh_desc.bc_state.offset == 104
-    assert C.sizeof(gdg.gdg_mesh_desc) == 344
+STRUCTS = ("gdg_mesh_desc", "gdg_params", "gdg_stats", "gdg_server_desc", "gdg_request_info")
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every ctypes mirror has the size and field offsets that a C compiler
+    gives the structures of include/gdg.h."""
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gdg.h"', "int main(void) {"]
+    for name in STRUCTS:
+        lines.append('printf("%s sizeof %%zu\\n", sizeof(%s));' % (name, name))
+        for f, _ in getattr(gdg, name)._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (name, f, name, f))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", str(ROOT / "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    seen = 0
+    for line in filter(None, out):
+        name, field, value = line.split()
+        st = getattr(gdg, name)
+        got = C.sizeof(st) if field == "sizeof" else getattr(st, field).offset
+        assert got == int(value), (name, field, got, value)
+        seen += 1
+    assert seen == sum(len(getattr(gdg, n)._fields_) + 1 for n in STRUCTS)
 
 
 @pytest.mark.parametrize("kind", [gdg.GDG_BC_DIRICHLET, gdg.GDG_BC_SUPERSONIC])
