@@ -445,6 +445,208 @@ def load_traffic(workload, kernels):
     return {n: k[n] for n in kernels}
 
 
+STAGE_KERNELS = ("sweep1", "sweep2", "limit1", "limit2")
+
+
+def _kernel_class(name):
+    """'void gdg::k_limit<3, 1>(gdg::KArgs, ...)' -> 'limit'; None for kernels
+    that are not one of the stage's."""
+    import re
+    m = re.search(r"gdg::k_(sweep1|sweep2|limit|prim)[<(]", name)
+    return m.group(1) if m else None
+
+
+def _region(rows, profile_steps):
+    """The dispatches of the host-driven profile region at the end of the run:
+    the last 3P launches of each sweep and the last 6P limiter launches, whose
+    order within a stage gives the pass.  rows: (dispatch id, kernel name,
+    value) in any order.  Returns {kernel: [values]}."""
+    by = {"sweep1": [], "sweep2": [], "limit": []}
+    for _, name, v in sorted(rows, key=lambda r: r[0]):
+        c = _kernel_class(name)
+        if c in by:
+            by[c].append(v)
+    n = 3 * profile_steps
+    out = {"sweep1": by["sweep1"][-n:], "sweep2": by["sweep2"][-n:]}
+    lim = by["limit"][-2 * n:]
+    out["limit1"], out["limit2"] = lim[0::2], lim[1::2]
+    if any(len(out[k]) != n for k in out):
+        raise SystemExit("profile region incomplete: %s" % {k: len(v) for k, v in out.items()})
+    return out
+
+
+def _read_csv(path):
+    import csv
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _find(dirname, suffix):
+    for root, _, files in os.walk(dirname):
+        for f in sorted(files):
+            if f.endswith(suffix):
+                return os.path.join(root, f)
+    raise SystemExit("no *%s under %s" % (suffix, dirname))
+
+
+def summarize_counters(workload, fetch_dir, write_dir, profile_steps, copy_gib, commands):
+    """profiles/traffic_<workload>.json (read by the bench line) and .md from
+    two rocprofv3 --pmc runs of this script, FETCH_SIZE and WRITE_SIZE (KiB
+    per dispatch), each scaled by what the same counter reads for the plain
+    device copy of copy_gib GiB that the runs made (--calib-copy-gib)."""
+    import statistics
+    res = {}
+    calib = {"copy_bytes": copy_gib * (1 << 30)}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _read_csv(_find(d, "counter_collection.csv")) if r["Counter_Name"] == counter]
+        vals = [(int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"]) * 1024.0) for r in rows]
+        copies = sorted(v for _, n, v in vals if "copyBuffer" in n)[-3:]
+        if len(copies) < 3:
+            raise SystemExit("no calibration copy in %s" % d)
+        measured = statistics.median(copies)
+        key = "fetch" if counter == "FETCH_SIZE" else "write"
+        calib[key + "_measured"] = measured
+        calib[key + "_scale"] = calib["copy_bytes"] / measured
+        for k, v in _region(vals, profile_steps).items():
+            res.setdefault(k, {})[key + "_bytes"] = statistics.mean(v) * calib[key + "_scale"]
+            res[k]["dispatches"] = len(v)
+    for k in res:
+        res[k]["bytes_per_launch"] = res[k]["fetch_bytes"] + res[k]["write_bytes"]
+    wl, desc = _workload(workload)
+    slots, ghosts = stencil_slots(wl.mesh)
+    N = wl.mesh.ndofs
+    rec = {"workload": workload, "description": desc, "kernel_source_hash": kernel_source_hash(),
+           "region": "the %d host-driven steps after the run's timed steps (%d stages)" % (profile_steps,
+                                                                                       3 * profile_steps),
+           "calibration": calib, "commands": commands, "kernels": res}
+    base = os.path.join(ROOT, "profiles", "traffic_%s" % workload)
+    with open(base + ".json", "w") as f:
+        json.dump(rec, f, indent=1)
+    lines = ["# HBM traffic per launch: %s" % desc, "",
+             "FETCH_SIZE and WRITE_SIZE from two `rocprofv3 --pmc` runs, averaged over the launches of "
+             "the profile region (%s), kernel source %s." % (rec["region"], rec["kernel_source_hash"]),
+             "Calibration: a plain %.0f GiB device copy in the same process reads FETCH_SIZE = %.3f GiB and "
+             "WRITE_SIZE = %.3f GiB, so fetches are scaled by %.4f and writes by %.4f." % (
+                 copy_gib, calib["fetch_measured"] / (1 << 30), calib["write_measured"] / (1 << 30),
+                 calib["fetch_scale"], calib["write_scale"]), "",
+             "| kernel | fetch GB | write GB | total GB | per-kernel model GB | measured / model |",
+             "|---|---|---|---|---|---|"]
+    for k in STAGE_KERNELS:
+        mdl = algorithmic_bytes(k, wl.mesh.dim, slots, ghosts) * N
+        r = res[k]
+        lines.append("| %s | %.3f | %.3f | %.3f | %.3f | %.2f |" % (
+            k, r["fetch_bytes"] / 1e9, r["write_bytes"] / 1e9, r["bytes_per_launch"] / 1e9, mdl / 1e9,
+            r["bytes_per_launch"] / mdl))
+    tot = sum(res[k]["bytes_per_launch"] for k in STAGE_KERNELS)
+    lines += ["", "Stage total %.3f GB against the whole-stage model's %.3f GB (%.1f bytes per dof-stage)." % (
+        tot / 1e9, b_alg(wl.mesh.dim, wl.mesh.degree) * N / 1e9, b_alg(wl.mesh.dim, wl.mesh.degree)), "",
+              "Commands (from the repository root on the GPU box):", ""]
+    lines += ["    " + c for c in commands]
+    with open(base + ".md", "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(json.dumps({k: res[k]["bytes_per_launch"] for k in STAGE_KERNELS}))
+
+
+def summarize_pmc(workload, dirs, profile_steps, commands):
+    """profiles/counters_<workload>.md: the mean of every counter of the given
+    rocprofv3 --pmc output folders over the launches of the profile region,
+    per stage kernel, with the derived occupancy, VALU-busy and L2 hit
+    figures."""
+    import statistics
+    vals = {}
+    for d in dirs:
+        rows = _read_csv(_find(d, "counter_collection.csv"))
+        for cn in sorted(set(r["Counter_Name"] for r in rows)):
+            sel = [(int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])) for r in rows
+                   if r["Counter_Name"] == cn]
+            for k, v in _region(sel, profile_steps).items():
+                vals.setdefault(k, {})[cn] = statistics.mean(v)
+    _, desc = _workload(workload)
+    names = sorted(set(c for k in vals for c in vals[k]))
+    out = ["# Counters per launch: %s" % desc, "",
+           "Means over the launches of the profile region (the %d host-driven steps after the run's timed steps, "
+           "%d launches of each kernel); one rocprofv3 --pmc pass per command below." % (profile_steps,
+                                                                                    3 * profile_steps), "",
+           "| counter | " + " | ".join(STAGE_KERNELS) + " |", "|---|" + "---|" * len(STAGE_KERNELS)]
+    for cn in names:
+        out.append("| %s | " % cn + " | ".join("%.4g" % vals[k].get(cn, float("nan")) for k in STAGE_KERNELS) + " |")
+
+    def derived(label, f):
+        cells = []
+        for k in STAGE_KERNELS:
+            try:
+                cells.append("%.3f" % f(vals[k]))
+            except (KeyError, ZeroDivisionError):
+                cells.append("-")
+        out.append("| %s | " % label + " | ".join(cells) + " |")
+
+    out += ["", "Derived.  SQ_BUSY_CYCLES sums the busy cycles of the 32 shader engines and SQ_WAVE_CYCLES the "
+                "resident time of every wave in units of four cycles, so the mean number of waves resident per "
+                "SIMD (1024 SIMDs) is 4 SQ_WAVE_CYCLES / (SQ_BUSY_CYCLES / 32 x 1024); its agreement with the "
+                "compiler's occupancy limit of each kernel checks that reading.", "",
+            "| figure | " + " | ".join(STAGE_KERNELS) + " |", "|---|" + "---|" * len(STAGE_KERNELS)]
+    derived("mean waves resident per SIMD", lambda v: v["SQ_WAVE_CYCLES"] / (8.0 * v["SQ_BUSY_CYCLES"]))
+    derived("VALU-active share of wave time (SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES)",
+            lambda v: v["SQ_ACTIVE_INST_VALU"] / v["SQ_WAVE_CYCLES"])
+    derived("waiting share of wave time (SQ_WAIT_ANY / SQ_WAVE_CYCLES)", lambda v: v["SQ_WAIT_ANY"] / v["SQ_WAVE_CYCLES"])
+    derived("VALU instructions per wave (SQ_INSTS_VALU / SQ_WAVES)", lambda v: v["SQ_INSTS_VALU"] / v["SQ_WAVES"])
+    derived("L2 hit rate (TCC_HIT_sum / TCC_REQ_sum)", lambda v: v["TCC_HIT_sum"] / v["TCC_REQ_sum"])
+    out += ["", "Commands (from the repository root on the GPU box):", ""] + ["    " + c for c in commands]
+    with open(os.path.join(ROOT, "profiles", "counters_%s.md" % workload), "w") as f:
+        f.write("\n".join(out) + "\n")
+
+
+def summarize_trace(workload, trace_dir, bench_json, profile_steps, command):
+    """profiles/kernels_<workload>.md from a rocprofv3 --kernel-trace --stats
+    run of this script: the profiler's per-kernel statistics over the whole
+    run, the launches of the profile region split by limiter pass (the
+    launches the bench line's per-kernel HIP events time), and the bench line
+    of the same run."""
+    import statistics
+    stats = _read_csv(_find(trace_dir, "kernel_stats.csv"))
+    trace = _read_csv(_find(trace_dir, "kernel_trace.csv"))
+    line = [json.loads(x) for x in open(bench_json).read().splitlines() if x.startswith('{"metric"')][-1]
+    wl, desc = _workload(workload)
+    rows = [(int(r["Dispatch_Id"]), r["Kernel_Name"],
+             (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3) for r in trace]
+    reg = _region(rows, profile_steps)
+    res = {}
+    for r in trace:
+        c = _kernel_class(r["Kernel_Name"])
+        if c and c not in res:
+            res[c] = r
+    out = ["# Kernel trace: %s" % desc, "", "Command (from the repository root on the GPU box):", "",
+           "    " + command, "", "rocprofv3 kernel statistics over the whole run (microseconds):", "",
+           "| kernel | calls | total us | average us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:12]:
+        out.append("| %s | %s | %.1f | %.3f | %.3f | %.3f | %.2f |" % (
+            r["Name"].replace("|", "/"), r["Calls"], float(r["TotalDurationNs"]) / 1e3,
+            float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
+            float(r["Percentage"])))
+    out += ["", "Launches of the host-driven profile region (%d steps after the timed run), the ones the bench "
+                "line's `kernels_ms_per_launch` times with HIP events:" % profile_steps, "",
+            "| kernel | launches | trace average us | bench HIP-event average us | VGPR_Count | Accum_VGPR_Count "
+            "| SGPR_Count | LDS B |",
+            "|---|---|---|---|---|---|---|---|"]
+    for k in STAGE_KERNELS:
+        r = res.get("limit" if k.startswith("limit") else k, {})
+        ev = line.get("kernels_ms_per_launch", {}).get(k)
+        out.append("| %s | %d | %.1f | %s | %s | %s | %s | %s |" % (
+            k, len(reg[k]), statistics.mean(reg[k]), "%.1f" % (ev * 1e3) if ev else "-",
+            r.get("VGPR_Count", "?"), r.get("Accum_VGPR_Count", "?"), r.get("SGPR_Count", "?"),
+            r.get("LDS_Block_Size", "?")))
+    out += ["", "The trace's VGPR_Count is half the VGPR count that the compiler's resource remark gives for the "
+                "same kernel (k_limit<3,1>: 120 against 239); occupancy follows the compiler's figure, as the "
+                "counter profile's measured waves per SIMD confirm."]
+    rf = line["roofline"]
+    out += ["", "Bench line of the same run: %.4e %s, %.3f ms/step, whole-stage roofline %.1f GB/s of %.0f "
+                "(frac %.4f), dominant kernel %s at %.3f ms/launch." % (
+                    line["value"], line["unit"], line["ms_per_step"], rf["achieved"], rf["peak"], rf["frac"],
+                    rf["dominant_kernel"]["kernel"], rf["dominant_kernel"]["avg_launch_ms"])]
+    with open(os.path.join(ROOT, "profiles", "kernels_%s.md" % workload), "w") as f:
+        f.write("\n".join(out) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -470,7 +672,28 @@ def main():
                     help="host-driven steps with per-launch HIP events after the timed region")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no GPU work: write profiles/traffic_<workload>.json and .md from the output folders "
+                         "of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "BENCH_JSON"),
+                    help="no GPU work: write profiles/kernels_<workload>.md from a rocprofv3 --kernel-trace "
+                         "--stats run of this script and the JSON line it printed")
+    ap.add_argument("--summarize-pmc", nargs="+", metavar="PMC_DIR",
+                    help="no GPU work: write profiles/counters_<workload>.md from rocprofv3 --pmc output folders")
+    ap.add_argument("--command", action="append", default=[],
+                    help="the profiling command(s) to record in the summary")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(args.workload, *args.summarize_counters, args.profile_steps,
+                           args.calib_copy_gib or 1.0, args.command)
+        return
+    if args.summarize_pmc:
+        summarize_pmc(args.workload, args.summarize_pmc, args.profile_steps, args.command)
+        return
+    if args.summarize_trace:
+        summarize_trace(args.workload, *args.summarize_trace, args.profile_steps,
+                        args.command[0] if args.command else "")
+        return
     global CELLS_OVERRIDE
     CELLS_OVERRIDE = args.cells
     world = int(os.environ.get("WORLD_SIZE", "1"))

@@ -66,6 +66,8 @@ struct Ctl {
 };
 // Reduction of a state for the statistics call: per block partials, then one
 // block combines them in a fixed order.  min rho, min eps, sum_i m_i U_i.
+// Most cell rows in y of a 3D tile of the sweep order.
+constexpr int64_t kTileRows = 64;
 constexpr int kRedBlocks = 512;
 constexpr int kRedThreads = 256;
 constexpr int kRedFields = 2 + kMaxD + 2;
@@ -137,7 +139,7 @@ struct KArgs {
   // z-plane, so the block one z-plane back was swept nbx * ty blocks earlier
   // (still in the XCD's L2) instead of a whole plane earlier.
   int32_t tiled;
-  int64_t t_nbx, t_ny, t_nz, t_ty;
+  int64_t t_nbx, t_ny, t_nz, t_tx, t_ty;
   // stencil
   int32_t *col;
   double *c;        // dim planes of nslots (FP64 precision)

@@ -304,13 +304,17 @@ __device__ __forceinline__ int64_t xcd_position(int64_t hw, int64_t nblocks) {
 
 // Row block at position L of the sweep order (a bijection of [0, nblocks)):
 // the block order itself, or for a tiled 3D mesh (KArgs::tiled) the order
-// tile by tile, z-plane by z-plane, y-row by y-row, x-block by x-block.
+// tile by tile (tiles of t_tx row blocks in x by t_ty cell rows in y, through
+// every z-plane), inside a tile z-plane by z-plane, y-row by y-row, x-block
+// by x-block.
 __device__ __forceinline__ int64_t sweep_block(const KArgs &A, int64_t L) {
   if (!A.tiled) return L;
-  const int64_t plane = A.t_nbx * A.t_ty;  // blocks of one tile in one z-plane
+  const int64_t plane = A.t_tx * A.t_ty;  // blocks of one tile in one z-plane
   const int64_t tile = L / (plane * A.t_nz), rem = L % (plane * A.t_nz);
   const int64_t z = rem / plane, rem2 = rem % plane;
-  const int64_t y = tile * A.t_ty + rem2 / A.t_nbx, bx = rem2 % A.t_nbx;
+  const int64_t ntx = A.t_nbx / A.t_tx;
+  const int64_t y = (tile / ntx) * A.t_ty + rem2 / A.t_tx;
+  const int64_t bx = (tile % ntx) * A.t_tx + rem2 % A.t_tx;
   return bx + A.t_nbx * (y + A.t_ny * z);
 }
 
