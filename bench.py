@@ -285,7 +285,7 @@ def mixed_vs_fp64(name, steps):
             "fp64_perturbed_1e-13": {"l1_rel_per_component": pcomp, "l1_consolidated": pcons}}
 
 
-def serving(count, n_max, t_final, budget_gib, max_slots, spg):
+def serving(count, n_max, t_final, budget_gib, max_slots, spg, solo_dofs=0):
     """The serving workload on a trace of `count` requests (2D Q1 four-quadrant
     Riemann problems of n x n cells, n log-uniform in [32, n_max], slip walls,
     run to t_final; Poisson arrivals at 20 per second), served in real time by
@@ -302,7 +302,7 @@ def serving(count, n_max, t_final, budget_gib, max_slots, spg):
     reqs = [(a, W.quadrant(cells=n, degree=1, seed_base=sb, bc=W.BC_SLIP)) for a, n, sb in trace]
     # -- batched, continuous admission, real time
     S = gdg.Server(2, 1, gdg.GDG_MIXED, budget_bytes=int(budget_gib * (1 << 30)), max_slots=max_slots,
-                   steps_per_graph=spg)
+                   steps_per_graph=spg, solo_dofs=solo_dofs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     tickets = [None] * count
@@ -338,7 +338,8 @@ def serving(count, n_max, t_final, budget_gib, max_slots, spg):
     served = {"requests": count, "failed": failed, "makespan_s": makespan,
               "p50_s": float(np.percentile(tts, 50)), "p99_s": float(np.percentile(tts, 99)),
               "dof_stage_per_s": work / makespan, "steps_total": int(steps.sum()),
-              "precision": "mixed", "max_slots": max_slots, "steps_per_graph": spg,
+              "precision": "mixed", "max_slots": max_slots, "steps_per_graph": spg, "solo_dofs": solo_dofs,
+              "solo_requests": sum(1 for _, wl in reqs if solo_dofs > 0 and wl.mesh.ndofs >= solo_dofs),
               "budget_gib": budget_gib}
     S.close()
     # -- one at a time, FP64, FIFO
@@ -440,9 +441,11 @@ def load_traffic(workload, kernels):
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     k = rec.get("kernels", {})
-    if not all(n in k for n in kernels):
+    if not all(n in k for n in STAGE_KERNELS):
         return None
-    return {n: k[n] for n in kernels}
+    # the primitives kernel runs once per run (after an upload or a reset),
+    # not per stage: the stage traffic is that of the four stage kernels
+    return {n: k[n] for n in kernels if n in STAGE_KERNELS}
 
 
 STAGE_KERNELS = ("sweep1", "sweep2", "limit1", "limit2")
@@ -664,6 +667,8 @@ def main():
     ap.add_argument("--serving-tfinal", type=float, default=0.02)
     ap.add_argument("--serving-budget-gib", type=float, default=4.0)
     ap.add_argument("--serving-slots", type=int, default=64)
+    ap.add_argument("--serving-solo-dofs", type=int, default=65536,
+                    help="requests of at least this many dofs run their own single-mesh graph in the server")
     ap.add_argument("--serving-steps-per-graph", type=int, default=8,
                     help="device-driven steps per server launch (host pump once per launch)")
     ap.add_argument("--cells", type=int, default=0,
@@ -725,8 +730,8 @@ def main():
     traffic_stage = None
     if traffic_k:
         # launches per stage: each profiled kernel's launches over the region's stages
-        per_stage = {k: prof[k][1] / (3.0 * prof_steps) for k in kernels}
-        traffic_stage = sum(traffic_k[k]["bytes_per_launch"] * per_stage[k] for k in kernels)
+        per_stage = {k: prof[k][1] / (3.0 * prof_steps) for k in traffic_k}
+        traffic_stage = sum(traffic_k[k]["bytes_per_launch"] * per_stage[k] for k in traffic_k)
     if args.calib_copy_gib > 0:
         import torch
         n = int(args.calib_copy_gib * (1 << 30)) // 8
@@ -765,8 +770,10 @@ def main():
                          "kernel": dom, "avg_launch_ms": dom_avg * 1e3,
                          "model_bytes_per_launch": dom_bytes,
                          "model_gbs": dom_bytes / dom_avg / 1e9,
-                         "traffic_bytes_per_launch": traffic_k[dom]["bytes_per_launch"] if traffic_k else None,
-                         "traffic_gbs": traffic_k[dom]["bytes_per_launch"] / dom_avg / 1e9 if traffic_k else None,
+                         "traffic_bytes_per_launch": traffic_k[dom]["bytes_per_launch"]
+                         if traffic_k and dom in traffic_k else None,
+                         "traffic_gbs": traffic_k[dom]["bytes_per_launch"] / dom_avg / 1e9
+                         if traffic_k and dom in traffic_k else None,
                          "timing": "HIP events around every launch on the library stream, %d host-driven steps "
                                    "after the timed region (%.3f ms/step)" % (prof_steps, prof_ms_step)}},
         "kernels_ms_per_launch": {k: (v[0] / v[1] if v[1] else None) for k, v in prof.items()},
@@ -795,7 +802,8 @@ def main():
     if not args.no_serving:
         log("serving")
         line["serving"] = serving(args.serving_requests, args.serving_nmax, args.serving_tfinal,
-                                  args.serving_budget_gib, args.serving_slots, args.serving_steps_per_graph)
+                                  args.serving_budget_gib, args.serving_slots, args.serving_steps_per_graph,
+                                  args.serving_solo_dofs)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -203,8 +203,11 @@ int64_t gdg_num_dofs(const gdg_ctx *ctx);
 /* Collocation points x_i into host_xyz[N * dim] (interleaved per dof). */
 gdg_status gdg_node_coords(const gdg_ctx *ctx, double *host_xyz);
 
-/* Copies a state (SoA, (dim+2) * N doubles) into the context; is_device_ptr
- * selects device or host memory.  Resets t and the step counters.  Returns
+/* Copies a state (SoA, (dim+2) * N doubles) into the context.  U may be host
+ * or device memory: the copy uses unified addressing (hipMemcpyDefault), so
+ * is_device_ptr only documents the caller's intent and is not needed for the
+ * copy (the same holds for gdg_download_state and gdg_read_field).  Resets t
+ * and the step counters.  Returns
  * GDG_E_INADMISSIBLE if some U_i is outside A (the paper's guarantees assume
  * admissible data, Sec. 3.1).  Synchronizes the stream. */
 gdg_status gdg_upload_state(gdg_ctx *ctx, const double *U, int32_t is_device_ptr);
@@ -322,7 +325,11 @@ typedef struct {
   int32_t dim, degree, precision; /* the request class */
   int32_t max_slots;              /* resident requests at most, 1 .. 256 */
   int32_t steps_per_graph;        /* SSP-RK3 steps per batched launch, >= 1 */
-  int32_t reserved;
+  int32_t solo_dofs;              /* > 0: a request of at least this many dofs is not batched; each
+                                     launch replays its own single-mesh graph of 8 steps after the
+                                     batched graph (large meshes fill the chip alone, and the
+                                     single-mesh kernels run them faster); 0: every request is
+                                     batched */
 } gdg_server_desc;
 
 typedef enum { GDG_REQ_PENDING = 0, GDG_REQ_RUNNING = 1, GDG_REQ_DONE = 2, GDG_REQ_FAILED = 3 } gdg_req_state;

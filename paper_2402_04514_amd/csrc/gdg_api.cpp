@@ -689,6 +689,13 @@ gdg_status ctx_restart(gdg_ctx *ctx, const Ctl &c, double t_final) {
 
 const char *ctx_error(const gdg_ctx *ctx) { return ctx->err.c_str(); }
 
+int ctx_launch_steps(gdg_ctx *ctx, void *stream) {
+  if (ensure_graph(ctx) != GDG_OK) return -1;
+  return hipGraphLaunch(ctx->graph_exec, (hipStream_t)stream) == hipSuccess ? 0 : -1;
+}
+
+const Ctl *ctx_dev_ctl(const gdg_ctx *ctx) { return ctx->A.ctl; }
+
 void set_create_error(const std::string &msg) { g_create_err = msg; }
 
 void ctx_counts(const gdg_ctx *ctx, double *t, int64_t *steps, int64_t *restarts) {

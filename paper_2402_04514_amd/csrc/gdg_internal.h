@@ -230,6 +230,11 @@ void ctx_sync(gdg_ctx *ctx, const Ctl &c);
 // rule of gdg_step), then re-arms the device-driven loop.
 gdg_status ctx_restart(gdg_ctx *ctx, const Ctl &c, double t_final);
 const char *ctx_error(const gdg_ctx *ctx);
+// Replays the context's captured graph of device-driven steps (captured at the
+// first call) on `stream`; 0 on success.
+int ctx_launch_steps(gdg_ctx *ctx, void *stream);
+// The context's device control block.
+const Ctl *ctx_dev_ctl(const gdg_ctx *ctx);
 // The device-driven time loop of gdg_run_to(); use_graph = false enqueues
 // the same launches directly instead of replaying a captured graph.
 gdg_status run_loop(gdg_ctx *ctx, double t_final, int64_t max_steps, gdg_stats *stats, bool use_graph);

@@ -35,6 +35,11 @@ namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Streams on which the graphs of solo requests run side by side: a large
+// request alone at the per-step floor of its dependent launches leaves most
+// of the chip idle, so up to this many of them overlap.
+constexpr int kSoloStreams = 3;
+
 // First-fit allocator over [0, size) in 256-byte granules; free ranges are
 // kept by offset and merged with their neighbours on release.
 class PoolAlloc {
@@ -90,6 +95,7 @@ struct Req {
   double t_final = 0.0;
   size_t bytes = 0, off = 0;
   gdg_ctx *ctx = nullptr;
+  bool solo = false;  // runs its own single-mesh graph instead of the batched kernels
   int state = GDG_REQ_PENDING;
   int status = GDG_OK;
   double t = 0.0;
@@ -109,6 +115,8 @@ struct gdg_server {
   hipStream_t stream = nullptr;      // batched launches
   hipStream_t adm_stream = nullptr;  // admissions, restarts, retirements (the requests' contexts)
   hipStream_t cap_stream = nullptr;
+  hipStream_t solo_stream[kSoloStreams] = {};  // solo requests' graphs, side by side
+  hipEvent_t solo_ev[kSoloStreams] = {};       // joins each solo stream into the status copy
   hipEvent_t done_ev = nullptr;      // after the status copy of the launch in flight
   hipEvent_t adm_ev = nullptr;       // joins the admission stream into the next launch
   hipGraphExec_t gexec = nullptr;
@@ -238,6 +246,7 @@ void admit(gdg_server *s) {
     }
     std::vector<double>().swap(q->U);
     q->state = GDG_REQ_RUNNING;
+    q->solo = s->d.solo_dofs > 0 && q->ndofs >= s->d.solo_dofs;
     if (!(0.0 < q->t_final)) {
       take_stats(q);
       finish_req(s, q);
@@ -292,6 +301,10 @@ gdg_status ensure_device(gdg_server *s) {
   SRVCHK(s, hipStreamCreateWithFlags(&s->adm_stream, hipStreamNonBlocking));
   SRVCHK(s, hipEventCreateWithFlags(&s->done_ev, hipEventDisableTiming));
   SRVCHK(s, hipEventCreateWithFlags(&s->adm_ev, hipEventDisableTiming));
+  for (int k = 0; k < kSoloStreams; ++k) {
+    SRVCHK(s, hipStreamCreateWithFlags(&s->solo_stream[k], hipStreamNonBlocking));
+    SRVCHK(s, hipEventCreateWithFlags(&s->solo_ev[k], hipEventDisableTiming));
+  }
   SRVCHK(s, hipHostMalloc((void **)&s->hstat, sizeof(Ctl) * kMaxBatch, hipHostMallocDefault));
   // one-wavefront workgroups: eight per CU keep every SIMD busy with two
   // waves while leaving room for the register budget of the sweeps
@@ -299,36 +312,59 @@ gdg_status ensure_device(gdg_server *s) {
   return GDG_OK;
 }
 
-// Step 5: refresh the device work list if the resident set changed, launch
-// the graph after the admission stream's work and queue the status copy.
-// Called only when no launch is in flight, so the caller's stream is idle.
+// Step 5: refresh the device work list if the batched set changed, launch
+// the batched graph and then each solo request's own graph after the
+// admission stream's work, and queue the status copy (batched requests
+// first, then the solo ones, in `launched` order).  Called only when no
+// launch is in flight, so the caller's stream is idle.
 gdg_status launch(gdg_server *s) {
   if (s->resident.empty()) return GDG_OK;
   if (gdg_status st = ensure_device(s)) return st;
-  const int n = (int)s->resident.size();
+  std::vector<Req *> batch, solo;
+  for (Req *q : s->resident) (q->solo ? solo : batch).push_back(q);
+  const int nb = (int)batch.size();
   if (s->list_dirty) {
     BatchList &L = *s->hlist;
-    L.nreq = n;
+    L.nreq = nb;
     L.tile_begin[0] = 0;
-    for (int r = 0; r < n; ++r) {
+    for (int r = 0; r < nb; ++r) {
       BatchEntry &E = L.e[r];
-      E.A = ctx_kargs(s->resident[r]->ctx);
-      ctx_stage_bufs(s->resident[r]->ctx, E.sb);
+      E.A = ctx_kargs(batch[r]->ctx);
+      ctx_stage_bufs(batch[r]->ctx, E.sb);
       L.tile_begin[r + 1] = L.tile_begin[r] + E.A.nblocks;
     }
-    L.ntiles = L.tile_begin[n];
-    const size_t bytes = offsetof(BatchList, e) + sizeof(BatchEntry) * (size_t)n;
+    L.ntiles = L.tile_begin[nb];
+    const size_t bytes = offsetof(BatchList, e) + sizeof(BatchEntry) * (size_t)nb;
     SRVCHK(s, hipMemcpyAsync(s->dlist, s->hlist, bytes, hipMemcpyHostToDevice, s->stream));
     SRVCHK(s, hipStreamSynchronize(s->stream));  // the host image may change before the next launch
     s->list_dirty = false;
   }
-  if (gdg_status st = ensure_graph(s)) return st;
+  if (nb > 0)
+    if (gdg_status st = ensure_graph(s)) return st;
   SRVCHK(s, hipEventRecord(s->adm_ev, s->adm_stream));
   SRVCHK(s, hipStreamWaitEvent(s->stream, s->adm_ev, 0));
-  SRVCHK(s, hipGraphLaunch(s->gexec, s->stream));
-  SRVCHK(s, hipMemcpyAsync(s->hstat, s->dstat, sizeof(Ctl) * (size_t)n, hipMemcpyDeviceToHost, s->stream));
+  if (nb > 0) SRVCHK(s, hipGraphLaunch(s->gexec, s->stream));
+  // solo request r runs on solo stream r % kSoloStreams after the admission
+  // stream's work; the status copy waits for every solo stream used
+  const int nstreams = solo.size() < (size_t)kSoloStreams ? (int)solo.size() : kSoloStreams;
+  for (int k = 0; k < nstreams; ++k) SRVCHK(s, hipStreamWaitEvent(s->solo_stream[k], s->adm_ev, 0));
+  for (size_t r = 0; r < solo.size(); ++r) {
+    hipStream_t st = s->solo_stream[r % kSoloStreams];
+    if (ctx_launch_steps(solo[r]->ctx, st) != 0) {
+      s->err = std::string("solo request launch failed: ") + ctx_error(solo[r]->ctx);
+      return GDG_E_DEVICE;
+    }
+    SRVCHK(s, hipMemcpyAsync(s->dstat + nb + r, ctx_dev_ctl(solo[r]->ctx), sizeof(Ctl), hipMemcpyDeviceToDevice, st));
+  }
+  for (int k = 0; k < nstreams; ++k) {
+    SRVCHK(s, hipEventRecord(s->solo_ev[k], s->solo_stream[k]));
+    SRVCHK(s, hipStreamWaitEvent(s->stream, s->solo_ev[k], 0));
+  }
+  const size_t n = batch.size() + solo.size();
+  SRVCHK(s, hipMemcpyAsync(s->hstat, s->dstat, sizeof(Ctl) * n, hipMemcpyDeviceToHost, s->stream));
   SRVCHK(s, hipEventRecord(s->done_ev, s->stream));
-  s->launched = s->resident;
+  s->launched = batch;
+  s->launched.insert(s->launched.end(), solo.begin(), solo.end());
   s->in_flight = true;
   return GDG_OK;
 }
@@ -350,7 +386,7 @@ gdg_status flight_done(gdg_server *s, bool *done) {
 bool desc_ok(const gdg_server_desc *d) {
   return d && d->dim >= 1 && d->dim <= 3 && d->degree >= 1 && d->degree <= 3 && !(d->degree == 3 && d->dim == 3) &&
          (d->precision == GDG_FP64 || d->precision == GDG_MIXED) && d->max_slots >= 1 &&
-         d->max_slots <= kMaxBatch && d->steps_per_graph >= 1 && d->steps_per_graph <= 64;
+         d->max_slots <= kMaxBatch && d->steps_per_graph >= 1 && d->steps_per_graph <= 64 && d->solo_dofs >= 0;
 }
 
 }  // namespace
@@ -476,6 +512,8 @@ void gdg_server_destroy(gdg_server *s) {
   if (!s) return;
   if (s->hstat || !s->resident.empty()) (void)hipStreamSynchronize(s->stream);
   if (s->adm_stream) (void)hipStreamSynchronize(s->adm_stream);
+  for (int k = 0; k < kSoloStreams; ++k)
+    if (s->solo_stream[k]) (void)hipStreamSynchronize(s->solo_stream[k]);
   for (auto &kv : s->reqs) {
     if (kv.second->ctx) gdg_destroy(kv.second->ctx);
     delete kv.second;
@@ -485,6 +523,10 @@ void gdg_server_destroy(gdg_server *s) {
   if (s->done_ev) (void)hipEventDestroy(s->done_ev);
   if (s->adm_ev) (void)hipEventDestroy(s->adm_ev);
   if (s->adm_stream) (void)hipStreamDestroy(s->adm_stream);
+  for (int k = 0; k < kSoloStreams; ++k) {
+    if (s->solo_ev[k]) (void)hipEventDestroy(s->solo_ev[k]);
+    if (s->solo_stream[k]) (void)hipStreamDestroy(s->solo_stream[k]);
+  }
   if (s->hstat) (void)hipHostFree(s->hstat);
   delete s->hlist;
   delete s;

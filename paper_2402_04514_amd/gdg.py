@@ -59,7 +59,7 @@ class gdg_stats(C.Structure):
 
 class gdg_server_desc(C.Structure):
     _fields_ = [("dim", C.c_int32), ("degree", C.c_int32), ("precision", C.c_int32),
-                ("max_slots", C.c_int32), ("steps_per_graph", C.c_int32), ("reserved", C.c_int32)]
+                ("max_slots", C.c_int32), ("steps_per_graph", C.c_int32), ("solo_dofs", C.c_int32)]
 
 
 class gdg_request_info(C.Structure):
@@ -344,9 +344,10 @@ def _scheck(st, srv):
         raise GdgError(st, load().gdg_server_last_error(srv).decode())
 
 
-def server_desc(dim, degree, precision=GDG_FP64, max_slots=64, steps_per_graph=8) -> gdg_server_desc:
+def server_desc(dim, degree, precision=GDG_FP64, max_slots=64, steps_per_graph=8, solo_dofs=0) -> gdg_server_desc:
     d = gdg_server_desc()
     d.dim, d.degree, d.precision, d.max_slots, d.steps_per_graph = dim, degree, precision, max_slots, steps_per_graph
+    d.solo_dofs = solo_dofs
     return d
 
 
@@ -407,9 +408,9 @@ class Server:
     tensor on ``device`` and whose stream is torch's current stream there."""
 
     def __init__(self, dim, degree, precision=GDG_FP64, budget_bytes=4 << 30, max_slots=64,
-                 steps_per_graph=8, device="cuda:0", stream=None):
+                 steps_per_graph=8, device="cuda:0", stream=None, solo_dofs=0):
         import torch
-        self.desc = server_desc(dim, degree, precision, max_slots, steps_per_graph)
+        self.desc = server_desc(dim, degree, precision, max_slots, steps_per_graph, solo_dofs)
         self.device = torch.device(device)
         self.pool = torch.empty(budget_bytes + 256, dtype=torch.uint8, device=self.device)
         self.pool_ptr = (self.pool.data_ptr() + 255) & ~255

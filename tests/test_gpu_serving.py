@@ -43,13 +43,14 @@ def _requests(dim, degree, n, seed0=40):
     return out
 
 
-def _run_server(reqs, precision, max_slots=8, budget=None, arrivals=None, spg=4):
+def _run_server(reqs, precision, max_slots=8, budget=None, arrivals=None, spg=4, solo_dofs=0):
     """Submits reqs (at pump index arrivals[r], default all at once), pumps
     until all finish; returns results, infos and the peak resident count."""
     dim, degree = reqs[0][0].dim, reqs[0][0].degree
     if budget is None:
         budget = 256 << 20
-    S = gdg.Server(dim, degree, precision, budget_bytes=budget, max_slots=max_slots, steps_per_graph=spg)
+    S = gdg.Server(dim, degree, precision, budget_bytes=budget, max_slots=max_slots, steps_per_graph=spg,
+                   solo_dofs=solo_dofs)
     arrivals = arrivals or [0] * len(reqs)
     tickets = [None] * len(reqs)
     peak, k = 0, 0
@@ -101,6 +102,31 @@ def test_mix_equals_alone_and_single_path(precision):
         err = (np.abs(outs[r] - ref) / scale).max()
         tol = 1e-12 if precision == gdg.GDG_FP64 else 1e-7
         assert err <= tol, ("served vs single-mesh path", r, err)
+
+
+@pytest.mark.parametrize("precision", [gdg.GDG_FP64, gdg.GDG_MIXED])
+def test_solo_requests_equal_the_single_mesh_path(precision):
+    """With solo_dofs set, the requests of at least that many dofs replay
+    their own single-mesh graph inside the server's launches: bit-identical
+    to gdg_run_to on a context of their own, while the smaller ones, batched
+    beside them, stay bit-identical to being served alone."""
+    _say("solo requests, precision %d" % precision)
+    reqs = _requests(2, 1, 8, seed0=120)
+    solo_dofs = 4 * 13 * 11  # the 13 x 11, 9 x 16, 21 x 7 and 17 x 19 requests
+    outs, infos, _ = _run_server(reqs, precision, max_slots=5, arrivals=[0, 0, 1, 1, 2, 4, 4, 6],
+                                 solo_dofs=solo_dofs)
+    nsolo = 0
+    for r, (ms, U, tf) in enumerate(reqs):
+        assert infos[r].state == gdg.GDG_REQ_DONE and infos[r].t == tf, (r, infos[r].state, infos[r].t)
+        if ms.ndofs >= solo_dofs:
+            nsolo += 1
+            ref, st = _alone_run_to(ms, U, tf, precision)
+            assert np.array_equal(outs[r], ref), ("solo request differs from gdg_run_to", r)
+            assert infos[r].steps == st.steps
+        else:
+            alone, _, _ = _run_server([(ms, U, tf)], precision, max_slots=1)
+            assert np.array_equal(outs[r], alone[0]), ("batched request differs from alone", r)
+    assert 0 < nsolo < len(reqs)
 
 
 def test_fp64_served_matches_oracle(oracle):
