@@ -139,8 +139,15 @@ typedef struct {
   int32_t limiter_passes; /* 0, 1 or 2 */
   int32_t scheme;         /* gdg_scheme */
   int32_t precision;      /* gdg_precision */
-  int32_t reserved;
+  int32_t flags;          /* 0, or GDG_FLAG_NO_QUIET_ROWS */
 } gdg_params;
+
+/* gdg_params.flags.  GDG_FLAG_NO_QUIET_ROWS: the first limiter pass visits
+ * the pairs of every row, also of rows whose whole stencil holds one state bit
+ * for bit (their antidiffusive fluxes are exactly zero, so by default the pass
+ * accepts them without a visit).  The results are the same; the flag exists to
+ * check that. */
+enum { GDG_FLAG_NO_QUIET_ROWS = 1 };
 
 /* Counters and measures of a run (Sec. 3 and 5: the properties the scheme
  * guarantees, so that a caller can check them without downloading the state).

@@ -129,6 +129,7 @@ bool validate(const gdg_mesh_desc *m, const gdg_params *p, std::string *err) {
     return false;
   }
   if (p->limiter_passes < 0 || p->limiter_passes > 2) { *err = "limiter_passes must be 0, 1 or 2"; return false; }
+  if (p->flags & ~GDG_FLAG_NO_QUIET_ROWS) { *err = "unknown flags"; return false; }
   if (p->scheme < 0 || p->scheme > 2) { *err = "unknown scheme"; return false; }
   if (p->precision != GDG_FP64 && p->precision != GDG_MIXED) { *err = "unknown precision"; return false; }
   return true;
@@ -406,6 +407,7 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   A.g75 = std::fabs(prm->gamma - 1.4) < 1e-15 ? 1 : 0;
   A.scheme = prm->scheme;
   A.passes = prm->limiter_passes;
+  A.no_quiet = (prm->flags & GDG_FLAG_NO_QUIET_ROWS) ? 1 : 0;
   A.nslots = L.nslots;
   A.ref = (const RefTables *)(ws + L.off_ref);
   ctx->dref = (RefTables *)(ws + L.off_ref);

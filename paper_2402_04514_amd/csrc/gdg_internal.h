@@ -123,6 +123,7 @@ struct KArgs {
   int64_t cells[3];
   int32_t bc[6];
   int32_t bcbits;   // the boundary kind of face f in bits 3f..3f+2
+  int32_t no_quiet; // GDG_FLAG_NO_QUIET_ROWS: sweep 2 marks no row quiet
   // data of the Dirichlet-type faces from the isentropic vortex (beta, x0,
   // u_inf, gamma) at the node and the stage time instead of bnode
   int32_t vortex_data;

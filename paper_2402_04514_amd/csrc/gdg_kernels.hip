@@ -949,11 +949,12 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
   constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
   __shared__ double rs[M][kBlockThreads];
   __shared__ int qs[kBlockThreads];
-  // The limiter records go out staged in LDS on 3D meshes and directly from
-  // each lane otherwise: measured, staging cut sweep 2 on the 128^3 Q1 blast
-  // from 5.0 to 3.5 ms but raised it on the 1024^2 Q2 quadrant from 2.3 to
-  // 6.4 ms (the same code; the cause is not identified).
-  constexpr bool kStaged = D == 3;
+  // The limiter records go out staged in LDS, except on 2D Q2 meshes, where
+  // each lane writes its own: measured, staging cut sweep 2 on the 128^3 Q1
+  // blast from 5.0 to 3.5 ms, on the 40^3 Q2 blast from 1.01 to 0.85 ms and on
+  // the 256^2 Q1 vortex from 45 to 32 us, but raised it on the 1024^2 Q2
+  // quadrant from 2.4 to 8.5 ms (the same code; the cause is not identified).
+  constexpr bool kStaged = !(D == 2 && DEG == 2);
   __shared__ double stage_lds[kStaged ? kStageDoubles : 1];
   double tau;
   if (!stage_tau(A, stage, &tau)) {
@@ -1096,7 +1097,7 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
   // is exactly zero: the limiter's first pass accepts the row as it stands
   // without visiting its pairs.
   {
-    int cq = 1;
+    int cq = A.no_quiet ? 0 : 1;
     for (int b = 0; b < NLOC; ++b) cq &= qs[cellbase + b];
     A.accepted[i] = (uint8_t)cq;
     wave_count_add(&A.ctl->quiet_rows, (unsigned)cq);

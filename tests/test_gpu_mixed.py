@@ -144,3 +144,48 @@ def test_mixed_graph_run_matches_eager():
         A.step()
     B.run_to(1e9, max_steps=11)
     assert np.array_equal(A.download(), B.download())
+
+
+@pytest.mark.parametrize("name", ["quadrant_2d_q2", "blast_3d_q1"])
+def test_low_order_update_against_unrelaxed_bounds(oracle, name):
+    """In FP64, U^L is a convex combination of bar states (eq. ConvexRef), so
+    it lies inside the unrelaxed local bounds up to rounding.  The mixed
+    variant forms U^L from FP32-accumulated flux sums while the bar states and
+    bounds are FP64, so U^L can leave the unrelaxed bounds by the FP32
+    rounding of those sums; the limiter then starts from inside the relaxed
+    bounds only if that excursion stays below the relaxation margin
+    r_i = c_r hhat_i^{p_r} (eq. ViscMinConst2).  Measured after 6 steps: the
+    largest excursion as a fraction of the margin (density below or above,
+    rescaled entropy below; negative when every U^L is inside), FP64 next to
+    mixed."""
+    if name == "quadrant_2d_q2":
+        ms, U = quadrant_on(2, 2, (24, 20), (1, 1, 1, 1))
+    else:
+        wl = W.blast(cells=12)
+        ms, U = wl.mesh, wl.U0
+    M = oracle.Mesh(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc)
+    mi = M.lumped()
+    p0 = gdg.gdg_default_params(ms.degree)
+    r = p0.c_r * (mi / M.volume) ** (p0.p_r / ms.dim)
+    frac = {}
+    for prec in (gdg.GDG_FP64, gdg.GDG_MIXED):
+        p = gdg.gdg_default_params(ms.degree)
+        p.precision = prec
+        S = gdg.Solver.from_spec(ms, p)
+        S.upload(U)
+        S.run_to(1e30, max_steps=6)
+        S.stage(0.0)
+        UL = S.field(gdg.GDG_FIELD_UL)
+        rmin_r, rmax_r, smin_r = S.field(gdg.GDG_FIELD_BOUNDS)
+        S.close()
+        rmin, rmax, smin = rmin_r / (1.0 - r), rmax_r / (1.0 + r), smin_r / (1.0 - r)
+        d = ms.dim
+        rho = UL[0]
+        s_l = (UL[d + 1] - 0.5 * np.sum(UL[1:d + 1] ** 2, 0) / rho) * rho ** (-p0.gamma)
+        exc = np.maximum.reduce([(rmin - rho) / (r * rmin), (rho - rmax) / (r * rmax), (smin - s_l) / (r * smin)])
+        frac[prec] = float(exc.max())
+    # negative: every U^L inside the unrelaxed bounds, by that many margins at the closest node
+    _say("%s: largest U^L excursion beyond the unrelaxed bounds, in units of the relaxation margin: "
+         "FP64 %.3e, mixed %.3e" % (name, frac[gdg.GDG_FP64], frac[gdg.GDG_MIXED]))
+    assert frac[gdg.GDG_FP64] <= 1e-9
+    assert frac[gdg.GDG_MIXED] <= 0.1

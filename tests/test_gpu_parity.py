@@ -329,6 +329,39 @@ def test_quiet_cells_next_to_a_blob(oracle, case):
     assert err <= max(1e-11, 10.0 * spread)
 
 
+QUIET_CASES = {
+    "blob_2d_q1": lambda: blob_on(2, 1, (20, 18), (1, 1, 2, 2)),
+    "blob_3d_q2": lambda: blob_on(3, 2, (6, 5, 6), (2, 1, 0, 0, 1, 2)),
+    "quadrant_2d_q2": lambda: quadrant_on(2, 2, (16, 14), (1, 1, 1, 1)),
+    "blast_3d_q1": lambda: (lambda wl: (wl.mesh, wl.U0))(W.blast(cells=12)),
+}
+
+
+@pytest.mark.parametrize("precision", [gdg.GDG_FP64, gdg.GDG_MIXED])
+@pytest.mark.parametrize("name", sorted(QUIET_CASES))
+def test_quiet_rows_change_no_result(name, precision):
+    """The quiet-row shortcut (limiter pass 1 accepts rows whose whole stencil
+    holds one state without visiting their pairs) against the same run with
+    GDG_FLAG_NO_QUIET_ROWS: bit-identical states after 12 device-driven
+    steps, and the shortcut was taken."""
+    _say("quiet rows off vs on: %s, precision %d" % (name, precision))
+    ms, U = QUIET_CASES[name]()
+    outs, quiet = [], []
+    for flags in (0, gdg.GDG_FLAG_NO_QUIET_ROWS):
+        p = gdg.gdg_default_params(ms.degree)
+        p.precision = precision
+        p.flags = flags
+        S = gdg.Solver.from_spec(ms, p)
+        S.upload(U)
+        st = S.run_to(1e30, max_steps=12)
+        assert st.steps == 12 and st.bound_violations == 0
+        outs.append(S.download())
+        quiet.append(st.quiet_rows)
+        S.close()
+    assert quiet[0] > 0 and quiet[1] == 0, quiet
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_constant_state_exact():
     """A uniform state is a fixed point in every sweep (difference form)."""
     ms = W.MeshSpec(2, 2, (6, 5), (0, 0), (1, 1), (1, 1, 2, 2))
