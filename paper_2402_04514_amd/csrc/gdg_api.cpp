@@ -48,7 +48,7 @@ struct Layout {
   int nloc, nb1, R, cpb, W, M;
   int64_t N, ncells, nblocks, nslots;
   size_t off_ref, off_ctl, off_col, off_c, off_meta, off_kscale, off_U[3], off_Nd, off_Qd, off_Ld, off_U1d,
-      off_dL, off_l1, off_acc, off_fsum, off_red, total;
+      off_dL, off_l1, off_acc, off_fsum, off_red, off_cnt, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -170,6 +170,7 @@ Layout layout(const gdg_mesh_desc *m, const gdg_params *p) {
   L.off_acc = take(N);
   L.off_fsum = take(M * N * 8);
   L.off_red = take((size_t)(kRedBlocks + 1) * kRedFields * 8);
+  L.off_cnt = take((size_t)kCntKinds * kCntSlots * kCntStride * 8);
   L.total = o;
   return L;
 }
@@ -429,6 +430,7 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   A.accepted = (uint8_t *)(ws + L.off_acc);
   A.fsum = (double *)(ws + L.off_fsum);
   A.red = (double *)(ws + L.off_red);
+  A.cnt = (unsigned long long *)(ws + L.off_cnt);
 
   RefTables *T = new RefTables();
   if (!build_ref_tables(mesh->dim, mesh->degree, h, T, &err)) {
@@ -470,6 +472,7 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   hipError_t e1 = hipMemcpyAsync(ctx->dref, T, sizeof(RefTables), hipMemcpyHostToDevice, ctx->stream);
   hipError_t e2 = hipMemcpyAsync(A.ctl, &ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream);
   int rc = (e1 == hipSuccess && e2 == hipSuccess) ? launch_fill(A, ctx->stream) : -1;
+  if (rc == 0) rc = launch_zero_counts(A, ctx->stream);
   hipError_t e4 = rc == 0 ? hipSuccess : hipGetLastError();
   hipError_t e3 = hipStreamSynchronize(ctx->stream);
   Ctl chk;
@@ -533,6 +536,7 @@ gdg_status gdg_upload_state(gdg_ctx *ctx, const double *U, int32_t is_device_ptr
   HIPCHK(ctx, hipMemcpyAsync(ctx->U[ctx->cur], U, bytes, hipMemcpyDefault, ctx->stream));
   std::memset(&ctx->hctl, 0, sizeof(Ctl));
   HIPCHK(ctx, hipMemcpyAsync(ctx->A.ctl, &ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
+  if (gdg_status s = launched(ctx, launch_zero_counts(ctx->A, ctx->stream), "zero counters")) return s;
   if (gdg_status s = launched(ctx, launch_begin(ctx->A, 0.0, 0.0, 0, ctx->stream), "begin")) return s;
   if (gdg_status s = launched(ctx, launch_prim(ctx->A, ctx->U[ctx->cur], 0, ctx->stream), "prim")) return s;
   if (gdg_status s = read_ctl(ctx)) return s;

@@ -56,14 +56,22 @@ struct Ctl {
   int bad_flag;                      // a state left A; read by the host only
   int viol_stage;
   int halt;                          // set by the step's first kernel: skip this step
-  // Counters since the last upload (integer atomics, so their values do not
-  // depend on the order of the blocks): stage outputs of the limited scheme
+  // Counters since the last upload: stage outputs of the limited scheme
   // outside their relaxed bounds (eq. local_bounds), pairs that limiter pass 1
   // cut (l_ij < 1), rows of quiet cells (every flux of the row exactly zero).
+  // The kernels add into kCntSlots spread copies (KArgs::cnt); the statistics
+  // call sums them here.
   unsigned long long bound_violations;
   unsigned long long limited_pairs;
   unsigned long long quiet_rows;
 };
+// Spread counters: counter c of slot s at cnt[(c * kCntSlots + s) * kCntStride]
+// (one 128-byte line each).  A wavefront adds into the slot of its hardware
+// block index, so that the device-scope atomics of the 8 XCDs meet at many
+// addresses instead of one (integer sums: the totals do not depend on the
+// order of the blocks).
+constexpr int kCntSlots = 256, kCntStride = 16;
+enum { kCntViolations = 0, kCntLimited = 1, kCntQuiet = 2, kCntKinds = 3 };
 // Reduction of a state for the statistics call: per block partials, then one
 // block combines them in a fixed order.  min rho, min eps, sum_i m_i U_i.
 // Most cell rows in y of a 3D tile of the sweep order.
@@ -79,17 +87,19 @@ constexpr int kRedFields = 2 + kMaxD + 2;
 //    [0, M) U, [M, M+D) velocity, then p, a, p^-alpha, f(s), s~, 1/p
 //  bound record (kQStride): rho_min, rho_max, s~_min of the ring-1 partials, N_i
 //  limiter record (kLimStride): [0, M) dU^H, [M, 2M) U^L, then rho_min,
-//    rho_max, s~_min of the relaxed bounds, 1/(kappa_i m_i), N_i
+//    rho_max, s~_min of the relaxed bounds, 1/(kappa_i m_i), N_i, and the
+//    stage input U_i (everything a limiter pass needs of a row, in one place)
 //  U^(1) record (kU1Stride): [0, M) the state after limiter pass 1
-constexpr int kNodeStride = 16, kQStride = 4, kLimStride = 16, kU1Stride = 8;
+constexpr int kNodeStride = 16, kQStride = 4, kLimStride = 20, kU1Stride = 8;
 template <int D> struct Rec {
   static constexpr int M = D + 2;
   // node record
   static constexpr int U = 0, u = M, p = 2 * D + 2, a = 2 * D + 3, pal = 2 * D + 4, fs = 2 * D + 5,
                        st = 2 * D + 6, ip = 2 * D + 7, nwide = D + 4;  // nwide: 16-byte loads of the whole record
   // limiter record
-  static constexpr int dUH = 0, UL = M, B = 2 * M, ks = 2 * M + 3, N = 2 * M + 4;
-  static_assert(ip < kNodeStride && N < kLimStride && M <= kU1Stride, "record strides");
+  static constexpr int dUH = 0, UL = M, B = 2 * M, ks = 2 * M + 3, N = 2 * M + 4, LU = 2 * M + 5,
+                       nlim = 3 * M + 5;  // nlim: the limiter record's used doubles
+  static_assert(ip < kNodeStride && nlim <= kLimStride && M <= kU1Stride, "record strides");
 };
 
 // Reference tables of one cell class (every cell of a uniform mesh).
@@ -160,6 +170,7 @@ struct KArgs {
   uint8_t *accepted;  // per row: set by sweep 2 for rows of quiet cells (every flux zero), then by
                       // limiter pass 1: it accepted every flux of the row whole
   double *red;        // kRedBlocks * kRedFields partials of the state reduction, then kRedFields results
+  unsigned long long *cnt;  // spread counters (kCntKinds * kCntSlots lines)
   Ctl *ctl;
 };
 
@@ -210,6 +221,8 @@ int launch_prim(const KArgs &A, const double *U, int stage, void *stream);
 // min rho, min eps and sum_i m_i U_i (per component) of the state U into
 // A.red[kRedBlocks * kRedFields ...], deterministically
 int launch_state_stats(const KArgs &A, const double *U, void *stream);
+// Zeroes the spread counters (a kernel, so that it may be captured).
+int launch_zero_counts(const KArgs &A, void *stream);
 // need_prim: launch the primitives sweep even when the last limiter pass of
 // the previous stage wrote the node cache (the stage input was not produced by
 // a completed stage of this context)

@@ -477,7 +477,9 @@ __device__ __forceinline__ double *node_buffer(const KArgs &A, int stage) {
 // (consecutive rows, so one contiguous range) leave as whole 16-byte chunks
 // of consecutive addresses.  The staging rows are padded by one double so
 // that the lanes' LDS writes spread over the banks.
-constexpr int kStageDoubles = kBlockThreads * (kNodeStride + 1);
+template <int S>
+constexpr int kStage = kBlockThreads * (S + 1);
+constexpr int kStageDoubles = kStage<kNodeStride>;
 
 template <int S>
 __device__ __forceinline__ double *stage_row(double *stage, int lane) {
@@ -750,6 +752,10 @@ __device__ __forceinline__ double block_min_atomic(double v, unsigned long long 
 // Adds the counts v (0 .. 127) of the wave's active lanes to *dst: the sum is
 // assembled bit by bit from ballots, and the first active lane issues one
 // atomic (none if the sum is zero).
+__device__ __forceinline__ unsigned long long *cnt_slot(const KArgs &A, int kind) {
+  return A.cnt + ((size_t)kind * kCntSlots + blockIdx.x % kCntSlots) * kCntStride;
+}
+
 __device__ __forceinline__ void wave_count_add(unsigned long long *dst, unsigned v) {
   const unsigned long long act = __ballot(1);
   unsigned long long tot = 0;
@@ -942,12 +948,16 @@ __device__ __forceinline__ bool stage_tau(const KArgs &A, int stage, double *tau
   return !(*tau > tm);
 }
 
+// Occupancy target of sweep 2 (waves per SIMD): three, except for 2D Q2,
+// whose body spills at three waves' register budget in the slot loop.
+constexpr int sweep2_waves(int d, int deg) { return d == 2 && deg == 2 ? 2 : GDG_WPE_SWEEP; }
+
 template <int D, int DEG, bool MX>
 __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb, int stage, int64_t blk) {
   constexpr int M = D + 2;
   constexpr int NB = DEG + 1;
   constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
-  __shared__ double rs[M][kBlockThreads];
+
   __shared__ int qs[kBlockThreads];
   // The limiter records go out staged in LDS, except on 2D Q2 meshes, where
   // each lane writes its own: measured, staging cut sweep 2 on the 128^3 Q1
@@ -955,7 +965,14 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
   // the 256^2 Q1 vortex from 45 to 32 us, but raised it on the 1024^2 Q2
   // quadrant from 2.4 to 8.5 ms (the same code; the cause is not identified).
   constexpr bool kStaged = !(D == 2 && DEG == 2);
-  __shared__ double stage_lds[kStaged ? kStageDoubles : 1];
+  __shared__ double stage_lds[kStaged ? kStage<kLimStride> : 1];
+  // the residual r^H of the cell solve: in the dU^H slots of the staged
+  // records (overwritten by dU^H after the solve), or an array of its own
+  __shared__ double rs_own[kStaged ? 1 : M][kStaged ? 1 : kBlockThreads];
+  auto rs = [&](int q, int row) -> double & {
+    if constexpr (kStaged) return stage_lds[row * (kLimStride + 1) + Rec<D>::dUH + q];
+    else return rs_own[q][row];
+  };
   double tau;
   if (!stage_tau(A, stage, &tau)) {
     if (stage > 0 && blk == 0 && threadIdx.x == 0 && A.ctl->cfl_flag == 0 && A.ctl->halt == 0) {
@@ -1081,7 +1098,8 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
     lr[R::B + 2] = (1.0 - rel) * smin;
     lr[R::ks] = A.kscale[i];
     lr[R::N] = Ni;
-    for (int q = 0; q < M; ++q) rs[q][lane] = -accH[q];
+    for (int q = 0; q < M; ++q) lr[R::LU + q] = ni.U[q];
+    for (int q = 0; q < M; ++q) rs(q, lane) = -accH[q];
     if (A.scheme == 0 || (A.scheme == 2 && A.passes == 0)) {
       for (int q = 0; q < M; ++q)
         sb.out[q * N + i] = sb.ca == 0.0 ? UL[q] : sb.ca * sb.Un[q * N + i] + sb.cb * UL[q];
@@ -1089,6 +1107,7 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
     }
   }
   __syncthreads();
+  double du[M];
   if (active) {
   // eq. HighScheme: M_K dU^H_K = tau r^H_K for the cell of row i, from LDS
   const int cellbase = lane - a;
@@ -1100,28 +1119,31 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
     int cq = A.no_quiet ? 0 : 1;
     for (int b = 0; b < NLOC; ++b) cq &= qs[cellbase + b];
     A.accepted[i] = (uint8_t)cq;
-    wave_count_add(&A.ctl->quiet_rows, (unsigned)cq);
+    wave_count_add(cnt_slot(A, kCntQuiet), (unsigned)cq);
   }
-  double V[M];
   for (int q = 0; q < M; ++q) {
     double s = 0.0;
-    for (int b = 0; b < NLOC; ++b) s += A.ref->minv[a * NLOC + b] * rs[q][cellbase + b];
-    const double du = tau * s;
-    lr[R::dUH + q] = du;
-    V[q] = ni.U[q] + du;
+    for (int b = 0; b < NLOC; ++b) s += A.ref->minv[a * NLOC + b] * rs(q, cellbase + b);
+    du[q] = tau * s;
   }
   if (A.scheme == 1) {
+    double V[M];
+    for (int q = 0; q < M; ++q) V[q] = ni.U[q] + du[q];
     for (int q = 0; q < M; ++q)
       sb.out[q * N + i] = sb.ca == 0.0 ? V[q] : sb.ca * sb.Un[q * N + i] + sb.cb * V[q];
     if (!(V[0] > 0.0) || !(eps_of<D>(V) > 0.0)) atomicOr(&A.ctl->bad_flag, 1);
   }
   }
+  // the cell's residuals are read: dU^H may take their place
+  if constexpr (kStaged) __syncthreads();
+  if (active)
+    for (int q = 0; q < M; ++q) lr[R::dUH + q] = du[q];
   const int64_t row0 = blk * A.R;
   if constexpr (kStaged) stage_flush<kLimStride>(stage_lds, A.Ld, row0, (int)(N - row0 < A.R ? N - row0 : A.R));
 }
 
 template <int D, int DEG, bool MX>
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_SWEEP))) void k_sweep2(
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(sweep2_waves(D, DEG)))) void k_sweep2(
     KArgs A, StageBufs sb, int stage) {
   sweep2_body<D, DEG, MX>(A, sb, stage, xcd_block(A, blockIdx.x));
 }
@@ -1190,7 +1212,7 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
   constexpr int M = D + 2;
   constexpr int NB = DEG + 1;
   constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
-  constexpr int NL = 2 * M + 5;  // limiter record: dU^H, U^L, bounds, 1/(kappa m), N
+  constexpr int NL = Rec<D>::nlim;  // limiter record: dU^H, U^L, bounds, 1/(kappa m), N, U
   using R = Rec<D>;
   if (A.ctl->halt || A.ctl->cfl_flag) return;  // the same for every block
   __shared__ double stage_lds[kStageDoubles];  // the block's output records
@@ -1215,9 +1237,11 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
   const double mi = A.ref->mlump[a];
   const double hpk = A.ref->hpk[a];
   double Ui[M], Li[M], dUi[M], lri[NL];
-  load_rec<M>(nd + (size_t)i * kNodeStride, Ui);
   load_rec<NL>(A.Ld + (size_t)i * kLimStride, lri);
-  for (int q = 0; q < M; ++q) dUi[q] = lri[R::dUH + q];
+  for (int q = 0; q < M; ++q) {
+    Ui[q] = lri[R::LU + q];
+    dUi[q] = lri[R::dUH + q];
+  }
   if (pass == 0) {
     for (int q = 0; q < M; ++q) Li[q] = lri[R::UL + q];
   } else {
@@ -1265,12 +1289,11 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
       rest = 1.0 - A.l1[s];
       if (rest == 0.0) continue;
     }
-    // the neighbour's state and limiter record: two cache lines
-    double Uj[M], lrj[NL];
-    load_rec<M>(nd + (size_t)j * kNodeStride, Uj);
+    // the neighbour's limiter record, its state included
+    double lrj[NL];
     load_rec<NL>(A.Ld + (size_t)j * kLimStride, lrj);
     double Aij[M];
-    pair_flux<D, NLOC>(A, Uj, lrj + R::dUH, lrj[R::N], meta, a, Ui, dUi, Ni, hpk, tau, d, Aij);
+    pair_flux<D, NLOC>(A, lrj + R::LU, lrj + R::dUH, lrj[R::N], meta, a, Ui, dUi, Ni, hpk, tau, d, Aij);
     bool zero = true;
     for (int q = 0; q < M; ++q) zero = zero && Aij[q] == 0.0;
     if (zero) {
@@ -1320,7 +1343,7 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
     double *u1 = stage_row<kU1Stride>(stage_lds, lane);
     for (int q = 0; q < M; ++q) u1[q] = V[q];
     A.accepted[i] = allone ? 1 : 0;
-    wave_count_add(&A.ctl->limited_pairs, ncut);
+    wave_count_add(cnt_slot(A, kCntLimited), ncut);
   }
   // Lemma ConsInvariants: the pass's output lies in B_i.  Counted with the
   // tolerances of rounding (1e-12 relative on rho, 1e-11 on s~), so that a
@@ -1337,7 +1360,7 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
     } else {
       in = in && re > 0.0 && re / V[0] * pow(V[0], -A.gamma) >= smin * (1.0 - 1e-11);
     }
-    wave_count_add(&A.ctl->bound_violations, in ? 0u : 1u);
+    wave_count_add(cnt_slot(A, kCntViolations), in ? 0u : 1u);
   }
   }  // rows through the pair loop
   }  // rows of the block
@@ -1504,6 +1527,26 @@ __global__ __launch_bounds__(kRedBlocks) void k_state_stats2(KArgs A) {
   }
   if (threadIdx.x == 0)
     for (int f = 0; f < F; ++f) A.red[kRedBlocks * kRedFields + f] = sh[f][0];
+  // the spread counters' totals into the control block
+  __shared__ unsigned long long cs[kCntKinds][kCntSlots];
+  if ((int)threadIdx.x < kCntSlots)
+    for (int c = 0; c < kCntKinds; ++c) cs[c][threadIdx.x] = A.cnt[((size_t)c * kCntSlots + threadIdx.x) * kCntStride];
+  __syncthreads();
+  for (int w = kCntSlots / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int c = 0; c < kCntKinds; ++c) cs[c][threadIdx.x] += cs[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    A.ctl->bound_violations = cs[kCntViolations][0];
+    A.ctl->limited_pairs = cs[kCntLimited][0];
+    A.ctl->quiet_rows = cs[kCntQuiet][0];
+  }
+}
+
+__global__ void k_zero_counts(unsigned long long *cnt, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) cnt[k] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1707,6 +1750,13 @@ int launch_state_stats(const KArgs &A, const double *U, void *stream) {
     case 3: stats_impl<3>(A, U, stream); break;
     default: return -2;
   }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_zero_counts(const KArgs &A, void *stream) {
+  clear_stale();
+  const int n = kCntKinds * kCntSlots * kCntStride;
+  hipLaunchKernelGGL(k_zero_counts, dim3((n + 255) / 256), dim3(256), 0, S(stream), A.cnt, n);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
