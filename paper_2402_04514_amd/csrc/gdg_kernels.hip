@@ -948,10 +948,6 @@ __device__ __forceinline__ bool stage_tau(const KArgs &A, int stage, double *tau
   return !(*tau > tm);
 }
 
-// Occupancy target of sweep 2 (waves per SIMD): three, except for 2D Q2,
-// whose body spills at three waves' register budget in the slot loop.
-constexpr int sweep2_waves(int d, int deg) { return d == 2 && deg == 2 ? 2 : GDG_WPE_SWEEP; }
-
 template <int D, int DEG, bool MX>
 __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb, int stage, int64_t blk) {
   constexpr int M = D + 2;
@@ -959,20 +955,11 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
   constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
 
   __shared__ int qs[kBlockThreads];
-  // The limiter records go out staged in LDS, except on 2D Q2 meshes, where
-  // each lane writes its own: measured, staging cut sweep 2 on the 128^3 Q1
-  // blast from 5.0 to 3.5 ms, on the 40^3 Q2 blast from 1.01 to 0.85 ms and on
-  // the 256^2 Q1 vortex from 45 to 32 us, but raised it on the 1024^2 Q2
-  // quadrant from 2.4 to 8.5 ms (the same code; the cause is not identified).
-  constexpr bool kStaged = !(D == 2 && DEG == 2);
-  __shared__ double stage_lds[kStaged ? kStage<kLimStride> : 1];
-  // the residual r^H of the cell solve: in the dU^H slots of the staged
-  // records (overwritten by dU^H after the solve), or an array of its own
-  __shared__ double rs_own[kStaged ? 1 : M][kStaged ? 1 : kBlockThreads];
-  auto rs = [&](int q, int row) -> double & {
-    if constexpr (kStaged) return stage_lds[row * (kLimStride + 1) + Rec<D>::dUH + q];
-    else return rs_own[q][row];
-  };
+  // The limiter records go out staged in LDS (whole lines of consecutive
+  // rows); the residual r^H of the cell solve lives in their dU^H slots until
+  // dU^H overwrites it.
+  __shared__ double stage_lds[kStage<kLimStride>];
+  auto rs = [&](int q, int row) -> double & { return stage_lds[row * (kLimStride + 1) + Rec<D>::dUH + q]; };
   double tau;
   if (!stage_tau(A, stage, &tau)) {
     if (stage > 0 && blk == 0 && threadIdx.x == 0 && A.ctl->cfl_flag == 0 && A.ctl->halt == 0) {
@@ -989,8 +976,8 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
   const bool active = lane < A.R && i < A.N;
   const int64_t N = A.N;
   const double g = A.gamma;
-  // this row's limiter record (staged, or in place)
-  double *lr = kStaged ? stage_row<kLimStride>(stage_lds, lane) : A.Ld + (size_t)i * kLimStride;
+  // this row's limiter record, staged
+  double *lr = stage_row<kLimStride>(stage_lds, lane);
   Node<D> ni;
   int a = 0;
   if (active) {
@@ -1063,15 +1050,9 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
       smin = fmin(smin, qj[2]);
       if (j == i) continue;
       const double dH = visc_high(A, d, Ni, qj[3], kind, hpk);
-      // U_j: from the neighbour's node record on 3D meshes, from the SoA state
-      // otherwise (of the record only these M values are needed here, and
-      // the SoA planes hold more neighbours per cache line); measured, the
-      // record is faster on the 128^3 Q1 blast (2.7 vs 3.5 ms), the planes on
-      // the 1024^2 Q2 quadrant
+      // U_j from the neighbour's node record
       double Uj[M];
-      if constexpr (D == 3) load_rec<M>(nd + (size_t)j * kNodeStride, Uj);
-      else
-        for (int q = 0; q < M; ++q) Uj[q] = sb.in[q * N + j];
+      load_rec<M>(nd + (size_t)j * kNodeStride, Uj);
       for (int q = 0; q < M; ++q) {
         const double du = Uj[q] - ni.U[q];
         dev += fabs(du);
@@ -1135,15 +1116,15 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
   }
   }
   // the cell's residuals are read: dU^H may take their place
-  if constexpr (kStaged) __syncthreads();
+  __syncthreads();
   if (active)
     for (int q = 0; q < M; ++q) lr[R::dUH + q] = du[q];
   const int64_t row0 = blk * A.R;
-  if constexpr (kStaged) stage_flush<kLimStride>(stage_lds, A.Ld, row0, (int)(N - row0 < A.R ? N - row0 : A.R));
+  stage_flush<kLimStride>(stage_lds, A.Ld, row0, (int)(N - row0 < A.R ? N - row0 : A.R));
 }
 
 template <int D, int DEG, bool MX>
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(sweep2_waves(D, DEG)))) void k_sweep2(
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(GDG_WPE_SWEEP))) void k_sweep2(
     KArgs A, StageBufs sb, int stage) {
   sweep2_body<D, DEG, MX>(A, sb, stage, xcd_block(A, blockIdx.x));
 }
