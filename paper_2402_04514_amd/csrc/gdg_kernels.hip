@@ -745,17 +745,23 @@ __device__ __forceinline__ void ghost_node(const KArgs &A, const Node<D> &ni, in
 
 __device__ __forceinline__ double block_min_atomic(double v, unsigned long long *dst) {
   for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
-  if ((threadIdx.x & 63) == 0) atomicMin(dst, (unsigned long long)__double_as_longlong(v));
+  if ((threadIdx.x & 63) == 0) {
+    // the minimum only falls, so a value not below what the address holds
+    // (even an older copy of it) changes nothing: most wavefronts skip the
+    // atomic, which all of them would otherwise queue on one address
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    if (b < *(volatile unsigned long long *)dst) atomicMin(dst, b);
+  }
   return v;
+}
+
+__device__ __forceinline__ unsigned long long *cnt_slot(const KArgs &A, int kind) {
+  return A.cnt + ((size_t)kind * kCntSlots + blockIdx.x % kCntSlots) * kCntStride;
 }
 
 // Adds the counts v (0 .. 127) of the wave's active lanes to *dst: the sum is
 // assembled bit by bit from ballots, and the first active lane issues one
 // atomic (none if the sum is zero).
-__device__ __forceinline__ unsigned long long *cnt_slot(const KArgs &A, int kind) {
-  return A.cnt + ((size_t)kind * kCntSlots + blockIdx.x % kCntSlots) * kCntStride;
-}
-
 __device__ __forceinline__ void wave_count_add(unsigned long long *dst, unsigned v) {
   const unsigned long long act = __ballot(1);
   unsigned long long tot = 0;
