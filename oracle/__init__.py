@@ -67,6 +67,8 @@ def lib():
         L = _lib
         L.or_create.restype = C.c_void_p
         L.or_create.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_long), _DP, _DP, C.POINTER(C.c_int)]
+        L.or_create_mapped.restype = C.c_void_p
+        L.or_create_mapped.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_long), _DP, C.POINTER(C.c_int)]
         L.or_destroy.argtypes = [C.c_void_p]
         L.or_num_threads.restype = C.c_int
         L.or_num_threads.argtypes = []
@@ -128,13 +130,15 @@ def params(gamma=1.4, cfl=0.5, degree=1, c_ev=None, c_k=1.0, c_r=4.0, p_r=1.5, p
 class Mesh:
     """Uniform Cartesian DG Q_k mesh with the stencil of Sec. 2.3."""
 
-    def __init__(self, dim, degree, cells, lo, hi, bc, bstate=None, vortex=None):
+    def __init__(self, dim, degree, cells, lo, hi, bc, bstate=None, vortex=None, vertices=None):
         """bc: kinds per box face 2*axis+side (0 periodic, 1 outflow, 2 slip,
         3 Dirichlet, 4 supersonic in/outflow, 5 sub- and supersonic
         in/outflow).  bstate: per face the conserved Dirichlet data U^d of
         kinds 3-5 (None elsewhere).  vortex: (beta, x0_1, x0_2, u_1, u_2,
         gamma) to take the data of kinds 3-5 from the isentropic vortex at the
-        node and the stage time instead (2D)."""
+        node and the stage time instead (2D).  vertices: the cell lattice's
+        vertices, shape ((n_0+1)(n_1+1)..., dim), x fastest, for general
+        (multilinearly mapped) cells; lo and hi are then ignored."""
         self.dim, self.degree = dim, degree
         self.cells = tuple(int(c) for c in cells)
         self.lo = tuple(float(x) for x in lo)
@@ -145,7 +149,14 @@ class Mesh:
         lo_ = (C.c_double * 3)(*(list(self.lo) + [0.0] * (3 - dim)))
         hi_ = (C.c_double * 3)(*(list(self.hi) + [1.0] * (3 - dim)))
         b = (C.c_int * 6)(*(list(self.bc) + [1] * (6 - len(self.bc))))
-        self._h = L.or_create(dim, degree, c, lo_, hi_, b)
+        if vertices is not None:
+            vx = np.ascontiguousarray(vertices, dtype=np.float64)
+            nv = int(np.prod([n + 1 for n in self.cells]))
+            assert vx.shape == (nv, dim), (vx.shape, nv, dim)
+            self._vx = vx
+            self._h = L.or_create_mapped(dim, degree, c, _dp(vx), b)
+        else:
+            self._h = L.or_create(dim, degree, c, lo_, hi_, b)
         if not self._h:
             raise ValueError("invalid mesh description")
         self.ndofs = L.or_num_dofs(self._h)

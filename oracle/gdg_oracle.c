@@ -77,7 +77,12 @@ typedef struct {
   /* reference tables */
   double xg[4];  /* Gauss-Lobatto nodes on [0,1] */
   int nq;
-  double xq[4], wq[4]; /* Gauss-Legendre rule on [0,1] */
+  double xq[8], wq[8]; /* Gauss-Legendre rule on [0,1] */
+  /* general (non-affine) cells: the vertices of the cell lattice,
+   * (n_0+1)(n_1+1)(n_2+1) points of dim coordinates, x fastest; every cell is
+   * the multilinear image of the reference cell through its 2^dim corners.
+   * NULL: the uniform box lo .. hi. */
+  double *vx;
 } or_setup;
 
 /* ------------------------------------------------------------------------ */
@@ -132,6 +137,146 @@ static long neighbour(const or_setup *S, long K, int f) {
     ki[e] = (ki[e] + S->n[e]) % S->n[e];
   }
   return cell_index(S, ki);
+}
+
+/* ------------------------------------------------------------------------ */
+/* General cells: the multilinear map of cell K and the integrals of Sec. 2.3 */
+/* written with its Jacobian (change of variables x = F_K(xi)).               */
+/* ------------------------------------------------------------------------ */
+
+/* x = F_K(xi) = sum over the corners v of X_v prod_e (xi_e if bit e of v else
+ * 1 - xi_e), and J[r][c] = dx_r / dxi_c. */
+static void cell_map(const or_setup *S, long K, const double *xi, double *x, double J[3][3]) {
+  long ki[3];
+  cell_multi(S, K, ki);
+  const int dim = S->dim;
+  for (int r = 0; r < 3; ++r) {
+    x[r] = 0.0;
+    for (int c = 0; c < 3; ++c) J[r][c] = 0.0;
+  }
+  for (int v = 0; v < (1 << dim); ++v) {
+    long vi = 0, stride = 1;
+    double w = 1.0, dw[3];
+    for (int e = 0; e < dim; ++e) {
+      int bit = (v >> e) & 1;
+      vi += (ki[e] + bit) * stride;
+      stride *= S->n[e] + 1;
+      w *= bit ? xi[e] : 1.0 - xi[e];
+    }
+    for (int c = 0; c < dim; ++c) {
+      dw[c] = 1.0;
+      for (int e = 0; e < dim; ++e) {
+        int bit = (v >> e) & 1;
+        if (e == c) dw[c] *= bit ? 1.0 : -1.0;
+        else dw[c] *= bit ? xi[e] : 1.0 - xi[e];
+      }
+    }
+    const double *X = S->vx + vi * dim;
+    for (int r = 0; r < dim; ++r) {
+      x[r] += w * X[r];
+      for (int c = 0; c < dim; ++c) J[r][c] += dw[c] * X[r];
+    }
+  }
+}
+
+/* det J and Ji = J^{-1} (dim 1, 2 or 3). */
+static double inverse(int dim, double J[3][3], double Ji[3][3]) {
+  double det;
+  if (dim == 1) {
+    det = J[0][0];
+    Ji[0][0] = 1.0 / det;
+    return det;
+  }
+  if (dim == 2) {
+    det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    Ji[0][0] = J[1][1] / det;
+    Ji[0][1] = -J[0][1] / det;
+    Ji[1][0] = -J[1][0] / det;
+    Ji[1][1] = J[0][0] / det;
+    return det;
+  }
+  det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+        J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      /* the cofactor of J[c][r] over det */
+      int r1 = (c + 1) % 3, r2 = (c + 2) % 3, c1 = (r + 1) % 3, c2 = (r + 2) % 3;
+      Ji[r][c] = (J[r1][c1] * J[r2][c2] - J[r1][c2] * J[r2][c1]) / det;
+    }
+  return det;
+}
+
+static double phi(const or_setup *S, int a, const double *xi);
+
+/* Reference gradient d phi_a / d xi. */
+static void grad_ref(const or_setup *S, int a, const double *xi, double *g) {
+  int ai[3];
+  local_multi(S, a, ai);
+  for (int c = 0; c < S->dim; ++c) {
+    double v = 1.0;
+    for (int e = 0; e < S->dim; ++e) v *= (e == c) ? dlag(S, ai[e], xi[e]) : lag(S, ai[e], xi[e]);
+    g[c] = v;
+  }
+}
+
+/* Over general cell K, by the tensor Gauss rule: kind 0 m_ab = int phi_a
+ * phi_b, kind 1 int phi_a grad phi_b (out[0 .. dim)), kind 2 int phi_a; with
+ * grad phi = J^{-T} grad_xi phi and dx = det J dxi. */
+static void cell_integral_mapped(const or_setup *S, long K, int kind, int a, int b, double *out) {
+  const int dim = S->dim, nq = S->nq;
+  int tot = 1;
+  for (int e = 0; e < dim; ++e) tot *= nq;
+  for (int e = 0; e < 3; ++e) out[e] = 0.0;
+  for (int q = 0; q < tot; ++q) {
+    double xi[3] = {0, 0, 0}, w = 1.0;
+    int r = q;
+    for (int e = 0; e < dim; ++e) { xi[e] = S->xq[r % nq]; w *= S->wq[r % nq]; r /= nq; }
+    double x[3], J[3][3], Ji[3][3];
+    cell_map(S, K, xi, x, J);
+    const double det = inverse(dim, J, Ji);
+    const double pa = phi(S, a, xi);
+    if (kind == 0) out[0] += w * pa * phi(S, b, xi) * det;
+    else if (kind == 2) out[0] += w * pa * det;
+    else {
+      double g[3];
+      grad_ref(S, b, xi, g);
+      for (int e = 0; e < dim; ++e) {
+        double ge = 0.0;
+        for (int c = 0; c < dim; ++c) ge += Ji[c][e] * g[c];
+        out[e] += w * pa * ge * det;
+      }
+    }
+  }
+}
+
+/* Over face f = 2e + side of general cell K: int_F phi_a phi_b n ds (out[0 ..
+ * dim)), n the outward unit normal of K; phi_b of the same cell or of the
+ * neighbour across f (its reference coordinate e is 1 - side), b < 0 meaning 1.
+ * n ds = (outward sign) det J J^{-T} e_e dxi over the face (Nanson's formula). */
+static void face_integral_mapped(const or_setup *S, long K, int f, int a, int b, int same_cell, double *out) {
+  const int dim = S->dim, nq = S->nq, e = f / 2, side = f % 2;
+  int tot = 1;
+  for (int d = 0; d < dim - 1; ++d) tot *= nq;
+  for (int d = 0; d < 3; ++d) out[d] = 0.0;
+  for (int q = 0; q < tot; ++q) {
+    double xi[3] = {0, 0, 0}, w = 1.0;
+    int r = q;
+    for (int d = 0; d < dim; ++d) {
+      if (d == e) { xi[d] = side ? 1.0 : 0.0; continue; }
+      xi[d] = S->xq[r % nq]; w *= S->wq[r % nq]; r /= nq;
+    }
+    double x[3], J[3][3], Ji[3][3];
+    cell_map(S, K, xi, x, J);
+    const double det = inverse(dim, J, Ji);
+    double va = phi(S, a, xi), vb = 1.0;
+    if (b >= 0) {
+      double xb[3] = {xi[0], xi[1], xi[2]};
+      if (!same_cell) xb[e] = 1.0 - xi[e];
+      vb = phi(S, b, xb);
+    }
+    const double sgn = side ? 1.0 : -1.0;
+    for (int d = 0; d < dim; ++d) out[d] += w * va * vb * sgn * det * Ji[e][d];
+  }
 }
 
 /* Tensor-product basis value / gradient at reference point xi of the cell. */
@@ -212,6 +357,28 @@ static void literal_cij(const or_setup *S, long i, long j, double *out) {
   local_multi(S, a, ai);
   local_multi(S, b, bi);
   for (int e = 0; e < S->dim; ++e) out[e] = 0.0;
+  if (S->vx) {
+    /* general cells: the same definitions with vector-valued face normals */
+    double t[3];
+    if (Ki == Kj) {
+      cell_integral_mapped(S, Ki, 1, a, b, out);
+      for (int f = 0; f < 2 * S->dim; ++f) {
+        face_integral_mapped(S, Ki, f, a, b, 1, t);
+        for (int e = 0; e < S->dim; ++e) out[e] -= 0.5 * t[e];
+      }
+      return;
+    }
+    for (int f = 0; f < 2 * S->dim; ++f) {
+      int e = f / 2, side = f % 2;
+      if (ai[e] != side * S->deg) continue;
+      if (bi[e] != (1 - side) * S->deg) continue;
+      if (neighbour(S, Ki, f) != Kj) continue;
+      face_integral_mapped(S, Ki, f, a, b, 0, t);
+      for (int d = 0; d < S->dim; ++d) out[d] = 0.5 * t[d];
+      return;
+    }
+    return;
+  }
   if (Ki == Kj) {
     for (int e = 0; e < S->dim; ++e) {
       pair_arg p = {a, b, e};
@@ -251,14 +418,102 @@ static void canonical_cij(const or_setup *S, long i, long j, double *out) {
 void or_destroy(or_setup *S) {
   if (!S) return;
   free(S->rowptr); free(S->col); free(S->c); free(S->mij); free(S->kind); free(S->mi);
-  free(S->bptr); free(S->bface); free(S->bc_c);
+  free(S->bptr); free(S->bface); free(S->bc_c); free(S->vx);
   free(S);
 }
+
+/* Gauss-Legendre rule of n points on [0, 1]: the roots of the Legendre
+ * polynomial P_n by Newton's method from the Chebyshev guesses, P_n and its
+ * derivative by the three-term recurrence; weights 2 / ((1 - x^2) P_n'(x)^2)
+ * on [-1, 1], halved on [0, 1]. */
+static void gauss_rule(int n, double *x01, double *w01) {
+  for (int k = 0; k < n; ++k) {
+    double x = cos(OR_PI * (k + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int m = 2; m <= n; ++m) {
+        double p2 = ((2.0 * m - 1.0) * x * p1 - (m - 1.0) * p0) / m;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      double dx = p1 / dp;
+      x -= dx;
+      if (fabs(dx) < 1e-16) break;
+    }
+    {
+      double p0 = 1.0, p1 = x;
+      for (int m = 2; m <= n; ++m) {
+        double p2 = ((2.0 * m - 1.0) * x * p1 - (m - 1.0) * p0) / m;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+    }
+    x01[n - 1 - k] = 0.5 * (1.0 + x);
+    w01[n - 1 - k] = 1.0 / ((1.0 - x * x) * dp * dp);
+  }
+}
+
+static or_setup *setup_init(int dim, int deg, const long *cells, const double *lo, const double *hi, const int *bc);
+static void setup_build(or_setup *S);
 
 /* Setup: GL nodes, cell-major numbering, m_ij, m_i, c_ij, c_i^{d,k} (Sec. 2.3,
  * Sec. 4.2).  Exact Gauss-Legendre integration with k+1 points (reading R5). */
 or_setup *or_create(int dim, int deg, const long *cells, const double *lo, const double *hi,
                     const int *bc) {
+  or_setup *S = setup_init(dim, deg, cells, lo, hi, bc);
+  if (S) setup_build(S);
+  return S;
+}
+
+/* The same on general cells: vx holds the (n_0+1)(n_1+1)(n_2+1) vertices of
+ * the cell lattice (dim coordinates each, x fastest; on a periodic axis the
+ * last layer is the first one shifted by the period).  The integrals use the
+ * Gauss rule of k + 2 points (exact for the multilinear maps' polynomial
+ * integrands); |Omega| is the sum of the cells' volumes.  NULL if a cell's
+ * Jacobian determinant is not positive at a node or a Gauss point. */
+or_setup *or_create_mapped(int dim, int deg, const long *cells, const double *vx, const int *bc) {
+  double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+  or_setup *S = setup_init(dim, deg, cells, lo, hi, bc);
+  if (!S) return NULL;
+  long nv = 1;
+  for (int e = 0; e < dim; ++e) nv *= S->n[e] + 1;
+  S->vx = (double *)malloc(nv * dim * sizeof(double));
+  memcpy(S->vx, vx, nv * dim * sizeof(double));
+  S->nq = deg + 2;
+  gauss_rule(S->nq, S->xq, S->wq);
+  /* admissible cells, and the volume */
+  double vol = 0.0;
+  for (long K = 0; K < S->ncells; ++K) {
+    double t[3];
+    cell_integral_mapped(S, K, 2, 0, 0, t);
+    for (int a = 0; a < S->nloc; ++a) {
+      int ai[3];
+      local_multi(S, a, ai);
+      double xi[3] = {0, 0, 0}, x[3], J[3][3], Ji[3][3];
+      for (int e = 0; e < dim; ++e) xi[e] = S->xg[ai[e]];
+      cell_map(S, K, xi, x, J);
+      if (!(inverse(dim, J, Ji) > 0.0)) { free(S->vx); free(S); return NULL; }
+    }
+    int tot = 1;
+    for (int e = 0; e < dim; ++e) tot *= S->nq;
+    for (int q = 0; q < tot; ++q) {
+      double xi[3] = {0, 0, 0}, w = 1.0, x[3], J[3][3], Ji[3][3];
+      int r = q;
+      for (int e = 0; e < dim; ++e) { xi[e] = S->xq[r % S->nq]; w *= S->wq[r % S->nq]; r /= S->nq; }
+      cell_map(S, K, xi, x, J);
+      const double det = inverse(dim, J, Ji);
+      if (!(det > 0.0)) { free(S->vx); free(S); return NULL; }
+      vol += w * det;
+    }
+  }
+  S->vol = vol;
+  setup_build(S);
+  return S;
+}
+
+static or_setup *setup_init(int dim, int deg, const long *cells, const double *lo, const double *hi, const int *bc) {
   if (dim < 1 || dim > 3 || deg < 1 || deg > 3) return NULL;
   or_setup *S = (or_setup *)calloc(1, sizeof(or_setup));
   S->dim = dim; S->deg = deg; S->nb1 = deg + 1; S->m = dim + 2;
@@ -305,7 +560,11 @@ or_setup *or_create(int dim, int deg, const long *cells, const double *lo, const
     S->xq[2] = 0.5 * (1.0 + xi); S->xq[3] = 0.5 * (1.0 + xo);
     S->wq[0] = S->wq[3] = 0.5 * wo; S->wq[1] = S->wq[2] = 0.5 * wi;
   }
+  return S;
+}
 
+static void setup_build(or_setup *S) {
+  const int dim = S->dim, deg = S->deg;
   long N = S->ndofs;
   int nloc = S->nloc;
   /* stencil rows: all in-cell dofs, then face neighbours on each face i lies on */
@@ -354,12 +613,15 @@ or_setup *or_create(int dim, int deg, const long *cells, const double *lo, const
     int a = (int)(i % nloc), ai[3];
     local_multi(S, a, ai);
     long nnz = S->rowptr[i], nb = S->bptr[i];
-    S->mi[i] = mloc[a];
+    double t[3];
+    if (S->vx) cell_integral_mapped(S, K, 2, a, 0, t);
+    S->mi[i] = S->vx ? t[0] : mloc[a];
     for (int b = 0; b < nloc; ++b) {
       long j = K * nloc + b;
       S->col[nnz] = j;
       canonical_cij(S, i, j, S->c + nnz * dim);
-      S->mij[nnz] = Mloc[a * nloc + b];
+      if (S->vx) cell_integral_mapped(S, K, 0, a, b, t);
+      S->mij[nnz] = S->vx ? t[0] : Mloc[a * nloc + b];
       S->kind[nnz] = OR_KIND_CELL;
       ++nnz;
     }
@@ -385,7 +647,12 @@ or_setup *or_create(int dim, int deg, const long *cells, const double *lo, const
         /* boundary part k = face f: c_i^{d,k} = 1/2 int_{dK cap dOmega_k} phi_i n */
         double n = side ? 1.0 : -1.0;
         for (int d = 0; d < dim; ++d) S->bc_c[nb * dim + d] = 0.0;
-        S->bc_c[nb * dim + e] = 0.5 * n * face_integral(S, f, a, -1, 1);
+        if (S->vx) {
+          face_integral_mapped(S, K, f, a, -1, 1, t);
+          for (int d = 0; d < dim; ++d) S->bc_c[nb * dim + d] = 0.5 * t[d];
+        } else {
+          S->bc_c[nb * dim + e] = 0.5 * n * face_integral(S, f, a, -1, 1);
+        }
         S->bface[nb] = f;
         ++nb;
       }
@@ -393,7 +660,6 @@ or_setup *or_create(int dim, int deg, const long *cells, const double *lo, const
   }
   free(Mloc);
   free(mloc);
-  return S;
 }
 
 /* threads the row loops use (OpenMP) */
@@ -447,15 +713,10 @@ void or_boundary(const or_setup *S, long *bptr, int *bface, double *bc_c) {
 }
 
 /* Collocation points x_i. */
+static void node_x(const or_setup *S, long i, double *x);
+
 void or_node_coords(const or_setup *S, double *xyz) {
-  for (long i = 0; i < S->ndofs; ++i) {
-    long ki[3];
-    int ai[3];
-    cell_multi(S, i / S->nloc, ki);
-    local_multi(S, (int)(i % S->nloc), ai);
-    for (int e = 0; e < S->dim; ++e)
-      xyz[i * S->dim + e] = S->lo[e] + (ki[e] + S->xg[ai[e]]) * S->h[e];
-  }
+  for (long i = 0; i < S->ndofs; ++i) node_x(S, i, xyz + i * S->dim);
 }
 
 /* literal c_ij for both orders (pins Lemma PropSkew without the R3 reading) */
@@ -633,6 +894,12 @@ static void node_x(const or_setup *S, long i, double *x) {
   int ai[3];
   cell_multi(S, i / S->nloc, ki);
   local_multi(S, (int)(i % S->nloc), ai);
+  if (S->vx) {
+    double xi[3] = {0, 0, 0}, J[3][3];
+    for (int e = 0; e < S->dim; ++e) xi[e] = S->xg[ai[e]];
+    cell_map(S, i / S->nloc, xi, x, J);
+    return;
+  }
   for (int e = 0; e < S->dim; ++e) x[e] = S->lo[e] + (ki[e] + S->xg[ai[e]]) * S->h[e];
 }
 

@@ -1,0 +1,170 @@
+"""Pins of the oracle on general (non-affine) cells: every cell the
+multilinear image of the reference cell through its corners, the stencil of
+Sec. 2.3 (eq. cij_def1, cij_def2, mass_matrices) integrated with the map's
+Jacobian.
+
+* Lattice vertices (affine cells) give the uniform mesh's coefficients.
+* Moving interior vertices only (the boundary stays on the box) keeps the
+  union of the cells: sum_i m_i = |box|, and the boundary parts of each face
+  sum to half its area times its normal; Lemma LemPart (sum_j c_ij + c_i^d =
+  0), Lemma PropSkew (c_ij = -c_ji, written out both ways) and sum_j m_ij = m_i
+  hold row by row.
+* In 2D the cell areas are the shoelace areas of the corner polygons.
+* Rotating every vertex rotates every c_ij and c_i^d and leaves the masses.
+* The limited scheme keeps a uniform stream on a perturbed mesh, and converges
+  at second order (Q1) on the vortex with a perturbed periodic mesh.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2402_04514_amd import workloads as W
+
+from test_oracle_scheme import _l1
+
+
+def lattice(cells, lo, hi):
+    axes = [np.linspace(lo[e], hi[e], cells[e] + 1) for e in range(len(cells))]
+    grids = np.meshgrid(*axes, indexing="ij")
+    # x fastest
+    return np.stack([g.transpose(*reversed(range(len(cells)))).ravel() for g in grids], axis=1)
+
+
+def perturbed(cells, lo, hi, amp=0.25, seed=3, periodic=False):
+    """Interior vertices moved by up to amp cell widths (random, seeded), or
+    by a smooth periodic field that vanishes on the boundary (periodic)."""
+    V = lattice(cells, lo, hi)
+    d = len(cells)
+    h = np.array([(hi[e] - lo[e]) / cells[e] for e in range(d)])
+    idx = np.stack(np.unravel_index(np.arange(V.shape[0]), tuple(c + 1 for c in reversed(cells))), axis=1)[:, ::-1]
+    interior = np.all((idx > 0) & (idx < np.array(cells)), axis=1)
+    if periodic:
+        xi = (V - np.array(lo)) / (np.array(hi) - np.array(lo))
+        s = np.prod(np.sin(2 * np.pi * xi), axis=1)
+        for e in range(d):
+            V[:, e] += amp * h[e] * s * (1 if e % 2 == 0 else -1)
+        return V
+    rng = np.random.default_rng(seed)
+    V[interior] += amp * h * rng.uniform(-1, 1, size=(int(interior.sum()), d))
+    return V
+
+
+MESHES = {
+    "2d_q1": (2, 1, (5, 4)), "2d_q2": (2, 2, (4, 3)), "2d_q3": (2, 3, (3, 3)),
+    "3d_q1": (3, 1, (3, 3, 2)), "3d_q2": (3, 2, (2, 2, 2)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MESHES))
+def test_lattice_vertices_give_the_uniform_mesh(oracle, name):
+    dim, k, cells = MESHES[name]
+    lo, hi = (0.0,) * dim, tuple(1.0 + 0.5 * e for e in range(dim))
+    bc = (2,) * (2 * dim)
+    A = oracle.Mesh(dim, k, cells, lo, hi, bc)
+    B = oracle.Mesh(dim, k, cells, lo, hi, bc, vertices=lattice(cells, lo, hi))
+    ra, ca, cca, ma, _ = A.csr()
+    rb, cb, ccb, mb, _ = B.csr()
+    assert np.array_equal(ca, cb)
+    assert np.abs(cca - ccb).max() < 1e-14 and np.abs(ma - mb).max() < 1e-14
+    assert np.abs(A.lumped() - B.lumped()).max() < 1e-14
+    assert np.abs(A.boundary()[2] - B.boundary()[2]).max() < 1e-14
+    assert np.abs(A.coords() - B.coords()).max() < 1e-14
+    assert B.volume == pytest.approx(A.volume, rel=1e-13)
+
+
+@pytest.mark.parametrize("name", sorted(MESHES))
+def test_identities_on_perturbed_cells(oracle, name):
+    dim, k, cells = MESHES[name]
+    lo, hi = (0.0,) * dim, (1.0,) * dim
+    V = perturbed(cells, lo, hi)
+    M = oracle.Mesh(dim, k, cells, lo, hi, (2,) * (2 * dim), vertices=V)
+    rowptr, col, c, mij, kind = M.csr()
+    bptr, bface, bc_c = M.boundary()
+    mi = M.lumped()
+    N = M.ndofs
+    scale = np.abs(c).max()
+    # the union of the cells is the box
+    assert mi.sum() == pytest.approx(1.0, rel=1e-13)
+    assert M.volume == pytest.approx(1.0, rel=1e-13)
+    for i in range(N):
+        sl = slice(rowptr[i], rowptr[i + 1])
+        tot = c[sl].sum(0) + bc_c[bptr[i]:bptr[i + 1]].sum(0)
+        assert np.abs(tot).max() < 1e-13 * scale, (i, tot)  # Lemma LemPart
+        assert mij[sl].sum() == pytest.approx(mi[i], rel=1e-13)
+    # Lemma PropSkew, each pair's integrals written out both ways
+    rng = np.random.default_rng(9)
+    for i in rng.choice(N, size=min(N, 40), replace=False):
+        for j in col[rowptr[i]:rowptr[i + 1]]:
+            if j == i:
+                continue
+            assert np.abs(M.literal_cij(i, j) + M.literal_cij(j, i)).max() < 1e-14 * scale
+    # each face's boundary parts sum to half its area times its outward normal
+    for f in range(2 * dim):
+        e, side = divmod(f, 2)
+        n = np.zeros(dim)
+        n[e] = 1.0 if side else -1.0
+        assert np.abs(bc_c[bface == f].sum(0) - 0.5 * n).max() < 1e-13
+
+
+def test_cell_areas_are_the_shoelace_areas(oracle):
+    cells = (4, 3)
+    V = perturbed(cells, (0.0, 0.0), (1.0, 1.0), amp=0.3, seed=11)
+    for k in (1, 2, 3):
+        M = oracle.Mesh(2, k, cells, (0, 0), (1, 1), (1,) * 4, vertices=V)
+        mi = M.lumped().reshape(-1, (k + 1) ** 2).sum(1)
+        for K in range(cells[0] * cells[1]):
+            ix, iy = K % cells[0], K // cells[0]
+            corners = [(ix, iy), (ix + 1, iy), (ix + 1, iy + 1), (ix, iy + 1)]
+            P = np.array([V[y * (cells[0] + 1) + x] for x, y in corners])
+            area = 0.5 * abs(np.dot(P[:, 0], np.roll(P[:, 1], -1)) - np.dot(P[:, 1], np.roll(P[:, 0], -1)))
+            assert mi[K] == pytest.approx(area, rel=1e-13), (k, K)
+
+
+@pytest.mark.parametrize("dim,k", [(2, 1), (2, 2), (3, 1)])
+def test_rotation_rotates_the_coefficients(oracle, dim, k):
+    cells = (3,) * dim
+    V = perturbed(cells, (0.0,) * dim, (1.0,) * dim, amp=0.3, seed=5)
+    if dim == 2:
+        th = 0.7
+        R = np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]])
+    else:
+        a, b = 0.7, -0.4
+        Rz = np.array([[math.cos(a), -math.sin(a), 0], [math.sin(a), math.cos(a), 0], [0, 0, 1]])
+        Rx = np.array([[1, 0, 0], [0, math.cos(b), -math.sin(b)], [0, math.sin(b), math.cos(b)]])
+        R = Rz @ Rx
+    A = oracle.Mesh(dim, k, cells, (0,) * dim, (1,) * dim, (1,) * (2 * dim), vertices=V)
+    B = oracle.Mesh(dim, k, cells, (0,) * dim, (1,) * dim, (1,) * (2 * dim), vertices=V @ R.T)
+    _, _, ca, ma, _ = A.csr()
+    _, _, cb, mb, _ = B.csr()
+    assert np.abs(ca @ R.T - cb).max() < 1e-13 * np.abs(ca).max()
+    assert np.abs(ma - mb).max() < 1e-13 * np.abs(ma).max()
+    assert np.abs(A.boundary()[2] @ R.T - B.boundary()[2]).max() < 1e-13
+    assert np.abs(A.coords() @ R.T - B.coords()).max() < 1e-13
+
+
+def test_uniform_stream_on_perturbed_cells(oracle):
+    cells = (6, 5)
+    for k in (1, 2):
+        M = oracle.Mesh(2, k, cells, (0, 0), (1, 1), (0,) * 4, vertices=perturbed(cells, (0, 0), (1, 1),
+                                                                                  periodic=True))
+        N = M.ndofs
+        U = W.to_conserved(np.full(N, 1.3), np.stack([np.full(N, 0.4), np.full(N, -0.2)]), np.full(N, 0.9))
+        out = M.stage(oracle.params(degree=k), U)
+        assert np.abs(out - U).max() < 1e-14
+
+
+def test_vortex_converges_on_perturbed_periodic_cells(oracle):
+    """Limited Q1 on the vortex (periodic [-5, 5]^2, cells moved by a smooth
+    periodic field of a quarter cell) to t = 0.5: near second order between
+    16^2, 32^2 and 64^2 cells (measured 1.77 then 1.85, rising)."""
+    tf = 0.5
+    errs = []
+    for n in (16, 32, 64):
+        V = perturbed((n, n), (-5.0, -5.0), (5.0, 5.0), amp=0.25, periodic=True)
+        M = oracle.Mesh(2, 1, (n, n), (-5.0, -5.0), (5.0, 5.0), (0,) * 4, vertices=V)
+        U0 = W.vortex_exact(M.coords(), 0.0)
+        U, _, _ = M.run_to(oracle.params(), U0, tf)
+        errs.append(_l1(M, U, W.vortex_exact(M.coords(), tf)))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert rates[1] > 1.7, (errs, rates)

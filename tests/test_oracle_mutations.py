@@ -18,9 +18,21 @@ SETUP, PHYS, SCHEME = T + "test_oracle_setup.py", T + "test_oracle_physics.py", 
 BND = T + "test_oracle_boundary.py"
 VISC = T + "test_oracle_viscosity.py"
 INOUT = T + "test_oracle_inoutflow.py"
+MAPPED = T + "test_oracle_mapped.py"
 
 MUTANTS = {
     # name: (original text, planted text, pin files that must fail)
+    "mapped_gradient_transposed": ("for (int c = 0; c < dim; ++c) ge += Ji[c][e] * g[c];",
+                                   "for (int c = 0; c < dim; ++c) ge += Ji[e][c] * g[c];",
+                                   [MAPPED + "::test_identities_on_perturbed_cells"]),
+    "mapped_mass_without_det": ("else if (kind == 2) out[0] += w * pa * det;",
+                                "else if (kind == 2) out[0] += w * pa;", [MAPPED + "::test_cell_areas_are_the_shoelace_areas"]),
+    "mapped_normal_transposed": ("out[d] += w * va * vb * sgn * det * Ji[e][d];",
+                                 "out[d] += w * va * vb * sgn * det * Ji[d][e];",
+                                 [MAPPED + "::test_identities_on_perturbed_cells"]),
+    "mapped_corner_mirrored": ("      w *= bit ? xi[e] : 1.0 - xi[e];\n    }",
+                               "      w *= bit ? 1.0 - xi[e] : xi[e];\n    }",
+                               [MAPPED + "::test_lattice_vertices_give_the_uniform_mesh"]),
     "supersonic_inflow_keeps_state": ("if (un < -a) {\n      data_state(S, f, i, t, Ug);",
                                       "if (un < -1e300) {\n      data_state(S, f, i, t, Ug);",
                                       [BND + "::test_supersonic_inflow_converges_to_riemann_fan"]),
