@@ -104,14 +104,28 @@ typedef enum { GDG_LOW_ORDER = 0, GDG_HIGH_ORDER = 1, GDG_LIMITED = 2 } gdg_sche
  * boundary parts use the double-precision flux that their bar state needs. */
 typedef enum { GDG_FP64 = 0, GDG_MIXED = 1 } gdg_precision;
 
-/* Uniform Cartesian mesh of cells[0] x cells[1] x cells[2] cells over the box
+/* Cartesian mesh of cells[0] x cells[1] x cells[2] cells over the box
  * [lo, hi] (only the first dim entries are read), Q_degree elements with
  * degree 1 or 2 in dim 1..3 and degree 3 in dim 1 and 2, bc[2*dim] boundary
  * kinds.  With data_kind GDG_DATA_CONSTANT, bc_state[f] holds the conserved
  * data (rho, momentum, E: the first dim+2 entries) of face f for the
  * DIRICHLET, SUPERSONIC and INOUTFLOW kinds; it must be admissible (rho > 0,
  * eps > 0) on those faces and is ignored elsewhere.  With GDG_DATA_VORTEX
- * the data of those faces come from the vortex (vortex[]). */
+ * the data of those faces come from the vortex (vortex[]).
+ *
+ * General cells (Sec. 2.3): with vertices non-NULL the cells keep the
+ * lattice's connectivity but each one is the multilinear image of the unit
+ * square or cube through its own 2^dim corners.  vertices holds
+ * (cells[0]+1) x .. x (cells[dim-1]+1) points of dim coordinates each
+ * (interleaved per point, the first axis fastest: point (p0, p1, p2) at
+ * index p0 + (cells[0]+1) (p1 + (cells[1]+1) p2)); cell (k0, k1, k2) takes the
+ * points (k0 + b0, k1 + b1, k2 + b2), b in {0, 1}^dim.  lo and hi are not
+ * read.  m_ij, c_ij and the boundary parts c_i^d are integrated through the
+ * map, so every Jacobian determinant must be positive (else GDG_E_INVALID).
+ * A periodic axis identifies the lattice's first and last layers of cells
+ * across it; the caller keeps the two boundary layers of points congruent.
+ * The pointer is read during gdg_create() only (the context keeps a copy for
+ * gdg_node_coords()).  Not combined with GDG_DATA_VORTEX. */
 typedef struct {
   int32_t dim;
   int32_t degree;
@@ -123,6 +137,7 @@ typedef struct {
   int32_t data_kind;  /* gdg_data_kind */
   int32_t reserved;
   double vortex[6];
+  const double *vertices; /* NULL: the uniform box [lo, hi]; else host memory, see above */
 } gdg_mesh_desc;
 
 /* Scheme constants.  gdg_default_params() gives the paper's values:
@@ -362,7 +377,8 @@ gdg_status gdg_server_overhead_bytes(const gdg_server_desc *desc, size_t *bytes)
 gdg_status gdg_server_create(const gdg_server_desc *desc, void *dev_pool, size_t pool_bytes, void *hip_stream,
                              gdg_server **out);
 
-/* Queues a request; U0 is a host state (SoA, (dim+2) * N doubles), copied.
+/* Queues a request; U0 is a host state (SoA, (dim+2) * N doubles), copied,
+ * as are the mesh's vertices (general cells).
  * GDG_E_INVALID for a description outside the server's class or bad
  * constants, GDG_E_BUDGET if its workspace exceeds the whole pool. */
 gdg_status gdg_server_submit(gdg_server *srv, const gdg_mesh_desc *mesh, const gdg_params *prm, const double *U0,

@@ -37,6 +37,8 @@ struct gdg_ctx {
   // device-driven runs: a captured graph of kGraphSteps steps
   hipStream_t cap_stream;
   hipGraphExec_t graph_exec;
+  // general cells: the caller's vertices (mesh.vertices points here)
+  std::vector<double> vx;
 };
 
 namespace {
@@ -48,7 +50,8 @@ struct Layout {
   int nloc, nb1, R, cpb, W, M;
   int64_t N, ncells, nblocks, nslots;
   size_t off_ref, off_ctl, off_col, off_c, off_meta, off_kscale, off_U[3], off_Nd, off_Qd, off_Ld, off_U1d,
-      off_dL, off_l1, off_acc, off_fsum, off_red, off_cnt, total;
+      off_dL, off_l1, off_acc, off_fsum, off_red, off_cnt, off_mrow, off_hprow, off_relrow, off_cmblk, off_cminv,
+      total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -61,7 +64,7 @@ bool validate(const gdg_mesh_desc *m, const gdg_params *p, std::string *err) {
   int64_t ncells = 1;
   for (int e = 0; e < m->dim; ++e) {
     if (m->cells[e] < 1) { *err = "cells must be >= 1"; return false; }
-    if (!(m->hi[e] > m->lo[e])) { *err = "hi must exceed lo"; return false; }
+    if (!m->vertices && !(m->hi[e] > m->lo[e])) { *err = "hi must exceed lo"; return false; }
     int b0 = m->bc[2 * e], b1 = m->bc[2 * e + 1];
     for (int b : {b0, b1})
       if (b < GDG_BC_PERIODIC || b > GDG_BC_INOUTFLOW) { *err = "unknown boundary kind"; return false; }
@@ -91,6 +94,10 @@ bool validate(const gdg_mesh_desc *m, const gdg_params *p, std::string *err) {
   }
   if (m->data_kind != GDG_DATA_CONSTANT && m->data_kind != GDG_DATA_VORTEX) {
     *err = "unknown boundary data kind";
+    return false;
+  }
+  if (m->vertices && m->data_kind == GDG_DATA_VORTEX) {
+    *err = "vortex boundary data are built for the uniform box (vertices must be NULL)";
     return false;
   }
   if (m->data_kind == GDG_DATA_VORTEX) {
@@ -171,6 +178,15 @@ Layout layout(const gdg_mesh_desc *m, const gdg_params *p) {
   L.off_fsum = take(M * N * 8);
   L.off_red = take((size_t)(kRedBlocks + 1) * kRedFields * 8);
   L.off_cnt = take((size_t)kCntKinds * kCntSlots * kCntStride * 8);
+  L.off_mrow = L.off_hprow = L.off_relrow = L.off_cmblk = L.off_cminv = 0;
+  if (m->vertices) {
+    const size_t blk = (size_t)L.ncells * L.nloc * L.nloc * 8;
+    L.off_mrow = take(N * 8);
+    L.off_hprow = take(N * 8);
+    L.off_relrow = take(N * 8);
+    L.off_cmblk = take(blk);
+    L.off_cminv = take(blk);
+  }
   L.total = o;
   return L;
 }
@@ -348,6 +364,12 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   }
   gdg_ctx *ctx = new gdg_ctx();
   ctx->mesh = *mesh;
+  if (mesh->vertices) {
+    size_t npts = 1;
+    for (int e = 0; e < mesh->dim; ++e) npts *= (size_t)(mesh->cells[e] + 1);
+    ctx->vx.assign(mesh->vertices, mesh->vertices + npts * mesh->dim);
+    ctx->mesh.vertices = ctx->vx.data();
+  }
   ctx->prm = *prm;
   ctx->stream = (hipStream_t)hip_stream;
   ctx->M = L.M;
@@ -384,7 +406,7 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   }
   double h[3] = {1, 1, 1}, vol = 1.0;
   for (int e = 0; e < 3; ++e) A.cells[e] = e < mesh->dim ? mesh->cells[e] : 1;
-  for (int e = 0; e < mesh->dim; ++e) {
+  for (int e = 0; e < mesh->dim && !mesh->vertices; ++e) {
     h[e] = (mesh->hi[e] - mesh->lo[e]) / (double)mesh->cells[e];
     vol *= mesh->hi[e] - mesh->lo[e];
   }
@@ -431,6 +453,14 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   A.fsum = (double *)(ws + L.off_fsum);
   A.red = (double *)(ws + L.off_red);
   A.cnt = (unsigned long long *)(ws + L.off_cnt);
+  A.general = mesh->vertices ? 1 : 0;
+  if (A.general) {
+    A.mrow = (const double *)(ws + L.off_mrow);
+    A.hprow = (const double *)(ws + L.off_hprow);
+    A.relrow = (const double *)(ws + L.off_relrow);
+    A.cmblk = (const double *)(ws + L.off_cmblk);
+    A.cminv = (const double *)(ws + L.off_cminv);
+  }
 
   RefTables *T = new RefTables();
   if (!build_ref_tables(mesh->dim, mesh->degree, h, T, &err)) {
@@ -439,7 +469,19 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
     delete ctx;
     return GDG_E_INVALID;
   }
-  for (int a = 0; a < L.nloc; ++a) {
+  // general cells: per-row and per-cell tables from the map, and the stencil
+  // coefficients that replace those of the fill kernel
+  MappedSetup G;
+  if (A.general) {
+    if (!build_mapped(&ctx->mesh, prm, ctx->vx.data(), *T, L.R, L.W, L.nslots, &G, &err)) {
+      g_create_err = err;
+      delete T;
+      delete ctx;
+      return GDG_E_INVALID;
+    }
+    A.vol = vol = G.vol;
+  }
+  for (int a = 0; a < L.nloc && !A.general; ++a) {
     double hh = std::pow(T->mlump[a] / vol, 1.0 / mesh->dim);
     T->hpk[a] = prm->c_k * std::pow(hh, A.pk);
     T->relax[a] = prm->c_r * std::pow(hh, prm->p_r);
@@ -472,6 +514,38 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   hipError_t e1 = hipMemcpyAsync(ctx->dref, T, sizeof(RefTables), hipMemcpyHostToDevice, ctx->stream);
   hipError_t e2 = hipMemcpyAsync(A.ctl, &ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream);
   int rc = (e1 == hipSuccess && e2 == hipSuccess) ? launch_fill(A, ctx->stream) : -1;
+  if (rc == 0 && A.general) {
+    // after the fill kernel on the same stream: its c and kappa entries are
+    // those of the uniform cell and are overwritten here
+    std::vector<float> cf;
+    const void *csrc = G.c.data();
+    size_t cbytes = G.c.size() * sizeof(double);
+    if (A.mixed) {
+      cf.assign(G.c.begin(), G.c.end());
+      csrc = cf.data();
+      cbytes = cf.size() * sizeof(float);
+    }
+    const size_t nb = (size_t)A.N * 8, bb = G.cmblk.size() * 8;
+    hipError_t e = hipSuccess;
+    auto cp = [&](const void *dst, const void *src, size_t bytes) {
+      if (e == hipSuccess) e = hipMemcpyAsync((void *)dst, src, bytes, hipMemcpyHostToDevice, ctx->stream);
+    };
+    cp(A.mixed ? (const void *)A.cf : (const void *)A.c, csrc, cbytes);
+    cp(A.kscale, G.kscale.data(), nb);
+    cp(A.mrow, G.mrow.data(), nb);
+    cp(A.hprow, G.hprow.data(), nb);
+    cp(A.relrow, G.relrow.data(), nb);
+    cp(A.cmblk, G.cmblk.data(), bb);
+    cp(A.cminv, G.cminv.data(), bb);
+    // the host vectors must outlive the copies
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+      g_create_err = std::string("copy of the general-cell tables failed: ") + hipGetErrorString(e);
+      delete T;
+      delete ctx;
+      return GDG_E_DEVICE;
+    }
+  }
   if (rc == 0) rc = launch_zero_counts(A, ctx->stream);
   hipError_t e4 = rc == 0 ? hipSuccess : hipGetLastError();
   hipError_t e3 = hipStreamSynchronize(ctx->stream);
@@ -514,6 +588,19 @@ gdg_status gdg_node_coords(const gdg_ctx *ctx, double *xyz) {
   const double r5 = 0.5 / std::sqrt(5.0);
   const double xg2[3] = {0.0, 0.5, 1.0}, xg1[2] = {0.0, 1.0}, xg3[4] = {0.0, 0.5 - r5, 0.5 + r5, 1.0};
   const double *xg = m.degree == 1 ? xg1 : (m.degree == 2 ? xg2 : xg3);
+  if (m.vertices) {
+    // x_i = F_K(xi_a): the cell's map at the node's reference point
+    for (int64_t K = 0; K < ctx->A.ncells; ++K) {
+      double X[8][3];
+      mapped_cell_corners(&m, m.vertices, K, X);
+      for (int a = 0; a < nloc; ++a) {
+        double xi[3] = {0, 0, 0};
+        for (int e = 0, r = a; e < d; ++e, r /= nb) xi[e] = xg[r % nb];
+        mapped_point(d, X, xi, &xyz[(K * nloc + a) * d]);
+      }
+    }
+    return GDG_OK;
+  }
   for (int64_t i = 0; i < ctx->A.N; ++i) {
     int64_t K = i / nloc;
     int a = (int)(i % nloc);

@@ -12,6 +12,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "gdg.h"
 
@@ -158,6 +159,14 @@ struct KArgs {
   uint8_t *meta;
   double *kscale;   // 1 / (kappa_i m_i) per row, kappa_i = 1/(card I(i) + 1)
   const RefTables *ref;
+  // General (mapped) cells: the per-node and per-cell-class entries of ref
+  // (mlump, hpk, relax, mblk, minv) are per row and per cell instead
+  int32_t general;
+  const double *mrow;   // m_i
+  const double *hprow;  // c_k hhat_i^{p_k}
+  const double *relrow; // c_r hhat_i^{p_r}
+  const double *cmblk;  // per cell: m_ab (nloc x nloc)
+  const double *cminv;  // per cell: (M_K^{-1})_ab
   int64_t nslots;
   // per-dof fields
   double *Nd;       // node records, two buffers of N * kNodeStride
@@ -210,6 +219,21 @@ struct BatchList {
 };
 
 bool build_ref_tables(int dim, int deg, const double *h, RefTables *T, std::string *err);
+
+// Host tables of a mesh of general cells (gdg_mapped.cpp), for the row-blocked
+// ELL layout of R rows per block and W slots per row.
+struct MappedSetup {
+  std::vector<double> mrow, hprow, relrow, kscale;  // per row
+  std::vector<double> cmblk, cminv;                  // per cell, nloc x nloc
+  std::vector<double> c;                             // dim planes of nslots, the slot order of the fill kernel
+  double vol;                                        // |Omega|
+};
+bool build_mapped(const gdg_mesh_desc *m, const gdg_params *p, const double *vx, const RefTables &T, int R, int W,
+                  int64_t nslots, MappedSetup *out, std::string *err);
+// The 2^dim corners of cell K (corner v: bit e of v is the side in direction e).
+void mapped_cell_corners(const gdg_mesh_desc *m, const double *vx, int64_t K, double (*X)[3]);
+// x = F_K(xi) for the corners X of a cell.
+void mapped_point(int d, const double (*X)[3], const double *xi, double *x);
 int launch_fill(const KArgs &A, void *stream);
 int launch_begin(const KArgs &A, double dt_cap, double tau_fixed, int device_driven, void *stream);
 int launch_end(const KArgs &A, void *stream);

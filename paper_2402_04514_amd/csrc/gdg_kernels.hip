@@ -918,7 +918,7 @@ __device__ __forceinline__ void sweep1_body(const KArgs &A, const double *__rest
     double2 *qr = reinterpret_cast<double2 *>(A.Qd + (size_t)i * kQStride);
     qr[0] = make_double2(rmin, rmax);
     qr[1] = make_double2(smin, Nval);
-    const double mi = A.ref->mlump[i % NLOC];
+    const double mi = A.general ? A.mrow[i] : A.ref->mlump[i % NLOC];
     tau_i = mi / (2.0 * dsum);
   }
   block_min_atomic(tau_i, &A.ctl->taumin_bits[stage]);
@@ -937,6 +937,15 @@ __device__ __forceinline__ double visc_high(const KArgs &A, double d, double Ni,
   double dev = d * fmin(A.c_ev * fmax(fabs(Ni), fabs(Nj)), 1.0);
   double dmin = kind == SK_FACE_COLLOC ? hpk * d : 0.0;
   return fmax(dmin, dev);
+}
+
+// c_k hhat^{p_k} of the pair (i, j) for eq. ViscMin: on general cells a
+// collocated pair takes hhat_ij = ((m_i + m_j) / (2 |Omega|))^{1/d}, the mean
+// of the two rows' masses (on a uniform mesh both rows have the same m and
+// this is hpk_i); odd degrees have p_k = 0 and need no power
+__device__ __forceinline__ double pair_hpk(const KArgs &A, double hpk_i, double mi, int64_t j, int kind) {
+  if (!A.general || kind != SK_FACE_COLLOC || A.pk == 0.0) return hpk_i;
+  return A.c_k * pow(pow(0.5 * (mi + A.mrow[j]) / A.vol, 1.0 / A.dim), A.pk);
 }
 
 // ---------------------------------------------------------------------------
@@ -990,8 +999,8 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
     a = (int)(i % NLOC);
     load_node<D>(nd, i, ni);
     const double Ni = A.Qd[(size_t)i * kQStride + 3];
-    const double hpk = A.ref->hpk[a];
-    const double mi = A.ref->mlump[a];
+    const double hpk = A.general ? A.hprow[i] : A.ref->hpk[a];
+    const double mi = A.general ? A.mrow[i] : A.ref->mlump[a];
     // accL / accH: the viscous terms sum_j d_ij (U_j - U_i) of the low- and
     // high-order updates (with their boundary parts); the flux sum comes from
     // sweep 1
@@ -1055,7 +1064,7 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
       rmax = fmax(rmax, qj[1]);
       smin = fmin(smin, qj[2]);
       if (j == i) continue;
-      const double dH = visc_high(A, d, Ni, qj[3], kind, hpk);
+      const double dH = visc_high(A, d, Ni, qj[3], kind, pair_hpk(A, hpk, mi, j, kind));
       // U_j from the neighbour's node record
       double Uj[M];
       load_rec<M>(nd + (size_t)j * kNodeStride, Uj);
@@ -1079,7 +1088,7 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
       lr[R::UL + q] = UL[q];
     }
     // eq. local_bounds with r^-+ = 1 -+ c_r hhat_i^{p_r}
-    const double rel = A.ref->relax[a];
+    const double rel = A.general ? A.relrow[i] : A.ref->relax[a];
     lr[R::B] = (1.0 - rel) * rmin;
     lr[R::B + 1] = (1.0 + rel) * rmax;
     lr[R::B + 2] = (1.0 - rel) * smin;
@@ -1108,9 +1117,10 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
     A.accepted[i] = (uint8_t)cq;
     wave_count_add(cnt_slot(A, kCntQuiet), (unsigned)cq);
   }
+  const double *minv = (A.general ? A.cminv + (i / NLOC) * (NLOC * NLOC) : A.ref->minv) + a * NLOC;
   for (int q = 0; q < M; ++q) {
     double s = 0.0;
-    for (int b = 0; b < NLOC; ++b) s += A.ref->minv[a * NLOC + b] * rs(q, cellbase + b);
+    for (int b = 0; b < NLOC; ++b) s += minv[b] * rs(q, cellbase + b);
     du[q] = tau * s;
   }
   if (A.scheme == 1) {
@@ -1139,13 +1149,15 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(G
 // Antidiffusive flux of eq. HighLowOrderIdentity for a graph pair:
 //   A_ij = tau (d^H_ij - d^L_ij)(U_j - U_i) - m_ij (dU^H_j - dU^H_i).
 // d^L, d^H and m_ij are symmetric, so row j computes exactly -A_ij.
-template <int D, int NLOC>
+// mblk_a: row a (of row i) of the cell's consistent mass block; hpk: c_k
+// hhat^{p_k} of the pair.
+template <int D>
 __device__ __forceinline__ void pair_flux(const KArgs &A, const double *Uj, const double *dUj, double Nj, uint8_t meta,
-                                          int a, const double *Ui, const double *dUi, double Ni, double hpk,
-                                          double tau, double d, double *Aij) {
+                                          const double *mblk_a, const double *Ui, const double *dUi, double Ni,
+                                          double hpk, double tau, double d, double *Aij) {
   const int kind = meta & 7;
   const double dH = visc_high(A, d, Ni, Nj, kind, hpk);
-  const double mij = kind == SK_CELL ? A.ref->mblk[a * NLOC + (meta >> 3)] : 0.0;
+  const double mij = kind == SK_CELL ? mblk_a[meta >> 3] : 0.0;
   const double td = tau * (dH - d);
   for (int q = 0; q < D + 2; ++q) Aij[q] = td * (Uj[q] - Ui[q]) - mij * (dUj[q] - dUi[q]);
 }
@@ -1221,8 +1233,9 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
     // is U^(1) itself
     load_rec<M>(A.U1d + (size_t)i * kU1Stride, V);
   } else {
-  const double mi = A.ref->mlump[a];
-  const double hpk = A.ref->hpk[a];
+  const double mi = A.general ? A.mrow[i] : A.ref->mlump[a];
+  const double hpk = A.general ? A.hprow[i] : A.ref->hpk[a];
+  const double *mblk_a = (A.general ? A.cmblk + (i / NLOC) * (NLOC * NLOC) : A.ref->mblk) + a * NLOC;
   double Ui[M], Li[M], dUi[M], lri[NL];
   load_rec<NL>(A.Ld + (size_t)i * kLimStride, lri);
   for (int q = 0; q < M; ++q) {
@@ -1280,7 +1293,8 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
     double lrj[NL];
     load_rec<NL>(A.Ld + (size_t)j * kLimStride, lrj);
     double Aij[M];
-    pair_flux<D, NLOC>(A, lrj + R::LU, lrj + R::dUH, lrj[R::N], meta, a, Ui, dUi, Ni, hpk, tau, d, Aij);
+    pair_flux<D>(A, lrj + R::LU, lrj + R::dUH, lrj[R::N], meta, mblk_a, Ui, dUi, Ni,
+                 pair_hpk(A, hpk, mi, j, meta & 7), tau, d, Aij);
     bool zero = true;
     for (int q = 0; q < M; ++q) zero = zero && Aij[q] == 0.0;
     if (zero) {
@@ -1481,7 +1495,7 @@ __global__ __launch_bounds__(kRedThreads) void k_state_stats1(KArgs A, const dou
     for (int c = 0; c < M; ++c) V[c] = U[c * N + i];
     v[0] = fmin(v[0], V[0]);
     v[1] = fmin(v[1], eps_of<D>(V));
-    const double mi = A.ref->mlump[i % A.nloc];
+    const double mi = A.general ? A.mrow[i] : A.ref->mlump[i % A.nloc];
     for (int c = 0; c < M; ++c) v[2 + c] += mi * V[c];
   }
   for (int f = 0; f < F; ++f) sh[f][threadIdx.x] = v[f];

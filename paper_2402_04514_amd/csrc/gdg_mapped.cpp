@@ -1,0 +1,401 @@
+// Stencil coefficients of general quadrilateral / hexahedral cells (Sec. 2.3,
+// eq. mass_matrices, cij_def1, cij_def2, with Sec. 4.2's boundary parts):
+// every cell is the multilinear image x = F_K(xi) of the reference cell
+// through its 2^d corners, and the integrals are taken on the reference cell
+// with the change of variables.  With cof(J) = det(J) J^{-T} (the cofactor
+// matrix of the Jacobian, a polynomial in xi for a multilinear map):
+//   m_ab      = int phi_a phi_b det J dxi,
+//   c^K_ab    = int phi_a cof(J) grad_xi phi_b dxi,
+//   n ds      = +-cof(J) e_e dxi on the face xi_e = 0 or 1 (outward sign),
+// so every integrand is a polynomial and a Gauss rule of k + 2 points per
+// direction integrates it exactly.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gdg.h"
+#include "gdg_internal.h"
+
+namespace gdg {
+
+namespace {
+
+// Gauss-Legendre rule of n = 2 .. 5 points on [0, 1], from the closed forms of
+// the roots of the Legendre polynomials on [-1, 1].
+void gauss01(int n, double *x, double *w) {
+  double r[5], q[5];
+  if (n == 2) {
+    r[0] = -1.0 / std::sqrt(3.0), r[1] = -r[0];
+    q[0] = q[1] = 1.0;
+  } else if (n == 3) {
+    r[0] = -std::sqrt(0.6), r[1] = 0.0, r[2] = -r[0];
+    q[0] = q[2] = 5.0 / 9.0, q[1] = 8.0 / 9.0;
+  } else if (n == 4) {
+    const double a = std::sqrt(3.0 / 7.0 - 2.0 / 7.0 * std::sqrt(1.2)), b = std::sqrt(3.0 / 7.0 + 2.0 / 7.0 * std::sqrt(1.2));
+    r[0] = -b, r[1] = -a, r[2] = a, r[3] = b;
+    q[1] = q[2] = (18.0 + std::sqrt(30.0)) / 36.0, q[0] = q[3] = (18.0 - std::sqrt(30.0)) / 36.0;
+  } else {
+    const double a = std::sqrt(5.0 - 2.0 * std::sqrt(10.0 / 7.0)) / 3.0,
+                 b = std::sqrt(5.0 + 2.0 * std::sqrt(10.0 / 7.0)) / 3.0;
+    r[0] = -b, r[1] = -a, r[2] = 0.0, r[3] = a, r[4] = b;
+    q[0] = q[4] = (322.0 - 13.0 * std::sqrt(70.0)) / 900.0;
+    q[1] = q[3] = (322.0 + 13.0 * std::sqrt(70.0)) / 900.0;
+    q[2] = 128.0 / 225.0;
+  }
+  for (int k = 0; k < n; ++k) {
+    x[k] = 0.5 * (1.0 + r[k]);
+    w[k] = 0.5 * q[k];
+  }
+}
+
+// 1D Lagrange basis on the Gauss-Lobatto nodes of degree k.
+struct Lag1D {
+  int nb;
+  double xg[4];
+  double val(int a, double t) const {
+    double v = 1.0;
+    for (int b = 0; b < nb; ++b)
+      if (b != a) v *= (t - xg[b]) / (xg[a] - xg[b]);
+    return v;
+  }
+  double der(int a, double t) const {
+    double s = 0.0;
+    for (int c = 0; c < nb; ++c) {
+      if (c == a) continue;
+      double p = 1.0 / (xg[a] - xg[c]);
+      for (int b = 0; b < nb; ++b)
+        if (b != a && b != c) p *= (t - xg[b]) / (xg[a] - xg[b]);
+      s += p;
+    }
+    return s;
+  }
+};
+
+Lag1D lag1d(int deg) {
+  Lag1D L;
+  L.nb = deg + 1;
+  const double r5 = 0.5 / std::sqrt(5.0);
+  const double x1[4] = {0.0, 1.0, 0, 0}, x2[4] = {0.0, 0.5, 1.0, 0}, x3[4] = {0.0, 0.5 - r5, 0.5 + r5, 1.0};
+  const double *x = deg == 1 ? x1 : (deg == 2 ? x2 : x3);
+  for (int k = 0; k < 4; ++k) L.xg[k] = x[k];
+  return L;
+}
+
+void split(int a, int nb, int *ai) {
+  for (int e = 0; e < 3; ++e) {
+    ai[e] = a % nb;
+    a /= nb;
+  }
+}
+
+// Jacobian J[r][c] = dx_r/dxi_c of the multilinear map through the corners X
+// (corner v at bit e of v = side in direction e), at xi; and its cofactor
+// matrix cof = det(J) J^{-T}; returns det J.
+double jacobian(int d, const double (*X)[3], const double *xi, double cof[3][3]) {
+  double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int v = 0; v < (1 << d); ++v)
+    for (int c = 0; c < d; ++c) {
+      double g = 1.0;
+      for (int e = 0; e < d; ++e) {
+        const int bit = (v >> e) & 1;
+        g *= e == c ? (bit ? 1.0 : -1.0) : (bit ? xi[e] : 1.0 - xi[e]);
+      }
+      for (int r = 0; r < d; ++r) J[r][c] += g * X[v][r];
+    }
+  if (d == 1) {
+    cof[0][0] = 1.0;
+    return J[0][0];
+  }
+  if (d == 2) {
+    cof[0][0] = J[1][1], cof[0][1] = -J[1][0];
+    cof[1][0] = -J[0][1], cof[1][1] = J[0][0];
+    return J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      // the (r, c) cofactor: the 2 x 2 minor without row r and column c, signed
+      const int r1 = (r + 1) % 3, r2 = (r + 2) % 3, c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+      cof[r][c] = J[r1][c1] * J[r2][c2] - J[r1][c2] * J[r2][c1];
+    }
+  return J[0][0] * cof[0][0] + J[0][1] * cof[0][1] + J[0][2] * cof[0][2];
+}
+
+// Gauss-Jordan inverse with partial pivoting of an n x n matrix.
+bool invert_n(int n, const double *A, double *Ai) {
+  std::vector<double> M((size_t)n * 2 * n);
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < 2 * n; ++c) M[r * 2 * n + c] = c < n ? A[r * n + c] : (c - n == r ? 1.0 : 0.0);
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    for (int r = k + 1; r < n; ++r)
+      if (std::fabs(M[r * 2 * n + k]) > std::fabs(M[p * 2 * n + k])) p = r;
+    if (M[p * 2 * n + k] == 0.0) return false;
+    if (p != k)
+      for (int c = 0; c < 2 * n; ++c) std::swap(M[k * 2 * n + c], M[p * 2 * n + c]);
+    const double piv = M[k * 2 * n + k];
+    for (int c = 0; c < 2 * n; ++c) M[k * 2 * n + c] /= piv;
+    for (int r = 0; r < n; ++r) {
+      if (r == k) continue;
+      const double f = M[r * 2 * n + k];
+      if (f == 0.0) continue;
+      for (int c = 0; c < 2 * n; ++c) M[r * 2 * n + c] -= f * M[k * 2 * n + c];
+    }
+  }
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < n; ++c) Ai[r * n + c] = M[r * 2 * n + c + n];
+  return true;
+}
+
+}  // namespace
+
+void mapped_cell_corners(const gdg_mesh_desc *m, const double *vx, int64_t K, double (*X)[3]) {
+  const int d = m->dim;
+  int64_t ki[3] = {0, 0, 0}, r = K;
+  for (int e = 0; e < d; ++e) {
+    ki[e] = r % m->cells[e];
+    r /= m->cells[e];
+  }
+  for (int v = 0; v < (1 << d); ++v) {
+    int64_t idx = 0, stride = 1;
+    for (int e = 0; e < d; ++e) {
+      idx += (ki[e] + ((v >> e) & 1)) * stride;
+      stride *= m->cells[e] + 1;
+    }
+    for (int c = 0; c < 3; ++c) X[v][c] = c < d ? vx[idx * d + c] : 0.0;
+  }
+}
+
+void mapped_point(int d, const double (*X)[3], const double *xi, double *x) {
+  for (int c = 0; c < d; ++c) x[c] = 0.0;
+  for (int v = 0; v < (1 << d); ++v) {
+    double g = 1.0;
+    for (int e = 0; e < d; ++e) g *= ((v >> e) & 1) ? xi[e] : 1.0 - xi[e];
+    for (int c = 0; c < d; ++c) x[c] += g * X[v][c];
+  }
+}
+
+bool build_mapped(const gdg_mesh_desc *m, const gdg_params *p, const double *vx, const RefTables &T, int R, int W,
+                  int64_t nslots, MappedSetup *out, std::string *err) {
+  const int d = m->dim, deg = m->degree, nb = deg + 1;
+  int nloc = 1;
+  for (int e = 0; e < d; ++e) nloc *= nb;
+  const int nface = nloc / nb;
+  int64_t ncells = 1;
+  for (int e = 0; e < d; ++e) ncells *= m->cells[e];
+  const int64_t N = ncells * nloc;
+  const Lag1D L = lag1d(deg);
+  const int nq = deg + 2;
+  double xq[5], wq[5];
+  gauss01(nq, xq, wq);
+  int nvol = 1, nsurf = 1;
+  for (int e = 0; e < d; ++e) nvol *= nq;
+  for (int e = 0; e + 1 < d; ++e) nsurf *= nq;
+
+  out->mrow.assign(N, 0.0);
+  out->cmblk.assign((size_t)ncells * nloc * nloc, 0.0);
+  out->cminv.assign((size_t)ncells * nloc * nloc, 0.0);
+  // per cell: in-cell c (nloc x nloc x d), each face's pair integrals from
+  // this cell's side (2d faces x face node x neighbour face node x d), and the
+  // boundary parts (2d faces x node x d)
+  std::vector<double> cin((size_t)ncells * nloc * nloc * d), cfc((size_t)ncells * 2 * d * nface * nface * d),
+      cgh((size_t)ncells * 2 * d * nloc * d);
+  // face nodes of each face, in the order of T.bface for the neighbour side
+  std::vector<int> fnode(2 * d * nface);
+  for (int f = 0; f < 2 * d; ++f) {
+    const int e = f / 2, side = f % 2;
+    int t = 0;
+    for (int a = 0; a < nloc; ++a) {
+      int ai[3];
+      split(a, nb, ai);
+      if (ai[e] == side * deg) fnode[f * nface + t++] = a;
+    }
+  }
+  double vol = 0.0;
+  bool ok = true;
+  for (int64_t K = 0; K < ncells && ok; ++K) {
+    double X[8][3];
+    mapped_cell_corners(m, vx, K, X);
+    double *Mk = &out->cmblk[(size_t)K * nloc * nloc];
+    double *Ck = &cin[(size_t)K * nloc * nloc * d];
+    std::vector<double> Craw((size_t)nloc * nloc * d, 0.0);
+    for (int q = 0; q < nvol; ++q) {
+      double xi[3] = {0, 0, 0}, w = 1.0;
+      int r = q;
+      for (int e = 0; e < d; ++e) {
+        xi[e] = xq[r % nq];
+        w *= wq[r % nq];
+        r /= nq;
+      }
+      double cof[3][3];
+      const double det = jacobian(d, X, xi, cof);
+      if (!(det > 0.0)) ok = false;
+      vol += w * det;
+      double phv[64], gr[64][3];
+      for (int a = 0; a < nloc; ++a) {
+        int ai[3];
+        split(a, nb, ai);
+        double v = 1.0;
+        for (int e = 0; e < d; ++e) v *= L.val(ai[e], xi[e]);
+        phv[a] = v;
+        for (int c = 0; c < d; ++c) {
+          double g = 1.0;
+          for (int e = 0; e < d; ++e) g *= e == c ? L.der(ai[e], xi[e]) : L.val(ai[e], xi[e]);
+          gr[a][c] = g;
+        }
+      }
+      for (int a = 0; a < nloc; ++a) {
+        out->mrow[K * nloc + a] += w * phv[a] * det;
+        for (int b = 0; b < nloc; ++b) {
+          Mk[a * nloc + b] += w * phv[a] * phv[b] * det;
+          for (int e = 0; e < d; ++e) {
+            double gx = 0.0;
+            for (int c = 0; c < d; ++c) gx += cof[e][c] * gr[b][c];
+            Craw[(a * nloc + b) * d + e] += w * phv[a] * gx;
+          }
+        }
+      }
+    }
+    // the cell's faces: n ds = sign cof(J) e_e dxi, column e of the cofactor matrix
+    for (int f = 0; f < 2 * d; ++f) {
+      const int e = f / 2, side = f % 2;
+      const double sgn = side ? 1.0 : -1.0;
+      for (int q = 0; q < nsurf; ++q) {
+        double xi[3] = {0, 0, 0}, w = 1.0;
+        int r = q;
+        for (int g = 0; g < d; ++g) {
+          if (g == e) {
+            xi[g] = side ? 1.0 : 0.0;
+            continue;
+          }
+          xi[g] = xq[r % nq];
+          w *= wq[r % nq];
+          r /= nq;
+        }
+        double cof[3][3];
+        jacobian(d, X, xi, cof);
+        double ns[3];
+        for (int c = 0; c < d; ++c) ns[c] = sgn * cof[c][e];
+        for (int ta = 0; ta < nface; ++ta) {
+          const int a = fnode[f * nface + ta];
+          int ai[3];
+          split(a, nb, ai);
+          double va = 1.0;
+          for (int g = 0; g < d; ++g)
+            if (g != e) va *= L.val(ai[g], xi[g]);
+          for (int c = 0; c < d; ++c) cgh[(((size_t)K * 2 * d + f) * nloc + a) * d + c] += 0.5 * w * va * ns[c];
+          for (int tb = 0; tb < nface; ++tb) {
+            // the same cell's node b on this face (c^{dK} of the in-cell pair)
+            const int b = fnode[f * nface + tb];
+            int bi[3];
+            split(b, nb, bi);
+            double vb = 1.0;
+            for (int g = 0; g < d; ++g)
+              if (g != e) vb *= L.val(bi[g], xi[g]);
+            for (int c = 0; c < d; ++c) Craw[(a * nloc + b) * d + c] -= 0.5 * w * va * vb * ns[c];
+            // the neighbour's node T.bface[f][tb] across this face: its trace
+            // on the face is the same tensor of the other directions' values
+            const int bn = T.bface[f * 9 + tb];
+            int bni[3];
+            split(bn, nb, bni);
+            double vbn = 1.0;
+            for (int g = 0; g < d; ++g)
+              if (g != e) vbn *= L.val(bni[g], xi[g]);
+            for (int c = 0; c < d; ++c)
+              cfc[((((size_t)K * 2 * d + f) * nface + ta) * nface + tb) * d + c] += 0.5 * w * va * vbn * ns[c];
+          }
+        }
+      }
+    }
+    // Lemma PropSkew as stored (reading R3): c_aa = 0, c_ba = -c_ab from a < b
+    for (int a = 0; a < nloc; ++a)
+      for (int b = 0; b < nloc; ++b)
+        for (int e = 0; e < d; ++e)
+          Ck[(a * nloc + b) * d + e] =
+              a == b ? 0.0 : (a < b ? Craw[(a * nloc + b) * d + e] : -Craw[(b * nloc + a) * d + e]);
+    if (!invert_n(nloc, Mk, &out->cminv[(size_t)K * nloc * nloc])) ok = false;
+  }
+  if (!ok) {
+    *err = "a mapped cell has a non-positive Jacobian determinant (inverted or degenerate corners)";
+    return false;
+  }
+  out->vol = vol;
+  // per-row constants and the stencil in the ELL layout of k_fill: in-cell
+  // nodes b = 0 .. nloc-1, then per face the node lies on either its boundary
+  // part or the neighbour's face nodes in the order of T.bface, then pads
+  const double pk = deg % 2 == 0 ? 0.5 : 0.0;
+  out->relrow.resize(N);
+  out->hprow.resize(N);
+  out->kscale.resize(N);
+  out->c.assign((size_t)d * nslots, 0.0);
+  for (int64_t i = 0; i < N; ++i) {
+    const int64_t K = i / nloc;
+    const int a = (int)(i % nloc);
+    const double hh = std::pow(out->mrow[i] / vol, 1.0 / d);
+    out->hprow[i] = p->c_k * std::pow(hh, pk);
+    out->relrow[i] = p->c_r * std::pow(hh, p->p_r);
+    if (!(out->relrow[i] < 1.0)) {
+      *err = "relaxation c_r h^p_r >= 1: the lower bounds would not be positive";
+      return false;
+    }
+    const int64_t blk = i / R, lane = i % R;
+    int t = 0, graph = 0;
+    auto put = [&](const double *c, double sgn) {
+      const int64_t s = (blk * W + t) * R + lane;
+      for (int e = 0; e < d; ++e) out->c[(size_t)e * nslots + s] = sgn * c[e];
+      ++t;
+    };
+    for (int b = 0; b < nloc; ++b) {
+      put(&cin[((size_t)K * nloc * nloc + a * nloc + b) * d], 1.0);
+      ++graph;
+    }
+    int64_t ki[3] = {0, 0, 0}, r = K;
+    for (int e = 0; e < d; ++e) {
+      ki[e] = r % m->cells[e];
+      r /= m->cells[e];
+    }
+    for (int f = 0; f < 2 * d; ++f) {
+      if (!T.onface[f * kMaxNloc + a]) continue;
+      const int e = f / 2, side = f % 2;
+      int64_t kn[3] = {ki[0], ki[1], ki[2]};
+      kn[e] += side ? 1 : -1;
+      if (kn[e] < 0 || kn[e] >= m->cells[e]) {
+        if (m->bc[f] != GDG_BC_PERIODIC) {
+          put(&cgh[(((size_t)K * 2 * d + f) * nloc + a) * d], 1.0);
+          continue;
+        }
+        kn[e] = (kn[e] + m->cells[e]) % m->cells[e];
+      }
+      int64_t Kn = 0, stride = 1;
+      for (int g = 0; g < d; ++g) {
+        Kn += kn[g] * stride;
+        stride *= m->cells[g];
+      }
+      int ta = 0;
+      while (fnode[f * nface + ta] != a) ++ta;
+      for (int tb = 0; tb < nface; ++tb) {
+        // the pair from the cell of the lower index (reading R3): from this
+        // side if K < Kn, else minus the neighbour's integral over its face
+        // f^1 (a cell that meets itself across a periodic axis: from side 1)
+        if (K < Kn || (K == Kn && side == 1)) {
+          put(&cfc[((((size_t)K * 2 * d + f) * nface + ta) * nface + tb) * d], 1.0);
+        } else {
+          const int bn = T.bface[f * 9 + tb];
+          int tbn = 0;
+          while (fnode[(f ^ 1) * nface + tbn] != bn) ++tbn;
+          // in the neighbour's face list, node a of this cell is T.bface[f^1][.]
+          int tan = 0;
+          while (T.bface[(f ^ 1) * 9 + tan] != a) ++tan;
+          put(&cfc[((((size_t)Kn * 2 * d + (f ^ 1)) * nface + tbn) * nface + tan) * d], -1.0);
+        }
+        ++graph;
+      }
+    }
+    out->kscale[i] = (double)(graph + 1) / out->mrow[i];
+  }
+  return true;
+}
+
+}  // namespace gdg

@@ -92,6 +92,7 @@ struct Req {
   gdg_mesh_desc mesh{};
   gdg_params prm{};
   std::vector<double> U;  // initial state until admission, final state after
+  std::vector<double> vx; // general cells: the request's vertices (mesh.vertices points here)
   double t_final = 0.0;
   size_t bytes = 0, off = 0;
   gdg_ctx *ctx = nullptr;
@@ -440,6 +441,12 @@ gdg_status gdg_server_submit(gdg_server *s, const gdg_mesh_desc *mesh, const gdg
   Req *q = new Req();
   q->ticket = s->next_ticket++;
   q->mesh = *mesh;
+  if (mesh->vertices) {
+    size_t npts = 1;
+    for (int e = 0; e < mesh->dim; ++e) npts *= (size_t)(mesh->cells[e] + 1);
+    q->vx.assign(mesh->vertices, mesh->vertices + npts * mesh->dim);
+    q->mesh.vertices = q->vx.data();
+  }
   q->prm = *prm;
   q->t_final = t_final;
   q->bytes = bytes;

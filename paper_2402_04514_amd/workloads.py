@@ -44,6 +44,9 @@ class MeshSpec:
     # (beta, x0_1, x0_2, u_1, u_2, gamma): the data of those faces from the
     # isentropic vortex at the node and the time instead
     vortex: tuple | None = None
+    # general cells: the lattice's points, shape (prod(cells + 1), dim), x
+    # fastest (lo and hi then only name the box the points were drawn in)
+    vertices: np.ndarray | None = field(default=None, repr=False, compare=False)
 
     @property
     def nloc(self) -> int:
@@ -97,6 +100,35 @@ def node_coords(ms: MeshSpec):
         x[:, e] = xs.reshape(-1)
         xc[:, e] = cs.reshape(-1)
     return x, xc
+
+
+def lattice(cells, lo, hi) -> np.ndarray:
+    """The points of a uniform cell lattice, (prod(cells + 1), dim), x fastest."""
+    axes = [np.linspace(lo[e], hi[e], cells[e] + 1) for e in range(len(cells))]
+    grids = np.meshgrid(*axes, indexing="ij")
+    return np.stack([g.transpose(*reversed(range(len(cells)))).ravel() for g in grids], axis=1)
+
+
+def perturbed_lattice(cells, lo, hi, amp=0.25, seed=3, periodic=False) -> np.ndarray:
+    """General cells: the lattice with its interior points moved by up to amp
+    cell widths per axis (uniform random, seeded), or (periodic) by the smooth
+    field amp h_e sin(2 pi xi_1) .. sin(2 pi xi_d) (+ on even axes, - on odd),
+    which vanishes on the box's faces, so opposite boundary layers stay
+    congruent."""
+    V = lattice(cells, lo, hi)
+    d = len(cells)
+    h = np.array([(hi[e] - lo[e]) / cells[e] for e in range(d)])
+    idx = np.stack(np.unravel_index(np.arange(V.shape[0]), tuple(c + 1 for c in reversed(cells))), axis=1)[:, ::-1]
+    interior = np.all((idx > 0) & (idx < np.array(cells)), axis=1)
+    if periodic:
+        xi = (V - np.array(lo)) / (np.array(hi) - np.array(lo))
+        s = np.prod(np.sin(2 * np.pi * xi), axis=1)
+        for e in range(d):
+            V[:, e] += amp * h[e] * s * (1 if e % 2 == 0 else -1)
+        return V
+    rng = np.random.default_rng(seed)
+    V[interior] += amp * h * rng.uniform(-1, 1, size=(int(interior.sum()), d))
+    return V
 
 
 def to_conserved(rho, vel, p, gamma=GAMMA) -> np.ndarray:

@@ -1,0 +1,291 @@
+"""GPU parity on general cells (Sec. 2.3): every cell the multilinear image of
+the reference cell through its own corners, so m_ij, c_ij and c_i^d vary from
+cell to cell (the library integrates them through the map on the host, the
+kernels read per-row masses and viscosity constants and per-cell mass blocks).
+The HIP path through the C-ABI against the oracle's mapped mesh on the same
+seeded vertices and states, element by element, at the tolerances of the
+uniform-mesh parity tests (1e-11 of each component's scale per stage, N_i at
+its conditioning, 1e-10 after several steps).
+"""
+import numpy as np
+import pytest
+
+from paper_2402_04514_amd import gdg
+from paper_2402_04514_amd import workloads as W
+
+from test_gpu_parity import TOL, _check_ev, _close
+from test_gpu_mixed import L1_TOL, l1_rel
+from test_gpu_serving import _run_server
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print("[gpu-mapped] " + msg, flush=True)
+
+
+def _mesh(dim, k, cells, bc, amp=0.25, seed=3, periodic=False, bstate=None):
+    lo, hi = (0.0,) * dim, (1.0,) * dim
+    V = W.perturbed_lattice(cells, lo, hi, amp=amp, seed=seed, periodic=periodic)
+    return W.MeshSpec(dim, k, tuple(cells), lo, hi, tuple(bc), bstate=bstate, vertices=V)
+
+
+def _oracle_mesh(oracle, ms):
+    return oracle.Mesh(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc, bstate=ms.bstate, vertices=ms.vertices)
+
+
+def _quadrant(oracle, ms, seed=240204514, wz=True):
+    """Four-quadrant states per cell, by the mean of the cell's nodes; in 3D
+    with a z-velocity (wz), taken from another quadrant's second component.
+
+    Without it, a Q2 row whose only jumps lie across a z-face has D_i = 0 of
+    the entropy residual in exact arithmetic on general cells too (the
+    in-plane parts of sum_j c_ij over that face vanish: Simpson's rule makes
+    int t L_0(t) dt = 0), but only up to rounding, so N_i there is the ratio
+    of two rounding errors on both sides (test_degenerate_rows)."""
+    x = _oracle_mesh(oracle, ms).coords()
+    xc = np.repeat(x.reshape(ms.ncells, ms.nloc, ms.dim).mean(axis=1), ms.nloc, axis=0)
+    q = np.zeros(ms.ndofs, dtype=int)
+    for e in range(min(ms.dim, 2)):
+        q += (xc[:, e] >= 0.5).astype(int) << e
+    if ms.dim == 3:
+        q = (q + (xc[:, 2] >= 0.5).astype(int)) % 4
+    st = np.array(W.quadrant_states(seed))
+    vel = np.zeros((ms.dim, ms.ndofs))
+    vel[0] = st[q, 1]
+    if ms.dim > 1:
+        vel[1] = st[q, 2]
+    if ms.dim == 3 and wz:
+        vel[2] = st[(q + 1) % 4, 2]
+    return W.to_conserved(st[q, 0], vel, st[q, 3])
+
+
+def _smooth(oracle, ms, seed=7):
+    x = _oracle_mesh(oracle, ms).coords()
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0, 2 * np.pi, size=(4, ms.dim))
+    f = lambda r: np.sum(np.sin(2 * np.pi * x + ph[r]), axis=1) / ms.dim
+    vel = np.stack([0.4 * f(1 + (e % 2)) for e in range(ms.dim)])
+    return W.to_conserved(1.0 + 0.4 * f(0), vel, 1.0 + 0.5 * f(3))
+
+
+INFLOW = (1.2, 0.3, -0.2, 3.0)  # rho, u, v, p of the Dirichlet faces
+
+# (mesh, initial data) builders; cell counts span several row blocks with a
+# ragged last one
+CASES = {
+    "q1_2d_outflow": (lambda: _mesh(2, 1, (9, 7), (1,) * 4), _quadrant),
+    "q1_2d_periodic": (lambda: _mesh(2, 1, (8, 8), (0,) * 4, periodic=True), _smooth),
+    "q1_2d_dirichlet": (lambda: _mesh(2, 1, (7, 6), (3, 1, 2, 2), seed=5,
+                                      bstate=(tuple(W.to_conserved(np.array([INFLOW[0]]),
+                                                                   np.array([[INFLOW[1]], [INFLOW[2]]]),
+                                                                   np.array([INFLOW[3]]))[:, 0]),) + (None,) * 3),
+                        _smooth),
+    "q2_2d_slip": (lambda: _mesh(2, 2, (6, 5), (2,) * 4, seed=9), _quadrant),
+    "q2_2d_periodic": (lambda: _mesh(2, 2, (6, 6), (0,) * 4, amp=0.2, periodic=True), _smooth),
+    "q3_2d_mixed": (lambda: _mesh(2, 3, (5, 4), (1, 1, 2, 2), amp=0.2, seed=11), _quadrant),
+    "q1_3d_slip": (lambda: _mesh(3, 1, (5, 4, 3), (2,) * 6, seed=13), _quadrant),
+    "q1_3d_tiled_mixed_bc": (lambda: _mesh(3, 1, (16, 3, 2), (2, 2, 1, 1, 2, 2), seed=17), _smooth),
+    "q2_3d_outflow": (lambda: _mesh(3, 2, (3, 3, 2), (1,) * 6, amp=0.2, seed=19), _quadrant),
+}
+
+
+def _pair(oracle, name, params=None):
+    build, data = CASES[name]
+    ms = build()
+    U = data(oracle, ms)
+    M = _oracle_mesh(oracle, ms)
+    p = gdg.gdg_default_params(ms.degree) if params is None else params
+    S = gdg.Solver.from_spec(ms, p)
+    S.upload(U)
+    op = oracle.params(gamma=p.gamma, cfl=p.cfl, c_ev=p.c_ev, c_k=p.c_k, c_r=p.c_r, p_r=p.p_r,
+                       passes=p.limiter_passes, scheme=p.scheme, degree=ms.degree)
+    return ms, U, M, S, op
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_node_coords(oracle, name):
+    """x_i = F_K(xi_a) on both sides."""
+    _say("coords " + name)
+    ms, U, M, S, op = _pair(oracle, name)
+    assert np.abs(S.coords() - M.coords()).max() < 1e-14
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_stage_fields(oracle, name):
+    """One forward-Euler stage: tau, U^L, bounds, N_i, dU^H, U^(1), Phi(U)."""
+    _say("stage fields " + name)
+    ms, U, M, S, op = _pair(oracle, name)
+    out, dg = M.stage(op, U, diag=True)
+    assert dg["status"] == 0
+    tau_o = op.cfl * dg["tau_max"]
+    tau_g = S.stage(0.0)
+    assert tau_g == pytest.approx(tau_o, rel=1e-13)
+    _close(S.field(gdg.GDG_FIELD_UL), dg["UL"], what="U^L")
+    B = S.field(gdg.GDG_FIELD_BOUNDS)
+    _close(B, np.stack([dg["rho_min"], dg["rho_max"], dg["s_min"]]), what="bounds")
+    _check_ev(S.field(gdg.GDG_FIELD_EV_N)[0], dg)
+    _close(S.field(gdg.GDG_FIELD_DUH), dg["dUH"], what="dU^H")
+    _close(S.field(gdg.GDG_FIELD_U1), dg["U1"], what="U^(1)")
+    _close(S.download(), out, what="Phi(U)")
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_steps(oracle, name):
+    """Five SSP-RK3 steps through the captured graphs: same steps, same time,
+    states to 1e-10; sum_i m_i U_i agrees with the oracle's masses."""
+    _say("steps " + name)
+    ms, U, M, S, op = _pair(oracle, name)
+    Uo, t_o, n_o = M.run_to(op, U, 1.0, max_steps=5)
+    st = S.run_to(1.0, max_steps=5)
+    assert st.steps == n_o == 5 and st.t == pytest.approx(t_o, rel=1e-12)
+    Ug = S.download()
+    _close(Ug, Uo, tol=1e-10, what="U after 5 steps")
+    mi = M.lumped()
+    tot = (Ug * mi).sum(axis=1)
+    scale = np.abs(Ug * mi).sum(axis=1)
+    assert np.all(np.abs(np.array(st.total[:ms.dim + 2]) - tot) <= 1e-12 * scale)
+
+
+@pytest.mark.parametrize("name", ["q1_2d_periodic", "q2_2d_periodic"])
+def test_periodic_totals_are_conserved(oracle, name):
+    """Lemma TotBalLemma on general cells: with every face periodic the
+    mass-weighted totals sum_i m_i U_i stay put to rounding."""
+    _say("totals " + name)
+    ms, U, M, S, op = _pair(oracle, name)
+    s0 = np.array(S.stats().total[:ms.dim + 2])
+    st = S.run_to(1.0, max_steps=16)
+    s1 = np.array(st.total[:ms.dim + 2])
+    scale = (np.abs(U) * M.lumped()).sum(axis=1)
+    assert np.all(np.abs(s1 - s0) <= 1e-13 * scale)
+
+
+@pytest.mark.parametrize("scheme", [gdg.GDG_LOW_ORDER, gdg.GDG_HIGH_ORDER])
+@pytest.mark.parametrize("name", ["q1_2d_outflow", "q2_2d_slip", "q1_3d_slip"])
+def test_scheme_modes(oracle, name, scheme):
+    _say("scheme %d %s" % (scheme, name))
+    p = gdg.gdg_default_params(CASES[name][0]().degree)
+    p.scheme = scheme
+    ms, U, M, S, op = _pair(oracle, name, p)
+    Uo, dt_o, _, st = M.step(op, U)
+    if st == -2:
+        with pytest.raises(gdg.GdgError) as ei:
+            S.step()
+        assert ei.value.status == gdg.GDG_E_INADMISSIBLE
+        return
+    assert st == 0
+    assert S.step() == pytest.approx(dt_o, rel=1e-13)
+    _close(S.download(), Uo, what="U^{n+1}")
+
+
+@pytest.mark.parametrize("name", ["q2_2d_slip", "q2_3d_outflow"])
+def test_high_order_minimal_viscosity(oracle, name):
+    """c_ev = 0: d^H = d^min of eq. ViscMin alone.  On Q2 (p_k = 1/2) a
+    collocated pair across a face of two different cells takes hhat from the
+    mean of the two rows' masses, which differ on general cells."""
+    _say("c_ev = 0 " + name)
+    p = gdg.gdg_default_params(2)
+    p.scheme = gdg.GDG_HIGH_ORDER
+    p.c_ev = 0.0
+    ms, U, M, S, op = _pair(oracle, name, p)
+    out, dg = M.stage(op, U, diag=True)
+    if dg["status"] == -2:
+        with pytest.raises(gdg.GdgError):
+            S.stage(0.0)
+    else:
+        S.stage(0.0)
+        _close(S.download(), out, what="U^H")
+    _close(S.field(gdg.GDG_FIELD_DUH), dg["dUH"], what="dU^H")
+
+
+@pytest.mark.parametrize("name", ["q1_2d_outflow", "q2_2d_slip", "q1_3d_slip"])
+def test_mixed_precision(oracle, name):
+    """GDG_MIXED on general cells: c_ij in FP32, the flux sums in FP32; after
+    five steps within the mixed variant's L1 bound of the FP64 oracle."""
+    _say("mixed " + name)
+    p = gdg.gdg_default_params(CASES[name][0]().degree)
+    p.precision = gdg.GDG_MIXED
+    ms, U, M, S, op = _pair(oracle, name, p)
+    Uo, t_o, n_o = M.run_to(op, U, 1.0, max_steps=5)
+    st = S.run_to(1.0, max_steps=5)
+    assert st.steps == n_o
+    assert st.t == pytest.approx(t_o, rel=1e-5)
+    assert np.all(l1_rel(S.download(), Uo, M.lumped()) <= L1_TOL)
+    assert st.bound_violations == 0
+
+
+def test_server_request_on_general_cells(oracle):
+    """Requests with vertices through the batched server: the same steps as
+    gdg_run_to and states within 1e-12 of it (the batched kernels' order of
+    blocks differs), and the server holds its own copy of the vertices."""
+    _say("server")
+    reqs = []
+    for name, tf in (("q1_2d_outflow", 0.01), ("q1_2d_periodic", 0.02), ("q1_2d_dirichlet", 0.01)):
+        ms = CASES[name][0]()
+        reqs.append((ms, CASES[name][1](oracle, ms), tf))
+    refs = []
+    for ms, U, tf in reqs:
+        S = gdg.Solver.from_spec(ms)
+        S.upload(U)
+        st = S.run_to(tf)
+        refs.append((S.download(), st.steps))
+        S.close()
+    moved = [(W.MeshSpec(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc, bstate=ms.bstate,
+                         vertices=ms.vertices.copy()), U, tf) for ms, U, tf in reqs]
+    outs, infos, _ = _run_server(moved, gdg.GDG_FP64, max_slots=4, after_submit=lambda: [
+        m.vertices.fill(np.nan) for m, _, _ in moved])
+    for r, (ref, steps) in enumerate(refs):
+        assert infos[r].state == gdg.GDG_REQ_DONE and infos[r].steps == steps, (r, infos[r].state)
+        scale = np.abs(ref).max(axis=1, keepdims=True)
+        assert (np.abs(outs[r] - ref) / scale).max() <= 1e-12, r
+
+
+def test_degenerate_rows(oracle):
+    """Rows where D_i of the entropy residual (Sec. 5.2) vanishes in exact
+    arithmetic but not in rounding: Q2 quadrant data without z-velocity on a
+    general 3D mesh.  There N_i = R_i / D_i is a ratio of rounding errors on
+    both sides (the oracle's conditioning number Ncond_i = sum |terms| / D_i
+    exceeds 1e15), so the two N_i need not agree, and neither need the stage
+    results of the cells whose stencil holds such a row.  What must hold:
+    |N_i| <= 1, N_i agrees wherever Ncond_i < 1e12, the stage output agrees
+    away from the affected cells, and it is admissible and inside its
+    bounds everywhere."""
+    _say("degenerate rows")
+    ms = _mesh(3, 2, (6, 6, 2), (1,) * 6, amp=0.2, seed=19)
+    U = _quadrant(oracle, ms, wz=False)
+    M = _oracle_mesh(oracle, ms)
+    p = gdg.gdg_default_params(2)
+    S = gdg.Solver.from_spec(ms, p)
+    S.upload(U)
+    op = oracle.params(degree=2)
+    out, dg = M.stage(op, U, diag=True)
+    S.stage(0.0)
+    Ng, No, cond = S.field(gdg.GDG_FIELD_EV_N)[0], dg["N"], dg["Ncond"]
+    noise = np.isfinite(cond) & (cond > 1e15)
+    assert noise.any(), "the configuration no longer has degenerate rows"
+    assert np.all(np.abs(Ng) <= 1 + 1e-14)
+    good = ~noise & (np.where(np.isfinite(cond), cond, 0.0) < 1e12)
+    assert np.all(np.abs(Ng - No)[good] <= 1e-12 + 1e-13 * np.where(np.isfinite(cond), cond, 0.0)[good])
+    # cells reached by a noisy N: d^H of a pair uses N_i and N_j, dU^H couples
+    # the cell, the limiter's fluxes use dU^H_j of the neighbours
+    rp, col, _, _, _ = M.csr()
+    nloc = ms.nloc
+    rows = np.repeat(np.arange(ms.ndofs), np.diff(rp))
+    touched = np.zeros(ms.ndofs, bool)
+    touched[rows[noise[col]]] = True
+    touched |= noise
+    cells = np.zeros(ms.ncells, bool)
+    cells[np.nonzero(touched)[0] // nloc] = True
+    ring = np.repeat(cells, nloc)
+    ring2 = ring.copy()
+    ring2[rows[ring[col]]] = True
+    ok = ~np.repeat(np.bincount(np.nonzero(ring2)[0] // nloc, minlength=ms.ncells) > 0, nloc)
+    assert ok.sum() > ms.ndofs // 4
+    Ug = S.download()
+    _close(Ug[:, ok], out[:, ok], what="Phi(U) away from the degenerate rows")
+    B = S.field(gdg.GDG_FIELD_BOUNDS)
+    eps = Ug[4] - 0.5 * np.sum(Ug[1:4] ** 2, 0) / Ug[0]
+    assert np.all(Ug[0] > 0) and np.all(eps > 0)
+    assert S.stats().bound_violations == 0
+    assert np.all(Ug[0] >= B[0] * (1 - 1e-12)) and np.all(Ug[0] <= B[1] * (1 + 1e-12))
+

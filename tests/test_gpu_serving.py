@@ -43,9 +43,11 @@ def _requests(dim, degree, n, seed0=40):
     return out
 
 
-def _run_server(reqs, precision, max_slots=8, budget=None, arrivals=None, spg=4, solo_dofs=0):
+def _run_server(reqs, precision, max_slots=8, budget=None, arrivals=None, spg=4, solo_dofs=0,
+                after_submit=None):
     """Submits reqs (at pump index arrivals[r], default all at once), pumps
-    until all finish; returns results, infos and the peak resident count."""
+    until all finish; returns results, infos and the peak resident count.
+    after_submit: called once all requests are submitted."""
     dim, degree = reqs[0][0].dim, reqs[0][0].degree
     if budget is None:
         budget = 256 << 20
@@ -59,6 +61,8 @@ def _run_server(reqs, precision, max_slots=8, budget=None, arrivals=None, spg=4,
         for r, (ms, U, tf) in enumerate(reqs):
             if tickets[r] is None and arrivals[r] <= k:
                 tickets[r] = S.submit(ms, U, tf)
+                if after_submit is not None and all(t is not None for t in tickets):
+                    after_submit()
         res, pend = S.pump()
         peak = max(peak, res)
         k += 1

@@ -24,30 +24,8 @@ from paper_2402_04514_amd import workloads as W
 from test_oracle_scheme import _l1
 
 
-def lattice(cells, lo, hi):
-    axes = [np.linspace(lo[e], hi[e], cells[e] + 1) for e in range(len(cells))]
-    grids = np.meshgrid(*axes, indexing="ij")
-    # x fastest
-    return np.stack([g.transpose(*reversed(range(len(cells)))).ravel() for g in grids], axis=1)
-
-
-def perturbed(cells, lo, hi, amp=0.25, seed=3, periodic=False):
-    """Interior vertices moved by up to amp cell widths (random, seeded), or
-    by a smooth periodic field that vanishes on the boundary (periodic)."""
-    V = lattice(cells, lo, hi)
-    d = len(cells)
-    h = np.array([(hi[e] - lo[e]) / cells[e] for e in range(d)])
-    idx = np.stack(np.unravel_index(np.arange(V.shape[0]), tuple(c + 1 for c in reversed(cells))), axis=1)[:, ::-1]
-    interior = np.all((idx > 0) & (idx < np.array(cells)), axis=1)
-    if periodic:
-        xi = (V - np.array(lo)) / (np.array(hi) - np.array(lo))
-        s = np.prod(np.sin(2 * np.pi * xi), axis=1)
-        for e in range(d):
-            V[:, e] += amp * h[e] * s * (1 if e % 2 == 0 else -1)
-        return V
-    rng = np.random.default_rng(seed)
-    V[interior] += amp * h * rng.uniform(-1, 1, size=(int(interior.sum()), d))
-    return V
+lattice = W.lattice
+perturbed = W.perturbed_lattice
 
 
 MESHES = {
