@@ -83,6 +83,8 @@ def lib():
         L.or_volume.argtypes = [C.c_void_p]
         L.or_set_reference_volume.restype = None
         L.or_set_reference_volume.argtypes = [C.c_void_p, C.c_double]
+        L.or_set_boundary_kinds.restype = C.c_int
+        L.or_set_boundary_kinds.argtypes = [C.c_void_p, C.POINTER(C.c_byte)]
         L.or_set_boundary_state.restype = None
         L.or_set_boundary_state.argtypes = [C.c_void_p, C.c_int, _DP]
         L.or_inoutflow_state.restype = C.c_int
@@ -130,7 +132,7 @@ def params(gamma=1.4, cfl=0.5, degree=1, c_ev=None, c_k=1.0, c_r=4.0, p_r=1.5, p
 class Mesh:
     """Uniform Cartesian DG Q_k mesh with the stencil of Sec. 2.3."""
 
-    def __init__(self, dim, degree, cells, lo, hi, bc, bstate=None, vortex=None, vertices=None):
+    def __init__(self, dim, degree, cells, lo, hi, bc, bstate=None, vortex=None, vertices=None, bc_cells=None):
         """bc: kinds per box face 2*axis+side (0 periodic, 1 outflow, 2 slip,
         3 Dirichlet, 4 supersonic in/outflow, 5 sub- and supersonic
         in/outflow).  bstate: per face the conserved Dirichlet data U^d of
@@ -138,7 +140,10 @@ class Mesh:
         gamma) to take the data of kinds 3-5 from the isentropic vortex at the
         node and the stage time instead (2D).  vertices: the cell lattice's
         vertices, shape ((n_0+1)(n_1+1)..., dim), x fastest, for general
-        (multilinearly mapped) cells; lo and hi are then ignored."""
+        (multilinearly mapped) cells; lo and hi are then ignored.  bc_cells:
+        a kind per boundary cell face (kinds 1-5): for each non-periodic box
+        face in order, its cells lexicographically over the other axes, the
+        lowest axis fastest; data kinds take that box face's data."""
         self.dim, self.degree = dim, degree
         self.cells = tuple(int(c) for c in cells)
         self.lo = tuple(float(x) for x in lo)
@@ -166,8 +171,23 @@ class Mesh:
             assert v.shape == (6,)
             if L.or_set_vortex_data(self._h, _dp(v)) != 0:
                 raise ValueError("vortex boundary data needs a 2D mesh")
+        kinds = [{self.bc[f]} for f in range(2 * dim)]
+        if bc_cells is not None:
+            k = np.ascontiguousarray(bc_cells, dtype=np.int8).ravel()
+            pos = 0
+            for f in range(2 * dim):
+                if self.bc[f] == 0:
+                    continue
+                cnt = int(np.prod([self.cells[g] for g in range(dim) if g != f // 2]))
+                kinds[f] = set(int(x) for x in k[pos:pos + cnt])
+                pos += cnt
+            if pos != k.size:
+                raise ValueError("bc_cells needs %d entries, not %d" % (pos, k.size))
+            self._bcc = k
+            if L.or_set_boundary_kinds(self._h, k.ctypes.data_as(C.POINTER(C.c_byte))) != 0:
+                raise ValueError("bc_cells holds a periodic or unknown kind")
         for f in range(2 * dim):
-            if self.bc[f] in (3, 4, 5) and vortex is None:
+            if kinds[f] & {3, 4, 5} and vortex is None:
                 if bstate is None or bstate[f] is None:
                     raise ValueError("face %d needs Dirichlet data" % f)
                 v = np.ascontiguousarray(bstate[f], dtype=np.float64)

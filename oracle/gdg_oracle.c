@@ -73,6 +73,8 @@ typedef struct {
   /* boundary parts per row (Sec. 4.2): face id, c_i^{d,k}, boundary kind */
   long *bptr;
   int *bface;
+  int *bkind;    /* boundary kind of each boundary part: bc[bface], or the
+                    part's own kind (or_set_boundary_kinds) */
   double *bc_c;  /* nbnd * dim */
   /* reference tables */
   double xg[4];  /* Gauss-Lobatto nodes on [0,1] */
@@ -418,7 +420,7 @@ static void canonical_cij(const or_setup *S, long i, long j, double *out) {
 void or_destroy(or_setup *S) {
   if (!S) return;
   free(S->rowptr); free(S->col); free(S->c); free(S->mij); free(S->kind); free(S->mi);
-  free(S->bptr); free(S->bface); free(S->bc_c); free(S->vx);
+  free(S->bptr); free(S->bface); free(S->bkind); free(S->bc_c); free(S->vx);
   free(S);
 }
 
@@ -577,6 +579,7 @@ static void setup_build(or_setup *S) {
   S->kind = (int *)malloc(cap * sizeof(int));
   S->mi = (double *)malloc(N * sizeof(double));
   S->bface = (int *)malloc(bcap * sizeof(int));
+  S->bkind = (int *)malloc(bcap * sizeof(int));
   S->bc_c = (double *)malloc(bcap * dim * sizeof(double));
 
   /* reference cell quantities (identical for every uniform cell, but computed
@@ -654,6 +657,7 @@ static void setup_build(or_setup *S) {
           S->bc_c[nb * dim + e] = 0.5 * n * face_integral(S, f, a, -1, 1);
         }
         S->bface[nb] = f;
+        S->bkind[nb] = S->bc[f];
         ++nb;
       }
     }
@@ -692,6 +696,42 @@ double or_volume(const or_setup *S) { return S->vol; }
  * its rows get the constants of the full problem. */
 void or_set_reference_volume(or_setup *S, double vol) {
   if (vol > 0.0) S->vol = vol;
+}
+
+/* Boundary kinds per boundary cell face instead of one per box face (Sec. 4.1
+ * applies its conditions part by part of the boundary): for each box face f
+ * that is not periodic, in order of f, one kind per cell face on it, the
+ * cells of that face taken lexicographically over the other axes with the
+ * lowest axis fastest.  Data kinds take the data of box face f.  Returns 0,
+ * or -1 (nothing changed) for a periodic kind or an unknown one. */
+int or_set_boundary_kinds(or_setup *S, const signed char *kinds) {
+  const int dim = S->dim;
+  long off[6], n = 0;
+  for (int f = 0; f < 2 * dim; ++f) {
+    off[f] = n;
+    if (S->bc[f] == OR_BC_PERIODIC) continue;
+    long cnt = 1;
+    for (int g = 0; g < dim; ++g)
+      if (g != f / 2) cnt *= S->n[g];
+    n += cnt;
+  }
+  for (long q = 0; q < n; ++q)
+    if (kinds[q] <= OR_BC_PERIODIC || kinds[q] > OR_BC_INOUTFLOW) return -1;
+  for (long i = 0; i < S->ndofs; ++i) {
+    long ki[3];
+    cell_multi(S, i / S->nloc, ki);
+    for (long b = S->bptr[i]; b < S->bptr[i + 1]; ++b) {
+      const int f = S->bface[b], e = f / 2;
+      long idx = 0, stride = 1;
+      for (int g = 0; g < dim; ++g) {
+        if (g == e) continue;
+        idx += ki[g] * stride;
+        stride *= S->n[g];
+      }
+      S->bkind[b] = kinds[off[f] + idx];
+    }
+  }
+  return 0;
 }
 
 void or_csr(const or_setup *S, long *rowptr, long *col, double *c, double *mij, int *kind) {
@@ -996,9 +1036,9 @@ static int inoutflow_state(int dim, double g, const double *Ui, const double *Ud
  *    returns -4 (and U_i as the ghost);
  *  - sub- and supersonic in/outflow: inoutflow_state().
  * Returns 0 or -4. */
-static int ghost_state(const or_setup *S, double gamma, int f, long i, double t, const double *Ui, const double *cb,
-                       double *Ug) {
-  int dim = S->dim, bkind = S->bc[f];
+static int ghost_state(const or_setup *S, double gamma, int f, int bkind, long i, double t, const double *Ui,
+                       const double *cb, double *Ug) {
+  int dim = S->dim;
   double nn = 0.0;
   for (int e = 0; e < dim; ++e) nn += cb[e] * cb[e];
   nn = sqrt(nn);
@@ -1229,7 +1269,7 @@ static int stage_at(const or_setup *S, const or_params *P, const double *U, doub
     double Ui[OR_MAXM];
     get_state(S, U, i, Ui);
     for (long b = S->bptr[i]; b < S->bptr[i + 1]; ++b)
-      if (ghost_state(S, g, S->bface[b], i, t, Ui, S->bc_c + b * dim, Ug + b * m)) subsonic = 1;
+      if (ghost_state(S, g, S->bface[b], S->bkind[b], i, t, Ui, S->bc_c + b * dim, Ug + b * m)) subsonic = 1;
   }
 
   /* eq. dij_low_order, dij_low_order_modified (reading R2: inside state on
@@ -1594,7 +1634,7 @@ void or_tau_rows(const or_setup *S, const or_params *P, const double *U, double 
     for (long b = S->bptr[i]; b < S->bptr[i + 1]; ++b) {
       const double *cb = S->bc_c + b * dim;
       double nc = norm_c(dim, cb), n[3];
-      ghost_state(S, P->gamma, S->bface[b], i, S->t0, Ui, cb, Ug);
+      ghost_state(S, P->gamma, S->bface[b], S->bkind[b], i, S->t0, Ui, cb, Ug);
       for (int e = 0; e < dim; ++e) n[e] = cb[e] / nc;
       s += nc * or_lambda_max(P->gamma, dim, Ui, Ug, n);
     }

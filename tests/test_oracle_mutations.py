@@ -19,9 +19,16 @@ BND = T + "test_oracle_boundary.py"
 VISC = T + "test_oracle_viscosity.py"
 INOUT = T + "test_oracle_inoutflow.py"
 MAPPED = T + "test_oracle_mapped.py"
+BCPARTS = T + "test_oracle_bcparts.py"
 
 MUTANTS = {
     # name: (original text, planted text, pin files that must fail)
+    "boundary_part_axes_reversed": ("      for (int g = 0; g < dim; ++g) {\n        if (g == e) continue;\n        idx += ki[g] * stride;",
+                                    "      for (int g = dim - 1; g >= 0; --g) {\n        if (g == e) continue;\n        idx += ki[g] * stride;",
+                                    [BCPARTS + "::test_split_face_is_local_3d"]),
+    "boundary_part_face_kind": ("      if (ghost_state(S, g, S->bface[b], S->bkind[b], i, t,",
+                                "      if (ghost_state(S, g, S->bface[b], S->bc[S->bface[b]], i, t,",
+                                [BCPARTS + "::test_split_face_is_local_2d"]),
     "mapped_gradient_transposed": ("for (int c = 0; c < dim; ++c) ge += Ji[c][e] * g[c];",
                                    "for (int c = 0; c < dim; ++c) ge += Ji[e][c] * g[c];",
                                    [MAPPED + "::test_identities_on_perturbed_cells"]),
