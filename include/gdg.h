@@ -125,7 +125,17 @@ typedef enum { GDG_FP64 = 0, GDG_MIXED = 1 } gdg_precision;
  * A periodic axis identifies the lattice's first and last layers of cells
  * across it; the caller keeps the two boundary layers of points congruent.
  * The pointer is read during gdg_create() only (the context keeps a copy for
- * gdg_node_coords()).  Not combined with GDG_DATA_VORTEX. */
+ * gdg_node_coords()).  Not combined with GDG_DATA_VORTEX.
+ *
+ * Boundary parts (Sec. 4.1 applies its conditions part by part): with
+ * bc_cells non-NULL each cell face on the boundary has its own kind.  For each
+ * box face f = 0 .. 2 dim - 1 whose bc[f] is not PERIODIC, in order of f, one
+ * entry per cell face on it, those cells taken lexicographically over the
+ * other axes with the lowest axis fastest; each entry is a gdg_bc other than
+ * PERIODIC.  The DIRICHLET, SUPERSONIC and INOUTFLOW parts of face f take
+ * face f's data (bc_state[f], or the vortex), which must then be admissible.
+ * bc[f] still decides which axes are periodic.  Read during gdg_create()
+ * only. */
 typedef struct {
   int32_t dim;
   int32_t degree;
@@ -138,6 +148,7 @@ typedef struct {
   int32_t reserved;
   double vortex[6];
   const double *vertices; /* NULL: the uniform box [lo, hi]; else host memory, see above */
+  const int8_t *bc_cells; /* NULL: kind bc[f] on all of box face f; else host memory, see above */
 } gdg_mesh_desc;
 
 /* Scheme constants.  gdg_default_params() gives the paper's values:
@@ -378,7 +389,7 @@ gdg_status gdg_server_create(const gdg_server_desc *desc, void *dev_pool, size_t
                              gdg_server **out);
 
 /* Queues a request; U0 is a host state (SoA, (dim+2) * N doubles), copied,
- * as are the mesh's vertices (general cells).
+ * as are the mesh's vertices (general cells) and boundary parts.
  * GDG_E_INVALID for a description outside the server's class or bad
  * constants, GDG_E_BUDGET if its workspace exceeds the whole pool. */
 gdg_status gdg_server_submit(gdg_server *srv, const gdg_mesh_desc *mesh, const gdg_params *prm, const double *U0,

@@ -37,8 +37,10 @@ struct gdg_ctx {
   // device-driven runs: a captured graph of kGraphSteps steps
   hipStream_t cap_stream;
   hipGraphExec_t graph_exec;
-  // general cells: the caller's vertices (mesh.vertices points here)
+  // general cells: the caller's vertices (mesh.vertices points here); boundary
+  // parts: their kinds (mesh.bc_cells points here)
   std::vector<double> vx;
+  std::vector<int8_t> bcc;
 };
 
 namespace {
@@ -51,10 +53,39 @@ struct Layout {
   int64_t N, ncells, nblocks, nslots;
   size_t off_ref, off_ctl, off_col, off_c, off_meta, off_kscale, off_U[3], off_Nd, off_Qd, off_Ld, off_U1d,
       off_dL, off_l1, off_acc, off_fsum, off_red, off_cnt, off_mrow, off_hprow, off_relrow, off_cmblk, off_cminv,
-      total;
+      off_bcc, total;
+  int64_t bcc_off[6], nbcc;  // boundary parts: first entry of each face, and the count
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool is_data_kind(int k) { return k == GDG_BC_DIRICHLET || k == GDG_BC_SUPERSONIC || k == GDG_BC_INOUTFLOW; }
+
+// Entries of the boundary parts before face f and on it (bc_cells layout).
+void part_offsets(const gdg_mesh_desc *m, int64_t *off, int64_t *total) {
+  int64_t n = 0;
+  for (int f = 0; f < 6; ++f) {
+    off[f] = n;
+    if (f >= 2 * m->dim || m->bc[f] == GDG_BC_PERIODIC) continue;
+    int64_t cnt = 1;
+    for (int g = 0; g < m->dim; ++g)
+      if (g != f / 2) cnt *= m->cells[g];
+    n += cnt;
+  }
+  *total = n;
+}
+
+// Whether some part of face f takes the face's data.
+bool face_has_data(const gdg_mesh_desc *m, int f) {
+  if (m->bc[f] == GDG_BC_PERIODIC) return false;
+  if (!m->bc_cells) return is_data_kind(m->bc[f]);
+  int64_t off[6], n;
+  part_offsets(m, off, &n);
+  const int64_t end = f + 1 < 6 ? off[f + 1] : n;
+  for (int64_t q = off[f]; q < end; ++q)
+    if (is_data_kind(m->bc_cells[q])) return true;
+  return false;
+}
 
 bool validate(const gdg_mesh_desc *m, const gdg_params *p, std::string *err) {
   if (!m || !p) { *err = "null argument"; return false; }
@@ -68,9 +99,35 @@ bool validate(const gdg_mesh_desc *m, const gdg_params *p, std::string *err) {
     int b0 = m->bc[2 * e], b1 = m->bc[2 * e + 1];
     for (int b : {b0, b1})
       if (b < GDG_BC_PERIODIC || b > GDG_BC_INOUTFLOW) { *err = "unknown boundary kind"; return false; }
+    if ((b0 == GDG_BC_PERIODIC) != (b1 == GDG_BC_PERIODIC)) {
+      *err = "periodic must be set on both faces of an axis";
+      return false;
+    }
+    if (b0 == GDG_BC_PERIODIC && m->cells[e] < 2) {
+      *err = "a periodic axis needs at least 2 cells";
+      return false;
+    }
+    ncells *= m->cells[e];
+  }
+  // boundary parts and the data of the faces, once every axis is checked
+  for (int e = 0; e < m->dim; ++e) {
+    if (m->bc_cells) {
+      // the parts' own kinds: no periodic or unknown kind
+      int64_t off[6], n;
+      part_offsets(m, off, &n);
+      for (int side = 0; side < 2; ++side) {
+        const int f = 2 * e + side;
+        const int64_t end = f + 1 < 6 ? off[f + 1] : n;
+        for (int64_t q = off[f]; q < end; ++q)
+          if (m->bc_cells[q] <= GDG_BC_PERIODIC || m->bc_cells[q] > GDG_BC_INOUTFLOW) {
+            *err = "a boundary part has a periodic or unknown kind";
+            return false;
+          }
+      }
+    }
     for (int side = 0; side < 2; ++side) {
       const int f = 2 * e + side;
-      if (m->bc[f] != GDG_BC_DIRICHLET && m->bc[f] != GDG_BC_SUPERSONIC && m->bc[f] != GDG_BC_INOUTFLOW) continue;
+      if (!face_has_data(m, f)) continue;
       if (m->data_kind == GDG_DATA_VORTEX) continue;  // checked below
       // the face's data must lie in A (eq. AddSet)
       const double *V = m->bc_state[f];
@@ -82,15 +139,6 @@ bool validate(const gdg_mesh_desc *m, const gdg_params *p, std::string *err) {
         return false;
       }
     }
-    if ((b0 == GDG_BC_PERIODIC) != (b1 == GDG_BC_PERIODIC)) {
-      *err = "periodic must be set on both faces of an axis";
-      return false;
-    }
-    if (b0 == GDG_BC_PERIODIC && m->cells[e] < 2) {
-      *err = "a periodic axis needs at least 2 cells";
-      return false;
-    }
-    ncells *= m->cells[e];
   }
   if (m->data_kind != GDG_DATA_CONSTANT && m->data_kind != GDG_DATA_VORTEX) {
     *err = "unknown boundary data kind";
@@ -178,7 +226,9 @@ Layout layout(const gdg_mesh_desc *m, const gdg_params *p) {
   L.off_fsum = take(M * N * 8);
   L.off_red = take((size_t)(kRedBlocks + 1) * kRedFields * 8);
   L.off_cnt = take((size_t)kCntKinds * kCntSlots * kCntStride * 8);
-  L.off_mrow = L.off_hprow = L.off_relrow = L.off_cmblk = L.off_cminv = 0;
+  L.off_mrow = L.off_hprow = L.off_relrow = L.off_cmblk = L.off_cminv = L.off_bcc = 0;
+  part_offsets(m, L.bcc_off, &L.nbcc);
+  if (m->bc_cells) L.off_bcc = take((size_t)L.nbcc);
   if (m->vertices) {
     const size_t blk = (size_t)L.ncells * L.nloc * L.nloc * 8;
     L.off_mrow = take(N * 8);
@@ -370,6 +420,10 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
     ctx->vx.assign(mesh->vertices, mesh->vertices + npts * mesh->dim);
     ctx->mesh.vertices = ctx->vx.data();
   }
+  if (mesh->bc_cells) {
+    ctx->bcc.assign(mesh->bc_cells, mesh->bc_cells + L.nbcc);
+    ctx->mesh.bc_cells = ctx->bcc.data();
+  }
   ctx->prm = *prm;
   ctx->stream = (hipStream_t)hip_stream;
   ctx->M = L.M;
@@ -410,11 +464,13 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
     h[e] = (mesh->hi[e] - mesh->lo[e]) / (double)mesh->cells[e];
     vol *= mesh->hi[e] - mesh->lo[e];
   }
-  A.bcbits = 0;
+  A.bcdata = 0;
   for (int f = 0; f < 6; ++f) {
     A.bc[f] = f < 2 * mesh->dim ? mesh->bc[f] : GDG_BC_OUTFLOW;
-    A.bcbits |= (A.bc[f] & 7) << (3 * f);
+    if (f < 2 * mesh->dim && face_has_data(mesh, f)) A.bcdata |= 1 << f;
+    A.bcc_off[f] = L.bcc_off[f];
   }
+  A.bcc = mesh->bc_cells ? (const int8_t *)(ws + L.off_bcc) : nullptr;
   A.gamma = prm->gamma;
   A.cfl = prm->cfl;
   A.c_ev = prm->c_ev;
@@ -495,7 +551,7 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   const bool data_faces = mesh->data_kind == GDG_DATA_CONSTANT;
   for (int f = 0; f < 2 * mesh->dim; ++f)
     if (data_faces &&
-        (A.bc[f] == GDG_BC_DIRICHLET || A.bc[f] == GDG_BC_SUPERSONIC || A.bc[f] == GDG_BC_INOUTFLOW))
+        ((A.bcdata >> f) & 1))
       for (int q = 0; q < L.M; ++q) T->bstate[f][q] = mesh->bc_state[f][q];
   {
     // Gauss-Lobatto nodes on [0, 1], as in gdg_node_coords
@@ -513,6 +569,8 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   std::memset(&ctx->hctl, 0, sizeof(Ctl));
   hipError_t e1 = hipMemcpyAsync(ctx->dref, T, sizeof(RefTables), hipMemcpyHostToDevice, ctx->stream);
   hipError_t e2 = hipMemcpyAsync(A.ctl, &ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream);
+  if (e2 == hipSuccess && A.bcc)
+    e2 = hipMemcpyAsync((void *)A.bcc, ctx->bcc.data(), (size_t)L.nbcc, hipMemcpyHostToDevice, ctx->stream);
   int rc = (e1 == hipSuccess && e2 == hipSuccess) ? launch_fill(A, ctx->stream) : -1;
   if (rc == 0 && A.general) {
     // after the fill kernel on the same stream: its c and kappa entries are

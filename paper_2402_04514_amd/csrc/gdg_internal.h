@@ -9,6 +9,7 @@
 // Slot t of row lane r in block b lives at index (b * W + t) * R + r, so the
 // lanes of a wavefront read consecutive addresses for every slot.
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include <string>
@@ -24,10 +25,15 @@ enum : uint8_t {
   SK_CELL = 1,        // j in the same cell (the diagonal included); aux = local index of j
   SK_FACE_COLLOC = 2, // j across a face, x_j = x_i (topologically)
   SK_FACE = 3,        // j across a face, other node of that face
-  SK_GHOST = 4        // boundary part: col = i, c = c_i^{d,k}; aux = boundary kind
+  SK_GHOST = 4        // boundary part: col = i, c = c_i^{d,k}; aux = its boundary class
 };
 static inline int meta_kind(uint8_t m) { return m & 7; }
 static inline int meta_aux(uint8_t m) { return m >> 3; }
+// Boundary class of a boundary part (the aux bits of its slot, 0 .. 29): the
+// box face f whose data it takes and its kind (a gdg_bc other than PERIODIC).
+__host__ __device__ inline int bclass(int f, int kind) { return (kind - 1) * 6 + f; }
+__host__ __device__ inline int bclass_face(int c) { return c % 6; }
+__host__ __device__ inline int bclass_kind(int c) { return c / 6 + 1; }
 
 // One wavefront per workgroup: whole cells per block (the cell solve stays in
 // LDS), and a finished wave's slot is refilled at once, which matters where
@@ -133,7 +139,11 @@ struct KArgs {
   int32_t R, W, nloc, nb1, deg, dim, cpb;
   int64_t cells[3];
   int32_t bc[6];
-  int32_t bcbits;   // the boundary kind of face f in bits 3f..3f+2
+  int32_t bcdata;   // bit f: some part of face f has a data kind (Dirichlet, supersonic, in/outflow)
+  // boundary parts with their own kinds (NULL: bc[f] everywhere): the kind of
+  // the cell face with index idx over the other axes of face f at bcc[bcc_off[f] + idx]
+  const int8_t *bcc;
+  int64_t bcc_off[6];
   int32_t no_quiet; // GDG_FLAG_NO_QUIET_ROWS: sweep 2 marks no row quiet
   // data of the Dirichlet-type faces from the isentropic vortex (beta, x0,
   // u_inf, gamma) at the node and the stage time instead of bnode

@@ -367,7 +367,18 @@ __global__ __launch_bounds__(kBlockThreads) void k_fill(KArgs A) {
         else bnd = true;
       }
       if (bnd) {
-        put((int32_t)i, &T->cghost[(f * kMaxNloc + a) * kMaxD], (uint8_t)(SK_GHOST | (f << 3)));
+        // the part's kind: its own (boundary parts), else the box face's
+        int kind = A.bc[f];
+        if (A.bcc) {
+          int64_t idx = 0, st = 1;
+          for (int g = 0; g < D; ++g) {
+            if (g == e) continue;
+            idx += ki[g] * st;
+            st *= A.cells[g];
+          }
+          kind = A.bcc[A.bcc_off[f] + idx];
+        }
+        put((int32_t)i, &T->cghost[(f * kMaxNloc + a) * kMaxD], (uint8_t)(SK_GHOST | (bclass(f, kind) << 3)));
         continue;
       }
       int64_t Kn = 0, stride = 1;
@@ -517,8 +528,7 @@ template <int D>
 __global__ void k_bnodes(KArgs A, RefTables *T) {
   const int f = threadIdx.x;
   if (f >= 2 * D || A.vortex_data) return;  // time-dependent data: evaluated where used
-  const int kind = (A.bcbits >> (3 * f)) & 7;
-  if (kind != GDG_BC_DIRICHLET && kind != GDG_BC_SUPERSONIC && kind != GDG_BC_INOUTFLOW) return;
+  if (!((A.bcdata >> f) & 1)) return;        // no part of the face takes data
   double V[D + 2], W[D + 6];
   for (int q = 0; q < D + 2; ++q) V[q] = T->bstate[f][q];
   if (!node_fields<D>(A, V, W)) atomicOr(&A.ctl->bad_flag, 1);
@@ -705,9 +715,10 @@ __device__ __forceinline__ bool characteristic_state(const KArgs &A, const Node<
 // BD = false: the mesh has no face with data (the caller knows), and that
 // code is left out.
 template <int D, int DEG, bool BD = true>
-__device__ __forceinline__ void ghost_node(const KArgs &A, const Node<D> &ni, int f, const double *n, int64_t i,
+__device__ __forceinline__ void ghost_node(const KArgs &A, const Node<D> &ni, int cls, const double *n, int64_t i,
                                            double t, Node<D> &gh) {
-  const int kind = (A.bcbits >> (3 * f)) & 7;
+  // cls: the part's boundary class (its data face and its kind)
+  const int f = bclass_face(cls), kind = bclass_kind(cls);
   gh = ni;
   if (kind == GDG_BC_SLIP) {
     double mn = 0.0, un = 0.0;
@@ -1176,14 +1187,14 @@ __device__ __forceinline__ void ghost_flux(const KArgs &A, const double *__restr
   const double inc = 1.0 / sqrt(nc2);
   double n[D];
   for (int e = 0; e < D; ++e) n[e] = c[e] * inc;
-  const int f = meta >> 3;
-  const int kind = (A.bcbits >> (3 * f)) & 7;
+  const int cls = meta >> 3;
+  const int kind = bclass_kind(cls);
   double Ug[D + 2];
   if (kind == GDG_BC_DIRICHLET || kind == GDG_BC_SUPERSONIC || kind == GDG_BC_INOUTFLOW) {
     // the data kinds decide from the node of row i, as the sweeps do
     Node<D> ni, gh;
     load_node<D>(nd, i, ni);
-    ghost_node<D, DEG>(A, ni, f, n, i, t, gh);
+    ghost_node<D, DEG>(A, ni, cls, n, i, t, gh);
     for (int q = 0; q < D + 2; ++q) Ug[q] = gh.U[q];
   } else {
     // outflow and slip need U_i alone (the same arithmetic as ghost_node)
@@ -1581,11 +1592,7 @@ static int stage_impl(const KArgs &A, const StageBufs &b, int stage, void *strea
   }
   // sweep 1 without the boundary-data code where no face has data: its
   // registers set the occupancy of the hottest kernel
-  bool bd = false;
-  for (int f = 0; f < 2 * D; ++f) {
-    const int kind = (A.bcbits >> (3 * f)) & 7;
-    bd = bd || kind == GDG_BC_DIRICHLET || kind == GDG_BC_SUPERSONIC || kind == GDG_BC_INOUTFLOW;
-  }
+  const bool bd = A.bcdata != 0;
   prof_mark(prof, KID_SWEEP1, 0, stream);
   if (bd)
     hipLaunchKernelGGL((k_sweep1<D, DEG, MX, true>), grid, blk, 0, S(stream), A, b.in, stage);

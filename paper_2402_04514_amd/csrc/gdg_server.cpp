@@ -93,6 +93,7 @@ struct Req {
   gdg_params prm{};
   std::vector<double> U;  // initial state until admission, final state after
   std::vector<double> vx; // general cells: the request's vertices (mesh.vertices points here)
+  std::vector<int8_t> bcc; // boundary parts: their kinds (mesh.bc_cells points here)
   double t_final = 0.0;
   size_t bytes = 0, off = 0;
   gdg_ctx *ctx = nullptr;
@@ -446,6 +447,19 @@ gdg_status gdg_server_submit(gdg_server *s, const gdg_mesh_desc *mesh, const gdg
     for (int e = 0; e < mesh->dim; ++e) npts *= (size_t)(mesh->cells[e] + 1);
     q->vx.assign(mesh->vertices, mesh->vertices + npts * mesh->dim);
     q->mesh.vertices = q->vx.data();
+  }
+  if (mesh->bc_cells) {
+    // one entry per cell face of each non-periodic box face (gdg.h)
+    int64_t n = 0;
+    for (int f = 0; f < 2 * mesh->dim; ++f) {
+      if (mesh->bc[f] == GDG_BC_PERIODIC) continue;
+      int64_t cnt = 1;
+      for (int g = 0; g < mesh->dim; ++g)
+        if (g != f / 2) cnt *= mesh->cells[g];
+      n += cnt;
+    }
+    q->bcc.assign(mesh->bc_cells, mesh->bc_cells + n);
+    q->mesh.bc_cells = q->bcc.data();
   }
   q->prm = *prm;
   q->t_final = t_final;

@@ -41,7 +41,8 @@ class gdg_mesh_desc(C.Structure):
     _fields_ = [("dim", C.c_int32), ("degree", C.c_int32), ("cells", C.c_int64 * 3),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("bc", C.c_int32 * 6),
                 ("bc_state", (C.c_double * 5) * 6), ("data_kind", C.c_int32), ("reserved", C.c_int32),
-                ("vortex", C.c_double * 6), ("vertices", C.POINTER(C.c_double))]
+                ("vortex", C.c_double * 6), ("vertices", C.POINTER(C.c_double)),
+                ("bc_cells", C.POINTER(C.c_int8))]
 
 
 class gdg_params(C.Structure):
@@ -136,13 +137,16 @@ def _check(st, ctx=None):
         raise GdgError(st, msg)
 
 
-def mesh_desc(dim, degree, cells, lo, hi, bc, bstate=None, vortex=None, vertices=None) -> gdg_mesh_desc:
+def mesh_desc(dim, degree, cells, lo, hi, bc, bstate=None, vortex=None, vertices=None,
+              bc_cells=None) -> gdg_mesh_desc:
     """bstate: per face the conserved Dirichlet data of the DIRICHLET,
     SUPERSONIC and INOUTFLOW kinds (None, or None entries, elsewhere); vortex:
     (beta, x0_1, x0_2, u_1, u_2, gamma) to take that data from the isentropic
     vortex instead.  vertices: general cells, the lattice's points as an array
     of shape (prod(cells + 1), dim), the first axis fastest; the descriptor
-    keeps a reference to its float64 copy (``m._vx``)."""
+    keeps a reference to its float64 copy (``m._vx``).  bc_cells: a kind per
+    boundary cell face (for each non-periodic box face in order, its cells
+    lexicographically over the other axes, the lowest axis fastest)."""
     m = gdg_mesh_desc()
     m.dim, m.degree = dim, degree
     for e in range(3):
@@ -165,6 +169,14 @@ def mesh_desc(dim, degree, cells, lo, hi, bc, bstate=None, vortex=None, vertices
             raise ValueError(f"vertices must have shape ({npts}, {dim})")
         m._vx = vx
         m.vertices = vx.ctypes.data_as(C.POINTER(C.c_double))
+    if bc_cells is not None:
+        k = np.ascontiguousarray(bc_cells, dtype=np.int8).ravel()
+        n = sum(int(np.prod([int(cells[g]) for g in range(dim) if g != f // 2]))
+                for f in range(2 * dim) if int(bc[f]) != GDG_BC_PERIODIC)
+        if k.size != n:
+            raise ValueError(f"bc_cells needs {n} entries, not {k.size}")
+        m._bcc = k
+        m.bc_cells = k.ctypes.data_as(C.POINTER(C.c_int8))
     return m
 
 
@@ -290,11 +302,11 @@ class Solver:
     and whose stream is torch's current stream there (or ``stream``)."""
 
     def __init__(self, dim, degree, cells, lo, hi, bc, params: gdg_params | None = None,
-                 device="cuda:0", stream=None, bstate=None, vortex=None, vertices=None):
+                 device="cuda:0", stream=None, bstate=None, vortex=None, vertices=None, bc_cells=None):
         import torch
         self.torch = torch
         self.dim, self.m = dim, dim + 2
-        self.mesh = mesh_desc(dim, degree, cells, lo, hi, bc, bstate, vortex, vertices)
+        self.mesh = mesh_desc(dim, degree, cells, lo, hi, bc, bstate, vortex, vertices, bc_cells)
         self.params = params if params is not None else gdg_default_params(degree)
         self.device = torch.device(device)
         nbytes = gdg_workspace_bytes(self.mesh, self.params)
@@ -309,7 +321,7 @@ class Solver:
     def from_spec(cls, ms, params=None, **kw):
         return cls(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc, params,
                    bstate=getattr(ms, "bstate", None), vortex=getattr(ms, "vortex", None),
-                   vertices=getattr(ms, "vertices", None), **kw)
+                   vertices=getattr(ms, "vertices", None), bc_cells=getattr(ms, "bc_cells", None), **kw)
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -434,7 +446,8 @@ class Server:
         if params is None:
             prm.precision = self.desc.precision
         mesh = mesh_desc(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc, getattr(ms, "bstate", None),
-                         getattr(ms, "vortex", None), getattr(ms, "vertices", None))
+                         getattr(ms, "vortex", None), getattr(ms, "vertices", None),
+                         getattr(ms, "bc_cells", None))
         return gdg_server_submit(self.srv, mesh, prm, U0, t_final)
 
     def pump(self):

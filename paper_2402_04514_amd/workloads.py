@@ -47,6 +47,9 @@ class MeshSpec:
     # general cells: the lattice's points, shape (prod(cells + 1), dim), x
     # fastest (lo and hi then only name the box the points were drawn in)
     vertices: np.ndarray | None = field(default=None, repr=False, compare=False)
+    # boundary parts: a kind per boundary cell face (each non-periodic box face
+    # in order, its cells over the other axes, the lowest axis fastest)
+    bc_cells: np.ndarray | None = field(default=None, repr=False, compare=False)
 
     @property
     def nloc(self) -> int:
@@ -290,10 +293,80 @@ def serving_trace(count: int = 256, n_min: int = 32, n_max: int = 512, seed0: in
     return out
 
 
+def cylinder_ogrid(ntheta: int = 512, nr: int = 128, degree: int = 1, mach: float = 3.0,
+                   center=(0.6, 0.0), radius: float = 0.25, box=((0.0, 4.0), (-1.0, 1.0)),
+                   stretch: float = 0.0):
+    """The geometry of the Mach 3 flow past a cylinder (Sec. 6.4): the channel
+    box[0] x box[1] minus the disk of the given centre and radius, meshed by
+    an O-grid of general cells.  Axis 0 runs around the cylinder (periodic,
+    ntheta cells, the first and last layers of points coincide), axis 1 from
+    the cylinder (face 2) to the channel's walls (face 3), nr cells.
+
+    The ray from the centre at angle theta_i = pi - 2 pi i / ntheta (i = 0 at
+    the upstream stagnation line) meets the circle and the channel's
+    boundary; points on it are spaced by (e^(stretch s) - 1)/(e^stretch - 1)
+    (uniform for stretch 0).  The outer point nearest each of the channel's
+    four corners is moved onto that corner, so the outer face is the
+    rectangle itself.  Boundary parts of face 3: Dirichlet on x = box[0][0]
+    (the inflow, data: the free stream), outflow on x = box[0][1], slip on the
+    top and bottom walls; the cylinder (face 2) is a slip wall.
+
+    Returns (vertices of shape ((ntheta+1)(nr+1), 2), bc, bc_cells, the free
+    stream as conserved data): rho = gamma, p = 1 (sound speed 1), u = mach."""
+    (x0, x1), (y0, y1) = box
+    cx, cy = center
+    # clockwise, so that (around, outwards) is a positively oriented frame
+    th = math.pi - 2.0 * math.pi * np.arange(ntheta + 1) / ntheta
+    dx, dy = np.cos(th), np.sin(th)
+    # distance along each ray to the rectangle
+    with np.errstate(divide="ignore", invalid="ignore"):
+        tx = np.where(dx > 0, (x1 - cx) / dx, np.where(dx < 0, (x0 - cx) / dx, np.inf))
+        ty = np.where(dy > 0, (y1 - cy) / dy, np.where(dy < 0, (y0 - cy) / dy, np.inf))
+    t = np.minimum(tx, ty)
+    outer = np.stack([cx + t * dx, cy + t * dy], axis=1)
+    for corner in ((x0, y0), (x0, y1), (x1, y0), (x1, y1)):
+        ang = math.atan2(corner[1] - cy, corner[0] - cx) % (2 * math.pi)
+        rel = (th - ang) % (2 * math.pi)
+        i = int(np.argmin(np.minimum(rel, 2 * math.pi - rel)[:ntheta]))
+        outer[i] = corner
+        if i == 0:
+            outer[ntheta] = corner
+    inner = np.stack([cx + radius * dx, cy + radius * dy], axis=1)
+    s = np.arange(nr + 1) / nr
+    g = s if stretch == 0.0 else np.expm1(stretch * s) / math.expm1(stretch)
+    # point (i, j): i around (fastest), j outwards
+    V = inner[None, :, :] + g[:, None, None] * (outer - inner)[None, :, :]
+    V = V.reshape(-1, 2)
+    # kinds of the outer face's cell faces, by the midpoint of each edge
+    mid = 0.5 * (outer[:-1] + outer[1:])
+    eps = 1e-9 * max(x1 - x0, y1 - y0)
+    kinds = np.full(ntheta, BC_SLIP, dtype=np.int8)
+    kinds[np.abs(mid[:, 0] - x0) < eps] = BC_DIRICHLET
+    kinds[np.abs(mid[:, 0] - x1) < eps] = BC_OUTFLOW
+    bc = (BC_PERIODIC, BC_PERIODIC, BC_SLIP, BC_SLIP)
+    bc_cells = np.concatenate([np.full(ntheta, BC_SLIP, dtype=np.int8), kinds])
+    free = to_conserved(np.array([GAMMA]), np.array([[mach], [0.0]]), np.array([1.0]))[:, 0]
+    return V, bc, bc_cells, free
+
+
+def cylinder(ntheta: int = 512, nr: int = 128, degree: int = 1, mach: float = 3.0, stretch: float = 0.0,
+             t_final: float = 4.0) -> Workload:
+    """Mach 3 flow past a cylinder on the O-grid of cylinder_ogrid(): uniform
+    free stream everywhere at t = 0 (the wall of the cylinder starts the bow
+    shock)."""
+    V, bc, bc_cells, free = cylinder_ogrid(ntheta, nr, degree, mach, stretch=stretch)
+    bstate = (None, None, None, tuple(free))
+    ms = MeshSpec(2, degree, (ntheta, nr), (0.0, -1.0), (4.0, 1.0), bc, bstate=bstate, vertices=V,
+                  bc_cells=bc_cells)
+    U = np.repeat(free[:, None], ms.ndofs, axis=1)
+    return Workload("cylinder_q%d_%dx%d" % (degree, ntheta, nr), ms, U, t_final=t_final)
+
+
 CONFIGS = {
     "sod": sod,
     "vortex": vortex,
     "quadrant": quadrant,
     "blast": blast,
     "inflow": inflow,
+    "cylinder": cylinder,
 }

@@ -8,9 +8,11 @@ import subprocess
 
 import ctypes as C
 
+import numpy as np
 import pytest
 
 from paper_2402_04514_amd import gdg
+from paper_2402_04514_amd import workloads as W
 
 ROOT = pathlib.Path(__file__).resolve().parent.parent
 
@@ -200,3 +202,40 @@ def test_server_host_side_validation():
             gdg.gdg_server_result(srv, t1, np.zeros((4, 16 * 16 * 4)))  # not finished
     finally:
         gdg.gdg_server_destroy(srv)
+
+
+def test_general_cells_and_boundary_parts_validated():
+    """Host-side checks of general cells and boundary parts (no device work):
+    their tables take workspace, parts of a periodic or unknown kind are
+    refused, a data part needs admissible data on its face, and general cells
+    do not take the vortex data kind."""
+    p = gdg.gdg_default_params(1)
+    cells = (6, 4)
+    V = W.lattice(cells, (0, 0), (1, 1))
+    plain = gdg.gdg_workspace_bytes(gdg.mesh_desc(2, 1, cells, (0, 0), (1, 1), (1,) * 4), p)
+    mapped = gdg.gdg_workspace_bytes(gdg.mesh_desc(2, 1, cells, (0, 0), (1, 1), (1,) * 4, vertices=V), p)
+    assert mapped > plain
+    kinds = np.full(2 * 4 + 2 * 6, 2, dtype=np.int8)
+    parted = gdg.gdg_workspace_bytes(gdg.mesh_desc(2, 1, cells, (0, 0), (1, 1), (1,) * 4, bc_cells=kinds), p)
+    assert parted > plain
+    for bad in (0, 6, -1):
+        k = kinds.copy()
+        k[5] = bad
+        with pytest.raises(gdg.GdgError):
+            gdg.gdg_workspace_bytes(gdg.mesh_desc(2, 1, cells, (0, 0), (1, 1), (1,) * 4, bc_cells=k), p)
+    with pytest.raises(ValueError):
+        gdg.mesh_desc(2, 1, cells, (0, 0), (1, 1), (1,) * 4, bc_cells=kinds[:-1])
+    # a Dirichlet part on face 2 (entries 8 .. 13) needs admissible data there
+    k = kinds.copy()
+    k[9] = 3
+    with pytest.raises(gdg.GdgError):
+        gdg.gdg_workspace_bytes(gdg.mesh_desc(2, 1, cells, (0, 0), (1, 1), (1,) * 4, bc_cells=k), p)
+    good = (None, None, (1.0, 0.0, 0.5, 2.0), None)
+    assert gdg.gdg_workspace_bytes(gdg.mesh_desc(2, 1, cells, (0, 0), (1, 1), (1,) * 4, bstate=good,
+                                                 bc_cells=k), p) > 0
+    # periodic axes have no parts: x periodic leaves the 2 x 6 entries of faces 2, 3
+    kp = np.full(12, 2, dtype=np.int8)
+    assert gdg.gdg_workspace_bytes(gdg.mesh_desc(2, 1, cells, (0, 0), (1, 1), (0, 0, 1, 1), bc_cells=kp), p) > 0
+    with pytest.raises(gdg.GdgError):
+        gdg.gdg_workspace_bytes(gdg.mesh_desc(2, 1, cells, (0, 0), (1, 1), (1,) * 4, vertices=V,
+                                              vortex=(5.0, -1.0, -1.0, 1.0, 1.0, 1.4)), p)
