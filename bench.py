@@ -66,6 +66,11 @@ WORKLOADS = {
                "2D Euler DG Q2, 1024x1024 cells on [0,1]^2 (9,437,184 dofs), supersonic inflow (Dirichlet data "
                "rho,u,p = 1,2.5,1) into a supersonic stream (0.5,2.5,0.6), supersonic in/outflow faces in x, "
                "periodic in y, FP64, convex-limited, SSP-RK3", 100, 3),
+    "cylinder": ({"ntheta": 2048, "nr": 1152},
+                 "2D Euler DG Q1, Mach 3 flow past a cylinder of radius 0.25 at (0.6, 0) in the channel "
+                 "[0,4]x[-1,1], O-grid of 2048x1152 general (bilinearly mapped) cells (9,437,184 dofs), Dirichlet "
+                 "inflow, slip channel walls and cylinder, outflow (boundary parts), FP64, convex-limited, "
+                 "SSP-RK3, 100 steps from the uniform free stream at t=0", 100, 3),
 }
 
 
