@@ -69,6 +69,8 @@ def lib():
         L.or_create.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_long), _DP, _DP, C.POINTER(C.c_int)]
         L.or_create_mapped.restype = C.c_void_p
         L.or_create_mapped.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_long), _DP, C.POINTER(C.c_int)]
+        L.or_create_curved.restype = C.c_void_p
+        L.or_create_curved.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_long), _DP, C.POINTER(C.c_int), C.c_int]
         L.or_destroy.argtypes = [C.c_void_p]
         L.or_num_threads.restype = C.c_int
         L.or_num_threads.argtypes = []
@@ -132,7 +134,8 @@ def params(gamma=1.4, cfl=0.5, degree=1, c_ev=None, c_k=1.0, c_r=4.0, p_r=1.5, p
 class Mesh:
     """Uniform Cartesian DG Q_k mesh with the stencil of Sec. 2.3."""
 
-    def __init__(self, dim, degree, cells, lo, hi, bc, bstate=None, vortex=None, vertices=None, bc_cells=None):
+    def __init__(self, dim, degree, cells, lo, hi, bc, bstate=None, vortex=None, vertices=None, bc_cells=None,
+                 map_degree=1):
         """bc: kinds per box face 2*axis+side (0 periodic, 1 outflow, 2 slip,
         3 Dirichlet, 4 supersonic in/outflow, 5 sub- and supersonic
         in/outflow).  bstate: per face the conserved Dirichlet data U^d of
@@ -140,7 +143,10 @@ class Mesh:
         gamma) to take the data of kinds 3-5 from the isentropic vortex at the
         node and the stage time instead (2D).  vertices: the cell lattice's
         vertices, shape ((n_0+1)(n_1+1)..., dim), x fastest, for general
-        (multilinearly mapped) cells; lo and hi are then ignored.  bc_cells:
+        (multilinearly mapped) cells; lo and hi are then ignored.
+        map_degree 2: curved cells, vertices then holds the lattice of
+        2 n_e + 1 points per axis (corners, edge and face midpoints, centres)
+        of quadratic cell maps.  bc_cells:
         a kind per boundary cell face (kinds 1-5): for each non-periodic box
         face in order, its cells lexicographically over the other axes, the
         lowest axis fastest; data kinds take that box face's data."""
@@ -156,10 +162,10 @@ class Mesh:
         b = (C.c_int * 6)(*(list(self.bc) + [1] * (6 - len(self.bc))))
         if vertices is not None:
             vx = np.ascontiguousarray(vertices, dtype=np.float64)
-            nv = int(np.prod([n + 1 for n in self.cells]))
+            nv = int(np.prod([map_degree * n + 1 for n in self.cells]))
             assert vx.shape == (nv, dim), (vx.shape, nv, dim)
             self._vx = vx
-            self._h = L.or_create_mapped(dim, degree, c, _dp(vx), b)
+            self._h = L.or_create_curved(dim, degree, c, _dp(vx), b, int(map_degree))
         else:
             self._h = L.or_create(dim, degree, c, lo_, hi_, b)
         if not self._h:

@@ -85,6 +85,7 @@ typedef struct {
    * the multilinear image of the reference cell through its 2^dim corners.
    * NULL: the uniform box lo .. hi. */
   double *vx;
+  int mapdeg;    /* general cells: degree g of the cell map (1 multilinear, 2 quadratic) */
 } or_setup;
 
 /* ------------------------------------------------------------------------ */
@@ -146,8 +147,18 @@ static long neighbour(const or_setup *S, long K, int f) {
 /* written with its Jacobian (change of variables x = F_K(xi)).               */
 /* ------------------------------------------------------------------------ */
 
-/* x = F_K(xi) = sum over the corners v of X_v prod_e (xi_e if bit e of v else
- * 1 - xi_e), and J[r][c] = dx_r / dxi_c. */
+/* Quadratic Lagrange basis on the points 0, 1/2, 1 of [0, 1]: value and
+ * derivative of the one at point q. */
+static double lag2(int q, double t) {
+  return q == 0 ? 2.0 * (t - 0.5) * (t - 1.0) : (q == 1 ? -4.0 * t * (t - 1.0) : 2.0 * t * (t - 0.5));
+}
+static double lag2d(int q, double t) { return q == 0 ? 4.0 * t - 3.0 : (q == 1 ? 4.0 - 8.0 * t : 4.0 * t - 1.0); }
+
+/* x = F_K(xi) and J[r][c] = dx_r / dxi_c.  Degree 1: the multilinear map,
+ * sum over the corners v of X_v prod_e (xi_e if bit e of v else 1 - xi_e).
+ * Degree 2: the tensor-product quadratic map through the 3^d points of the
+ * cell on the point lattice of 2 n_e + 1 points per axis (corners, edge and
+ * face midpoints, centre), each weighted by prod_e lag2(q_e, xi_e). */
 static void cell_map(const or_setup *S, long K, const double *xi, double *x, double J[3][3]) {
   long ki[3];
   cell_multi(S, K, ki);
@@ -155,6 +166,31 @@ static void cell_map(const or_setup *S, long K, const double *xi, double *x, dou
   for (int r = 0; r < 3; ++r) {
     x[r] = 0.0;
     for (int c = 0; c < 3; ++c) J[r][c] = 0.0;
+  }
+  if (S->mapdeg == 2) {
+    int npt = 1;
+    for (int e = 0; e < dim; ++e) npt *= 3;
+    for (int v = 0; v < npt; ++v) {
+      int q[3] = {0, 0, 0}, r = v;
+      for (int e = 0; e < dim; ++e) { q[e] = r % 3; r /= 3; }
+      long vi = 0, stride = 1;
+      double w = 1.0, dw[3];
+      for (int e = 0; e < dim; ++e) {
+        vi += (2 * ki[e] + q[e]) * stride;
+        stride *= 2 * S->n[e] + 1;
+        w *= lag2(q[e], xi[e]);
+      }
+      for (int c = 0; c < dim; ++c) {
+        dw[c] = 1.0;
+        for (int e = 0; e < dim; ++e) dw[c] *= e == c ? lag2d(q[e], xi[e]) : lag2(q[e], xi[e]);
+      }
+      const double *X = S->vx + vi * dim;
+      for (int rr = 0; rr < dim; ++rr) {
+        x[rr] += w * X[rr];
+        for (int c = 0; c < dim; ++c) J[rr][c] += dw[c] * X[rr];
+      }
+    }
+    return;
   }
   for (int v = 0; v < (1 << dim); ++v) {
     long vi = 0, stride = 1;
@@ -475,15 +511,22 @@ or_setup *or_create(int dim, int deg, const long *cells, const double *lo, const
  * Gauss rule of k + 2 points (exact for the multilinear maps' polynomial
  * integrands); |Omega| is the sum of the cells' volumes.  NULL if a cell's
  * Jacobian determinant is not positive at a node or a Gauss point. */
-or_setup *or_create_mapped(int dim, int deg, const long *cells, const double *vx, const int *bc) {
+/* General cells with a cell map of degree mapdeg (1: the lattice of
+ * n_e + 1 points per axis, multilinear cells; 2: 2 n_e + 1 points per axis,
+ * quadratic (curved) cells). */
+or_setup *or_create_curved(int dim, int deg, const long *cells, const double *vx, const int *bc, int mapdeg) {
   double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+  if (mapdeg != 1 && mapdeg != 2) return NULL;
   or_setup *S = setup_init(dim, deg, cells, lo, hi, bc);
   if (!S) return NULL;
+  S->mapdeg = mapdeg;
   long nv = 1;
-  for (int e = 0; e < dim; ++e) nv *= S->n[e] + 1;
+  for (int e = 0; e < dim; ++e) nv *= mapdeg * S->n[e] + 1;
   S->vx = (double *)malloc(nv * dim * sizeof(double));
   memcpy(S->vx, vx, nv * dim * sizeof(double));
-  S->nq = deg + 2;
+  /* a rule exact for the integrands: products of the basis with det J or
+   * with the cofactors, of degree at most 2 deg + 3 mapdeg - 1 per direction */
+  S->nq = deg + 2 + (mapdeg == 2 ? 2 : 0);
   gauss_rule(S->nq, S->xq, S->wq);
   /* admissible cells, and the volume */
   double vol = 0.0;
@@ -513,6 +556,10 @@ or_setup *or_create_mapped(int dim, int deg, const long *cells, const double *vx
   S->vol = vol;
   setup_build(S);
   return S;
+}
+
+or_setup *or_create_mapped(int dim, int deg, const long *cells, const double *vx, const int *bc) {
+  return or_create_curved(dim, deg, cells, vx, bc, 1);
 }
 
 static or_setup *setup_init(int dim, int deg, const long *cells, const double *lo, const double *hi, const int *bc) {

@@ -112,6 +112,38 @@ def lattice(cells, lo, hi) -> np.ndarray:
     return np.stack([g.transpose(*reversed(range(len(cells)))).ravel() for g in grids], axis=1)
 
 
+def refine_points(V, cells) -> np.ndarray:
+    """The quadratic point lattice (2 n_e + 1 per axis, x fastest) of the
+    multilinear cells of the lattice V: each new point is the multilinear
+    interpolation of its cell's corners at the edge, face or cell midpoint, so
+    the quadratic cell maps through these points equal the multilinear ones."""
+    d = len(cells)
+    n1 = [c + 1 for c in cells]
+    n2 = [2 * c + 1 for c in cells]
+    P = np.asarray(V, dtype=np.float64).reshape(tuple(reversed(n1)) + (d,))
+    out = np.zeros(tuple(reversed(n2)) + (d,))
+    # axis order of P and out: (z, y, x) reversed; interpolate axis by axis
+    cur = P
+    for ax in range(d):
+        a = d - 1 - ax  # array axis of lattice axis ax
+        shape = list(cur.shape)
+        shape[a] = 2 * (shape[a] - 1) + 1
+        nxt = np.zeros(shape)
+        sl_even = [slice(None)] * len(shape)
+        sl_even[a] = slice(0, None, 2)
+        nxt[tuple(sl_even)] = cur
+        sl_odd = [slice(None)] * len(shape)
+        sl_odd[a] = slice(1, None, 2)
+        lo_ = [slice(None)] * len(shape)
+        hi_ = [slice(None)] * len(shape)
+        lo_[a] = slice(0, -1)
+        hi_[a] = slice(1, None)
+        nxt[tuple(sl_odd)] = 0.5 * (cur[tuple(lo_)] + cur[tuple(hi_)])
+        cur = nxt
+    out[...] = cur
+    return out.reshape(-1, d)
+
+
 def perturbed_lattice(cells, lo, hi, amp=0.25, seed=3, periodic=False) -> np.ndarray:
     """General cells: the lattice with its interior points moved by up to amp
     cell widths per axis (uniform random, seeded), or (periodic) by the smooth
@@ -347,6 +379,18 @@ def cylinder_ogrid(ntheta: int = 512, nr: int = 128, degree: int = 1, mach: floa
     bc_cells = np.concatenate([np.full(ntheta, BC_SLIP, dtype=np.int8), kinds])
     free = to_conserved(np.array([GAMMA]), np.array([[mach], [0.0]]), np.array([1.0]))[:, 0]
     return V, bc, bc_cells, free
+
+
+def annulus_ogrid(ntheta: int, nr: int, r0: float = 0.5, r1: float = 1.0, map_degree: int = 2) -> np.ndarray:
+    """Points of an O-grid of the annulus r0 < r < r1 (axis 0 around,
+    clockwise, periodic; axis 1 outwards): map_degree * n + 1 points per axis
+    on circles and rays, so that quadratic cells (map_degree 2) follow the
+    circles through their edge midpoints and bilinear ones (1) are polygons."""
+    m = map_degree
+    th = -2.0 * math.pi * np.arange(m * ntheta + 1) / (m * ntheta)
+    r = r0 + (r1 - r0) * np.arange(m * nr + 1) / (m * nr)
+    R, T = np.meshgrid(r, th, indexing="ij")  # (radial, angular): angular fastest
+    return np.stack([R * np.cos(T), R * np.sin(T)], axis=-1).reshape(-1, 2)
 
 
 def cylinder(ntheta: int = 512, nr: int = 128, degree: int = 1, mach: float = 3.0, stretch: float = 0.0,

@@ -20,9 +20,16 @@ VISC = T + "test_oracle_viscosity.py"
 INOUT = T + "test_oracle_inoutflow.py"
 MAPPED = T + "test_oracle_mapped.py"
 BCPARTS = T + "test_oracle_bcparts.py"
+CURVED = T + "test_oracle_curved.py"
 
 MUTANTS = {
     # name: (original text, planted text, pin files that must fail)
+    "curved_map_midpoint_weight": ("(q == 1 ? -4.0 * t * (t - 1.0) : 2.0 * t * (t - 0.5))",
+                                   "(q == 1 ? -2.0 * t * (t - 1.0) : 2.0 * t * (t - 0.5))",
+                                   [CURVED + "::test_quadratic_points_of_multilinear_cells_give_the_multilinear_mesh"]),
+    "curved_map_derivative_sign": ("(q == 1 ? 4.0 - 8.0 * t : 4.0 * t - 1.0)",
+                                   "(q == 1 ? 8.0 * t - 4.0 : 4.0 * t - 1.0)",
+                                   [CURVED + "::test_identities_on_curved_cells"]),
     "boundary_part_axes_reversed": ("      for (int g = 0; g < dim; ++g) {\n        if (g == e) continue;\n        idx += ki[g] * stride;",
                                     "      for (int g = dim - 1; g >= 0; --g) {\n        if (g == e) continue;\n        idx += ki[g] * stride;",
                                     [BCPARTS + "::test_split_face_is_local_3d"]),
