@@ -127,6 +127,14 @@ typedef enum { GDG_FP64 = 0, GDG_MIXED = 1 } gdg_precision;
  * The pointer is read during gdg_create() only (the context keeps a copy for
  * gdg_node_coords()).  Not combined with GDG_DATA_VORTEX.
  *
+ * Curved cells: with map_degree 2 each cell is the image of the reference
+ * cell under the tensor-product quadratic map through its 3^dim points
+ * (corners, edge and face midpoints, centre), and vertices holds the lattice
+ * of (2 cells[0]+1) x .. points, same order; cell (k0, k1, k2) takes the
+ * points (2 k0 + q0, 2 k1 + q1, 2 k2 + q2), q in {0, 1, 2}^dim.  The integrals
+ * stay exact (Gauss rules of degree + 2 points per direction, degree + 3 for
+ * the 3D masses).
+ *
  * Boundary parts (Sec. 4.1 applies its conditions part by part): with
  * bc_cells non-NULL each cell face on the boundary has its own kind.  For each
  * box face f = 0 .. 2 dim - 1 whose bc[f] is not PERIODIC, in order of f, one
@@ -145,7 +153,7 @@ typedef struct {
   int32_t bc[6];
   double bc_state[6][5];
   int32_t data_kind;  /* gdg_data_kind */
-  int32_t reserved;
+  int32_t map_degree; /* general cells: 0 or 1 multilinear, 2 quadratic (curved); see above */
   double vortex[6];
   const double *vertices; /* NULL: the uniform box [lo, hi]; else host memory, see above */
   const int8_t *bc_cells; /* NULL: kind bc[f] on all of box face f; else host memory, see above */

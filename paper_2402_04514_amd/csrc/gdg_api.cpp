@@ -144,6 +144,10 @@ bool validate(const gdg_mesh_desc *m, const gdg_params *p, std::string *err) {
     *err = "unknown boundary data kind";
     return false;
   }
+  if (m->map_degree < 0 || m->map_degree > 2 || (m->map_degree == 2 && !m->vertices)) {
+    *err = "map_degree must be 0 or 1 (multilinear), or 2 (quadratic, with vertices)";
+    return false;
+  }
   if (m->vertices && m->data_kind == GDG_DATA_VORTEX) {
     *err = "vortex boundary data are built for the uniform box (vertices must be NULL)";
     return false;
@@ -416,7 +420,7 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   ctx->mesh = *mesh;
   if (mesh->vertices) {
     size_t npts = 1;
-    for (int e = 0; e < mesh->dim; ++e) npts *= (size_t)(mesh->cells[e] + 1);
+    for (int e = 0; e < mesh->dim; ++e) npts *= (size_t)(map_degree(mesh) * mesh->cells[e] + 1);
     ctx->vx.assign(mesh->vertices, mesh->vertices + npts * mesh->dim);
     ctx->mesh.vertices = ctx->vx.data();
   }
@@ -649,12 +653,12 @@ gdg_status gdg_node_coords(const gdg_ctx *ctx, double *xyz) {
   if (m.vertices) {
     // x_i = F_K(xi_a): the cell's map at the node's reference point
     for (int64_t K = 0; K < ctx->A.ncells; ++K) {
-      double X[8][3];
-      mapped_cell_corners(&m, m.vertices, K, X);
+      double X[27][3];
+      mapped_cell_points(&m, m.vertices, K, X);
       for (int a = 0; a < nloc; ++a) {
         double xi[3] = {0, 0, 0};
         for (int e = 0, r = a; e < d; ++e, r /= nb) xi[e] = xg[r % nb];
-        mapped_point(d, X, xi, &xyz[(K * nloc + a) * d]);
+        mapped_point(d, map_degree(&m), X, xi, &xyz[(K * nloc + a) * d]);
       }
     }
     return GDG_OK;

@@ -240,10 +240,13 @@ struct MappedSetup {
 };
 bool build_mapped(const gdg_mesh_desc *m, const gdg_params *p, const double *vx, const RefTables &T, int R, int W,
                   int64_t nslots, MappedSetup *out, std::string *err);
-// The 2^dim corners of cell K (corner v: bit e of v is the side in direction e).
-void mapped_cell_corners(const gdg_mesh_desc *m, const double *vx, int64_t K, double (*X)[3]);
-// x = F_K(xi) for the corners X of a cell.
-void mapped_point(int d, const double (*X)[3], const double *xi, double *x);
+// Degree of the cell maps (1 multilinear, 2 quadratic) of a mesh of general cells.
+int map_degree(const gdg_mesh_desc *m);
+// The (g+1)^dim points of cell K's map of degree g (point v: digits q_e of v
+// in base g + 1, first axis lowest).
+void mapped_cell_points(const gdg_mesh_desc *m, const double *vx, int64_t K, double (*X)[3]);
+// x = F_K(xi) for the points X of a cell's map of degree g.
+void mapped_point(int d, int g, const double (*X)[3], const double *xi, double *x);
 int launch_fill(const KArgs &A, void *stream);
 int launch_begin(const KArgs &A, double dt_cap, double tau_fixed, int device_driven, void *stream);
 int launch_end(const KArgs &A, void *stream);

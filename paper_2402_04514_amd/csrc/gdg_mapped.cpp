@@ -94,19 +94,30 @@ void split(int a, int nb, int *ai) {
   }
 }
 
-// Jacobian J[r][c] = dx_r/dxi_c of the multilinear map through the corners X
-// (corner v at bit e of v = side in direction e), at xi; and its cofactor
-// matrix cof = det(J) J^{-T}; returns det J.
-double jacobian(int d, const double (*X)[3], const double *xi, double cof[3][3]) {
+// 1D shape functions of a cell map of degree g (1: the end points; 2: the
+// points 0, 1/2, 1 of [0, 1]) and their derivatives.
+double shape(int g, int q, double t) {
+  if (g == 1) return q ? t : 1.0 - t;
+  return q == 0 ? (1.0 - t) * (1.0 - 2.0 * t) : (q == 1 ? 4.0 * t * (1.0 - t) : t * (2.0 * t - 1.0));
+}
+double dshape(int g, int q, double t) {
+  if (g == 1) return q ? 1.0 : -1.0;
+  return q == 0 ? 4.0 * t - 3.0 : (q == 1 ? 4.0 - 8.0 * t : 4.0 * t - 1.0);
+}
+
+// Jacobian J[r][c] = dx_r/dxi_c at xi of the degree-g map through the cell's
+// (g+1)^d points X (point v: digits q_e of v in base g + 1, the first axis
+// lowest); its cofactor matrix cof = det(J) J^{-T}; returns det J.
+double jacobian(int d, int g, const double (*X)[3], const double *xi, double cof[3][3]) {
   double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  for (int v = 0; v < (1 << d); ++v)
+  int np = 1;
+  for (int e = 0; e < d; ++e) np *= g + 1;
+  for (int v = 0; v < np; ++v)
     for (int c = 0; c < d; ++c) {
-      double g = 1.0;
-      for (int e = 0; e < d; ++e) {
-        const int bit = (v >> e) & 1;
-        g *= e == c ? (bit ? 1.0 : -1.0) : (bit ? xi[e] : 1.0 - xi[e]);
-      }
-      for (int r = 0; r < d; ++r) J[r][c] += g * X[v][r];
+      double w = 1.0;
+      for (int e = 0, r = v; e < d; ++e, r /= g + 1)
+        w *= e == c ? dshape(g, r % (g + 1), xi[e]) : shape(g, r % (g + 1), xi[e]);
+      for (int r = 0; r < d; ++r) J[r][c] += w * X[v][r];
     }
   if (d == 1) {
     cof[0][0] = 1.0;
@@ -166,29 +177,35 @@ void parallel_ranges(int64_t n, F body) {
 
 }  // namespace
 
-void mapped_cell_corners(const gdg_mesh_desc *m, const double *vx, int64_t K, double (*X)[3]) {
-  const int d = m->dim;
+int map_degree(const gdg_mesh_desc *m) { return m->map_degree == 2 ? 2 : 1; }
+
+void mapped_cell_points(const gdg_mesh_desc *m, const double *vx, int64_t K, double (*X)[3]) {
+  const int d = m->dim, g = map_degree(m);
   int64_t ki[3] = {0, 0, 0}, r = K;
   for (int e = 0; e < d; ++e) {
     ki[e] = r % m->cells[e];
     r /= m->cells[e];
   }
-  for (int v = 0; v < (1 << d); ++v) {
+  int np = 1;
+  for (int e = 0; e < d; ++e) np *= g + 1;
+  for (int v = 0; v < np; ++v) {
     int64_t idx = 0, stride = 1;
-    for (int e = 0; e < d; ++e) {
-      idx += (ki[e] + ((v >> e) & 1)) * stride;
-      stride *= m->cells[e] + 1;
+    for (int e = 0, q = v; e < d; ++e, q /= g + 1) {
+      idx += (g * ki[e] + q % (g + 1)) * stride;
+      stride *= g * m->cells[e] + 1;
     }
     for (int c = 0; c < 3; ++c) X[v][c] = c < d ? vx[idx * d + c] : 0.0;
   }
 }
 
-void mapped_point(int d, const double (*X)[3], const double *xi, double *x) {
+void mapped_point(int d, int g, const double (*X)[3], const double *xi, double *x) {
   for (int c = 0; c < d; ++c) x[c] = 0.0;
-  for (int v = 0; v < (1 << d); ++v) {
-    double g = 1.0;
-    for (int e = 0; e < d; ++e) g *= ((v >> e) & 1) ? xi[e] : 1.0 - xi[e];
-    for (int c = 0; c < d; ++c) x[c] += g * X[v][c];
+  int np = 1;
+  for (int e = 0; e < d; ++e) np *= g + 1;
+  for (int v = 0; v < np; ++v) {
+    double w = 1.0;
+    for (int e = 0, q = v; e < d; ++e, q /= g + 1) w *= shape(g, q % (g + 1), xi[e]);
+    for (int c = 0; c < d; ++c) x[c] += w * X[v][c];
   }
 }
 
@@ -202,7 +219,12 @@ bool build_mapped(const gdg_mesh_desc *m, const gdg_params *p, const double *vx,
   for (int e = 0; e < d; ++e) ncells *= m->cells[e];
   const int64_t N = ncells * nloc;
   const Lag1D L = lag1d(deg);
-  const int nq = deg + 2;
+  // Gauss points per direction, exact for every integrand: with a map of
+  // degree gm, det J has degree d gm - 1 per direction and the cofactors
+  // (d - 1) gm, so the masses need deg + 2 points in 2D and deg + 3 in 3D
+  // with quadratic maps, the stencil coefficients deg + 2
+  const int gm = map_degree(m);
+  const int nq = deg + 2 + (d == 3 && gm == 2 ? 1 : 0);
   double xq[5], wq[5];
   gauss01(nq, xq, wq);
   int nvol = 1, nsurf = 1;
@@ -232,8 +254,8 @@ bool build_mapped(const gdg_mesh_desc *m, const gdg_params *p, const double *vx,
   std::atomic<bool> ok{true};
   parallel_ranges(ncells, [&](int64_t K0, int64_t K1) {
   for (int64_t K = K0; K < K1; ++K) {
-    double X[8][3];
-    mapped_cell_corners(m, vx, K, X);
+    double X[27][3];
+    mapped_cell_points(m, vx, K, X);
     double *Mk = &out->cmblk[(size_t)K * nloc * nloc];
     double *Ck = &cin[(size_t)K * nloc * nloc * d];
     std::vector<double> Craw((size_t)nloc * nloc * d, 0.0);
@@ -246,7 +268,7 @@ bool build_mapped(const gdg_mesh_desc *m, const gdg_params *p, const double *vx,
         r /= nq;
       }
       double cof[3][3];
-      const double det = jacobian(d, X, xi, cof);
+      const double det = jacobian(d, gm, X, xi, cof);
       if (!(det > 0.0)) ok = false;
       cvol[K] += w * det;
       double phv[64], gr[64][3];
@@ -291,7 +313,7 @@ bool build_mapped(const gdg_mesh_desc *m, const gdg_params *p, const double *vx,
           r /= nq;
         }
         double cof[3][3];
-        jacobian(d, X, xi, cof);
+        jacobian(d, gm, X, xi, cof);
         double ns[3];
         for (int c = 0; c < d; ++c) ns[c] = sgn * cof[c][e];
         for (int ta = 0; ta < nface; ++ta) {

@@ -444,7 +444,8 @@ gdg_status gdg_server_submit(gdg_server *s, const gdg_mesh_desc *mesh, const gdg
   q->mesh = *mesh;
   if (mesh->vertices) {
     size_t npts = 1;
-    for (int e = 0; e < mesh->dim; ++e) npts *= (size_t)(mesh->cells[e] + 1);
+    const int g = mesh->map_degree == 2 ? 2 : 1;
+    for (int e = 0; e < mesh->dim; ++e) npts *= (size_t)(g * mesh->cells[e] + 1);
     q->vx.assign(mesh->vertices, mesh->vertices + npts * mesh->dim);
     q->mesh.vertices = q->vx.data();
   }

@@ -40,7 +40,7 @@ class GdgError(RuntimeError):
 class gdg_mesh_desc(C.Structure):
     _fields_ = [("dim", C.c_int32), ("degree", C.c_int32), ("cells", C.c_int64 * 3),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("bc", C.c_int32 * 6),
-                ("bc_state", (C.c_double * 5) * 6), ("data_kind", C.c_int32), ("reserved", C.c_int32),
+                ("bc_state", (C.c_double * 5) * 6), ("data_kind", C.c_int32), ("map_degree", C.c_int32),
                 ("vortex", C.c_double * 6), ("vertices", C.POINTER(C.c_double)),
                 ("bc_cells", C.POINTER(C.c_int8))]
 
@@ -138,13 +138,15 @@ def _check(st, ctx=None):
 
 
 def mesh_desc(dim, degree, cells, lo, hi, bc, bstate=None, vortex=None, vertices=None,
-              bc_cells=None) -> gdg_mesh_desc:
+              bc_cells=None, map_degree=1) -> gdg_mesh_desc:
     """bstate: per face the conserved Dirichlet data of the DIRICHLET,
     SUPERSONIC and INOUTFLOW kinds (None, or None entries, elsewhere); vortex:
     (beta, x0_1, x0_2, u_1, u_2, gamma) to take that data from the isentropic
     vortex instead.  vertices: general cells, the lattice's points as an array
     of shape (prod(cells + 1), dim), the first axis fastest; the descriptor
-    keeps a reference to its float64 copy (``m._vx``).  bc_cells: a kind per
+    keeps a reference to its float64 copy (``m._vx``); map_degree 2: curved
+    cells, vertices the lattice of 2 cells + 1 points per axis of their
+    quadratic maps.  bc_cells: a kind per
     boundary cell face (for each non-periodic box face in order, its cells
     lexicographically over the other axes, the lowest axis fastest)."""
     m = gdg_mesh_desc()
@@ -164,7 +166,8 @@ def mesh_desc(dim, degree, cells, lo, hi, bc, bstate=None, vortex=None, vertices
             m.vortex[k] = float(v)
     if vertices is not None:
         vx = np.ascontiguousarray(vertices, dtype=np.float64)
-        npts = int(np.prod([int(c) + 1 for c in cells[:dim]]))
+        m.map_degree = int(map_degree)
+        npts = int(np.prod([int(map_degree) * int(c) + 1 for c in cells[:dim]]))
         if vx.shape != (npts, dim):
             raise ValueError(f"vertices must have shape ({npts}, {dim})")
         m._vx = vx
@@ -302,11 +305,12 @@ class Solver:
     and whose stream is torch's current stream there (or ``stream``)."""
 
     def __init__(self, dim, degree, cells, lo, hi, bc, params: gdg_params | None = None,
-                 device="cuda:0", stream=None, bstate=None, vortex=None, vertices=None, bc_cells=None):
+                 device="cuda:0", stream=None, bstate=None, vortex=None, vertices=None, bc_cells=None,
+                 map_degree=1):
         import torch
         self.torch = torch
         self.dim, self.m = dim, dim + 2
-        self.mesh = mesh_desc(dim, degree, cells, lo, hi, bc, bstate, vortex, vertices, bc_cells)
+        self.mesh = mesh_desc(dim, degree, cells, lo, hi, bc, bstate, vortex, vertices, bc_cells, map_degree)
         self.params = params if params is not None else gdg_default_params(degree)
         self.device = torch.device(device)
         nbytes = gdg_workspace_bytes(self.mesh, self.params)
@@ -321,7 +325,8 @@ class Solver:
     def from_spec(cls, ms, params=None, **kw):
         return cls(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc, params,
                    bstate=getattr(ms, "bstate", None), vortex=getattr(ms, "vortex", None),
-                   vertices=getattr(ms, "vertices", None), bc_cells=getattr(ms, "bc_cells", None), **kw)
+                   vertices=getattr(ms, "vertices", None), bc_cells=getattr(ms, "bc_cells", None),
+                   map_degree=getattr(ms, "map_degree", 1), **kw)
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -447,7 +452,7 @@ class Server:
             prm.precision = self.desc.precision
         mesh = mesh_desc(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc, getattr(ms, "bstate", None),
                          getattr(ms, "vortex", None), getattr(ms, "vertices", None),
-                         getattr(ms, "bc_cells", None))
+                         getattr(ms, "bc_cells", None), getattr(ms, "map_degree", 1))
         return gdg_server_submit(self.srv, mesh, prm, U0, t_final)
 
     def pump(self):

@@ -50,6 +50,9 @@ class MeshSpec:
     # boundary parts: a kind per boundary cell face (each non-periodic box face
     # in order, its cells over the other axes, the lowest axis fastest)
     bc_cells: np.ndarray | None = field(default=None, repr=False, compare=False)
+    # degree of the cell maps of general cells: 1 multilinear, 2 quadratic
+    # (vertices then holds 2 cells + 1 points per axis)
+    map_degree: int = 1
 
     @property
     def nloc(self) -> int:
@@ -327,7 +330,7 @@ def serving_trace(count: int = 256, n_min: int = 32, n_max: int = 512, seed0: in
 
 def cylinder_ogrid(ntheta: int = 512, nr: int = 128, degree: int = 1, mach: float = 3.0,
                    center=(0.6, 0.0), radius: float = 0.25, box=((0.0, 4.0), (-1.0, 1.0)),
-                   stretch: float = 0.0):
+                   stretch: float = 0.0, map_degree: int = 1):
     """The geometry of the Mach 3 flow past a cylinder (Sec. 6.4): the channel
     box[0] x box[1] minus the disk of the given centre and radius, meshed by
     an O-grid of general cells.  Axis 0 runs around the cylinder (periodic,
@@ -343,8 +346,14 @@ def cylinder_ogrid(ntheta: int = 512, nr: int = 128, degree: int = 1, mach: floa
     (the inflow, data: the free stream), outflow on x = box[0][1], slip on the
     top and bottom walls; the cylinder (face 2) is a slip wall.
 
-    Returns (vertices of shape ((ntheta+1)(nr+1), 2), bc, bc_cells, the free
-    stream as conserved data): rho = gamma, p = 1 (sound speed 1), u = mach."""
+    map_degree 2 gives curved cells: the lattice of 2 n + 1 points per axis,
+    with the cylinder's edge midpoints on the circle, the outer edge
+    midpoints halfway along the straight channel walls, and the points
+    between on the rays of the half angles at the half radial steps.
+
+    Returns (vertices of shape ((m ntheta+1)(m nr+1), 2) for map degree m, bc,
+    bc_cells, the free stream as conserved data): rho = gamma, p = 1 (sound
+    speed 1), u = mach."""
     (x0, x1), (y0, y1) = box
     cx, cy = center
     # clockwise, so that (around, outwards) is a positively oriented frame
@@ -363,14 +372,22 @@ def cylinder_ogrid(ntheta: int = 512, nr: int = 128, degree: int = 1, mach: floa
         outer[i] = corner
         if i == 0:
             outer[ntheta] = corner
+    m = int(map_degree)
+    # kinds of the outer face's cell faces, by the midpoint of each edge
+    mid = 0.5 * (outer[:-1] + outer[1:])
+    if m == 2:
+        thh = math.pi - 2.0 * math.pi * np.arange(2 * ntheta + 1) / (2 * ntheta)
+        dx, dy = np.cos(thh), np.sin(thh)
+        o2 = np.zeros((2 * ntheta + 1, 2))
+        o2[0::2] = outer
+        o2[1::2] = mid
+        outer = o2
     inner = np.stack([cx + radius * dx, cy + radius * dy], axis=1)
-    s = np.arange(nr + 1) / nr
+    s = np.arange(m * nr + 1) / (m * nr)
     g = s if stretch == 0.0 else np.expm1(stretch * s) / math.expm1(stretch)
     # point (i, j): i around (fastest), j outwards
     V = inner[None, :, :] + g[:, None, None] * (outer - inner)[None, :, :]
     V = V.reshape(-1, 2)
-    # kinds of the outer face's cell faces, by the midpoint of each edge
-    mid = 0.5 * (outer[:-1] + outer[1:])
     eps = 1e-9 * max(x1 - x0, y1 - y0)
     kinds = np.full(ntheta, BC_SLIP, dtype=np.int8)
     kinds[np.abs(mid[:, 0] - x0) < eps] = BC_DIRICHLET
@@ -394,16 +411,17 @@ def annulus_ogrid(ntheta: int, nr: int, r0: float = 0.5, r1: float = 1.0, map_de
 
 
 def cylinder(ntheta: int = 512, nr: int = 128, degree: int = 1, mach: float = 3.0, stretch: float = 0.0,
-             t_final: float = 4.0) -> Workload:
+             t_final: float = 4.0, map_degree: int = 1) -> Workload:
     """Mach 3 flow past a cylinder on the O-grid of cylinder_ogrid(): uniform
     free stream everywhere at t = 0 (the wall of the cylinder starts the bow
     shock)."""
-    V, bc, bc_cells, free = cylinder_ogrid(ntheta, nr, degree, mach, stretch=stretch)
+    V, bc, bc_cells, free = cylinder_ogrid(ntheta, nr, degree, mach, stretch=stretch, map_degree=map_degree)
     bstate = (None, None, None, tuple(free))
     ms = MeshSpec(2, degree, (ntheta, nr), (0.0, -1.0), (4.0, 1.0), bc, bstate=bstate, vertices=V,
-                  bc_cells=bc_cells)
+                  bc_cells=bc_cells, map_degree=map_degree)
     U = np.repeat(free[:, None], ms.ndofs, axis=1)
-    return Workload("cylinder_q%d_%dx%d" % (degree, ntheta, nr), ms, U, t_final=t_final)
+    name = "cylinder_q%d_%dx%d" % (degree, ntheta, nr) + ("_curved" if map_degree == 2 else "")
+    return Workload(name, ms, U, t_final=t_final)
 
 
 CONFIGS = {

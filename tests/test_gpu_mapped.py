@@ -31,7 +31,23 @@ def _mesh(dim, k, cells, bc, amp=0.25, seed=3, periodic=False, bstate=None):
 
 
 def _oracle_mesh(oracle, ms):
-    return oracle.Mesh(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc, bstate=ms.bstate, vertices=ms.vertices)
+    return oracle.Mesh(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc, bstate=ms.bstate, vertices=ms.vertices,
+                       bc_cells=ms.bc_cells, map_degree=ms.map_degree)
+
+
+def _annulus(k, cells, bc):
+    """Curved cells: the O-grid of the annulus 0.5 < r < 1 with quadratic maps
+    through points on circles."""
+    return W.MeshSpec(2, k, tuple(cells), (0.0, 0.0), (1.0, 1.0), tuple(bc),
+                      vertices=W.annulus_ogrid(*cells, map_degree=2), map_degree=2)
+
+
+def _shell(k, cells, bc):
+    """Curved 3D cells: the annulus O-grid extruded over z in [0, 0.5]."""
+    P = W.annulus_ogrid(cells[0], cells[1], map_degree=2)
+    z = 0.5 * np.arange(2 * cells[2] + 1) / (2 * cells[2])
+    V = np.concatenate([np.column_stack([P, np.full(len(P), zz)]) for zz in z])
+    return W.MeshSpec(3, k, tuple(cells), (0.0,) * 3, (1.0,) * 3, tuple(bc), vertices=V, map_degree=2)
 
 
 def _quadrant(oracle, ms, seed=240204514, wz=True):
@@ -87,6 +103,13 @@ CASES = {
     "q1_3d_slip": (lambda: _mesh(3, 1, (5, 4, 3), (2,) * 6, seed=13), _quadrant),
     "q1_3d_tiled_mixed_bc": (lambda: _mesh(3, 1, (16, 3, 2), (2, 2, 1, 1, 2, 2), seed=17), _smooth),
     "q2_3d_outflow": (lambda: _mesh(3, 2, (3, 3, 2), (1,) * 6, amp=0.2, seed=19), _quadrant),
+    # curved cells (quadratic maps)
+    "curved_annulus_q1": (lambda: _annulus(1, (24, 6), (0, 0, 2, 1)), _quadrant),
+    "curved_annulus_q2": (lambda: _annulus(2, (16, 5), (0, 0, 2, 1)), _smooth),
+    "curved_annulus_q3": (lambda: _annulus(3, (10, 3), (0, 0, 1, 2)), _quadrant),
+    "curved_shell_q1": (lambda: _shell(1, (12, 3, 2), (0, 0, 2, 1, 2, 2)), _quadrant),
+    "curved_shell_q2": (lambda: _shell(2, (8, 2, 2), (0, 0, 2, 1, 1, 2)), _smooth),
+    "curved_cylinder_q2": (lambda: W.cylinder(32, 10, degree=2, map_degree=2).mesh, _quadrant),
 }
 
 

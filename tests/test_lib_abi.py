@@ -239,3 +239,20 @@ def test_general_cells_and_boundary_parts_validated():
     with pytest.raises(gdg.GdgError):
         gdg.gdg_workspace_bytes(gdg.mesh_desc(2, 1, cells, (0, 0), (1, 1), (1,) * 4, vertices=V,
                                               vortex=(5.0, -1.0, -1.0, 1.0, 1.0, 1.4)), p)
+
+
+def test_curved_cells_validated():
+    """map_degree 2 needs vertices (the lattice of 2 cells + 1 points per
+    axis); other degrees are refused; the binding checks the point count."""
+    p = gdg.gdg_default_params(2)
+    cells = (6, 4)
+    V2 = W.refine_points(W.lattice(cells, (0, 0), (1, 1)), cells)
+    m = gdg.mesh_desc(2, 2, cells, (0, 0), (1, 1), (1,) * 4, vertices=V2, map_degree=2)
+    assert gdg.gdg_workspace_bytes(m, p) > 0
+    with pytest.raises(ValueError):
+        gdg.mesh_desc(2, 2, cells, (0, 0), (1, 1), (1,) * 4, vertices=V2, map_degree=1)
+    bad = gdg.mesh_desc(2, 2, cells, (0, 0), (1, 1), (1,) * 4)
+    for g in (2, 3, -1):
+        bad.map_degree = g
+        with pytest.raises(gdg.GdgError):
+            gdg.gdg_workspace_bytes(bad, p)
