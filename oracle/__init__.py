@@ -71,6 +71,9 @@ def lib():
         L.or_create_mapped.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_long), _DP, C.POINTER(C.c_int)]
         L.or_create_curved.restype = C.c_void_p
         L.or_create_curved.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_long), _DP, C.POINTER(C.c_int), C.c_int]
+        L.or_create_unstructured.restype = C.c_void_p
+        L.or_create_unstructured.argtypes = [C.c_int, C.c_int, C.c_long, C.POINTER(C.c_long), C.c_long, _DP, C.c_int,
+                                             C.POINTER(C.c_byte)]
         L.or_destroy.argtypes = [C.c_void_p]
         L.or_num_threads.restype = C.c_int
         L.or_num_threads.argtypes = []
@@ -199,6 +202,39 @@ class Mesh:
                 v = np.ascontiguousarray(bstate[f], dtype=np.float64)
                 assert v.shape == (self.m,)
                 L.or_set_boundary_state(self._h, f, _dp(v))
+
+    @classmethod
+    def unstructured(cls, dim, degree, cell_points, points, face_bc, bstate=None, map_degree=1):
+        """Unstructured mesh: cell K is the image of the reference cell under
+        the map of degree map_degree through points[cell_points[K, v]] (v the
+        digits q_e in base map_degree + 1, first axis lowest); cells sharing a
+        face's corner points are neighbours.  face_bc[K, f]: for a face on no
+        other cell, its kind (1-5) + 8 * the box-face slot of its data in
+        bstate."""
+        self = cls.__new__(cls)
+        L = lib()
+        cp = np.ascontiguousarray(cell_points, dtype=np.int64)
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        fb = np.ascontiguousarray(face_bc, dtype=np.int8)
+        ncells = cp.shape[0]
+        assert cp.shape == (ncells, (map_degree + 1) ** dim) and pts.shape[1] == dim
+        assert fb.shape == (ncells, 2 * dim)
+        self._keep = (cp, pts, fb)
+        self._h = L.or_create_unstructured(dim, degree, ncells, cp.ctypes.data_as(C.POINTER(C.c_long)),
+                                           pts.shape[0], _dp(pts), int(map_degree),
+                                           fb.ctypes.data_as(C.POINTER(C.c_byte)))
+        if not self._h:
+            raise ValueError("invalid unstructured mesh")
+        self.dim, self.degree = dim, degree
+        self.cells = (ncells,)
+        self.bc = (1,) * (2 * dim)
+        self.ndofs = L.or_num_dofs(self._h)
+        self.m = dim + 2
+        for f in range(6):
+            if bstate is not None and f < len(bstate) and bstate[f] is not None:
+                v = np.ascontiguousarray(bstate[f], dtype=np.float64)
+                L.or_set_boundary_state(self._h, f, _dp(v))
+        return self
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -86,6 +86,12 @@ typedef struct {
    * NULL: the uniform box lo .. hi. */
   double *vx;
   int mapdeg;    /* general cells: degree g of the cell map (1 multilinear, 2 quadratic) */
+  /* unstructured meshes: the (mapdeg+1)^dim point ids of each cell, the
+   * neighbour across each local face (-1: boundary) and its local face, and
+   * per boundary face its kind | data face << 3 */
+  long *ucp, *unb;
+  int *unf;
+  signed char *ubc;
 } or_setup;
 
 /* ------------------------------------------------------------------------ */
@@ -131,6 +137,7 @@ static long cell_index(const or_setup *S, const long *ki) {
 
 /* Neighbour of cell K across face f = 2e+side; -1 on a non-periodic boundary. */
 static long neighbour(const or_setup *S, long K, int f) {
+  if (S->ucp) return S->unb[K * 2 * S->dim + f];
   int e = f / 2, side = f % 2;
   long ki[3];
   cell_multi(S, K, ki);
@@ -154,14 +161,29 @@ static double lag2(int q, double t) {
 }
 static double lag2d(int q, double t) { return q == 0 ? 4.0 * t - 3.0 : (q == 1 ? 4.0 - 8.0 * t : 4.0 * t - 1.0); }
 
+/* Point q (q_e in 0 .. mapdeg per axis) of cell K's map: from the cell's own
+ * list on unstructured meshes, else from the point lattice of mapdeg n_e + 1
+ * points per axis. */
+static const double *map_point(const or_setup *S, long K, const int *q) {
+  const int g = S->mapdeg, dim = S->dim;
+  if (S->ucp) {
+    long v = 0, st = 1;
+    for (int e = 0; e < dim; ++e) { v += q[e] * st; st *= g + 1; }
+    return S->vx + S->ucp[K * st + v] * dim;
+  }
+  long ki[3];
+  cell_multi(S, K, ki);
+  long vi = 0, stride = 1;
+  for (int e = 0; e < dim; ++e) { vi += (g * ki[e] + q[e]) * stride; stride *= g * S->n[e] + 1; }
+  return S->vx + vi * dim;
+}
+
 /* x = F_K(xi) and J[r][c] = dx_r / dxi_c.  Degree 1: the multilinear map,
  * sum over the corners v of X_v prod_e (xi_e if bit e of v else 1 - xi_e).
  * Degree 2: the tensor-product quadratic map through the 3^d points of the
  * cell on the point lattice of 2 n_e + 1 points per axis (corners, edge and
  * face midpoints, centre), each weighted by prod_e lag2(q_e, xi_e). */
 static void cell_map(const or_setup *S, long K, const double *xi, double *x, double J[3][3]) {
-  long ki[3];
-  cell_multi(S, K, ki);
   const int dim = S->dim;
   for (int r = 0; r < 3; ++r) {
     x[r] = 0.0;
@@ -173,18 +195,13 @@ static void cell_map(const or_setup *S, long K, const double *xi, double *x, dou
     for (int v = 0; v < npt; ++v) {
       int q[3] = {0, 0, 0}, r = v;
       for (int e = 0; e < dim; ++e) { q[e] = r % 3; r /= 3; }
-      long vi = 0, stride = 1;
       double w = 1.0, dw[3];
-      for (int e = 0; e < dim; ++e) {
-        vi += (2 * ki[e] + q[e]) * stride;
-        stride *= 2 * S->n[e] + 1;
-        w *= lag2(q[e], xi[e]);
-      }
+      for (int e = 0; e < dim; ++e) w *= lag2(q[e], xi[e]);
       for (int c = 0; c < dim; ++c) {
         dw[c] = 1.0;
         for (int e = 0; e < dim; ++e) dw[c] *= e == c ? lag2d(q[e], xi[e]) : lag2(q[e], xi[e]);
       }
-      const double *X = S->vx + vi * dim;
+      const double *X = map_point(S, K, q);
       for (int rr = 0; rr < dim; ++rr) {
         x[rr] += w * X[rr];
         for (int c = 0; c < dim; ++c) J[rr][c] += dw[c] * X[rr];
@@ -193,12 +210,11 @@ static void cell_map(const or_setup *S, long K, const double *xi, double *x, dou
     return;
   }
   for (int v = 0; v < (1 << dim); ++v) {
-    long vi = 0, stride = 1;
+    int q[3] = {0, 0, 0};
     double w = 1.0, dw[3];
     for (int e = 0; e < dim; ++e) {
       int bit = (v >> e) & 1;
-      vi += (ki[e] + bit) * stride;
-      stride *= S->n[e] + 1;
+      q[e] = bit;
       w *= bit ? xi[e] : 1.0 - xi[e];
     }
     for (int c = 0; c < dim; ++c) {
@@ -209,7 +225,7 @@ static void cell_map(const or_setup *S, long K, const double *xi, double *x, dou
         else dw[c] *= bit ? xi[e] : 1.0 - xi[e];
       }
     }
-    const double *X = S->vx + vi * dim;
+    const double *X = map_point(S, K, q);
     for (int r = 0; r < dim; ++r) {
       x[r] += w * X[r];
       for (int c = 0; c < dim; ++c) J[r][c] += dw[c] * X[r];
@@ -291,6 +307,36 @@ static void cell_integral_mapped(const or_setup *S, long K, int kind, int a, int
  * dim)), n the outward unit normal of K; phi_b of the same cell or of the
  * neighbour across f (its reference coordinate e is 1 - side), b < 0 meaning 1.
  * n ds = (outward sign) det J J^{-T} e_e dxi over the face (Nanson's formula). */
+/* The reference point eta of cell K with F_K(eta) = x, by Newton's method
+ * from the cell's centre (used for points on the cell's boundary). */
+static void map_inverse(const or_setup *S, long K, const double *x, double *eta) {
+  const int dim = S->dim;
+  for (int e = 0; e < 3; ++e) eta[e] = e < dim ? 0.5 : 0.0;
+  for (int it = 0; it < 60; ++it) {
+    double y[3], J[3][3], Ji[3][3], dmax = 0.0;
+    cell_map(S, K, eta, y, J);
+    inverse(dim, J, Ji);
+    double d[3] = {0, 0, 0};
+    for (int r = 0; r < dim; ++r)
+      for (int c = 0; c < dim; ++c) d[r] += Ji[r][c] * (x[c] - y[c]);
+    for (int r = 0; r < dim; ++r) { eta[r] += d[r]; dmax = fmax(dmax, fabs(d[r])); }
+    if (dmax < 1e-15) break;
+  }
+}
+
+/* Whether local node b of cell Kn lies on the face that Kn shares with cell
+ * K across K's face f (lattice: the opposite face; unstructured: the
+ * neighbour's own local face). */
+static int on_shared_face(const or_setup *S, long K, int f, int b) {
+  int bi[3];
+  local_multi(S, b, bi);
+  if (S->ucp) {
+    int fn = S->unf[K * 2 * S->dim + f];
+    return bi[fn / 2] == (fn % 2) * S->deg;
+  }
+  return bi[f / 2] == (1 - f % 2) * S->deg;
+}
+
 static void face_integral_mapped(const or_setup *S, long K, int f, int a, int b, int same_cell, double *out) {
   const int dim = S->dim, nq = S->nq, e = f / 2, side = f % 2;
   int tot = 1;
@@ -309,7 +355,15 @@ static void face_integral_mapped(const or_setup *S, long K, int f, int a, int b,
     double va = phi(S, a, xi), vb = 1.0;
     if (b >= 0) {
       double xb[3] = {xi[0], xi[1], xi[2]};
-      if (!same_cell) xb[e] = 1.0 - xi[e];
+      if (!same_cell && S->ucp) {
+        /* b belongs to the neighbour: its reference point of x, on its face */
+        const long Kn = S->unb[K * 2 * dim + f];
+        const int fn = S->unf[K * 2 * dim + f];
+        map_inverse(S, Kn, x, xb);
+        xb[fn / 2] = (fn % 2) ? 1.0 : 0.0;
+      } else if (!same_cell) {
+        xb[e] = 1.0 - xi[e];
+      }
       vb = phi(S, b, xb);
     }
     const double sgn = side ? 1.0 : -1.0;
@@ -409,8 +463,8 @@ static void literal_cij(const or_setup *S, long i, long j, double *out) {
     for (int f = 0; f < 2 * S->dim; ++f) {
       int e = f / 2, side = f % 2;
       if (ai[e] != side * S->deg) continue;
-      if (bi[e] != (1 - side) * S->deg) continue;
       if (neighbour(S, Ki, f) != Kj) continue;
+      if (!on_shared_face(S, Ki, f, b)) continue;
       face_integral_mapped(S, Ki, f, a, b, 0, t);
       for (int d = 0; d < S->dim; ++d) out[d] = 0.5 * t[d];
       return;
@@ -457,6 +511,7 @@ void or_destroy(or_setup *S) {
   if (!S) return;
   free(S->rowptr); free(S->col); free(S->c); free(S->mij); free(S->kind); free(S->mi);
   free(S->bptr); free(S->bface); free(S->bkind); free(S->bc_c); free(S->vx);
+  free(S->ucp); free(S->unb); free(S->unf); free(S->ubc);
   free(S);
 }
 
@@ -495,6 +550,7 @@ static void gauss_rule(int n, double *x01, double *w01) {
 
 static or_setup *setup_init(int dim, int deg, const long *cells, const double *lo, const double *hi, const int *bc);
 static void setup_build(or_setup *S);
+static void node_x(const or_setup *S, long i, double *x);
 
 /* Setup: GL nodes, cell-major numbering, m_ij, m_i, c_ij, c_i^{d,k} (Sec. 2.3,
  * Sec. 4.2).  Exact Gauss-Legendre integration with k+1 points (reading R5). */
@@ -514,6 +570,9 @@ or_setup *or_create(int dim, int deg, const long *cells, const double *lo, const
 /* General cells with a cell map of degree mapdeg (1: the lattice of
  * n_e + 1 points per axis, multilinear cells; 2: 2 n_e + 1 points per axis,
  * quadratic (curved) cells). */
+static or_setup *finish_general(or_setup *S);
+void or_destroy(or_setup *S);
+
 or_setup *or_create_curved(int dim, int deg, const long *cells, const double *vx, const int *bc, int mapdeg) {
   double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
   if (mapdeg != 1 && mapdeg != 2) return NULL;
@@ -524,6 +583,13 @@ or_setup *or_create_curved(int dim, int deg, const long *cells, const double *vx
   for (int e = 0; e < dim; ++e) nv *= mapdeg * S->n[e] + 1;
   S->vx = (double *)malloc(nv * dim * sizeof(double));
   memcpy(S->vx, vx, nv * dim * sizeof(double));
+  return finish_general(S);
+}
+
+/* The quadrature, the admissibility of every cell (det J > 0 at the nodes
+ * and quadrature points), |Omega| and the stencil of general cells. */
+static or_setup *finish_general(or_setup *S) {
+  const int dim = S->dim, deg = S->deg, mapdeg = S->mapdeg;
   /* a rule exact for the integrands: products of the basis with det J or
    * with the cofactors, of degree at most 2 deg + 3 mapdeg - 1 per direction */
   S->nq = deg + 2 + (mapdeg == 2 ? 2 : 0);
@@ -539,7 +605,7 @@ or_setup *or_create_curved(int dim, int deg, const long *cells, const double *vx
       double xi[3] = {0, 0, 0}, x[3], J[3][3], Ji[3][3];
       for (int e = 0; e < dim; ++e) xi[e] = S->xg[ai[e]];
       cell_map(S, K, xi, x, J);
-      if (!(inverse(dim, J, Ji) > 0.0)) { free(S->vx); free(S); return NULL; }
+      if (!(inverse(dim, J, Ji) > 0.0)) { or_destroy(S); return NULL; }
     }
     int tot = 1;
     for (int e = 0; e < dim; ++e) tot *= S->nq;
@@ -549,7 +615,7 @@ or_setup *or_create_curved(int dim, int deg, const long *cells, const double *vx
       for (int e = 0; e < dim; ++e) { xi[e] = S->xq[r % S->nq]; w *= S->wq[r % S->nq]; r /= S->nq; }
       cell_map(S, K, xi, x, J);
       const double det = inverse(dim, J, Ji);
-      if (!(det > 0.0)) { free(S->vx); free(S); return NULL; }
+      if (!(det > 0.0)) { or_destroy(S); return NULL; }
       vol += w * det;
     }
   }
@@ -560,6 +626,89 @@ or_setup *or_create_curved(int dim, int deg, const long *cells, const double *vx
 
 or_setup *or_create_mapped(int dim, int deg, const long *cells, const double *vx, const int *bc) {
   return or_create_curved(dim, deg, cells, vx, bc, 1);
+}
+
+/* Unstructured meshes: ncells cells, cell K the image of the reference cell
+ * under the map of degree mapdeg through the points pts[cell_pts[K (g+1)^dim
+ * + v]] (v: digits q_e in base g + 1, the first axis lowest).  Two cells are
+ * neighbours across the faces whose corner points are the same set; a face
+ * without a neighbour is a boundary part with kind ubc[K 2 dim + f] & 7 and
+ * the data of face ubc >> 3.  NULL for a face shared by more than two cells,
+ * bad kinds or a non-positive Jacobian. */
+typedef struct { long key[4]; long K; int f; } or_facekey;
+static int facekey_cmp(const void *pa, const void *pb) {
+  const or_facekey *a = (const or_facekey *)pa, *b = (const or_facekey *)pb;
+  for (int k = 0; k < 4; ++k)
+    if (a->key[k] != b->key[k]) return a->key[k] < b->key[k] ? -1 : 1;
+  return 0;
+}
+static int long_cmp(const void *pa, const void *pb) {
+  long a = *(const long *)pa, b = *(const long *)pb;
+  return a < b ? -1 : (a > b);
+}
+
+or_setup *or_create_unstructured(int dim, int deg, long ncells, const long *cell_pts, long npts, const double *pts,
+                                 int mapdeg, const signed char *ubc) {
+  if ((mapdeg != 1 && mapdeg != 2) || ncells < 1 || dim < 2) return NULL;
+  long cells[3] = {ncells, 1, 1};
+  double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+  int bc[6] = {1, 1, 1, 1, 1, 1};
+  or_setup *S = setup_init(dim, deg, cells, lo, hi, bc);
+  if (!S) return NULL;
+  S->mapdeg = mapdeg;
+  int np = 1;
+  for (int e = 0; e < dim; ++e) np *= mapdeg + 1;
+  S->ucp = (long *)malloc(ncells * np * sizeof(long));
+  memcpy(S->ucp, cell_pts, ncells * np * sizeof(long));
+  S->vx = (double *)malloc(npts * dim * sizeof(double));
+  memcpy(S->vx, pts, npts * dim * sizeof(double));
+  S->ubc = (signed char *)malloc(ncells * 2 * dim);
+  memcpy(S->ubc, ubc, ncells * 2 * dim);
+  S->unb = (long *)malloc(ncells * 2 * dim * sizeof(long));
+  S->unf = (int *)malloc(ncells * 2 * dim * sizeof(int));
+  for (long q = 0; q < ncells * np; ++q)
+    if (S->ucp[q] < 0 || S->ucp[q] >= npts) { or_destroy(S); return NULL; }
+  /* faces keyed by their sorted corner point ids */
+  const long nf = ncells * 2 * dim;
+  or_facekey *fk = (or_facekey *)malloc(nf * sizeof(or_facekey));
+  for (long K = 0; K < ncells; ++K)
+    for (int f = 0; f < 2 * dim; ++f) {
+      or_facekey *k = &fk[K * 2 * dim + f];
+      int nc = 0;
+      for (int v = 0; v < (1 << dim); ++v) {
+        if (((v >> (f / 2)) & 1) != f % 2) continue;
+        long idx = 0, st = 1;
+        for (int e = 0; e < dim; ++e) { idx += ((v >> e) & 1) * mapdeg * st; st *= mapdeg + 1; }
+        k->key[nc++] = S->ucp[K * np + idx];
+      }
+      for (int c = nc; c < 4; ++c) k->key[c] = -1;
+      qsort(k->key, nc, sizeof(long), long_cmp);
+      k->K = K;
+      k->f = f;
+      S->unb[K * 2 * dim + f] = -1;
+      S->unf[K * 2 * dim + f] = -1;
+    }
+  qsort(fk, nf, sizeof(or_facekey), facekey_cmp);
+  int bad = 0;
+  for (long q = 0; q < nf;) {
+    long r = q + 1;
+    while (r < nf && facekey_cmp(&fk[q], &fk[r]) == 0) ++r;
+    if (r - q == 2) {
+      S->unb[fk[q].K * 2 * dim + fk[q].f] = fk[q + 1].K;
+      S->unf[fk[q].K * 2 * dim + fk[q].f] = fk[q + 1].f;
+      S->unb[fk[q + 1].K * 2 * dim + fk[q + 1].f] = fk[q].K;
+      S->unf[fk[q + 1].K * 2 * dim + fk[q + 1].f] = fk[q].f;
+    } else if (r - q == 1) {
+      const signed char u = S->ubc[fk[q].K * 2 * dim + fk[q].f];
+      if (u < 0 || (u & 7) < OR_BC_OUTFLOW || (u & 7) > OR_BC_INOUTFLOW || (u >> 3) > 5) bad = 1;
+    } else {
+      bad = 1;
+    }
+    q = r;
+  }
+  free(fk);
+  if (bad) { or_destroy(S); return NULL; }
+  return finish_general(S);
 }
 
 static or_setup *setup_init(int dim, int deg, const long *cells, const double *lo, const double *hi, const int *bc) {
@@ -683,10 +832,19 @@ static void setup_build(or_setup *S) {
         for (int b = 0; b < nloc; ++b) {
           int bi[3];
           local_multi(S, b, bi);
-          if (bi[e] != (1 - side) * deg) continue;
+          if (!on_shared_face(S, K, f, b)) continue;
           long j = Kn * nloc + b;
           int colloc = 1;
-          for (int d = 0; d < dim; ++d) if (d != e && bi[d] != ai[d]) colloc = 0;
+          if (S->ucp) {
+            /* collocated: the same point (reading R12 on unstructured cells) */
+            double xa[3], xb[3], dd = 0.0, hs = 0.0;
+            node_x(S, i, xa);
+            node_x(S, j, xb);
+            for (int d = 0; d < dim; ++d) { dd = fmax(dd, fabs(xa[d] - xb[d])); hs = fmax(hs, fabs(xa[d])); }
+            colloc = dd <= 1e-12 * (1.0 + hs);
+          } else {
+            for (int d = 0; d < dim; ++d) if (d != e && bi[d] != ai[d]) colloc = 0;
+          }
           S->col[nnz] = j;
           canonical_cij(S, i, j, S->c + nnz * dim);
           S->mij[nnz] = 0.0;
@@ -705,6 +863,11 @@ static void setup_build(or_setup *S) {
         }
         S->bface[nb] = f;
         S->bkind[nb] = S->bc[f];
+        if (S->ucp) {
+          const signed char u = S->ubc[K * 2 * dim + f];
+          S->bface[nb] = u >> 3;
+          S->bkind[nb] = u & 7;
+        }
         ++nb;
       }
     }

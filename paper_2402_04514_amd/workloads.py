@@ -410,6 +410,117 @@ def annulus_ogrid(ntheta: int, nr: int, r0: float = 0.5, r1: float = 1.0, map_de
     return np.stack([R * np.cos(T), R * np.sin(T)], axis=-1).reshape(-1, 2)
 
 
+def _rotations(dim):
+    """The orientation-preserving symmetries of the reference square or cube,
+    as integer matrices acting on centred coordinates."""
+    out = []
+    for perm in ([0, 1], [1, 0]) if dim == 2 else ([0, 1, 2], [0, 2, 1], [1, 0, 2], [1, 2, 0], [2, 0, 1], [2, 1, 0]):
+        for signs in np.ndindex(*(2,) * dim):
+            R = np.zeros((dim, dim), dtype=int)
+            for r in range(dim):
+                R[r, perm[r]] = 1 if signs[r] == 0 else -1
+            if round(np.linalg.det(R)) == 1:
+                out.append(R)
+    return out
+
+
+def unstructured_from_lattice(cells, points, bc, map_degree=1, seed=0, shuffle=True):
+    """The lattice mesh of `points` (map_degree * n_e + 1 per axis, x fastest)
+    written as an unstructured mesh: the point list, each cell's (g+1)^d
+    point ids in a randomly rotated local order, the cells in a random order
+    (seeded).  No axis may be periodic: an unstructured mesh connects cells
+    through shared points only, and a translated periodic image is another
+    point.  face_bc[K, f] = kind + 8 *
+    the lattice face the part lies on (that face's data).
+
+    Returns (cell_points, points, face_bc, perm, rot): cell perm[K] of the
+    unstructured mesh is lattice cell K, with its local axes turned by rot[K]
+    (an index into _rotations(d))."""
+    d = len(cells)
+    g = map_degree
+    npa = [g * c + 1 for c in cells]
+    P = np.asarray(points, dtype=np.float64)
+    if any(b == 0 for b in bc):
+        raise ValueError("periodic axes cannot be written as an unstructured mesh")
+
+    def pid(idx):
+        k, st = 0, 1
+        for e in range(d):
+            k += idx[e] * st
+            st *= npa[e]
+        return k
+    ncells = int(np.prod(cells))
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(ncells) if shuffle else np.arange(ncells)
+    rots = _rotations(d)
+    rot = rng.integers(0, len(rots), size=ncells) if shuffle else np.zeros(ncells, dtype=int)
+    np_ = (g + 1) ** d
+    cp = np.zeros((ncells, np_), dtype=np.int64)
+    fb = np.zeros((ncells, 2 * d), dtype=np.int8)
+    for K in range(ncells):
+        ki, r = [], K
+        for e in range(d):
+            ki.append(r % cells[e])
+            r //= cells[e]
+        R = rots[rot[K]]
+        for v in range(np_):
+            q, rr = [], v
+            for e in range(d):
+                q.append(rr % (g + 1))
+                rr //= g + 1
+            # new local position q comes from old position R^T (q - c) + c
+            c = g / 2.0
+            old = np.rint(R.T @ (np.array(q) - c) + c).astype(int)
+            cp[perm[K], v] = pid([g * ki[e] + old[e] for e in range(d)])
+        # local face f of the new cell: outward normal R e_f in old axes
+        for f in range(2 * d):
+            nvec = np.zeros(d, dtype=int)
+            nvec[f // 2] = 1 if f % 2 else -1
+            o = R.T @ nvec
+            e = int(np.nonzero(o)[0][0])
+            fo = 2 * e + (1 if o[e] > 0 else 0)
+            on_bnd = (ki[e] == 0 and fo % 2 == 0) or (ki[e] == cells[e] - 1 and fo % 2 == 1)
+            if on_bnd and bc[fo] != 0:
+                fb[perm[K], f] = bc[fo] + 8 * fo
+    return cp, P, fb, perm, rot
+
+
+def triangle_three_blocks(n, corners=((0.0, 0.0), (1.0, 0.0), (0.3, 0.9)), map_degree=1):
+    """An unstructured mesh of a triangle: three quadrilateral blocks (each
+    corner, the two adjacent edge midpoints and the centroid), each cut into
+    n x n cells by bilinear interpolation; the centroid has three cells.
+    Returns (cell_points, points, face_bc with kind 0 everywhere; the caller
+    sets the boundary kinds on the faces without a neighbour)."""
+    A = [np.array(c, dtype=float) for c in corners]
+    G = (A[0] + A[1] + A[2]) / 3.0
+    blocks = []
+    for i in range(3):
+        a, b, c = A[i], A[(i + 1) % 3], A[(i + 2) % 3]
+        blocks.append((a, 0.5 * (a + b), G, 0.5 * (a + c)))  # counterclockwise: a, mab, G, mac
+    g = map_degree
+    m = g * n
+    pts, index = [], {}
+    def point_id(x):
+        key = (round(x[0], 12), round(x[1], 12))
+        if key not in index:
+            index[key] = len(pts)
+            pts.append(x)
+        return index[key]
+    cps = []
+    for (p00, p10, p11, p01) in blocks:
+        ids = np.zeros((m + 1, m + 1), dtype=np.int64)
+        for j in range(m + 1):
+            for i in range(m + 1):
+                s, t = i / m, j / m
+                x = (1 - s) * (1 - t) * p00 + s * (1 - t) * p10 + s * t * p11 + (1 - s) * t * p01
+                ids[j, i] = point_id(x)
+        for cj in range(n):
+            for ci in range(n):
+                cps.append([ids[g * cj + qj, g * ci + qi] for qj in range(g + 1) for qi in range(g + 1)])
+    cp = np.array(cps, dtype=np.int64)
+    return cp, np.array(pts), np.zeros((len(cp), 4), dtype=np.int8)
+
+
 def cylinder(ntheta: int = 512, nr: int = 128, degree: int = 1, mach: float = 3.0, stretch: float = 0.0,
              t_final: float = 4.0, map_degree: int = 1) -> Workload:
     """Mach 3 flow past a cylinder on the O-grid of cylinder_ogrid(): uniform

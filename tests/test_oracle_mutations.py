@@ -21,9 +21,14 @@ INOUT = T + "test_oracle_inoutflow.py"
 MAPPED = T + "test_oracle_mapped.py"
 BCPARTS = T + "test_oracle_bcparts.py"
 CURVED = T + "test_oracle_curved.py"
+UNSTR = T + "test_oracle_unstructured.py"
 
 MUTANTS = {
     # name: (original text, planted text, pin files that must fail)
+    "unstructured_neighbour_mirrored": ("      if (!same_cell && S->ucp) {", "      if (0) {",
+                                        [UNSTR + "::test_renumbered_lattice_gives_the_lattice_result"]),
+    "unstructured_face_key_unsorted": ("      qsort(k->key, nc, sizeof(long), long_cmp);\n", "",
+                                       [UNSTR + "::test_renumbered_lattice_gives_the_lattice_result"]),
     "curved_map_midpoint_weight": ("(q == 1 ? -4.0 * t * (t - 1.0) : 2.0 * t * (t - 0.5))",
                                    "(q == 1 ? -2.0 * t * (t - 1.0) : 2.0 * t * (t - 0.5))",
                                    [CURVED + "::test_quadratic_points_of_multilinear_cells_give_the_multilinear_mesh"]),
