@@ -143,7 +143,22 @@ typedef enum { GDG_FP64 = 0, GDG_MIXED = 1 } gdg_precision;
  * PERIODIC.  The DIRICHLET, SUPERSONIC and INOUTFLOW parts of face f take
  * face f's data (bc_state[f], or the vortex), which must then be admissible.
  * bc[f] still decides which axes are periodic.  Read during gdg_create()
- * only. */
+ * only.
+ *
+ * Unstructured meshes (dim 2 or 3): with ucells > 0 the mesh is ucells cells
+ * of any connectivity.  Cell q is the image of the reference cell under its
+ * map of degree map_degree (multilinear or quadratic) through the points
+ * vertices[ucell_points[q (g+1)^dim + v]] (npoints points of dim coordinates;
+ * v: the digits q_e of v in base g + 1, the first axis lowest).  Two cells
+ * are neighbours across faces with the same corner points (in any relative
+ * orientation; with map_degree 2 all the face's points must agree); a face
+ * may be shared by two cells at most.  A face of no other cell is a boundary
+ * part: uface_bc[q 2 dim + f] (local face f = 2 axis + side) is its kind (a
+ * gdg_bc other than PERIODIC) + 8 * the box-face slot (< 2 dim) whose data
+ * (bc_state) it takes; entries of interior faces must be 0.  cells, lo, hi,
+ * bc and bc_cells are not read; cells connect through shared points only, so
+ * an O-grid's seam is periodic by construction and a translated periodic
+ * image is not expressible.  The arrays are read during gdg_create() only. */
 typedef struct {
   int32_t dim;
   int32_t degree;
@@ -157,6 +172,11 @@ typedef struct {
   double vortex[6];
   const double *vertices; /* NULL: the uniform box [lo, hi]; else host memory, see above */
   const int8_t *bc_cells; /* NULL: kind bc[f] on all of box face f; else host memory, see above */
+  /* unstructured meshes (see above); ucells = 0: the lattice of cells[] */
+  int64_t ucells;
+  int64_t npoints;
+  const int64_t *ucell_points;
+  const int8_t *uface_bc;
 } gdg_mesh_desc;
 
 /* Scheme constants.  gdg_default_params() gives the paper's values:
@@ -398,6 +418,7 @@ gdg_status gdg_server_create(const gdg_server_desc *desc, void *dev_pool, size_t
 
 /* Queues a request; U0 is a host state (SoA, (dim+2) * N doubles), copied,
  * as are the mesh's vertices (general cells) and boundary parts.
+ * Unstructured meshes are not served (GDG_E_INVALID).
  * GDG_E_INVALID for a description outside the server's class or bad
  * constants, GDG_E_BUDGET if its workspace exceeds the whole pool. */
 gdg_status gdg_server_submit(gdg_server *srv, const gdg_mesh_desc *mesh, const gdg_params *prm, const double *U0,

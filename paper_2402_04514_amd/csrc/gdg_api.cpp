@@ -41,6 +41,9 @@ struct gdg_ctx {
   // parts: their kinds (mesh.bc_cells points here)
   std::vector<double> vx;
   std::vector<int8_t> bcc;
+  // unstructured meshes: the cells' point ids and the boundary faces' kinds
+  std::vector<int64_t> ucp;
+  std::vector<int8_t> ufb;
 };
 
 namespace {
@@ -77,6 +80,14 @@ void part_offsets(const gdg_mesh_desc *m, int64_t *off, int64_t *total) {
 
 // Whether some part of face f takes the face's data.
 bool face_has_data(const gdg_mesh_desc *m, int f) {
+  if (m->ucells > 0) {
+    // unstructured: some boundary face names a data kind with data slot f
+    for (int64_t q = 0; q < m->ucells * 2 * m->dim; ++q) {
+      const int8_t u = m->uface_bc[q];
+      if (u > 0 && is_data_kind(u & 7) && (u >> 3) == f) return true;
+    }
+    return false;
+  }
   if (m->bc[f] == GDG_BC_PERIODIC) return false;
   if (!m->bc_cells) return is_data_kind(m->bc[f]);
   int64_t off[6], n;
@@ -93,7 +104,27 @@ bool validate(const gdg_mesh_desc *m, const gdg_params *p, std::string *err) {
   if (m->degree < 1 || m->degree > 3) { *err = "degree must be 1, 2 or 3"; return false; }
   if (m->degree == 3 && m->dim == 3) { *err = "degree 3 is built for dim 1 and 2"; return false; }
   int64_t ncells = 1;
-  for (int e = 0; e < m->dim; ++e) {
+  if (m->ucells < 0) { *err = "ucells must be >= 0"; return false; }
+  if (m->ucells > 0) {
+    // unstructured: points, cells' point lists and boundary faces
+    if (m->dim < 2) { *err = "unstructured meshes are built for dim 2 and 3"; return false; }
+    if (!m->vertices || !m->ucell_points || !m->uface_bc || m->npoints < 1) {
+      *err = "an unstructured mesh needs vertices, npoints, ucell_points and uface_bc";
+      return false;
+    }
+    if (m->bc_cells) { *err = "bc_cells is for lattice meshes (unstructured: uface_bc)"; return false; }
+    if (m->data_kind == GDG_DATA_VORTEX) { *err = "vortex data are built for the uniform box"; return false; }
+    const int g = m->map_degree == 2 ? 2 : 1;
+    int np = 1;
+    for (int e = 0; e < m->dim; ++e) np *= g + 1;
+    for (int64_t q = 0; q < m->ucells * np; ++q)
+      if (m->ucell_points[q] < 0 || m->ucell_points[q] >= m->npoints) {
+        *err = "a cell names a point outside vertices";
+        return false;
+      }
+    ncells = m->ucells;
+  }
+  for (int e = 0; e < m->dim && m->ucells == 0; ++e) {
     if (m->cells[e] < 1) { *err = "cells must be >= 1"; return false; }
     if (!m->vertices && !(m->hi[e] > m->lo[e])) { *err = "hi must exceed lo"; return false; }
     int b0 = m->bc[2 * e], b1 = m->bc[2 * e + 1];
@@ -111,6 +142,21 @@ bool validate(const gdg_mesh_desc *m, const gdg_params *p, std::string *err) {
   }
   // boundary parts and the data of the faces, once every axis is checked
   for (int e = 0; e < m->dim; ++e) {
+    if (m->ucells > 0) {
+      for (int side = 0; side < 2; ++side) {
+        const int f = 2 * e + side;
+        if (!face_has_data(m, f) || m->data_kind == GDG_DATA_VORTEX) continue;
+        const double *V = m->bc_state[f];
+        double m2 = 0.0;
+        for (int k = 0; k < m->dim; ++k) m2 += V[1 + k] * V[1 + k];
+        const double rho = V[0], eps = V[m->dim + 1] - 0.5 * m2 / rho;
+        if (!(rho > 0.0) || !(eps > 0.0) || !std::isfinite(rho) || !std::isfinite(V[m->dim + 1])) {
+          *err = "Dirichlet data of a face is not admissible (rho <= 0, eps <= 0 or not finite)";
+          return false;
+        }
+      }
+      continue;
+    }
     if (m->bc_cells) {
       // the parts' own kinds: no periodic or unknown kind
       int64_t off[6], n;
@@ -207,6 +253,7 @@ Layout layout(const gdg_mesh_desc *m, const gdg_params *p) {
   L.W = L.nloc + m->dim * nface;
   L.ncells = 1;
   for (int e = 0; e < m->dim; ++e) L.ncells *= m->cells[e];
+  if (m->ucells > 0) L.ncells = m->ucells;
   L.N = L.ncells * L.nloc;
   L.nblocks = (L.ncells + L.cpb - 1) / L.cpb;
   L.nslots = L.nblocks * L.W * L.R;
@@ -231,7 +278,9 @@ Layout layout(const gdg_mesh_desc *m, const gdg_params *p) {
   L.off_red = take((size_t)(kRedBlocks + 1) * kRedFields * 8);
   L.off_cnt = take((size_t)kCntKinds * kCntSlots * kCntStride * 8);
   L.off_mrow = L.off_hprow = L.off_relrow = L.off_cmblk = L.off_cminv = L.off_bcc = 0;
-  part_offsets(m, L.bcc_off, &L.nbcc);
+  for (int f = 0; f < 6; ++f) L.bcc_off[f] = 0;
+  L.nbcc = 0;
+  if (m->bc_cells) part_offsets(m, L.bcc_off, &L.nbcc);
   if (m->bc_cells) L.off_bcc = take((size_t)L.nbcc);
   if (m->vertices) {
     const size_t blk = (size_t)L.ncells * L.nloc * L.nloc * 8;
@@ -421,8 +470,17 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   if (mesh->vertices) {
     size_t npts = 1;
     for (int e = 0; e < mesh->dim; ++e) npts *= (size_t)(map_degree(mesh) * mesh->cells[e] + 1);
+    if (mesh->ucells > 0) npts = (size_t)mesh->npoints;
     ctx->vx.assign(mesh->vertices, mesh->vertices + npts * mesh->dim);
     ctx->mesh.vertices = ctx->vx.data();
+  }
+  if (mesh->ucells > 0) {
+    int np = 1;
+    for (int e = 0; e < mesh->dim; ++e) np *= map_degree(mesh) + 1;
+    ctx->ucp.assign(mesh->ucell_points, mesh->ucell_points + mesh->ucells * np);
+    ctx->ufb.assign(mesh->uface_bc, mesh->uface_bc + mesh->ucells * 2 * mesh->dim);
+    ctx->mesh.ucell_points = ctx->ucp.data();
+    ctx->mesh.uface_bc = ctx->ufb.data();
   }
   if (mesh->bc_cells) {
     ctx->bcc.assign(mesh->bc_cells, mesh->bc_cells + L.nbcc);
@@ -446,7 +504,7 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   A.cpb = L.cpb;
   A.tiled = 0;
   A.t_nbx = A.t_ny = A.t_nz = A.t_tx = A.t_ty = 1;
-  if (mesh->dim == 3 && mesh->cells[0] % L.cpb == 0) {
+  if (mesh->dim == 3 && mesh->ucells == 0 && mesh->cells[0] % L.cpb == 0) {
     // tiles one row block wide in x and ty cell rows in y, ty the largest
     // divisor of ny up to kTileRows (measured on the 128^3 blast: 1 x 32 and
     // 1 x 64 beat the 16 x 8 tiles by 5 %)
@@ -464,13 +522,14 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   }
   double h[3] = {1, 1, 1}, vol = 1.0;
   for (int e = 0; e < 3; ++e) A.cells[e] = e < mesh->dim ? mesh->cells[e] : 1;
+  if (mesh->ucells > 0) A.cells[0] = mesh->ucells, A.cells[1] = A.cells[2] = 1;
   for (int e = 0; e < mesh->dim && !mesh->vertices; ++e) {
     h[e] = (mesh->hi[e] - mesh->lo[e]) / (double)mesh->cells[e];
     vol *= mesh->hi[e] - mesh->lo[e];
   }
   A.bcdata = 0;
   for (int f = 0; f < 6; ++f) {
-    A.bc[f] = f < 2 * mesh->dim ? mesh->bc[f] : GDG_BC_OUTFLOW;
+    A.bc[f] = f < 2 * mesh->dim && mesh->ucells == 0 ? mesh->bc[f] : GDG_BC_OUTFLOW;
     if (f < 2 * mesh->dim && face_has_data(mesh, f)) A.bcdata |= 1 << f;
     A.bcc_off[f] = L.bcc_off[f];
   }
@@ -514,6 +573,7 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   A.red = (double *)(ws + L.off_red);
   A.cnt = (unsigned long long *)(ws + L.off_cnt);
   A.general = mesh->vertices ? 1 : 0;
+  A.ustruct = mesh->ucells > 0 ? 1 : 0;
   if (A.general) {
     A.mrow = (const double *)(ws + L.off_mrow);
     A.hprow = (const double *)(ws + L.off_hprow);
@@ -599,6 +659,11 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
     cp(A.relrow, G.relrow.data(), nb);
     cp(A.cmblk, G.cmblk.data(), bb);
     cp(A.cminv, G.cminv.data(), bb);
+    if (A.ustruct) {
+      // the whole stencil: the fill kernel leaves unstructured meshes alone
+      cp(A.col, G.col.data(), G.col.size() * sizeof(int32_t));
+      cp(A.meta, G.meta.data(), G.meta.size());
+    }
     // the host vectors must outlive the copies
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {

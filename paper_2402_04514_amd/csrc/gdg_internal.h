@@ -172,6 +172,7 @@ struct KArgs {
   // General (mapped) cells: the per-node and per-cell-class entries of ref
   // (mlump, hpk, relax, mblk, minv) are per row and per cell instead
   int32_t general;
+  int32_t ustruct;      // unstructured: the host wrote col, meta and c (the fill kernel only sets boundary data)
   const double *mrow;   // m_i
   const double *hprow;  // c_k hhat_i^{p_k}
   const double *relrow; // c_r hhat_i^{p_r}
@@ -237,6 +238,9 @@ struct MappedSetup {
   std::vector<double> cmblk, cminv;                  // per cell, nloc x nloc
   std::vector<double> c;                             // dim planes of nslots, the slot order of the fill kernel
   double vol;                                        // |Omega|
+  // unstructured meshes: the whole stencil (the fill kernel does not run)
+  std::vector<int32_t> col;
+  std::vector<uint8_t> meta;
 };
 bool build_mapped(const gdg_mesh_desc *m, const gdg_params *p, const double *vx, const RefTables &T, int R, int W,
                   int64_t nslots, MappedSetup *out, std::string *err);

@@ -330,7 +330,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_fill(KArgs A) {
   constexpr int NLOC = D == 1 ? NB : (D == 2 ? NB * NB : NB * NB * NB);
   constexpr int NFACE = NLOC / NB;
   const int lane = threadIdx.x;
-  if (lane >= A.R) return;
+  if (lane >= A.R || A.ustruct) return;
   const int64_t blk = xcd_block(A, blockIdx.x);
   const int64_t i = blk * A.R + lane;
   const RefTables *T = A.ref;

@@ -181,6 +181,16 @@ int map_degree(const gdg_mesh_desc *m) { return m->map_degree == 2 ? 2 : 1; }
 
 void mapped_cell_points(const gdg_mesh_desc *m, const double *vx, int64_t K, double (*X)[3]) {
   const int d = m->dim, g = map_degree(m);
+  if (m->ucells > 0) {
+    // unstructured: the cell's own point list
+    int np = 1;
+    for (int e = 0; e < d; ++e) np *= g + 1;
+    for (int v = 0; v < np; ++v) {
+      const int64_t id = m->ucell_points[K * np + v];
+      for (int c = 0; c < 3; ++c) X[v][c] = c < d ? vx[id * d + c] : 0.0;
+    }
+    return;
+  }
   int64_t ki[3] = {0, 0, 0}, r = K;
   for (int e = 0; e < d; ++e) {
     ki[e] = r % m->cells[e];
@@ -209,6 +219,208 @@ void mapped_point(int d, int g, const double (*X)[3], const double *xi, double *
   }
 }
 
+namespace {
+
+// A face of an unstructured mesh keyed by its sorted corner point ids.
+struct FaceKey {
+  int64_t id[4];
+  int64_t K;
+  int f;
+  bool operator<(const FaceKey &o) const {
+    for (int k = 0; k < 4; ++k)
+      if (id[k] != o.id[k]) return id[k] < o.id[k];
+    return K != o.K ? K < o.K : f < o.f;
+  }
+  bool same_face(const FaceKey &o) const { return std::equal(id, id + 4, o.id); }
+};
+
+// Point id of cell K at map position q (0 .. g per axis).
+int64_t upoint(const gdg_mesh_desc *m, int64_t K, const int *q) {
+  const int g = map_degree(m), d = m->dim;
+  int np = 1, v = 0, st = 1;
+  for (int e = 0; e < d; ++e) np *= g + 1;
+  for (int e = 0; e < d; ++e) {
+    v += q[e] * st;
+    st *= g + 1;
+  }
+  return m->ucell_points[K * np + v];
+}
+
+// Map position of face f's point at in-face position t (0 .. g on the face's
+// axes, the lower axis first): q_e = side * g on the face's own axis.
+void face_point(int d, int g, int f, const int *t, int *q) {
+  const int e = f / 2, side = f % 2;
+  for (int a = 0, j = 0; a < d; ++a) q[a] = a == e ? side * g : t[j++];
+}
+
+}  // namespace
+
+// Stencil of an unstructured mesh in the ELL layout: per row the in-cell
+// nodes, then per local face the row lies on its neighbour's face nodes (by
+// the position of each on this cell's face) or its boundary part; c_ij from
+// the cell of the lower index, negated in the other row (reading R3).  The
+// neighbour's face parametrization is this cell's turned by the symmetry
+// that matches the two cells' face corners.
+bool assemble_unstructured(const gdg_mesh_desc *m, const RefTables &T, int R, int W, int64_t nslots, int nloc,
+                           int nface, const std::vector<int> &fnode, const std::vector<double> &cin,
+                           const std::vector<double> &cfc, const std::vector<double> &cgh, MappedSetup *out,
+                           std::string *err) {
+  const int d = m->dim, deg = m->degree, g = map_degree(m), nb = deg + 1;
+  const int64_t ncells = m->ucells, N = ncells * nloc;
+  const int nfc = 1 << (d - 1);  // corners per face
+  // 1. neighbours: faces with the same corner set
+  std::vector<FaceKey> keys((size_t)ncells * 2 * d);
+  for (int64_t K = 0; K < ncells; ++K)
+    for (int f = 0; f < 2 * d; ++f) {
+      FaceKey &k = keys[(size_t)K * 2 * d + f];
+      for (int c = 0; c < 4; ++c) k.id[c] = -1;
+      for (int c = 0; c < nfc; ++c) {
+        int t[2] = {(c & 1) * g, ((c >> 1) & 1) * g}, q[3];
+        face_point(d, g, f, t, q);
+        k.id[c] = upoint(m, K, q);
+      }
+      std::sort(k.id, k.id + nfc);
+      k.K = K;
+      k.f = f;
+    }
+  std::vector<FaceKey> sorted = keys;
+  std::sort(sorted.begin(), sorted.end());
+  std::vector<int64_t> nbr((size_t)ncells * 2 * d, -1);
+  std::vector<int> nbf((size_t)ncells * 2 * d, -1);
+  for (size_t q = 0; q < sorted.size();) {
+    size_t r = q + 1;
+    while (r < sorted.size() && sorted[r].same_face(sorted[q])) ++r;
+    if (r - q > 2) {
+      *err = "a face is shared by more than two cells";
+      return false;
+    }
+    if (r - q == 2) {
+      const FaceKey &a = sorted[q], &b = sorted[q + 1];
+      nbr[(size_t)a.K * 2 * d + a.f] = b.K, nbf[(size_t)a.K * 2 * d + a.f] = b.f;
+      nbr[(size_t)b.K * 2 * d + b.f] = a.K, nbf[(size_t)b.K * 2 * d + b.f] = a.f;
+    }
+    q = r;
+  }
+  // 2. the symmetry between the two face parametrizations: corner c of this
+  // face (bits on the face's axes) sits at corner c' of the neighbour's;
+  // position t maps to o k + t_0 u + t_1 v, per face of each cell
+  struct Orient { int o[2], u[2], v[2]; };
+  std::vector<Orient> orient((size_t)ncells * 2 * d);
+  for (int64_t K = 0; K < ncells; ++K)
+    for (int f = 0; f < 2 * d; ++f) {
+      const int64_t Kn = nbr[(size_t)K * 2 * d + f];
+      if (Kn < 0) {
+        const int8_t u = m->uface_bc[K * 2 * d + f];
+        const int kind = u & 7, df = u >> 3;
+        if (u < 0 || kind < GDG_BC_OUTFLOW || kind > GDG_BC_INOUTFLOW || df >= 2 * d) {
+          *err = "a boundary face has no valid kind and data face in uface_bc";
+          return false;
+        }
+        continue;
+      }
+      const int fn = nbf[(size_t)K * 2 * d + f];
+      int cc[4][2];  // neighbour corner bits of each of this face's corners
+      for (int c = 0; c < nfc; ++c) {
+        int t[2] = {(c & 1) * g, ((c >> 1) & 1) * g}, q[3];
+        face_point(d, g, f, t, q);
+        const int64_t id = upoint(m, K, q);
+        int found = -1;
+        for (int c2 = 0; c2 < nfc && found < 0; ++c2) {
+          int t2[2] = {(c2 & 1) * g, ((c2 >> 1) & 1) * g}, q2[3];
+          face_point(d, g, fn, t2, q2);
+          if (upoint(m, Kn, q2) == id) found = c2;
+        }
+        cc[c][0] = found & 1, cc[c][1] = (found >> 1) & 1;
+      }
+      Orient &o = orient[(size_t)K * 2 * d + f];
+      for (int j = 0; j < 2; ++j) {
+        o.o[j] = cc[0][j];
+        o.u[j] = nfc > 1 ? cc[1][j] - cc[0][j] : 0;
+        o.v[j] = nfc > 2 ? cc[2][j] - cc[0][j] : 0;
+      }
+      // every point of the face must agree (edge midpoints of curved faces)
+      for (int t0 = 0; t0 <= g; ++t0)
+        for (int t1 = 0; t1 <= (d == 3 ? g : 0); ++t1) {
+          int t[2] = {t0, t1}, tn[2], q[3], qn[3];
+          for (int j = 0; j < 2; ++j) tn[j] = o.o[j] * g + o.u[j] * t0 + o.v[j] * t1;
+          face_point(d, g, f, t, q);
+          face_point(d, g, fn, tn, qn);
+          if (upoint(m, K, q) != upoint(m, Kn, qn)) {
+            *err = "a face's points differ between its two cells";
+            return false;
+          }
+        }
+    }
+  // position (t_0, t_1) on a face <-> index (first axis fastest), 0 .. nface-1
+  auto pos_of = [&](int tb, int *t) { t[0] = tb % nb, t[1] = tb / nb; };
+  auto index_of = [&](const int *t) { return t[0] + (d == 3 ? nb * t[1] : 0); };
+  auto map_pos = [&](const Orient &o, const int *t, int *tn) {
+    for (int j = 0; j < 2; ++j) tn[j] = o.o[j] * deg + o.u[j] * t[0] + o.v[j] * t[1];
+  };
+  // 3. rows
+  out->col.assign((size_t)nslots, 0);
+  out->meta.assign((size_t)nslots, (uint8_t)SK_PAD);
+  out->kscale.assign(N, 0.0);
+  const int64_t nblocks = nslots / ((int64_t)W * R);
+  for (int64_t i = 0; i < nblocks * R; ++i) {
+    const int64_t blk = i / R, lane = i % R;
+    int t = 0;
+    auto put = [&](int32_t col, const double *c, double sgn, uint8_t meta) {
+      const int64_t s = (blk * W + t) * R + lane;
+      out->col[s] = col;
+      out->meta[s] = meta;
+      for (int e = 0; e < d; ++e) out->c[(size_t)e * nslots + s] = c ? sgn * c[e] : 0.0;
+      ++t;
+    };
+    if (i < N) {
+      const int64_t K = i / nloc;
+      const int a = (int)(i % nloc);
+      int graph = 0;
+      for (int b = 0; b < nloc; ++b) {
+        put((int32_t)(K * nloc + b), &cin[((size_t)K * nloc * nloc + a * nloc + b) * d], 1.0,
+            (uint8_t)(SK_CELL | (b << 3)));
+        ++graph;
+      }
+      for (int f = 0; f < 2 * d; ++f) {
+        if (!T.onface[f * kMaxNloc + a]) continue;
+        int ta = 0;
+        while (fnode[f * nface + ta] != a) ++ta;
+        const int64_t Kn = nbr[(size_t)K * 2 * d + f];
+        if (Kn < 0) {
+          const int8_t u = m->uface_bc[K * 2 * d + f];
+          put((int32_t)i, &cgh[(((size_t)K * 2 * d + f) * nloc + a) * d], 1.0,
+              (uint8_t)(SK_GHOST | (bclass(u >> 3, u & 7) << 3)));
+          continue;
+        }
+        const int fn = nbf[(size_t)K * 2 * d + f];
+        const Orient &o = orient[(size_t)K * 2 * d + f];
+        int tA[2], tAn[2];
+        pos_of(ta, tA);
+        map_pos(o, tA, tAn);
+        const int tan_ = index_of(tAn);
+        for (int tb = 0; tb < nface; ++tb) {
+          int tB[2], tBn[2];
+          pos_of(tb, tB);
+          map_pos(o, tB, tBn);
+          const int tbn = index_of(tBn);
+          const int bn = fnode[fn * nface + tbn];  // the neighbour's node at this position
+          const uint8_t kind = tb == ta ? SK_FACE_COLLOC : SK_FACE;
+          if (K < Kn)
+            put((int32_t)(Kn * nloc + bn), &cfc[((((size_t)K * 2 * d + f) * nface + ta) * nface + tb) * d], 1.0,
+                kind);
+          else
+            put((int32_t)(Kn * nloc + bn), &cfc[((((size_t)Kn * 2 * d + fn) * nface + tbn) * nface + tan_) * d],
+                -1.0, kind);
+          ++graph;
+        }
+      }
+      out->kscale[i] = (double)(graph + 1) / out->mrow[i];
+    }
+    while (t < W) put((int32_t)(i < N ? i : 0), nullptr, 0.0, (uint8_t)SK_PAD);
+  }
+  return true;
+}
+
 bool build_mapped(const gdg_mesh_desc *m, const gdg_params *p, const double *vx, const RefTables &T, int R, int W,
                   int64_t nslots, MappedSetup *out, std::string *err) {
   const int d = m->dim, deg = m->degree, nb = deg + 1;
@@ -217,6 +429,7 @@ bool build_mapped(const gdg_mesh_desc *m, const gdg_params *p, const double *vx,
   const int nface = nloc / nb;
   int64_t ncells = 1;
   for (int e = 0; e < d; ++e) ncells *= m->cells[e];
+  if (m->ucells > 0) ncells = m->ucells;
   const int64_t N = ncells * nloc;
   const Lag1D L = lag1d(deg);
   // Gauss points per direction, exact for every integrand: with a map of
@@ -371,6 +584,18 @@ bool build_mapped(const gdg_mesh_desc *m, const gdg_params *p, const double *vx,
   out->hprow.resize(N);
   out->kscale.resize(N);
   out->c.assign((size_t)d * nslots, 0.0);
+  if (m->ucells > 0) {
+    for (int64_t i = 0; i < N; ++i) {
+      const double hh = std::pow(out->mrow[i] / vol, 1.0 / d);
+      out->hprow[i] = p->c_k * std::pow(hh, pk);
+      out->relrow[i] = p->c_r * std::pow(hh, p->p_r);
+      if (!(out->relrow[i] < 1.0)) {
+        *err = "relaxation c_r h^p_r >= 1: the lower bounds would not be positive";
+        return false;
+      }
+    }
+    return assemble_unstructured(m, T, R, W, nslots, nloc, nface, fnode, cin, cfc, cgh, out, err);
+  }
   std::atomic<bool> relax_ok{true};
   parallel_ranges(N, [&](int64_t i0, int64_t i1) {
   for (int64_t i = i0; i < i1; ++i) {

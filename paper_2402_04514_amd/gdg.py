@@ -42,7 +42,8 @@ class gdg_mesh_desc(C.Structure):
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("bc", C.c_int32 * 6),
                 ("bc_state", (C.c_double * 5) * 6), ("data_kind", C.c_int32), ("map_degree", C.c_int32),
                 ("vortex", C.c_double * 6), ("vertices", C.POINTER(C.c_double)),
-                ("bc_cells", C.POINTER(C.c_int8))]
+                ("bc_cells", C.POINTER(C.c_int8)), ("ucells", C.c_int64), ("npoints", C.c_int64),
+                ("ucell_points", C.POINTER(C.c_int64)), ("uface_bc", C.POINTER(C.c_int8))]
 
 
 class gdg_params(C.Structure):
@@ -183,6 +184,36 @@ def mesh_desc(dim, degree, cells, lo, hi, bc, bstate=None, vortex=None, vertices
     return m
 
 
+def umesh_desc(dim, degree, cell_points, points, face_bc, bstate=None, map_degree=1) -> gdg_mesh_desc:
+    """Unstructured mesh: cell q is the image of the reference cell under its
+    map of degree map_degree through points[cell_points[q, v]]; face_bc[q, f]
+    is the kind + 8 * data slot of a face on no other cell (0 elsewhere).  The
+    descriptor keeps references to its arrays."""
+    m = gdg_mesh_desc()
+    m.dim, m.degree = dim, degree
+    cp = np.ascontiguousarray(cell_points, dtype=np.int64)
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    fb = np.ascontiguousarray(face_bc, dtype=np.int8)
+    if cp.ndim != 2 or cp.shape[1] != (int(map_degree) + 1) ** dim or pts.ndim != 2 or pts.shape[1] != dim \
+            or fb.shape != (cp.shape[0], 2 * dim):
+        raise ValueError("unstructured mesh arrays of the wrong shape")
+    for e in range(3):
+        m.cells[e] = 1
+        m.hi[e] = 1.0
+    for f in range(6):
+        m.bc[f] = GDG_BC_OUTFLOW
+        if bstate is not None and f < len(bstate) and bstate[f] is not None:
+            for q, v in enumerate(bstate[f]):
+                m.bc_state[f][q] = float(v)
+    m.map_degree = int(map_degree)
+    m.ucells, m.npoints = cp.shape[0], pts.shape[0]
+    m._keep = (cp, pts, fb)
+    m.vertices = pts.ctypes.data_as(C.POINTER(C.c_double))
+    m.ucell_points = cp.ctypes.data_as(C.POINTER(C.c_int64))
+    m.uface_bc = fb.ctypes.data_as(C.POINTER(C.c_int8))
+    return m
+
+
 # -- the C entry points -------------------------------------------------------
 def gdg_default_params(degree: int) -> gdg_params:
     p = gdg_params()
@@ -306,11 +337,13 @@ class Solver:
 
     def __init__(self, dim, degree, cells, lo, hi, bc, params: gdg_params | None = None,
                  device="cuda:0", stream=None, bstate=None, vortex=None, vertices=None, bc_cells=None,
-                 map_degree=1):
+                 map_degree=1, desc=None):
         import torch
         self.torch = torch
         self.dim, self.m = dim, dim + 2
-        self.mesh = mesh_desc(dim, degree, cells, lo, hi, bc, bstate, vortex, vertices, bc_cells, map_degree)
+        # desc: a ready descriptor (an unstructured mesh's, umesh_desc)
+        self.mesh = desc if desc is not None else mesh_desc(dim, degree, cells, lo, hi, bc, bstate, vortex,
+                                                            vertices, bc_cells, map_degree)
         self.params = params if params is not None else gdg_default_params(degree)
         self.device = torch.device(device)
         nbytes = gdg_workspace_bytes(self.mesh, self.params)
@@ -327,6 +360,11 @@ class Solver:
                    bstate=getattr(ms, "bstate", None), vortex=getattr(ms, "vortex", None),
                    vertices=getattr(ms, "vertices", None), bc_cells=getattr(ms, "bc_cells", None),
                    map_degree=getattr(ms, "map_degree", 1), **kw)
+
+    @classmethod
+    def unstructured(cls, dim, degree, cell_points, points, face_bc, params=None, bstate=None, map_degree=1, **kw):
+        desc = umesh_desc(dim, degree, cell_points, points, face_bc, bstate, map_degree)
+        return cls(dim, degree, None, None, None, None, params, desc=desc, **kw)
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -256,3 +256,26 @@ def test_curved_cells_validated():
         bad.map_degree = g
         with pytest.raises(gdg.GdgError):
             gdg.gdg_workspace_bytes(bad, p)
+
+
+def test_unstructured_meshes_validated():
+    """Host-side checks of unstructured meshes: point ids inside the point
+    list, dim 2 or 3, the binding's array shapes."""
+    p = gdg.gdg_default_params(1)
+    cp, P, fb = W.triangle_three_blocks(2)
+    fb[:] = 0
+    m = gdg.umesh_desc(2, 1, cp, P, fb)
+    assert gdg.gdg_workspace_bytes(m, p) > 0
+    bad = cp.copy()
+    bad[3, 1] = len(P)
+    with pytest.raises(gdg.GdgError):
+        gdg.gdg_workspace_bytes(gdg.umesh_desc(2, 1, bad, P, fb), p)
+    bad[3, 1] = -1
+    with pytest.raises(gdg.GdgError):
+        gdg.gdg_workspace_bytes(gdg.umesh_desc(2, 1, bad, P, fb), p)
+    with pytest.raises(ValueError):
+        gdg.umesh_desc(2, 1, cp[:, :3], P, fb)
+    m1 = gdg.umesh_desc(2, 1, cp, P, fb)
+    m1.dim = 1
+    with pytest.raises(gdg.GdgError):
+        gdg.gdg_workspace_bytes(m1, p)
