@@ -71,6 +71,8 @@ def lib():
         L.or_create_mapped.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_long), _DP, C.POINTER(C.c_int)]
         L.or_create_curved.restype = C.c_void_p
         L.or_create_curved.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_long), _DP, C.POINTER(C.c_int), C.c_int]
+        L.or_create_cg.restype = C.c_void_p
+        L.or_create_cg.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_long), _DP, _DP, C.POINTER(C.c_int)]
         L.or_create_unstructured.restype = C.c_void_p
         L.or_create_unstructured.argtypes = [C.c_int, C.c_int, C.c_long, C.POINTER(C.c_long), C.c_long, _DP, C.c_int,
                                              C.POINTER(C.c_byte)]
@@ -138,7 +140,7 @@ class Mesh:
     """Uniform Cartesian DG Q_k mesh with the stencil of Sec. 2.3."""
 
     def __init__(self, dim, degree, cells, lo, hi, bc, bstate=None, vortex=None, vertices=None, bc_cells=None,
-                 map_degree=1):
+                 map_degree=1, continuous=False):
         """bc: kinds per box face 2*axis+side (0 periodic, 1 outflow, 2 slip,
         3 Dirichlet, 4 supersonic in/outflow, 5 sub- and supersonic
         in/outflow).  bstate: per face the conserved Dirichlet data U^d of
@@ -149,7 +151,9 @@ class Mesh:
         (multilinearly mapped) cells; lo and hi are then ignored.
         map_degree 2: curved cells, vertices then holds the lattice of
         2 n_e + 1 points per axis (corners, edge and face midpoints, centres)
-        of quadratic cell maps.  bc_cells:
+        of quadratic cell maps.  continuous: continuous Q_k elements on the
+        box (App. B): one dof per lattice node, c_ij and c_i^d of
+        eq. cijcidefCg; the low-order scheme only.  bc_cells:
         a kind per boundary cell face (kinds 1-5): for each non-periodic box
         face in order, its cells lexicographically over the other axes, the
         lowest axis fastest; data kinds take that box face's data."""
@@ -169,6 +173,8 @@ class Mesh:
             assert vx.shape == (nv, dim), (vx.shape, nv, dim)
             self._vx = vx
             self._h = L.or_create_curved(dim, degree, c, _dp(vx), b, int(map_degree))
+        elif continuous:
+            self._h = L.or_create_cg(dim, degree, c, lo_, hi_, b)
         else:
             self._h = L.or_create(dim, degree, c, lo_, hi_, b)
         if not self._h:

@@ -86,6 +86,11 @@ typedef struct {
    * NULL: the uniform box lo .. hi. */
   double *vx;
   int mapdeg;    /* general cells: degree g of the cell map (1 multilinear, 2 quadratic) */
+  /* continuous elements (App. B): one dof per lattice node of the box, gn[e]
+   * nodes per axis, their coordinates */
+  int cg;
+  long gn[3];
+  double *cgx;
   /* unstructured meshes: the (mapdeg+1)^dim point ids of each cell, the
    * neighbour across each local face (-1: boundary) and its local face, and
    * per boundary face its kind | data face << 3 */
@@ -511,7 +516,7 @@ void or_destroy(or_setup *S) {
   if (!S) return;
   free(S->rowptr); free(S->col); free(S->c); free(S->mij); free(S->kind); free(S->mi);
   free(S->bptr); free(S->bface); free(S->bkind); free(S->bc_c); free(S->vx);
-  free(S->ucp); free(S->unb); free(S->unf); free(S->ubc);
+  free(S->ucp); free(S->unb); free(S->unf); free(S->ubc); free(S->cgx);
   free(S);
 }
 
@@ -709,6 +714,189 @@ or_setup *or_create_unstructured(int dim, int deg, long ncells, const long *cell
   free(fk);
   if (bad) { or_destroy(S); return NULL; }
   return finish_general(S);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Continuous elements (App. B): the same graph scheme on the dofs of a       */
+/* continuous Q_k space, with c_ij and c_i^d of eq. cijcidefCg.               */
+/* ------------------------------------------------------------------------ */
+
+/* Global node of local node a of cell K: index k K_e + a_e per axis (modulo
+ * the axis's node count on a periodic axis), x fastest. */
+static long cg_node(const or_setup *S, long K, int a) {
+  long ki[3];
+  int ai[3];
+  cell_multi(S, K, ki);
+  local_multi(S, a, ai);
+  long g = 0, st = 1;
+  for (int e = 0; e < S->dim; ++e) {
+    long ge = S->deg * ki[e] + ai[e];
+    if (ge >= S->gn[e]) ge -= S->gn[e];  /* periodic wrap */
+    g += ge * st;
+    st *= S->gn[e];
+  }
+  return g;
+}
+
+/* c_ij of eq. cijcidefCg from its definition: the volume integrals over
+ * every cell that holds both nodes, minus half the boundary integral of
+ * phi_j phi_i n over the box faces (not periodic) that hold both. */
+static void literal_cij_cg(const or_setup *S, long i, long j, double *out) {
+  const int dim = S->dim, nloc = S->nloc;
+  for (int e = 0; e < dim; ++e) out[e] = 0.0;
+  for (long K = 0; K < S->ncells; ++K) {
+    int a = -1, b = -1;
+    for (int q = 0; q < nloc; ++q) {
+      long g = cg_node(S, K, q);
+      if (g == i) a = q;
+      if (g == j) b = q;
+    }
+    if (a < 0 || b < 0) continue;
+    for (int e = 0; e < dim; ++e) {
+      pair_arg pr = {a, b, e};
+      out[e] += cell_integral(S, 1, pr);
+    }
+    long ki[3];
+    int ai[3], bi[3];
+    cell_multi(S, K, ki);
+    local_multi(S, a, ai);
+    local_multi(S, b, bi);
+    for (int f = 0; f < 2 * dim; ++f) {
+      int e = f / 2, side = f % 2;
+      if (S->bc[f] == OR_BC_PERIODIC) continue;
+      if (ki[e] != (side ? S->n[e] - 1 : 0)) continue;       /* a cell face on box face f */
+      if (ai[e] != side * S->deg || bi[e] != side * S->deg) continue;
+      out[e] -= 0.5 * (side ? 1.0 : -1.0) * face_integral(S, f, a, b, 1);
+    }
+  }
+}
+
+or_setup *or_create_cg(int dim, int deg, const long *cells, const double *lo, const double *hi, const int *bc) {
+  or_setup *S = setup_init(dim, deg, cells, lo, hi, bc);
+  if (!S) return NULL;
+  S->cg = 1;
+  long N = 1;
+  for (int e = 0; e < 3; ++e) {
+    S->gn[e] = e < dim ? deg * S->n[e] + (S->bc[2 * e] == OR_BC_PERIODIC ? 0 : 1) : 1;
+    /* a periodic axis needs 2k + 1 distinct nodes for a node's neighbours */
+    if (e < dim && S->bc[2 * e] == OR_BC_PERIODIC && S->gn[e] < 2 * deg + 1) { free(S); return NULL; }
+    N *= S->gn[e];
+  }
+  S->ndofs = N;
+  const int nloc = S->nloc, W = 1;
+  (void)W;
+  /* the stencil of node i: the nodes of every cell that holds i, found by
+   * offsets -k .. k per axis (dense per row), then compacted */
+  int span = 1;
+  for (int e = 0; e < dim; ++e) span *= 2 * deg + 1;
+  double *cc = (double *)calloc((size_t)N * span * dim, sizeof(double));
+  double *mm = (double *)calloc((size_t)N * span, sizeof(double));
+  char *used = (char *)calloc((size_t)N * span, 1);
+  double *cb = (double *)calloc((size_t)N * 2 * dim * dim, sizeof(double));
+  char *onb = (char *)calloc((size_t)N * 2 * dim, 1);
+  S->mi = (double *)calloc(N, sizeof(double));
+  S->cgx = (double *)malloc(N * dim * sizeof(double));
+  for (long K = 0; K < S->ncells; ++K) {
+    long ki[3];
+    cell_multi(S, K, ki);
+    for (int a = 0; a < nloc; ++a) {
+      const long i = cg_node(S, K, a);
+      int ai[3];
+      local_multi(S, a, ai);
+      pair_arg pa = {a, 0, 0};
+      S->mi[i] += cell_integral(S, 2, pa);
+      for (int e = 0; e < dim; ++e) S->cgx[i * dim + e] = S->lo[e] + (ki[e] + S->xg[ai[e]]) * S->h[e];
+      for (int b = 0; b < nloc; ++b) {
+        int bi[3], off = 0, st = 1;
+        local_multi(S, b, bi);
+        for (int e = 0; e < dim; ++e) { off += (bi[e] - ai[e] + deg) * st; st *= 2 * deg + 1; }
+        used[(size_t)i * span + off] = 1;
+        for (int e = 0; e < dim; ++e) {
+          pair_arg pr = {a, b, e};
+          cc[((size_t)i * span + off) * dim + e] += cell_integral(S, 1, pr);
+        }
+        pair_arg pm = {a, b, 0};
+        mm[(size_t)i * span + off] += cell_integral(S, 0, pm);
+      }
+      /* boundary terms of the cell faces on box faces (App. B) */
+      for (int f = 0; f < 2 * dim; ++f) {
+        int e = f / 2, side = f % 2;
+        if (S->bc[f] == OR_BC_PERIODIC) continue;
+        if (ki[e] != (side ? S->n[e] - 1 : 0) || ai[e] != side * deg) continue;
+        const double n = side ? 1.0 : -1.0;
+        onb[(size_t)i * 2 * dim + f] = 1;
+        cb[((size_t)i * 2 * dim + f) * dim + e] += 0.5 * n * face_integral(S, f, a, -1, 1);
+        for (int b = 0; b < nloc; ++b) {
+          int bi[3], off = 0, st = 1;
+          local_multi(S, b, bi);
+          if (bi[e] != side * deg) continue;
+          for (int d = 0; d < dim; ++d) { off += (bi[d] - ai[d] + deg) * st; st *= 2 * deg + 1; }
+          cc[((size_t)i * span + off) * dim + e] -= 0.5 * n * face_integral(S, f, a, b, 1);
+        }
+      }
+    }
+  }
+  /* CSR: the used offsets in offset order; boundary parts per box face */
+  S->rowptr = (long *)calloc(N + 1, sizeof(long));
+  S->bptr = (long *)calloc(N + 1, sizeof(long));
+  for (long i = 0; i < N; ++i) {
+    long g = 0, nb = 0;
+    for (int o = 0; o < span; ++o) g += used[(size_t)i * span + o];
+    for (int f = 0; f < 2 * dim; ++f) nb += onb[(size_t)i * 2 * dim + f];
+    S->rowptr[i + 1] = S->rowptr[i] + g;
+    S->bptr[i + 1] = S->bptr[i] + nb;
+  }
+  long nnz = S->rowptr[N], nbt = S->bptr[N];
+  S->col = (long *)malloc(nnz * sizeof(long));
+  S->c = (double *)malloc(nnz * dim * sizeof(double));
+  S->mij = (double *)malloc(nnz * sizeof(double));
+  S->kind = (int *)malloc(nnz * sizeof(int));
+  S->bface = (int *)malloc((nbt + 1) * sizeof(int));
+  S->bkind = (int *)malloc((nbt + 1) * sizeof(int));
+  S->bc_c = (double *)malloc((nbt + 1) * dim * sizeof(double));
+  for (long i = 0; i < N; ++i) {
+    long gi[3], r = i;
+    for (int e = 0; e < dim; ++e) { gi[e] = r % S->gn[e]; r /= S->gn[e]; }
+    long q = S->rowptr[i];
+    for (int o = 0; o < span; ++o) {
+      if (!used[(size_t)i * span + o]) continue;
+      long j = 0, st = 1;
+      int rr = o;
+      for (int e = 0; e < dim; ++e) {
+        long ge = gi[e] + rr % (2 * deg + 1) - deg;
+        rr /= 2 * deg + 1;
+        if (ge < 0) ge += S->gn[e];
+        if (ge >= S->gn[e]) ge -= S->gn[e];
+        j += ge * st;
+        st *= S->gn[e];
+      }
+      S->col[q] = j;
+      for (int e = 0; e < dim; ++e) S->c[q * dim + e] = cc[((size_t)i * span + o) * dim + e];
+      S->mij[q] = mm[(size_t)i * span + o];
+      S->kind[q] = OR_KIND_CELL;
+      ++q;
+    }
+    long b = S->bptr[i];
+    for (int f = 0; f < 2 * dim; ++f) {
+      if (!onb[(size_t)i * 2 * dim + f]) continue;
+      for (int e = 0; e < dim; ++e) S->bc_c[b * dim + e] = cb[((size_t)i * 2 * dim + f) * dim + e];
+      S->bface[b] = f;
+      S->bkind[b] = S->bc[f];
+      ++b;
+    }
+  }
+  /* reading R3: c_ji is stored as exactly -c_ij, from the lower index */
+  for (long i = 0; i < N; ++i)
+    for (long q = S->rowptr[i]; q < S->rowptr[i + 1]; ++q) {
+      const long j = S->col[q];
+      if (j == i) { for (int e = 0; e < dim; ++e) S->c[q * dim + e] = 0.0; continue; }
+      if (j > i) continue;
+      for (long p = S->rowptr[j]; p < S->rowptr[j + 1]; ++p)
+        if (S->col[p] == i)
+          for (int e = 0; e < dim; ++e) S->c[q * dim + e] = -S->c[p * dim + e];
+    }
+  free(cc); free(mm); free(used); free(cb); free(onb);
+  return S;
 }
 
 static or_setup *setup_init(int dim, int deg, const long *cells, const double *lo, const double *hi, const int *bc) {
@@ -970,7 +1158,11 @@ void or_node_coords(const or_setup *S, double *xyz) {
 }
 
 /* literal c_ij for both orders (pins Lemma PropSkew without the R3 reading) */
-void or_literal_cij(const or_setup *S, long i, long j, double *out) { literal_cij(S, i, j, out); }
+static void literal_cij_cg(const or_setup *S, long i, long j, double *out);
+void or_literal_cij(const or_setup *S, long i, long j, double *out) {
+  if (S->cg) literal_cij_cg(S, i, j, out);
+  else literal_cij(S, i, j, out);
+}
 
 /* ------------------------------------------------------------------------ */
 /* Euler physics (Sec. 2.2)                                                   */
@@ -1140,6 +1332,10 @@ void or_riemann_sample(double g, double rl, double ul, double pl, double rr, dou
  * Returns 0 or -4. */
 /* Node coordinates x_i. */
 static void node_x(const or_setup *S, long i, double *x) {
+  if (S->cg) {
+    for (int e = 0; e < S->dim; ++e) x[e] = S->cgx[i * S->dim + e];
+    return;
+  }
   long ki[3];
   int ai[3];
   cell_multi(S, i / S->nloc, ki);

@@ -1,0 +1,108 @@
+"""Pins of the oracle's continuous-element variant (App. B): one dof per
+lattice node of the box, c_ij = int grad phi_j phi_i - 1/2 int_{dOmega}
+phi_j phi_i n and c_i^d = 1/2 int_{dOmega} phi_i n (eq. cijcidefCg), with
+the low-order scheme of eq. cijdijscheme - dij_low_order.
+
+* 1D Q1 by hand: c_{i,i+1} = 1/2, c_{i,i-1} = -1/2, c_ii = 0, boundary parts
+  -1/2 and +1/2, lumped masses h/2 at the ends and h inside.
+* App. B's skew-symmetry proposition (c_ij and c_ji each from the definition)
+  and its partition of unity sum_j c_ij + c_i^d = 0 row by row, the masses
+  summing to |Omega| (2D Q1-Q3, 3D Q1-Q2, periodic and wall axes).
+* App. B's total balance: mass and energy kept to rounding inside slip walls,
+  every component on a periodic box.
+* Sod: first-order convergence to the exact solution.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2402_04514_amd import workloads as W
+
+from test_oracle_scheme import _l1
+
+G = 1.4
+
+
+def test_hand_values_1d_q1(oracle):
+    M = oracle.Mesh(1, 1, (4,), (0.0,), (1.0,), (1, 1), continuous=True)
+    rp, col, cc, mij, _ = M.csr()
+    bp, bf, bcc = M.boundary()
+    assert M.ndofs == 5
+    for i in range(5):
+        for q in range(rp[i], rp[i + 1]):
+            j = col[q]
+            assert cc[q, 0] == {0: 0.0, 1: 0.5, -1: -0.5}[j - i]
+    assert np.array_equal(bcc[:, 0], [-0.5, 0.5]) and np.array_equal(bp, [0, 1, 1, 1, 1, 2])
+    assert np.allclose(M.lumped(), [0.125, 0.25, 0.25, 0.25, 0.125], rtol=0, atol=1e-16)
+    assert np.allclose(M.coords()[:, 0], np.linspace(0, 1, 5), rtol=0, atol=1e-16)
+
+
+MESHES = {
+    "2d_q1": (2, 1, (5, 4), (1, 2, 0, 0)), "2d_q2": (2, 2, (4, 3), (2, 2, 1, 1)),
+    "2d_q3": (2, 3, (3, 3), (0, 0, 2, 1)), "3d_q1": (3, 1, (3, 3, 3), (1, 2, 2, 1, 0, 0)),
+    "3d_q2": (3, 2, (2, 2, 2), (2, 1, 1, 2, 2, 1)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MESHES))
+def test_skew_symmetry_and_partition_of_unity(oracle, name):
+    dim, k, cells, bc = MESHES[name]
+    lo, hi = (0.0,) * dim, tuple(1.0 + 0.25 * e for e in range(dim))
+    M = oracle.Mesh(dim, k, cells, lo, hi, bc, continuous=True)
+    rp, col, cc, mij, _ = M.csr()
+    bp, bf, bcc = M.boundary()
+    N = M.ndofs
+    rows = np.repeat(np.arange(N), np.diff(rp))
+    part = np.zeros((N, dim))
+    np.add.at(part, rows, cc)
+    np.add.at(part, np.repeat(np.arange(N), np.diff(bp)), bcc)
+    scale = np.abs(cc).max()
+    assert np.abs(part).max() < 1e-13 * scale, "partition of unity"
+    assert M.lumped().sum() == pytest.approx(np.prod(np.array(hi) - np.array(lo)), rel=1e-13)
+    assert np.all(M.lumped() > 0)
+    rng = np.random.default_rng(1)
+    for q in rng.choice(len(col), size=min(200, len(col)), replace=False):
+        i, j = rows[q], col[q]
+        cij, cji = M.literal_cij(i, j), M.literal_cij(j, i)
+        assert np.abs(cij + cji).max() < 1e-13 * scale, "skew symmetry"
+        assert np.abs(cc[q] - cij).max() < 1e-13 * scale
+
+
+def _smooth(x, dim, seed=5):
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0, 2 * np.pi, size=(4, dim))
+    f = lambda r: np.sum(np.sin(2 * np.pi * x + ph[r]), axis=1) / dim
+    vel = np.stack([0.3 * f(1 + (e % 2)) for e in range(dim)])
+    return W.to_conserved(1.0 + 0.3 * f(0), vel, 1.0 + 0.4 * f(3))
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+@pytest.mark.parametrize("dim,k", [(2, 1), (2, 2), (3, 1)])
+def test_total_balance(oracle, dim, k, periodic):
+    cells = (6, 5, 4)[:dim]
+    bc = (0 if periodic else 2,) * (2 * dim)
+    M = oracle.Mesh(dim, k, cells, (0.0,) * dim, (1.0,) * dim, bc, continuous=True)
+    U = _smooth(M.coords(), dim)
+    op = oracle.params(degree=k, scheme=0)
+    Un, _, n = M.run_to(op, U, 1.0, max_steps=20)
+    assert n == 20
+    mi = M.lumped()
+    for c in (range(dim + 2) if periodic else (0, dim + 1)):
+        t0, t1 = (U[c] * mi).sum(), (Un[c] * mi).sum()
+        assert abs(t1 - t0) <= 1e-13 * np.abs(U[c] * mi).sum()
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_sod_converges_at_first_order(oracle, k):
+    errs = []
+    for n in (100, 200, 400):
+        M = oracle.Mesh(1, k, (n,), (0.0,), (1.0,), (1, 1), continuous=True)
+        x = M.coords()[:, 0]
+        left = x < 0.5
+        U0 = W.to_conserved(np.where(left, 1.0, 0.125), np.zeros((1, len(x))), np.where(left, 1.0, 0.1))
+        U, t, _ = M.run_to(oracle.params(degree=k, scheme=0), U0, 0.2)
+        ex = np.array([oracle.riemann_sample(G, (1, 0, 1), (0.125, 0, 0.1), (xx - 0.5) / 0.2) for xx in x])
+        errs.append(_l1(M, U, W.to_conserved(ex[:, 0], ex[:, 1][None], ex[:, 2])))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(0.6 < r < 1.2 for r in rates), (errs, rates)
