@@ -158,7 +158,17 @@ typedef enum { GDG_FP64 = 0, GDG_MIXED = 1 } gdg_precision;
  * (bc_state) it takes; entries of interior faces must be 0.  cells, lo, hi,
  * bc and bc_cells are not read; cells connect through shared points only, so
  * an O-grid's seam is periodic by construction and a translated periodic
- * image is not expressible.  The arrays are read during gdg_create() only. */
+ * image is not expressible.  The arrays are read during gdg_create() only.
+ *
+ * Continuous elements (App. B): with continuous = 1 the dofs are the nodes of
+ * the continuous Q_degree space on the box (degree * cells[e] + 1 per axis,
+ * degree * cells[e] on a periodic axis, which needs at least 2 degree + 1 of
+ * them; node (I_0, I_1, I_2) at index I_0 + n_0 (I_1 + n_1 I_2)), the graph
+ * of a node is every node of the cells around it, and c_ij and the boundary
+ * parts c_i^d (one per box face the node lies on) are those of
+ * eq. cijcidefCg.  The scheme must be GDG_LOW_ORDER: the high-order update
+ * of continuous elements needs a global mass solve, which the paper does not
+ * give.  Not with vertices, bc_cells, unstructured meshes or vortex data. */
 typedef struct {
   int32_t dim;
   int32_t degree;
@@ -177,6 +187,8 @@ typedef struct {
   int64_t npoints;
   const int64_t *ucell_points;
   const int8_t *uface_bc;
+  int32_t continuous; /* 1: continuous Q_degree elements on the box (App. B), see above */
+  int32_t reserved;   /* 0 */
 } gdg_mesh_desc;
 
 /* Scheme constants.  gdg_default_params() gives the paper's values:
@@ -418,7 +430,7 @@ gdg_status gdg_server_create(const gdg_server_desc *desc, void *dev_pool, size_t
 
 /* Queues a request; U0 is a host state (SoA, (dim+2) * N doubles), copied,
  * as are the mesh's vertices (general cells) and boundary parts.
- * Unstructured meshes are not served (GDG_E_INVALID).
+ * Unstructured meshes and continuous elements are not served (GDG_E_INVALID).
  * GDG_E_INVALID for a description outside the server's class or bad
  * constants, GDG_E_BUDGET if its workspace exceeds the whole pool. */
 gdg_status gdg_server_submit(gdg_server *srv, const gdg_mesh_desc *mesh, const gdg_params *prm, const double *U0,

@@ -805,7 +805,9 @@ or_setup *or_create_cg(int dim, int deg, const long *cells, const double *lo, co
       local_multi(S, a, ai);
       pair_arg pa = {a, 0, 0};
       S->mi[i] += cell_integral(S, 2, pa);
-      for (int e = 0; e < dim; ++e) S->cgx[i * dim + e] = S->lo[e] + (ki[e] + S->xg[ai[e]]) * S->h[e];
+      int wrapped = 0;  /* the last node of a periodic axis is the first: keep the first's position */
+      for (int e = 0; e < dim; ++e) wrapped |= deg * ki[e] + ai[e] >= S->gn[e];
+      for (int e = 0; e < dim && !wrapped; ++e) S->cgx[i * dim + e] = S->lo[e] + (ki[e] + S->xg[ai[e]]) * S->h[e];
       for (int b = 0; b < nloc; ++b) {
         int bi[3], off = 0, st = 1;
         local_multi(S, b, bi);

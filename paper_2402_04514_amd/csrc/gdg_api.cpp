@@ -190,6 +190,24 @@ bool validate(const gdg_mesh_desc *m, const gdg_params *p, std::string *err) {
     *err = "unknown boundary data kind";
     return false;
   }
+  if (m->continuous != 0 && m->continuous != 1) { *err = "continuous must be 0 or 1"; return false; }
+  if (m->continuous) {
+    if (m->vertices || m->bc_cells || m->ucells > 0 || m->data_kind == GDG_DATA_VORTEX) {
+      *err = "continuous elements are built for the uniform box (no vertices, bc_cells, unstructured cells or "
+             "vortex data)";
+      return false;
+    }
+    if (p->scheme != GDG_LOW_ORDER) {
+      *err = "continuous elements take the low-order scheme (their high-order update needs a global mass "
+             "solve)";
+      return false;
+    }
+    for (int e = 0; e < m->dim; ++e)
+      if (m->bc[2 * e] == GDG_BC_PERIODIC && m->degree * m->cells[e] < 2 * m->degree + 1) {
+        *err = "a periodic axis of continuous elements needs at least 2 degree + 1 nodes";
+        return false;
+      }
+  }
   if (m->map_degree < 0 || m->map_degree > 2 || (m->map_degree == 2 && !m->vertices)) {
     *err = "map_degree must be 0 or 1 (multilinear), or 2 (quadratic, with vertices)";
     return false;
@@ -256,6 +274,18 @@ Layout layout(const gdg_mesh_desc *m, const gdg_params *p) {
   if (m->ucells > 0) L.ncells = m->ucells;
   L.N = L.ncells * L.nloc;
   L.nblocks = (L.ncells + L.cpb - 1) / L.cpb;
+  if (m->continuous) {
+    // one row per node of the continuous space, full wavefronts of rows; a
+    // row holds the (2k+1)^d nodes around it and a part per box face
+    int64_t gn[3];
+    cg_nodes(m, gn);
+    L.N = gn[0] * gn[1] * gn[2];
+    L.R = kBlockThreads;
+    int span = 1;
+    for (int e = 0; e < m->dim; ++e) span *= 2 * m->degree + 1;
+    L.W = span + m->dim;
+    L.nblocks = (L.N + L.R - 1) / L.R;
+  }
   L.nslots = L.nblocks * L.W * L.R;
   const size_t N = (size_t)L.N, S = (size_t)L.nslots, d = (size_t)m->dim, M = (size_t)L.M;
   size_t o = 0;
@@ -264,6 +294,7 @@ Layout layout(const gdg_mesh_desc *m, const gdg_params *p) {
   L.off_ctl = take(sizeof(Ctl));
   L.off_col = take(S * 4);
   L.off_c = take(S * d * (p->precision == GDG_MIXED ? 4 : 8));
+  const bool host_tables = m->vertices || m->continuous;
   L.off_meta = take(S);
   L.off_kscale = take(N * 8);
   for (int k = 0; k < 3; ++k) L.off_U[k] = take(M * N * 8);
@@ -282,8 +313,8 @@ Layout layout(const gdg_mesh_desc *m, const gdg_params *p) {
   L.nbcc = 0;
   if (m->bc_cells) part_offsets(m, L.bcc_off, &L.nbcc);
   if (m->bc_cells) L.off_bcc = take((size_t)L.nbcc);
-  if (m->vertices) {
-    const size_t blk = (size_t)L.ncells * L.nloc * L.nloc * 8;
+  if (host_tables) {
+    const size_t blk = m->continuous ? 0 : (size_t)L.ncells * L.nloc * L.nloc * 8;
     L.off_mrow = take(N * 8);
     L.off_hprow = take(N * 8);
     L.off_relrow = take(N * 8);
@@ -504,7 +535,7 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   A.cpb = L.cpb;
   A.tiled = 0;
   A.t_nbx = A.t_ny = A.t_nz = A.t_tx = A.t_ty = 1;
-  if (mesh->dim == 3 && mesh->ucells == 0 && mesh->cells[0] % L.cpb == 0) {
+  if (mesh->dim == 3 && mesh->ucells == 0 && !mesh->continuous && mesh->cells[0] % L.cpb == 0) {
     // tiles one row block wide in x and ty cell rows in y, ty the largest
     // divisor of ny up to kTileRows (measured on the 128^3 blast: 1 x 32 and
     // 1 x 64 beat the 16 x 8 tiles by 5 %)
@@ -572,8 +603,9 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   A.fsum = (double *)(ws + L.off_fsum);
   A.red = (double *)(ws + L.off_red);
   A.cnt = (unsigned long long *)(ws + L.off_cnt);
-  A.general = mesh->vertices ? 1 : 0;
-  A.ustruct = mesh->ucells > 0 ? 1 : 0;
+  A.general = mesh->vertices || mesh->continuous ? 1 : 0;
+  A.ustruct = mesh->ucells > 0 || mesh->continuous ? 1 : 0;
+  A.cg = mesh->continuous ? 1 : 0;
   if (A.general) {
     A.mrow = (const double *)(ws + L.off_mrow);
     A.hprow = (const double *)(ws + L.off_hprow);
@@ -592,7 +624,15 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   // general cells: per-row and per-cell tables from the map, and the stencil
   // coefficients that replace those of the fill kernel
   MappedSetup G;
-  if (A.general) {
+  if (A.cg) {
+    if (!build_cg(&ctx->mesh, prm, L.R, L.W, L.nslots, &G, &err)) {
+      g_create_err = err;
+      delete T;
+      delete ctx;
+      return GDG_E_INVALID;
+    }
+    A.vol = vol = G.vol;
+  } else if (A.general) {
     if (!build_mapped(&ctx->mesh, prm, ctx->vx.data(), *T, L.R, L.W, L.nslots, &G, &err)) {
       g_create_err = err;
       delete T;
@@ -715,6 +755,24 @@ gdg_status gdg_node_coords(const gdg_ctx *ctx, double *xyz) {
   const double r5 = 0.5 / std::sqrt(5.0);
   const double xg2[3] = {0.0, 0.5, 1.0}, xg1[2] = {0.0, 1.0}, xg3[4] = {0.0, 0.5 - r5, 0.5 + r5, 1.0};
   const double *xg = m.degree == 1 ? xg1 : (m.degree == 2 ? xg2 : xg3);
+  if (m.continuous) {
+    // node (I_0, I_1, I_2): cell I_e / k (the last node: the last cell's end), local node I_e % k
+    int64_t gn[3];
+    cg_nodes(&m, gn);
+    for (int64_t i = 0; i < ctx->A.N; ++i) {
+      int64_t r = i;
+      for (int e = 0; e < d; ++e) {
+        const int64_t I = r % gn[e];
+        r /= gn[e];
+        int64_t K = I / m.degree;
+        int a = (int)(I % m.degree);
+        if (K == m.cells[e]) K -= 1, a = m.degree;
+        const double h = (m.hi[e] - m.lo[e]) / (double)m.cells[e];
+        xyz[i * d + e] = m.lo[e] + ((double)K + xg[a]) * h;
+      }
+    }
+    return GDG_OK;
+  }
   if (m.vertices) {
     // x_i = F_K(xi_a): the cell's map at the node's reference point
     for (int64_t K = 0; K < ctx->A.ncells; ++K) {

@@ -173,6 +173,7 @@ struct KArgs {
   // (mlump, hpk, relax, mblk, minv) are per row and per cell instead
   int32_t general;
   int32_t ustruct;      // unstructured: the host wrote col, meta and c (the fill kernel only sets boundary data)
+  int32_t cg;           // continuous elements: rows are global nodes in blocks of R, no cell solve
   const double *mrow;   // m_i
   const double *hprow;  // c_k hhat_i^{p_k}
   const double *relrow; // c_r hhat_i^{p_r}
@@ -244,6 +245,13 @@ struct MappedSetup {
 };
 bool build_mapped(const gdg_mesh_desc *m, const gdg_params *p, const double *vx, const RefTables &T, int R, int W,
                   int64_t nslots, MappedSetup *out, std::string *err);
+// Continuous elements on the box (gdg_cg.cpp): per-row tables, c_ij, c_i^d
+// and the whole ELL stencil (col, meta, c, kappa) for R rows per block and W
+// slots per row.
+bool build_cg(const gdg_mesh_desc *m, const gdg_params *p, int R, int W, int64_t nslots, MappedSetup *out,
+              std::string *err);
+// Node counts per axis of the continuous space of a box mesh.
+void cg_nodes(const gdg_mesh_desc *m, int64_t *gn);
 // Degree of the cell maps (1 multilinear, 2 quadratic) of a mesh of general cells.
 int map_degree(const gdg_mesh_desc *m);
 // The (g+1)^dim points of cell K's map of degree g (point v: digits q_e of v

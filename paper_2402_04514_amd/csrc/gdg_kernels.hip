@@ -1115,7 +1115,10 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
   }
   __syncthreads();
   double du[M];
-  if (active) {
+  for (int q = 0; q < M; ++q) du[q] = 0.0;
+  // continuous elements run the low-order scheme only: no cell solve (their
+  // rows are nodes, not whole cells)
+  if (active && !A.cg) {
   // eq. HighScheme: M_K dU^H_K = tau r^H_K for the cell of row i, from LDS
   const int cellbase = lane - a;
   // A cell whose rows are all quiet has a zero residual and dU^H = 0 in every

@@ -426,8 +426,8 @@ gdg_status gdg_server_create(const gdg_server_desc *desc, void *dev_pool, size_t
 gdg_status gdg_server_submit(gdg_server *s, const gdg_mesh_desc *mesh, const gdg_params *prm, const double *U0,
                              double t_final, uint64_t *ticket) {
   if (!s || !mesh || !prm || !U0 || !ticket) return GDG_E_INVALID;
-  if (mesh->ucells > 0) {
-    s->err = "unstructured meshes are not served";
+  if (mesh->ucells > 0 || mesh->continuous) {
+    s->err = "unstructured meshes and continuous elements are not served";
     return GDG_E_INVALID;
   }
   if (mesh->dim != s->d.dim || mesh->degree != s->d.degree || prm->precision != s->d.precision) {

@@ -43,7 +43,8 @@ class gdg_mesh_desc(C.Structure):
                 ("bc_state", (C.c_double * 5) * 6), ("data_kind", C.c_int32), ("map_degree", C.c_int32),
                 ("vortex", C.c_double * 6), ("vertices", C.POINTER(C.c_double)),
                 ("bc_cells", C.POINTER(C.c_int8)), ("ucells", C.c_int64), ("npoints", C.c_int64),
-                ("ucell_points", C.POINTER(C.c_int64)), ("uface_bc", C.POINTER(C.c_int8))]
+                ("ucell_points", C.POINTER(C.c_int64)), ("uface_bc", C.POINTER(C.c_int8)),
+                ("continuous", C.c_int32), ("reserved", C.c_int32)]
 
 
 class gdg_params(C.Structure):
@@ -139,7 +140,7 @@ def _check(st, ctx=None):
 
 
 def mesh_desc(dim, degree, cells, lo, hi, bc, bstate=None, vortex=None, vertices=None,
-              bc_cells=None, map_degree=1) -> gdg_mesh_desc:
+              bc_cells=None, map_degree=1, continuous=False) -> gdg_mesh_desc:
     """bstate: per face the conserved Dirichlet data of the DIRICHLET,
     SUPERSONIC and INOUTFLOW kinds (None, or None entries, elsewhere); vortex:
     (beta, x0_1, x0_2, u_1, u_2, gamma) to take that data from the isentropic
@@ -152,6 +153,7 @@ def mesh_desc(dim, degree, cells, lo, hi, bc, bstate=None, vortex=None, vertices
     lexicographically over the other axes, the lowest axis fastest)."""
     m = gdg_mesh_desc()
     m.dim, m.degree = dim, degree
+    m.continuous = 1 if continuous else 0
     for e in range(3):
         m.cells[e] = int(cells[e]) if e < dim else 1
         m.lo[e] = float(lo[e]) if e < dim else 0.0
@@ -337,13 +339,13 @@ class Solver:
 
     def __init__(self, dim, degree, cells, lo, hi, bc, params: gdg_params | None = None,
                  device="cuda:0", stream=None, bstate=None, vortex=None, vertices=None, bc_cells=None,
-                 map_degree=1, desc=None):
+                 map_degree=1, desc=None, continuous=False):
         import torch
         self.torch = torch
         self.dim, self.m = dim, dim + 2
         # desc: a ready descriptor (an unstructured mesh's, umesh_desc)
         self.mesh = desc if desc is not None else mesh_desc(dim, degree, cells, lo, hi, bc, bstate, vortex,
-                                                            vertices, bc_cells, map_degree)
+                                                            vertices, bc_cells, map_degree, continuous)
         self.params = params if params is not None else gdg_default_params(degree)
         self.device = torch.device(device)
         nbytes = gdg_workspace_bytes(self.mesh, self.params)

@@ -1,0 +1,110 @@
+"""GPU parity for continuous elements (App. B): the low-order graph scheme
+on the nodes of a continuous Q_k space with the c_ij and c_i^d of
+eq. cijcidefCg, through the C-ABI, against the oracle's continuous mesh on
+the same seeded inputs, element by element: the stage (tau, U^L) at 1e-11 of
+each component's scale, ten SSP-RK3 steps at 1e-10; totals kept inside slip
+walls.
+"""
+import numpy as np
+import pytest
+
+from paper_2402_04514_amd import gdg
+from paper_2402_04514_amd import workloads as W
+
+from test_gpu_parity import _close
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print("[gpu-cg] " + msg, flush=True)
+
+
+def _smooth(x, dim, seed=5):
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0, 2 * np.pi, size=(4, dim))
+    f = lambda r: np.sum(np.sin(2 * np.pi * x + ph[r]), axis=1) / dim
+    vel = np.stack([0.3 * f(1 + (e % 2)) for e in range(dim)])
+    return W.to_conserved(1.0 + 0.3 * f(0), vel, 1.0 + 0.4 * f(3))
+
+
+def _quadrant(x, dim, seed=240204514):
+    q = np.zeros(len(x), dtype=int)
+    for e in range(min(dim, 2)):
+        q += (x[:, e] >= 0.5).astype(int) << e
+    st = np.array(W.quadrant_states(seed))
+    vel = np.zeros((dim, len(x)))
+    vel[0] = st[q, 1]
+    if dim > 1:
+        vel[1] = st[q, 2]
+    return W.to_conserved(st[q, 0], vel, st[q, 3])
+
+
+DATA = tuple(W.to_conserved(np.array([1.2]), np.array([[0.4], [0.1]]), np.array([1.5]))[:, 0])
+
+CASES = {
+    # name: dim, degree, cells, bc, bstate, data
+    "1d_q1_outflow": (1, 1, (40,), (1, 1), None, _quadrant),
+    "1d_q2_periodic": (1, 2, (17,), (0, 0), None, _smooth),
+    "2d_q1_periodic_x_slip_y": (2, 1, (12, 9), (0, 0, 2, 2), None, _quadrant),
+    "2d_q2_dirichlet": (2, 2, (7, 6), (3, 1, 2, 2), (DATA, None, None, None), _smooth),
+    "2d_q3_slip": (2, 3, (5, 4), (2, 2, 2, 2), None, _quadrant),
+    "3d_q1_mixed": (3, 1, (5, 4, 3), (1, 2, 2, 1, 0, 0), None, _smooth),
+    "3d_q2_slip": (3, 2, (3, 3, 2), (2,) * 6, None, _quadrant),
+}
+
+
+def _pair(oracle, name):
+    dim, k, cells, bc, bstate, data = CASES[name]
+    lo, hi = (0.0,) * dim, (1.0,) * dim
+    M = oracle.Mesh(dim, k, cells, lo, hi, bc, bstate=bstate, continuous=True)
+    U = data(M.coords(), dim)
+    p = gdg.gdg_default_params(k)
+    p.scheme = gdg.GDG_LOW_ORDER
+    S = gdg.Solver(dim, k, cells, lo, hi, bc, p, bstate=bstate, continuous=True)
+    S.upload(U)
+    op = oracle.params(degree=k, scheme=0)
+    return U, M, S, op
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_node_coords(oracle, name):
+    _say("coords " + name)
+    U, M, S, op = _pair(oracle, name)
+    assert S.ndofs == M.ndofs
+    assert np.abs(S.coords() - M.coords()).max() < 1e-15
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_stage(oracle, name):
+    _say("stage " + name)
+    U, M, S, op = _pair(oracle, name)
+    out, dg = M.stage(op, U, diag=True)
+    assert S.stage(0.0) == pytest.approx(op.cfl * dg["tau_max"], rel=1e-13)
+    _close(S.field(gdg.GDG_FIELD_UL), dg["UL"], what="U^L")
+    _close(S.download(), out, what="Phi(U)")
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_steps(oracle, name):
+    _say("steps " + name)
+    U, M, S, op = _pair(oracle, name)
+    Uo, t_o, n_o = M.run_to(op, U, 1.0, max_steps=10)
+    st = S.run_to(1.0, max_steps=10)
+    assert st.steps == n_o == 10 and st.t == pytest.approx(t_o, rel=1e-12)
+    _close(S.download(), Uo, tol=1e-10, what="U after 10 steps")
+
+
+@pytest.mark.parametrize("name", ["2d_q3_slip", "3d_q2_slip"])
+def test_total_balance_inside_walls(oracle, name):
+    """App. B's total balance: mass and energy totals from the device kept
+    to rounding over 30 steps inside slip walls."""
+    _say("totals " + name)
+    U, M, S, op = _pair(oracle, name)
+    dim = CASES[name][0]
+    s0 = np.array(S.stats().total[:dim + 2])
+    st = S.run_to(1.0, max_steps=30)
+    s1 = np.array(st.total[:dim + 2])
+    scale = (np.abs(U) * M.lumped()).sum(axis=1)
+    for c in (0, dim + 1):
+        assert abs(s1[c] - s0[c]) <= 1e-13 * scale[c]

@@ -279,3 +279,19 @@ def test_unstructured_meshes_validated():
     m1.dim = 1
     with pytest.raises(gdg.GdgError):
         gdg.gdg_workspace_bytes(m1, p)
+
+
+def test_continuous_elements_validated():
+    """Continuous elements take the low-order scheme on the uniform box, and a
+    periodic axis needs 2 degree + 1 nodes."""
+    p = gdg.gdg_default_params(2)
+    m = gdg.mesh_desc(2, 2, (4, 3), (0, 0), (1, 1), (1,) * 4, continuous=True)
+    with pytest.raises(gdg.GdgError):
+        gdg.gdg_workspace_bytes(m, p)          # the limited scheme
+    p.scheme = gdg.GDG_LOW_ORDER
+    assert gdg.gdg_workspace_bytes(m, p) > 0
+    with pytest.raises(gdg.GdgError):
+        gdg.gdg_workspace_bytes(gdg.mesh_desc(2, 2, (2, 3), (0, 0), (1, 1), (0, 0, 1, 1), continuous=True), p)
+    with pytest.raises(gdg.GdgError):
+        gdg.gdg_workspace_bytes(gdg.mesh_desc(2, 2, (4, 3), (0, 0), (1, 1), (1,) * 4, continuous=True,
+                                              vertices=W.lattice((4, 3), (0, 0), (1, 1))), p)
