@@ -401,14 +401,18 @@ def cpu_baseline(name, budget_s):
     note = ""
     if full.mesh.ndofs > 300_000:  # one oracle step would exceed the budget: same problem, coarser
         f = {2: 8, 3: 4}.get(full.mesh.dim, 1)
-        kw = dict(base, cells=full.mesh.cells[0] // f)
+        if "ntheta" in base:  # the cylinder's O-grid: both axes
+            kw = dict(base, ntheta=base["ntheta"] // f, nr=base["nr"] // f)
+        else:
+            kw = dict(base, cells=full.mesh.cells[0] // f)
         if "cross" in kw:
             kw["cross"] = kw["cross"] // f
         wl = W.CONFIGS[name](**kw)
         note = "; the same problem on %s cells (1/%d per axis) to bound the CPU time" % (
             "x".join(str(c) for c in wl.mesh.cells), f)
     ms = wl.mesh
-    M = oracle.Mesh(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc, bstate=ms.bstate)
+    M = oracle.Mesh(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc, bstate=ms.bstate, vortex=ms.vortex,
+                    vertices=ms.vertices, bc_cells=ms.bc_cells, map_degree=ms.map_degree)
     prm = oracle.params(degree=ms.degree)
 
     def timed(threads, budget):

@@ -295,3 +295,27 @@ def test_continuous_elements_validated():
     with pytest.raises(gdg.GdgError):
         gdg.gdg_workspace_bytes(gdg.mesh_desc(2, 2, (4, 3), (0, 0), (1, 1), (1,) * 4, continuous=True,
                                               vertices=W.lattice((4, 3), (0, 0), (1, 1))), p)
+
+
+def _create_error(m, p):
+    """gdg_create's host-side refusal of a mesh (the checks that run before
+    any device work: a stand-in workspace address is never touched)."""
+    nbytes = gdg.gdg_workspace_bytes(m, p)
+    with pytest.raises(gdg.GdgError) as ei:
+        gdg.gdg_create(m, p, 256, nbytes, 0)
+    assert ei.value.status == gdg.GDG_E_INVALID
+    return str(ei.value)
+
+
+def test_create_refuses_bad_general_and_unstructured_meshes():
+    p = gdg.gdg_default_params(1)
+    cells = (4, 3)
+    V = W.lattice(cells, (0, 0), (1, 1))
+    V[[6, 7]] = V[[7, 6]]  # two points of a row swapped: inverted cells
+    assert "Jacobian" in _create_error(gdg.mesh_desc(2, 1, cells, (0, 0), (1, 1), (1,) * 4, vertices=V), p)
+    cp, P, fb = W.triangle_three_blocks(2)
+    fb[:] = 0  # boundary faces without a kind
+    assert "kind" in _create_error(gdg.umesh_desc(2, 1, cp, P, fb), p)
+    cp3 = np.concatenate([cp, cp[:1]])  # a cell twice: its faces on three cells
+    fb3 = np.full((len(cp3), 4), 2, dtype=np.int8)
+    assert "more than two" in _create_error(gdg.umesh_desc(2, 1, cp3, P, fb3), p)
