@@ -71,6 +71,8 @@ def lib():
         L.or_create_mapped.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_long), _DP, C.POINTER(C.c_int)]
         L.or_create_curved.restype = C.c_void_p
         L.or_create_curved.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_long), _DP, C.POINTER(C.c_int), C.c_int]
+        L.or_create_cg_curved.restype = C.c_void_p
+        L.or_create_cg_curved.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_long), _DP, C.POINTER(C.c_int), C.c_int]
         L.or_create_cg.restype = C.c_void_p
         L.or_create_cg.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_long), _DP, _DP, C.POINTER(C.c_int)]
         L.or_create_unstructured.restype = C.c_void_p
@@ -172,7 +174,10 @@ class Mesh:
             nv = int(np.prod([map_degree * n + 1 for n in self.cells]))
             assert vx.shape == (nv, dim), (vx.shape, nv, dim)
             self._vx = vx
-            self._h = L.or_create_curved(dim, degree, c, _dp(vx), b, int(map_degree))
+            if continuous:
+                self._h = L.or_create_cg_curved(dim, degree, c, _dp(vx), b, int(map_degree))
+            else:
+                self._h = L.or_create_curved(dim, degree, c, _dp(vx), b, int(map_degree))
         elif continuous:
             self._h = L.or_create_cg(dim, degree, c, lo_, hi_, b)
         else:

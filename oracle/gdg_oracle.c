@@ -752,9 +752,15 @@ static void literal_cij_cg(const or_setup *S, long i, long j, double *out) {
       if (g == j) b = q;
     }
     if (a < 0 || b < 0) continue;
-    for (int e = 0; e < dim; ++e) {
-      pair_arg pr = {a, b, e};
-      out[e] += cell_integral(S, 1, pr);
+    if (S->vx) {
+      double t[3];
+      cell_integral_mapped(S, K, 1, a, b, t);
+      for (int e = 0; e < dim; ++e) out[e] += t[e];
+    } else {
+      for (int e = 0; e < dim; ++e) {
+        pair_arg pr = {a, b, e};
+        out[e] += cell_integral(S, 1, pr);
+      }
     }
     long ki[3];
     int ai[3], bi[3];
@@ -766,14 +772,62 @@ static void literal_cij_cg(const or_setup *S, long i, long j, double *out) {
       if (S->bc[f] == OR_BC_PERIODIC) continue;
       if (ki[e] != (side ? S->n[e] - 1 : 0)) continue;       /* a cell face on box face f */
       if (ai[e] != side * S->deg || bi[e] != side * S->deg) continue;
-      out[e] -= 0.5 * (side ? 1.0 : -1.0) * face_integral(S, f, a, b, 1);
+      if (S->vx) {
+        double t[3];
+        face_integral_mapped(S, K, f, a, b, 1, t);
+        for (int d = 0; d < dim; ++d) out[d] -= 0.5 * t[d];
+      } else {
+        out[e] -= 0.5 * (side ? 1.0 : -1.0) * face_integral(S, f, a, b, 1);
+      }
     }
   }
 }
 
+static or_setup *cg_structure(or_setup *S);
+
 or_setup *or_create_cg(int dim, int deg, const long *cells, const double *lo, const double *hi, const int *bc) {
   or_setup *S = setup_init(dim, deg, cells, lo, hi, bc);
   if (!S) return NULL;
+  return cg_structure(S);
+}
+
+/* Continuous elements on general (mapdeg 1) or curved (mapdeg 2) cells of
+ * the lattice: the integrals of eq. cijcidefCg through each cell's map. */
+or_setup *or_create_cg_curved(int dim, int deg, const long *cells, const double *vx, const int *bc, int mapdeg) {
+  double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+  if (mapdeg != 1 && mapdeg != 2) return NULL;
+  or_setup *S = setup_init(dim, deg, cells, lo, hi, bc);
+  if (!S) return NULL;
+  S->mapdeg = mapdeg;
+  long nv = 1;
+  for (int e = 0; e < dim; ++e) nv *= mapdeg * S->n[e] + 1;
+  S->vx = (double *)malloc(nv * dim * sizeof(double));
+  memcpy(S->vx, vx, nv * dim * sizeof(double));
+  S->nq = deg + 2 + (mapdeg == 2 ? 2 : 0);
+  gauss_rule(S->nq, S->xq, S->wq);
+  double vol = 0.0;
+  for (long K = 0; K < S->ncells; ++K) {
+    double t[3];
+    for (int a = 0; a < S->nloc; ++a) {
+      cell_integral_mapped(S, K, 2, a, 0, t);
+      vol += t[0];
+    }
+    int tot = 1;
+    for (int e = 0; e < dim; ++e) tot *= S->nq;
+    for (int q = 0; q < tot; ++q) {
+      double xi[3] = {0, 0, 0}, x[3], J[3][3], Ji[3][3];
+      int r = q;
+      for (int e = 0; e < dim; ++e) { xi[e] = S->xq[r % S->nq]; r /= S->nq; }
+      cell_map(S, K, xi, x, J);
+      if (!(inverse(dim, J, Ji) > 0.0)) { or_destroy(S); return NULL; }
+    }
+  }
+  S->vol = vol;
+  return cg_structure(S);
+}
+
+static or_setup *cg_structure(or_setup *S) {
+  const int dim = S->dim, deg = S->deg;
   S->cg = 1;
   long N = 1;
   for (int e = 0; e < 3; ++e) {
@@ -804,21 +858,37 @@ or_setup *or_create_cg(int dim, int deg, const long *cells, const double *lo, co
       int ai[3];
       local_multi(S, a, ai);
       pair_arg pa = {a, 0, 0};
-      S->mi[i] += cell_integral(S, 2, pa);
+      double tm[3];
+      if (S->vx) cell_integral_mapped(S, K, 2, a, 0, tm);
+      S->mi[i] += S->vx ? tm[0] : cell_integral(S, 2, pa);
       int wrapped = 0;  /* the last node of a periodic axis is the first: keep the first's position */
       for (int e = 0; e < dim; ++e) wrapped |= deg * ki[e] + ai[e] >= S->gn[e];
-      for (int e = 0; e < dim && !wrapped; ++e) S->cgx[i * dim + e] = S->lo[e] + (ki[e] + S->xg[ai[e]]) * S->h[e];
+      if (!wrapped && S->vx) {
+        double xi[3] = {0, 0, 0}, J[3][3];
+        for (int e = 0; e < dim; ++e) xi[e] = S->xg[ai[e]];
+        cell_map(S, K, xi, S->cgx + i * dim, J);
+      }
+      for (int e = 0; e < dim && !wrapped && !S->vx; ++e)
+        S->cgx[i * dim + e] = S->lo[e] + (ki[e] + S->xg[ai[e]]) * S->h[e];
       for (int b = 0; b < nloc; ++b) {
         int bi[3], off = 0, st = 1;
         local_multi(S, b, bi);
         for (int e = 0; e < dim; ++e) { off += (bi[e] - ai[e] + deg) * st; st *= 2 * deg + 1; }
         used[(size_t)i * span + off] = 1;
-        for (int e = 0; e < dim; ++e) {
-          pair_arg pr = {a, b, e};
-          cc[((size_t)i * span + off) * dim + e] += cell_integral(S, 1, pr);
+        if (S->vx) {
+          double t[3];
+          cell_integral_mapped(S, K, 1, a, b, t);
+          for (int e = 0; e < dim; ++e) cc[((size_t)i * span + off) * dim + e] += t[e];
+          cell_integral_mapped(S, K, 0, a, b, t);
+          mm[(size_t)i * span + off] += t[0];
+        } else {
+          for (int e = 0; e < dim; ++e) {
+            pair_arg pr = {a, b, e};
+            cc[((size_t)i * span + off) * dim + e] += cell_integral(S, 1, pr);
+          }
+          pair_arg pm = {a, b, 0};
+          mm[(size_t)i * span + off] += cell_integral(S, 0, pm);
         }
-        pair_arg pm = {a, b, 0};
-        mm[(size_t)i * span + off] += cell_integral(S, 0, pm);
       }
       /* boundary terms of the cell faces on box faces (App. B) */
       for (int f = 0; f < 2 * dim; ++f) {
@@ -827,13 +897,25 @@ or_setup *or_create_cg(int dim, int deg, const long *cells, const double *lo, co
         if (ki[e] != (side ? S->n[e] - 1 : 0) || ai[e] != side * deg) continue;
         const double n = side ? 1.0 : -1.0;
         onb[(size_t)i * 2 * dim + f] = 1;
-        cb[((size_t)i * 2 * dim + f) * dim + e] += 0.5 * n * face_integral(S, f, a, -1, 1);
+        if (S->vx) {
+          double t[3];
+          face_integral_mapped(S, K, f, a, -1, 1, t);
+          for (int d = 0; d < dim; ++d) cb[((size_t)i * 2 * dim + f) * dim + d] += 0.5 * t[d];
+        } else {
+          cb[((size_t)i * 2 * dim + f) * dim + e] += 0.5 * n * face_integral(S, f, a, -1, 1);
+        }
         for (int b = 0; b < nloc; ++b) {
           int bi[3], off = 0, st = 1;
           local_multi(S, b, bi);
           if (bi[e] != side * deg) continue;
           for (int d = 0; d < dim; ++d) { off += (bi[d] - ai[d] + deg) * st; st *= 2 * deg + 1; }
-          cc[((size_t)i * span + off) * dim + e] -= 0.5 * n * face_integral(S, f, a, b, 1);
+          if (S->vx) {
+            double t[3];
+            face_integral_mapped(S, K, f, a, b, 1, t);
+            for (int d = 0; d < dim; ++d) cc[((size_t)i * span + off) * dim + d] -= 0.5 * t[d];
+          } else {
+            cc[((size_t)i * span + off) * dim + e] -= 0.5 * n * face_integral(S, f, a, b, 1);
+          }
         }
       }
     }

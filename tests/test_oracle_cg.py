@@ -11,6 +11,9 @@ the low-order scheme of eq. cijdijscheme - dij_low_order.
 * App. B's total balance: mass and energy kept to rounding inside slip walls,
   every component on a periodic box.
 * Sod: first-order convergence to the exact solution.
+* General and curved cells (integrals through the cell maps): lattice points
+  give the box's values; on moved points the partition of unity, the
+  skew-symmetry, the box's volume and the total balance still hold.
 """
 import math
 
@@ -106,3 +109,61 @@ def test_sod_converges_at_first_order(oracle, k):
         errs.append(_l1(M, U, W.to_conserved(ex[:, 0], ex[:, 1][None], ex[:, 2])))
     rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert all(0.6 < r < 1.2 for r in rates), (errs, rates)
+
+
+GENERAL = {"2d_q1": (2, 1, (5, 4), (1, 2, 1, 1)), "2d_q2": (2, 2, (4, 3), (2, 2, 1, 1)),
+           "2d_q3": (2, 3, (3, 3), (1, 1, 2, 2)), "3d_q1": (3, 1, (3, 3, 3), (1, 2, 2, 1, 2, 2))}
+
+
+@pytest.mark.parametrize("name", sorted(GENERAL))
+def test_lattice_points_give_the_box(oracle, name):
+    """Continuous elements through cell maps: lattice points reproduce the
+    box's coefficients, masses, boundary parts and nodes."""
+    dim, k, cells, bc = GENERAL[name]
+    lo, hi = (0.0,) * dim, (1.0,) * dim
+    A = oracle.Mesh(dim, k, cells, lo, hi, bc, continuous=True)
+    B = oracle.Mesh(dim, k, cells, lo, hi, bc, continuous=True, vertices=W.lattice(cells, lo, hi))
+    ra, ca, cca, _, _ = A.csr()
+    rb, cb, ccb, _, _ = B.csr()
+    assert np.array_equal(ca, cb) and np.abs(cca - ccb).max() < 1e-15
+    assert np.abs(A.lumped() - B.lumped()).max() < 1e-15
+    assert np.abs(A.boundary()[2] - B.boundary()[2]).max() < 1e-15
+    assert np.abs(A.coords() - B.coords()).max() < 1e-15
+
+
+@pytest.mark.parametrize("curved", [False, True])
+@pytest.mark.parametrize("name", sorted(GENERAL))
+def test_general_and_curved_cells(oracle, name, curved):
+    """Interior points moved (and, curved, quadratic maps through moved edge
+    midpoints): App. B's partition of unity and skew-symmetry row by row, the
+    box's volume, and the total balance inside slip walls."""
+    dim, k, cells, bc = GENERAL[name]
+    lo, hi = (0.0,) * dim, (1.0,) * dim
+    V = W.perturbed_lattice(cells, lo, hi, amp=0.2, seed=3)
+    g = 1
+    if curved:
+        V = W.refine_points(V, cells)
+        inner = np.all((V > 1e-12) & (V < 1 - 1e-12), axis=1)
+        V[inner, 0] += 0.01 * np.sin(3 * np.pi * V[inner, 1])
+        g = 2
+    M = oracle.Mesh(dim, k, cells, lo, hi, bc, continuous=True, vertices=V, map_degree=g)
+    rp, col, cc, _, _ = M.csr()
+    bp, bf, bcc = M.boundary()
+    N = M.ndofs
+    rows = np.repeat(np.arange(N), np.diff(rp))
+    part = np.zeros((N, dim))
+    np.add.at(part, rows, cc)
+    np.add.at(part, np.repeat(np.arange(N), np.diff(bp)), bcc)
+    scale = np.abs(cc).max()
+    assert np.abs(part).max() < 1e-13 * scale
+    assert M.lumped().sum() == pytest.approx(1.0, rel=1e-13)
+    rng = np.random.default_rng(2)
+    for q in rng.choice(len(col), size=min(150, len(col)), replace=False):
+        i, j = rows[q], col[q]
+        assert np.abs(M.literal_cij(i, j) + M.literal_cij(j, i)).max() < 1e-13 * scale
+    walls = oracle.Mesh(dim, k, cells, lo, hi, (2,) * (2 * dim), continuous=True, vertices=V, map_degree=g)
+    U = _smooth(walls.coords(), dim)
+    Un, _, _ = walls.run_to(oracle.params(degree=k, scheme=0), U, 1.0, max_steps=10)
+    mi = walls.lumped()
+    for c in (0, dim + 1):
+        assert abs((Un[c] * mi).sum() - (U[c] * mi).sum()) <= 1e-13 * np.abs(U[c] * mi).sum()
