@@ -192,9 +192,9 @@ bool validate(const gdg_mesh_desc *m, const gdg_params *p, std::string *err) {
   }
   if (m->continuous != 0 && m->continuous != 1) { *err = "continuous must be 0 or 1"; return false; }
   if (m->continuous) {
-    if (m->vertices || m->bc_cells || m->ucells > 0 || m->data_kind == GDG_DATA_VORTEX) {
-      *err = "continuous elements are built for the uniform box (no vertices, bc_cells, unstructured cells or "
-             "vortex data)";
+    if (m->bc_cells || m->ucells > 0 || m->data_kind == GDG_DATA_VORTEX) {
+      *err = "continuous elements are built for lattices of cells (no bc_cells, unstructured cells or vortex "
+             "data)";
       return false;
     }
     if (p->scheme != GDG_LOW_ORDER) {
@@ -760,7 +760,8 @@ gdg_status gdg_node_coords(const gdg_ctx *ctx, double *xyz) {
     int64_t gn[3];
     cg_nodes(&m, gn);
     for (int64_t i = 0; i < ctx->A.N; ++i) {
-      int64_t r = i;
+      int64_t r = i, Kc = 0, stc = 1;
+      double xi[3] = {0, 0, 0};
       for (int e = 0; e < d; ++e) {
         const int64_t I = r % gn[e];
         r /= gn[e];
@@ -769,6 +770,15 @@ gdg_status gdg_node_coords(const gdg_ctx *ctx, double *xyz) {
         if (K == m.cells[e]) K -= 1, a = m.degree;
         const double h = (m.hi[e] - m.lo[e]) / (double)m.cells[e];
         xyz[i * d + e] = m.lo[e] + ((double)K + xg[a]) * h;
+        xi[e] = xg[a];
+        Kc += K * stc;
+        stc *= m.cells[e];
+      }
+      if (m.vertices) {
+        // general cells: the node's cell's map at its reference point
+        double X[27][3];
+        mapped_cell_points(&m, m.vertices, Kc, X);
+        mapped_point(d, map_degree(&m), X, xi, &xyz[i * d]);
       }
     }
     return GDG_OK;

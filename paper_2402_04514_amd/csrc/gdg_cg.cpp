@@ -2,11 +2,15 @@
 //   c_ij   = int_Omega phi_i grad phi_j - 1/2 int_{dOmega} phi_i phi_j n,
 //   c_i^d  = 1/2 int_{dOmega} phi_i n           (one part per box face),
 //   m_i    = int_Omega phi_i.
-// Every cell of the box is the same scaled reference cell, so the integrals
+// On the box every cell is the same scaled reference cell, so the integrals
 // are tensor products of 1D integrals of the Gauss-Lobatto Lagrange basis
-// (exact Gauss rules), scattered from each cell to the global nodes it holds.
+// (exact Gauss rules); general and curved cells (vertices, map_degree) take
+// them through each cell's map (cofactors, Nanson's formula on faces, the
+// exact Gauss rules of the discontinuous general cells).  Each cell's values
+// are scattered to the global nodes it holds.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -102,9 +106,87 @@ bool build_cg(const gdg_mesh_desc *m, const gdg_params *p, int R, int W, int64_t
   out->mrow.assign(N, 0.0);
   int64_t ncells = 1;
   for (int e = 0; e < d; ++e) ncells *= m->cells[e];
+  // general cells: per cell, int phi_a cof(J) grad phi_b, int phi_a det J,
+  // and on each face int phi_a phi_b n ds and int phi_a n ds
+  const int gm = map_degree(m);
+  const int nqm = k + 2 + (d == 3 && gm == 2 ? 1 : 0);
+  double xqm[5], wqm[5];
+  if (m->vertices) gauss_rule01(nqm, xqm, wqm);
+  std::vector<double> gv(nloc * nloc * d), gmass(nloc), gfp(2 * d * nloc * nloc * d), gfs(2 * d * nloc * d);
+  double gvol = 0.0;
+  auto general_cell = [&](int64_t K) -> bool {
+    double X[27][3];
+    mapped_cell_points(m, m->vertices, K, X);
+    std::fill(gv.begin(), gv.end(), 0.0);
+    std::fill(gmass.begin(), gmass.end(), 0.0);
+    std::fill(gfp.begin(), gfp.end(), 0.0);
+    std::fill(gfs.begin(), gfs.end(), 0.0);
+    int nvol = 1;
+    for (int e = 0; e < d; ++e) nvol *= nqm;
+    double phv[64], gr[64][3];
+    auto basis = [&](const double *xi) {
+      for (int a = 0; a < nloc; ++a) {
+        int ai[3] = {0, 0, 0};
+        for (int e = 0, q = a; e < d; ++e, q /= nb) ai[e] = q % nb;
+        double v = 1.0;
+        for (int e = 0; e < d; ++e) v *= B.val(ai[e], xi[e]);
+        phv[a] = v;
+        for (int c = 0; c < d; ++c) {
+          double g = 1.0;
+          for (int e = 0; e < d; ++e) g *= e == c ? B.der(ai[e], xi[e]) : B.val(ai[e], xi[e]);
+          gr[a][c] = g;
+        }
+      }
+    };
+    for (int q = 0; q < nvol; ++q) {
+      double xi[3] = {0, 0, 0}, w = 1.0, cof[3][3];
+      for (int e = 0, r = q; e < d; ++e, r /= nqm) xi[e] = xqm[r % nqm], w *= wqm[r % nqm];
+      const double det = map_jacobian(d, gm, X, xi, cof);
+      if (!(det > 0.0)) return false;
+      gvol += w * det;
+      basis(xi);
+      for (int a = 0; a < nloc; ++a) {
+        gmass[a] += w * phv[a] * det;
+        for (int b = 0; b < nloc; ++b)
+          for (int e = 0; e < d; ++e) {
+            double gx = 0.0;
+            for (int c = 0; c < d; ++c) gx += cof[e][c] * gr[b][c];
+            gv[(a * nloc + b) * d + e] += w * phv[a] * gx;
+          }
+      }
+    }
+    int nsurf = 1;
+    for (int e = 0; e + 1 < d; ++e) nsurf *= nqm;
+    for (int f = 0; f < 2 * d; ++f) {
+      const int e = f / 2, side = f % 2;
+      for (int q = 0; q < nsurf; ++q) {
+        double xi[3] = {0, 0, 0}, w = 1.0, cof[3][3];
+        for (int g = 0, r = q; g < d; ++g) {
+          if (g == e) {
+            xi[g] = side ? 1.0 : 0.0;
+            continue;
+          }
+          xi[g] = xqm[r % nqm], w *= wqm[r % nqm], r /= nqm;
+        }
+        map_jacobian(d, gm, X, xi, cof);
+        basis(xi);
+        for (int a = 0; a < nloc; ++a) {
+          for (int c = 0; c < d; ++c) gfs[(f * nloc + a) * d + c] += w * phv[a] * (side ? 1.0 : -1.0) * cof[c][e];
+          for (int b = 0; b < nloc; ++b)
+            for (int c = 0; c < d; ++c)
+              gfp[((f * nloc + a) * nloc + b) * d + c] += w * phv[a] * phv[b] * (side ? 1.0 : -1.0) * cof[c][e];
+        }
+      }
+    }
+    return true;
+  };
   for (int64_t K = 0; K < ncells; ++K) {
     int64_t ki[3] = {0, 0, 0}, r = K;
     for (int e = 0; e < d; ++e) ki[e] = r % m->cells[e], r /= m->cells[e];
+    if (m->vertices && !general_cell(K)) {
+      *err = "a mapped cell has a non-positive Jacobian determinant (inverted or degenerate corners)";
+      return false;
+    }
     for (int a = 0; a < nloc; ++a) {
       int ai[3] = {0, 0, 0};
       for (int e = 0, q = a; e < d; ++e, q /= nb) ai[e] = q % nb;
@@ -117,7 +199,7 @@ bool build_cg(const gdg_mesh_desc *m, const gdg_params *p, int R, int W, int64_t
       }
       double ma = 1.0;
       for (int e = 0; e < d; ++e) ma *= h[e] * w1[ai[e]];
-      out->mrow[i] += ma;
+      out->mrow[i] += m->vertices ? gmass[a] : ma;
       for (int b = 0; b < nloc; ++b) {
         int bi[3] = {0, 0, 0};
         for (int e = 0, q = b; e < d; ++e, q /= nb) bi[e] = q % nb;
@@ -130,7 +212,7 @@ bool build_cg(const gdg_mesh_desc *m, const gdg_params *p, int R, int W, int64_t
           double v = G1[ai[e]][bi[e]];
           for (int g = 0; g < d; ++g)
             if (g != e) v *= h[g] * M1[ai[g]][bi[g]];
-          cc[((size_t)i * span + off) * d + e] += v;
+          cc[((size_t)i * span + off) * d + e] += m->vertices ? gv[(a * nloc + b) * d + e] : v;
         }
       }
       // the cell's faces on box faces (not periodic)
@@ -143,7 +225,10 @@ bool build_cg(const gdg_mesh_desc *m, const gdg_params *p, int R, int W, int64_t
         double wa = 1.0;
         for (int g = 0; g < d; ++g)
           if (g != e) wa *= h[g] * w1[ai[g]];
-        cb[((size_t)i * 2 * d + f) * d + e] += 0.5 * n * wa;
+        if (m->vertices)
+          for (int c = 0; c < d; ++c) cb[((size_t)i * 2 * d + f) * d + c] += 0.5 * gfs[(f * nloc + a) * d + c];
+        else
+          cb[((size_t)i * 2 * d + f) * d + e] += 0.5 * n * wa;
         for (int b = 0; b < nloc; ++b) {
           int bi[3] = {0, 0, 0};
           for (int g = 0, q = b; g < d; ++g, q /= nb) bi[g] = q % nb;
@@ -153,7 +238,11 @@ bool build_cg(const gdg_mesh_desc *m, const gdg_params *p, int R, int W, int64_t
           double v = 1.0;
           for (int g = 0; g < d; ++g)
             if (g != e) v *= h[g] * M1[ai[g]][bi[g]];
-          cc[((size_t)i * span + off) * d + e] -= 0.5 * n * v;
+          if (m->vertices)
+            for (int c = 0; c < d; ++c)
+              cc[((size_t)i * span + off) * d + c] -= 0.5 * gfp[((f * nloc + a) * nloc + b) * d + c];
+          else
+            cc[((size_t)i * span + off) * d + e] -= 0.5 * n * v;
         }
       }
     }
@@ -171,6 +260,7 @@ bool build_cg(const gdg_mesh_desc *m, const gdg_params *p, int R, int W, int64_t
     }
     return j;
   };
+  if (m->vertices) vol = gvol;
   out->vol = vol;
   const double pk = k % 2 == 0 ? 0.5 : 0.0;
   out->hprow.resize(N);

@@ -254,6 +254,11 @@ bool build_cg(const gdg_mesh_desc *m, const gdg_params *p, int R, int W, int64_t
 void cg_nodes(const gdg_mesh_desc *m, int64_t *gn);
 // Degree of the cell maps (1 multilinear, 2 quadratic) of a mesh of general cells.
 int map_degree(const gdg_mesh_desc *m);
+// Gauss-Legendre rule of n = 2 .. 5 points on [0, 1].
+void gauss_rule01(int n, double *x, double *w);
+// det J at xi of the degree-g map through a cell's points X, and its cofactor
+// matrix cof = det(J) J^{-T}.
+double map_jacobian(int d, int g, const double (*X)[3], const double *xi, double cof[3][3]);
 // The (g+1)^dim points of cell K's map of degree g (point v: digits q_e of v
 // in base g + 1, first axis lowest).
 void mapped_cell_points(const gdg_mesh_desc *m, const double *vx, int64_t K, double (*X)[3]);

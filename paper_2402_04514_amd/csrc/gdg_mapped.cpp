@@ -179,6 +179,12 @@ void parallel_ranges(int64_t n, F body) {
 
 int map_degree(const gdg_mesh_desc *m) { return m->map_degree == 2 ? 2 : 1; }
 
+void gauss_rule01(int n, double *x, double *w) { gauss01(n, x, w); }
+
+double map_jacobian(int d, int g, const double (*X)[3], const double *xi, double cof[3][3]) {
+  return jacobian(d, g, X, xi, cof);
+}
+
 void mapped_cell_points(const gdg_mesh_desc *m, const double *vx, int64_t K, double (*X)[3]) {
   const int d = m->dim, g = map_degree(m);
   if (m->ucells > 0) {
