@@ -27,6 +27,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 BC_PERIODIC, BC_OUTFLOW, BC_SLIP, BC_DIRICHLET, BC_SUPERSONIC, BC_INOUTFLOW = 0, 1, 2, 3, 4, 5
 LOW_ORDER, HIGH_ORDER, LIMITED = 0, 1, 2
+SSPRK3, SSPRK54 = 0, 1
 KIND_CELL, KIND_FACE_COLLOC, KIND_FACE = 0, 1, 2
 
 
@@ -43,7 +44,7 @@ def build(force: bool = False) -> str:
 class _Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("cfl", C.c_double), ("c_ev", C.c_double),
                 ("c_k", C.c_double), ("c_r", C.c_double), ("p_r", C.c_double),
-                ("passes", C.c_int), ("scheme", C.c_int)]
+                ("passes", C.c_int), ("scheme", C.c_int), ("integrator", C.c_int)]
 
 
 _DP = C.POINTER(C.c_double)
@@ -119,6 +120,8 @@ def lib():
         L.or_stage.argtypes = [C.c_void_p, C.POINTER(_Params), _DP, C.c_double, _DP,
                                C.POINTER(_Diag)]
         L.or_tau_rows.argtypes = [C.c_void_p, C.POINTER(_Params), _DP, _DP]
+        L.or_ssprk54_table.restype = None
+        L.or_ssprk54_table.argtypes = [_DP, _DP]
         L.or_step.restype = C.c_int
         L.or_step.argtypes = [C.c_void_p, C.POINTER(_Params), _DP, C.c_double, C.c_double, _DP,
                               C.POINTER(C.c_int)]
@@ -131,11 +134,21 @@ def _dp(a: np.ndarray):
 
 
 def params(gamma=1.4, cfl=0.5, degree=1, c_ev=None, c_k=1.0, c_r=4.0, p_r=1.5, passes=2,
-           scheme=LIMITED) -> _Params:
-    """Scheme constants of Sec. 5 (c_ev = 1, 0.5, 0.25 for k = 1, 2, 3)."""
+           scheme=LIMITED, integrator=SSPRK3) -> _Params:
+    """Scheme constants of Sec. 5 (c_ev = 1, 0.5, 0.25 for k = 1, 2, 3);
+    integrator SSPRK3 or SSPRK54 (the fourth-order SSP method of Sec. 6.2)."""
     if c_ev is None:
         c_ev = lib().or_default_cev(degree)
-    return _Params(gamma, cfl, c_ev, c_k, c_r, p_r, passes, scheme)
+    return _Params(gamma, cfl, c_ev, c_k, c_r, p_r, passes, scheme, integrator)
+
+
+def ssprk54_table():
+    """(alpha, beta): the Shu-Osher coefficients of the oracle's SSPRK(5,4),
+    rows i = 0..5 (stage u(i)), columns k = 0..4."""
+    a = np.zeros(30)
+    b = np.zeros(30)
+    lib().or_ssprk54_table(_dp(a), _dp(b))
+    return a.reshape(6, 5), b.reshape(6, 5)
 
 
 class Mesh:
@@ -331,7 +344,8 @@ class Mesh:
         lib().or_set_time(self._h, float(t))
 
     def step(self, prm: _Params, U: np.ndarray, dt_cap: float = 0.0, dt_fixed: float = 0.0):
-        """One SSP-RK3 step.  Returns (U_new, dt_taken, restarts, status)."""
+        """One step of the integrator prm names.  Returns (U_new, dt_taken,
+        restarts, status)."""
         U = np.array(U, dtype=np.float64).reshape(self.m, self.ndofs)
         dt = C.c_double(0.0)
         nres = C.c_int(0)

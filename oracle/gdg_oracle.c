@@ -47,6 +47,7 @@ typedef struct {
   double p_r;     /* relaxation power (eq. ViscMinConst2) */
   int passes;     /* limiter passes (Sec. 6.1: two) */
   int scheme;     /* OR_LOW_ORDER / OR_HIGH_ORDER / OR_LIMITED */
+  int integrator; /* 0: SSP-RK3; 1: SSPRK(5,4) (Sec. 6.2's fourth-order runs) */
 } or_params;
 
 typedef struct {
@@ -2140,8 +2141,111 @@ void or_tau_rows(const or_setup *S, const or_params *P, const double *U, double 
  * dt_fixed > 0 replaces the CFL rule for stage 1.
  * Returns 0, -2 (inadmissible output), -3 (CFL restarts exhausted) or -4
  * (subsonic normal flow at a supersonic in/outflow face). */
+/* SSPRK(5,4) of Spiteri and Ruuth in Shu-Osher form,
+ *   u(i) = sum_k alpha_ik u(k) + beta_ik tau L(u(k)),  u(0) = U^n, u(5) = U^{n+1},
+ * the coefficients as that work prints them (15 digits).  Every stage is a
+ * convex combination of forward-Euler steps of size (beta/alpha) tau. */
+static const double rk54_a[6][5] = {
+    {0, 0, 0, 0, 0},
+    {1.0, 0, 0, 0, 0},
+    {0.444370493651235, 0.555629506348765, 0, 0, 0},
+    {0.620101851488403, 0, 0.379898148511597, 0, 0},
+    {0.178079954393132, 0, 0, 0.821920045606868, 0},
+    {0, 0, 0.517231671970585, 0.096059710526147, 0.386708617503269}};
+static const double rk54_b[6][5] = {
+    {0, 0, 0, 0, 0},
+    {0.391752226571890, 0, 0, 0, 0},
+    {0, 0.368410593050371, 0, 0, 0},
+    {0, 0, 0.251891774271694, 0, 0},
+    {0, 0, 0, 0.544974750228521, 0},
+    {0, 0, 0, 0.063692468666290, 0.226007483236906}};
+
+/* The Shu-Osher table for the pins (order conditions, SSP coefficient). */
+void or_ssprk54_table(double *alpha, double *beta) {
+  for (int i = 0; i < 6; ++i)
+    for (int k = 0; k < 5; ++k) {
+      alpha[i * 5 + k] = rk54_a[i][k];
+      beta[i * 5 + k] = rk54_b[i][k];
+    }
+}
+
+/* One SSPRK(5,4) step (reading R45).  Stage k takes the forward-Euler step
+ * Phi of size r_k tau, r_k = beta_{k+1,k} / alpha_{k+1,k}, at its own state
+ * u(k) and time t + c_k tau (c_k: the stage's abscissa, the row sums of the
+ * Butcher table of the same method); the last stage also reuses the step of
+ * u(3) for the term beta_53 tau L(u(3)) (its ratio beta/alpha equals r_3 to
+ * the printed digits).  tau = Cr tau_max(U^n) / max_k r_k, so that every
+ * Euler step is within Cr of the CFL bound of U^n; stage k re-checks
+ * r_k tau <= tau_max(u(k)) and on violation the step restarts with
+ * tau = Cr tau_max(u(k)) / r_k. */
+static int step_rk54(const or_setup *S, const or_params *P, double *U, double dt_cap, double dt_fixed,
+                     double *dt_taken, int *restarts) {
+  const long M = (long)S->m * S->ndofs;
+  double *u[5], *Ph = dalloc(M), *acc = dalloc(M);
+  for (int k = 0; k < 5; ++k) u[k] = dalloc(M);
+  double r[5], c[5], A[6][5];
+  memset(A, 0, sizeof A);
+  for (int i = 1; i < 6; ++i)
+    for (int k = 0; k < i; ++k) {
+      for (int j = 0; j < 5; ++j) A[i][j] += rk54_a[i][k] * A[k][j];
+      A[i][k] += rk54_b[i][k];
+    }
+  double rmax = 0.0;
+  for (int k = 0; k < 5; ++k) {
+    r[k] = rk54_b[k + 1][k] / rk54_a[k + 1][k];
+    rmax = fmax(rmax, r[k]);
+    c[k] = 0.0;
+    for (int j = 0; j < 5; ++j) c[k] += A[k][j];
+  }
+  or_diag dg;
+  memset(&dg, 0, sizeof(dg));
+  int st = 0, nres = 0;
+  double tau;
+  if (dt_fixed > 0.0) {
+    tau = dt_fixed;
+  } else {
+    double *tr = dalloc(S->ndofs);
+    or_tau_rows(S, P, U, tr);
+    double tm = INFINITY;
+    for (long i = 0; i < S->ndofs; ++i) tm = fmin(tm, tr[i]);
+    free(tr);
+    tau = P->cfl * tm / rmax;
+  }
+  if (dt_cap > 0.0 && tau > dt_cap) tau = dt_cap;
+  for (;;) {
+    memcpy(u[0], U, M * sizeof(double));
+    int restart = 0;
+    for (int k = 0; k < 5 && !st && !restart; ++k) {
+      st = stage_at(S, P, u[k], r[k] * tau, S->t0 + c[k] * tau, Ph, &dg);
+      if (k > 0 && r[k] * tau > dg.tau_max) {
+        if (++nres > 8) { st = -3; break; }
+        tau = P->cfl * dg.tau_max / r[k];
+        restart = 1;
+        st = 0;
+        break;
+      }
+      if (st) break;
+      if (k == 3)  /* the last stage's terms in u(2) and L(u(3)) */
+        for (long q = 0; q < M; ++q) acc[q] = rk54_a[5][2] * u[2][q] + rk54_a[5][3] * Ph[q];
+      if (k < 4) {
+        for (long q = 0; q < M; ++q) u[k + 1][q] = rk54_a[k + 1][k] * Ph[q] + (k ? rk54_a[k + 1][0] * u[0][q] : 0.0);
+      } else {
+        for (long q = 0; q < M; ++q) U[q] = acc[q] + rk54_a[5][4] * Ph[q];
+      }
+    }
+    if (restart) continue;
+    break;
+  }
+  *dt_taken = tau;
+  if (restarts) *restarts = nres;
+  for (int k = 0; k < 5; ++k) free(u[k]);
+  free(Ph); free(acc);
+  return st;
+}
+
 int or_step(const or_setup *S, const or_params *P, double *U, double dt_cap, double dt_fixed,
             double *dt_taken, int *restarts) {
+  if (P->integrator == 1) return step_rk54(S, P, U, dt_cap, dt_fixed, dt_taken, restarts);
   const long M = (long)S->m * S->ndofs;
   double *Ua = dalloc(M), *Ub = dalloc(M), *Ph = dalloc(M);
   or_diag dg;

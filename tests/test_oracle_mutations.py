@@ -23,9 +23,16 @@ BCPARTS = T + "test_oracle_bcparts.py"
 CURVED = T + "test_oracle_curved.py"
 UNSTR = T + "test_oracle_unstructured.py"
 CG = T + "test_oracle_cg.py"
+RK54 = T + "test_oracle_rk54.py"
 
 MUTANTS = {
     # name: (original text, planted text, pin files that must fail)
+    "rk54_last_stage_takes_u3": ("acc[q] = rk54_a[5][2] * u[2][q]", "acc[q] = rk54_a[5][2] * u[3][q]",
+                                 [RK54 + "::test_step_equals_the_butcher_form_with_stage_times"]),
+    "rk54_stage_time_from_substep": ("S->t0 + c[k] * tau", "S->t0 + r[k] * tau",
+                                     [RK54 + "::test_step_equals_the_butcher_form_with_stage_times"]),
+    "rk54_coefficient_digits_swapped": ("{0, 0.368410593050371, 0, 0, 0}", "{0, 0.368410593050317, 0, 0, 0}",
+                                        [RK54 + "::test_order_conditions"]),
     "cg_boundary_pair_term_sign": ("          cc[((size_t)i * span + off) * dim + e] -= 0.5 * n * face_integral(S, f, a, b, 1);",
                                    "          cc[((size_t)i * span + off) * dim + e] += 0.5 * n * face_integral(S, f, a, b, 1);",
                                    [CG + "::test_skew_symmetry_and_partition_of_unity"]),
