@@ -84,7 +84,8 @@ typedef enum {
                             the stage time (2D): vortex[] = beta, x0 (2),
                             u_inf (2), gamma of the data; free space (no
                             periodic images).  The SSP-RK3 stages take their
-                            data at t, t + tau and t + tau / 2. */
+                            data at t, t + tau and t + tau / 2; those of
+                            SSPRK(5,4) at t + c_k tau (gdg_integrator). */
 } gdg_data_kind;
 
 /* GDG_LOW_ORDER: eq. cijdijscheme only.  GDG_HIGH_ORDER: eq. HighScheme
@@ -103,6 +104,23 @@ typedef enum { GDG_LOW_ORDER = 0, GDG_HIGH_ORDER = 1, GDG_LIMITED = 2 } gdg_sche
  * double precision, so every stage output is still checked against A.  The
  * boundary parts use the double-precision flux that their bar state needs. */
 typedef enum { GDG_FP64 = 0, GDG_MIXED = 1 } gdg_precision;
+
+/* Time integration of gdg_step() and gdg_run_to().
+ * GDG_SSPRK3: the three-stage, third-order SSP Runge-Kutta method in
+ * Shu-Osher form (Sec. 6): stages at t, t + tau, t + tau / 2, each a
+ * forward-Euler stage of size tau; tau = Cr min_i (-m_i / (2 d_ii)) of U^n
+ * (eq. MaxCFLdt).
+ * GDG_SSPRK54: the five-stage, fourth-order SSP method of Spiteri and Ruuth
+ * that Sec. 6.2 uses for the isentropic vortex, in its Shu-Osher form with
+ * non-negative coefficients.  Stage k is the forward-Euler stage of size
+ * r_k tau (r_k = beta_{k+1,k} / alpha_{k+1,k}: 0.3918, 0.6631, 0.6631,
+ * 0.6631, 0.5844) at time t + c_k tau (c = 0, 0.3918, 0.5861, 0.4745,
+ * 0.9350), and the new state is the convex combination of the method.
+ * tau = Cr tau_max(U^n) / max_k r_k, so that every stage is an Euler step
+ * within Cr of the CFL bound of U^n (about 1.51 times the SSP-RK3 step, for
+ * 5/3 of its stages).  Either method restarts a step whose stage k finds
+ * r_k tau above its own bound tau_max(u_k), with tau = Cr tau_max(u_k) / r_k. */
+typedef enum { GDG_SSPRK3 = 0, GDG_SSPRK54 = 1 } gdg_integrator;
 
 /* Cartesian mesh of cells[0] x cells[1] x cells[2] cells over the box
  * [lo, hi] (only the first dim entries are read), Q_degree elements with
@@ -194,7 +212,7 @@ typedef struct {
 /* Scheme constants.  gdg_default_params() gives the paper's values:
  * gamma 1.4, Cr 0.5 (eq. MaxCFLdt), c_ev 1 / 0.5 / 0.25 for k = 1 / 2 / 3 (Sec. 5.2),
  * c_k 1 (eq. ViscMin), c_r 4 and p_r 1.5 (eq. ViscMinConst2), two limiter
- * passes (Sec. 6.1), the limited scheme, FP64. */
+ * passes (Sec. 6.1), the limited scheme, FP64, SSP-RK3. */
 typedef struct {
   double gamma;
   double cfl;
@@ -206,6 +224,8 @@ typedef struct {
   int32_t scheme;         /* gdg_scheme */
   int32_t precision;      /* gdg_precision */
   int32_t flags;          /* 0, or GDG_FLAG_NO_QUIET_ROWS */
+  int32_t integrator;     /* gdg_integrator */
+  int32_t reserved;       /* 0 */
 } gdg_params;
 
 /* gdg_params.flags.  GDG_FLAG_NO_QUIET_ROWS: the first limiter pass visits
@@ -288,11 +308,12 @@ gdg_status gdg_upload_state(gdg_ctx *ctx, const double *U, int32_t is_device_ptr
 /* Copies the current state out (same layout).  Synchronizes the stream. */
 gdg_status gdg_download_state(gdg_ctx *ctx, double *U, int32_t is_device_ptr);
 
-/* One SSP-RK3 step (Shu-Osher form).  tau = Cr * min_i(-m_i / (2 d_ii))
- * from stage 1 (eq. MaxCFLdt), or dt_fixed if dt_fixed > 0; then capped by
- * dt_cap if dt_cap > 0.  Stages 2 and 3 re-check eq. CFLcond on their own
- * state; on violation the step restarts with tau = Cr * that stage's bound
- * (at most 8 times, then GDG_E_CFL).  *dt_taken (may be NULL) receives tau.
+/* One step of the params' integrator (gdg_integrator).  tau from the first
+ * stage's bound (eq. MaxCFLdt; divided by max_k r_k for GDG_SSPRK54), or
+ * dt_fixed if dt_fixed > 0; then capped by dt_cap if dt_cap > 0.  Every later
+ * stage re-checks eq. CFLcond for its own Euler step on its own state; on
+ * violation the step restarts with the tau of gdg_integrator's rule (at most
+ * 8 times, then GDG_E_CFL).  *dt_taken (may be NULL) receives tau.
  * Returns GDG_E_INADMISSIBLE if a stage output left A, GDG_E_BOUNDARY if a
  * node of a GDG_BC_SUPERSONIC face saw subsonic normal flow; after either
  * error the context's state is not a valid step result: upload a state
@@ -430,7 +451,8 @@ gdg_status gdg_server_create(const gdg_server_desc *desc, void *dev_pool, size_t
 
 /* Queues a request; U0 is a host state (SoA, (dim+2) * N doubles), copied,
  * as are the mesh's vertices (general cells) and boundary parts.
- * Unstructured meshes and continuous elements are not served (GDG_E_INVALID).
+ * Unstructured meshes, continuous elements and GDG_SSPRK54 are not served
+ * (GDG_E_INVALID).
  * GDG_E_INVALID for a description outside the server's class or bad
  * constants, GDG_E_BUDGET if its workspace exceeds the whole pool. */
 gdg_status gdg_server_submit(gdg_server *srv, const gdg_mesh_desc *mesh, const gdg_params *prm, const double *U0,

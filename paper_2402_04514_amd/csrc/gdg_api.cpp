@@ -255,6 +255,7 @@ bool validate(const gdg_mesh_desc *m, const gdg_params *p, std::string *err) {
   if (p->flags & ~GDG_FLAG_NO_QUIET_ROWS) { *err = "unknown flags"; return false; }
   if (p->scheme < 0 || p->scheme > 2) { *err = "unknown scheme"; return false; }
   if (p->precision != GDG_FP64 && p->precision != GDG_MIXED) { *err = "unknown precision"; return false; }
+  if (p->integrator != GDG_SSPRK3 && p->integrator != GDG_SSPRK54) { *err = "unknown integrator"; return false; }
   return true;
 }
 
@@ -392,23 +393,80 @@ void drop_graph(gdg_ctx *ctx) {
 }
 
 // One SSP-RK3 step on a stream: begin, three stages, end.
+// SSPRK(5,4) of Spiteri and Ruuth, Shu-Osher form
+//   u(i) = sum_k alpha_ik u(k) + tau beta_ik L(u(k)),  u(0) = U^n, u(5) = U^{n+1},
+// with the coefficients as published (15 digits).  Each stage i > 0 reads at
+// most two earlier states besides its Euler step, which the buffers below
+// exploit.
+constexpr double kA10 = 1.0;
+constexpr double kB10 = 0.391752226571890;
+constexpr double kA20 = 0.444370493651235, kA21 = 0.555629506348765, kB21 = 0.368410593050371;
+constexpr double kA30 = 0.620101851488403, kA32 = 0.379898148511597, kB32 = 0.251891774271694;
+constexpr double kA40 = 0.178079954393132, kA43 = 0.821920045606868, kB43 = 0.544974750228521;
+constexpr double kA52 = 0.517231671970585, kA53 = 0.096059710526147;  // beta_53 = 0.063692468666290
+constexpr double kA54 = 0.386708617503269, kB54 = 0.226007483236906;
+
+// Stage k of a step as a forward-Euler stage of size tstep[k] tau at time
+// t + tfrac[k] tau.  SSP-RK3: three stages of size tau at t, t + tau,
+// t + tau / 2.  SSPRK(5,4): r_k = beta_{k+1,k} / alpha_{k+1,k}; tfrac[k] is
+// the stage's abscissa c_k, the row sum of the method's Butcher matrix
+// (c_0 = 0, c_1 = b10, c_2 = a21 b10 + b21, c_3 = a32 c_2 + b32,
+// c_4 = a43 c_3 + b43).  The term beta_53 tau L(u(3)) of the last stage
+// reuses the Euler step of u(3): beta_53 / alpha_53 equals r_3 to the
+// published digits (they differ by 1.2e-15 relative).
+void set_integrator(KArgs &A, int integrator) {
+  if (integrator == GDG_SSPRK54) {
+    A.nst = 5;
+    const double c1 = kB10, c2 = kA21 * kB10 + kB21, c3 = kA32 * c2 + kB32, c4 = kA43 * c3 + kB43;
+    const double r[5] = {kB10 / kA10, kB21 / kA21, kB32 / kA32, kB43 / kA43, kB54 / kA54};
+    const double c[5] = {0.0, c1, c2, c3, c4};
+    A.tstep_max = 0.0;
+    for (int k = 0; k < 5; ++k) {
+      A.tstep[k] = r[k];
+      A.tfrac[k] = c[k];
+      A.tstep_max = r[k] > A.tstep_max ? r[k] : A.tstep_max;
+    }
+    return;
+  }
+  A.nst = 3;
+  const double c[5] = {0.0, 1.0, 0.5, 0.0, 0.0};
+  for (int k = 0; k < kMaxStages; ++k) {
+    A.tstep[k] = k < 3 ? 1.0 : 0.0;
+    A.tfrac[k] = c[k];
+  }
+  A.tstep_max = 1.0;
+}
+
 // first / last: whether this step opens / closes a sequence of device-driven
 // steps (inside a sequence, one launch ends a step and starts the next).
 int enqueue_step(gdg_ctx *ctx, hipStream_t st, int device_driven, double dt_cap, double tau_fixed, Prof *prof,
                  bool first = true, bool last = true) {
   const KArgs &A = ctx->A;
   const int c0 = ctx->cur, c1 = (c0 + 1) % 3, c2 = (c0 + 2) % 3;
-  StageBufs b1 = {ctx->U[c0], ctx->U[c1], ctx->U[c0], 0.0, 1.0};
-  StageBufs b2 = {ctx->U[c1], ctx->U[c2], ctx->U[c0], 0.75, 0.25};
-  StageBufs b3 = {ctx->U[c2], ctx->U[c0], ctx->U[c0], 1.0 / 3.0, 2.0 / 3.0};
+  double *B0 = ctx->U[c0], *B1 = ctx->U[c1], *B2 = ctx->U[c2];
+  StageBufs b[kMaxStages];
+  if (A.nst == 5) {
+    // U^n stays whole in B0 until the last stage has passed its CFL check
+    // (a restart starts again from it).  A stage reads its input state in
+    // its first sweep only (later sweeps read the node records), so stage 3
+    // may write u(4) over its input u(3).  u(2) turns into the partial sum
+    // alpha_52 u(2) + beta_53 tau L(u(3)) in place.
+    b[0] = {B0, B1, B0, 0.0, 1.0};                        // u1 = Phi_0(u0)
+    b[1] = {B1, B2, B0, kA20, kA21};                      // u2
+    b[2] = {B2, B1, B0, kA30, kA32};                      // u3 over u1
+    b[3] = {B1, B1, B0, kA40, kA43, B2, B2, kA52, kA53};  // u4 over u3, partial sum over u2
+    b[4] = {B1, B0, B2, 1.0, kA54};                       // u5 = partial sum + alpha_54 Phi_4(u4)
+  } else {
+    b[0] = {B0, B1, B0, 0.0, 1.0};
+    b[1] = {B1, B2, B0, 0.75, 0.25};
+    b[2] = {B2, B0, B0, 1.0 / 3.0, 2.0 / 3.0};
+  }
   int rc = first ? launch_begin(A, dt_cap, tau_fixed, device_driven, st) : 0;
   // host-driven steps recompute the node cache of U^n: after a restart it
   // holds the state of an abandoned stage; device-driven steps follow a
   // completed step (or the upload, or a host-driven step) whose last stage
   // wrote it
-  rc |= launch_stage(A, b1, 0, st, prof, device_driven ? 0 : 1);
-  rc |= launch_stage(A, b2, 1, st, prof, 0);
-  rc |= launch_stage(A, b3, 2, st, prof, 0);
+  for (int k = 0; k < A.nst; ++k) rc |= launch_stage(A, b[k], k, st, prof, k == 0 && !device_driven ? 1 : 0);
   rc |= last ? launch_end(A, st) : launch_end_begin(A, st);
   return rc;
 }
@@ -580,6 +638,7 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   A.g75 = std::fabs(prm->gamma - 1.4) < 1e-15 ? 1 : 0;
   A.scheme = prm->scheme;
   A.passes = prm->limiter_passes;
+  set_integrator(A, prm->integrator);
   A.no_quiet = (prm->flags & GDG_FLAG_NO_QUIET_ROWS) ? 1 : 0;
   A.nslots = L.nslots;
   A.ref = (const RefTables *)(ws + L.off_ref);
@@ -847,7 +906,14 @@ gdg_status gdg_download_state(gdg_ctx *ctx, double *U, int32_t is_device_ptr) {
 namespace {
 constexpr int kMaxRestarts = 8;
 
-// One SSP-RK3 step with the restart rule; `used` restarts of this step were
+// tau of a restarted step: stage vs found its Euler step tstep[vs] tau above
+// its bound tau_max(u_vs); the new tau gives it Cr tau_max(u_vs).
+double restart_tau(const gdg_ctx *ctx, const Ctl &h) {
+  const int vs = h.viol_stage < 1 ? 1 : (h.viol_stage >= ctx->A.nst ? ctx->A.nst - 1 : h.viol_stage);
+  return ctx->prm.cfl * bits_to_double(h.taumin_bits[vs]) / ctx->A.tstep[vs];
+}
+
+// One step of the integrator with the restart rule; `used` restarts of this step were
 // already spent (a device-driven attempt that halted on a violation).
 gdg_status step_impl(gdg_ctx *ctx, double dt_cap, double dt_fixed, double *dt_taken, int used) {
   double tau_fixed = dt_fixed > 0.0 ? dt_fixed : 0.0;
@@ -858,8 +924,7 @@ gdg_status step_impl(gdg_ctx *ctx, double dt_cap, double dt_fixed, double *dt_ta
     if (gdg_status s = harvest(ctx)) return s;
     const Ctl &h = ctx->hctl;
     if (h.cfl_flag) {
-      const int vs = h.viol_stage < 1 ? 1 : h.viol_stage;
-      tau_fixed = ctx->prm.cfl * bits_to_double(h.taumin_bits[vs]);
+      tau_fixed = restart_tau(ctx, h);
       ++ctx->restarts;
       continue;
     }
@@ -920,8 +985,7 @@ gdg_status run_loop(gdg_ctx *ctx, double t_final, int64_t max_steps, gdg_stats *
     ctx->last_dt = h.tau;
     sync_time(ctx);
     if (h.cfl_flag) {
-      const int vs = h.viol_stage < 1 ? 1 : h.viol_stage;
-      const double tau = ctx->prm.cfl * bits_to_double(h.taumin_bits[vs]);
+      const double tau = restart_tau(ctx, h);
       ++ctx->restarts;
       double dt = 0.0;
       if (gdg_status s = step_impl(ctx, t_final - ctx->t, tau, &dt, 1)) return s;
@@ -967,8 +1031,7 @@ void ctx_sync(gdg_ctx *ctx, const Ctl &c) {
 
 gdg_status ctx_restart(gdg_ctx *ctx, const Ctl &c, double t_final) {
   ctx_sync(ctx, c);
-  const int vs = c.viol_stage < 1 ? 1 : c.viol_stage;
-  const double tau = ctx->prm.cfl * bits_to_double(c.taumin_bits[vs]);
+  const double tau = restart_tau(ctx, c);
   ++ctx->restarts;
   double dt = 0.0;
   if (gdg_status s = step_impl(ctx, t_final - ctx->t, tau, &dt, 1)) return s;
@@ -1011,7 +1074,11 @@ gdg_status gdg_stage(gdg_ctx *ctx, double tau, double *tau_used) {
   if (gdg_status s = launched(ctx, launch_begin(ctx->A, 0.0, tau > 0.0 ? tau : 0.0, 0, ctx->stream), "begin"))
     return s;
   StageBufs b = {ctx->U[c0], ctx->U[c1], ctx->U[c0], 0.0, 1.0};
-  if (gdg_status s = launched(ctx, launch_stage(ctx->A, b, 0, ctx->stream, prof_of(ctx), 1), "stage")) return s;
+  // one forward-Euler stage of size tau = Cr tau_max (or the given tau),
+  // whatever the context's integrator
+  KArgs A1 = ctx->A;
+  set_integrator(A1, GDG_SSPRK3);
+  if (gdg_status s = launched(ctx, launch_stage(A1, b, 0, ctx->stream, prof_of(ctx), 1), "stage")) return s;
   if (gdg_status s = read_ctl(ctx)) return s;
   if (gdg_status s = harvest(ctx)) return s;
   if (ctx->hctl.bad_flag) return gdg::flag_status(ctx, ctx->hctl.bad_flag, "the stage output left the admissible set");

@@ -44,11 +44,12 @@ __host__ __device__ inline int bclass_kind(int c) { return c / 6 + 1; }
 constexpr int kBlockThreads = GDG_BLOCK;
 constexpr int kMaxD = 3;
 constexpr int kMaxNloc = 27;
+constexpr int kMaxStages = 5;  // stages of a step (SSP-RK3: 3, SSPRK(5,4): 5)
 
 // Control block in device memory.  In a device-driven run (captured graphs
 // of several steps) the time loop state lives here too.
 struct Ctl {
-  unsigned long long taumin_bits[3]; // per stage: min_i m_i / (2 |d_ii|) as IEEE bits
+  unsigned long long taumin_bits[kMaxStages]; // per stage: min_i m_i / (2 |d_ii|) as IEEE bits
   double tau;                        // tau of the current step
   double dt_cap;                     // cap on tau (<= 0: none)
   double tau_fixed;                  // > 0: replaces the CFL rule in stage 1
@@ -155,6 +156,11 @@ struct KArgs {
   int32_t ipow;     // > 0: 1/alpha equals this integer, the p* power is taken by multiplies
   int32_t g75;      // gamma == 7/5: entropy comparisons by integer powers
   int32_t scheme, passes;
+  // time integration: nst stages per step; stage k is a forward-Euler stage
+  // of size tstep[k] * tau at time t + tfrac[k] * tau, and the first stage
+  // picks tau = cfl * tau_max / tstep_max
+  int32_t nst;
+  double tstep[kMaxStages], tfrac[kMaxStages], tstep_max;
   int32_t mixed;    // 1: c_ij stored in FP32 and the flux / entropy-viscosity sums taken in FP32
   // Order in which the row blocks of a 3D mesh are swept (0: block order).
   // With whole x-lines of blocks, tiles of ty y-rows are swept z-plane by
@@ -201,6 +207,11 @@ struct StageBufs {
   double *out;        // stage output (may alias Un)
   const double *Un;   // state at the start of the step (SSP combination)
   double ca, cb;      // out = ca * Un + cb * Phi(in)
+  // optional second output (NULL: none): out2 = cx * X2 + cy * Phi(in),
+  // read and written at the same element (X2 may alias out2)
+  double *out2;
+  const double *X2;
+  double cx, cy;
 };
 // Optional kernel timing: when a Prof is passed, each launch is bracketed by
 // HIP events on the same stream (also inside a captured graph); the host folds

@@ -412,7 +412,7 @@ __device__ __forceinline__ void begin_step(Ctl *ctl, double dt_cap, double tau_f
   } else {
     ctl->t_final = dt_cap > 0.0 ? ctl->t + dt_cap : 0.0;
   }
-  for (int s = 0; s < 3; ++s) ctl->taumin_bits[s] = 0x7ff0000000000000ull;  // +inf
+  for (int s = 0; s < kMaxStages; ++s) ctl->taumin_bits[s] = 0x7ff0000000000000ull;  // +inf
   ctl->cfl_flag = 0;
   ctl->bad_flag = 0;
   ctl->halt = 0;
@@ -474,10 +474,10 @@ __device__ __forceinline__ bool node_fields(const KArgs &A, const double *V, dou
 }
 
 // Node record of the stage input (buffer 0 or 1 by the parity of
-// 3 * steps + stage: each stage reads one buffer and its last sweep writes the
-// other, which the next stage reads).
+// nst * steps + stage: each stage reads one buffer and its last sweep writes
+// the other, which the next stage reads).
 __device__ __forceinline__ double *node_buffer(const KArgs &A, int stage) {
-  const long long k = 3 * A.ctl->steps + stage;
+  const long long k = (long long)A.nst * A.ctl->steps + stage;
   return A.Nd + (size_t)(k & 1) * (size_t)A.N * kNodeStride;
 }
 
@@ -599,11 +599,12 @@ __device__ __forceinline__ void load_rec(const double *__restrict__ rec, double 
   if (NV % 2) out[NV - 1] = rec[NV - 1];
 }
 
-// Time of a stage's boundary data: the stages of the Shu-Osher form sit at
-// t, t + tau and t + tau / 2 (tau is fixed in stage 1, whose data are at t).
+// Time of a stage's boundary data: t + c_k tau, c_k the stage's abscissa
+// (SSP-RK3: t, t + tau, t + tau / 2; tau is fixed in stage 1, whose data are
+// at t).
 __device__ __forceinline__ double stage_time(const KArgs &A, int stage) {
   const double t = A.ctl->t;
-  return stage == 0 ? t : (stage == 1 ? t + A.ctl->tau : t + 0.5 * A.ctl->tau);
+  return stage == 0 ? t : t + A.tfrac[stage] * A.ctl->tau;
 }
 
 // The isentropic vortex of Sec. 6.2 at dof i and time t (free space): with
@@ -960,18 +961,21 @@ __device__ __forceinline__ double pair_hpk(const KArgs &A, double hpk_i, double 
 }
 
 // ---------------------------------------------------------------------------
-// Resolves tau of this stage; returns false (uniformly) if the stage must stop.
-__device__ __forceinline__ bool stage_tau(const KArgs &A, int stage, double *tau) {
+// Resolves the step's tau (stage 0 picks it) and this stage's Euler step
+// tstep[stage] * tau; returns false (uniformly) if the stage must stop.
+__device__ __forceinline__ bool stage_tau(const KArgs &A, int stage, double *tau, double *tau_e) {
   if (A.ctl->halt || A.ctl->cfl_flag) return false;
   const double tm = __longlong_as_double((long long)A.ctl->taumin_bits[stage]);
   if (stage == 0) {
-    double t = A.ctl->tau_fixed > 0.0 ? A.ctl->tau_fixed : A.cfl * tm;
+    double t = A.ctl->tau_fixed > 0.0 ? A.ctl->tau_fixed : A.cfl * tm / A.tstep_max;
     if (A.ctl->dt_cap > 0.0 && t > A.ctl->dt_cap) t = A.ctl->dt_cap;
     *tau = t;
+    *tau_e = A.tstep[0] * t;
     return true;
   }
   *tau = A.ctl->tau;
-  return !(*tau > tm);
+  *tau_e = A.tstep[stage] * *tau;
+  return !(*tau_e > tm);
 }
 
 template <int D, int DEG, bool MX>
@@ -986,15 +990,15 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
   // dU^H overwrites it.
   __shared__ double stage_lds[kStage<kLimStride>];
   auto rs = [&](int q, int row) -> double & { return stage_lds[row * (kLimStride + 1) + Rec<D>::dUH + q]; };
-  double tau;
-  if (!stage_tau(A, stage, &tau)) {
+  double tau_step, tau;
+  if (!stage_tau(A, stage, &tau_step, &tau)) {
     if (stage > 0 && blk == 0 && threadIdx.x == 0 && A.ctl->cfl_flag == 0 && A.ctl->halt == 0) {
       A.ctl->viol_stage = stage;
       atomicOr(&A.ctl->cfl_flag, 1);
     }
     return;
   }
-  if (stage == 0 && blk == 0 && threadIdx.x == 0) A.ctl->tau = tau;
+  if (stage == 0 && blk == 0 && threadIdx.x == 0) A.ctl->tau = tau_step;
   using R = Rec<D>;
   const double *__restrict__ nd = node_buffer(A, stage);
   const int lane = threadIdx.x;
@@ -1108,8 +1112,10 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
     for (int q = 0; q < M; ++q) lr[R::LU + q] = ni.U[q];
     for (int q = 0; q < M; ++q) rs(q, lane) = -accH[q];
     if (A.scheme == 0 || (A.scheme == 2 && A.passes == 0)) {
-      for (int q = 0; q < M; ++q)
+      for (int q = 0; q < M; ++q) {
         sb.out[q * N + i] = sb.ca == 0.0 ? UL[q] : sb.ca * sb.Un[q * N + i] + sb.cb * UL[q];
+        if (sb.out2) sb.out2[q * N + i] = sb.cx * sb.X2[q * N + i] + sb.cy * UL[q];
+      }
       if (!(UL[0] > 0.0) || !(eps_of<D>(UL) > 0.0)) atomicOr(&A.ctl->bad_flag, 1);
     }
   }
@@ -1140,8 +1146,10 @@ __device__ __forceinline__ void sweep2_body(const KArgs &A, const StageBufs &sb,
   if (A.scheme == 1) {
     double V[M];
     for (int q = 0; q < M; ++q) V[q] = ni.U[q] + du[q];
-    for (int q = 0; q < M; ++q)
+    for (int q = 0; q < M; ++q) {
       sb.out[q * N + i] = sb.ca == 0.0 ? V[q] : sb.ca * sb.Un[q * N + i] + sb.cb * V[q];
+      if (sb.out2) sb.out2[q * N + i] = sb.cx * sb.X2[q * N + i] + sb.cy * V[q];
+    }
     if (!(V[0] > 0.0) || !(eps_of<D>(V) > 0.0)) atomicOr(&A.ctl->bad_flag, 1);
   }
   }
@@ -1239,7 +1247,7 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
   // and stored by the whole wavefront); rows outside the block compute nothing
   double V[M];
   if (lane < nrows) {
-  const double tau = A.ctl->tau;
+  const double tau = A.tstep[stage] * A.ctl->tau;
   const int a = (int)(i % NLOC);
   if (pass == 1 && final_pass && A.accepted[i]) {
     // pass 1 accepted every pair and the boundary part of this row whole:
@@ -1388,6 +1396,7 @@ __device__ __forceinline__ void limit_body(const KArgs &A, const StageBufs &sb, 
       for (int q = 0; q < M; ++q) {
         O[q] = sb.ca == 0.0 ? V[q] : sb.ca * sb.Un[q * N + i] + sb.cb * V[q];
         sb.out[q * N + i] = O[q];
+        if (sb.out2) sb.out2[q * N + i] = sb.cx * sb.X2[q * N + i] + sb.cy * V[q];
       }
       if (!(V[0] > 0.0) || !(eps_of<D>(V) > 0.0)) atomicOr(&A.ctl->bad_flag, 1);
       stage_node<D>(A, stage_row<kNodeStride>(stage_lds, lane), O);

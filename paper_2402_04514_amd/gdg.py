@@ -23,6 +23,7 @@ GDG_DATA_CONSTANT, GDG_DATA_VORTEX = 0, 1
 GDG_LOW_ORDER, GDG_HIGH_ORDER, GDG_LIMITED = 0, 1, 2
 GDG_FLAG_NO_QUIET_ROWS = 1
 GDG_FP64, GDG_MIXED = 0, 1
+GDG_SSPRK3, GDG_SSPRK54 = 0, 1
 (GDG_FIELD_STATE, GDG_FIELD_EV_N, GDG_FIELD_BOUNDS, GDG_FIELD_UL, GDG_FIELD_DUH,
  GDG_FIELD_U1) = range(6)
 _FIELD_PLANES = {GDG_FIELD_EV_N: 1, GDG_FIELD_BOUNDS: 3}
@@ -51,7 +52,7 @@ class gdg_params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("cfl", C.c_double), ("c_ev", C.c_double),
                 ("c_k", C.c_double), ("c_r", C.c_double), ("p_r", C.c_double),
                 ("limiter_passes", C.c_int32), ("scheme", C.c_int32), ("precision", C.c_int32),
-                ("flags", C.c_int32)]
+                ("flags", C.c_int32), ("integrator", C.c_int32), ("reserved", C.c_int32)]
 
 
 class gdg_stats(C.Structure):

@@ -1,0 +1,135 @@
+"""GPU parity of SSPRK(5,4) (the fourth-order SSP method Sec. 6.2 uses for
+the isentropic vortex) against the oracle's, through the C-ABI, on the same
+seeded inputs: steps, simulated time and the state element by element at
+1e-10 of each component's scale; the captured-graph loop against single
+host-driven steps bit for bit; a restarted step (a fixed tau above the CFL
+bound of a later stage) against the oracle's restart rule; the single-stage
+call unchanged by the context's integrator.
+"""
+import numpy as np
+import pytest
+
+from paper_2402_04514_amd import gdg
+from paper_2402_04514_amd import workloads as W
+
+from test_gpu_parity import CASES as PAR, _close
+
+pytestmark = pytest.mark.gpu
+
+G53 = 5.0 / 3.0
+
+
+def _say(msg):
+    print("[gpu-rk54] " + msg, flush=True)
+
+
+def _vortex(n, k, x0=(-1.0, -1.0)):
+    ms = W.MeshSpec(2, k, (n, n), (-5.0, -5.0), (5.0, 5.0), (W.BC_DIRICHLET,) * 4,
+                    vortex=(5.0, x0[0], x0[1], 1.0, 1.0, G53))
+    x, _ = W.node_coords(ms)
+    return ms, W.vortex_exact(x, 0.0, x0=x0, gamma=G53, periodic=False)
+
+
+CASES = {
+    "q1_2d_periodic": (PAR["q1_2d_periodic"], gdg.GDG_LIMITED),
+    "q2_2d_slip": (PAR["q2_2d_slip"], gdg.GDG_LIMITED),
+    "q3_2d_slip_ragged": (PAR["q3_2d_slip_ragged"], gdg.GDG_LIMITED),
+    "q1_3d_mixed": (PAR["q1_3d_mixed"], gdg.GDG_LIMITED),
+    "q3_1d_outflow_high_order": (PAR["q3_1d_outflow"], gdg.GDG_HIGH_ORDER),
+    "q2_2d_outflow_low_order": (PAR["q2_2d_outflow"], gdg.GDG_LOW_ORDER),
+    "vortex_q2_dirichlet": ((lambda: _vortex(10, 2, x0=(2.0, 2.0))), gdg.GDG_LIMITED),
+    "vortex_q3_dirichlet": ((lambda: _vortex(8, 3, x0=(2.5, 2.5))), gdg.GDG_LIMITED),
+}
+
+
+def _pair(oracle, name):
+    make, scheme = CASES[name]
+    ms, U = make()
+    gamma = G53 if ms.vortex is not None else 1.4
+    M = oracle.Mesh(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc, bstate=ms.bstate, vortex=ms.vortex)
+    p = gdg.gdg_default_params(ms.degree)
+    p.gamma = gamma
+    p.scheme = scheme
+    p.integrator = gdg.GDG_SSPRK54
+    S = gdg.Solver.from_spec(ms, p)
+    S.upload(U)
+    op = oracle.params(gamma=gamma, degree=ms.degree, scheme=scheme, integrator=oracle.SSPRK54)
+    return ms, U, M, S, op
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_steps(oracle, name):
+    _say("steps " + name)
+    ms, U, M, S, op = _pair(oracle, name)
+    Uo, t_o, n_o = M.run_to(op, U, 1.0, max_steps=10)
+    st = S.run_to(1.0, max_steps=10)
+    assert st.steps == n_o == 10 and st.t == pytest.approx(t_o, rel=1e-12)
+    assert st.restarts == 0
+    _close(S.download(), Uo, tol=1e-10, what="U after 10 SSPRK(5,4) steps")
+
+
+@pytest.mark.parametrize("name", ["q2_2d_slip", "vortex_q2_dirichlet"])
+def test_first_step_and_cfl_rule(oracle, name):
+    """One step: tau = Cr tau_max(U^n) / max_k r_k as the oracle takes it,
+    and the state at 1e-11."""
+    _say("first step " + name)
+    ms, U, M, S, op = _pair(oracle, name)
+    Uo, dt_o, nres, st = M.step(op, U)
+    assert st == 0 and nres == 0
+    dt = S.step()
+    assert dt == pytest.approx(dt_o, rel=1e-14)
+    _close(S.download(), Uo, tol=1e-11, what="U after one step")
+
+
+def test_graph_loop_equals_host_steps(oracle):
+    """Twenty steps through the captured graph against twenty single
+    host-driven steps: the same bits."""
+    _say("graph vs host steps")
+    _, U, _, A, _ = _pair(oracle, "q2_2d_slip")
+    _, _, _, B, _ = _pair(oracle, "q2_2d_slip")
+    st = A.run_to(10.0, max_steps=20)
+    t = 0.0
+    for _ in range(20):
+        t += B.step(dt_cap=10.0 - t)
+    assert st.steps == 20 and st.t == t
+    assert np.array_equal(A.download(), B.download())
+
+
+def test_restart_rule(oracle):
+    """A fixed tau whose first Euler step is within the bound of U^n but whose
+    later stages exceed theirs: the device restarts as the oracle does
+    (tau = Cr tau_max(u_k) / r_k), the same number of times, and lands on
+    the oracle's state."""
+    _say("restart")
+    ms, U, M, S, op = _pair(oracle, "q1_2d_periodic")
+    _, dg = M.stage(op, U, diag=True)
+    tau = 2.3 * dg["tau_max"]  # r_0 tau = 0.90 tau_max, r_1 tau = 1.52 tau_max
+    Uo, dt_o, nres, st = M.step(op, U, dt_fixed=tau)
+    assert st == 0 and nres >= 1
+    dt = S.step(dt_fixed=tau)
+    assert S.stats().restarts == nres
+    assert dt == pytest.approx(dt_o, rel=1e-13)
+    _close(S.download(), Uo, tol=1e-11, what="U after a restarted step")
+
+
+def test_single_stage_ignores_the_integrator(oracle):
+    """gdg_stage() is one forward-Euler stage of Cr tau_max whatever the
+    context's integrator."""
+    _say("single stage")
+    ms, U, M, S, op = _pair(oracle, "q2_2d_slip")
+    out, dg = M.stage(op, U, diag=True)
+    assert S.stage(0.0) == pytest.approx(op.cfl * dg["tau_max"], rel=1e-13)
+    _close(S.download(), out, what="Phi(U)")
+
+
+def test_server_refuses_ssprk54():
+    _say("server refusal")
+    srv = gdg.Server(2, 1, budget_bytes=64 << 20)
+    ms = W.MeshSpec(2, 1, (8, 8), (0.0, 0.0), (1.0, 1.0), (0,) * 4)
+    p = gdg.gdg_default_params(1)
+    p.integrator = gdg.GDG_SSPRK54
+    x, _ = W.node_coords(ms)
+    U0 = W.to_conserved(1.0 + 0 * x[:, 0], np.zeros((2, len(x))), 1.0 + 0 * x[:, 0])
+    with pytest.raises(gdg.GdgError):
+        srv.submit(ms, U0, 0.1, params=p)
+    srv.close()

@@ -35,6 +35,9 @@ def test_default_params_are_the_papers():
     p = gdg.gdg_default_params(1)
     assert (p.gamma, p.cfl, p.c_ev, p.c_k, p.c_r, p.p_r) == (1.4, 0.5, 1.0, 1.0, 4.0, 1.5)
     assert (p.limiter_passes, p.scheme, p.precision) == (2, gdg.GDG_LIMITED, gdg.GDG_FP64)
+    assert p.integrator == gdg.GDG_SSPRK3
+    p.integrator = gdg.GDG_SSPRK54
+    assert gdg.gdg_workspace_bytes(gdg.mesh_desc(2, 1, (8, 8), (0, 0), (1, 1), (1,) * 4), p) > 0
     assert gdg.gdg_default_params(2).c_ev == 0.5
     with pytest.raises(gdg.GdgError):
         gdg.gdg_default_params(7)
@@ -125,7 +128,8 @@ def test_dirichlet_data_validated(kind, state, ok):
 
 
 @pytest.mark.parametrize("field,value", [("gamma", 2.0), ("gamma", 1.0), ("cfl", 0.0), ("cfl", 1.5),
-                                         ("limiter_passes", 3), ("scheme", 5), ("precision", 9)])
+                                         ("limiter_passes", 3), ("scheme", 5), ("precision", 9),
+                                         ("integrator", 2), ("integrator", -1)])
 def test_invalid_params_rejected(field, value):
     p = gdg.gdg_default_params(1)
     setattr(p, field, value)
@@ -292,9 +296,12 @@ def test_continuous_elements_validated():
     assert gdg.gdg_workspace_bytes(m, p) > 0
     with pytest.raises(gdg.GdgError):
         gdg.gdg_workspace_bytes(gdg.mesh_desc(2, 2, (2, 3), (0, 0), (1, 1), (0, 0, 1, 1), continuous=True), p)
-    with pytest.raises(gdg.GdgError):
+    # general cells are accepted (the integrals go through the cell maps)
+    assert gdg.gdg_workspace_bytes(gdg.mesh_desc(2, 2, (4, 3), (0, 0), (1, 1), (1,) * 4, continuous=True,
+                                                 vertices=W.lattice((4, 3), (0, 0), (1, 1))), p) > 0
+    with pytest.raises(gdg.GdgError):  # boundary parts are not
         gdg.gdg_workspace_bytes(gdg.mesh_desc(2, 2, (4, 3), (0, 0), (1, 1), (1,) * 4, continuous=True,
-                                              vertices=W.lattice((4, 3), (0, 0), (1, 1))), p)
+                                              bc_cells=np.full(2 * 3 + 2 * 4, 1, dtype=np.int8)), p)
 
 
 def _create_error(m, p):
