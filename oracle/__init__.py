@@ -120,6 +120,8 @@ def lib():
         L.or_stage.argtypes = [C.c_void_p, C.POINTER(_Params), _DP, C.c_double, _DP,
                                C.POINTER(_Diag)]
         L.or_tau_rows.argtypes = [C.c_void_p, C.POINTER(_Params), _DP, _DP]
+        L.or_set_step_start_data.restype = None
+        L.or_set_step_start_data.argtypes = [C.c_void_p]
         L.or_ssprk54_table.restype = None
         L.or_ssprk54_table.argtypes = [_DP, _DP]
         L.or_step.restype = C.c_int
@@ -155,7 +157,7 @@ class Mesh:
     """Uniform Cartesian DG Q_k mesh with the stencil of Sec. 2.3."""
 
     def __init__(self, dim, degree, cells, lo, hi, bc, bstate=None, vortex=None, vertices=None, bc_cells=None,
-                 map_degree=1, continuous=False):
+                 map_degree=1, continuous=False, step_start_data=False):
         """bc: kinds per box face 2*axis+side (0 periodic, 1 outflow, 2 slip,
         3 Dirichlet, 4 supersonic in/outflow, 5 sub- and supersonic
         in/outflow).  bstate: per face the conserved Dirichlet data U^d of
@@ -171,7 +173,9 @@ class Mesh:
         eq. cijcidefCg; the low-order scheme only.  bc_cells:
         a kind per boundary cell face (kinds 1-5): for each non-periodic box
         face in order, its cells lexicographically over the other axes, the
-        lowest axis fastest; data kinds take that box face's data."""
+        lowest axis fastest; data kinds take that box face's data.
+        step_start_data: the data of kinds 3-5 are the node's own state at
+        the start of the step (strategy (d) of Sec. 6.3)."""
         self.dim, self.degree = dim, degree
         self.cells = tuple(int(c) for c in cells)
         self.lo = tuple(float(x) for x in lo)
@@ -204,6 +208,8 @@ class Mesh:
             assert v.shape == (6,)
             if L.or_set_vortex_data(self._h, _dp(v)) != 0:
                 raise ValueError("vortex boundary data needs a 2D mesh")
+        if step_start_data:
+            L.or_set_step_start_data(self._h)
         kinds = [{self.bc[f]} for f in range(2 * dim)]
         if bc_cells is not None:
             k = np.ascontiguousarray(bc_cells, dtype=np.int8).ravel()
@@ -220,7 +226,7 @@ class Mesh:
             if L.or_set_boundary_kinds(self._h, k.ctypes.data_as(C.POINTER(C.c_byte))) != 0:
                 raise ValueError("bc_cells holds a periodic or unknown kind")
         for f in range(2 * dim):
-            if kinds[f] & {3, 4, 5} and vortex is None:
+            if kinds[f] & {3, 4, 5} and vortex is None and not step_start_data:
                 if bstate is None or bstate[f] is None:
                     raise ValueError("face %d needs Dirichlet data" % f)
                 v = np.ascontiguousarray(bstate[f], dtype=np.float64)

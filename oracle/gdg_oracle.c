@@ -60,6 +60,11 @@ typedef struct {
    * beta, x0 (2), u_inf (2), gamma of the data; evaluated at the node and the
    * stage time */
   int vortex_data;
+  /* strategy (d) of Sec. 6.3: the data of every Dirichlet-type face are the
+   * node's own state at the start of the step, U^n_i, kept here by the step
+   * (and by a single stage: its input) */
+  int step_start_data;
+  double *un;
   double vortex[6];
   double t0;                  /* time at the start of the step (boundary data) */
   long ncells, ndofs;
@@ -517,7 +522,7 @@ void or_destroy(or_setup *S) {
   if (!S) return;
   free(S->rowptr); free(S->col); free(S->c); free(S->mij); free(S->kind); free(S->mi);
   free(S->bptr); free(S->bface); free(S->bkind); free(S->bc_c); free(S->vx);
-  free(S->ucp); free(S->unb); free(S->unf); free(S->ubc); free(S->cgx);
+  free(S->ucp); free(S->unb); free(S->unf); free(S->ubc); free(S->cgx); free(S->un);
   free(S);
 }
 
@@ -1457,6 +1462,10 @@ static void vortex_at(const double *vp, const double *x, double t, double *U) {
 /* Dirichlet data U^d of box face f at node i and time t (Sec. 4.1: the data
  * at position x_i for time t). */
 static void data_state(const or_setup *S, int f, long i, double t, double *Ud) {
+  if (S->step_start_data) {
+    for (int c = 0; c < S->m; ++c) Ud[c] = S->un[(long)c * S->ndofs + i];
+    return;
+  }
   if (S->vortex_data) {
     double x[3];
     node_x(S, i, x);
@@ -1574,6 +1583,18 @@ int or_set_vortex_data(or_setup *S, const double *params) {
   S->vortex_data = 1;
   for (int k = 0; k < 6; ++k) S->vortex[k] = params[k];
   return 0;
+}
+
+/* Boundary data of every Dirichlet-type face from the step's start state at
+ * the node (strategy (d) of Sec. 6.3). */
+void or_set_step_start_data(or_setup *S) {
+  S->step_start_data = 1;
+  if (!S->un) S->un = (double *)calloc((size_t)S->m * S->ndofs, sizeof(double));
+}
+
+/* Keeps U^n for step-start data. */
+static void keep_step_start(const or_setup *S, const double *U) {
+  if (S->step_start_data) memcpy(S->un, U, (size_t)S->m * S->ndofs * sizeof(double));
 }
 
 /* Dirichlet data U^d (conserved, m components) of box face f, used by the
@@ -1735,6 +1756,7 @@ static int stage_at(const or_setup *S, const or_params *P, const double *U, doub
 /* One stage at the time of the step's start (or_set_time). */
 int or_stage(const or_setup *S, const or_params *P, const double *U, double tau, double *Uout,
              or_diag *dg) {
+  keep_step_start(S, U);
   return stage_at(S, P, U, tau, S->t0, Uout, dg);
 }
 
@@ -2245,6 +2267,7 @@ static int step_rk54(const or_setup *S, const or_params *P, double *U, double dt
 
 int or_step(const or_setup *S, const or_params *P, double *U, double dt_cap, double dt_fixed,
             double *dt_taken, int *restarts) {
+  keep_step_start(S, U);
   if (P->integrator == 1) return step_rk54(S, P, U, dt_cap, dt_fixed, dt_taken, restarts);
   const long M = (long)S->m * S->ndofs;
   double *Ua = dalloc(M), *Ub = dalloc(M), *Ph = dalloc(M);

@@ -27,6 +27,10 @@ RK54 = T + "test_oracle_rk54.py"
 
 MUTANTS = {
     # name: (original text, planted text, pin files that must fail)
+    "step_start_data_from_the_stage_input": ("                    or_diag *dg) {\n  const int dim = S->dim, m = S->m;",
+                                             "                    or_diag *dg) {\n  keep_step_start(S, U);\n"
+                                             "  const int dim = S->dim, m = S->m;",
+                                             [INOUT + "::test_step_start_data_is_the_state_at_the_step_start"]),
     "rk54_last_stage_takes_u3": ("acc[q] = rk54_a[5][2] * u[2][q]", "acc[q] = rk54_a[5][2] * u[3][q]",
                                  [RK54 + "::test_step_equals_the_butcher_form_with_stage_times"]),
     "rk54_stage_time_from_substep": ("S->t0 + c[k] * tau", "S->t0 + r[k] * tau",
