@@ -80,12 +80,18 @@ typedef enum {
 /* Source of the data U^d of the DIRICHLET, SUPERSONIC and INOUTFLOW faces. */
 typedef enum {
   GDG_DATA_CONSTANT = 0, /* bc_state[f], constant in space and time */
-  GDG_DATA_VORTEX = 1    /* the isentropic vortex of Sec. 6.2 at the node and
+  GDG_DATA_VORTEX = 1,   /* the isentropic vortex of Sec. 6.2 at the node and
                             the stage time (2D): vortex[] = beta, x0 (2),
                             u_inf (2), gamma of the data; free space (no
                             periodic images).  The SSP-RK3 stages take their
                             data at t, t + tau and t + tau / 2; those of
                             SSPRK(5,4) at t + c_k tau (gdg_integrator). */
+  GDG_DATA_STEP_START = 2 /* U^d_i = U^n_i, the node's own state at the start
+                            of the step, in every stage (strategy (d) of
+                            Sec. 6.3, for flows without known boundary
+                            data); bc_state is not read.  Lattice, general
+                            and unstructured meshes; not continuous
+                            elements, not served. */
 } gdg_data_kind;
 
 /* GDG_LOW_ORDER: eq. cijdijscheme only.  GDG_HIGH_ORDER: eq. HighScheme

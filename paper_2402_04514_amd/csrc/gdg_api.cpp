@@ -145,7 +145,7 @@ bool validate(const gdg_mesh_desc *m, const gdg_params *p, std::string *err) {
     if (m->ucells > 0) {
       for (int side = 0; side < 2; ++side) {
         const int f = 2 * e + side;
-        if (!face_has_data(m, f) || m->data_kind == GDG_DATA_VORTEX) continue;
+        if (!face_has_data(m, f) || m->data_kind != GDG_DATA_CONSTANT) continue;
         const double *V = m->bc_state[f];
         double m2 = 0.0;
         for (int k = 0; k < m->dim; ++k) m2 += V[1 + k] * V[1 + k];
@@ -174,7 +174,7 @@ bool validate(const gdg_mesh_desc *m, const gdg_params *p, std::string *err) {
     for (int side = 0; side < 2; ++side) {
       const int f = 2 * e + side;
       if (!face_has_data(m, f)) continue;
-      if (m->data_kind == GDG_DATA_VORTEX) continue;  // checked below
+      if (m->data_kind != GDG_DATA_CONSTANT) continue;  // vortex: checked below; step start: U^n
       // the face's data must lie in A (eq. AddSet)
       const double *V = m->bc_state[f];
       double m2 = 0.0;
@@ -186,15 +186,15 @@ bool validate(const gdg_mesh_desc *m, const gdg_params *p, std::string *err) {
       }
     }
   }
-  if (m->data_kind != GDG_DATA_CONSTANT && m->data_kind != GDG_DATA_VORTEX) {
+  if (m->data_kind != GDG_DATA_CONSTANT && m->data_kind != GDG_DATA_VORTEX && m->data_kind != GDG_DATA_STEP_START) {
     *err = "unknown boundary data kind";
     return false;
   }
   if (m->continuous != 0 && m->continuous != 1) { *err = "continuous must be 0 or 1"; return false; }
   if (m->continuous) {
-    if (m->bc_cells || m->ucells > 0 || m->data_kind == GDG_DATA_VORTEX) {
-      *err = "continuous elements are built for lattices of cells (no bc_cells, unstructured cells or vortex "
-             "data)";
+    if (m->bc_cells || m->ucells > 0 || m->data_kind != GDG_DATA_CONSTANT) {
+      *err = "continuous elements are built for lattices of cells (no bc_cells, unstructured cells, vortex or "
+             "step-start data)";
       return false;
     }
     if (p->scheme != GDG_LOW_ORDER) {
@@ -652,6 +652,7 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   A.kscale = (double *)(ws + L.off_kscale);
   for (int k = 0; k < 3; ++k) ctx->U[k] = (double *)(ws + L.off_U[k]);
   ctx->cur = 0;
+  A.uold = ctx->U[0];
   A.Nd = (double *)(ws + L.off_Nd);
   A.Qd = (double *)(ws + L.off_Qd);
   A.Ld = (double *)(ws + L.off_Ld);
@@ -724,6 +725,7 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
     for (int k = 0; k < 4; ++k) T->xg[k] = xg[k];
   }
   A.vortex_data = mesh->data_kind == GDG_DATA_VORTEX ? 1 : 0;
+  A.old_data = mesh->data_kind == GDG_DATA_STEP_START ? 1 : 0;
   for (int k = 0; k < 6; ++k) A.vx[k] = mesh->vortex[k];
   for (int e = 0; e < 3; ++e) {
     A.lo[e] = e < mesh->dim ? mesh->lo[e] : 0.0;
@@ -1083,6 +1085,7 @@ gdg_status gdg_stage(gdg_ctx *ctx, double tau, double *tau_used) {
   if (gdg_status s = harvest(ctx)) return s;
   if (ctx->hctl.bad_flag) return gdg::flag_status(ctx, ctx->hctl.bad_flag, "the stage output left the admissible set");
   ctx->cur = c1;
+  ctx->A.uold = ctx->U[c1];
   drop_graph(ctx);  // the captured graph names the old buffer roles
   // the node records of the next stage input: the step counter did not move,
   // so the next step reads the buffer this stage read

@@ -527,7 +527,7 @@ __device__ __forceinline__ void stage_node(const KArgs &A, double *row, const do
 template <int D>
 __global__ void k_bnodes(KArgs A, RefTables *T) {
   const int f = threadIdx.x;
-  if (f >= 2 * D || A.vortex_data) return;  // time-dependent data: evaluated where used
+  if (f >= 2 * D || A.vortex_data || A.old_data) return;  // data that vary: evaluated where used
   if (!((A.bcdata >> f) & 1)) return;        // no part of the face takes data
   double V[D + 2], W[D + 6];
   for (int q = 0; q < D + 2; ++q) V[q] = T->bstate[f][q];
@@ -638,9 +638,18 @@ template <int D>
 __device__ __forceinline__ void node_from_state(const KArgs &A, const double *V, Node<D> &n);
 
 // Data U^d of face f at dof i and time t, as a node (state and fields): the
-// face's constant data (fields computed at set-up) or the vortex.
+// face's constant data (fields computed at set-up), the vortex, or the
+// node's state at the start of the step.  A stage that writes U^n (the last
+// one) writes row i's output after every read of row i's data, in the same
+// thread.
 template <int D, int DEG>
 __device__ __forceinline__ void data_node(const KArgs &A, int f, int64_t i, double t, Node<D> &d) {
+  if (A.old_data) {
+    double V[D + 2];
+    for (int q = 0; q < D + 2; ++q) V[q] = A.uold[q * A.N + i];
+    node_from_state<D>(A, V, d);
+    return;
+  }
   if (D == 2 && A.vortex_data) {
     double V[D + 2];
     vortex_state<D, DEG>(A, i, t, V);

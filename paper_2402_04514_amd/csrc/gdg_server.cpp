@@ -434,6 +434,10 @@ gdg_status gdg_server_submit(gdg_server *s, const gdg_mesh_desc *mesh, const gdg
     s->err = "the server steps with SSP-RK3 only";
     return GDG_E_INVALID;
   }
+  if (mesh->data_kind == GDG_DATA_STEP_START) {
+    s->err = "step-start boundary data are not served";
+    return GDG_E_INVALID;
+  }
   if (mesh->dim != s->d.dim || mesh->degree != s->d.degree || prm->precision != s->d.precision) {
     s->err = "request outside the server's class (dim, degree, precision)";
     return GDG_E_INVALID;

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libgdg.so")
  GDG_E_BOUNDARY) = (0, -1, -2, -3, -4, -5, -6, -7)
 GDG_REQ_PENDING, GDG_REQ_RUNNING, GDG_REQ_DONE, GDG_REQ_FAILED = 0, 1, 2, 3
 GDG_BC_PERIODIC, GDG_BC_OUTFLOW, GDG_BC_SLIP, GDG_BC_DIRICHLET, GDG_BC_SUPERSONIC, GDG_BC_INOUTFLOW = 0, 1, 2, 3, 4, 5
-GDG_DATA_CONSTANT, GDG_DATA_VORTEX = 0, 1
+GDG_DATA_CONSTANT, GDG_DATA_VORTEX, GDG_DATA_STEP_START = 0, 1, 2
 GDG_LOW_ORDER, GDG_HIGH_ORDER, GDG_LIMITED = 0, 1, 2
 GDG_FLAG_NO_QUIET_ROWS = 1
 GDG_FP64, GDG_MIXED = 0, 1
@@ -141,7 +141,7 @@ def _check(st, ctx=None):
 
 
 def mesh_desc(dim, degree, cells, lo, hi, bc, bstate=None, vortex=None, vertices=None,
-              bc_cells=None, map_degree=1, continuous=False) -> gdg_mesh_desc:
+              bc_cells=None, map_degree=1, continuous=False, step_start_data=False) -> gdg_mesh_desc:
     """bstate: per face the conserved Dirichlet data of the DIRICHLET,
     SUPERSONIC and INOUTFLOW kinds (None, or None entries, elsewhere); vortex:
     (beta, x0_1, x0_2, u_1, u_2, gamma) to take that data from the isentropic
@@ -151,10 +151,14 @@ def mesh_desc(dim, degree, cells, lo, hi, bc, bstate=None, vortex=None, vertices
     cells, vertices the lattice of 2 cells + 1 points per axis of their
     quadratic maps.  bc_cells: a kind per
     boundary cell face (for each non-periodic box face in order, its cells
-    lexicographically over the other axes, the lowest axis fastest)."""
+    lexicographically over the other axes, the lowest axis fastest).
+    step_start_data: the data of those kinds are the node's own state at the
+    start of the step (GDG_DATA_STEP_START)."""
     m = gdg_mesh_desc()
     m.dim, m.degree = dim, degree
     m.continuous = 1 if continuous else 0
+    if step_start_data:
+        m.data_kind = GDG_DATA_STEP_START
     for e in range(3):
         m.cells[e] = int(cells[e]) if e < dim else 1
         m.lo[e] = float(lo[e]) if e < dim else 0.0
@@ -340,13 +344,14 @@ class Solver:
 
     def __init__(self, dim, degree, cells, lo, hi, bc, params: gdg_params | None = None,
                  device="cuda:0", stream=None, bstate=None, vortex=None, vertices=None, bc_cells=None,
-                 map_degree=1, desc=None, continuous=False):
+                 map_degree=1, desc=None, continuous=False, step_start_data=False):
         import torch
         self.torch = torch
         self.dim, self.m = dim, dim + 2
         # desc: a ready descriptor (an unstructured mesh's, umesh_desc)
         self.mesh = desc if desc is not None else mesh_desc(dim, degree, cells, lo, hi, bc, bstate, vortex,
-                                                            vertices, bc_cells, map_degree, continuous)
+                                                            vertices, bc_cells, map_degree, continuous,
+                                                            step_start_data)
         self.params = params if params is not None else gdg_default_params(degree)
         self.device = torch.device(device)
         nbytes = gdg_workspace_bytes(self.mesh, self.params)

@@ -326,3 +326,19 @@ def test_create_refuses_bad_general_and_unstructured_meshes():
     cp3 = np.concatenate([cp, cp[:1]])  # a cell twice: its faces on three cells
     fb3 = np.full((len(cp3), 4), 2, dtype=np.int8)
     assert "more than two" in _create_error(gdg.umesh_desc(2, 1, cp3, P, fb3), p)
+
+
+def test_step_start_data_validated():
+    """GDG_DATA_STEP_START needs no face data (bc_state is not read), is
+    refused for continuous elements, and an unknown data kind is refused."""
+    p = gdg.gdg_default_params(1)
+    m = gdg.mesh_desc(2, 1, (8, 8), (0, 0), (1, 1), (gdg.GDG_BC_INOUTFLOW,) * 4, step_start_data=True)
+    assert m.data_kind == gdg.GDG_DATA_STEP_START
+    assert gdg.gdg_workspace_bytes(m, p) > 0
+    m.data_kind = 3
+    with pytest.raises(gdg.GdgError):
+        gdg.gdg_workspace_bytes(m, p)
+    p.scheme = gdg.GDG_LOW_ORDER
+    with pytest.raises(gdg.GdgError):
+        gdg.gdg_workspace_bytes(gdg.mesh_desc(2, 1, (8, 8), (0, 0), (1, 1), (3,) * 4, continuous=True,
+                                              step_start_data=True), p)

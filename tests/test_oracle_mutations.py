@@ -40,7 +40,8 @@ MUTANTS = {
     "cg_boundary_pair_term_sign": ("          cc[((size_t)i * span + off) * dim + e] -= 0.5 * n * face_integral(S, f, a, b, 1);",
                                    "          cc[((size_t)i * span + off) * dim + e] += 0.5 * n * face_integral(S, f, a, b, 1);",
                                    [CG + "::test_skew_symmetry_and_partition_of_unity"]),
-    "cg_mass_not_summed_over_cells": ("      S->mi[i] += cell_integral(S, 2, pa);", "      S->mi[i] = cell_integral(S, 2, pa);",
+    "cg_mass_not_summed_over_cells": ("      S->mi[i] += S->vx ? tm[0] : cell_integral(S, 2, pa);",
+                                      "      S->mi[i] = S->vx ? tm[0] : cell_integral(S, 2, pa);",
                                       [CG + "::test_hand_values_1d_q1"]),
     "unstructured_neighbour_mirrored": ("      if (!same_cell && S->ucp) {", "      if (0) {",
                                         [UNSTR + "::test_renumbered_lattice_gives_the_lattice_result"]),
