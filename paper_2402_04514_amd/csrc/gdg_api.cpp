@@ -54,7 +54,7 @@ thread_local std::string g_create_err;
 struct Layout {
   int nloc, nb1, R, cpb, W, M;
   int64_t N, ncells, nblocks, nslots;
-  size_t off_ref, off_ctl, off_col, off_c, off_meta, off_kscale, off_U[3], off_Nd, off_Qd, off_Ld, off_U1d,
+  size_t off_ref, off_ctl, off_col, off_c, off_meta, off_kscale, off_U[3], off_Nd, off_Nold, off_Qd, off_Ld, off_U1d,
       off_dL, off_l1, off_acc, off_fsum, off_red, off_cnt, off_mrow, off_hprow, off_relrow, off_cmblk, off_cminv,
       off_bcc, total;
   int64_t bcc_off[6], nbcc;  // boundary parts: first entry of each face, and the count
@@ -300,6 +300,7 @@ Layout layout(const gdg_mesh_desc *m, const gdg_params *p) {
   L.off_kscale = take(N * 8);
   for (int k = 0; k < 3; ++k) L.off_U[k] = take(M * N * 8);
   L.off_Nd = take(2 * N * kNodeStride * 8);
+  L.off_Nold = m->data_kind == GDG_DATA_STEP_START ? take(N * kNodeStride * 8) : 0;
   L.off_Qd = take(N * kQStride * 8);
   L.off_Ld = take(N * kLimStride * 8);
   L.off_U1d = take(N * kU1Stride * 8);
@@ -652,8 +653,9 @@ gdg_status gdg_create(const gdg_mesh_desc *mesh, const gdg_params *prm, void *de
   A.kscale = (double *)(ws + L.off_kscale);
   for (int k = 0; k < 3; ++k) ctx->U[k] = (double *)(ws + L.off_U[k]);
   ctx->cur = 0;
-  A.uold = ctx->U[0];
+
   A.Nd = (double *)(ws + L.off_Nd);
+  A.Nold = mesh->data_kind == GDG_DATA_STEP_START ? (double *)(ws + L.off_Nold) : nullptr;
   A.Qd = (double *)(ws + L.off_Qd);
   A.Ld = (double *)(ws + L.off_Ld);
   A.U1d = (double *)(ws + L.off_U1d);
@@ -1085,7 +1087,6 @@ gdg_status gdg_stage(gdg_ctx *ctx, double tau, double *tau_used) {
   if (gdg_status s = harvest(ctx)) return s;
   if (ctx->hctl.bad_flag) return gdg::flag_status(ctx, ctx->hctl.bad_flag, "the stage output left the admissible set");
   ctx->cur = c1;
-  ctx->A.uold = ctx->U[c1];
   drop_graph(ctx);  // the captured graph names the old buffer roles
   // the node records of the next stage input: the step counter did not move,
   // so the next step reads the buffer this stage read

@@ -150,9 +150,9 @@ struct KArgs {
   // u_inf, gamma) at the node and the stage time instead of bnode
   int32_t vortex_data;
   // data of the Dirichlet-type faces from U^n, the state at the start of the
-  // step (U[cur] of the context: whole until the step's last stage writes it)
+  // step: its node records, written by the step's first stage
   int32_t old_data;
-  const double *uold;
+  double *Nold;
   double vx[6];
   double lo[3], hx[3];  // box corner and cell sizes (node coordinates)
   double gamma, cfl, c_ev, c_k, pk, c_r, p_r, vol;

@@ -559,6 +559,16 @@ __global__ __launch_bounds__(kBlockThreads) void k_prim(KArgs A, const double *_
   prim_rows<D>(A, U, row0, nrows, node_buffer(A, stage));
 }
 
+// Node records of U^n for step-start boundary data, from the first stage's
+// input (U^n itself), in a buffer of their own that the step's later stages
+// do not write.
+template <int D>
+__global__ __launch_bounds__(kBlockThreads) void k_start_records(KArgs A, const double *__restrict__ U) {
+  const int64_t row0 = (int64_t)blockIdx.x * kBlockThreads;
+  const int nrows = (int)(A.N - row0 < kBlockThreads ? A.N - row0 : kBlockThreads);
+  prim_rows<D>(A, U, row0, nrows, A.Nold);
+}
+
 template <int D>
 struct Node {
   double U[D + 2];
@@ -639,24 +649,17 @@ __device__ __forceinline__ void node_from_state(const KArgs &A, const double *V,
 
 // Data U^d of face f at dof i and time t, as a node (state and fields): the
 // face's constant data (fields computed at set-up), the vortex, or the
-// node's state at the start of the step.  A stage that writes U^n (the last
-// one) writes row i's output after every read of row i's data, in the same
-// thread.
+// node's state at the start of the step (its record, kept for the step).
 template <int D, int DEG>
 __device__ __forceinline__ void data_node(const KArgs &A, int f, int64_t i, double t, Node<D> &d) {
-  if (A.old_data) {
-    double V[D + 2];
-    for (int q = 0; q < D + 2; ++q) V[q] = A.uold[q * A.N + i];
-    node_from_state<D>(A, V, d);
-    return;
-  }
   if (D == 2 && A.vortex_data) {
     double V[D + 2];
     vortex_state<D, DEG>(A, i, t, V);
     node_from_state<D>(A, V, d);
     return;
   }
-  const double *b = A.ref->bnode[f];
+  // a step-start record has the layout of bnode
+  const double *b = A.old_data ? A.Nold + (size_t)i * kNodeStride : A.ref->bnode[f];
   for (int q = 0; q < D + 2; ++q) d.U[q] = b[q];
   for (int e = 0; e < D; ++e) d.u[e] = b[D + 2 + e];
   d.p = b[2 * D + 2];
@@ -1611,6 +1614,7 @@ static int stage_impl(const KArgs &A, const StageBufs &b, int stage, void *strea
     hipLaunchKernelGGL(k_prim<D>, dim3(gp), blk, 0, S(stream), A, b.in, stage);
     prof_mark(prof, KID_PRIM, 1, stream);
   }
+  if (A.old_data && stage == 0) hipLaunchKernelGGL(k_start_records<D>, dim3(gp), blk, 0, S(stream), A, b.in);
   // sweep 1 without the boundary-data code where no face has data: its
   // registers set the occupancy of the hottest kernel
   const bool bd = A.bcdata != 0;
