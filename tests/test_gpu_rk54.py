@@ -133,3 +133,23 @@ def test_server_refuses_ssprk54():
     with pytest.raises(gdg.GdgError):
         srv.submit(ms, U0, 0.1, params=p)
     srv.close()
+
+
+def test_noalloc_solve_with_ssprk54(oracle):
+    """The no-allocation solve steps with the integrator its params name:
+    SSPRK(5,4) there gives the context path's state bit for bit."""
+    _say("no-alloc solve")
+    import torch
+    ms, U = PAR["q2_2d_slip"]()
+    p = gdg.gdg_default_params(ms.degree)
+    p.integrator = gdg.GDG_SSPRK54
+    S = gdg.Solver.from_spec(ms, p)
+    S.upload(U)
+    st = S.run_to(1e30, max_steps=9)
+    want = S.download()
+    out = np.zeros_like(want)
+    mesh = gdg.mesh_desc(ms.dim, ms.degree, ms.cells, ms.lo, ms.hi, ms.bc)
+    st2 = gdg.gdg_solve_noalloc(mesh, p, np.ascontiguousarray(U), out, 1e30, 9,
+                                torch.cuda.current_stream().cuda_stream)
+    assert st2.steps == st.steps == 9 and st2.t == st.t
+    assert np.array_equal(out, want)
