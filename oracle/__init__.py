@@ -234,13 +234,15 @@ class Mesh:
                 L.or_set_boundary_state(self._h, f, _dp(v))
 
     @classmethod
-    def unstructured(cls, dim, degree, cell_points, points, face_bc, bstate=None, map_degree=1):
+    def unstructured(cls, dim, degree, cell_points, points, face_bc, bstate=None, map_degree=1,
+                     step_start_data=False):
         """Unstructured mesh: cell K is the image of the reference cell under
         the map of degree map_degree through points[cell_points[K, v]] (v the
         digits q_e in base map_degree + 1, first axis lowest); cells sharing a
         face's corner points are neighbours.  face_bc[K, f]: for a face on no
         other cell, its kind (1-5) + 8 * the box-face slot of its data in
-        bstate."""
+        bstate.  step_start_data: the data are the node's own state at the
+        start of the step instead (strategy (d) of Sec. 6.3)."""
         self = cls.__new__(cls)
         L = lib()
         cp = np.ascontiguousarray(cell_points, dtype=np.int64)
@@ -264,6 +266,8 @@ class Mesh:
             if bstate is not None and f < len(bstate) and bstate[f] is not None:
                 v = np.ascontiguousarray(bstate[f], dtype=np.float64)
                 L.or_set_boundary_state(self._h, f, _dp(v))
+        if step_start_data:
+            L.or_set_step_start_data(self._h)
         return self
 
     def __del__(self):

@@ -191,7 +191,8 @@ def mesh_desc(dim, degree, cells, lo, hi, bc, bstate=None, vortex=None, vertices
     return m
 
 
-def umesh_desc(dim, degree, cell_points, points, face_bc, bstate=None, map_degree=1) -> gdg_mesh_desc:
+def umesh_desc(dim, degree, cell_points, points, face_bc, bstate=None, map_degree=1,
+               step_start_data=False) -> gdg_mesh_desc:
     """Unstructured mesh: cell q is the image of the reference cell under its
     map of degree map_degree through points[cell_points[q, v]]; face_bc[q, f]
     is the kind + 8 * data slot of a face on no other cell (0 elsewhere).  The
@@ -218,6 +219,8 @@ def umesh_desc(dim, degree, cell_points, points, face_bc, bstate=None, map_degre
     m.vertices = pts.ctypes.data_as(C.POINTER(C.c_double))
     m.ucell_points = cp.ctypes.data_as(C.POINTER(C.c_int64))
     m.uface_bc = fb.ctypes.data_as(C.POINTER(C.c_int8))
+    if step_start_data:
+        m.data_kind = GDG_DATA_STEP_START
     return m
 
 
@@ -370,8 +373,9 @@ class Solver:
                    map_degree=getattr(ms, "map_degree", 1), **kw)
 
     @classmethod
-    def unstructured(cls, dim, degree, cell_points, points, face_bc, params=None, bstate=None, map_degree=1, **kw):
-        desc = umesh_desc(dim, degree, cell_points, points, face_bc, bstate, map_degree)
+    def unstructured(cls, dim, degree, cell_points, points, face_bc, params=None, bstate=None, map_degree=1,
+                     step_start_data=False, **kw):
+        desc = umesh_desc(dim, degree, cell_points, points, face_bc, bstate, map_degree, step_start_data)
         return cls(dim, degree, None, None, None, None, params, desc=desc, **kw)
 
     def close(self):

@@ -167,3 +167,21 @@ def test_triangle_keeps_mass_inside_walls():
     assert st.bound_violations == 0
     for c in (0, 3):
         assert abs(s1[c] - s0[c]) <= 1e-13 * abs(s0[c])
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_step_start_data_on_the_triangle(oracle, k):
+    """Boundary data from the node's state at the start of the step (strategy
+    (d) of Sec. 6.3) on the three-block triangle's Dirichlet and outflow
+    parts: five steps against the oracle's."""
+    _say("step-start data triangle q%d" % k)
+    dim, k, g, cp, P, fb, _ = _triangle(k)
+    M = oracle.Mesh.unstructured(dim, k, cp, P, fb, map_degree=g, step_start_data=True)
+    U = _smooth(M.coords(), dim)
+    S = gdg.Solver.unstructured(dim, k, cp, P, fb, map_degree=g, step_start_data=True)
+    S.upload(U)
+    op = oracle.params(degree=k)
+    Uo, t_o, n_o = M.run_to(op, U, 1.0, max_steps=5)
+    st = S.run_to(1.0, max_steps=5)
+    assert st.steps == n_o == 5 and st.t == pytest.approx(t_o, rel=1e-12)
+    _close(S.download(), Uo, tol=1e-10, what="U after 5 steps")
