@@ -10,7 +10,7 @@
  * DG Q_k space on a mesh, and boundary data built from them (Sec. 4), produce
  * U^{n+1} with a time step from the CFL rule (eq. MaxCFLdt), using the
  * low-order update, the entropy-viscosity high-order update and convex
- * limiting (Sec. 5) inside SSP-RK3 (Sec. 6.2).
+ * limiting (Sec. 5) inside SSP-RK3 or SSPRK(5,4) (Sec. 6.2).
  *
  * Conventions
  *  - dofs: cell-major.  Cells lexicographic with x fastest; inside a cell the
@@ -249,7 +249,7 @@ enum { GDG_FLAG_NO_QUIET_ROWS = 1 };
  * restarted. */
 typedef struct {
   double t;          /* simulated time */
-  int64_t steps;     /* SSP-RK3 steps taken */
+  int64_t steps;     /* time steps taken */
   int64_t restarts;  /* steps restarted after a CFL violation in stage 2 or 3 */
   double last_dt;    /* tau of the last step */
   double min_rho;    /* min_i rho_i of the current state (eq. AddSet: > 0) */

@@ -1,5 +1,5 @@
 // gdg_api.cpp -- the C-ABI of include/gdg.h: validation, workspace layout,
-// SSP-RK3 driver with CFL restarts, state transfer.
+// SSP-RK3 and SSPRK(5,4) driver with CFL restarts, state transfer.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -393,7 +393,6 @@ void drop_graph(gdg_ctx *ctx) {
   ctx->graph_exec = nullptr;
 }
 
-// One SSP-RK3 step on a stream: begin, three stages, end.
 // SSPRK(5,4) of Spiteri and Ruuth, Shu-Osher form
 //   u(i) = sum_k alpha_ik u(k) + tau beta_ik L(u(k)),  u(0) = U^n, u(5) = U^{n+1},
 // with the coefficients as published (15 digits).  Each stage i > 0 reads at
@@ -438,6 +437,7 @@ void set_integrator(KArgs &A, int integrator) {
   A.tstep_max = 1.0;
 }
 
+// One step on a stream: begin, the integrator's stages, end.
 // first / last: whether this step opens / closes a sequence of device-driven
 // steps (inside a sequence, one launch ends a step and starts the next).
 int enqueue_step(gdg_ctx *ctx, hipStream_t st, int device_driven, double dt_cap, double tau_fixed, Prof *prof,

@@ -91,7 +91,7 @@ constexpr int kRedFields = 2 + kMaxD + 2;
 // its neighbours sit together, so that a neighbour costs one or two cache
 // lines and a few wide loads instead of one line per field.
 //  node record (kNodeStride doubles), two buffers: the stage input's and the
-//  stage output's, chosen by the parity of 3 * steps + stage (node_buffer):
+//  stage output's, chosen by the parity of nst * steps + stage (node_buffer):
 //    [0, M) U, [M, M+D) velocity, then p, a, p^-alpha, f(s), s~, 1/p
 //  bound record (kQStride): rho_min, rho_max, s~_min of the ring-1 partials, N_i
 //  limiter record (kLimStride): [0, M) dU^H, [M, 2M) U^L, then rho_min,
@@ -209,7 +209,7 @@ struct KArgs {
 struct StageBufs {
   const double *in;   // stage input state
   double *out;        // stage output (may alias Un)
-  const double *Un;   // state at the start of the step (SSP combination)
+  const double *Un;   // the state the SSP combination takes (U^n, or a partial sum)
   double ca, cb;      // out = ca * Un + cb * Phi(in)
   // optional second output (NULL: none): out2 = cx * X2 + cy * Phi(in),
   // read and written at the same element (X2 may alias out2)
