@@ -12,7 +12,7 @@
  * the method: setup (Sec. 2.3), low-order update (Sec. 3, eq. cijdijscheme,
  * dij_low_order), boundary data (Sec. 4), high-order update with entropy
  * viscosity (Sec. 5.1-5.2), algebraic reformulation (Sec. 5.3) and convex
- * limiting (Sec. 5.4), inside SSP-RK3 (Sec. 6.2).  Sums over a stencil run in
+ * limiting (Sec. 5.4), inside SSP-RK3 or SSPRK(5,4) (Sec. 6.2).  Sums over a stencil run in
  * stored CSR order.  Where the paper is silent or garbled the reading used is
  * named in a comment ("reading R<n>"); the list of readings is kept with the
  * design notes of the repository.
